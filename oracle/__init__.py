@@ -1,0 +1,276 @@
+"""CPU oracle for exact s-t max-flow / min-cut (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU solver:
+the C part (``oracle.c`` -> ``liboracle.so``) is built from its own source with
+gcc, and the helpers below are plain numpy.
+
+What it computes (all integer, int64 accumulators):
+
+* ``solve_pairs`` / ``solve_grid`` -- the maximum flow value and the two extremal
+  minimum cuts of the network of the paper's Sec. 2 (excess form), by a textbook
+  highest-label push-relabel (``method="pr"``) or by Dinic on the explicit s-t
+  network (``method="dinic"``).
+* ``ard_grid`` -- the paper's own method run step by step on the CPU: Init,
+  Alg. 2 (P-ARD) or Alg. 1 (S-ARD), Proc. ARD with Augment (Sec. 4.2), region
+  relabel (Alg. 3) and the global gap (Sec. 5.1), with the per-sweep checks of
+  the statements of Sec. 4 switched on by ``checks``.
+* ``brute_force`` -- every cut of a network of at most ~20 vertices.
+* ``certify`` -- feasibility, conservation and max-flow = min-cut duality of a
+  residual state, from the original capacities.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+CHK_VALID = 1
+CHK_MONO = 2
+CHK_ACTIVE_B = 4
+CHK_LOWER = 8
+CHK_DISCHARGE = 16
+CHK_ALL = 31
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (no GPU code involved)."""
+    if force or not os.path.exists(_LIB_PATH):
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC",
+                               "-o", _LIB_PATH, _SRC])
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        common = [ctypes.c_int32, ctypes.c_int64, P, P, P, P, P, P, P, P, P, P, P, P, P]
+        lib.orc_pushrelabel.argtypes = common
+        lib.orc_pushrelabel.restype = ctypes.c_int
+        lib.orc_dinic.argtypes = common
+        lib.orc_dinic.restype = ctypes.c_int
+        lib.orc_cuts.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P, P, P, P, P]
+        lib.orc_cuts.restype = ctypes.c_int
+        lib.orc_ard.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P, P, P, P,
+                                ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                P, P, P, P, P, P, P, P, P, P, P]
+        lib.orc_ard.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _c32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+# ---------------------------------------------------------------------------
+# Grid -> vertex pairs
+# ---------------------------------------------------------------------------
+
+def grid_pairs(dims, nbr, offsets):
+    """Every geometric neighbour pair {v, v+o_k} of the grid (zero arcs included),
+    one per undirected arc, with c(v, v+o_k) and c(v+o_k, v)."""
+    dims = tuple(dims)
+    n = int(np.prod(dims))
+    idx = np.arange(n, dtype=np.int64).reshape(dims)
+    pu, pv, cuv, cvu = [], [], [], []
+    for k in range(0, len(offsets), 2):
+        off = offsets[k]
+        src, dst = [], []
+        for size, o in zip(dims, off):
+            if o >= 0:
+                src.append(slice(0, size - o))
+                dst.append(slice(o, size))
+            else:
+                src.append(slice(-o, size))
+                dst.append(slice(0, size + o))
+        u = idx[tuple(src)].reshape(-1)
+        v = idx[tuple(dst)].reshape(-1)
+        pu.append(u)
+        pv.append(v)
+        cuv.append(nbr[k][u])
+        cvu.append(nbr[k + 1][v])
+    cat = lambda xs: np.concatenate(xs) if xs else np.zeros(0, dtype=np.int64)
+    return (cat(pu).astype(np.int32), cat(pv).astype(np.int32),
+            _c32(cat(cuv)), _c32(cat(cvu)))
+
+
+def grid_regions(dims, tile):
+    """Region id of every vertex for a tiling of the grid into boxes of shape tile
+    (the last box along an axis may be partial)."""
+    dims = tuple(dims)
+    grids = np.meshgrid(*[np.arange(d) // t for d, t in zip(dims, tile)], indexing="ij")
+    nt = [-(-d // t) for d, t in zip(dims, tile)]
+    rid = np.zeros(dims, dtype=np.int64)
+    for ax, g in enumerate(grids):
+        rid = rid * nt[ax] + g
+    return rid.reshape(-1).astype(np.int32)
+
+
+def _offsets(inst):
+    from synth import offsets_for
+    return offsets_for(len(inst.dims), inst.conn)
+
+
+# ---------------------------------------------------------------------------
+# Solvers
+# ---------------------------------------------------------------------------
+
+def solve_pairs(n, pu, pv, cuv, cvu, cs, ct, method="pr"):
+    lib = _load()
+    pu, pv, cuv, cvu, cs, ct = map(_c32, (pu, pv, cuv, cvu, cs, ct))
+    m = pu.shape[0]
+    r_uv = np.zeros(m, dtype=np.int64)
+    r_vu = np.zeros(m, dtype=np.int64)
+    rt = np.zeros(n, dtype=np.int64)
+    ex = np.zeros(n, dtype=np.int64)
+    flow = np.zeros(1, dtype=np.int64)
+    smin = np.zeros(n, dtype=np.uint8)
+    smax = np.zeros(n, dtype=np.uint8)
+    fn = {"pr": lib.orc_pushrelabel, "dinic": lib.orc_dinic}[method]
+    rc = fn(n, m, _p(pu), _p(pv), _p(cuv), _p(cvu), _p(cs), _p(ct), _p(r_uv), _p(r_vu),
+            _p(rt), _p(ex), _p(flow), _p(smin), _p(smax))
+    if rc != 0:
+        raise RuntimeError(f"oracle {method} failed with code {rc}")
+    return dict(flow=int(flow[0]), smin=smin, smax=smax, r_uv=r_uv, r_vu=r_vu, rt=rt, ex=ex)
+
+
+def solve_grid(inst, method="pr"):
+    pu, pv, cuv, cvu = grid_pairs(inst.dims, inst.nbr, _offsets(inst))
+    out = solve_pairs(inst.n, pu, pv, cuv, cvu, inst.cs, inst.ct, method=method)
+    out["pairs"] = (pu, pv, cuv, cvu)
+    return out
+
+
+def cuts_of_state(n, pu, pv, r_uv, r_vu, rt, ex):
+    lib = _load()
+    pu, pv = _c32(pu), _c32(pv)
+    r_uv, r_vu, rt, ex = (np.ascontiguousarray(x, dtype=np.int64) for x in (r_uv, r_vu, rt, ex))
+    smin = np.zeros(n, dtype=np.uint8)
+    smax = np.zeros(n, dtype=np.uint8)
+    rc = lib.orc_cuts(n, pu.shape[0], _p(pu), _p(pv), _p(r_uv), _p(r_vu), _p(rt), _p(ex),
+                      _p(smin), _p(smax))
+    if rc != 0:
+        raise RuntimeError(f"orc_cuts failed with code {rc}")
+    return smin, smax
+
+
+def ard_pairs(n, pu, pv, cuv, cvu, cs, ct, region, parallel=True, checks=CHK_ALL,
+              max_sweeps=None):
+    lib = _load()
+    pu, pv, cuv, cvu, cs, ct, region = map(_c32, (pu, pv, cuv, cvu, cs, ct, region))
+    m = pu.shape[0]
+    r_uv = np.zeros(m, dtype=np.int64)
+    r_vu = np.zeros(m, dtype=np.int64)
+    rt = np.zeros(n, dtype=np.int64)
+    ex = np.zeros(n, dtype=np.int64)
+    flow = np.zeros(1, dtype=np.int64)
+    smin = np.zeros(n, dtype=np.uint8)
+    smax = np.zeros(n, dtype=np.uint8)
+    labels = np.zeros(n, dtype=np.int32)
+    sweeps = np.zeros(1, dtype=np.int64)
+    bsize = np.zeros(1, dtype=np.int64)
+    failed = np.zeros(1, dtype=np.int32)
+    if max_sweeps is None:
+        max_sweeps = (1 << 62)
+    rc = lib.orc_ard(n, m, _p(pu), _p(pv), _p(cuv), _p(cvu), _p(cs), _p(ct), _p(region),
+                     1 if parallel else 0, int(max_sweeps), int(checks), _p(r_uv), _p(r_vu),
+                     _p(rt), _p(ex), _p(flow), _p(smin), _p(smax), _p(labels), _p(sweeps),
+                     _p(bsize), _p(failed))
+    if rc == 3:
+        raise AssertionError(f"reference ARD invariant check {int(failed[0])} failed")
+    if rc != 0:
+        raise RuntimeError(f"orc_ard failed with code {rc}")
+    return dict(flow=int(flow[0]), smin=smin, smax=smax, r_uv=r_uv, r_vu=r_vu, rt=rt, ex=ex,
+                labels=labels, sweeps=int(sweeps[0]), bsize=int(bsize[0]))
+
+
+def ard_grid(inst, tile=None, parallel=True, checks=CHK_ALL, max_sweeps=None):
+    tile = tuple(tile if tile is not None else inst.tile)
+    pu, pv, cuv, cvu = grid_pairs(inst.dims, inst.nbr, _offsets(inst))
+    region = grid_regions(inst.dims, tile)
+    out = ard_pairs(inst.n, pu, pv, cuv, cvu, inst.cs, inst.ct, region, parallel=parallel,
+                    checks=checks, max_sweeps=max_sweeps)
+    out["pairs"] = (pu, pv, cuv, cvu)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Brute force and certificate
+# ---------------------------------------------------------------------------
+
+def cut_cost(side, pu, pv, cuv, cvu, cs, ct):
+    """Cost of the cut with source side {v : side[v]} (eq. (1), excess form):
+    s-links of sink-side vertices + t-links of source-side vertices + n-links
+    from the source side to the sink side.  Works on one mask or a stack."""
+    side = np.asarray(side).astype(np.int64)
+    cs = np.asarray(cs, dtype=np.int64)
+    ct = np.asarray(ct, dtype=np.int64)
+    cost = (1 - side) @ cs + side @ ct
+    su = side[..., np.asarray(pu, dtype=np.int64)]
+    sv = side[..., np.asarray(pv, dtype=np.int64)]
+    cost = cost + (su * (1 - sv)) @ np.asarray(cuv, dtype=np.int64) \
+        + (sv * (1 - su)) @ np.asarray(cvu, dtype=np.int64)
+    return cost
+
+
+def brute_force(n, pu, pv, cuv, cvu, cs, ct):
+    """Enumerate every source side C of V: min cost, and the intersection /
+    union of all minimisers (the unique minimal / maximal minimum cuts)."""
+    if n > 22:
+        raise ValueError("brute force is for tiny networks only")
+    masks = np.arange(1 << n, dtype=np.int64)
+    bits = ((masks[:, None] >> np.arange(n, dtype=np.int64)[None, :]) & 1).astype(np.int64)
+    cost = cut_cost(bits, pu, pv, cuv, cvu, cs, ct)
+    best = int(cost.min())
+    arg = bits[cost == best]
+    smin = arg.min(axis=0).astype(np.uint8)
+    smax = arg.max(axis=0).astype(np.uint8)
+    return dict(flow=best, smin=smin, smax=smax)
+
+
+def certify(n, pu, pv, cuv, cvu, cs, ct, r_uv, r_vu, rt, ex, flow, smin=None, smax=None):
+    """Raise AssertionError unless (r, rt, ex) is a feasible preflow state of
+    the network with flow value ``flow`` and the given cuts have cost ``flow``."""
+    pu = np.asarray(pu, dtype=np.int64)
+    pv = np.asarray(pv, dtype=np.int64)
+    cuv = np.asarray(cuv, dtype=np.int64)
+    cvu = np.asarray(cvu, dtype=np.int64)
+    r_uv = np.asarray(r_uv, dtype=np.int64)
+    r_vu = np.asarray(r_vu, dtype=np.int64)
+    rt = np.asarray(rt, dtype=np.int64)
+    ex = np.asarray(ex, dtype=np.int64)
+    cs = np.asarray(cs, dtype=np.int64)
+    ct = np.asarray(ct, dtype=np.int64)
+    assert (r_uv >= 0).all() and (r_vu >= 0).all(), "negative residual"
+    assert (r_uv + r_vu == cuv + cvu).all(), "residual pair sum changed"
+    assert ((rt >= 0) & (rt <= ct)).all(), "t-link residual out of range"
+    assert (ex >= 0).all(), "negative excess"
+    f_uv = cuv - r_uv  # net flow pu -> pv
+    net_in = np.zeros(n, dtype=np.int64)
+    np.add.at(net_in, pv, f_uv)
+    np.subtract.at(net_in, pu, f_uv)
+    assert (ex == cs - (ct - rt) + net_in).all(), "conservation violated"
+    assert int(ex.sum()) + int(flow) == int(cs.sum()), "sum of excess + flow != sum of s-links"
+    assert int((ct - rt).sum()) == int(flow), "flow value mismatch"
+    for side in (smin, smax):
+        if side is not None:
+            c = int(cut_cost(side, pu, pv, cuv, cvu, cs, ct))
+            assert c == int(flow), f"cut cost {c} != flow {flow}"
+    return True

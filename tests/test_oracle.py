@@ -1,0 +1,227 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+* brute-force enumeration of every cut (the definition, eq. (1) of Sec. 2);
+* hand-derived examples (tests/golden/hand_examples.json);
+* closed forms at full workload size (all n-links zero; n-links too strong to cut);
+* two independent solvers (push-relabel and Dinic) and the duality certificate;
+* the paper's own method (reference P-ARD / S-ARD) with its statements checked
+  after every sweep (Sec. 4.2-4.4) and the 2|B|^2+1 sweep bound.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _grid_from_json(ex):
+    dims = tuple(ex["dims"])
+    return synth.GridInstance(dims=dims, conn=ex["conn"], cs=np.array(ex["cs"], np.int32),
+                              ct=np.array(ex["ct"], np.int32),
+                              nbr=np.array(ex["nbr"], np.int32))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _build():
+    oracle.build(force=False)
+
+
+@pytest.mark.parametrize("seed", range(120))
+def test_pushrelabel_and_dinic_match_brute_force(seed):
+    n = 2 + seed % 15
+    pu, pv, cuv, cvu, cs, ct = synth.random_digraph(n, seed)
+    bf = oracle.brute_force(n, pu, pv, cuv, cvu, cs, ct)
+    for method in ("pr", "dinic"):
+        r = oracle.solve_pairs(n, pu, pv, cuv, cvu, cs, ct, method=method)
+        assert r["flow"] == bf["flow"]
+        assert (r["smin"] == bf["smin"]).all()
+        assert (r["smax"] == bf["smax"]).all()
+        oracle.certify(n, pu, pv, cuv, cvu, cs, ct, r["r_uv"], r["r_vu"], r["rt"], r["ex"],
+                       r["flow"], r["smin"], r["smax"])
+
+
+def test_brute_force_cut_cost_terms():
+    # one vertex, s-link 7, t-link 3: cutting it to the sink side costs 7, to the source side 3
+    z = np.zeros(0, np.int32)
+    cs = np.array([7], np.int32)
+    ct = np.array([3], np.int32)
+    assert oracle.cut_cost(np.array([0]), z, z, z, z, cs, ct) == 7
+    assert oracle.cut_cost(np.array([1]), z, z, z, z, cs, ct) == 3
+    # two vertices, arc 0->1 of 5 and 1->0 of 2: only the arc leaving the source side counts
+    pu, pv = np.array([0], np.int32), np.array([1], np.int32)
+    cuv, cvu = np.array([5], np.int32), np.array([2], np.int32)
+    zero2 = np.zeros(2, np.int32)
+    assert oracle.cut_cost(np.array([1, 0]), pu, pv, cuv, cvu, zero2, zero2) == 5
+    assert oracle.cut_cost(np.array([0, 1]), pu, pv, cuv, cvu, zero2, zero2) == 2
+
+
+def test_hand_examples():
+    with open(os.path.join(HERE, "golden", "hand_examples.json")) as f:
+        data = json.load(f)
+    for ex in data["examples"]:
+        inst = _grid_from_json(ex)
+        for method in ("pr", "dinic"):
+            r = oracle.solve_grid(inst, method=method)
+            assert r["flow"] == ex["flow"], ex["name"]
+            assert r["smin"].tolist() == ex["smin"], ex["name"]
+            assert r["smax"].tolist() == ex["smax"], ex["name"]
+        pu, pv, cuv, cvu = oracle.grid_pairs(inst.dims, inst.nbr, synth.offsets_for(2, 4))
+        bf = oracle.brute_force(inst.n, pu, pv, cuv, cvu, inst.cs, inst.ct)
+        assert bf["flow"] == ex["flow"]
+        assert bf["smin"].tolist() == ex["smin"] and bf["smax"].tolist() == ex["smax"]
+        a = oracle.ard_grid(inst, tile=(1, 2))
+        assert a["flow"] == ex["flow"] and a["smin"].tolist() == ex["smin"]
+
+
+@pytest.mark.parametrize("cfg", [0, 1])
+def test_closed_form_no_nlinks(cfg):
+    """All n-links zero: every vertex is independent, |f| = sum min(cs, ct),
+    S_min = {cs > ct}, S_max = {cs >= ct}."""
+    inst = synth.config(cfg)
+    inst.nbr[:] = 0
+    r = oracle.solve_grid(inst)
+    cs = inst.cs.astype(np.int64)
+    ct = inst.ct.astype(np.int64)
+    assert r["flow"] == int(np.minimum(cs, ct).sum())
+    assert (r["smin"] == (cs > ct)).all()
+    assert (r["smax"] == (cs >= ct)).all()
+
+
+def test_closed_form_strong_nlinks():
+    """n-links stronger than every t-link together: the only candidate minimum
+    cuts keep the grid in one piece, |f| = min(sum cs, sum ct)."""
+    for seed, conn in [(5, 4), (6, 8)]:
+        inst = synth.random_grid((20, 24), conn, seed)
+        offs = synth.offsets_for(2, conn)
+        big = int(inst.cs.sum() + inst.ct.sum() + 1)
+        for k, off in enumerate(offs):
+            valid = synth.grids._shift_valid(inst.dims, off).reshape(-1)
+            inst.nbr[k] = np.where(valid, big, 0)
+        r = oracle.solve_grid(inst)
+        sc, st = int(inst.cs.sum()), int(inst.ct.sum())
+        assert r["flow"] == min(sc, st)
+        if sc < st:
+            assert r["smin"].sum() == 0 and r["smax"].sum() == 0
+        elif st < sc:
+            assert r["smin"].all() and r["smax"].all()
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_chain_closed_form(seed):
+    """A 1 x L chain fed at its left end and drained at its right end carries
+    min(source, sink, every forward capacity)."""
+    rng = np.random.default_rng(seed)
+    L = int(rng.integers(2, 40))
+    nbr = np.zeros((4, L), np.int32)
+    fwd = rng.integers(1, 30, size=L - 1)
+    nbr[0, :L - 1] = fwd
+    nbr[1, 1:] = rng.integers(0, 30, size=L - 1)
+    cs = np.zeros(L, np.int32)
+    ct = np.zeros(L, np.int32)
+    cs[0] = int(rng.integers(1, 50))
+    ct[-1] = int(rng.integers(1, 50))
+    inst = synth.GridInstance(dims=(1, L), conn=4, cs=cs, ct=ct, nbr=nbr)
+    r = oracle.solve_grid(inst, method="pr")
+    assert r["flow"] == min(int(cs[0]), int(ct[-1]), int(fwd.min()))
+    d = oracle.solve_grid(inst, method="dinic")
+    assert d["flow"] == r["flow"] and (d["smin"] == r["smin"]).all()
+
+
+def test_workload0_solvers_agree_and_certify():
+    inst = synth.config(0)
+    r = oracle.solve_grid(inst, "pr")
+    d = oracle.solve_grid(inst, "dinic")
+    assert r["flow"] == d["flow"]
+    assert (r["smin"] == d["smin"]).all() and (r["smax"] == d["smax"]).all()
+    pu, pv, cuv, cvu = r["pairs"]
+    oracle.certify(inst.n, pu, pv, cuv, cvu, inst.cs, inst.ct, r["r_uv"], r["r_vu"], r["rt"],
+                   r["ex"], r["flow"], r["smin"], r["smax"])
+    oracle.certify(inst.n, pu, pv, cuv, cvu, inst.cs, inst.ct, d["r_uv"], d["r_vu"], d["rt"],
+                   d["ex"], d["flow"], d["smin"], d["smax"])
+
+
+def test_certify_rejects_planted_mistakes():
+    inst = synth.random_grid((8, 8), 4, 3)
+    r = oracle.solve_grid(inst)
+    pu, pv, cuv, cvu = r["pairs"]
+    args = [inst.n, pu, pv, cuv, cvu, inst.cs, inst.ct]
+    good = [r["r_uv"], r["r_vu"], r["rt"], r["ex"], r["flow"], r["smin"], r["smax"]]
+    oracle.certify(*args, *good)
+    # a wrong flow value
+    with pytest.raises(AssertionError):
+        oracle.certify(*args, *good[:4], good[4] + 1, good[5], good[6])
+    # a cut that is not minimal
+    wrong = good[5].copy()
+    wrong[np.argmax(wrong == 0)] = 1
+    if oracle.cut_cost(wrong, pu, pv, cuv, cvu, inst.cs, inst.ct) != good[4]:
+        with pytest.raises(AssertionError):
+            oracle.certify(*args, *good[:5], wrong, None)
+    # a residual pair that lost a unit
+    bad = good[0].copy()
+    i = int(np.argmax(bad > 0))
+    bad[i] -= 1
+    with pytest.raises(AssertionError):
+        oracle.certify(*args, bad, *good[1:])
+
+
+# ---------------------------------------------------------------------------
+# The paper's method on the CPU (reference ARD)
+# ---------------------------------------------------------------------------
+
+CASES = [((12, 13), 4, (4, 5)), ((16, 16), 8, (8, 8)), ((9, 20), 4, (3, 7)),
+         ((6, 7, 8), 6, (3, 4, 4)), ((10, 10), 8, (10, 10)), ((15, 9), 8, (2, 2))]
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_reference_ard_exact_and_invariants(seed):
+    dims, conn, tile = CASES[seed % len(CASES)]
+    inst = synth.random_grid(dims, conn, seed, tile=tile)
+    r = oracle.solve_grid(inst)
+    for parallel in (True, False):
+        a = oracle.ard_grid(inst, parallel=parallel, checks=oracle.CHK_ALL)
+        assert a["flow"] == r["flow"]
+        assert (a["smin"] == r["smin"]).all() and (a["smax"] == r["smax"]).all()
+        assert a["sweeps"] <= 2 * max(a["bsize"], 1) ** 2 + 1
+        pu, pv, cuv, cvu = a["pairs"]
+        oracle.certify(inst.n, pu, pv, cuv, cvu, inst.cs, inst.ct, a["r_uv"], a["r_vu"],
+                       a["rt"], a["ex"], a["flow"], a["smin"], a["smax"])
+
+
+@pytest.mark.parametrize("strength", [5, 40, 150, 400])
+def test_reference_ard_paper_family(strength):
+    """The synthetic family of Sec. 7.1 (excess in [-500, 500], constant strength)."""
+    for seed in range(3):
+        inst = synth.paper_e1_grid((30, 30), 8, seed, strength, tile=(15, 15))
+        r = oracle.solve_grid(inst)
+        a = oracle.ard_grid(inst, checks=oracle.CHK_ALL)
+        assert a["flow"] == r["flow"] and (a["smin"] == r["smin"]).all()
+        s = oracle.ard_grid(inst, parallel=False, checks=oracle.CHK_ALL)
+        assert s["flow"] == r["flow"]
+
+
+def test_reference_ard_single_region_is_one_sweep():
+    inst = synth.random_grid((14, 11), 8, 11)
+    a = oracle.ard_grid(inst, tile=(14, 11))
+    r = oracle.solve_grid(inst)
+    assert a["bsize"] == 0 and a["sweeps"] == 1 and a["flow"] == r["flow"]
+
+
+def test_reference_ard_boundary_size_closed_form():
+    """|B| for a tiling = vertices with a grid neighbour in another tile; for
+    box tiles this is n minus the product of per-axis non-edge coordinates."""
+    for dims, conn, tile in [((64, 64), 4, (32, 32)), ((50, 37), 8, (16, 8)),
+                             ((9, 10, 11), 6, (4, 4, 4))]:
+        inst = synth.random_grid(dims, conn, 0, tile=tile)
+        a = oracle.ard_grid(inst, checks=0)
+        inner = 1
+        for d, t in zip(dims, tile):
+            x = np.arange(d)
+            edge = ((x % t == 0) & (x > 0)) | ((x % t == t - 1) & (x < d - 1))
+            inner *= int((~edge).sum())
+        assert a["bsize"] == int(np.prod(dims)) - inner
+    assert oracle.ard_grid(synth.config(0), checks=0)["bsize"] == 252
