@@ -1,0 +1,160 @@
+/*
+ * mf.h -- exact s-t minimum cut / maximum flow on grid graphs by parallel
+ * augmented-path region discharge (P-ARD), on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem (paper Sec. 2, eq. (1)): a network G = (V, E, s, t, c, e) with
+ * integer capacities.  Here V is a 2D or 3D grid, E joins each vertex to its
+ * grid neighbours at the canonical offsets below, c(s, v) and c(v, t) are the
+ * terminal links.  The library computes a maximum preflow (Sec. 2: no vertex
+ * with positive excess reaches t in the residual network), its flow value
+ * |f| = sum_v f(v, t), and the two extremal minimum cuts.
+ *
+ * Method: the grid is partitioned into box regions (Sec. 3, fixed partition);
+ * each sweep discharges every region holding an active vertex against the
+ * boundary labels of the previous sweep (Alg. 2), where a discharge moves
+ * excess to t first and then to boundary vertices in increasing label order
+ * and finally relabels the region (Proc. ARD, Sec. 4.2; region relabel,
+ * Alg. 3); flows over boundary arcs are then fused under the valid-pair rule
+ * of Alg. 2 and the global gap heuristic over boundary labels is applied
+ * (Sec. 5.1).  Sweeps repeat until no vertex is active (Sec. 4.4).
+ *
+ * Everything runs in HIP kernels on the device; there is no CPU fallback.
+ *
+ * Conventions shared by every entry point
+ *   - dims are row-major, last axis fastest: 2D {H, W}, 3D {D, H, W}; vertex
+ *     v has index y*W + x (2D) or (z*H + y)*W + x (3D).
+ *   - connectivity 4 or 8 (2D) or 6 (3D); canonical offsets, opposite
+ *     directions adjacent (reverse of direction k is k ^ 1):
+ *       2D-4: +x, -x, +y, -y
+ *       2D-8: 2D-4 then +x+y, -x-y, +x-y, -x+y
+ *       3D-6: +x, -x, +y, -y, +z, -z
+ *   - capacities are int32 >= 0; the flow value is int64.
+ *   - status codes: no entry point throws; every failure is reported by the
+ *     returned mf_status and leaves the handle usable unless MF_E_DEVICE.
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mf_grid mf_grid; /* opaque, owned by the library */
+
+typedef enum {
+    MF_OK = 0,
+    MF_E_INVAL = 1,    /* bad argument: shape, connectivity, negative or out-of-grid capacity */
+    MF_E_NOMEM = 2,    /* device or host allocation failed */
+    MF_E_DEVICE = 3,   /* a HIP call failed or a kernel reported an internal error */
+    MF_E_STATE = 4,    /* call order violated (e.g. solve before set_caps) */
+    MF_E_OVERFLOW = 5, /* capacities could overflow int32 residuals or excesses */
+    MF_E_SWEEPS = 6    /* max_sweeps reached before the preflow became maximum */
+} mf_status;
+
+/* which minimum cut mf_min_cut returns */
+enum {
+    MF_CUT_MIN_SOURCE = 0, /* unique minimal source side: s and every vertex an
+                              excess vertex reaches in the final residual network */
+    MF_CUT_MAX_SOURCE = 1  /* the paper's (T-bar, T): every vertex that does not reach t */
+};
+
+/* region schedule inside a sweep */
+enum {
+    MF_SCHED_PARD = 0,    /* Alg. 2: all active regions against the previous sweep's labels */
+    MF_SCHED_COLORED = 1, /* Alg. 1 as phases of non-interacting regions (reserved) */
+    MF_SCHED_LEARNED = 2, /* region order and deferral from a trained scorer (reserved) */
+    MF_SCHED_AUTO = 3     /* library's choice (currently MF_SCHED_PARD) */
+};
+
+typedef struct {
+    int32_t schedule;             /* MF_SCHED_*; 0 is P-ARD */
+    int32_t global_relabel_every; /* exact region-distance relabel every N sweeps; 0 = off */
+    int32_t gap;                  /* 1 = global gap heuristic on (default), 0 = off */
+    int32_t check_every;          /* sweeps enqueued between host-side termination checks; 0 = 8 */
+    int64_t max_sweeps;           /* guard; 0 = 2|B|^2 + 1 (the bound of Sec. 4.3-4.4) */
+    const void *model;            /* scorer weights for MF_SCHED_LEARNED, else NULL */
+    void *stream;                 /* hipStream_t to run on; NULL = the null stream */
+    int32_t profile;              /* 1 = time every discharge launch with HIP events */
+    int32_t reserved;
+} mf_solve_opts;
+
+typedef struct {
+    int64_t sweeps;             /* sweeps that started with an active vertex (Sec. 3) */
+    int64_t region_discharges;  /* regions discharged, summed over sweeps */
+    int64_t boundary_size;      /* |B| (Sec. 4.1), geometric */
+    int64_t d_inf;              /* max(|B|, 1) */
+    double solve_ms;            /* wall time of mf_solve, host clock, stream synchronised */
+    double discharge_ms;        /* profile=1: summed duration of the discharge launches */
+    int64_t discharge_launches; /* profile=1: number of timed discharge launches */
+    double discharge_bytes;     /* algorithmic bytes of all discharges, see mf_discharge_bytes_per_vertex */
+    int64_t discharged_vertices;/* real vertices in discharged regions, summed over sweeps */
+} mf_solve_stats;
+
+/* Create a solver handle for a grid shape and region partition.
+ *   ndim          2 or 3
+ *   dims          [ndim] grid extents, each >= 1, product < 2^31
+ *   connectivity  4 or 8 for ndim = 2, 6 for ndim = 3
+ *   region_shape  [ndim] box region extents (Sec. 3 fixed partition; the last
+ *                 region along an axis may be partial), or NULL / all zeros to
+ *                 let the library pick
+ *   out           receives the handle; unchanged on failure
+ * Allocates all device memory for the shape.  Errors: MF_E_INVAL, MF_E_NOMEM,
+ * MF_E_DEVICE.  Uses the current HIP device. */
+mf_status mf_create_grid(int32_t ndim, const int64_t *dims, int32_t connectivity,
+                         const int32_t *region_shape, mf_grid **out);
+
+/* Load an instance (Sec. 2 network; Init of Sec. 2 happens in mf_solve).
+ *   src_cap   [n]     c(s, v) >= 0
+ *   sink_cap  [n]     c(v, t) >= 0
+ *   nbr_cap   [K][n]  c(v, v + o_k) >= 0, 0 where v + o_k leaves the grid
+ *   on_device 0: the three pointers are host memory; 1: device memory of the
+ *             current device (e.g. torch CUDA tensors); the library copies
+ *             them and keeps no reference.
+ *   stream    hipStream_t used for the copies and checks, or NULL
+ * Errors: MF_E_INVAL (negative capacity or non-zero capacity on an arc that
+ * leaves the grid), MF_E_OVERFLOW (c(u,v) + c(v,u) > INT32_MAX, or
+ * c(s,v) + sum_u c(u,v) > INT32_MAX), MF_E_DEVICE.  On error the handle holds
+ * no instance (a following mf_solve returns MF_E_STATE). */
+mf_status mf_set_caps(mf_grid *g, const int32_t *src_cap, const int32_t *sink_cap,
+                      const int32_t *nbr_cap, int32_t on_device, void *stream);
+
+/* Solve the loaded instance to a maximum preflow.  opts may be NULL
+ * (defaults: P-ARD, gap on, global relabel off).  st may be NULL.  Blocks
+ * until the result is on the device and the stream is synchronised.  A second
+ * call re-solves the same instance from Init.
+ * Errors: MF_E_STATE (no instance), MF_E_SWEEPS, MF_E_DEVICE, MF_E_INVAL. */
+mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_stats *st);
+
+/* Flow value |f| = sum_v (c(v,t) - c_f(v,t)) of the last solve (Sec. 2).
+ * Errors: MF_E_STATE if no solve has completed. */
+mf_status mf_flow_value(const mf_grid *g, int64_t *out);
+
+/* Minimum cut of the last solve as a source-side indicator.
+ *   kind             MF_CUT_MIN_SOURCE or MF_CUT_MAX_SOURCE
+ *   out_source_side  [n] host array, 1 = source side, row-major like dims
+ * Computed on the device by residual reachability.  Errors: MF_E_STATE,
+ * MF_E_INVAL, MF_E_DEVICE. */
+mf_status mf_min_cut(const mf_grid *g, int32_t kind, uint8_t *out_source_side);
+
+/* Final state of the last solve in the row-major layout of the inputs, for
+ * certification: residuals [K][n] (c_f(v, v+o_k)), residual t-links [n],
+ * excess [n], labels [n].  Any pointer may be NULL.  Host arrays. */
+mf_status mf_get_state(const mf_grid *g, int32_t *res, int32_t *rt, int32_t *ex, int32_t *labels);
+
+/* Shape facts of a handle: number of vertices, K, regions, |B|, region shape. */
+mf_status mf_get_info(const mf_grid *g, int64_t *n, int32_t *K, int64_t *regions,
+                      int64_t *boundary_size, int32_t *region_shape3);
+
+/* Algorithmic bytes one discharged vertex moves: its K residuals, residual
+ * t-link and excess are read and written, its label is written. */
+int64_t mf_discharge_bytes_per_vertex(int32_t connectivity);
+
+void mf_destroy(mf_grid *g);
+const char *mf_status_str(mf_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MF_H */

@@ -1,0 +1,482 @@
+// C ABI of the region-discharge max-flow solver (see include/mf.h): handle,
+// validation, region partition and boundary builder, sweep driver, results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "mf.h"
+#include "mf_launch.h"
+
+using mfd::Geo;
+typedef unsigned long long u64;
+
+struct mf_grid {
+    Geo G;
+    int ndim = 0, conn = 0, K = 0;
+    long long n = 0;
+    long long nB = 0;
+    int dinf = 1;
+    int nring = 0;
+    int device = 0;
+    int numCU = 0;
+    // device state
+    int *res = nullptr, *rt = nullptr, *ex = nullptr, *lab[2] = {nullptr, nullptr};
+    int *pushb = nullptr, *ractive = nullptr, *order = nullptr, *bidx = nullptr;
+    int *ringL = nullptr, *rvcount = nullptr, *mark = nullptr, *dirty = nullptr;
+    unsigned char *ringM = nullptr, *cutbuf = nullptr;
+    int *in_cs = nullptr, *in_ct = nullptr, *in_nbr = nullptr;
+    int *scratch = nullptr;
+    int nslots = 0;
+    bool useLDS = false;
+    int threads = 256;
+    // device control block
+    u64 *act = nullptr;           // [2]
+    unsigned int *qhead = nullptr;  // [2]
+    unsigned int *hist = nullptr;
+    int *maxlab = nullptr, *gap = nullptr, *err = nullptr;
+    u64 *counters = nullptr;      // [0] sweeps
+    u64 *stats = nullptr;         // [0] discharges [1] vertices
+    u64 *sums = nullptr;          // [0] sum cs [1] sum ct [2] sum rt
+    unsigned int *changed = nullptr;
+    int *tmp_plane = nullptr;
+    u64 *pinned = nullptr;        // host pinned mailbox
+    // instance state
+    bool has_caps = false, solved = false;
+    long long sum_cs = 0, sum_ct = 0, flow = 0;
+    int final_parity = 0;
+};
+
+static bool ok(hipError_t e) { return e == hipSuccess; }
+#define HIP_TRY(x)                         \
+    do {                                   \
+        if (!ok(x)) return MF_E_DEVICE;    \
+    } while (0)
+
+template <typename T>
+static hipError_t dalloc(T **p, size_t count) {
+    if (count == 0) count = 1;
+    return hipMalloc((void **)p, count * sizeof(T));
+}
+
+static void free_all(mf_grid *g) {
+    void *ptrs[] = {g->res, g->rt, g->ex, g->lab[0], g->lab[1], g->pushb, g->ractive, g->order,
+                    g->bidx, g->ringL, g->rvcount, g->mark, g->dirty, g->ringM, g->cutbuf,
+                    g->in_cs, g->in_ct, g->in_nbr, g->scratch, g->act, g->qhead, g->hist,
+                    g->maxlab, g->gap, g->err, g->counters, g->stats, g->sums, g->changed,
+                    g->tmp_plane};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (g->pinned) (void)hipHostFree(g->pinned);
+}
+
+static const int8_t OFF2D[8][2] = {{0, 1}, {0, -1}, {1, 0}, {-1, 0}, {1, 1}, {-1, -1}, {-1, 1}, {1, -1}};
+static const int8_t OFF3D[6][3] = {{0, 0, 1}, {0, 0, -1}, {0, 1, 0}, {0, -1, 0}, {1, 0, 0}, {-1, 0, 0}};
+
+extern "C" const char *mf_status_str(mf_status s) {
+    switch (s) {
+        case MF_OK: return "ok";
+        case MF_E_INVAL: return "invalid argument";
+        case MF_E_NOMEM: return "out of memory";
+        case MF_E_DEVICE: return "device error";
+        case MF_E_STATE: return "call order violated";
+        case MF_E_OVERFLOW: return "capacities could overflow int32";
+        case MF_E_SWEEPS: return "sweep limit reached";
+    }
+    return "unknown status";
+}
+
+extern "C" int64_t mf_discharge_bytes_per_vertex(int32_t connectivity) {
+    // read K residuals + t-link + excess, write them back, write the label
+    return (int64_t)(2 * connectivity + 5) * 4;
+}
+
+extern "C" mf_status mf_create_grid(int32_t ndim, const int64_t *dims, int32_t connectivity,
+                                    const int32_t *region_shape, mf_grid **out) {
+    if (!out || !dims || (ndim != 2 && ndim != 3)) return MF_E_INVAL;
+    if (ndim == 2 && connectivity != 4 && connectivity != 8) return MF_E_INVAL;
+    if (ndim == 3 && connectivity != 6) return MF_E_INVAL;
+    long long d[3] = {1, 1, 1};
+    for (int i = 0; i < ndim; i++) {
+        if (dims[i] < 1) return MF_E_INVAL;
+        d[3 - ndim + i] = dims[i];
+    }
+    long long n = d[0] * d[1] * d[2];
+    if (n >= (1LL << 31)) return MF_E_INVAL;
+    int t[3] = {1, 1, 1};
+    bool given = region_shape != nullptr;
+    if (given) {
+        bool allzero = true;
+        for (int i = 0; i < ndim; i++) allzero = allzero && region_shape[i] == 0;
+        if (allzero) given = false;
+    }
+    for (int i = 0; i < ndim; i++) {
+        int ax = 3 - ndim + i;
+        if (given) {
+            if (region_shape[i] < 1) return MF_E_INVAL;
+            t[ax] = (int)std::min<long long>(region_shape[i], d[ax]);
+        } else {
+            t[ax] = (int)std::min<long long>(ndim == 2 ? 64 : 32, d[ax]);
+        }
+    }
+    mf_grid *g = new (std::nothrow) mf_grid();
+    if (!g) return MF_E_NOMEM;
+    Geo &G = g->G;
+    memset(&G, 0, sizeof(G));
+    G.K = connectivity;
+    G.dz = (int)d[0]; G.dy = (int)d[1]; G.dx = (int)d[2];
+    G.tz = t[0]; G.ty = t[1]; G.tx = t[2];
+    G.rz = (int)((d[0] + t[0] - 1) / t[0]);
+    G.ry = (int)((d[1] + t[1] - 1) / t[1]);
+    G.rx = (int)((d[2] + t[2] - 1) / t[2]);
+    long long V = (long long)t[0] * t[1] * t[2];
+    long long nreg = (long long)G.rz * G.ry * G.rx;
+    if (V * nreg * std::max(connectivity, 1) >= (1LL << 31) * 4LL || V * nreg >= (1LL << 31) || V > (1 << 20)) {
+        delete g;
+        return MF_E_INVAL;
+    }
+    G.V = (int)V;
+    G.nreg = (int)nreg;
+    G.N = (int)(V * nreg);
+    for (int k = 0; k < connectivity; k++) {
+        if (ndim == 2) {
+            G.oz[k] = 0; G.oy[k] = OFF2D[k][0]; G.ox[k] = OFF2D[k][1];
+        } else {
+            G.oz[k] = OFF3D[k][0]; G.oy[k] = OFF3D[k][1]; G.ox[k] = OFF3D[k][2];
+        }
+    }
+    g->ndim = ndim;
+    g->conn = connectivity;
+    g->K = connectivity;
+    g->n = n;
+
+    // tile border ("ring"): local vertices with a direction leaving the tile
+    std::vector<int> ringL;
+    std::vector<unsigned char> ringM;
+    for (int l = 0; l < G.V; l++) {
+        int lx = l % G.tx, tt = l / G.tx, ly = tt % G.ty, lz = tt / G.ty;
+        unsigned m = 0;
+        for (int k = 0; k < G.K; k++) {
+            int z = lz + G.oz[k], y = ly + G.oy[k], x = lx + G.ox[k];
+            if (x < 0 || x >= G.tx || y < 0 || y >= G.ty || z < 0 || z >= G.tz) m |= 1u << k;
+        }
+        if (m) { ringL.push_back(l); ringM.push_back((unsigned char)m); }
+    }
+    g->nring = (int)ringL.size();
+    // boundary set B (Sec. 4.1): real vertices with a real grid neighbour in another region
+    std::vector<int> bidx;
+    std::vector<int> rvcount(G.nreg);
+    for (int r = 0; r < G.nreg; r++) {
+        int rx = r % G.rx, tt = r / G.rx, ry = tt % G.ry, rz = tt / G.ry;
+        int oz = rz * G.tz, oy = ry * G.ty, ox = rx * G.tx;
+        rvcount[r] = std::min(G.tz, G.dz - oz) * std::min(G.ty, G.dy - oy) * std::min(G.tx, G.dx - ox);
+        for (size_t i = 0; i < ringL.size(); i++) {
+            int l = ringL[i];
+            int lx = l % G.tx, t2 = l / G.tx, ly = t2 % G.ty, lz = t2 / G.ty;
+            int z = oz + lz, y = oy + ly, x = ox + lx;
+            if (z >= G.dz || y >= G.dy || x >= G.dx) continue;
+            bool inB = false;
+            for (int k = 0; k < G.K && !inB; k++) {
+                if (!((ringM[i] >> k) & 1u)) continue;
+                int zz = z + G.oz[k], yy = y + G.oy[k], xx = x + G.ox[k];
+                if (zz >= 0 && zz < G.dz && yy >= 0 && yy < G.dy && xx >= 0 && xx < G.dx) inB = true;
+            }
+            if (inB) bidx.push_back(r * G.V + l);
+        }
+    }
+    g->nB = (long long)bidx.size();
+    g->dinf = g->nB > 0 ? (int)g->nB : 1;
+
+    hipDeviceProp_t prop;
+    if (!ok(hipGetDevice(&g->device)) || !ok(hipGetDeviceProperties(&prop, g->device))) {
+        delete g;
+        return MF_E_DEVICE;
+    }
+    g->numCU = prop.multiProcessorCount;
+    g->threads = 256;
+    // the four search arrays (16 B per vertex) live in LDS when they fit beside
+    // the kernel's static shared words; otherwise in per-workgroup HBM scratch
+    g->useLDS = (size_t)16 * G.V + 1024 <= (size_t)prop.sharedMemPerBlock;
+    g->nslots = std::max(1, std::min(G.nreg, 2 * g->numCU));
+
+    size_t N = (size_t)G.N, K = (size_t)G.K;
+    bool good = ok(dalloc(&g->res, K * N)) && ok(dalloc(&g->pushb, K * N)) &&
+                ok(dalloc(&g->rt, N)) && ok(dalloc(&g->ex, N)) && ok(dalloc(&g->lab[0], N)) &&
+                ok(dalloc(&g->lab[1], N)) && ok(dalloc(&g->mark, N)) &&
+                ok(dalloc(&g->ractive, (size_t)G.nreg)) && ok(dalloc(&g->order, (size_t)G.nreg)) &&
+                ok(dalloc(&g->rvcount, (size_t)G.nreg)) && ok(dalloc(&g->dirty, 2 * (size_t)G.nreg)) &&
+                ok(dalloc(&g->bidx, (size_t)g->nB)) && ok(dalloc(&g->ringL, (size_t)g->nring)) &&
+                ok(dalloc(&g->ringM, (size_t)g->nring)) && ok(dalloc(&g->cutbuf, (size_t)n)) &&
+                ok(dalloc(&g->in_cs, (size_t)n)) && ok(dalloc(&g->in_ct, (size_t)n)) &&
+                ok(dalloc(&g->in_nbr, K * (size_t)n)) && ok(dalloc(&g->tmp_plane, (size_t)n)) &&
+                ok(dalloc(&g->scratch, (size_t)g->nslots * 4 * G.V)) && ok(dalloc(&g->act, 2)) &&
+                ok(dalloc(&g->qhead, 2)) && ok(dalloc(&g->hist, (size_t)mfd::kHistBins)) &&
+                ok(dalloc(&g->maxlab, 1)) && ok(dalloc(&g->gap, 1)) && ok(dalloc(&g->err, 1)) &&
+                ok(dalloc(&g->counters, 4)) && ok(dalloc(&g->stats, 2)) && ok(dalloc(&g->sums, 4)) &&
+                ok(dalloc(&g->changed, 1)) &&
+                ok(hipHostMalloc((void **)&g->pinned, 16 * sizeof(u64), hipHostMallocDefault));
+    if (!good) {
+        (void)hipGetLastError();
+        free_all(g);
+        delete g;
+        return MF_E_NOMEM;
+    }
+    std::vector<int> order(G.nreg);
+    for (int r = 0; r < G.nreg; r++) order[r] = r;
+    good = ok(hipMemcpy(g->order, order.data(), sizeof(int) * G.nreg, hipMemcpyHostToDevice)) &&
+           ok(hipMemcpy(g->rvcount, rvcount.data(), sizeof(int) * G.nreg, hipMemcpyHostToDevice)) &&
+           (bidx.empty() || ok(hipMemcpy(g->bidx, bidx.data(), sizeof(int) * bidx.size(), hipMemcpyHostToDevice))) &&
+           (ringL.empty() || ok(hipMemcpy(g->ringL, ringL.data(), sizeof(int) * ringL.size(), hipMemcpyHostToDevice))) &&
+           (ringM.empty() || ok(hipMemcpy(g->ringM, ringM.data(), ringM.size(), hipMemcpyHostToDevice)));
+    if (!good) {
+        free_all(g);
+        delete g;
+        return MF_E_DEVICE;
+    }
+    *out = g;
+    return MF_OK;
+}
+
+extern "C" void mf_destroy(mf_grid *g) {
+    if (!g) return;
+    (void)hipDeviceSynchronize();
+    free_all(g);
+    delete g;
+}
+
+extern "C" mf_status mf_get_info(const mf_grid *g, int64_t *n, int32_t *K, int64_t *regions,
+                                 int64_t *boundary_size, int32_t *region_shape3) {
+    if (!g) return MF_E_INVAL;
+    if (n) *n = g->n;
+    if (K) *K = g->K;
+    if (regions) *regions = g->G.nreg;
+    if (boundary_size) *boundary_size = g->nB;
+    if (region_shape3) {
+        region_shape3[0] = g->G.tz;
+        region_shape3[1] = g->G.ty;
+        region_shape3[2] = g->G.tx;
+    }
+    return MF_OK;
+}
+
+extern "C" mf_status mf_set_caps(mf_grid *g, const int32_t *src_cap, const int32_t *sink_cap,
+                                 const int32_t *nbr_cap, int32_t on_device, void *stream) {
+    if (!g || !src_cap || !sink_cap || !nbr_cap) return MF_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    g->has_caps = false;
+    g->solved = false;
+    size_t n = (size_t)g->n, K = (size_t)g->K;
+    hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIP_TRY(hipMemcpyAsync(g->in_cs, src_cap, n * sizeof(int), kind, s));
+    HIP_TRY(hipMemcpyAsync(g->in_ct, sink_cap, n * sizeof(int), kind, s));
+    HIP_TRY(hipMemcpyAsync(g->in_nbr, nbr_cap, K * n * sizeof(int), kind, s));
+    HIP_TRY(hipMemsetAsync(g->err, 0, sizeof(int), s));
+    HIP_TRY(hipMemsetAsync(g->sums, 0, 4 * sizeof(u64), s));
+    HIP_TRY(mfd::launch_validate(g->G, g->in_cs, g->in_ct, g->in_nbr, (int)n, g->err, s));
+    HIP_TRY(mfd::launch_sum_links(g->in_cs, g->in_ct, (int)n, g->sums, s));
+    HIP_TRY(hipMemcpyAsync(g->pinned, g->sums, 2 * sizeof(u64), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(g->pinned + 2, g->err, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int err = *(int *)(g->pinned + 2);
+    if (err & 1) return MF_E_INVAL;
+    if (err & 2) return MF_E_OVERFLOW;
+    g->sum_cs = (long long)g->pinned[0];
+    g->sum_ct = (long long)g->pinned[1];
+    g->has_caps = true;
+    return MF_OK;
+}
+
+extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_stats *st) {
+    if (!g) return MF_E_INVAL;
+    if (!g->has_caps) return MF_E_STATE;
+    mf_solve_opts o;
+    memset(&o, 0, sizeof(o));
+    o.gap = 1;
+    if (opts) o = *opts;
+    if (o.schedule < 0 || o.schedule > MF_SCHED_AUTO) return MF_E_INVAL;
+    if (o.schedule == MF_SCHED_COLORED || o.schedule == MF_SCHED_LEARNED) return MF_E_INVAL;
+    int check_every = o.check_every > 0 ? o.check_every : 8;
+    long long B = g->nB > 0 ? g->nB : 1;
+    long long bound = (B > 2000000000LL) ? (1LL << 62) : 2 * B * B + 1;
+    long long max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : bound;
+    hipStream_t s = (hipStream_t)o.stream;
+    g->solved = false;
+    const Geo &G = g->G;
+    auto t0 = std::chrono::high_resolution_clock::now();
+
+    // control block reset + Init
+    HIP_TRY(hipMemsetAsync(g->act, 0, 2 * sizeof(u64), s));
+    HIP_TRY(hipMemsetAsync(g->qhead, 0, 2 * sizeof(unsigned), s));
+    HIP_TRY(hipMemsetAsync(g->hist, 0, sizeof(unsigned) * mfd::kHistBins, s));
+    HIP_TRY(hipMemsetAsync(g->maxlab, 0xff, sizeof(int), s));
+    HIP_TRY(hipMemsetAsync(g->gap, 0xff, sizeof(int), s));
+    HIP_TRY(hipMemsetAsync(g->err, 0, sizeof(int), s));
+    HIP_TRY(hipMemsetAsync(g->counters, 0, 4 * sizeof(u64), s));
+    HIP_TRY(hipMemsetAsync(g->stats, 0, 2 * sizeof(u64), s));
+    HIP_TRY(hipMemsetAsync(g->ractive, 0, sizeof(int) * G.nreg, s));
+    HIP_TRY(mfd::launch_init(G, g->in_cs, g->in_ct, g->in_nbr, (int)g->n, g->res, g->rt, g->ex,
+                             g->lab[0], g->lab[1], g->pushb, g->ractive, g->act, s));
+
+    mfd::DischargeArgs D;
+    memset(&D, 0, sizeof(D));
+    D.G = G;
+    D.res = g->res; D.rt = g->rt; D.ex = g->ex; D.pushb = g->pushb;
+    D.ractive = g->ractive; D.order = g->order; D.nwork = G.nreg;
+    D.dinf = g->dinf; D.scratch = g->scratch; D.ringL = g->ringL; D.ringM = g->ringM;
+    D.nring = g->nring; D.stats = g->stats; D.rvcount = g->rvcount; D.err = g->err;
+    D.useLDS = g->useLDS ? 1 : 0;
+    D.maxIter = 1 << 18;
+    size_t lds = g->useLDS ? (size_t)16 * G.V : 0;
+
+    mfd::FuseArgs F;
+    memset(&F, 0, sizeof(F));
+    F.G = G; F.bidx = g->bidx; F.nB = (int)g->nB; F.res = g->res; F.ex = g->ex; F.pushb = g->pushb;
+    F.dinf = g->dinf; F.hist = g->hist; F.maxlab = g->maxlab;
+
+    mfd::GapArgs P;
+    P.hist = g->hist; P.maxlab = g->maxlab; P.gap = g->gap; P.gapOn = o.gap ? 1 : 0;
+    P.counters = g->counters;
+
+    mfd::GapApplyArgs Q;
+    memset(&Q, 0, sizeof(Q));
+    Q.G = G; Q.bidx = g->bidx; Q.nB = (int)g->nB; Q.ex = g->ex; Q.ractive = g->ractive;
+    Q.gap = g->gap; Q.dinf = g->dinf;
+
+    std::vector<hipEvent_t> ev;
+    if (o.profile) {
+        ev.resize(2 * check_every);
+        for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    }
+    double discharge_ms = 0.0;
+    long long timed = 0;
+    long long sweep = 0;
+    mf_status status = MF_OK;
+    for (;;) {
+        for (int j = 0; j < check_every; j++, sweep++) {
+            const int p = (int)(sweep & 1);
+            D.labOld = g->lab[p]; D.labNew = g->lab[p ^ 1];
+            D.actIn = g->act + p; D.qhead = g->qhead + p;
+            if (o.profile) HIP_TRY(hipEventRecord(ev[2 * j], s));
+            HIP_TRY(mfd::launch_discharge(D, g->nslots, g->threads, lds, s));
+            if (o.profile) HIP_TRY(hipEventRecord(ev[2 * j + 1], s));
+            F.lab = g->lab[p ^ 1]; F.actIn = g->act + p;
+            HIP_TRY(mfd::launch_fuse(F, s));
+            P.actIn = g->act + p; P.actOut = g->act + (p ^ 1); P.qheadNext = g->qhead + (p ^ 1);
+            HIP_TRY(mfd::launch_gap_find(P, s));
+            Q.lab = g->lab[p ^ 1]; Q.actIn = g->act + p; Q.actOut = g->act + (p ^ 1);
+            HIP_TRY(mfd::launch_gap_apply(Q, s));
+        }
+        const int p = (int)(sweep & 1);
+        HIP_TRY(hipMemcpyAsync(g->pinned, g->act + p, sizeof(u64), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(g->pinned + 1, g->counters, sizeof(u64), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(g->pinned + 2, g->err, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (o.profile) {
+            // only launches of sweeps that did work are counted
+            long long done_sweeps = (long long)g->pinned[1];
+            long long first = sweep - check_every;
+            for (int j = 0; j < check_every; j++) {
+                if (first + j >= done_sweeps) break;
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]));
+                discharge_ms += ms;
+                timed++;
+            }
+        }
+        if (*(int *)(g->pinned + 2) != 0) { status = MF_E_DEVICE; break; }
+        if (g->pinned[0] == 0ull) break;
+        if ((long long)g->pinned[1] >= max_sweeps) { status = MF_E_SWEEPS; break; }
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (status != MF_OK) return status;
+    long long sweeps = (long long)g->pinned[1];
+    g->final_parity = (int)(sweeps & 1);
+    // flow value |f| = sum (c_t - c_f(., t))
+    HIP_TRY(hipMemsetAsync(g->sums + 2, 0, sizeof(u64), s));
+    HIP_TRY(mfd::launch_sum_i32(g->rt, G.N, g->sums + 2, s));
+    HIP_TRY(hipMemcpyAsync(g->pinned + 3, g->sums + 2, sizeof(u64), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(g->pinned + 4, g->stats, 2 * sizeof(u64), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    g->flow = g->sum_ct - (long long)g->pinned[3];
+    g->solved = true;
+    auto t1 = std::chrono::high_resolution_clock::now();
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->sweeps = sweeps;
+        st->region_discharges = (int64_t)g->pinned[4];
+        st->discharged_vertices = (int64_t)g->pinned[5];
+        st->boundary_size = g->nB;
+        st->d_inf = g->dinf;
+        st->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        st->discharge_ms = discharge_ms;
+        st->discharge_launches = timed;
+        st->discharge_bytes = (double)st->discharged_vertices * (double)mf_discharge_bytes_per_vertex(g->K);
+    }
+    return MF_OK;
+}
+
+extern "C" mf_status mf_flow_value(const mf_grid *g, int64_t *out) {
+    if (!g || !out) return MF_E_INVAL;
+    if (!g->solved) return MF_E_STATE;
+    *out = g->flow;
+    return MF_OK;
+}
+
+extern "C" mf_status mf_min_cut(const mf_grid *gc, int32_t kind, uint8_t *out_source_side) {
+    mf_grid *g = const_cast<mf_grid *>(gc);
+    if (!g || !out_source_side) return MF_E_INVAL;
+    if (kind != MF_CUT_MIN_SOURCE && kind != MF_CUT_MAX_SOURCE) return MF_E_INVAL;
+    if (!g->solved) return MF_E_STATE;
+    const Geo &G = g->G;
+    hipStream_t s = nullptr;
+    HIP_TRY(hipMemsetAsync(g->mark, 0, sizeof(int) * (size_t)G.N, s));
+    HIP_TRY(hipMemsetAsync(g->dirty, 0, sizeof(int) * 2 * (size_t)G.nreg, s));
+    mfd::FloodArgs A;
+    memset(&A, 0, sizeof(A));
+    A.G = G;
+    A.dir = kind == MF_CUT_MIN_SOURCE ? 0 : 1;
+    A.mark = g->mark;
+    A.res = g->res; A.ex = g->ex; A.rt = g->rt;
+    A.scratch = g->scratch;
+    A.changed = g->changed;
+    int blocks = std::min(G.nreg, g->nslots * 4);  // scratch holds 4V ints per slot
+    for (int round = 0;; round++) {
+        A.round = round;
+        A.dirtyIn = g->dirty + (size_t)(round & 1) * G.nreg;
+        A.dirtyOut = g->dirty + (size_t)((round + 1) & 1) * G.nreg;
+        HIP_TRY(hipMemsetAsync(g->changed, 0, sizeof(unsigned), s));
+        HIP_TRY(mfd::launch_flood(A, blocks, s));
+        HIP_TRY(hipMemcpyAsync(g->pinned, g->changed, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (*(unsigned *)g->pinned == 0u) break;
+        if (round > G.N + 8) return MF_E_DEVICE;
+    }
+    HIP_TRY(mfd::launch_cut_out(G, g->mark, g->cutbuf, (int)g->n, kind == MF_CUT_MAX_SOURCE ? 1 : 0, s));
+    HIP_TRY(hipMemcpyAsync(out_source_side, g->cutbuf, (size_t)g->n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MF_OK;
+}
+
+extern "C" mf_status mf_get_state(const mf_grid *gc, int32_t *res, int32_t *rt, int32_t *ex,
+                                  int32_t *labels) {
+    mf_grid *g = const_cast<mf_grid *>(gc);
+    if (!g) return MF_E_INVAL;
+    if (!g->solved) return MF_E_STATE;
+    const Geo &G = g->G;
+    size_t n = (size_t)g->n;
+    hipStream_t s = nullptr;
+    auto one = [&](const int *src, int32_t *dst) -> bool {
+        if (!dst) return true;
+        if (!ok(mfd::launch_gather_plane(G, src, g->tmp_plane, (int)n, s))) return false;
+        if (!ok(hipMemcpyAsync(dst, g->tmp_plane, n * sizeof(int), hipMemcpyDeviceToHost, s))) return false;
+        return ok(hipStreamSynchronize(s));
+    };
+    if (res)
+        for (int k = 0; k < g->K; k++)
+            if (!one(g->res + (size_t)k * G.N, res + (size_t)k * n)) return MF_E_DEVICE;
+    if (!one(g->rt, rt) || !one(g->ex, ex) || !one(g->lab[g->final_parity], labels)) return MF_E_DEVICE;
+    return MF_OK;
+}

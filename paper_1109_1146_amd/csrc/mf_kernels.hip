@@ -1,0 +1,683 @@
+// HIP kernels of the region-discharge max-flow solver for gfx950 (wave64).
+//
+// Data layout (HBM), all int32, blocked (region-major, see mf_device.h):
+//   res[k*N + g]   residual capacity c_f(g, g + o_k)
+//   rt[g]          residual t-link c_f(g, t)
+//   ex[g]          excess e_f(g)
+//   lab[p][g]      labels, two buffers: a sweep reads p and writes p ^ 1
+//   pushb[k*N + g] flow a discharge sent over the boundary arc (g, g + o_k),
+//                  consumed (and zeroed) by the fuse kernel
+#include "mf_device.h"
+#include "mf_launch.h"
+
+namespace mfd {
+
+typedef unsigned long long u64;
+
+__device__ __forceinline__ int wave_sum_i(int v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_min_i(int v) {
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Input validation (row-major inputs, before anything is written).
+// ---------------------------------------------------------------------------
+__global__ void k_validate(Geo G, const int *cs, const int *ct, const int *nbr, int n, int *err) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int x = v % G.dx, t = v / G.dx, y = t % G.dy, z = t / G.dy;
+    int bad = 0;
+    if (cs[v] < 0 || ct[v] < 0) bad |= 1;
+    long long inflow = cs[v] < 0 ? 0 : cs[v];
+    for (int k = 0; k < G.K; k++) {
+        int c = nbr[(size_t)k * n + v];
+        if (c < 0) { bad |= 1; continue; }
+        int zz = z + G.oz[k], yy = y + G.oy[k], xx = x + G.ox[k];
+        bool in = (unsigned)xx < (unsigned)G.dx && (unsigned)yy < (unsigned)G.dy &&
+                  (unsigned)zz < (unsigned)G.dz;
+        if (!in) {
+            if (c != 0) bad |= 1;
+            continue;
+        }
+        int w = (zz * G.dy + yy) * G.dx + xx;
+        int crev = nbr[(size_t)(k ^ 1) * n + w];  // c(w, v)
+        if (crev < 0) { bad |= 1; continue; }
+        if ((long long)c + crev > 0x7fffffffLL) bad |= 2;
+        inflow += crev;
+    }
+    if (inflow > 0x7fffffffLL) bad |= 2;
+    if (bad) atomicOr(err, bad);
+}
+
+// Sums of the s- and t-links (int64) for the flow value and the certificate.
+__global__ void k_sum_links(const int *cs, const int *ct, int n, u64 *out2) {
+    long long a = 0, b = 0;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        a += cs[v];
+        b += ct[v];
+    }
+    a = wave_sum_ll(a);
+    b = wave_sum_ll(b);
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&out2[0], (u64)a);
+        atomicAdd(&out2[1], (u64)b);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Init (Sec. 2): saturate s-links into the excess, f := 0, d := 0.
+// ---------------------------------------------------------------------------
+__global__ void k_init(Geo G, const int *cs, const int *ct, const int *nbr, int n, int *res,
+                       int *rt, int *ex, int *lab0, int *lab1, int *pushb, int *ractive,
+                       u64 *act0) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    int active = 0;
+    if (g < G.N) {
+        int z, y, x;
+        bool real = blocked_to_grid(G, g, z, y, x);
+        int e = 0, t = 0;
+        if (real) {
+            int v = (z * G.dy + y) * G.dx + x;
+            e = cs[v];
+            t = ct[v];
+            for (int k = 0; k < G.K; k++) res[(size_t)k * G.N + g] = nbr[(size_t)k * n + v];
+        } else {
+            for (int k = 0; k < G.K; k++) res[(size_t)k * G.N + g] = 0;
+        }
+        for (int k = 0; k < G.K; k++) pushb[(size_t)k * G.N + g] = 0;
+        ex[g] = e;
+        rt[g] = t;
+        lab0[g] = 0;
+        lab1[g] = 0;
+        if (e > 0) {
+            active = 1;
+            ractive[g / G.V] = 1;
+        }
+    }
+    active = wave_sum_i(active);
+    if ((threadIdx.x & 63) == 0 && active) atomicAdd(act0, (u64)active);
+}
+
+// ---------------------------------------------------------------------------
+// Region discharge (Proc. ARD of Sec. 4.2 with region relabel, Alg. 3).
+//
+// One workgroup owns one region at a time and takes regions from a queue.
+// ARD's staged Augment(R, T_k) is carried out as push-relabel with the
+// lexicographic label (k, hops): a multi-level breadth-first search from the
+// targets (t first, then boundary vertices w in increasing d(w) + 1; the
+// search never relabels a vertex twice, exactly as Alg. 3) yields for every
+// vertex u of R the smallest stage k with u -> T_k and its hop distance to
+// T_k.  Excess then flows downhill through the search levels, from the last
+// level to the first, along arcs that drop exactly one level inside a stage;
+// first-level vertices of stage 0 push to t, of stage k > 0 over boundary
+// arcs to w with d(w) + 1 = k.  Search and push alternate until no excess
+// vertex of R reaches T_{d_inf}.  The last search is the region relabel.
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
+    extern __shared__ int smem[];
+    __shared__ int s_r, s_active, s_qtail, s_nsteps, s_min, s_found;
+    __shared__ int s_wmin[NT / 64];
+    if (*A.actIn == 0ull) return;
+    const Geo &G = A.G;
+    const int V = G.V, N = G.N, tid = threadIdx.x;
+    int *S, *Q, *stepEnd, *stepLevel;
+    if (A.useLDS) {
+        S = smem;
+    } else {
+        S = A.scratch + (size_t)blockIdx.x * 4 * V;
+    }
+    Q = S + V;
+    stepEnd = Q + V;
+    stepLevel = stepEnd + V;
+    int *res = A.res, *rt = A.rt, *ex = A.ex, *pushb = A.pushb;
+    const int *labOld = A.labOld;
+    const int dinf = A.dinf;
+
+    for (;;) {
+        if (tid == 0) {
+            unsigned i = atomicAdd(A.qhead, 1u);
+            s_r = (i < (unsigned)A.nwork) ? A.order[i] : -1;
+        }
+        __syncthreads();
+        const int r = s_r;
+        if (r < 0) return;
+        const int base = r * V;
+        if (tid == 0) {
+            s_active = A.ractive[r];
+            A.ractive[r] = 0;
+        }
+        __syncthreads();
+        if (!s_active) {
+            // skipped region (no active vertex): labels carry over unchanged
+            for (int l = tid; l < V; l += NT) A.labNew[base + l] = labOld[base + l];
+            __syncthreads();
+            continue;
+        }
+
+        int iter = 0;
+        for (;;) {
+            // ---------------- multi-level search from the targets ----------------
+            for (int l = tid; l < V; l += NT) S[l] = kInf;
+            if (tid == 0) {
+                s_qtail = 0;
+                s_nsteps = 0;
+                s_found = 0;
+            }
+            __syncthreads();
+            for (int l = tid; l < V; l += NT) {
+                if (rt[base + l] > 0) {
+                    S[l] = 0;
+                    Q[atomicAdd(&s_qtail, 1)] = l;
+                }
+            }
+            __syncthreads();
+            if (tid == 0 && s_qtail > 0) {
+                stepEnd[0] = s_qtail;
+                stepLevel[0] = 0;
+                s_nsteps = 1;
+            }
+            __syncthreads();
+            int fs = 0;
+            for (;;) {
+                // flood inside the region: u with c_f(u, v) > 0 to a frontier v
+                for (;;) {
+                    const int fe = s_qtail;
+                    if (fs == fe) break;
+                    const int step = s_nsteps;
+                    for (int i = fs + tid; i < fe; i += NT) {
+                        int v = Q[i];
+                        int vz, vy, vx;
+                        local_xyz(G, v, vz, vy, vx);
+                        for (int k = 0; k < G.K; k++) {
+                            int u = local_nbr(G, vz, vy, vx, k ^ 1);  // u + o_k = v
+                            if (u < 0) continue;
+                            if (res[(size_t)k * N + base + u] > 0 && S[u] == kInf) {
+                                if (atomicCAS(&S[u], kInf, step) == kInf) Q[atomicAdd(&s_qtail, 1)] = u;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                    if (tid == 0 && s_qtail > fe) {
+                        stepEnd[step] = s_qtail;
+                        stepLevel[step] = step > 0 ? stepLevel[step - 1] : 0;
+                        s_nsteps = step + 1;
+                    }
+                    fs = fe;
+                    __syncthreads();
+                }
+                // next stage: smallest d(w) + 1 over residual boundary arcs of unlabeled u
+                int best = kInf;
+                for (int i = tid; i < A.nring; i += NT) {
+                    int l = A.ringL[i];
+                    if (S[l] != kInf) continue;
+                    unsigned m = A.ringM[i];
+                    int lz, ly, lx;
+                    local_xyz(G, l, lz, ly, lx);
+                    for (int k = 0; k < G.K; k++) {
+                        if (!((m >> k) & 1u)) continue;
+                        if (res[(size_t)k * N + base + l] <= 0) continue;
+                        int w = cross_nbr(G, r, lz, ly, lx, k);
+                        if (w < 0) continue;
+                        int d = labOld[w];
+                        if (d < dinf) best = min(best, d + 1);
+                    }
+                }
+                best = wave_min_i(best);
+                if ((tid & 63) == 0) s_wmin[tid >> 6] = best;
+                __syncthreads();
+                if (tid == 0) {
+                    int b = kInf;
+                    for (int w = 0; w < NT / 64; w++) b = min(b, s_wmin[w]);
+                    s_min = b;
+                }
+                __syncthreads();
+                const int level = s_min;
+                if (level == kInf) break;
+                const int step = s_nsteps;
+                for (int i = tid; i < A.nring; i += NT) {
+                    int l = A.ringL[i];
+                    if (S[l] != kInf) continue;
+                    unsigned m = A.ringM[i];
+                    int lz, ly, lx;
+                    local_xyz(G, l, lz, ly, lx);
+                    for (int k = 0; k < G.K; k++) {
+                        if (!((m >> k) & 1u)) continue;
+                        if (res[(size_t)k * N + base + l] <= 0) continue;
+                        int w = cross_nbr(G, r, lz, ly, lx, k);
+                        if (w < 0) continue;
+                        int d = labOld[w];
+                        if (d < dinf && d + 1 == level) {
+                            S[l] = step;
+                            Q[atomicAdd(&s_qtail, 1)] = l;
+                            break;
+                        }
+                    }
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    // at least one seed exists: level came from an unlabeled ring vertex
+                    stepEnd[step] = s_qtail;
+                    stepLevel[step] = level;
+                    s_nsteps = step + 1;
+                }
+                __syncthreads();
+            }
+            // ---------------- any excess vertex that reaches a target? ----------------
+            int found = 0;
+            for (int l = tid; l < V; l += NT)
+                if (S[l] != kInf && ex[base + l] > 0) found = 1;
+            if (found) s_found = 1;
+            __syncthreads();
+            if (!s_found) break;
+            if (++iter > A.maxIter) {
+                if (tid == 0) atomicOr(A.err, 4);
+                break;
+            }
+            // ---------------- push excess down the search levels ----------------
+            const int nsteps = s_nsteps;
+            for (int s = nsteps - 1; s >= 0; s--) {
+                const int lo = s > 0 ? stepEnd[s - 1] : 0, hi = stepEnd[s];
+                const int L = stepLevel[s];
+                const bool seed = (s == 0) || (stepLevel[s - 1] != L);
+                for (int i = lo + tid; i < hi; i += NT) {
+                    const int u = Q[i];
+                    int e = ex[base + u];
+                    if (e <= 0) continue;
+                    int uz, uy, ux;
+                    local_xyz(G, u, uz, uy, ux);
+                    if (seed) {
+                        if (L == 0) {
+                            int t = rt[base + u];
+                            if (t > 0) {
+                                int d = min(e, t);
+                                rt[base + u] = t - d;
+                                e -= d;
+                            }
+                        } else {
+                            for (int k = 0; k < G.K && e > 0; k++) {
+                                if (local_nbr(G, uz, uy, ux, k) >= 0) continue;
+                                const size_t a = (size_t)k * N + base + u;
+                                int c = res[a];
+                                if (c <= 0) continue;
+                                int w = cross_nbr(G, r, uz, uy, ux, k);
+                                if (w < 0) continue;
+                                int dw = labOld[w];
+                                if (dw >= dinf || dw + 1 != L) continue;
+                                int d = min(e, c);
+                                res[a] = c - d;
+                                pushb[a] += d;
+                                e -= d;
+                            }
+                        }
+                    } else {
+                        for (int k = 0; k < G.K && e > 0; k++) {
+                            int v = local_nbr(G, uz, uy, ux, k);
+                            if (v < 0) continue;
+                            const size_t a = (size_t)k * N + base + u;
+                            int c = res[a];
+                            if (c <= 0 || S[v] != s - 1) continue;
+                            int d = min(e, c);
+                            res[a] = c - d;
+                            res[(size_t)(k ^ 1) * N + base + v] += d;
+                            atomicAdd(&ex[base + v], d);
+                            e -= d;
+                        }
+                    }
+                    ex[base + u] = e;
+                }
+                __syncthreads();
+            }
+        }
+        // ---------------- region relabel result ----------------
+        for (int l = tid; l < V; l += NT) {
+            int s = S[l];
+            A.labNew[base + l] = (s == kInf) ? dinf : min(stepLevel[s], dinf);
+        }
+        if (tid == 0) {
+            atomicAdd(&A.stats[0], 1ull);
+            atomicAdd(&A.stats[1], (u64)A.rvcount[r]);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Flow fusion (Alg. 2): for every inter-region pair {u, v} a push u -> v stays
+// iff d'(v) <= d'(u) + 1, otherwise it returns to u; same for v -> u.  One
+// thread per boundary vertex handles its pairs in the canonical (even)
+// directions, so every pair has exactly one owner.  Also builds the histogram
+// of boundary labels for the gap heuristic.
+// ---------------------------------------------------------------------------
+__global__ void k_fuse(FuseArgs A) {
+    __shared__ unsigned int lh[kHistLds];
+    __shared__ int s_wmax[4];
+    if (*A.actIn == 0ull) return;
+    const Geo &G = A.G;
+    const int N = G.N;
+    for (int i = threadIdx.x; i < kHistLds; i += blockDim.x) lh[i] = 0;
+    __syncthreads();
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int mylab = -1;
+    if (i < A.nB) {
+        const int u = A.bidx[i];
+        const int r = u / G.V, l = u - r * G.V;
+        int lz, ly, lx;
+        local_xyz(G, l, lz, ly, lx);
+        const int du = A.lab[u];
+        int addu = 0;
+        for (int k = 0; k < G.K; k += 2) {
+            if (local_nbr(G, lz, ly, lx, k) >= 0) continue;
+            int v = cross_nbr(G, r, lz, ly, lx, k);
+            if (v < 0) continue;
+            const size_t auv = (size_t)k * N + u, avu = (size_t)(k ^ 1) * N + v;
+            int pout = A.pushb[auv], pin = A.pushb[avu];
+            if ((pout | pin) == 0) continue;
+            const int dv = A.lab[v];
+            A.pushb[auv] = 0;
+            A.pushb[avu] = 0;
+            int addv = 0;
+            if (pout) {
+                if (dv <= du + 1) { A.res[avu] += pout; addv += pout; }
+                else { A.res[auv] += pout; addu += pout; }
+            }
+            if (pin) {
+                if (du <= dv + 1) { A.res[auv] += pin; addu += pin; }
+                else { A.res[avu] += pin; addv += pin; }
+            }
+            if (addv) atomicAdd(&A.ex[v], addv);
+        }
+        if (addu) atomicAdd(&A.ex[u], addu);
+        if (du < A.dinf) {
+            mylab = du;
+            if (du < kHistLds) atomicAdd(&lh[du], 1u);
+            else if (du < kHistBins) atomicAdd(&A.hist[du], 1u);
+        }
+    }
+    int m = wave_max_i(mylab);
+    if ((threadIdx.x & 63) == 0) s_wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    for (int b = threadIdx.x; b < kHistLds; b += blockDim.x)
+        if (lh[b]) atomicAdd(&A.hist[b], lh[b]);
+    if (threadIdx.x == 0) {
+        int mm = -1;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) mm = max(mm, s_wmax[w]);
+        if (mm >= 0) atomicMax(A.maxlab, mm);
+    }
+}
+
+// Global gap (Sec. 5.1, over boundary labels): the smallest g >= 1 below the
+// highest boundary label with no boundary vertex labelled g.  Also closes the
+// sweep: counts it, resets the next sweep's queue and active counter.
+__global__ void k_gap_find(GapArgs A) {
+    __shared__ int s_wmin[16];
+    const int tid = threadIdx.x;
+    if (*A.actIn == 0ull) {
+        if (tid == 0) {
+            *A.actOut = 0ull;
+            *A.qheadNext = 0u;
+        }
+        return;
+    }
+    int top = *A.maxlab;
+    int lim = min(top, kHistBins);
+    int g = kInf;
+    if (A.gapOn) {
+        for (int l = 1 + tid; l < lim; l += blockDim.x)
+            if (A.hist[l] == 0u) { g = l; break; }
+    }
+    g = wave_min_i(g);
+    if ((tid & 63) == 0) s_wmin[tid >> 6] = g;
+    __syncthreads();
+    if (tid == 0) {
+        int b = kInf;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) b = min(b, s_wmin[w]);
+        *A.gap = (b == kInf) ? -1 : b;
+        *A.actOut = 0ull;
+        *A.qheadNext = 0u;
+        *A.maxlab = -1;
+        A.counters[0] += 1ull;  // sweeps
+    }
+    __syncthreads();
+    int clr = min(top + 1, kHistBins);
+    for (int l = tid; l < clr; l += blockDim.x) A.hist[l] = 0u;
+}
+
+__global__ void k_gap_apply(GapApplyArgs A) {
+    __shared__ int s_w[4];
+    if (*A.actIn == 0ull) return;
+    const Geo &G = A.G;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int act = 0;
+    if (i < A.nB) {
+        const int u = A.bidx[i];
+        const int g = *A.gap;
+        int d = A.lab[u];
+        if (g >= 0 && d > g && d < A.dinf) {
+            d = A.dinf;
+            A.lab[u] = d;
+        }
+        if (A.ex[u] > 0 && d < A.dinf) {
+            act = 1;
+            A.ractive[u / G.V] = 1;
+        }
+    }
+    act = wave_sum_i(act);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = act;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) t += s_w[w];
+        if (t) atomicAdd(A.actOut, (u64)t);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Results
+// ---------------------------------------------------------------------------
+__global__ void k_sum_i32(const int *a, int n, u64 *out) {
+    long long s = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) s += a[i];
+    s = wave_sum_ll(s);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(out, (u64)s);
+}
+
+// blocked -> row-major copy of one int32 plane
+__global__ void k_gather_plane(Geo G, const int *src, int *dst, int n) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int x = v % G.dx, t = v / G.dx, y = t % G.dy, z = t / G.dy;
+    dst[v] = src[grid_to_blocked(G, z, y, x)];
+}
+
+// Residual reachability by region floods: each workgroup floods its region
+// from the marked vertices, marks across the region border and flags the
+// neighbouring region for the next round.  dir 0: forward from the excess
+// vertices (minimal source side); dir 1: backward from t (the sink side T).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_flood(FloodArgs A) {
+    __shared__ int s_qtail, s_go;
+    const Geo &G = A.G;
+    const int V = G.V, N = G.N, tid = threadIdx.x;
+    int *Q = A.scratch + (size_t)blockIdx.x * V;
+    for (int r = blockIdx.x; r < G.nreg; r += gridDim.x) {
+        const int base = r * V;
+        if (tid == 0) {
+            s_go = (A.round == 0) ? 1 : A.dirtyIn[r];
+            A.dirtyIn[r] = 0;
+            s_qtail = 0;
+        }
+        __syncthreads();
+        if (!s_go) { __syncthreads(); continue; }
+        for (int l = tid; l < V; l += NT) {
+            int m = A.mark[base + l];
+            if (A.round == 0) {
+                int seed = (A.dir == 0) ? (A.ex[base + l] > 0) : (A.rt[base + l] > 0);
+                if (seed) { A.mark[base + l] = 1; m = 1; }
+            }
+            if (m) Q[atomicAdd(&s_qtail, 1)] = l;
+        }
+        __syncthreads();
+        int fs = 0;
+        for (;;) {
+            const int fe = s_qtail;
+            if (fs == fe) break;
+            for (int i = fs + tid; i < fe; i += NT) {
+                const int v = Q[i];
+                int vz, vy, vx;
+                local_xyz(G, v, vz, vy, vx);
+                for (int k = 0; k < G.K; k++) {
+                    if (A.dir == 0) {
+                        // forward: arc (v, v + o_k) with c_f > 0
+                        if (A.res[(size_t)k * N + base + v] <= 0) continue;
+                        int w = local_nbr(G, vz, vy, vx, k);
+                        if (w >= 0) {
+                            if (atomicExch(&A.mark[base + w], 1) == 0) Q[atomicAdd(&s_qtail, 1)] = w;
+                        } else {
+                            int wg = cross_nbr(G, r, vz, vy, vx, k);
+                            if (wg >= 0 && atomicExch(&A.mark[wg], 1) == 0) {
+                                A.dirtyOut[wg / V] = 1;
+                                atomicAdd(A.changed, 1u);
+                            }
+                        }
+                    } else {
+                        // backward: arc (u, v) with u = v - o_k and c_f(u, v) > 0
+                        int w = local_nbr(G, vz, vy, vx, k ^ 1);
+                        if (w >= 0) {
+                            if (A.res[(size_t)k * N + base + w] > 0 && atomicExch(&A.mark[base + w], 1) == 0)
+                                Q[atomicAdd(&s_qtail, 1)] = w;
+                        } else {
+                            int wg = cross_nbr(G, r, vz, vy, vx, k ^ 1);
+                            if (wg >= 0 && A.res[(size_t)k * N + wg] > 0 && atomicExch(&A.mark[wg], 1) == 0) {
+                                A.dirtyOut[wg / V] = 1;
+                                atomicAdd(A.changed, 1u);
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            fs = fe;
+            __syncthreads();
+        }
+    }
+}
+
+// blocked marks -> row-major source-side indicator
+__global__ void k_cut_out(Geo G, const int *mark, unsigned char *out, int n, int invert) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int x = v % G.dx, t = v / G.dx, y = t % G.dy, z = t / G.dy;
+    int m = mark[grid_to_blocked(G, z, y, x)] ? 1 : 0;
+    out[v] = (unsigned char)(invert ? 1 - m : m);
+}
+
+__global__ void k_fill_i32(int *p, int n, int val) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = val;
+}
+
+// ---------------------------------------------------------------------------
+// Launch wrappers
+// ---------------------------------------------------------------------------
+static inline int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
+
+hipError_t launch_validate(const Geo &G, const int *cs, const int *ct, const int *nbr, int n,
+                           int *err, hipStream_t s) {
+    hipLaunchKernelGGL(k_validate, dim3(cdiv(n, 256)), dim3(256), 0, s, G, cs, ct, nbr, n, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_links(const int *cs, const int *ct, int n, unsigned long long *out2,
+                            hipStream_t s) {
+    int blocks = min(cdiv(n, 256), 1024);
+    hipLaunchKernelGGL(k_sum_links, dim3(blocks), dim3(256), 0, s, cs, ct, n, out2);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const Geo &G, const int *cs, const int *ct, const int *nbr, int n, int *res,
+                       int *rt, int *ex, int *lab0, int *lab1, int *pushb, int *ractive,
+                       unsigned long long *act0, hipStream_t s) {
+    hipLaunchKernelGGL(k_init, dim3(cdiv(G.N, 256)), dim3(256), 0, s, G, cs, ct, nbr, n, res, rt,
+                       ex, lab0, lab1, pushb, ractive, act0);
+    return hipGetLastError();
+}
+
+hipError_t launch_discharge(const DischargeArgs &A, int blocks, int threads, size_t lds,
+                            hipStream_t s) {
+    static bool attr_done = false;
+    if (!attr_done && lds > 65536) {
+        (void)hipFuncSetAttribute((const void *)k_discharge<256>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipFuncSetAttribute((const void *)k_discharge<512>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipGetLastError();
+        attr_done = true;
+    }
+    if (threads == 256)
+        hipLaunchKernelGGL(k_discharge<256>, dim3(blocks), dim3(256), lds, s, A);
+    else if (threads == 512)
+        hipLaunchKernelGGL(k_discharge<512>, dim3(blocks), dim3(512), lds, s, A);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_fuse(const FuseArgs &A, hipStream_t s) {
+    if (A.nB == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fuse, dim3(cdiv(A.nB, 256)), dim3(256), 0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_gap_find(const GapArgs &A, hipStream_t s) {
+    hipLaunchKernelGGL(k_gap_find, dim3(1), dim3(1024), 0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_gap_apply(const GapApplyArgs &A, hipStream_t s) {
+    if (A.nB == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gap_apply, dim3(cdiv(A.nB, 256)), dim3(256), 0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_i32(const int *a, int n, unsigned long long *out, hipStream_t s) {
+    int blocks = min(cdiv(n, 256), 1024);
+    hipLaunchKernelGGL(k_sum_i32, dim3(blocks), dim3(256), 0, s, a, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_plane(const Geo &G, const int *src, int *dst, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_plane, dim3(cdiv(n, 256)), dim3(256), 0, s, G, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_flood(const FloodArgs &A, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_flood<256>, dim3(blocks), dim3(256), 0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_cut_out(const Geo &G, const int *mark, unsigned char *out, int n, int invert,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_cut_out, dim3(cdiv(n, 256)), dim3(256), 0, s, G, mark, out, n, invert);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int *p, int n, int val, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3(cdiv(n, 256)), dim3(256), 0, s, p, n, val);
+    return hipGetLastError();
+}
+
+}  // namespace mfd

@@ -1,0 +1,97 @@
+// Kernel argument blocks and launch wrappers (host side of mf_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "mf_device.h"
+
+namespace mfd {
+
+struct DischargeArgs {
+    Geo G;
+    int *res, *rt, *ex;
+    const int *labOld;
+    int *labNew;
+    int *pushb;
+    int *ractive;
+    const int *order;   // queue of regions in processing order
+    int nwork;
+    unsigned int *qhead;
+    const unsigned long long *actIn;  // active-vertex count at sweep start (0 => no-op)
+    int dinf;
+    int *scratch;       // 4*V ints per workgroup when the search arrays do not fit in LDS
+    const int *ringL;   // local indices of the tile's border vertices
+    const unsigned char *ringM;  // per border vertex: bit k set if direction k leaves the tile
+    int nring;
+    unsigned long long *stats;   // [0] regions discharged, [1] real vertices discharged
+    const int *rvcount;          // real (non-padding) vertices per region
+    int *err;
+    int useLDS;
+    int maxIter;
+};
+
+struct FuseArgs {
+    Geo G;
+    const int *bidx;
+    int nB;
+    int *res, *ex, *pushb;
+    const int *lab;
+    int dinf;
+    unsigned int *hist;
+    int *maxlab;
+    const unsigned long long *actIn;
+};
+
+struct GapArgs {
+    unsigned int *hist;
+    int *maxlab;
+    int *gap;
+    int gapOn;
+    const unsigned long long *actIn;
+    unsigned long long *actOut;
+    unsigned int *qheadNext;
+    unsigned long long *counters;  // [0] sweeps
+};
+
+struct GapApplyArgs {
+    Geo G;
+    const int *bidx;
+    int nB;
+    int *lab;
+    const int *ex;
+    int *ractive;
+    const int *gap;
+    int dinf;
+    const unsigned long long *actIn;
+    unsigned long long *actOut;
+};
+
+struct FloodArgs {
+    Geo G;
+    int dir;     // 0: forward from excess vertices, 1: backward from t
+    int round;
+    int *mark;
+    int *dirtyIn, *dirtyOut;
+    unsigned int *changed;
+    const int *res, *ex, *rt;
+    int *scratch;  // V ints per workgroup
+};
+
+hipError_t launch_validate(const Geo &G, const int *cs, const int *ct, const int *nbr, int n,
+                           int *err, hipStream_t s);
+hipError_t launch_sum_links(const int *cs, const int *ct, int n, unsigned long long *out2,
+                            hipStream_t s);
+hipError_t launch_init(const Geo &G, const int *cs, const int *ct, const int *nbr, int n, int *res,
+                       int *rt, int *ex, int *lab0, int *lab1, int *pushb, int *ractive,
+                       unsigned long long *act0, hipStream_t s);
+hipError_t launch_discharge(const DischargeArgs &A, int blocks, int threads, size_t lds,
+                            hipStream_t s);
+hipError_t launch_fuse(const FuseArgs &A, hipStream_t s);
+hipError_t launch_gap_find(const GapArgs &A, hipStream_t s);
+hipError_t launch_gap_apply(const GapApplyArgs &A, hipStream_t s);
+hipError_t launch_sum_i32(const int *a, int n, unsigned long long *out, hipStream_t s);
+hipError_t launch_gather_plane(const Geo &G, const int *src, int *dst, int n, hipStream_t s);
+hipError_t launch_flood(const FloodArgs &A, int blocks, hipStream_t s);
+hipError_t launch_cut_out(const Geo &G, const int *mark, unsigned char *out, int n, int invert,
+                          hipStream_t s);
+hipError_t launch_fill_i32(int *p, int n, int val, hipStream_t s);
+
+}  // namespace mfd

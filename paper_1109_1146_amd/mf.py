@@ -1,0 +1,223 @@
+"""Thin ctypes binding of libmfard.so (include/mf.h); argument marshalling only.
+
+Every step of the solve runs in the library's HIP kernels.  Host numpy arrays
+or device tensors (torch CUDA tensors on ROCm) may be passed as capacities;
+torch is used only for device memory and streams.  There is no CPU fallback:
+if the library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmfard.so")
+
+MF_OK, MF_E_INVAL, MF_E_NOMEM, MF_E_DEVICE, MF_E_STATE, MF_E_OVERFLOW, MF_E_SWEEPS = range(7)
+MF_CUT_MIN_SOURCE, MF_CUT_MAX_SOURCE = 0, 1
+MF_SCHED_PARD, MF_SCHED_COLORED, MF_SCHED_LEARNED, MF_SCHED_AUTO = 0, 1, 2, 3
+
+EXPORTED = ("mf_create_grid", "mf_set_caps", "mf_solve", "mf_flow_value", "mf_min_cut",
+            "mf_get_state", "mf_get_info", "mf_discharge_bytes_per_vertex", "mf_destroy",
+            "mf_status_str")
+
+
+class mf_solve_opts(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int32), ("global_relabel_every", ctypes.c_int32),
+                ("gap", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("max_sweeps", ctypes.c_int64), ("model", ctypes.c_void_p),
+                ("stream", ctypes.c_void_p), ("profile", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class mf_solve_stats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("region_discharges", ctypes.c_int64),
+                ("boundary_size", ctypes.c_int64), ("d_inf", ctypes.c_int64),
+                ("solve_ms", ctypes.c_double), ("discharge_ms", ctypes.c_double),
+                ("discharge_launches", ctypes.c_int64), ("discharge_bytes", ctypes.c_double),
+                ("discharged_vertices", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class MFError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {status_str(status)} (status {status})")
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmfard.so and declare the C ABI; raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library {path} is missing; build it with "
+                           "`python -m paper_1109_1146_amd.build` (there is no CPU fallback)")
+    # torch ships its own libamdhip64.so.7; loading it first makes the library
+    # bind to that same HIP runtime, so device pointers and streams from torch
+    # are valid in both (two runtimes in one process leave torch without GPUs).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.mf_create_grid.argtypes = [ctypes.c_int32, P, ctypes.c_int32, P, ctypes.POINTER(P)]
+    lib.mf_create_grid.restype = ctypes.c_int
+    lib.mf_set_caps.argtypes = [P, P, P, P, ctypes.c_int32, P]
+    lib.mf_set_caps.restype = ctypes.c_int
+    lib.mf_solve.argtypes = [P, ctypes.POINTER(mf_solve_opts), ctypes.POINTER(mf_solve_stats)]
+    lib.mf_solve.restype = ctypes.c_int
+    lib.mf_flow_value.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+    lib.mf_flow_value.restype = ctypes.c_int
+    lib.mf_min_cut.argtypes = [P, ctypes.c_int32, P]
+    lib.mf_min_cut.restype = ctypes.c_int
+    lib.mf_get_state.argtypes = [P, P, P, P, P]
+    lib.mf_get_state.restype = ctypes.c_int
+    lib.mf_get_info.argtypes = [P, P, P, P, P, P]
+    lib.mf_get_info.restype = ctypes.c_int
+    lib.mf_discharge_bytes_per_vertex.argtypes = [ctypes.c_int32]
+    lib.mf_discharge_bytes_per_vertex.restype = ctypes.c_int64
+    lib.mf_destroy.argtypes = [P]
+    lib.mf_destroy.restype = None
+    lib.mf_status_str.argtypes = [ctypes.c_int]
+    lib.mf_status_str.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_str(status: int) -> str:
+    return load().mf_status_str(int(status)).decode()
+
+
+def _check(status, where):
+    if status != MF_OK:
+        raise MFError(status, where)
+
+
+def _ptr(a):
+    """Host numpy array or device tensor -> (pointer, on_device)."""
+    if isinstance(a, np.ndarray):
+        if a.dtype != np.int32 or not a.flags["C_CONTIGUOUS"]:
+            raise TypeError("capacity arrays must be C-contiguous int32")
+        return ctypes.c_void_p(a.ctypes.data), 0
+    # torch tensor (duck-typed so this module does not import torch)
+    if getattr(a, "dtype", None) is not None and hasattr(a, "data_ptr"):
+        import torch
+        if a.dtype != torch.int32 or not a.is_contiguous():
+            raise TypeError("capacity tensors must be contiguous int32")
+        return ctypes.c_void_p(a.data_ptr()), 1 if a.is_cuda else 0
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+def discharge_bytes_per_vertex(connectivity: int) -> int:
+    return int(load().mf_discharge_bytes_per_vertex(int(connectivity)))
+
+
+class Grid:
+    """One solver handle (mf_create_grid ... mf_destroy)."""
+
+    def __init__(self, dims, connectivity, region_shape=None):
+        lib = load()
+        self.dims = tuple(int(d) for d in dims)
+        self.ndim = len(self.dims)
+        self.conn = int(connectivity)
+        d = (ctypes.c_int64 * self.ndim)(*self.dims)
+        rs = None
+        if region_shape is not None:
+            rs = (ctypes.c_int32 * self.ndim)(*[int(t) for t in region_shape])
+        h = ctypes.c_void_p()
+        _check(lib.mf_create_grid(self.ndim, d, self.conn, rs, ctypes.byref(h)), "mf_create_grid")
+        self._h = h
+        self.n = int(np.prod(self.dims))
+        self.K = self.conn
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().mf_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def info(self):
+        n = ctypes.c_int64()
+        K = ctypes.c_int32()
+        regs = ctypes.c_int64()
+        b = ctypes.c_int64()
+        rs = (ctypes.c_int32 * 3)()
+        _check(load().mf_get_info(self._h, ctypes.byref(n), ctypes.byref(K), ctypes.byref(regs),
+                                  ctypes.byref(b), rs), "mf_get_info")
+        return dict(n=n.value, K=K.value, regions=regs.value, boundary_size=b.value,
+                    region_shape=tuple(rs[3 - self.ndim:]))
+
+    def set_caps(self, cs, ct, nbr, stream=None):
+        p1, d1 = _ptr(cs)
+        p2, d2 = _ptr(ct)
+        p3, d3 = _ptr(nbr)
+        if not (d1 == d2 == d3):
+            raise ValueError("capacity arrays must all be on the host or all on the device")
+        for a, size in ((cs, self.n), (ct, self.n), (nbr, self.K * self.n)):
+            numel = a.size if isinstance(a, np.ndarray) else a.numel()
+            if int(numel) != size:
+                raise ValueError(f"expected {size} capacities, got {int(numel)}")
+        st = ctypes.c_void_p(stream) if stream else None
+        _check(load().mf_set_caps(self._h, p1, p2, p3, d1, st), "mf_set_caps")
+
+    def solve(self, schedule=MF_SCHED_PARD, gap=True, global_relabel_every=0, check_every=0,
+              max_sweeps=0, stream=None, profile=False):
+        o = mf_solve_opts(schedule=schedule, global_relabel_every=global_relabel_every,
+                          gap=1 if gap else 0, check_every=check_every, max_sweeps=max_sweeps,
+                          model=None, stream=stream, profile=1 if profile else 0, reserved=0)
+        s = mf_solve_stats()
+        _check(load().mf_solve(self._h, ctypes.byref(o), ctypes.byref(s)), "mf_solve")
+        return s.as_dict()
+
+    def flow_value(self):
+        f = ctypes.c_int64()
+        _check(load().mf_flow_value(self._h, ctypes.byref(f)), "mf_flow_value")
+        return int(f.value)
+
+    def min_cut(self, kind=MF_CUT_MIN_SOURCE):
+        out = np.zeros(self.n, dtype=np.uint8)
+        _check(load().mf_min_cut(self._h, int(kind), ctypes.c_void_p(out.ctypes.data)),
+               "mf_min_cut")
+        return out
+
+    def state(self):
+        res = np.zeros((self.K, self.n), dtype=np.int32)
+        rt = np.zeros(self.n, dtype=np.int32)
+        ex = np.zeros(self.n, dtype=np.int32)
+        lab = np.zeros(self.n, dtype=np.int32)
+        P = lambda a: ctypes.c_void_p(a.ctypes.data)
+        _check(load().mf_get_state(self._h, P(res), P(rt), P(ex), P(lab)), "mf_get_state")
+        return dict(res=res, rt=rt, ex=ex, labels=lab)
+
+
+def solve_instance(inst, tile=None, **solve_kw):
+    """Solve a synth.GridInstance; returns dict(flow, smin, smax, stats)."""
+    tile = tile if tile is not None else inst.tile
+    with Grid(inst.dims, inst.conn, tile) as g:
+        g.set_caps(np.ascontiguousarray(inst.cs, np.int32), np.ascontiguousarray(inst.ct, np.int32),
+                   np.ascontiguousarray(inst.nbr, np.int32))
+        st = g.solve(**solve_kw)
+        out = dict(flow=g.flow_value(), smin=g.min_cut(MF_CUT_MIN_SOURCE),
+                   smax=g.min_cut(MF_CUT_MAX_SOURCE), stats=st, info=g.info())
+        out["state"] = g.state()
+    return out
