@@ -77,8 +77,35 @@ typedef struct {
     const void *model;            /* scorer weights for MF_SCHED_LEARNED, else NULL */
     void *stream;                 /* hipStream_t to run on; NULL = the null stream */
     int32_t profile;              /* 1 = time every discharge launch with HIP events */
-    int32_t reserved;
+    int32_t region_kernel;        /* MF_KERNEL_*: where a discharging region lives */
+    int32_t *trace;               /* device buffer of MF_TRACE_FIELDS x trace_cap int32, or NULL:
+                                     one record per region discharge, see MF_TR_* */
+    int64_t trace_cap;            /* records the trace buffer holds; extra records are dropped */
 } mf_solve_opts;
+
+/* trace record fields (int32 each) */
+enum {
+    MF_TR_SWEEP = 0,      /* sweep index, from 0 */
+    MF_TR_REGION = 1,     /* region id (z-major over the region grid) */
+    MF_TR_ROUNDS = 2,     /* search + push rounds of the discharge */
+    MF_TR_LEVELS = 3,     /* breadth-first search levels over all rounds */
+    MF_TR_STAGES = 4,     /* boundary stages opened over all rounds */
+    MF_TR_TICKS = 5,      /* duration in ticks of the 100 MHz device wall clock */
+    MF_TR_EXCESS_IN = 6,  /* total excess of the region when the discharge started (saturated) */
+    MF_TR_TO_SINK = 7,    /* flow the discharge sent to t */
+    MF_TR_TO_BOUNDARY = 8,/* flow the discharge pushed over boundary arcs */
+    MF_TR_LABEL_SUM = 9,  /* sum over the region's boundary vertices of min(new label, 65535) */
+    MF_TRACE_FIELDS = 10
+};
+
+/* region_kernel values */
+enum {
+    MF_KERNEL_AUTO = 0, /* WAVE for 2D regions up to 64 x 64, else LDS when it fits, else HBM */
+    MF_KERNEL_HBM = 1,  /* region state stays in HBM; search arrays in LDS or HBM scratch */
+    MF_KERNEL_LDS = 2,  /* whole region in LDS, one workgroup; MF_E_INVAL if it does not fit */
+    MF_KERNEL_WAVE = 3  /* 2D region of at most 64 x 64 in LDS, one wavefront, row-bitmask
+                           search; MF_E_INVAL if not applicable */
+};
 
 typedef struct {
     int64_t sweeps;             /* sweeps that started with an active vertex (Sec. 3) */
@@ -90,6 +117,16 @@ typedef struct {
     int64_t discharge_launches; /* profile=1: number of timed discharge launches */
     double discharge_bytes;     /* algorithmic bytes of all discharges, see mf_discharge_bytes_per_vertex */
     int64_t discharged_vertices;/* real vertices in discharged regions, summed over sweeps */
+    int64_t discharge_iterations; /* search + push rounds, summed over all discharges */
+    int64_t search_levels;      /* breadth-first search levels, summed over all searches */
+    int64_t search_stages;      /* boundary stages opened by the searches (targets d(w)+1) */
+    int64_t trace_records;      /* records written to opts->trace (may exceed trace_cap) */
+    int64_t search_ticks;       /* 100 MHz device-clock ticks in searches, summed over workgroups */
+    int64_t push_ticks;         /* 100 MHz device-clock ticks in push passes, summed over workgroups */
+    int64_t setup_ticks;        /* part of search_ticks spent resetting and seeding a search */
+    int64_t flood_ticks;        /* part of search_ticks spent in the in-region floods */
+    int64_t global_relabels;    /* exact region-distance relabels performed */
+    int64_t global_relabel_levels; /* distance levels over all global relabels */
 } mf_solve_stats;
 
 /* Create a solver handle for a grid shape and region partition.

@@ -27,11 +27,13 @@ struct mf_grid {
     int *res = nullptr, *rt = nullptr, *ex = nullptr, *lab[2] = {nullptr, nullptr};
     int *pushb = nullptr, *ractive = nullptr, *order = nullptr, *bidx = nullptr;
     int *ringL = nullptr, *rvcount = nullptr, *mark = nullptr, *dirty = nullptr;
-    unsigned char *ringM = nullptr, *cutbuf = nullptr;
+    unsigned char *ringM = nullptr, *cutbuf = nullptr, *cand = nullptr;  // cand: 2 x N
     int *in_cs = nullptr, *in_ct = nullptr, *in_nbr = nullptr;
     int *scratch = nullptr;
     int nslots = 0;
     bool useLDS = false;
+    size_t ldsMax = 0;            // LDS bytes a workgroup may use
+    int maxPair = 0, maxCt = 0;   // largest c(u,v)+c(v,u) and c(v,t) of the loaded instance
     int threads = 256;
     // device control block
     u64 *act = nullptr;           // [2]
@@ -67,7 +69,7 @@ static void free_all(mf_grid *g) {
                     g->bidx, g->ringL, g->rvcount, g->mark, g->dirty, g->ringM, g->cutbuf,
                     g->in_cs, g->in_ct, g->in_nbr, g->scratch, g->act, g->qhead, g->hist,
                     g->maxlab, g->gap, g->err, g->counters, g->stats, g->sums, g->changed,
-                    g->tmp_plane};
+                    g->tmp_plane, g->cand};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (g->pinned) (void)hipHostFree(g->pinned);
@@ -196,6 +198,7 @@ extern "C" mf_status mf_create_grid(int32_t ndim, const int64_t *dims, int32_t c
         return MF_E_DEVICE;
     }
     g->numCU = prop.multiProcessorCount;
+    g->ldsMax = (size_t)prop.sharedMemPerBlock;
     g->threads = 256;
     // the four search arrays (16 B per vertex) live in LDS when they fit beside
     // the kernel's static shared words; otherwise in per-workgroup HBM scratch
@@ -210,14 +213,15 @@ extern "C" mf_status mf_create_grid(int32_t ndim, const int64_t *dims, int32_t c
                 ok(dalloc(&g->rvcount, (size_t)G.nreg)) && ok(dalloc(&g->dirty, 2 * (size_t)G.nreg)) &&
                 ok(dalloc(&g->bidx, (size_t)g->nB)) && ok(dalloc(&g->ringL, (size_t)g->nring)) &&
                 ok(dalloc(&g->ringM, (size_t)g->nring)) && ok(dalloc(&g->cutbuf, (size_t)n)) &&
+                ok(dalloc(&g->cand, 2 * N)) &&
                 ok(dalloc(&g->in_cs, (size_t)n)) && ok(dalloc(&g->in_ct, (size_t)n)) &&
                 ok(dalloc(&g->in_nbr, K * (size_t)n)) && ok(dalloc(&g->tmp_plane, (size_t)n)) &&
                 ok(dalloc(&g->scratch, (size_t)g->nslots * 4 * G.V)) && ok(dalloc(&g->act, 2)) &&
                 ok(dalloc(&g->qhead, 2)) && ok(dalloc(&g->hist, (size_t)mfd::kHistBins)) &&
-                ok(dalloc(&g->maxlab, 1)) && ok(dalloc(&g->gap, 1)) && ok(dalloc(&g->err, 1)) &&
-                ok(dalloc(&g->counters, 4)) && ok(dalloc(&g->stats, 2)) && ok(dalloc(&g->sums, 4)) &&
+                ok(dalloc(&g->maxlab, 1)) && ok(dalloc(&g->gap, 1)) && ok(dalloc(&g->err, 4)) &&
+                ok(dalloc(&g->counters, 4)) && ok(dalloc(&g->stats, 16)) && ok(dalloc(&g->sums, 4)) &&
                 ok(dalloc(&g->changed, 1)) &&
-                ok(hipHostMalloc((void **)&g->pinned, 16 * sizeof(u64), hipHostMallocDefault));
+                ok(hipHostMalloc((void **)&g->pinned, 32 * sizeof(u64), hipHostMallocDefault));
     if (!good) {
         (void)hipGetLastError();
         free_all(g);
@@ -273,20 +277,58 @@ extern "C" mf_status mf_set_caps(mf_grid *g, const int32_t *src_cap, const int32
     HIP_TRY(hipMemcpyAsync(g->in_cs, src_cap, n * sizeof(int), kind, s));
     HIP_TRY(hipMemcpyAsync(g->in_ct, sink_cap, n * sizeof(int), kind, s));
     HIP_TRY(hipMemcpyAsync(g->in_nbr, nbr_cap, K * n * sizeof(int), kind, s));
-    HIP_TRY(hipMemsetAsync(g->err, 0, sizeof(int), s));
+    HIP_TRY(hipMemsetAsync(g->err, 0, 4 * sizeof(int), s));
     HIP_TRY(hipMemsetAsync(g->sums, 0, 4 * sizeof(u64), s));
     HIP_TRY(mfd::launch_validate(g->G, g->in_cs, g->in_ct, g->in_nbr, (int)n, g->err, s));
     HIP_TRY(mfd::launch_sum_links(g->in_cs, g->in_ct, (int)n, g->sums, s));
     HIP_TRY(hipMemcpyAsync(g->pinned, g->sums, 2 * sizeof(u64), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(g->pinned + 2, g->err, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(g->pinned + 2, g->err, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    int err = *(int *)(g->pinned + 2);
+    int err = ((int *)(g->pinned + 2))[0];
+    g->maxPair = ((int *)(g->pinned + 2))[1];
+    g->maxCt = ((int *)(g->pinned + 2))[2];
     if (err & 1) return MF_E_INVAL;
     if (err & 2) return MF_E_OVERFLOW;
     g->sum_cs = (long long)g->pinned[0];
     g->sum_ct = (long long)g->pinned[1];
     g->has_caps = true;
     return MF_OK;
+}
+
+// Exact region-distance labels into lab (see k_grelabel), then the active
+// regions and the active-vertex count *act for the next sweep.  Returns the
+// number of distance levels, or -1 on a HIP error.
+static int global_relabel(mf_grid *g, int *lab, u64 *act, hipStream_t s) {
+    const Geo &G = g->G;
+    if (!ok(mfd::launch_fill_i32(lab, G.N, g->dinf, s))) return -1;
+    if (!ok(hipMemsetAsync(g->cand, 0, 2 * (size_t)G.N, s))) return -1;
+    if (!ok(hipMemsetAsync(g->dirty, 0, sizeof(int) * 2 * (size_t)G.nreg, s))) return -1;
+    mfd::GRelabelArgs A;
+    memset(&A, 0, sizeof(A));
+    A.G = G;
+    A.res = g->res; A.rt = g->rt; A.lab = lab;
+    A.ringL = g->ringL; A.nring = g->nring; A.dinf = g->dinf;
+    A.scratch = g->scratch;
+    A.flagged = g->changed;
+    const int blocks = std::min(G.nreg, g->nslots * 4);
+    int D = 0;
+    for (;; D++) {
+        A.level = D;
+        A.candIn = g->cand + (size_t)(D & 1) * G.N;
+        A.candOut = g->cand + (size_t)((D + 1) & 1) * G.N;
+        A.flagIn = g->dirty + (size_t)(D & 1) * G.nreg;
+        A.flagOut = g->dirty + (size_t)((D + 1) & 1) * G.nreg;
+        if (!ok(hipMemsetAsync(g->changed, 0, sizeof(unsigned), s))) return -1;
+        if (!ok(mfd::launch_grelabel(A, blocks, s))) return -1;
+        if (!ok(hipMemcpyAsync(g->pinned + 14, g->changed, sizeof(unsigned), hipMemcpyDeviceToHost, s))) return -1;
+        if (!ok(hipStreamSynchronize(s))) return -1;
+        if (*(unsigned *)(g->pinned + 14) == 0u) break;
+        if (D > g->dinf + 1) return -1;
+    }
+    if (!ok(hipMemsetAsync(g->ractive, 0, sizeof(int) * G.nreg, s))) return -1;
+    if (!ok(hipMemsetAsync(act, 0, sizeof(u64), s))) return -1;
+    if (!ok(mfd::launch_activity(G, g->ex, lab, g->dinf, g->ractive, act, s))) return -1;
+    return D + 1;
 }
 
 extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_stats *st) {
@@ -299,6 +341,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     if (o.schedule < 0 || o.schedule > MF_SCHED_AUTO) return MF_E_INVAL;
     if (o.schedule == MF_SCHED_COLORED || o.schedule == MF_SCHED_LEARNED) return MF_E_INVAL;
     int check_every = o.check_every > 0 ? o.check_every : 8;
+    if (o.global_relabel_every < 0) return MF_E_INVAL;
+    if (o.global_relabel_every > 0) check_every = o.global_relabel_every;
     long long B = g->nB > 0 ? g->nB : 1;
     long long bound = (B > 2000000000LL) ? (1LL << 62) : 2 * B * B + 1;
     long long max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : bound;
@@ -315,7 +359,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     HIP_TRY(hipMemsetAsync(g->gap, 0xff, sizeof(int), s));
     HIP_TRY(hipMemsetAsync(g->err, 0, sizeof(int), s));
     HIP_TRY(hipMemsetAsync(g->counters, 0, 4 * sizeof(u64), s));
-    HIP_TRY(hipMemsetAsync(g->stats, 0, 2 * sizeof(u64), s));
+    HIP_TRY(hipMemsetAsync(g->stats, 0, 16 * sizeof(u64), s));
     HIP_TRY(hipMemsetAsync(g->ractive, 0, sizeof(int) * G.nreg, s));
     HIP_TRY(mfd::launch_init(G, g->in_cs, g->in_ct, g->in_nbr, (int)g->n, g->res, g->rt, g->ex,
                              g->lab[0], g->lab[1], g->pushb, g->ractive, g->act, s));
@@ -329,8 +373,44 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     D.nring = g->nring; D.stats = g->stats; D.rvcount = g->rvcount; D.err = g->err;
     D.useLDS = g->useLDS ? 1 : 0;
     D.maxIter = 1 << 18;
+    D.trace = o.trace;
+    D.traceCap = o.trace ? o.trace_cap : 0;
     size_t lds = g->useLDS ? (size_t)16 * G.V : 0;
-
+    // Region kernels: a single wavefront with row bitmasks for 2D regions of
+    // at most 64 x 64 (WAVE), one workgroup with the whole region in LDS
+    // (LDS), or the region left in HBM (HBM).  LDS-resident residuals are int16
+    // when every residual (bounded by its pair sum) and t-link fits, else int32.
+    const size_t ldsBudget = g->ldsMax > 512 ? g->ldsMax - 512 : 0;
+    const bool narrowOk = g->maxPair <= 32767 && g->maxCt <= 32767;
+    size_t waveLds = 0, groupLds = 0;
+    int waveNarrow = 0, groupNarrow = 0;
+    if (g->ndim == 2 && G.tz == 1 && G.tx <= 64 && G.ty <= 64) {
+        size_t b16 = mfd::discharge_wave_bytes(G.V, G.K, g->nring, 1);
+        size_t b32 = mfd::discharge_wave_bytes(G.V, G.K, g->nring, 0);
+        if (narrowOk && b16 <= ldsBudget) { waveLds = b16; waveNarrow = 1; }
+        else if (b32 <= ldsBudget) { waveLds = b32; }
+    }
+    if (G.V <= 32767) {
+        size_t b16 = mfd::discharge_lds_bytes(G.V, G.K, g->nring, 1);
+        size_t b32 = mfd::discharge_lds_bytes(G.V, G.K, g->nring, 0);
+        if (narrowOk && b16 <= ldsBudget) { groupLds = b16; groupNarrow = 1; }
+        else if (b32 <= ldsBudget) { groupLds = b32; }
+    }
+    int regionMode = 0;  // 0: HBM, 1: LDS workgroup, 2: wavefront
+    switch (o.region_kernel) {
+        case MF_KERNEL_AUTO: regionMode = waveLds ? 2 : (groupLds ? 1 : 0); break;
+        case MF_KERNEL_HBM: regionMode = 0; break;
+        case MF_KERNEL_LDS: if (!groupLds) return MF_E_INVAL; regionMode = 1; break;
+        case MF_KERNEL_WAVE: if (!waveLds) return MF_E_INVAL; regionMode = 2; break;
+        default: return MF_E_INVAL;
+    }
+    const size_t regionLds = regionMode == 2 ? waveLds : groupLds;
+    const int regionNarrow = regionMode == 2 ? waveNarrow : groupNarrow;
+    int regionBlocks = g->nslots;
+    if (regionMode) {
+        int occ = (int)std::max<size_t>(1, std::min<size_t>(8, g->ldsMax / (regionLds + 256)));
+        regionBlocks = std::max(1, std::min(G.nreg, g->numCU * occ));
+    }
     mfd::FuseArgs F;
     memset(&F, 0, sizeof(F));
     F.G = G; F.bidx = g->bidx; F.nB = (int)g->nB; F.res = g->res; F.ex = g->ex; F.pushb = g->pushb;
@@ -353,14 +433,28 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     double discharge_ms = 0.0;
     long long timed = 0;
     long long sweep = 0;
+    long long relabels = 0, relabel_levels = 0;
     mf_status status = MF_OK;
     for (;;) {
+        if (o.global_relabel_every > 0) {
+            const int p = (int)(sweep & 1);
+            int lv = global_relabel(g, g->lab[p], g->act + p, s);
+            if (lv < 0) return MF_E_DEVICE;
+            relabels++;
+            relabel_levels += lv;
+        }
         for (int j = 0; j < check_every; j++, sweep++) {
             const int p = (int)(sweep & 1);
             D.labOld = g->lab[p]; D.labNew = g->lab[p ^ 1];
             D.actIn = g->act + p; D.qhead = g->qhead + p;
+            D.sweep = (int)sweep;
             if (o.profile) HIP_TRY(hipEventRecord(ev[2 * j], s));
-            HIP_TRY(mfd::launch_discharge(D, g->nslots, g->threads, lds, s));
+            if (regionMode == 2)
+                HIP_TRY(mfd::launch_discharge_wave(D, regionBlocks, regionLds, regionNarrow, s));
+            else if (regionMode == 1)
+                HIP_TRY(mfd::launch_discharge_lds(D, regionBlocks, regionLds, regionNarrow, s));
+            else
+                HIP_TRY(mfd::launch_discharge(D, g->nslots, g->threads, lds, s));
             if (o.profile) HIP_TRY(hipEventRecord(ev[2 * j + 1], s));
             F.lab = g->lab[p ^ 1]; F.actIn = g->act + p;
             HIP_TRY(mfd::launch_fuse(F, s));
@@ -386,7 +480,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                 timed++;
             }
         }
-        if (*(int *)(g->pinned + 2) != 0) { status = MF_E_DEVICE; break; }
+        if (*(int *)(g->pinned + 2) & 4) { status = MF_E_DEVICE; break; }
         if (g->pinned[0] == 0ull) break;
         if ((long long)g->pinned[1] >= max_sweeps) { status = MF_E_SWEEPS; break; }
     }
@@ -398,7 +492,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     HIP_TRY(hipMemsetAsync(g->sums + 2, 0, sizeof(u64), s));
     HIP_TRY(mfd::launch_sum_i32(g->rt, G.N, g->sums + 2, s));
     HIP_TRY(hipMemcpyAsync(g->pinned + 3, g->sums + 2, sizeof(u64), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(g->pinned + 4, g->stats, 2 * sizeof(u64), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(g->pinned + 16, g->stats, 16 * sizeof(u64), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     g->flow = g->sum_ct - (long long)g->pinned[3];
     g->solved = true;
@@ -406,8 +500,18 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     if (st) {
         memset(st, 0, sizeof(*st));
         st->sweeps = sweeps;
-        st->region_discharges = (int64_t)g->pinned[4];
-        st->discharged_vertices = (int64_t)g->pinned[5];
+        st->region_discharges = (int64_t)g->pinned[16];
+        st->discharged_vertices = (int64_t)g->pinned[17];
+        st->discharge_iterations = (int64_t)g->pinned[18];
+        st->search_levels = (int64_t)g->pinned[19];
+        st->search_stages = (int64_t)g->pinned[20];
+        st->trace_records = (int64_t)g->pinned[21];
+        st->search_ticks = (int64_t)g->pinned[22];
+        st->push_ticks = (int64_t)g->pinned[23];
+        st->setup_ticks = (int64_t)g->pinned[24];
+        st->flood_ticks = (int64_t)g->pinned[25];
+        st->global_relabels = relabels;
+        st->global_relabel_levels = relabel_levels;
         st->boundary_size = g->nB;
         st->d_inf = g->dinf;
         st->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();

@@ -54,10 +54,13 @@ __global__ void k_validate(Geo G, const int *cs, const int *ct, const int *nbr, 
         int w = (zz * G.dy + yy) * G.dx + xx;
         int crev = nbr[(size_t)(k ^ 1) * n + w];  // c(w, v)
         if (crev < 0) { bad |= 1; continue; }
-        if ((long long)c + crev > 0x7fffffffLL) bad |= 2;
+        long long pair = (long long)c + crev;
+        if (pair > 0x7fffffffLL) bad |= 2;
+        else atomicMax(&err[1], (int)pair);
         inflow += crev;
     }
     if (inflow > 0x7fffffffLL) bad |= 2;
+    if (ct[v] > 0) atomicMax(&err[2], ct[v]);
     if (bad) atomicOr(err, bad);
 }
 
@@ -168,6 +171,7 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
         }
 
         int iter = 0;
+        long long bfs_steps = 0, classes = 0;
         for (;;) {
             // ---------------- multi-level search from the targets ----------------
             for (int l = tid; l < V; l += NT) S[l] = kInf;
@@ -246,6 +250,7 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
                 __syncthreads();
                 const int level = s_min;
                 if (level == kInf) break;
+                classes++;
                 const int step = s_nsteps;
                 for (int i = tid; i < A.nring; i += NT) {
                     int l = A.ringL[i];
@@ -275,6 +280,7 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
                 }
                 __syncthreads();
             }
+            bfs_steps += s_nsteps;
             // ---------------- any excess vertex that reaches a target? ----------------
             int found = 0;
             for (int l = tid; l < V; l += NT)
@@ -349,6 +355,9 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
         if (tid == 0) {
             atomicAdd(&A.stats[0], 1ull);
             atomicAdd(&A.stats[1], (u64)A.rvcount[r]);
+            atomicAdd(&A.stats[2], (u64)(iter + 1));
+            atomicAdd(&A.stats[3], (u64)bfs_steps);
+            atomicAdd(&A.stats[4], (u64)classes);
         }
         __syncthreads();
     }
@@ -677,6 +686,116 @@ hipError_t launch_cut_out(const Geo &G, const int *mark, unsigned char *out, int
 hipError_t launch_fill_i32(int *p, int n, int val, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_i32, dim3(cdiv(n, 256)), dim3(256), 0, s, p, n, val);
+    return hipGetLastError();
+}
+
+}  // namespace mfd
+
+namespace mfd {
+
+// ---------------------------------------------------------------------------
+// Global relabel: exact region distance d*B (Sec. 4.1) by a breadth-first
+// search from t in which arcs inside a region have length 0 and arcs between
+// regions length 1.  One launch per distance D: every flagged region floods
+// backwards over its residual arcs from its seeds (D = 0: vertices with a
+// residual t-link; D > 0: vertices marked by a neighbouring region at D - 1),
+// labelling the unlabelled vertices it reaches with D; a labelled border
+// vertex marks its residual predecessors across the region border as seeds of
+// D + 1 and flags their regions.  d*B is a valid labeling and an upper bound
+// of every valid labeling (Sec. 4.1), so it may replace the labels at any time.
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(NT) void k_grelabel(GRelabelArgs A) {
+    __shared__ int s_qtail, s_go;
+    const Geo &G = A.G;
+    const int V = G.V, N = G.N, tid = threadIdx.x, D = A.level;
+    int *Q = A.scratch + (size_t)blockIdx.x * V;
+    for (int r = blockIdx.x; r < G.nreg; r += gridDim.x) {
+        const int base = r * V;
+        if (tid == 0) {
+            s_go = (D == 0) ? 1 : A.flagIn[r];
+            A.flagIn[r] = 0;
+            s_qtail = 0;
+        }
+        __syncthreads();
+        if (!s_go) { __syncthreads(); continue; }
+        if (D == 0) {
+            for (int l = tid; l < V; l += NT)
+                if (A.rt[base + l] > 0) {
+                    A.lab[base + l] = 0;
+                    Q[atomicAdd(&s_qtail, 1)] = l;
+                }
+        } else {
+            for (int i = tid; i < A.nring; i += NT) {
+                const int l = A.ringL[i];
+                if (A.candIn[base + l]) {
+                    A.candIn[base + l] = 0;
+                    if (A.lab[base + l] == A.dinf) {
+                        A.lab[base + l] = D;
+                        Q[atomicAdd(&s_qtail, 1)] = l;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        int fs = 0;
+        for (;;) {
+            const int fe = s_qtail;
+            if (fs == fe) break;
+            for (int i = fs + tid; i < fe; i += NT) {
+                const int v = Q[i];
+                int vz, vy, vx;
+                local_xyz(G, v, vz, vy, vx);
+                for (int k = 0; k < G.K; k++) {
+                    // predecessor u = v - o_k with residual arc (u, v) in direction k
+                    const int u = local_nbr(G, vz, vy, vx, k ^ 1);
+                    if (u >= 0) {
+                        if (A.res[(size_t)k * N + base + u] > 0 && A.lab[base + u] == A.dinf &&
+                            atomicCAS(&A.lab[base + u], A.dinf, D) == A.dinf)
+                            Q[atomicAdd(&s_qtail, 1)] = u;
+                    } else {
+                        const int ug = cross_nbr(G, r, vz, vy, vx, k ^ 1);
+                        if (ug >= 0 && A.res[(size_t)k * N + ug] > 0 && A.lab[ug] == A.dinf) {
+                            A.candOut[ug] = 1;
+                            if (atomicExch(&A.flagOut[ug / V], 1) == 0) atomicAdd(A.flagged, 1u);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            fs = fe;
+            __syncthreads();
+        }
+    }
+}
+
+// Active regions and the active-vertex count after new labels.
+__global__ void k_activity(Geo G, const int *ex, const int *lab, int dinf, int *ractive,
+                           unsigned long long *act) {
+    __shared__ int s_w[4];
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    int a = 0;
+    if (g < G.N && ex[g] > 0 && lab[g] < dinf) {
+        a = 1;
+        ractive[g / G.V] = 1;
+    }
+    a = wave_sum_i(a);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        if (t) atomicAdd(act, (unsigned long long)t);
+    }
+}
+
+hipError_t launch_grelabel(const GRelabelArgs &A, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_grelabel<256>, dim3(blocks), dim3(256), 0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_activity(const Geo &G, const int *ex, const int *lab, int dinf, int *ractive,
+                           unsigned long long *act, hipStream_t s) {
+    hipLaunchKernelGGL(k_activity, dim3(cdiv(G.N, 256)), dim3(256), 0, s, G, ex, lab, dinf, ractive, act);
     return hipGetLastError();
 }
 

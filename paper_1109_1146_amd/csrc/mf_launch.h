@@ -26,6 +26,9 @@ struct DischargeArgs {
     int *err;
     int useLDS;
     int maxIter;
+    int *trace;          // optional per-discharge records (MF_TRACE_FIELDS int32 each)
+    long long traceCap;
+    int sweep;           // sweep index of this launch
 };
 
 struct FuseArgs {
@@ -75,6 +78,24 @@ struct FloodArgs {
     int *scratch;  // V ints per workgroup
 };
 
+struct GRelabelArgs {
+    Geo G;
+    int level;
+    const int *res, *rt;
+    int *lab;             // output labels (dinf = not reached yet)
+    unsigned char *candIn, *candOut;  // seeds of this level / marks for the next
+    int *flagIn, *flagOut;            // regions with seeds of this / the next level
+    unsigned int *flagged;            // regions flagged for the next level
+    const int *ringL;
+    int nring;
+    int dinf;
+    int *scratch;         // V ints per workgroup
+};
+
+hipError_t launch_grelabel(const GRelabelArgs &A, int blocks, hipStream_t s);
+hipError_t launch_activity(const Geo &G, const int *ex, const int *lab, int dinf, int *ractive,
+                           unsigned long long *act, hipStream_t s);
+
 hipError_t launch_validate(const Geo &G, const int *cs, const int *ct, const int *nbr, int n,
                            int *err, hipStream_t s);
 hipError_t launch_sum_links(const int *cs, const int *ct, int n, unsigned long long *out2,
@@ -84,6 +105,12 @@ hipError_t launch_init(const Geo &G, const int *cs, const int *ct, const int *nb
                        unsigned long long *act0, hipStream_t s);
 hipError_t launch_discharge(const DischargeArgs &A, int blocks, int threads, size_t lds,
                             hipStream_t s);
+hipError_t launch_discharge_lds(const DischargeArgs &A, int blocks, size_t lds, int narrow,
+                                hipStream_t s);
+size_t discharge_lds_bytes(int V, int K, int nring, int narrow);
+hipError_t launch_discharge_wave(const DischargeArgs &A, int blocks, size_t lds, int narrow,
+                                 hipStream_t s);
+size_t discharge_wave_bytes(int V, int K, int nring, int narrow);
 hipError_t launch_fuse(const FuseArgs &A, hipStream_t s);
 hipError_t launch_gap_find(const GapArgs &A, hipStream_t s);
 hipError_t launch_gap_apply(const GapApplyArgs &A, hipStream_t s);

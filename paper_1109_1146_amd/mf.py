@@ -18,6 +18,10 @@ LIB_PATH = os.path.join(_PKG, "libmfard.so")
 MF_OK, MF_E_INVAL, MF_E_NOMEM, MF_E_DEVICE, MF_E_STATE, MF_E_OVERFLOW, MF_E_SWEEPS = range(7)
 MF_CUT_MIN_SOURCE, MF_CUT_MAX_SOURCE = 0, 1
 MF_SCHED_PARD, MF_SCHED_COLORED, MF_SCHED_LEARNED, MF_SCHED_AUTO = 0, 1, 2, 3
+MF_KERNEL_AUTO, MF_KERNEL_HBM, MF_KERNEL_LDS, MF_KERNEL_WAVE = 0, 1, 2, 3
+TRACE_FIELDS = 10
+TRACE_NAMES = ("sweep", "region", "rounds", "levels", "stages", "ticks", "excess_in", "to_sink",
+               "to_boundary", "label_sum")
 
 EXPORTED = ("mf_create_grid", "mf_set_caps", "mf_solve", "mf_flow_value", "mf_min_cut",
             "mf_get_state", "mf_get_info", "mf_discharge_bytes_per_vertex", "mf_destroy",
@@ -29,7 +33,8 @@ class mf_solve_opts(ctypes.Structure):
                 ("gap", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("max_sweeps", ctypes.c_int64), ("model", ctypes.c_void_p),
                 ("stream", ctypes.c_void_p), ("profile", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("region_kernel", ctypes.c_int32), ("trace", ctypes.c_void_p),
+                ("trace_cap", ctypes.c_int64)]
 
 
 class mf_solve_stats(ctypes.Structure):
@@ -37,7 +42,12 @@ class mf_solve_stats(ctypes.Structure):
                 ("boundary_size", ctypes.c_int64), ("d_inf", ctypes.c_int64),
                 ("solve_ms", ctypes.c_double), ("discharge_ms", ctypes.c_double),
                 ("discharge_launches", ctypes.c_int64), ("discharge_bytes", ctypes.c_double),
-                ("discharged_vertices", ctypes.c_int64)]
+                ("discharged_vertices", ctypes.c_int64), ("discharge_iterations", ctypes.c_int64),
+                ("search_levels", ctypes.c_int64), ("search_stages", ctypes.c_int64),
+                ("trace_records", ctypes.c_int64), ("search_ticks", ctypes.c_int64),
+                ("push_ticks", ctypes.c_int64), ("setup_ticks", ctypes.c_int64),
+                ("flood_ticks", ctypes.c_int64), ("global_relabels", ctypes.c_int64),
+                ("global_relabel_levels", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -181,10 +191,16 @@ class Grid:
         _check(load().mf_set_caps(self._h, p1, p2, p3, d1, st), "mf_set_caps")
 
     def solve(self, schedule=MF_SCHED_PARD, gap=True, global_relabel_every=0, check_every=0,
-              max_sweeps=0, stream=None, profile=False):
+              max_sweeps=0, stream=None, profile=False, region_kernel=MF_KERNEL_AUTO,
+              trace=None):
+        """trace: optional int32 device tensor of shape (cap, TRACE_FIELDS)."""
+        tptr, tcap = None, 0
+        if trace is not None:
+            tptr, tcap = trace.data_ptr(), int(trace.shape[0])
         o = mf_solve_opts(schedule=schedule, global_relabel_every=global_relabel_every,
                           gap=1 if gap else 0, check_every=check_every, max_sweeps=max_sweeps,
-                          model=None, stream=stream, profile=1 if profile else 0, reserved=0)
+                          model=None, stream=stream, profile=1 if profile else 0,
+                          region_kernel=region_kernel, trace=tptr, trace_cap=tcap)
         s = mf_solve_stats()
         _check(load().mf_solve(self._h, ctypes.byref(o), ctypes.byref(s)), "mf_solve")
         return s.as_dict()

@@ -49,13 +49,33 @@ RANDOM_CASES = [
 ]
 
 
+@pytest.mark.parametrize("kernel", ["auto", "hbm", "lds"])
 @pytest.mark.parametrize("seed", range(48))
-def test_random_grids_exact(mf, seed):
+def test_random_grids_exact(mf, seed, kernel):
     dims, conn, tile = RANDOM_CASES[seed % len(RANDOM_CASES)]
     inst = synth.random_grid(dims, conn, seed, tile=tile)
-    out, _ = _check(mf, inst)
+    rk = {"auto": mf.MF_KERNEL_AUTO, "hbm": mf.MF_KERNEL_HBM, "lds": mf.MF_KERNEL_LDS}[kernel]
+    out, _ = _check(mf, inst, region_kernel=rk)
     B = out["info"]["boundary_size"]
     assert out["stats"]["sweeps"] <= 2 * max(B, 1) ** 2 + 1
+
+
+@pytest.mark.parametrize("every", [1, 3])
+@pytest.mark.parametrize("seed", range(12))
+def test_global_relabel_exact(mf, seed, every):
+    """Exact region-distance relabels between sweeps change the path, never the result."""
+    dims, conn, tile = RANDOM_CASES[seed % len(RANDOM_CASES)]
+    inst = synth.random_grid(dims, conn, 500 + seed, tile=tile)
+    out, _ = _check(mf, inst, global_relabel_every=every)
+    assert out["stats"]["global_relabels"] >= 1
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_lds_kernel_int32_residuals(mf, seed):
+    """Capacities too large for int16 residuals select the int32 LDS layout."""
+    inst = synth.random_grid((40, 36), 8 if seed % 2 else 4, 100 + seed, tile=(16, 16))
+    inst.nbr = (inst.nbr.astype(np.int64) * 7000).astype(np.int32)
+    _check(mf, inst, region_kernel=mf.MF_KERNEL_LDS)
 
 
 @pytest.mark.parametrize("strength", [5, 40, 150, 400])
@@ -120,6 +140,40 @@ def test_large_capacities(mf):
 def test_full_size_workloads_exact(mf, cfg):
     inst = synth.config(cfg)
     _check(mf, inst, certify=(cfg == 1))
+
+
+@pytest.mark.parametrize("kernel", ["hbm", "lds"])
+def test_workload1_other_kernels_exact(mf, kernel):
+    inst = synth.config(1)
+    rk = {"hbm": mf.MF_KERNEL_HBM, "lds": mf.MF_KERNEL_LDS}[kernel]
+    _check(mf, inst, certify=False, region_kernel=rk)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_wave_kernel_tiles(mf, seed):
+    """The wavefront kernel on 2D tiles of every width/height up to 64, ragged grids."""
+    rng = np.random.default_rng(seed)
+    tile = (int(rng.integers(1, 65)), int(rng.integers(1, 65)))
+    dims = (int(rng.integers(1, 3 * tile[0] + 2)), int(rng.integers(1, 3 * tile[1] + 2)))
+    conn = 4 if seed % 2 else 8
+    inst = synth.random_grid(dims, conn, 900 + seed, tile=tile, cap_hi=30)
+    _check(mf, inst, region_kernel=mf.MF_KERNEL_WAVE)
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_full_size_global_relabel_exact(mf, cfg):
+    inst = synth.config(cfg)
+    _check(mf, inst, certify=False, global_relabel_every=4)
+
+
+def test_region_kernel_selection_errors(mf):
+    inst = synth.config(2)  # 32^3 regions do not fit in LDS and are not 2D
+    with mf.Grid(inst.dims, inst.conn, inst.tile) as g:
+        g.set_caps(inst.cs, inst.ct, inst.nbr)
+        for rk in (mf.MF_KERNEL_LDS, mf.MF_KERNEL_WAVE):
+            with pytest.raises(mf.MFError) as e:
+                g.solve(region_kernel=rk)
+            assert e.value.status == mf.MF_E_INVAL
 
 
 def test_resolve_and_device_inputs(mf):
