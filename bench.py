@@ -21,6 +21,25 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 
+
+def measured_traffic(kernel_src, summary):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated), or None when
+    the summary is missing or the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", summary)
+    src = os.path.join(ROOT, kernel_src)
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("source_sha256") != sha:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
 WORKLOADS = {
     "2d": dict(cfg=1, desc="2048x2048 2D 8-connected blob grid, 64 blobs, 10% n-links zeroed, "
                            "64x64 regions (1024), seed 1"),
@@ -37,7 +56,24 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="CPU work budget of the oracle baseline sample")
+    p.add_argument("--relabel-every", type=int, default=8,
+                   help="exact region-distance relabel every N sweeps (0 = off)")
+    p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                   help="only run a device-to-device copy of MIB MiB (HBM counter calibration)")
     return p.parse_args()
+
+
+def calibrate_copy(mib):
+    """A plain copy kernel of known size: reads and writes mib MiB once each, so
+    that a hardware-counter run can relate FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": n * 4}), flush=True)
 
 
 def cpu_baseline(inst, budget_s):
@@ -64,6 +100,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     import numpy as np
     import torch
     import synth
@@ -84,7 +123,8 @@ def main():
     info = g.info()
 
     def step(profile):
-        st = g.solve(stream=stream.cuda_stream, profile=profile)
+        st = g.solve(stream=stream.cuda_stream, profile=profile,
+                     global_relabel_every=args.relabel_every)
         cut = g.min_cut(mf.MF_CUT_MIN_SOURCE)
         return st, cut
 
@@ -107,6 +147,10 @@ def main():
     d_launch = sum(s["discharge_launches"] for s in stats)
     d_bytes = sum(s["discharge_bytes"] for s in stats)
     achieved = d_bytes / (d_ms / 1e3) / 1e9 if d_ms > 0 else 0.0
+    traffic = None
+    if args.workload == "2d":
+        traffic = measured_traffic("paper_1109_1146_amd/csrc/mf_discharge_wave.hip",
+                                   "k_discharge_wave_grid2d8_2048_traffic.json")
     rec = {
         "metric": "exact-maxflow solve throughput (plain P-ARD), sweeps, % HBM peak",
         "value": round(value, 3),
@@ -122,19 +166,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "n": inst.n, "regions": info["regions"],
                    "region_shape": list(info["region_shape"]), "boundary_size": info["boundary_size"],
-                   "schedule": "P-ARD", "connectivity": inst.conn},
+                   "schedule": "P-ARD", "connectivity": inst.conn,
+                   "global_relabel_every": args.relabel_every},
         "sweeps": stats[-1]["sweeps"],
         "region_discharges": stats[-1]["region_discharges"],
         "flow": flow,
         "solve_ms": round(sum(s["solve_ms"] for s in stats) / len(stats), 3),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_discharge",
+            "kernel": "k_discharge_wave" if args.workload == "2d" else "k_discharge",
             "achieved": round(achieved, 3),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 6),
-            "traffic": None,
+            "traffic": traffic,
             "avg_launch_ms": round(d_ms / max(d_launch, 1), 4),
             "algorithmic_bytes_per_launch": round(d_bytes / max(d_launch, 1), 1),
         },

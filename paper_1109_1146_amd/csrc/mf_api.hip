@@ -216,11 +216,11 @@ extern "C" mf_status mf_create_grid(int32_t ndim, const int64_t *dims, int32_t c
                 ok(dalloc(&g->cand, 2 * N)) &&
                 ok(dalloc(&g->in_cs, (size_t)n)) && ok(dalloc(&g->in_ct, (size_t)n)) &&
                 ok(dalloc(&g->in_nbr, K * (size_t)n)) && ok(dalloc(&g->tmp_plane, (size_t)n)) &&
-                ok(dalloc(&g->scratch, (size_t)g->nslots * 4 * G.V)) && ok(dalloc(&g->act, 2)) &&
-                ok(dalloc(&g->qhead, 2)) && ok(dalloc(&g->hist, (size_t)mfd::kHistBins)) &&
+                ok(dalloc(&g->scratch, (size_t)g->nslots * 4 * G.V)) && ok(dalloc(&g->act, 4)) &&
+                ok(dalloc(&g->qhead, 4)) && ok(dalloc(&g->hist, (size_t)mfd::kHistBins)) &&
                 ok(dalloc(&g->maxlab, 1)) && ok(dalloc(&g->gap, 1)) && ok(dalloc(&g->err, 4)) &&
                 ok(dalloc(&g->counters, 4)) && ok(dalloc(&g->stats, 16)) && ok(dalloc(&g->sums, 4)) &&
-                ok(dalloc(&g->changed, 1)) &&
+                ok(dalloc(&g->changed, 8)) &&
                 ok(hipHostMalloc((void **)&g->pinned, 32 * sizeof(u64), hipHostMallocDefault));
     if (!good) {
         (void)hipGetLastError();
@@ -307,28 +307,38 @@ static int global_relabel(mf_grid *g, int *lab, u64 *act, hipStream_t s) {
     memset(&A, 0, sizeof(A));
     A.G = G;
     A.res = g->res; A.rt = g->rt; A.lab = lab;
-    A.ringL = g->ringL; A.nring = g->nring; A.dinf = g->dinf;
+    A.ringL = g->ringL; A.ringM = g->ringM; A.nring = g->nring; A.dinf = g->dinf;
     A.scratch = g->scratch;
-    A.flagged = g->changed;
-    const int blocks = std::min(G.nreg, g->nslots * 4);
+    // 2D regions of at most 64 x 64: one wavefront per region, row-bitmask flood
+    const bool wave = g->ndim == 2 && G.tx <= 64 && G.ty <= 64;
+    const int blocks = wave ? std::min(G.nreg, g->numCU * 8) : std::min(G.nreg, g->nslots * 4);
+    // levels are launched in batches; a level with no flagged region is a cheap no-op
+    const int batch = 4;
     int D = 0;
-    for (;; D++) {
-        A.level = D;
-        A.candIn = g->cand + (size_t)(D & 1) * G.N;
-        A.candOut = g->cand + (size_t)((D + 1) & 1) * G.N;
-        A.flagIn = g->dirty + (size_t)(D & 1) * G.nreg;
-        A.flagOut = g->dirty + (size_t)((D + 1) & 1) * G.nreg;
-        if (!ok(hipMemsetAsync(g->changed, 0, sizeof(unsigned), s))) return -1;
-        if (!ok(mfd::launch_grelabel(A, blocks, s))) return -1;
-        if (!ok(hipMemcpyAsync(g->pinned + 14, g->changed, sizeof(unsigned), hipMemcpyDeviceToHost, s))) return -1;
+    for (;;) {
+        for (int j = 0; j < batch; j++) {
+            const int lv = D + j;
+            A.level = lv;
+            A.candIn = g->cand + (size_t)(lv & 1) * G.N;
+            A.candOut = g->cand + (size_t)((lv + 1) & 1) * G.N;
+            A.flagIn = g->dirty + (size_t)(lv & 1) * G.nreg;
+            A.flagOut = g->dirty + (size_t)((lv + 1) & 1) * G.nreg;
+            A.flagged = g->changed + j;
+            if (!ok(hipMemsetAsync(g->changed + j, 0, sizeof(unsigned), s))) return -1;
+            if (!ok(wave ? mfd::launch_grelabel_wave(A, blocks, s) : mfd::launch_grelabel(A, blocks, s)))
+                return -1;
+        }
+        if (!ok(hipMemcpyAsync(g->pinned + 14, g->changed + batch - 1, sizeof(unsigned), hipMemcpyDeviceToHost, s)))
+            return -1;
         if (!ok(hipStreamSynchronize(s))) return -1;
+        D += batch;
         if (*(unsigned *)(g->pinned + 14) == 0u) break;
-        if (D > g->dinf + 1) return -1;
+        if (D > g->dinf + batch + 1) return -1;
     }
     if (!ok(hipMemsetAsync(g->ractive, 0, sizeof(int) * G.nreg, s))) return -1;
     if (!ok(hipMemsetAsync(act, 0, sizeof(u64), s))) return -1;
     if (!ok(mfd::launch_activity(G, g->ex, lab, g->dinf, g->ractive, act, s))) return -1;
-    return D + 1;
+    return D;
 }
 
 extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_stats *st) {
@@ -352,8 +362,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     auto t0 = std::chrono::high_resolution_clock::now();
 
     // control block reset + Init
-    HIP_TRY(hipMemsetAsync(g->act, 0, 2 * sizeof(u64), s));
-    HIP_TRY(hipMemsetAsync(g->qhead, 0, 2 * sizeof(unsigned), s));
+    HIP_TRY(hipMemsetAsync(g->act, 0, 4 * sizeof(u64), s));
+    HIP_TRY(hipMemsetAsync(g->qhead, 0, 4 * sizeof(unsigned), s));
     HIP_TRY(hipMemsetAsync(g->hist, 0, sizeof(unsigned) * mfd::kHistBins, s));
     HIP_TRY(hipMemsetAsync(g->maxlab, 0xff, sizeof(int), s));
     HIP_TRY(hipMemsetAsync(g->gap, 0xff, sizeof(int), s));
@@ -469,11 +479,9 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         HIP_TRY(hipMemcpyAsync(g->pinned + 2, g->err, sizeof(int), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (o.profile) {
-            // only launches of sweeps that did work are counted
-            long long done_sweeps = (long long)g->pinned[1];
-            long long first = sweep - check_every;
+            // every discharge launch is timed, including those of the sweeps
+            // enqueued after convergence (they exit at once)
             for (int j = 0; j < check_every; j++) {
-                if (first + j >= done_sweeps) break;
                 float ms = 0.f;
                 HIP_TRY(hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]));
                 discharge_ms += ms;

@@ -471,4 +471,107 @@ hipError_t launch_discharge_wave(const DischargeArgs &A, int blocks, size_t lds,
     return hipErrorInvalidValue;
 }
 
+// Global relabel, one distance level (see k_grelabel in mf_kernels.hip), for
+// 2D regions of at most 64 x 64 with the row-bitmask flood of one wavefront:
+// masks are built from HBM by ballot, the flood runs in registers, labels and
+// next-level marks are written back.
+template <int K>
+__global__ __launch_bounds__(64) void k_grelabel_wave(GRelabelArgs A) {
+    const Geo &G = A.G;
+    const int V = G.V, N = G.N, TX = G.tx, TY = G.ty, D = A.level, dinf = A.dinf;
+    const int lane = threadIdx.x, y = lane;
+    const bool myrow = y < TY;
+    const u64 rowmask = TX == 64 ? ~0ull : ((1ull << TX) - 1);
+    int dy[K], dx[K];
+    u64 inside[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        dy[k] = G.oy[k];
+        dx[k] = G.ox[k];
+        const bool rowok = myrow && y + dy[k] >= 0 && y + dy[k] < TY;
+        u64 m = rowok ? rowmask : 0ull;
+        if (dx[k] > 0) m &= rowmask >> dx[k];
+        if (dx[k] < 0) m &= (rowmask << (-dx[k])) & rowmask;
+        inside[k] = m;
+    }
+    for (int r = blockIdx.x; r < G.nreg; r += gridDim.x) {
+        int go = 1;
+        if (D > 0) {
+            if (lane == 0) {
+                go = A.flagIn[r];
+                A.flagIn[r] = 0;
+            }
+            go = __shfl(go, 0, 64);
+        }
+        if (!go) continue;
+        const int base = r * V;
+        u64 R[K], U = 0, SEED = 0;
+        for (int row = 0; row < TY; row++) {
+            const int l = row * TX + lane;
+            const bool ok = lane < TX;
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const u64 b = __ballot(ok && A.res[(size_t)k * N + base + l] > 0);
+                if (lane == row) R[k] = b;
+            }
+            const int lv = ok ? A.lab[base + l] : 0;
+            const bool unl = ok && lv == dinf;
+            bool sd;
+            if (D == 0) {
+                sd = unl && A.rt[base + l] > 0;
+            } else {
+                const bool c = ok && A.candIn[base + l] != 0;
+                if (c) A.candIn[base + l] = 0;
+                sd = unl && c;
+            }
+            const u64 bu = __ballot(unl), bs = __ballot(sd);
+            if (lane == row) { U = bu; SEED = bs; }
+        }
+#pragma unroll
+        for (int k = 0; k < K; k++) R[k] &= inside[k];
+        u64 reached = SEED, F = SEED;
+        for (;;) {
+            const Rows3 FR = rows3(F, y, TY);
+            u64 nw = 0;
+#pragma unroll
+            for (int k = 0; k < K; k++) nw |= R[k] & shift_dx(FR.at(dy[k]), dx[k]);
+            nw &= U & ~reached;
+            if (!__ballot(nw != 0ull)) break;
+            reached |= nw;
+            F = nw;
+        }
+        for (int row = 0; row < TY; row++) {
+            const u64 m = shfl64(reached, row);
+            if (lane < TX && ((m >> lane) & 1ull)) A.lab[base + row * TX + lane] = D;
+        }
+        // marks for D + 1: residual predecessors across the border of reached border vertices
+        for (int i0 = 0; i0 < A.nring; i0 += 64) {
+            const int i = i0 + lane;
+            const int l = i < A.nring ? A.ringL[i] : 0;
+            const int ry = l / TX, rx = l - ry * TX;
+            const u64 m = shfl64(reached, ry);
+            if (i < A.nring && ((m >> rx) & 1ull)) {
+                const unsigned lm = A.ringM[i];
+#pragma unroll
+                for (int k = 0; k < K; k++) {
+                    // predecessor u = v - o_k lies across the border when direction k^1 leaves
+                    if (!((lm >> (k ^ 1)) & 1u)) continue;
+                    const int ug = cross_nbr(G, r, 0, ry, rx, k ^ 1);
+                    if (ug < 0 || A.res[(size_t)k * N + ug] <= 0 || A.lab[ug] != dinf) continue;
+                    A.candOut[ug] = 1;
+                    if (atomicExch(&A.flagOut[ug / V], 1) == 0) atomicAdd(A.flagged, 1u);
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_grelabel_wave(const GRelabelArgs &A, int blocks, hipStream_t s) {
+    if (A.G.tz != 1 || A.G.tx > 64 || A.G.ty > 64) return hipErrorInvalidValue;
+    if (A.G.K == 4) hipLaunchKernelGGL(k_grelabel_wave<4>, dim3(blocks), dim3(64), 0, s, A);
+    else if (A.G.K == 8) hipLaunchKernelGGL(k_grelabel_wave<8>, dim3(blocks), dim3(64), 0, s, A);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 }  // namespace mfd

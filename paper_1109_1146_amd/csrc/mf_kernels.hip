@@ -36,9 +36,10 @@ __device__ __forceinline__ int wave_min_i(int v) {
 // ---------------------------------------------------------------------------
 __global__ void k_validate(Geo G, const int *cs, const int *ct, const int *nbr, int n, int *err) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
+    const bool live = v < n;
+    if (!live) v = n - 1;  // duplicate the last vertex so every lane joins the reductions
     int x = v % G.dx, t = v / G.dx, y = t % G.dy, z = t / G.dy;
-    int bad = 0;
+    int bad = 0, maxpair = 0;
     if (cs[v] < 0 || ct[v] < 0) bad |= 1;
     long long inflow = cs[v] < 0 ? 0 : cs[v];
     for (int k = 0; k < G.K; k++) {
@@ -56,12 +57,18 @@ __global__ void k_validate(Geo G, const int *cs, const int *ct, const int *nbr, 
         if (crev < 0) { bad |= 1; continue; }
         long long pair = (long long)c + crev;
         if (pair > 0x7fffffffLL) bad |= 2;
-        else atomicMax(&err[1], (int)pair);
+        else maxpair = max(maxpair, (int)pair);
         inflow += crev;
     }
     if (inflow > 0x7fffffffLL) bad |= 2;
-    if (ct[v] > 0) atomicMax(&err[2], ct[v]);
     if (bad) atomicOr(err, bad);
+    // largest pair sum and t-link, one atomic per wavefront
+    maxpair = wave_max_i(maxpair);
+    const int mct = wave_max_i(ct[v] > 0 ? ct[v] : 0);
+    if ((threadIdx.x & 63) == 0) {
+        if (maxpair > 0) atomicMax(&err[1], maxpair);
+        if (mct > 0) atomicMax(&err[2], mct);
+    }
 }
 
 // Sums of the s- and t-links (int64) for the flow value and the certificate.

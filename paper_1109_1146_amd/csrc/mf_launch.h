@@ -87,12 +87,14 @@ struct GRelabelArgs {
     int *flagIn, *flagOut;            // regions with seeds of this / the next level
     unsigned int *flagged;            // regions flagged for the next level
     const int *ringL;
+    const unsigned char *ringM;
     int nring;
     int dinf;
     int *scratch;         // V ints per workgroup
 };
 
 hipError_t launch_grelabel(const GRelabelArgs &A, int blocks, hipStream_t s);
+hipError_t launch_grelabel_wave(const GRelabelArgs &A, int blocks, hipStream_t s);
 hipError_t launch_activity(const Geo &G, const int *ex, const int *lab, int dinf, int *ractive,
                            unsigned long long *act, hipStream_t s);
 
