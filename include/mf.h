@@ -81,6 +81,10 @@ typedef struct {
     int32_t *trace;               /* device buffer of MF_TRACE_FIELDS x trace_cap int32, or NULL:
                                      one record per region discharge, see MF_TR_* */
     int64_t trace_cap;            /* records the trace buffer holds; extra records are dropped */
+    int32_t graph;                /* 1 = replay batches of sweeps as a captured HIP graph (ignored
+                                     with profile or trace); a NULL stream is then replaced by a
+                                     stream owned by the handle */
+    int32_t reserved2;
 } mf_solve_opts;
 
 /* trace record fields (int32 each) */
@@ -183,6 +187,42 @@ mf_status mf_get_state(const mf_grid *g, int32_t *res, int32_t *rt, int32_t *ex,
 /* Shape facts of a handle: number of vertices, K, regions, |B|, region shape. */
 mf_status mf_get_info(const mf_grid *g, int64_t *n, int32_t *K, int64_t *regions,
                       int64_t *boundary_size, int32_t *region_shape3);
+
+/* ---- Batches: many independent 2D instances solved together (one sweep
+ * launch discharges regions of every instance from one work queue).  The
+ * instances are packed, region-aligned, on one canvas with no arcs between
+ * them, so the canvas maximum flow is the union of the instance maximum flows
+ * (Sec. 2 network of each instance unchanged); a 4-connected instance is
+ * carried with zero diagonal capacities when the batch holds 8-connected ones.
+ *
+ * mf_create_batch
+ *   count         number of instances (>= 1)
+ *   dims          [count][2] row-major {H, W} of each instance
+ *   connectivity  [count] 4 or 8
+ *   region_shape  [2] region extents shared by all instances, or NULL / zeros
+ *                 for 32 x 32
+ * The handle works with mf_solve, mf_flow_value (sum over instances),
+ * mf_destroy and the mf_batch_* calls below; mf_set_caps on it is MF_E_INVAL. */
+mf_status mf_create_batch(int32_t count, const int64_t *dims, const int32_t *connectivity,
+                          const int32_t *region_shape, mf_grid **out);
+
+/* Placement of instance `index` on the canvas (offset {y, x} and dims {H, W}),
+ * or with index = -1 the canvas itself (offset {0, 0}). */
+mf_status mf_batch_info(const mf_grid *g, int32_t index, int64_t *canvas_offset2,
+                        int64_t *canvas_dims2);
+
+/* Load instance `index` (same layout, rules and errors as mf_set_caps, with
+ * that instance's dims and connectivity).  mf_solve needs every instance loaded
+ * (MF_E_STATE otherwise). */
+mf_status mf_batch_set_caps(mf_grid *g, int32_t index, const int32_t *src_cap,
+                            const int32_t *sink_cap, const int32_t *nbr_cap, int32_t on_device,
+                            void *stream);
+
+/* Flow value of every instance after mf_solve: out[count] (int64). */
+mf_status mf_batch_flow_values(const mf_grid *g, int64_t *out);
+
+/* Minimum cut of instance `index` (kind as for mf_min_cut), out[H*W] host. */
+mf_status mf_batch_min_cut(const mf_grid *g, int32_t index, int32_t kind, uint8_t *out_source_side);
 
 /* Algorithmic bytes one discharged vertex moves: its K residuals, residual
  * t-link and excess are read and written, its label is written. */

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -50,6 +51,20 @@ struct mf_grid {
     bool has_caps = false, solved = false;
     long long sum_cs = 0, sum_ct = 0, flow = 0;
     int final_parity = 0;
+    int cut_kind_cached = -1;     // kind whose reachability marks g->mark holds
+    // batch handles: independent 2D instances packed on one canvas
+    int batch = 0;                // number of instances; 0 for a single grid
+    std::vector<int> iy0, ix0, ih, iw, iconn;
+    std::vector<long long> isum_cs, isum_ct, iflow;
+    std::vector<int> imaxpair, imaxct;
+    std::vector<char> iloaded;
+    int *reginst = nullptr;       // instance of each region (-1: canvas padding)
+    int *stage = nullptr;         // one instance's caps on their way to the canvas
+    u64 *instRt = nullptr;        // per-instance sum of residual t-links
+    // captured sweep batches
+    hipStream_t own_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    long long graph_key = -1;
 };
 
 static bool ok(hipError_t e) { return e == hipSuccess; }
@@ -72,6 +87,11 @@ static void free_all(mf_grid *g) {
                     g->tmp_plane, g->cand};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    if (g->reginst) (void)hipFree(g->reginst);
+    if (g->stage) (void)hipFree(g->stage);
+    if (g->instRt) (void)hipFree(g->instRt);
+    if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
+    if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
     if (g->pinned) (void)hipHostFree(g->pinned);
 }
 
@@ -96,8 +116,16 @@ extern "C" int64_t mf_discharge_bytes_per_vertex(int32_t connectivity) {
     return (int64_t)(2 * connectivity + 5) * 4;
 }
 
+static mf_status create_impl(int32_t ndim, const int64_t *dims, int32_t connectivity,
+                             const int32_t *region_shape, mf_grid **out);
+
 extern "C" mf_status mf_create_grid(int32_t ndim, const int64_t *dims, int32_t connectivity,
                                     const int32_t *region_shape, mf_grid **out) {
+    return create_impl(ndim, dims, connectivity, region_shape, out);
+}
+
+static mf_status create_impl(int32_t ndim, const int64_t *dims, int32_t connectivity,
+                             const int32_t *region_shape, mf_grid **out) {
     if (!out || !dims || (ndim != 2 && ndim != 3)) return MF_E_INVAL;
     if (ndim == 2 && connectivity != 4 && connectivity != 8) return MF_E_INVAL;
     if (ndim == 3 && connectivity != 6) return MF_E_INVAL;
@@ -192,6 +220,13 @@ extern "C" mf_status mf_create_grid(int32_t ndim, const int64_t *dims, int32_t c
     g->nB = (long long)bidx.size();
     g->dinf = g->nB > 0 ? (int)g->nB : 1;
 
+    static bool attributes_set = false;
+    if (!attributes_set) {
+        mfd::set_wave_attributes();
+        mfd::set_lds_attributes();
+        mfd::set_hbm_attributes();
+        attributes_set = true;
+    }
     hipDeviceProp_t prop;
     if (!ok(hipGetDevice(&g->device)) || !ok(hipGetDeviceProperties(&prop, g->device))) {
         delete g;
@@ -268,7 +303,8 @@ extern "C" mf_status mf_get_info(const mf_grid *g, int64_t *n, int32_t *K, int64
 
 extern "C" mf_status mf_set_caps(mf_grid *g, const int32_t *src_cap, const int32_t *sink_cap,
                                  const int32_t *nbr_cap, int32_t on_device, void *stream) {
-    if (!g || !src_cap || !sink_cap || !nbr_cap) return MF_E_INVAL;
+    if (!g || !src_cap || !sink_cap || !nbr_cap || g->batch) return MF_E_INVAL;
+    g->cut_kind_cached = -1;
     hipStream_t s = (hipStream_t)stream;
     g->has_caps = false;
     g->solved = false;
@@ -357,7 +393,17 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     long long bound = (B > 2000000000LL) ? (1LL << 62) : 2 * B * B + 1;
     long long max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : bound;
     hipStream_t s = (hipStream_t)o.stream;
+    const bool use_graph = o.graph && !o.profile && !o.trace;
+    if (use_graph) {
+        // capture needs a stream of our own; it orders with the null stream
+        if (!s) {
+            if (!g->own_stream && !ok(hipStreamCreate(&g->own_stream))) return MF_E_DEVICE;
+            s = g->own_stream;
+        }
+        check_every += check_every & 1;  // whole even/odd sweep pairs
+    }
     g->solved = false;
+    g->cut_kind_cached = -1;
     const Geo &G = g->G;
     auto t0 = std::chrono::high_resolution_clock::now();
 
@@ -453,25 +499,53 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
             relabels++;
             relabel_levels += lv;
         }
-        for (int j = 0; j < check_every; j++, sweep++) {
-            const int p = (int)(sweep & 1);
-            D.labOld = g->lab[p]; D.labNew = g->lab[p ^ 1];
-            D.actIn = g->act + p; D.qhead = g->qhead + p;
-            D.sweep = (int)sweep;
-            if (o.profile) HIP_TRY(hipEventRecord(ev[2 * j], s));
-            if (regionMode == 2)
-                HIP_TRY(mfd::launch_discharge_wave(D, regionBlocks, regionLds, regionNarrow, s));
-            else if (regionMode == 1)
-                HIP_TRY(mfd::launch_discharge_lds(D, regionBlocks, regionLds, regionNarrow, s));
-            else
-                HIP_TRY(mfd::launch_discharge(D, g->nslots, g->threads, lds, s));
-            if (o.profile) HIP_TRY(hipEventRecord(ev[2 * j + 1], s));
-            F.lab = g->lab[p ^ 1]; F.actIn = g->act + p;
-            HIP_TRY(mfd::launch_fuse(F, s));
-            P.actIn = g->act + p; P.actOut = g->act + (p ^ 1); P.qheadNext = g->qhead + (p ^ 1);
-            HIP_TRY(mfd::launch_gap_find(P, s));
-            Q.lab = g->lab[p ^ 1]; Q.actIn = g->act + p; Q.actOut = g->act + (p ^ 1);
-            HIP_TRY(mfd::launch_gap_apply(Q, s));
+        // one batch of check_every sweeps; sweep parity selects the buffers
+        auto enqueue_batch = [&](long long first) -> bool {
+            for (int j = 0; j < check_every; j++) {
+                const int p = (int)((first + j) & 1);
+                D.labOld = g->lab[p]; D.labNew = g->lab[p ^ 1];
+                D.actIn = g->act + p; D.qhead = g->qhead + p;
+                D.sweep = (int)(first + j);
+                if (o.profile && !ok(hipEventRecord(ev[2 * j], s))) return false;
+                hipError_t e;
+                if (regionMode == 2) e = mfd::launch_discharge_wave(D, regionBlocks, regionLds, regionNarrow, s);
+                else if (regionMode == 1) e = mfd::launch_discharge_lds(D, regionBlocks, regionLds, regionNarrow, s);
+                else e = mfd::launch_discharge(D, g->nslots, g->threads, lds, s);
+                if (!ok(e)) return false;
+                if (o.profile && !ok(hipEventRecord(ev[2 * j + 1], s))) return false;
+                F.lab = g->lab[p ^ 1]; F.actIn = g->act + p;
+                if (!ok(mfd::launch_fuse(F, s))) return false;
+                P.actIn = g->act + p; P.actOut = g->act + (p ^ 1); P.qheadNext = g->qhead + (p ^ 1);
+                if (!ok(mfd::launch_gap_find(P, s))) return false;
+                Q.lab = g->lab[p ^ 1]; Q.actIn = g->act + p; Q.actOut = g->act + (p ^ 1);
+                if (!ok(mfd::launch_gap_apply(Q, s))) return false;
+            }
+            return true;
+        };
+        if (use_graph) {
+            // a captured batch replays on any even first sweep: the buffers it
+            // uses depend only on parity (labels may be swapped by relabels, so
+            // the graph is rebuilt when their order changed)
+            const long long key = ((long long)check_every << 8) | (o.gap ? 1 : 0) << 1 |
+                                  (long long)(regionMode << 2) | (long long)(regionNarrow << 4) |
+                                  (long long)((g->lab[0] < g->lab[1]) ? 1 : 0) << 5;
+            if (!g->graph_exec || g->graph_key != key) {
+                if (g->graph_exec) { (void)hipGraphExecDestroy(g->graph_exec); g->graph_exec = nullptr; }
+                hipGraph_t graph = nullptr;
+                HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                const bool enq = enqueue_batch(0);
+                hipError_t ec = hipStreamEndCapture(s, &graph);
+                if (!enq || !ok(ec)) return MF_E_DEVICE;
+                hipError_t ei = hipGraphInstantiate(&g->graph_exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (!ok(ei)) return MF_E_DEVICE;
+                g->graph_key = key;
+            }
+            HIP_TRY(hipGraphLaunch(g->graph_exec, s));
+            sweep += check_every;
+        } else {
+            if (!enqueue_batch(sweep)) return MF_E_DEVICE;
+            sweep += check_every;
         }
         const int p = (int)(sweep & 1);
         HIP_TRY(hipMemcpyAsync(g->pinned, g->act + p, sizeof(u64), hipMemcpyDeviceToHost, s));
@@ -503,6 +577,14 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     HIP_TRY(hipMemcpyAsync(g->pinned + 16, g->stats, 16 * sizeof(u64), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     g->flow = g->sum_ct - (long long)g->pinned[3];
+    if (g->batch) {
+        HIP_TRY(hipMemsetAsync(g->instRt, 0, sizeof(u64) * g->batch, s));
+        HIP_TRY(mfd::launch_instance_rt(G, g->rt, g->reginst, g->instRt, s));
+        std::vector<u64> rts(g->batch);
+        HIP_TRY(hipMemcpyAsync(rts.data(), g->instRt, sizeof(u64) * g->batch, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int i = 0; i < g->batch; i++) g->iflow[i] = g->isum_ct[i] - (long long)rts[i];
+    }
     g->solved = true;
     auto t1 = std::chrono::high_resolution_clock::now();
     if (st) {
@@ -537,13 +619,13 @@ extern "C" mf_status mf_flow_value(const mf_grid *g, int64_t *out) {
     return MF_OK;
 }
 
-extern "C" mf_status mf_min_cut(const mf_grid *gc, int32_t kind, uint8_t *out_source_side) {
-    mf_grid *g = const_cast<mf_grid *>(gc);
-    if (!g || !out_source_side) return MF_E_INVAL;
-    if (kind != MF_CUT_MIN_SOURCE && kind != MF_CUT_MAX_SOURCE) return MF_E_INVAL;
-    if (!g->solved) return MF_E_STATE;
+// Residual reachability marks for a cut kind into g->mark (cached until the
+// next solve): forward from the excess vertices, or backward from t.
+static mf_status compute_marks(mf_grid *g, int32_t kind) {
+    if (g->cut_kind_cached == kind) return MF_OK;
     const Geo &G = g->G;
     hipStream_t s = nullptr;
+    g->cut_kind_cached = -1;
     HIP_TRY(hipMemsetAsync(g->mark, 0, sizeof(int) * (size_t)G.N, s));
     HIP_TRY(hipMemsetAsync(g->dirty, 0, sizeof(int) * 2 * (size_t)G.nreg, s));
     mfd::FloodArgs A;
@@ -566,8 +648,204 @@ extern "C" mf_status mf_min_cut(const mf_grid *gc, int32_t kind, uint8_t *out_so
         if (*(unsigned *)g->pinned == 0u) break;
         if (round > G.N + 8) return MF_E_DEVICE;
     }
+    g->cut_kind_cached = kind;
+    return MF_OK;
+}
+
+extern "C" mf_status mf_min_cut(const mf_grid *gc, int32_t kind, uint8_t *out_source_side) {
+    mf_grid *g = const_cast<mf_grid *>(gc);
+    if (!g || !out_source_side) return MF_E_INVAL;
+    if (kind != MF_CUT_MIN_SOURCE && kind != MF_CUT_MAX_SOURCE) return MF_E_INVAL;
+    if (!g->solved) return MF_E_STATE;
+    mf_status st = compute_marks(g, kind);
+    if (st != MF_OK) return st;
+    const Geo &G = g->G;
+    hipStream_t s = nullptr;
     HIP_TRY(mfd::launch_cut_out(G, g->mark, g->cutbuf, (int)g->n, kind == MF_CUT_MAX_SOURCE ? 1 : 0, s));
     HIP_TRY(hipMemcpyAsync(out_source_side, g->cutbuf, (size_t)g->n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches of independent 2D instances
+// ---------------------------------------------------------------------------
+extern "C" mf_status mf_create_batch(int32_t count, const int64_t *dims, const int32_t *connectivity,
+                                     const int32_t *region_shape, mf_grid **out) {
+    if (!out || !dims || !connectivity || count < 1) return MF_E_INVAL;
+    int th = 32, tw = 32;
+    if (region_shape && (region_shape[0] || region_shape[1])) {
+        if (region_shape[0] < 1 || region_shape[1] < 1) return MF_E_INVAL;
+        th = region_shape[0];
+        tw = region_shape[1];
+    }
+    int K = 4;
+    long long area = 0, maxw = 0, maxn = 0;
+    std::vector<long long> H(count), W(count);
+    for (int i = 0; i < count; i++) {
+        const long long h = dims[2 * i], w = dims[2 * i + 1];
+        if (h < 1 || w < 1 || h * w >= (1LL << 30)) return MF_E_INVAL;
+        if (connectivity[i] != 4 && connectivity[i] != 8) return MF_E_INVAL;
+        if (connectivity[i] == 8) K = 8;
+        H[i] = (h + th - 1) / th * th;
+        W[i] = (w + tw - 1) / tw * tw;
+        area += H[i] * W[i];
+        maxw = std::max(maxw, W[i]);
+        maxn = std::max(maxn, h * w);
+    }
+    // shelf packing, tallest first, on a canvas about as wide as it is high
+    long long Wc = (long long)std::ceil(std::sqrt((double)area) / tw) * tw;
+    Wc = std::max(Wc, maxw);
+    std::vector<int> order(count);
+    for (int i = 0; i < count; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return H[a] > H[b]; });
+    std::vector<int> y0(count), x0(count);
+    long long shelfY = 0, shelfH = 0, curX = 0;
+    for (int i : order) {
+        if (curX + W[i] > Wc) {
+            shelfY += shelfH;
+            shelfH = 0;
+            curX = 0;
+        }
+        y0[i] = (int)shelfY;
+        x0[i] = (int)curX;
+        curX += W[i];
+        shelfH = std::max(shelfH, H[i]);
+    }
+    const long long Hc = shelfY + shelfH;
+    if (Hc * Wc >= (1LL << 31)) return MF_E_INVAL;
+    const int64_t cdims[2] = {Hc, Wc};
+    const int32_t tile[2] = {th, tw};
+    mf_grid *g = nullptr;
+    mf_status st = create_impl(2, cdims, K, tile, &g);
+    if (st != MF_OK) return st;
+    g->batch = count;
+    g->iy0 = y0;
+    g->ix0 = x0;
+    g->ih.resize(count);
+    g->iw.resize(count);
+    g->iconn.resize(count);
+    for (int i = 0; i < count; i++) {
+        g->ih[i] = (int)dims[2 * i];
+        g->iw[i] = (int)dims[2 * i + 1];
+        g->iconn[i] = connectivity[i];
+    }
+    g->isum_cs.assign(count, 0);
+    g->isum_ct.assign(count, 0);
+    g->iflow.assign(count, 0);
+    g->imaxpair.assign(count, 0);
+    g->imaxct.assign(count, 0);
+    g->iloaded.assign(count, 0);
+    const Geo &G = g->G;
+    std::vector<int> reginst(G.nreg, -1);
+    for (int i = 0; i < count; i++)
+        for (int ry = y0[i] / th; ry < (y0[i] + g->ih[i] + th - 1) / th; ry++)
+            for (int rx = x0[i] / tw; rx < (x0[i] + g->iw[i] + tw - 1) / tw; rx++) reginst[ry * G.rx + rx] = i;
+    const size_t n = (size_t)g->n;
+    bool good = ok(dalloc(&g->reginst, (size_t)G.nreg)) && ok(dalloc(&g->stage, (size_t)(K + 2) * maxn)) &&
+                ok(dalloc(&g->instRt, (size_t)count)) &&
+                ok(hipMemcpy(g->reginst, reginst.data(), sizeof(int) * G.nreg, hipMemcpyHostToDevice)) &&
+                ok(hipMemset(g->in_cs, 0, n * sizeof(int))) && ok(hipMemset(g->in_ct, 0, n * sizeof(int))) &&
+                ok(hipMemset(g->in_nbr, 0, (size_t)K * n * sizeof(int))) && ok(hipDeviceSynchronize());
+    if (!good) {
+        mf_destroy(g);
+        return MF_E_NOMEM;
+    }
+    *out = g;
+    return MF_OK;
+}
+
+extern "C" mf_status mf_batch_info(const mf_grid *g, int32_t index, int64_t *canvas_offset2,
+                                   int64_t *canvas_dims2) {
+    if (!g || !g->batch || index < -1 || index >= g->batch) return MF_E_INVAL;
+    if (index < 0) {
+        if (canvas_dims2) { canvas_dims2[0] = g->G.dy; canvas_dims2[1] = g->G.dx; }
+        if (canvas_offset2) { canvas_offset2[0] = 0; canvas_offset2[1] = 0; }
+        return MF_OK;
+    }
+    if (canvas_offset2) { canvas_offset2[0] = g->iy0[index]; canvas_offset2[1] = g->ix0[index]; }
+    if (canvas_dims2) { canvas_dims2[0] = g->ih[index]; canvas_dims2[1] = g->iw[index]; }
+    return MF_OK;
+}
+
+extern "C" mf_status mf_batch_set_caps(mf_grid *g, int32_t index, const int32_t *src_cap,
+                                       const int32_t *sink_cap, const int32_t *nbr_cap,
+                                       int32_t on_device, void *stream) {
+    if (!g || !g->batch || index < 0 || index >= g->batch || !src_cap || !sink_cap || !nbr_cap)
+        return MF_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const int h = g->ih[index], w = g->iw[index], Ki = g->iconn[index];
+    const size_t n = (size_t)h * w;
+    g->solved = false;
+    g->cut_kind_cached = -1;
+    g->has_caps = false;
+    g->iloaded[index] = 0;
+    hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    int *cs = g->stage, *ct = g->stage + n, *nb = g->stage + 2 * n;
+    HIP_TRY(hipMemcpyAsync(cs, src_cap, n * sizeof(int), kind, s));
+    HIP_TRY(hipMemcpyAsync(ct, sink_cap, n * sizeof(int), kind, s));
+    HIP_TRY(hipMemcpyAsync(nb, nbr_cap, (size_t)Ki * n * sizeof(int), kind, s));
+    Geo I;
+    memset(&I, 0, sizeof(I));
+    I.K = Ki;
+    I.dz = 1; I.dy = h; I.dx = w;
+    for (int k = 0; k < Ki; k++) { I.oz[k] = 0; I.oy[k] = OFF2D[k][0]; I.ox[k] = OFF2D[k][1]; }
+    HIP_TRY(hipMemsetAsync(g->err, 0, 4 * sizeof(int), s));
+    HIP_TRY(hipMemsetAsync(g->sums, 0, 4 * sizeof(u64), s));
+    HIP_TRY(mfd::launch_validate(I, cs, ct, nb, (int)n, g->err, s));
+    HIP_TRY(mfd::launch_sum_links(cs, ct, (int)n, g->sums, s));
+    HIP_TRY(hipMemcpyAsync(g->pinned, g->sums, 2 * sizeof(u64), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(g->pinned + 2, g->err, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int err = ((int *)(g->pinned + 2))[0];
+    if (err & 1) return MF_E_INVAL;
+    if (err & 2) return MF_E_OVERFLOW;
+    g->isum_cs[index] = (long long)g->pinned[0];
+    g->isum_ct[index] = (long long)g->pinned[1];
+    g->imaxpair[index] = ((int *)(g->pinned + 2))[1];
+    g->imaxct[index] = ((int *)(g->pinned + 2))[2];
+    HIP_TRY(mfd::launch_scatter_instance(cs, ct, nb, h, w, Ki, g->in_cs, g->in_ct, g->in_nbr, g->G.dx,
+                                         g->n, g->iy0[index], g->ix0[index], s));
+    HIP_TRY(hipStreamSynchronize(s));
+    g->iloaded[index] = 1;
+    bool all = true;
+    long long scs = 0, sct = 0;
+    int mp = 0, mc = 0;
+    for (int i = 0; i < g->batch; i++) {
+        all = all && g->iloaded[i];
+        scs += g->isum_cs[i];
+        sct += g->isum_ct[i];
+        mp = std::max(mp, g->imaxpair[i]);
+        mc = std::max(mc, g->imaxct[i]);
+    }
+    g->sum_cs = scs;
+    g->sum_ct = sct;
+    g->maxPair = mp;
+    g->maxCt = mc;
+    g->has_caps = all;
+    return MF_OK;
+}
+
+extern "C" mf_status mf_batch_flow_values(const mf_grid *g, int64_t *out) {
+    if (!g || !g->batch || !out) return MF_E_INVAL;
+    if (!g->solved) return MF_E_STATE;
+    for (int i = 0; i < g->batch; i++) out[i] = g->iflow[i];
+    return MF_OK;
+}
+
+extern "C" mf_status mf_batch_min_cut(const mf_grid *gc, int32_t index, int32_t kind,
+                                      uint8_t *out_source_side) {
+    mf_grid *g = const_cast<mf_grid *>(gc);
+    if (!g || !g->batch || index < 0 || index >= g->batch || !out_source_side) return MF_E_INVAL;
+    if (kind != MF_CUT_MIN_SOURCE && kind != MF_CUT_MAX_SOURCE) return MF_E_INVAL;
+    if (!g->solved) return MF_E_STATE;
+    mf_status st = compute_marks(g, kind);
+    if (st != MF_OK) return st;
+    hipStream_t s = nullptr;
+    const int h = g->ih[index], w = g->iw[index];
+    HIP_TRY(mfd::launch_cut_rect(g->G, g->mark, g->cutbuf, h, w, g->iy0[index], g->ix0[index],
+                                 kind == MF_CUT_MAX_SOURCE ? 1 : 0, s));
+    HIP_TRY(hipMemcpyAsync(out_source_side, g->cutbuf, (size_t)h * w, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return MF_OK;
 }

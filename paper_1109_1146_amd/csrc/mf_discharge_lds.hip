@@ -472,15 +472,22 @@ __global__ __launch_bounds__(NT) void k_discharge_lds(DischargeArgs A) {
     }
 }
 
+template <int K, typename RT>
+static void set_attr_k() {
+    (void)hipFuncSetAttribute((const void *)k_discharge_lds<K, RT, 512, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void *)k_discharge_lds<K, RT, 512, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+void set_lds_attributes() {
+    set_attr_k<4, short>(); set_attr_k<6, short>(); set_attr_k<8, short>();
+    set_attr_k<4, int>(); set_attr_k<6, int>(); set_attr_k<8, int>();
+    (void)hipGetLastError();
+}
+
 template <int K, typename RT, bool P2>
 static hipError_t launch_lds_t(const DischargeArgs &A, int blocks, size_t lds, hipStream_t s) {
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k_discharge_lds<K, RT, 512, P2>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipGetLastError();
-        attr = true;
-    }
     hipLaunchKernelGGL((k_discharge_lds<K, RT, 512, P2>), dim3(blocks), dim3(512), lds, s, A);
     return hipGetLastError();
 }

@@ -444,15 +444,20 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
     }
 }
 
+void set_wave_attributes() {
+    (void)hipFuncSetAttribute((const void *)k_discharge_wave<4, short>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void *)k_discharge_wave<8, short>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void *)k_discharge_wave<4, int>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void *)k_discharge_wave<8, int>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();
+}
+
 template <int K, typename RT>
 static hipError_t launch_wave_t(const DischargeArgs &A, int blocks, size_t lds, hipStream_t s) {
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void *)k_discharge_wave<K, RT>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipGetLastError();
-        attr = true;
-    }
     hipLaunchKernelGGL((k_discharge_wave<K, RT>), dim3(blocks), dim3(64), lds, s, A);
     return hipGetLastError();
 }

@@ -631,17 +631,16 @@ hipError_t launch_init(const Geo &G, const int *cs, const int *ct, const int *nb
     return hipGetLastError();
 }
 
+void set_hbm_attributes() {
+    (void)hipFuncSetAttribute((const void *)k_discharge<256>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute((const void *)k_discharge<512>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();
+}
+
 hipError_t launch_discharge(const DischargeArgs &A, int blocks, int threads, size_t lds,
                             hipStream_t s) {
-    static bool attr_done = false;
-    if (!attr_done && lds > 65536) {
-        (void)hipFuncSetAttribute((const void *)k_discharge<256>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        (void)hipFuncSetAttribute((const void *)k_discharge<512>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        (void)hipGetLastError();
-        attr_done = true;
-    }
     if (threads == 256)
         hipLaunchKernelGGL(k_discharge<256>, dim3(blocks), dim3(256), lds, s, A);
     else if (threads == 512)
@@ -803,6 +802,76 @@ hipError_t launch_grelabel(const GRelabelArgs &A, int blocks, hipStream_t s) {
 hipError_t launch_activity(const Geo &G, const int *ex, const int *lab, int dinf, int *ractive,
                            unsigned long long *act, hipStream_t s) {
     hipLaunchKernelGGL(k_activity, dim3(cdiv(G.N, 256)), dim3(256), 0, s, G, ex, lab, dinf, ractive, act);
+    return hipGetLastError();
+}
+
+}  // namespace mfd
+
+namespace mfd {
+
+// ---------------------------------------------------------------------------
+// Batches: independent instances packed on one canvas (region-aligned, no
+// arcs between instances), so the canvas solve is the union of the instance
+// solves.
+// ---------------------------------------------------------------------------
+__global__ void k_scatter_instance(const int *cs, const int *ct, const int *nbr, int h, int w,
+                                   int Ki, int *ccs, int *cct, int *cnbr, int Wc, long long nc,
+                                   int y0, int x0) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = h * w;
+    if (v >= n) return;
+    const int y = v / w, x = v - (v / w) * w;
+    const long long cv = (long long)(y0 + y) * Wc + (x0 + x);
+    ccs[cv] = cs[v];
+    cct[cv] = ct[v];
+    for (int k = 0; k < Ki; k++) cnbr[(size_t)k * nc + cv] = nbr[(size_t)k * n + v];
+}
+
+// sum of residual t-links per instance (one workgroup per region)
+__global__ void k_instance_rt(Geo G, const int *rt, const int *reginst, unsigned long long *instRt) {
+    __shared__ long long s_w[4];
+    const int r = blockIdx.x;
+    const int inst = reginst[r];
+    if (inst < 0) return;
+    long long a = 0;
+    for (int l = threadIdx.x; l < G.V; l += blockDim.x) a += rt[(size_t)r * G.V + l];
+    a = wave_sum_ll(a);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const long long t = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        if (t) atomicAdd(&instRt[inst], (unsigned long long)t);
+    }
+}
+
+// source-side indicator of one instance's rectangle from the canvas marks
+__global__ void k_cut_rect(Geo G, const int *mark, unsigned char *out, int h, int w, int y0, int x0,
+                           int invert) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= h * w) return;
+    const int y = v / w, x = v - (v / w) * w;
+    const int m = mark[grid_to_blocked(G, 0, y0 + y, x0 + x)] ? 1 : 0;
+    out[v] = (unsigned char)(invert ? 1 - m : m);
+}
+
+hipError_t launch_scatter_instance(const int *cs, const int *ct, const int *nbr, int h, int w, int Ki,
+                                   int *ccs, int *cct, int *cnbr, int Wc, long long nc, int y0,
+                                   int x0, hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter_instance, dim3(cdiv((long long)h * w, 256)), dim3(256), 0, s, cs, ct,
+                       nbr, h, w, Ki, ccs, cct, cnbr, Wc, nc, y0, x0);
+    return hipGetLastError();
+}
+
+hipError_t launch_instance_rt(const Geo &G, const int *rt, const int *reginst,
+                              unsigned long long *instRt, hipStream_t s) {
+    hipLaunchKernelGGL(k_instance_rt, dim3(G.nreg), dim3(256), 0, s, G, rt, reginst, instRt);
+    return hipGetLastError();
+}
+
+hipError_t launch_cut_rect(const Geo &G, const int *mark, unsigned char *out, int h, int w, int y0,
+                           int x0, int invert, hipStream_t s) {
+    hipLaunchKernelGGL(k_cut_rect, dim3(cdiv((long long)h * w, 256)), dim3(256), 0, s, G, mark, out, h,
+                       w, y0, x0, invert);
     return hipGetLastError();
 }
 

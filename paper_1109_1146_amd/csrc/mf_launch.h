@@ -98,6 +98,12 @@ hipError_t launch_grelabel_wave(const GRelabelArgs &A, int blocks, hipStream_t s
 hipError_t launch_activity(const Geo &G, const int *ex, const int *lab, int dinf, int *ractive,
                            unsigned long long *act, hipStream_t s);
 
+// Let every discharge kernel use the full LDS of a compute unit (done once,
+// before any launch or stream capture).
+void set_wave_attributes();
+void set_lds_attributes();
+void set_hbm_attributes();
+
 hipError_t launch_validate(const Geo &G, const int *cs, const int *ct, const int *nbr, int n,
                            int *err, hipStream_t s);
 hipError_t launch_sum_links(const int *cs, const int *ct, int n, unsigned long long *out2,
@@ -122,5 +128,12 @@ hipError_t launch_flood(const FloodArgs &A, int blocks, hipStream_t s);
 hipError_t launch_cut_out(const Geo &G, const int *mark, unsigned char *out, int n, int invert,
                           hipStream_t s);
 hipError_t launch_fill_i32(int *p, int n, int val, hipStream_t s);
+hipError_t launch_scatter_instance(const int *cs, const int *ct, const int *nbr, int h, int w, int Ki,
+                                   int *ccs, int *cct, int *cnbr, int Wc, long long nc, int y0,
+                                   int x0, hipStream_t s);
+hipError_t launch_instance_rt(const Geo &G, const int *rt, const int *reginst,
+                              unsigned long long *instRt, hipStream_t s);
+hipError_t launch_cut_rect(const Geo &G, const int *mark, unsigned char *out, int h, int w, int y0,
+                           int x0, int invert, hipStream_t s);
 
 }  // namespace mfd

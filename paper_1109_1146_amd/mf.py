@@ -25,7 +25,8 @@ TRACE_NAMES = ("sweep", "region", "rounds", "levels", "stages", "ticks", "excess
 
 EXPORTED = ("mf_create_grid", "mf_set_caps", "mf_solve", "mf_flow_value", "mf_min_cut",
             "mf_get_state", "mf_get_info", "mf_discharge_bytes_per_vertex", "mf_destroy",
-            "mf_status_str")
+            "mf_status_str", "mf_create_batch", "mf_batch_info", "mf_batch_set_caps",
+            "mf_batch_flow_values", "mf_batch_min_cut")
 
 
 class mf_solve_opts(ctypes.Structure):
@@ -34,7 +35,8 @@ class mf_solve_opts(ctypes.Structure):
                 ("max_sweeps", ctypes.c_int64), ("model", ctypes.c_void_p),
                 ("stream", ctypes.c_void_p), ("profile", ctypes.c_int32),
                 ("region_kernel", ctypes.c_int32), ("trace", ctypes.c_void_p),
-                ("trace_cap", ctypes.c_int64)]
+                ("trace_cap", ctypes.c_int64), ("graph", ctypes.c_int32),
+                ("reserved2", ctypes.c_int32)]
 
 
 class mf_solve_stats(ctypes.Structure):
@@ -99,6 +101,16 @@ def load(path: str = LIB_PATH):
     lib.mf_destroy.restype = None
     lib.mf_status_str.argtypes = [ctypes.c_int]
     lib.mf_status_str.restype = ctypes.c_char_p
+    lib.mf_create_batch.argtypes = [ctypes.c_int32, P, P, P, ctypes.POINTER(P)]
+    lib.mf_create_batch.restype = ctypes.c_int
+    lib.mf_batch_info.argtypes = [P, ctypes.c_int32, P, P]
+    lib.mf_batch_info.restype = ctypes.c_int
+    lib.mf_batch_set_caps.argtypes = [P, ctypes.c_int32, P, P, P, ctypes.c_int32, P]
+    lib.mf_batch_set_caps.restype = ctypes.c_int
+    lib.mf_batch_flow_values.argtypes = [P, P]
+    lib.mf_batch_flow_values.restype = ctypes.c_int
+    lib.mf_batch_min_cut.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P]
+    lib.mf_batch_min_cut.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -192,7 +204,7 @@ class Grid:
 
     def solve(self, schedule=MF_SCHED_PARD, gap=True, global_relabel_every=0, check_every=0,
               max_sweeps=0, stream=None, profile=False, region_kernel=MF_KERNEL_AUTO,
-              trace=None):
+              trace=None, graph=False):
         """trace: optional int32 device tensor of shape (cap, TRACE_FIELDS)."""
         tptr, tcap = None, 0
         if trace is not None:
@@ -200,7 +212,8 @@ class Grid:
         o = mf_solve_opts(schedule=schedule, global_relabel_every=global_relabel_every,
                           gap=1 if gap else 0, check_every=check_every, max_sweeps=max_sweeps,
                           model=None, stream=stream, profile=1 if profile else 0,
-                          region_kernel=region_kernel, trace=tptr, trace_cap=tcap)
+                          region_kernel=region_kernel, trace=tptr, trace_cap=tcap,
+                          graph=1 if graph else 0, reserved2=0)
         s = mf_solve_stats()
         _check(load().mf_solve(self._h, ctypes.byref(o), ctypes.byref(s)), "mf_solve")
         return s.as_dict()
@@ -224,6 +237,74 @@ class Grid:
         P = lambda a: ctypes.c_void_p(a.ctypes.data)
         _check(load().mf_get_state(self._h, P(res), P(rt), P(ex), P(lab)), "mf_get_state")
         return dict(res=res, rt=rt, ex=ex, labels=lab)
+
+
+class Batch(Grid):
+    """Many independent 2D instances solved together (mf_create_batch ... mf_destroy)."""
+
+    def __init__(self, dims_list, conn_list, region_shape=None):
+        lib = load()
+        self.count = len(dims_list)
+        self.inst_dims = [tuple(int(x) for x in d) for d in dims_list]
+        self.inst_conn = [int(c) for c in conn_list]
+        d = (ctypes.c_int64 * (2 * self.count))(*[x for dd in self.inst_dims for x in dd])
+        c = (ctypes.c_int32 * self.count)(*self.inst_conn)
+        rs = None
+        if region_shape is not None:
+            rs = (ctypes.c_int32 * 2)(*[int(t) for t in region_shape])
+        h = ctypes.c_void_p()
+        _check(lib.mf_create_batch(self.count, d, c, rs, ctypes.byref(h)), "mf_create_batch")
+        self._h = h
+        off = (ctypes.c_int64 * 2)()
+        dims = (ctypes.c_int64 * 2)()
+        _check(lib.mf_batch_info(self._h, -1, off, dims), "mf_batch_info")
+        self.dims = (dims[0], dims[1])
+        self.ndim = 2
+        self.n = int(dims[0] * dims[1])
+        self.K = 8 if 8 in self.inst_conn else 4
+        self.conn = self.K
+
+    def placement(self, i):
+        off = (ctypes.c_int64 * 2)()
+        dims = (ctypes.c_int64 * 2)()
+        _check(load().mf_batch_info(self._h, int(i), off, dims), "mf_batch_info")
+        return (off[0], off[1]), (dims[0], dims[1])
+
+    def set_caps(self, i, cs, ct, nbr, stream=None):  # noqa: D401 - per instance
+        p1, d1 = _ptr(cs)
+        p2, d2 = _ptr(ct)
+        p3, d3 = _ptr(nbr)
+        if not (d1 == d2 == d3):
+            raise ValueError("capacity arrays must all be on the host or all on the device")
+        n = self.inst_dims[i][0] * self.inst_dims[i][1]
+        for a, size in ((cs, n), (ct, n), (nbr, self.inst_conn[i] * n)):
+            numel = a.size if isinstance(a, np.ndarray) else a.numel()
+            if int(numel) != size:
+                raise ValueError(f"instance {i}: expected {size} capacities, got {int(numel)}")
+        st = ctypes.c_void_p(stream) if stream else None
+        _check(load().mf_batch_set_caps(self._h, int(i), p1, p2, p3, d1, st), "mf_batch_set_caps")
+
+    def flow_values(self):
+        out = np.zeros(self.count, dtype=np.int64)
+        _check(load().mf_batch_flow_values(self._h, ctypes.c_void_p(out.ctypes.data)),
+               "mf_batch_flow_values")
+        return out
+
+    def instance_cut(self, i, kind=MF_CUT_MIN_SOURCE):
+        h, w = self.inst_dims[i]
+        out = np.zeros(h * w, dtype=np.uint8)
+        _check(load().mf_batch_min_cut(self._h, int(i), int(kind), ctypes.c_void_p(out.ctypes.data)),
+               "mf_batch_min_cut")
+        return out
+
+
+def load_batch(instances, region_shape=None):
+    """Create a Batch for synth.GridInstance objects (2D) and load their caps."""
+    b = Batch([inst.dims for inst in instances], [inst.conn for inst in instances], region_shape)
+    for i, inst in enumerate(instances):
+        b.set_caps(i, np.ascontiguousarray(inst.cs, np.int32), np.ascontiguousarray(inst.ct, np.int32),
+                   np.ascontiguousarray(inst.nbr, np.int32))
+    return b
 
 
 def solve_instance(inst, tile=None, **solve_kw):

@@ -235,3 +235,90 @@ def test_abi_errors(mf):
         mf.Grid((8, 8), 6)
     with pytest.raises(mf.MFError):
         mf.Grid((8, 8, 8), 4)
+
+
+# ---------------------------------------------------------------------------
+# Batches (independent instances in one solve)
+# ---------------------------------------------------------------------------
+
+def _batch_check(mf, insts, region_shape, **kw):
+    b = mf.load_batch(insts, region_shape=region_shape)
+    try:
+        st = b.solve(max_sweeps=100000, **kw)
+        flows = b.flow_values()
+        for i, inst in enumerate(insts):
+            ref = oracle.solve_grid(inst)
+            assert flows[i] == ref["flow"], (i, inst.name)
+            assert (b.instance_cut(i, mf.MF_CUT_MIN_SOURCE) == ref["smin"]).all(), (i, inst.name)
+            assert (b.instance_cut(i, mf.MF_CUT_MAX_SOURCE) == ref["smax"]).all(), (i, inst.name)
+        assert b.flow_value() == int(flows.sum())
+    finally:
+        b.close()
+    return st
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (32, 32), (64, 64), (24, 40)])
+def test_batch_mixed_instances_exact(mf, tile):
+    rng = np.random.default_rng(7)
+    insts = []
+    for i in range(30):
+        dims = (int(rng.integers(1, 140)), int(rng.integers(1, 140)))
+        if i % 3 == 0:
+            insts.append(synth.random_grid(dims, 4 if i % 2 else 8, 2000 + i))
+        else:
+            insts.append(synth.blob_grid(dims, 4 if i % 2 else 8, 2000 + i, 3, 6.0, 6.0))
+    print(f"batch of {len(insts)} tile={tile}", flush=True)
+    _batch_check(mf, insts, tile)
+
+
+def test_batch_graph_replay_matches_eager(mf):
+    insts = synth.config3_instances(24)
+    b = mf.load_batch(insts, region_shape=(32, 32))
+    try:
+        b.solve()
+        eager = b.flow_values().copy()
+        cut = b.instance_cut(5)
+        for rep in range(3):  # replays of the captured sweep batches, eager work in between
+            b.solve(graph=True, global_relabel_every=2 * rep)
+            assert (b.flow_values() == eager).all()
+            assert (b.instance_cut(5) == cut).all()
+            b.solve()
+            assert (b.flow_values() == eager).all()
+    finally:
+        b.close()
+
+
+def test_batch_single_connectivity_and_errors(mf):
+    insts = [synth.random_grid((9, 13), 4, 30 + i) for i in range(5)]
+    _batch_check(mf, insts, (8, 8))
+    b = mf.Batch([(9, 13)] * 2, [4, 4], (8, 8))
+    try:
+        b.set_caps(0, insts[0].cs, insts[0].ct, insts[0].nbr)
+        with pytest.raises(mf.MFError) as e:
+            b.solve()  # instance 1 not loaded
+        assert e.value.status == mf.MF_E_STATE
+        bad = insts[1].cs.copy()
+        bad[0] = -3
+        with pytest.raises(mf.MFError) as e:
+            b.set_caps(1, bad, insts[1].ct, insts[1].nbr)
+        assert e.value.status == mf.MF_E_INVAL
+        with pytest.raises(mf.MFError):
+            load = mf.load()
+            import ctypes
+            rc = load.mf_set_caps(b._h, ctypes.c_void_p(insts[0].cs.ctypes.data),
+                                  ctypes.c_void_p(insts[0].ct.ctypes.data),
+                                  ctypes.c_void_p(insts[0].nbr.ctypes.data), 0, None)
+            mf._check(rc, "mf_set_caps")
+    finally:
+        b.close()
+
+
+def test_batch_workload_512_exact(mf):
+    """All 512 instances of the batch workload, autotuned, each exact."""
+    from paper_1109_1146_amd import autotune
+    insts = synth.config3_instances(512)
+    tune = autotune.autotune_batch(insts, calib=24, reps=1)
+    print("autotuned", tune["region_shape"], tune["relabel_every"], flush=True)
+    st = _batch_check(mf, insts, tune["region_shape"], global_relabel_every=tune["relabel_every"],
+                      graph=True)
+    assert st["sweeps"] > 0
