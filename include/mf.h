@@ -64,7 +64,7 @@ enum {
 enum {
     MF_SCHED_PARD = 0,    /* Alg. 2: all active regions against the previous sweep's labels */
     MF_SCHED_COLORED = 1, /* Alg. 1 as phases of non-interacting regions (reserved) */
-    MF_SCHED_LEARNED = 2, /* region order and deferral from a trained scorer (reserved) */
+    MF_SCHED_LEARNED = 2, /* region order and deferral from a trained scorer (opts->model) */
     MF_SCHED_AUTO = 3     /* library's choice (currently MF_SCHED_PARD) */
 };
 
@@ -74,7 +74,7 @@ typedef struct {
     int32_t gap;                  /* 1 = global gap heuristic on (default), 0 = off */
     int32_t check_every;          /* sweeps enqueued between host-side termination checks; 0 = 8 */
     int64_t max_sweeps;           /* guard; 0 = 2|B|^2 + 1 (the bound of Sec. 4.3-4.4) */
-    const void *model;            /* scorer weights for MF_SCHED_LEARNED, else NULL */
+    const void *model;            /* mf_model * for MF_SCHED_LEARNED, else NULL */
     void *stream;                 /* hipStream_t to run on; NULL = the null stream */
     int32_t profile;              /* 1 = time every discharge launch with HIP events */
     int32_t region_kernel;        /* MF_KERNEL_*: where a discharging region lives */
@@ -82,10 +82,28 @@ typedef struct {
                                      one record per region discharge, see MF_TR_* */
     int64_t trace_cap;            /* records the trace buffer holds; extra records are dropped */
     int32_t graph;                /* 1 = replay batches of sweeps as a captured HIP graph (ignored
-                                     with profile or trace); a NULL stream is then replaced by a
-                                     stream owned by the handle */
-    int32_t reserved2;
+                                     with profile, trace, features or MF_SCHED_LEARNED); a NULL
+                                     stream is then replaced by a stream owned by the handle */
+    int32_t max_defer;            /* MF_SCHED_LEARNED: consecutive deferrals after which a region
+                                     is discharged anyway; 0 = 2 */
+    float defer_threshold;        /* MF_SCHED_LEARNED: defer an active region whose predicted
+                                     probability of useful work is below this; 0 = 0.5 */
+    int32_t reserved3;
+    float *features;              /* device buffer [features_cap][regions][MF_FEATURES] or NULL:
+                                     the scheduler's region features at the start of each sweep */
+    int64_t features_cap;         /* sweeps the features buffer holds */
 } mf_solve_opts;
+
+/* region features (floats) written per region and sweep, see mf_solve_opts.features */
+enum {
+    MF_FT_EXCESS = 0,     /* log1p(total excess of active vertices) / 8 */
+    MF_FT_LABEL = 1,      /* log1p(mean finite label of the region's border vertices) / 8 */
+    MF_FT_RESDEG = 2,     /* fraction of outgoing boundary arcs with positive residual */
+    MF_FT_ACTIVE = 3,     /* 1 if the region holds an active vertex */
+    MF_FT_LABEL_SUM = 4,  /* sum over border vertices of min(label, 65535) */
+    MF_FT_EXCESS_RAW = 5, /* total excess of active vertices */
+    MF_FEATURES = 6
+};
 
 /* trace record fields (int32 each) */
 enum {
@@ -223,6 +241,35 @@ mf_status mf_batch_flow_values(const mf_grid *g, int64_t *out);
 
 /* Minimum cut of instance `index` (kind as for mf_min_cut), out[H*W] host. */
 mf_status mf_batch_min_cut(const mf_grid *g, int32_t index, int32_t kind, uint8_t *out_source_side);
+
+/* ---- Learned region scheduler: a CNN over the grid of regions (channels
+ * last, region id order: z-major, x fastest) with 3 input channels (the first
+ * three region features), two hidden layers of `channels` ReLU units and one
+ * output logit per region, all 3x3x3 convolutions with zero padding.  Trained
+ * here with FP32 forward/backward kernels and Adam; used by MF_SCHED_LEARNED
+ * in BF16 (weights and activations rounded to bfloat16, FP32 accumulation).
+ * The score only orders and defers discharges; it never changes the result. */
+typedef struct mf_model mf_model;
+
+/* New model with He-uniform weights from `seed` and zero biases. */
+mf_status mf_model_create(int32_t channels, uint64_t seed, mf_model **out);
+void mf_model_destroy(mf_model *m);
+/* Number of parameters: w1[C][3][27] b1[C] w2[C][C][27] b2[C] w3[1][C][27] b3[1]. */
+int64_t mf_model_num_params(const mf_model *m);
+mf_status mf_model_get_params(const mf_model *m, float *host_out);
+mf_status mf_model_set_params(mf_model *m, const float *host_in);
+/* logits[v] for a D x H x W grid of feature vectors x (device, stride xs floats
+ * per voxel, channels 0..2 used); bf16 = 1 for the inference precision. */
+mf_status mf_model_forward(mf_model *m, const float *x, int32_t xs, int32_t D, int32_t H, int32_t W,
+                           float *logits, int32_t bf16, void *stream);
+/* FP32 forward, binary cross-entropy with logits averaged over mask[v] = 1
+ * voxels (target, mask device arrays [D*H*W]), backward into the model's
+ * gradient buffer; loss and (if not NULL) the gradients are copied to host. */
+mf_status mf_model_loss_grad(mf_model *m, const float *x, int32_t xs, const float *target,
+                             const float *mask, int32_t D, int32_t H, int32_t W, float *loss,
+                             float *grads_out, void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the last gradients. */
+mf_status mf_model_adam_step(mf_model *m, float lr, void *stream);
 
 /* Algorithmic bytes one discharged vertex moves: its K residuals, residual
  * t-link and excess are read and written, its label is written. */

@@ -61,6 +61,9 @@ struct mf_grid {
     int *reginst = nullptr;       // instance of each region (-1: canvas padding)
     int *stage = nullptr;         // one instance's caps on their way to the canvas
     u64 *instRt = nullptr;        // per-instance sum of residual t-links
+    // learned schedule
+    float *feat = nullptr, *score = nullptr;
+    int *defer = nullptr, *deferCount = nullptr, *lorder = nullptr;
     // captured sweep batches
     hipStream_t own_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -88,6 +91,11 @@ static void free_all(mf_grid *g) {
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (g->reginst) (void)hipFree(g->reginst);
+    {
+        void *q[] = {g->feat, g->score, g->defer, g->deferCount, g->lorder};
+        for (void *x : q)
+            if (x) (void)hipFree(x);
+    }
     if (g->stage) (void)hipFree(g->stage);
     if (g->instRt) (void)hipFree(g->instRt);
     if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
@@ -225,6 +233,7 @@ static mf_status create_impl(int32_t ndim, const int64_t *dims, int32_t connecti
         mfd::set_wave_attributes();
         mfd::set_lds_attributes();
         mfd::set_hbm_attributes();
+        mfd::set_sched_attributes();
         attributes_set = true;
     }
     hipDeviceProp_t prop;
@@ -331,6 +340,169 @@ extern "C" mf_status mf_set_caps(mf_grid *g, const int32_t *src_cap, const int32
     return MF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Learned region scheduler model: 3 -> C -> C -> 1 channel 3x3x3 CNN over the
+// region grid (parameter layout in mf_sched.hip), FP32 master parameters,
+// Adam state, and a workspace sized for the largest region grid seen.
+// ---------------------------------------------------------------------------
+struct mf_model {
+    int C = 16;
+    int P = 0;  // number of parameters
+    float *params = nullptr, *grads = nullptr, *am = nullptr, *av = nullptr;
+    int step = 0;
+    int cap = 0;  // voxels the workspace holds
+    float *h1 = nullptr, *h2 = nullptr, *z = nullptr, *gz = nullptr, *gh2 = nullptr, *gh1 = nullptr;
+    float *loss = nullptr;
+    float *hloss = nullptr;  // pinned
+    size_t off_w1 = 0, off_b1 = 0, off_w2 = 0, off_b2 = 0, off_w3 = 0, off_b3 = 0;
+};
+
+static void model_free_ws(mf_model *m) {
+    float *p[] = {m->h1, m->h2, m->z, m->gz, m->gh2, m->gh1};
+    for (float *q : p)
+        if (q) (void)hipFree(q);
+    m->h1 = m->h2 = m->z = m->gz = m->gh2 = m->gh1 = nullptr;
+    m->cap = 0;
+}
+
+static bool model_ws(mf_model *m, int nv) {
+    if (nv <= m->cap) return true;
+    model_free_ws(m);
+    const size_t C = (size_t)m->C;
+    if (!ok(dalloc(&m->h1, C * nv)) || !ok(dalloc(&m->h2, C * nv)) || !ok(dalloc(&m->z, (size_t)nv)) ||
+        !ok(dalloc(&m->gz, (size_t)nv)) || !ok(dalloc(&m->gh2, C * nv)) || !ok(dalloc(&m->gh1, C * nv)))
+        return false;
+    m->cap = nv;
+    return true;
+}
+
+static uint64_t splitmix64(uint64_t &x) {
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+extern "C" mf_status mf_model_create(int32_t channels, uint64_t seed, mf_model **out) {
+    if (!out || channels < 1 || channels > 64) return MF_E_INVAL;
+    mf_model *m = new (std::nothrow) mf_model();
+    if (!m) return MF_E_NOMEM;
+    const int C = channels;
+    m->C = C;
+    m->off_w1 = 0;
+    m->off_b1 = m->off_w1 + (size_t)C * 3 * 27;
+    m->off_w2 = m->off_b1 + C;
+    m->off_b2 = m->off_w2 + (size_t)C * C * 27;
+    m->off_w3 = m->off_b2 + C;
+    m->off_b3 = m->off_w3 + (size_t)C * 27;
+    m->P = (int)(m->off_b3 + 1);
+    std::vector<float> h(m->P, 0.f);
+    uint64_t st = seed;
+    auto fill = [&](size_t off, size_t n, int fan_in) {
+        const double a = std::sqrt(6.0 / fan_in);  // He-uniform
+        for (size_t i = 0; i < n; i++) {
+            const double u = (double)(splitmix64(st) >> 11) * (1.0 / 9007199254740992.0);
+            h[off + i] = (float)((2.0 * u - 1.0) * a);
+        }
+    };
+    fill(m->off_w1, (size_t)C * 3 * 27, 3 * 27);
+    fill(m->off_w2, (size_t)C * C * 27, C * 27);
+    fill(m->off_w3, (size_t)C * 27, C * 27);
+    bool good = ok(dalloc(&m->params, (size_t)m->P)) && ok(dalloc(&m->grads, (size_t)m->P)) &&
+                ok(dalloc(&m->am, (size_t)m->P)) && ok(dalloc(&m->av, (size_t)m->P)) &&
+                ok(dalloc(&m->loss, 1)) &&
+                ok(hipHostMalloc((void **)&m->hloss, sizeof(float), hipHostMallocDefault)) &&
+                ok(hipMemcpy(m->params, h.data(), sizeof(float) * m->P, hipMemcpyHostToDevice)) &&
+                ok(hipMemset(m->grads, 0, sizeof(float) * m->P)) && ok(hipMemset(m->am, 0, sizeof(float) * m->P)) &&
+                ok(hipMemset(m->av, 0, sizeof(float) * m->P));
+    if (!good) {
+        mf_model_destroy(m);
+        return MF_E_NOMEM;
+    }
+    *out = m;
+    return MF_OK;
+}
+
+extern "C" void mf_model_destroy(mf_model *m) {
+    if (!m) return;
+    (void)hipDeviceSynchronize();
+    model_free_ws(m);
+    float *p[] = {m->params, m->grads, m->am, m->av, m->loss};
+    for (float *q : p)
+        if (q) (void)hipFree(q);
+    if (m->hloss) (void)hipHostFree(m->hloss);
+    delete m;
+}
+
+extern "C" int64_t mf_model_num_params(const mf_model *m) { return m ? m->P : 0; }
+
+extern "C" mf_status mf_model_get_params(const mf_model *m, float *host_out) {
+    if (!m || !host_out) return MF_E_INVAL;
+    HIP_TRY(hipMemcpy(host_out, m->params, sizeof(float) * m->P, hipMemcpyDeviceToHost));
+    return MF_OK;
+}
+
+extern "C" mf_status mf_model_set_params(mf_model *m, const float *host_in) {
+    if (!m || !host_in) return MF_E_INVAL;
+    HIP_TRY(hipMemcpy(m->params, host_in, sizeof(float) * m->P, hipMemcpyHostToDevice));
+    return MF_OK;
+}
+
+static hipError_t model_forward(mf_model *m, const float *x, int xs, int D, int H, int W, float *z,
+                                int bf16, hipStream_t s) {
+    const int C = m->C;
+    const float *p = m->params;
+    hipError_t e = mfd::launch_conv3_fwd(x, xs, 3, p + m->off_w1, p + m->off_b1, C, m->h1, D, H, W, 1, bf16, s);
+    if (e != hipSuccess) return e;
+    e = mfd::launch_conv3_fwd(m->h1, C, C, p + m->off_w2, p + m->off_b2, C, m->h2, D, H, W, 1, bf16, s);
+    if (e != hipSuccess) return e;
+    return mfd::launch_conv3_fwd(m->h2, C, C, p + m->off_w3, p + m->off_b3, 1, z, D, H, W, 0, bf16, s);
+}
+
+extern "C" mf_status mf_model_forward(mf_model *m, const float *x, int32_t xs, int32_t D, int32_t H,
+                                      int32_t W, float *logits, int32_t bf16, void *stream) {
+    if (!m || !x || !logits || xs < 3 || D < 1 || H < 1 || W < 1) return MF_E_INVAL;
+    if (!model_ws(m, D * H * W)) return MF_E_NOMEM;
+    HIP_TRY(model_forward(m, x, xs, D, H, W, logits, bf16 ? 1 : 0, (hipStream_t)stream));
+    return MF_OK;
+}
+
+extern "C" mf_status mf_model_loss_grad(mf_model *m, const float *x, int32_t xs, const float *target,
+                                        const float *mask, int32_t D, int32_t H, int32_t W,
+                                        float *loss, float *grads_out, void *stream) {
+    if (!m || !x || !target || !mask || xs < 3 || D < 1 || H < 1 || W < 1) return MF_E_INVAL;
+    const int nv = D * H * W, C = m->C;
+    if (!model_ws(m, nv)) return MF_E_NOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    float *g = m->grads;
+    const float *p = m->params;
+    HIP_TRY(model_forward(m, x, xs, D, H, W, m->z, 0, s));
+    HIP_TRY(mfd::launch_bce(m->z, target, mask, nv, m->gz, m->loss, s));
+    HIP_TRY(mfd::launch_conv3_bwd(m->h2, C, C, p + m->off_w3, m->gz, 1, m->gh2, g + m->off_w3, g + m->off_b3,
+                                  D, H, W, s));
+    HIP_TRY(mfd::launch_relu_bwd(m->gh2, m->h2, nv * C, s));
+    HIP_TRY(mfd::launch_conv3_bwd(m->h1, C, C, p + m->off_w2, m->gh2, C, m->gh1, g + m->off_w2, g + m->off_b2,
+                                  D, H, W, s));
+    HIP_TRY(mfd::launch_relu_bwd(m->gh1, m->h1, nv * C, s));
+    HIP_TRY(mfd::launch_conv3_bwd(x, xs, 3, p + m->off_w1, m->gh1, C, nullptr, g + m->off_w1, g + m->off_b1,
+                                  D, H, W, s));
+    HIP_TRY(hipMemcpyAsync(m->hloss, m->loss, sizeof(float), hipMemcpyDeviceToHost, s));
+    if (grads_out) HIP_TRY(hipMemcpyAsync(grads_out, g, sizeof(float) * m->P, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (loss) *loss = *m->hloss;
+    return MF_OK;
+}
+
+extern "C" mf_status mf_model_adam_step(mf_model *m, float lr, void *stream) {
+    if (!m || !(lr > 0.f)) return MF_E_INVAL;
+    m->step++;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, (float)m->step), c2 = 1.f - std::pow(b2, (float)m->step);
+    HIP_TRY(mfd::launch_adam(m->params, m->grads, m->am, m->av, m->P, lr, b1, b2, 1e-8f, c1, c2,
+                             (hipStream_t)stream));
+    return MF_OK;
+}
+
 // Exact region-distance labels into lab (see k_grelabel), then the active
 // regions and the active-vertex count *act for the next sweep.  Returns the
 // number of distance levels, or -1 on a HIP error.
@@ -385,7 +557,21 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     o.gap = 1;
     if (opts) o = *opts;
     if (o.schedule < 0 || o.schedule > MF_SCHED_AUTO) return MF_E_INVAL;
-    if (o.schedule == MF_SCHED_COLORED || o.schedule == MF_SCHED_LEARNED) return MF_E_INVAL;
+    if (o.schedule == MF_SCHED_COLORED) return MF_E_INVAL;
+    const bool learned = o.schedule == MF_SCHED_LEARNED;
+    mf_model *model = (mf_model *)o.model;
+    if (learned && (!model || g->G.nreg > 16384)) return MF_E_INVAL;
+    const bool feats = learned || (o.features && o.features_cap > 0);
+    if (feats) {
+        const size_t R = (size_t)g->G.nreg;
+        if (!g->feat && !(ok(dalloc(&g->feat, R * mfd::kFeat)) && ok(dalloc(&g->score, R)) &&
+                          ok(dalloc(&g->defer, R)) && ok(dalloc(&g->deferCount, R)) &&
+                          ok(dalloc(&g->lorder, R))))
+            return MF_E_NOMEM;
+        if (learned && !model_ws(model, g->G.nreg)) return MF_E_NOMEM;
+    }
+    if (learned) o.graph = 0;
+    if (feats) o.graph = 0;
     int check_every = o.check_every > 0 ? o.check_every : 8;
     if (o.global_relabel_every < 0) return MF_E_INVAL;
     if (o.global_relabel_every > 0) check_every = o.global_relabel_every;
@@ -417,6 +603,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     HIP_TRY(hipMemsetAsync(g->counters, 0, 4 * sizeof(u64), s));
     HIP_TRY(hipMemsetAsync(g->stats, 0, 16 * sizeof(u64), s));
     HIP_TRY(hipMemsetAsync(g->ractive, 0, sizeof(int) * G.nreg, s));
+    if (learned) HIP_TRY(hipMemsetAsync(g->deferCount, 0, sizeof(int) * G.nreg, s));
     HIP_TRY(mfd::launch_init(G, g->in_cs, g->in_ct, g->in_nbr, (int)g->n, g->res, g->rt, g->ex,
                              g->lab[0], g->lab[1], g->pushb, g->ractive, g->act, s));
 
@@ -506,6 +693,32 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                 D.labOld = g->lab[p]; D.labNew = g->lab[p ^ 1];
                 D.actIn = g->act + p; D.qhead = g->qhead + p;
                 D.sweep = (int)(first + j);
+                if (feats) {
+                    // region features at the start of the sweep; the learned
+                    // schedule scores them (BF16) and builds the queue
+                    mfd::FeatArgs FA;
+                    FA.G = G; FA.ex = g->ex; FA.lab = g->lab[p]; FA.res = g->res;
+                    FA.ringL = g->ringL; FA.ringM = g->ringM; FA.nring = g->nring; FA.dinf = g->dinf;
+                    FA.out = (o.features && first + j < o.features_cap)
+                                 ? o.features + (size_t)(first + j) * G.nreg * mfd::kFeat
+                                 : g->feat;
+                    if (!ok(mfd::launch_region_features(FA, s))) return false;
+                    if (learned) {
+                        if (!ok(model_forward(model, FA.out, mfd::kFeat, G.rz, G.ry, G.rx, g->score, 1, s)))
+                            return false;
+                        mfd::SchedArgs SA;
+                        SA.nreg = G.nreg; SA.feat = FA.out; SA.score = g->score;
+                        // no deferral in the first sweep: every initially active
+                        // region is discharged once, so afterwards only boundary
+                        // vertices can be active and the active count sees them all
+                        SA.threshold = (first + j == 0) ? -1.f : (o.defer_threshold > 0.f ? o.defer_threshold : 0.5f);
+                        SA.maxDefer = o.max_defer > 0 ? o.max_defer : 2;
+                        SA.defer = g->defer; SA.deferCount = g->deferCount; SA.order = g->lorder;
+                        if (!ok(mfd::launch_sched_queue(SA, s))) return false;
+                        D.order = g->lorder;
+                        D.defer = g->defer;
+                    }
+                }
                 if (o.profile && !ok(hipEventRecord(ev[2 * j], s))) return false;
                 hipError_t e;
                 if (regionMode == 2) e = mfd::launch_discharge_wave(D, regionBlocks, regionLds, regionNarrow, s);

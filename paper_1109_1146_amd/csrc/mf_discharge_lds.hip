@@ -146,7 +146,9 @@ __global__ __launch_bounds__(NT) void k_discharge_lds(DischargeArgs A) {
         const int base = r * V;
         if (tid == 0) {
             s_active = A.ractive[r];
-            A.ractive[r] = 0;
+            // a deferred region keeps its flag and is discharged in a later sweep
+            if (s_active && A.defer && A.defer[r]) s_active = 0;
+            else A.ractive[r] = 0;
         }
         __syncthreads();
         if (!s_active) {

@@ -138,7 +138,9 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
         int active = 0;
         if (lane == 0) {
             active = A.ractive[r];
-            A.ractive[r] = 0;
+            // a deferred region keeps its flag and is discharged in a later sweep
+            if (active && A.defer && A.defer[r]) active = 0;
+            else A.ractive[r] = 0;
         }
         active = __shfl(active, 0, 64);
         if (!active) {

@@ -140,6 +140,7 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
     extern __shared__ int smem[];
     __shared__ int s_r, s_active, s_qtail, s_nsteps, s_min, s_found;
     __shared__ int s_wmin[NT / 64];
+    __shared__ long long s_tr[4];  // trace: excess out, to sink, to boundary, label sum
     if (*A.actIn == 0ull) return;
     const Geo &G = A.G;
     const int V = G.V, N = G.N, tid = threadIdx.x;
@@ -167,7 +168,9 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
         const int base = r * V;
         if (tid == 0) {
             s_active = A.ractive[r];
-            A.ractive[r] = 0;
+            // a deferred region keeps its flag and is discharged in a later sweep
+            if (s_active && A.defer && A.defer[r]) s_active = 0;
+            else A.ractive[r] = 0;
         }
         __syncthreads();
         if (!s_active) {
@@ -179,6 +182,8 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
 
         int iter = 0;
         long long bfs_steps = 0, classes = 0;
+        const long long t_start = wall_clock64();
+        if (tid < 4) s_tr[tid] = 0;
         for (;;) {
             // ---------------- multi-level search from the targets ----------------
             for (int l = tid; l < V; l += NT) S[l] = kInf;
@@ -318,6 +323,7 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
                                 int d = min(e, t);
                                 rt[base + u] = t - d;
                                 e -= d;
+                                if (A.trace) atomicAdd((unsigned long long *)&s_tr[1], (u64)d);
                             }
                         } else {
                             for (int k = 0; k < G.K && e > 0; k++) {
@@ -333,6 +339,7 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
                                 res[a] = c - d;
                                 pushb[a] += d;
                                 e -= d;
+                                if (A.trace) atomicAdd((unsigned long long *)&s_tr[2], (u64)d);
                             }
                         }
                     } else {
@@ -359,12 +366,39 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
             int s = S[l];
             A.labNew[base + l] = (s == kInf) ? dinf : min(stepLevel[s], dinf);
         }
+        if (A.trace) {
+            long long ex_out = 0, lsum = 0;
+            for (int l = tid; l < V; l += NT) ex_out += ex[base + l];
+            for (int i = tid; i < A.nring; i += NT) {
+                const int s = S[A.ringL[i]];
+                lsum += (s == kInf) ? 65535 : min(stepLevel[s], 65535);
+            }
+            atomicAdd((unsigned long long *)&s_tr[0], (u64)ex_out);
+            atomicAdd((unsigned long long *)&s_tr[3], (u64)lsum);
+        }
+        __syncthreads();
         if (tid == 0) {
             atomicAdd(&A.stats[0], 1ull);
             atomicAdd(&A.stats[1], (u64)A.rvcount[r]);
             atomicAdd(&A.stats[2], (u64)(iter + 1));
             atomicAdd(&A.stats[3], (u64)bfs_steps);
             atomicAdd(&A.stats[4], (u64)classes);
+            if (A.trace) {
+                unsigned long long idx = atomicAdd(&A.stats[5], 1ull);
+                if ((long long)idx < A.traceCap) {
+                    int *rec = A.trace + idx * 10;
+                    rec[0] = A.sweep;
+                    rec[1] = r;
+                    rec[2] = iter + 1;
+                    rec[3] = (int)min(bfs_steps, 0x7fffffffLL);
+                    rec[4] = (int)min(classes, 0x7fffffffLL);
+                    rec[5] = (int)min(wall_clock64() - t_start, 0x7fffffffLL);
+                    rec[6] = (int)min(s_tr[0] + s_tr[1] + s_tr[2], 0x7fffffffLL);
+                    rec[7] = (int)min(s_tr[1], 0x7fffffffLL);
+                    rec[8] = (int)min(s_tr[2], 0x7fffffffLL);
+                    rec[9] = (int)min(s_tr[3], 0x7fffffffLL);
+                }
+            }
         }
         __syncthreads();
     }

@@ -29,6 +29,28 @@ struct DischargeArgs {
     int *trace;          // optional per-discharge records (MF_TRACE_FIELDS int32 each)
     long long traceCap;
     int sweep;           // sweep index of this launch
+    const int *defer;    // optional: 1 = an active region is deferred this sweep (keeps its flag)
+};
+
+constexpr int kFeat = 6;  // floats per region in the scheduler features
+
+struct FeatArgs {
+    Geo G;
+    const int *ex, *lab, *res;
+    const int *ringL;
+    const unsigned char *ringM;
+    int nring;
+    int dinf;
+    float *out;  // [nreg][kFeat]
+};
+
+struct SchedArgs {
+    int nreg;
+    const float *feat;    // [nreg][kFeat]
+    const float *score;   // [nreg] logits
+    float threshold;      // defer an active region when sigmoid(score) < threshold
+    int maxDefer;         // ... unless it was deferred this many sweeps in a row
+    int *defer, *deferCount, *order;
 };
 
 struct FuseArgs {
@@ -103,6 +125,19 @@ hipError_t launch_activity(const Geo &G, const int *ex, const int *lab, int dinf
 void set_wave_attributes();
 void set_lds_attributes();
 void set_hbm_attributes();
+void set_sched_attributes();
+
+hipError_t launch_region_features(const FeatArgs &A, hipStream_t s);
+hipError_t launch_conv3_fwd(const float *x, int xs, int cin, const float *w, const float *b, int cout,
+                            float *y, int D, int H, int W, int relu, int bf16, hipStream_t s);
+hipError_t launch_conv3_bwd(const float *x, int xs, int cin, const float *w, const float *gy, int cout,
+                            float *gx, float *gw, float *gb, int D, int H, int W, hipStream_t s);
+hipError_t launch_relu_bwd(float *g, const float *y, int n, hipStream_t s);
+hipError_t launch_bce(const float *z, const float *t, const float *m, int n, float *gz, float *loss,
+                      hipStream_t s);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_sched_queue(const SchedArgs &A, hipStream_t s);
 
 hipError_t launch_validate(const Geo &G, const int *cs, const int *ct, const int *nbr, int n,
                            int *err, hipStream_t s);

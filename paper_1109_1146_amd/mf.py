@@ -20,13 +20,16 @@ MF_CUT_MIN_SOURCE, MF_CUT_MAX_SOURCE = 0, 1
 MF_SCHED_PARD, MF_SCHED_COLORED, MF_SCHED_LEARNED, MF_SCHED_AUTO = 0, 1, 2, 3
 MF_KERNEL_AUTO, MF_KERNEL_HBM, MF_KERNEL_LDS, MF_KERNEL_WAVE = 0, 1, 2, 3
 TRACE_FIELDS = 10
+FEATURES = 6
 TRACE_NAMES = ("sweep", "region", "rounds", "levels", "stages", "ticks", "excess_in", "to_sink",
                "to_boundary", "label_sum")
 
 EXPORTED = ("mf_create_grid", "mf_set_caps", "mf_solve", "mf_flow_value", "mf_min_cut",
             "mf_get_state", "mf_get_info", "mf_discharge_bytes_per_vertex", "mf_destroy",
             "mf_status_str", "mf_create_batch", "mf_batch_info", "mf_batch_set_caps",
-            "mf_batch_flow_values", "mf_batch_min_cut")
+            "mf_batch_flow_values", "mf_batch_min_cut", "mf_model_create", "mf_model_destroy",
+            "mf_model_num_params", "mf_model_get_params", "mf_model_set_params", "mf_model_forward",
+            "mf_model_loss_grad", "mf_model_adam_step")
 
 
 class mf_solve_opts(ctypes.Structure):
@@ -36,7 +39,9 @@ class mf_solve_opts(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("profile", ctypes.c_int32),
                 ("region_kernel", ctypes.c_int32), ("trace", ctypes.c_void_p),
                 ("trace_cap", ctypes.c_int64), ("graph", ctypes.c_int32),
-                ("reserved2", ctypes.c_int32)]
+                ("max_defer", ctypes.c_int32), ("defer_threshold", ctypes.c_float),
+                ("reserved3", ctypes.c_int32), ("features", ctypes.c_void_p),
+                ("features_cap", ctypes.c_int64)]
 
 
 class mf_solve_stats(ctypes.Structure):
@@ -111,6 +116,24 @@ def load(path: str = LIB_PATH):
     lib.mf_batch_flow_values.restype = ctypes.c_int
     lib.mf_batch_min_cut.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P]
     lib.mf_batch_min_cut.restype = ctypes.c_int
+    lib.mf_model_create.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(P)]
+    lib.mf_model_create.restype = ctypes.c_int
+    lib.mf_model_destroy.argtypes = [P]
+    lib.mf_model_destroy.restype = None
+    lib.mf_model_num_params.argtypes = [P]
+    lib.mf_model_num_params.restype = ctypes.c_int64
+    lib.mf_model_get_params.argtypes = [P, P]
+    lib.mf_model_get_params.restype = ctypes.c_int
+    lib.mf_model_set_params.argtypes = [P, P]
+    lib.mf_model_set_params.restype = ctypes.c_int
+    lib.mf_model_forward.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, P, ctypes.c_int32, P]
+    lib.mf_model_forward.restype = ctypes.c_int
+    lib.mf_model_loss_grad.argtypes = [P, P, ctypes.c_int32, P, P, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_float), P, P]
+    lib.mf_model_loss_grad.restype = ctypes.c_int
+    lib.mf_model_adam_step.argtypes = [P, ctypes.c_float, P]
+    lib.mf_model_adam_step.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -204,16 +227,24 @@ class Grid:
 
     def solve(self, schedule=MF_SCHED_PARD, gap=True, global_relabel_every=0, check_every=0,
               max_sweeps=0, stream=None, profile=False, region_kernel=MF_KERNEL_AUTO,
-              trace=None, graph=False):
+              trace=None, graph=False, model=None, max_defer=0, defer_threshold=0.0,
+              features=None):
         """trace: optional int32 device tensor of shape (cap, TRACE_FIELDS)."""
         tptr, tcap = None, 0
         if trace is not None:
             tptr, tcap = trace.data_ptr(), int(trace.shape[0])
+        fptr, fcap = None, 0
+        if features is not None:
+            fptr, fcap = features.data_ptr(), int(features.shape[0])
         o = mf_solve_opts(schedule=schedule, global_relabel_every=global_relabel_every,
                           gap=1 if gap else 0, check_every=check_every, max_sweeps=max_sweeps,
                           model=None, stream=stream, profile=1 if profile else 0,
                           region_kernel=region_kernel, trace=tptr, trace_cap=tcap,
-                          graph=1 if graph else 0, reserved2=0)
+                          graph=1 if graph else 0, max_defer=max_defer,
+                          defer_threshold=defer_threshold, reserved3=0, features=fptr,
+                          features_cap=fcap)
+        if model is not None:
+            o.model = model._h
         s = mf_solve_stats()
         _check(load().mf_solve(self._h, ctypes.byref(o), ctypes.byref(s)), "mf_solve")
         return s.as_dict()
@@ -296,6 +327,66 @@ class Batch(Grid):
         _check(load().mf_batch_min_cut(self._h, int(i), int(kind), ctypes.c_void_p(out.ctypes.data)),
                "mf_batch_min_cut")
         return out
+
+
+class Model:
+    """The scheduler CNN (mf_model_*).  Tensors are torch CUDA float32 tensors."""
+
+    def __init__(self, channels=16, seed=0):
+        h = ctypes.c_void_p()
+        _check(load().mf_model_create(int(channels), int(seed), ctypes.byref(h)), "mf_model_create")
+        self._h = h
+        self.channels = int(channels)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().mf_model_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_params(self):
+        return int(load().mf_model_num_params(self._h))
+
+    def get_params(self):
+        out = np.zeros(self.num_params, dtype=np.float32)
+        _check(load().mf_model_get_params(self._h, ctypes.c_void_p(out.ctypes.data)), "get_params")
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.num_params
+        _check(load().mf_model_set_params(self._h, ctypes.c_void_p(p.ctypes.data)), "set_params")
+
+    def forward(self, x, dims, bf16=True, stream=None):
+        """x: CUDA float32 tensor [D*H*W, xs]; returns logits tensor [D*H*W]."""
+        import torch
+        D, H, W = dims
+        out = torch.empty(D * H * W, dtype=torch.float32, device=x.device)
+        _check(load().mf_model_forward(self._h, ctypes.c_void_p(x.data_ptr()), int(x.shape[1]), D, H, W,
+                                       ctypes.c_void_p(out.data_ptr()), 1 if bf16 else 0,
+                                       ctypes.c_void_p(stream) if stream else None), "forward")
+        return out
+
+    def loss_grad(self, x, target, mask, dims, want_grads=False, stream=None):
+        D, H, W = dims
+        loss = ctypes.c_float()
+        g = np.zeros(self.num_params, dtype=np.float32) if want_grads else None
+        _check(load().mf_model_loss_grad(
+            self._h, ctypes.c_void_p(x.data_ptr()), int(x.shape[1]), ctypes.c_void_p(target.data_ptr()),
+            ctypes.c_void_p(mask.data_ptr()), D, H, W, ctypes.byref(loss),
+            ctypes.c_void_p(g.ctypes.data) if g is not None else None,
+            ctypes.c_void_p(stream) if stream else None), "loss_grad")
+        return float(loss.value), g
+
+    def adam_step(self, lr, stream=None):
+        _check(load().mf_model_adam_step(self._h, float(lr), ctypes.c_void_p(stream) if stream else None),
+               "adam_step")
 
 
 def load_batch(instances, region_shape=None):

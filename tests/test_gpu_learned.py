@@ -1,0 +1,133 @@
+"""Learned region scheduler on the GPU: gradient check of the HIP training
+kernels against the FP64 CPU reference, BF16 inference tolerance, training
+progress, and exactness of solves under learned (or arbitrary) scores."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import cnn
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mf():
+    from paper_1109_1146_amd import mf as _mf
+    _mf.load()
+    return _mf
+
+
+def _rand_problem(rng, dims, C=16):
+    p = rng.normal(scale=0.3, size=cnn.num_params(C)).astype(np.float32)
+    x = rng.normal(size=dims + (6,)).astype(np.float32)
+    t = (rng.uniform(size=dims) < 0.4).astype(np.float32)
+    m = (rng.uniform(size=dims) < 0.7).astype(np.float32)
+    return p, x, t, m
+
+
+@pytest.mark.parametrize("dims", [(1, 32, 32), (8, 8, 8), (2, 5, 7)])
+def test_gpu_gradients_match_fp64_reference(mf, dims):
+    import torch
+    rng = np.random.default_rng(3)
+    p, x, t, m = _rand_problem(rng, dims)
+    model = mf.Model(16)
+    model.set_params(p)
+    X = torch.from_numpy(x.reshape(-1, 6)).cuda()
+    loss, g = model.loss_grad(X, torch.from_numpy(t.reshape(-1)).cuda(),
+                              torch.from_numpy(m.reshape(-1)).cuda(), dims, want_grads=True)
+    rl, rg = cnn.loss_and_grad(p.astype(np.float64), x.astype(np.float64), t, m, 16)
+    assert abs(loss - rl) <= 1e-4 * max(1.0, abs(rl))
+    scale = np.abs(rg).max()
+    np.testing.assert_allclose(g, rg, rtol=0, atol=2e-4 * scale)
+
+
+def test_gpu_forward_fp32_and_bf16(mf):
+    import torch
+    rng = np.random.default_rng(4)
+    dims = (8, 8, 8)
+    p, x, _, _ = _rand_problem(rng, dims)
+    model = mf.Model(16)
+    model.set_params(p)
+    X = torch.from_numpy(x.reshape(-1, 6)).cuda()
+    z32 = model.forward(X, dims, bf16=False).cpu().numpy()
+    z16 = model.forward(X, dims, bf16=True).cpu().numpy()
+    ref, _ = cnn.forward(p.astype(np.float64), x.astype(np.float64), 16)
+    ref = ref.reshape(-1)
+    scale = np.abs(ref).max()
+    np.testing.assert_allclose(z32, ref, rtol=0, atol=1e-4 * scale)
+    # bfloat16 keeps 8 significand bits: 3 layers of rounding stay within a few percent of the scale
+    np.testing.assert_allclose(z16, ref, rtol=0, atol=5e-2 * scale)
+
+
+def test_training_reduces_loss(mf):
+    import torch
+    rng = np.random.default_rng(5)
+    dims = (1, 16, 16)
+    x = rng.normal(size=dims + (6,)).astype(np.float32)
+    t = (x[..., 0] + 0.5 * x[..., 2] > 0).astype(np.float32)  # a learnable rule
+    m = np.ones(dims, np.float32)
+    X = torch.from_numpy(x.reshape(-1, 6)).cuda()
+    T = torch.from_numpy(t.reshape(-1)).cuda()
+    M = torch.from_numpy(m.reshape(-1)).cuda()
+    model = mf.Model(16, seed=1)
+    first, _ = model.loss_grad(X, T, M, dims)
+    for _ in range(150):
+        loss, _ = model.loss_grad(X, T, M, dims)
+        model.adam_step(3e-3)
+    assert loss < 0.5 * first
+
+
+def _exact(mf, inst, **kw):
+    out = mf.solve_instance(inst, max_sweeps=100000, **kw)
+    ref = oracle.solve_grid(inst)
+    assert out["flow"] == ref["flow"]
+    assert (out["smin"] == ref["smin"]).all() and (out["smax"] == ref["smax"]).all()
+    return out
+
+
+@pytest.mark.parametrize("threshold,max_defer", [(0.5, 2), (0.95, 1), (0.99, 4)])
+@pytest.mark.parametrize("seed", range(6))
+def test_learned_schedule_exact_with_arbitrary_scores(mf, seed, threshold, max_defer):
+    """Whatever the network says, the flow and cuts are the oracle's."""
+    cases = [((40, 36), 8, (8, 8)), ((30, 50), 4, (10, 16)), ((9, 10, 11), 6, (4, 4, 4))]
+    dims, conn, tile = cases[seed % len(cases)]
+    inst = synth.random_grid(dims, conn, 700 + seed, tile=tile)
+    model = mf.Model(16, seed=seed)  # untrained: arbitrary scores
+    _exact(mf, inst, schedule=mf.MF_SCHED_LEARNED, model=model, defer_threshold=threshold,
+           max_defer=max_defer)
+
+
+def test_learned_schedule_needs_model(mf):
+    inst = synth.random_grid((8, 8), 4, 1, tile=(4, 4))
+    with mf.Grid(inst.dims, 4, (4, 4)) as g:
+        g.set_caps(inst.cs, inst.ct, inst.nbr)
+        with pytest.raises(mf.MFError) as e:
+            g.solve(schedule=mf.MF_SCHED_LEARNED)
+        assert e.value.status == mf.MF_E_INVAL
+
+
+def test_trained_network_gain_over_skeleton(mf):
+    """Ablation: the same learned-schedule skeleton driven by the trained network
+    vs by an untrained network (random weights), and plain P-ARD.  All three give
+    the oracle's flow; the trained network defers fewer useful discharges than
+    random scores (so it needs no more sweeps) and skips discharges plain P-ARD does."""
+    from paper_1109_1146_amd import learned
+    inst = synth.blob_grid((1024, 1024), 8, 7, 24, 10.0, 60.0, zero_frac=0.1, tile=(64, 64))
+    ref = oracle.solve_grid(inst)
+    trained = learned.load_model()
+    untrained = mf.Model(16, seed=123)
+    res = {}
+    with mf.Grid(inst.dims, inst.conn, inst.tile) as g:
+        g.set_caps(inst.cs, inst.ct, inst.nbr)
+        for name, kw in (("plain", {}),
+                         ("trained", dict(schedule=mf.MF_SCHED_LEARNED, model=trained)),
+                         ("untrained", dict(schedule=mf.MF_SCHED_LEARNED, model=untrained))):
+            if "model" in kw:
+                kw.update(defer_threshold=learned.DEFAULT_THRESHOLD, max_defer=learned.DEFAULT_MAX_DEFER)
+            st = g.solve(global_relabel_every=8, **kw)
+            assert g.flow_value() == ref["flow"]
+            res[name] = (st["sweeps"], st["region_discharges"])
+    print("ablation (sweeps, region discharges):", res, flush=True)
+    assert res["trained"][0] <= res["untrained"][0]
+    assert res["trained"][1] < res["plain"][1]
