@@ -56,6 +56,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", choices=sorted(WORKLOADS), default="2d")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-learned", action="store_true",
+                   help="skip the learned-schedule comparison solves (profiling runs)")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="CPU work budget of the oracle baseline sample")
     p.add_argument("--relabel-every", type=int, default=8,
@@ -259,6 +261,30 @@ def main():
             "algorithmic_bytes_per_launch": round(d_bytes / max(d_launch, 1), 1),
         },
     }
+    # the learned-ordered schedule on the same input (untimed in value): sweeps,
+    # discharges and wall time next to plain P-ARD, same exact flow
+    try:
+        if args.no_learned:
+            raise ValueError("skipped (--no-learned)")
+        from paper_1109_1146_amd import learned
+        model = learned.load_model()
+        lkw = dict(schedule=mf.MF_SCHED_LEARNED, model=model, defer_threshold=learned.DEFAULT_THRESHOLD,
+                   max_defer=learned.DEFAULT_MAX_DEFER, global_relabel_every=args.relabel_every,
+                   stream=stream.cuda_stream)
+        g.solve(**lkw)
+        times = []
+        for _ in range(max(1, min(args.steps, 3))):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            lst = g.solve(**lkw)
+            times.append((time.perf_counter() - t1) * 1e3)
+        rec["learned"] = {"solve_ms": round(float(np.median(times)), 3), "sweeps": lst["sweeps"],
+                          "region_discharges": lst["region_discharges"],
+                          "flow_equal": g.flow_value() == flow,
+                          "plain_solve_ms": rec["solve_ms"], "plain_sweeps": rec["sweeps"],
+                          "plain_region_discharges": rec["region_discharges"]}
+    except (OSError, ValueError) as e:  # no trained model in the tree
+        rec["learned"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         ref, cb = cpu_baseline(inst, args.cpu_seconds)
         rec["cpu_baseline"] = cb
