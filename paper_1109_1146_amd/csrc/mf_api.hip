@@ -231,6 +231,7 @@ static mf_status create_impl(int32_t ndim, const int64_t *dims, int32_t connecti
     static bool attributes_set = false;
     if (!attributes_set) {
         mfd::set_wave_attributes();
+        mfd::set_rows_attributes();
         mfd::set_lds_attributes();
         mfd::set_hbm_attributes();
         mfd::set_sched_attributes();
@@ -639,18 +640,33 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         if (narrowOk && b16 <= ldsBudget) { groupLds = b16; groupNarrow = 1; }
         else if (b32 <= ldsBudget) { groupLds = b32; }
     }
-    int regionMode = 0;  // 0: HBM, 1: LDS workgroup, 2: wavefront
+    // 3D 6-connected regions with 32-vertex rows: one workgroup, row bitmasks
+    // in registers and LDS, integer state in HBM (ROWS)
+    size_t rowsLds = 0;
+    {
+        const int R = G.ty * G.tz;
+        if (g->ndim == 3 && G.K == 6 && G.tx == 32 && G.ty >= 2 && G.tz >= 2 && R % 64 == 0 &&
+            R <= 1024 && mfd::rows_slots(g->nring) > 0 && mfd::discharge_rows_bytes(G.ty, G.tz, g->nring) <= ldsBudget) {
+            rowsLds = mfd::discharge_rows_bytes(G.ty, G.tz, g->nring);
+        }
+    }
+    int regionMode = 0;  // 0: HBM, 1: LDS workgroup, 2: wavefront, 3: row-bitmask workgroup
     switch (o.region_kernel) {
-        case MF_KERNEL_AUTO: regionMode = waveLds ? 2 : (groupLds ? 1 : 0); break;
+        case MF_KERNEL_AUTO: regionMode = waveLds ? 2 : (rowsLds ? 3 : (groupLds ? 1 : 0)); break;
         case MF_KERNEL_HBM: regionMode = 0; break;
         case MF_KERNEL_LDS: if (!groupLds) return MF_E_INVAL; regionMode = 1; break;
         case MF_KERNEL_WAVE: if (!waveLds) return MF_E_INVAL; regionMode = 2; break;
+        case MF_KERNEL_ROWS: if (!rowsLds) return MF_E_INVAL; regionMode = 3; break;
         default: return MF_E_INVAL;
     }
-    const size_t regionLds = regionMode == 2 ? waveLds : groupLds;
+    const size_t regionLds = regionMode == 3 ? rowsLds : (regionMode == 2 ? waveLds : groupLds);
     const int regionNarrow = regionMode == 2 ? waveNarrow : groupNarrow;
     int regionBlocks = g->nslots;
-    if (regionMode) {
+    if (regionMode == 3) {
+        // at most two 1024-thread workgroups fit the wave slots of a compute unit
+        int occ = (int)std::max<size_t>(1, std::min<size_t>(2, g->ldsMax / (regionLds + 256)));
+        regionBlocks = std::max(1, std::min(G.nreg, g->numCU * occ));
+    } else if (regionMode) {
         int occ = (int)std::max<size_t>(1, std::min<size_t>(8, g->ldsMax / (regionLds + 256)));
         regionBlocks = std::max(1, std::min(G.nreg, g->numCU * occ));
     }
@@ -721,7 +737,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                 }
                 if (o.profile && !ok(hipEventRecord(ev[2 * j], s))) return false;
                 hipError_t e;
-                if (regionMode == 2) e = mfd::launch_discharge_wave(D, regionBlocks, regionLds, regionNarrow, s);
+                if (regionMode == 3) e = mfd::launch_discharge_rows(D, regionBlocks, regionLds, s);
+                else if (regionMode == 2) e = mfd::launch_discharge_wave(D, regionBlocks, regionLds, regionNarrow, s);
                 else if (regionMode == 1) e = mfd::launch_discharge_lds(D, regionBlocks, regionLds, regionNarrow, s);
                 else e = mfd::launch_discharge(D, g->nslots, g->threads, lds, s);
                 if (!ok(e)) return false;

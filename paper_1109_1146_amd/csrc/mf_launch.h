@@ -123,6 +123,7 @@ hipError_t launch_activity(const Geo &G, const int *ex, const int *lab, int dinf
 // Let every discharge kernel use the full LDS of a compute unit (done once,
 // before any launch or stream capture).
 void set_wave_attributes();
+void set_rows_attributes();
 void set_lds_attributes();
 void set_hbm_attributes();
 void set_sched_attributes();
@@ -154,6 +155,12 @@ size_t discharge_lds_bytes(int V, int K, int nring, int narrow);
 hipError_t launch_discharge_wave(const DischargeArgs &A, int blocks, size_t lds, int narrow,
                                  hipStream_t s);
 size_t discharge_wave_bytes(int V, int K, int nring, int narrow);
+// Row-bitmask workgroup discharge: 3D 6-connected regions with tx == 32,
+// ty, tz >= 2, ty * tz a multiple of 64 and at most 1024, and at most 21 * 1024
+// border vertices (rows_slots() == 0: not applicable).
+hipError_t launch_discharge_rows(const DischargeArgs &A, int blocks, size_t lds, hipStream_t s);
+size_t discharge_rows_bytes(int ty, int tz, int nring);
+int rows_slots(int nring);
 hipError_t launch_fuse(const FuseArgs &A, hipStream_t s);
 hipError_t launch_gap_find(const GapArgs &A, hipStream_t s);
 hipError_t launch_gap_apply(const GapApplyArgs &A, hipStream_t s);

@@ -160,6 +160,46 @@ def test_wave_kernel_tiles(mf, seed):
     _check(mf, inst, region_kernel=mf.MF_KERNEL_WAVE)
 
 
+ROWS_TILES = [(2, 32, 32), (4, 16, 32), (8, 8, 32), (16, 4, 32), (32, 2, 32), (32, 32, 32), (4, 32, 32)]
+
+
+@pytest.mark.parametrize("seed", range(21))
+def test_rows_kernel_tiles(mf, seed):
+    """The row-bitmask workgroup kernel on 3D tiles with 32-vertex rows and every
+    admissible row count, ragged grids, random and blob capacities."""
+    rng = np.random.default_rng(seed)
+    tile = ROWS_TILES[seed % len(ROWS_TILES)]
+    dims = tuple(int(rng.integers(t, 2 * t + 3)) for t in tile)  # tiles are clamped to the grid
+    if seed % 3 == 2:
+        inst = synth.blob_grid(dims, 6, 1300 + seed, 4, 2.0, 6.0, tile=tile, name=f"rows_blob_{seed}")
+    else:
+        inst = synth.random_grid(dims, 6, 1200 + seed, tile=tile, cap_hi=20 if seed % 2 else 10)
+    out, _ = _check(mf, inst, region_kernel=mf.MF_KERNEL_ROWS)
+    B = out["info"]["boundary_size"]
+    assert out["stats"]["sweeps"] <= 2 * max(B, 1) ** 2 + 1
+    _check(mf, inst, region_kernel=mf.MF_KERNEL_ROWS, global_relabel_every=2)
+
+
+def test_workload2_hbm_kernel_exact(mf):
+    inst = synth.config(2)
+    _check(mf, inst, certify=False, region_kernel=mf.MF_KERNEL_HBM)
+
+
+def test_rows_kernel_selection(mf):
+    """ROWS needs 3D tiles with 32-vertex rows; it is the default where it applies."""
+    inst = synth.random_grid((10, 20, 40), 6, 5, tile=(4, 16, 32))
+    with mf.Grid(inst.dims, inst.conn, inst.tile) as g:
+        g.set_caps(inst.cs, inst.ct, inst.nbr)
+        g.solve(region_kernel=mf.MF_KERNEL_ROWS)
+    for dims, conn, tile in (((64, 64), 8, (32, 32)), ((8, 8, 40), 6, (8, 8, 16)), ((8, 8, 40), 6, (3, 8, 32))):
+        inst = synth.random_grid(dims, conn, 6, tile=tile)
+        with mf.Grid(inst.dims, inst.conn, inst.tile) as g:
+            g.set_caps(inst.cs, inst.ct, inst.nbr)
+            with pytest.raises(mf.MFError) as e:
+                g.solve(region_kernel=mf.MF_KERNEL_ROWS)
+            assert e.value.status == mf.MF_E_INVAL
+
+
 @pytest.mark.parametrize("cfg", [1, 2])
 def test_full_size_global_relabel_exact(mf, cfg):
     inst = synth.config(cfg)
