@@ -35,6 +35,7 @@ struct mf_grid {
     bool useLDS = false;
     size_t ldsMax = 0;            // LDS bytes a workgroup may use
     int maxPair = 0, maxCt = 0;   // largest c(u,v)+c(v,u) and c(v,t) of the loaded instance
+    int maxIn = 0;                // largest c(s,v) + sum_u c(u,v): bounds every excess
     int threads = 256;
     // device control block
     u64 *act = nullptr;           // [2]
@@ -56,7 +57,7 @@ struct mf_grid {
     int batch = 0;                // number of instances; 0 for a single grid
     std::vector<int> iy0, ix0, ih, iw, iconn;
     std::vector<long long> isum_cs, isum_ct, iflow;
-    std::vector<int> imaxpair, imaxct;
+    std::vector<int> imaxpair, imaxct, imaxin;
     std::vector<char> iloaded;
     int *reginst = nullptr;       // instance of each region (-1: canvas padding)
     int *stage = nullptr;         // one instance's caps on their way to the canvas
@@ -333,6 +334,7 @@ extern "C" mf_status mf_set_caps(mf_grid *g, const int32_t *src_cap, const int32
     int err = ((int *)(g->pinned + 2))[0];
     g->maxPair = ((int *)(g->pinned + 2))[1];
     g->maxCt = ((int *)(g->pinned + 2))[2];
+    g->maxIn = ((int *)(g->pinned + 2))[3];
     if (err & 1) return MF_E_INVAL;
     if (err & 2) return MF_E_OVERFLOW;
     g->sum_cs = (long long)g->pinned[0];
@@ -830,6 +832,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         st->push_ticks = (int64_t)g->pinned[23];
         st->setup_ticks = (int64_t)g->pinned[24];
         st->flood_ticks = (int64_t)g->pinned[25];
+        st->push_iterations = (int64_t)g->pinned[26];
         st->global_relabels = relabels;
         st->global_relabel_levels = relabel_levels;
         st->boundary_size = g->nB;
@@ -965,6 +968,7 @@ extern "C" mf_status mf_create_batch(int32_t count, const int64_t *dims, const i
     g->iflow.assign(count, 0);
     g->imaxpair.assign(count, 0);
     g->imaxct.assign(count, 0);
+    g->imaxin.assign(count, 0);
     g->iloaded.assign(count, 0);
     const Geo &G = g->G;
     std::vector<int> reginst(G.nreg, -1);
@@ -1034,24 +1038,27 @@ extern "C" mf_status mf_batch_set_caps(mf_grid *g, int32_t index, const int32_t 
     g->isum_ct[index] = (long long)g->pinned[1];
     g->imaxpair[index] = ((int *)(g->pinned + 2))[1];
     g->imaxct[index] = ((int *)(g->pinned + 2))[2];
+    g->imaxin[index] = ((int *)(g->pinned + 2))[3];
     HIP_TRY(mfd::launch_scatter_instance(cs, ct, nb, h, w, Ki, g->in_cs, g->in_ct, g->in_nbr, g->G.dx,
                                          g->n, g->iy0[index], g->ix0[index], s));
     HIP_TRY(hipStreamSynchronize(s));
     g->iloaded[index] = 1;
     bool all = true;
     long long scs = 0, sct = 0;
-    int mp = 0, mc = 0;
+    int mp = 0, mc = 0, mi = 0;
     for (int i = 0; i < g->batch; i++) {
         all = all && g->iloaded[i];
         scs += g->isum_cs[i];
         sct += g->isum_ct[i];
         mp = std::max(mp, g->imaxpair[i]);
         mc = std::max(mc, g->imaxct[i]);
+        mi = std::max(mi, g->imaxin[i]);
     }
     g->sum_cs = scs;
     g->sum_ct = sct;
     g->maxPair = mp;
     g->maxCt = mc;
+    g->maxIn = mi;
     g->has_caps = all;
     return MF_OK;
 }

@@ -3,14 +3,15 @@
 // Sec. 4.2 with the region relabel of Alg. 3; same method as k_discharge,
 // different execution).
 //
-// One 1024-thread workgroup owns a region; thread t owns row t = y + ty * z as
-// 32-bit masks in registers: residual arc present in each of the six
-// directions, residual t-link, excess present, visited, frontier, and the arcs
-// by which the search reached each vertex (its admissible arcs).  The integer
-// state (residuals, t-links, excess, boundary pushes) stays in HBM; LDS holds
-// the exact residual-arc masks of the region, the frontier rows that a search
-// level exchanges between neighbouring rows, and the per-row lists of vertices
-// whose excess changed in a push iteration, and the halo labels d(w).
+// One 1024-thread workgroup owns a region; each thread owns one row (y, z) of
+// 32 vertices as 32-bit masks in registers: residual arc present in each of the
+// six directions, visited, frontier, and the arcs by which the search reached
+// each vertex (its admissible arcs).  The integer state (residuals, t-links,
+// excess, boundary pushes) stays in HBM.  LDS holds the exact residual-arc and
+// t-link masks of the region, the admissible-arc masks of the current round, the
+// frontier rows a search level exchanges between neighbouring rows, the rows of
+// vertices whose excess changed in a push iteration, the halo labels d(w) and
+// the stage candidates of the border vertices, and per-wave work lists.
 //
 // * Search: the multi-level breadth-first search from the targets (stage 0
 //   from t, then one stage per distinct d(w) + 1 over residual boundary arcs)
@@ -21,7 +22,10 @@
 //   vertices of stage 0 and over boundary arcs for the first-level vertices of a
 //   stage k > 0 (to w with d(w) + 1 = k).  All vertices push in parallel, one
 //   iteration per barrier, until no push is possible; arcs only go down the
-//   (stage, level) order, so an arc is changed by one side only.
+//   (stage, level) order, so an arc is changed by one side only.  The excess
+//   vertices of a wave's rows are spread over its 64 lanes through a list in
+//   LDS, and for 32 x 32 rows each wave owns a diagonal of (y, z), so that a
+//   front of excess on a y or z plane is shared by all waves.
 // * Search and push alternate until no excess vertex reaches a target.  The
 //   last search is run once more to write the labels (Alg. 3).
 #include "mf_device.h"
@@ -36,8 +40,10 @@ namespace {
 constexpr int kRowsNT = 1024;
 constexpr int kRowsWaves = kRowsNT / 64;
 
+constexpr int kListCap = 256;  // work-list entries per wave and pass
+
 struct RowsLayout {
-    size_t resM, F, vis, recv, clr, halo, slot, total;  // offsets in 32-bit words
+    size_t resM, F, vis, recv, clr, adm, rtm, halo, slotC, slotL, list, total;  // offsets in 32-bit words
 };
 
 // Halo labels d(w) of the boundary arcs, one array per tile face: faces -+x
@@ -54,9 +60,13 @@ __host__ __device__ inline RowsLayout rows_layout(int R, int TY, int TZ, int nri
     L.vis = o; o += (size_t)R;       // visited rows (read by the border owners)
     L.recv = o; o += 2 * (size_t)R;  // vertices that received excess, by iteration parity
     L.clr = o; o += 2 * (size_t)R;   // vertices whose excess dropped to zero
+    L.adm = o; o += 7 * (size_t)R;   // admissible arcs of the round: six directions, then t
+    L.rtm = o; o += (size_t)R;       // residual t-link > 0
     L.halo = o;
     for (int k = 0; k < 6; k++) o += face_size(k, TY, TZ);
-    L.slot = o; o += (size_t)nring;  // border vertex: local index | live leaving directions << 16
+    L.slotC = o; o += (size_t)nring;            // stage candidate of each border vertex
+    L.slotL = o; o += ((size_t)nring + 1) / 2;  // its local index (16 bit)
+    L.list = o; o += (size_t)kRowsWaves * kListCap / 2;
     L.total = o;
     return L;
 }
@@ -101,13 +111,6 @@ __device__ __forceinline__ void store_labels(int *lab, size_t rowBase, unsigned 
     }
 }
 
-// Direction k of axis a that leaves the tile at a border vertex: exactly one of
-// the two directions of an axis leaves it (tiles are at least 2 wide on y and z
-// and 32 on x).
-__device__ __forceinline__ int axis_dir(unsigned keep, int a) {
-    return ((keep >> (2 * a)) & 1u) ? 2 * a : 2 * a + 1;
-}
-
 }  // namespace
 
 size_t discharge_rows_bytes(int ty, int tz, int nring) {
@@ -122,9 +125,45 @@ __device__ __forceinline__ int face_pos(int k, int l, int TY) {
     return k < 4 ? x + 32 * z : x + 32 * y;
 }
 
+// Row owned by thread tid.  For 32 x 32 rows, wave w holds the rows with
+// (y + z) mod 16 == w (two per z), so the rows of any y or z plane are spread
+// over all waves; other shapes use rows in thread order.
+__device__ __forceinline__ int row_of(int tid, int TY, int TZ) {
+    if (TY == 32 && TZ == 32) {
+        const int w = tid >> 6, lane = tid & 63;
+        const int z = lane >> 1;
+        const int y = ((w - z) & 15) + 16 * (lane & 1);
+        return y + 32 * z;
+    }
+    return tid;
+}
+
+// LDS written by one lane of a wave and read by another lane of the same wave.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(v, off, 64);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// Leaving direction of axis a at a border vertex with leaving mask mm: exactly
+// one of the two directions of an axis leaves it (tiles are at least 2 wide on
+// y and z and 32 on x).
+__device__ __forceinline__ int axis_dir_m(unsigned mm, int a) {
+    return ((mm >> (2 * a)) & 1u) ? 2 * a : 2 * a + 1;
+}
+
 __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
     extern __shared__ __align__(16) unsigned smem_rows[];
-    __shared__ int red[2][kRowsWaves];
+    __shared__ __align__(16) int red[2][kRowsWaves];
     __shared__ int s_r, s_active;
     __shared__ long long s_tr[4];  // trace: excess out, to sink, to boundary, label sum
     if (*A.actIn == 0ull) return;
@@ -136,15 +175,21 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
     unsigned *Vb = smem_rows + L.vis;
     unsigned *recvB = smem_rows + L.recv;
     unsigned *clrB = smem_rows + L.clr;
+    unsigned *admL = smem_rows + L.adm;
+    unsigned *rtmL = smem_rows + L.rtm;
     int *halo = (int *)(smem_rows + L.halo);
-    int *slot = (int *)(smem_rows + L.slot);
+    int *slotC = (int *)(smem_rows + L.slotC);
+    unsigned short *slotL = (unsigned short *)(smem_rows + L.slotL);
+    unsigned short *wlist = (unsigned short *)(smem_rows + L.list) + wid * kListCap;
     int faceOff[6];
     faceOff[0] = 0;
 #pragma unroll
     for (int k = 1; k < 6; k++) faceOff[k] = faceOff[k - 1] + face_size(k - 1, TY, TZ);
     const bool myrow = tid < R;
-    const int y = tid % TY, z = tid / TY;
+    const int row = myrow ? row_of(tid, TY, TZ) : 0;
+    const int y = row % TY, z = row / TY;
     const int dinf = A.dinf;
+    const int nring = A.nring;
     int rc = 0;
 
     // recv and clr are contiguous and return to zero after every use
@@ -178,15 +223,15 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
         if (tid < 4) s_tr[tid] = 0;
 
         // ---------------- row masks from HBM (coalesced loads + ballots) ----------------
-        // Wave w covers rows 64w .. 64w + 63: load i brings rows 64w + 2i and
+        // Wave w reads rows 64w .. 64w + 63: load i brings rows 64w + 2i and
         // 64w + 2i + 1 (one 32-bit half of the ballot each).  Residual masks go
-        // to resM, the t-link and excess masks to the two frontier buffers.
+        // to resM, the t-link mask to rtm, the excess mask to a frontier buffer.
         {
             const int row0 = wid * 64;
             if (row0 + 64 <= R) {
                 for (int q = 0; q < 8; q++) {
                     const int *plane = q < 6 ? A.res + (size_t)q * N : (q == 6 ? A.rt : A.ex);
-                    unsigned *dst = q < 6 ? resM + q * R : Fb + (q - 6) * R;
+                    unsigned *dst = q < 6 ? resM + q * R : (q == 6 ? rtmL : Fb);
                     const int *src = plane + base + (size_t)row0 * 32 + lane;
 #pragma unroll 8
                     for (int i = 0; i < 32; i++) {
@@ -200,63 +245,92 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
             }
         }
         // ---------------- border vertices: halo labels into LDS ----------------
-        // slot[i] for border vertex i (handled by thread i mod 1024): local index
-        // | (leaving directions with a finite halo label) << 16, or -1
-        for (int i = tid; i < A.nring; i += kRowsNT) {
+        for (int i = tid; i < nring; i += kRowsNT) {
             const int l = A.ringL[i];
             const unsigned mm = A.ringM[i];
             int lz, ly, lx;
             local_xyz(A.G, l, lz, ly, lx);
-            unsigned keep = 0u;
             for (int k = 0; k < 6; k++) {
                 if (!((mm >> k) & 1u)) continue;
                 const int w = cross_nbr(A.G, r, lz, ly, lx, k);
-                const int d = w >= 0 ? A.labOld[w] : kInf;
-                halo[faceOff[k] + face_pos(k, l, TY)] = d;
-                if (d < dinf) keep |= 1u << k;  // otherwise never a target
+                halo[faceOff[k] + face_pos(k, l, TY)] = w >= 0 ? A.labOld[w] : kInf;
             }
-            slot[i] = keep ? (l | (int)(keep << 16)) : -1;
+            slotL[i] = (unsigned short)l;
         }
         __syncthreads();
-        unsigned rtM = myrow ? Fb[tid] : 0u;
-        unsigned exM = myrow ? Fb[R + tid] : 0u;
+        unsigned exM = myrow ? Fb[row] : 0u;
 
         int iter = 0;
-        long long levels = 0, stages = 0;
+        long long levels = 0, stages = 0, pushIters = 0, t_search = 0, t_flood = 0, t_stage = 0, t_push = 0;
         bool writeMode = false;
-        const size_t rowBase = base + (size_t)tid * 32;
+        const size_t rowBase = base + (size_t)row * 32;
         for (;;) {
             // ---------------- multi-level search from the targets ----------------
+            const long long t0s = wall_clock64();
             unsigned rk[6];
 #pragma unroll
-            for (int k = 0; k < 6; k++) rk[k] = myrow ? resM[k * R + tid] : 0u;
+            for (int k = 0; k < 6; k++) rk[k] = myrow ? resM[k * R + row] : 0u;
+            const unsigned rtM = myrow ? rtmL[row] : 0u;
             unsigned vis = rtM, F = rtM, admT = rtM;
             unsigned adm[6];
 #pragma unroll
             for (int k = 0; k < 6; k++) adm[k] = 0u;
             u64 admB = 0ull;  // border slot j (vertex tid + 1024 j), bit 3j + axis: boundary arc to push over
+            // stage candidate of each border vertex of this thread: smallest
+            // d(w) + 1 over its residual boundary arcs (fixed during a search)
+#pragma unroll 4
+            for (int i = tid; i < nring; i += kRowsNT) {
+                const int l = slotL[i];
+                const unsigned mm = A.ringM[i];
+                const int rw = l >> 5;
+                const unsigned bit = 1u << (l & 31);
+                int c = kInf;
+                for (int k = 0; k < 6; k++) {
+                    if (!((mm >> k) & 1u) || !(resM[k * R + rw] & bit)) continue;
+                    const int d = halo[faceOff[k] + face_pos(k, l, TY)];
+                    if (d < dinf) c = min(c, d + 1);
+                }
+                slotC[i] = c;
+            }
             int p = 0;
             int stage = 0;
             if (writeMode && myrow) store_labels(A.labNew, rowBase, F, 0);
             for (;;) {
                 // flood inside the region: u with c_f(u, u + o_k) > 0 and u + o_k in the frontier
+                const long long t0f = wall_clock64();
                 for (;;) {
                     if (myrow) {
-                        Fb[p * R + tid] = F;
-                        Vb[tid] = vis;
+                        Fb[p * R + row] = F;
+                        Vb[row] = vis;
                     }
-                    if (!block_any(F != 0u, red, rc)) break;
-                    levels++;
+                    // one barrier; the OR of the waves' flags and the neighbour
+                    // rows are read in the same LDS round trip
+                    {
+                        const u64 b = __ballot(F != 0u);
+                        if (lane == 0) red[rc & 1][wid] = (b != 0ull) ? 1 : 0;
+                    }
+                    __syncthreads();
+                    const int4 *r4 = (const int4 *)red[rc & 1];
+                    rc++;
+                    const unsigned *Fp = Fb + p * R;
+                    unsigned fyp = 0u, fym = 0u, fzp = 0u, fzm = 0u;
                     if (myrow) {
-                        const unsigned *Fp = Fb + p * R;
-                        const unsigned fyp = (y + 1 < TY) ? Fp[tid + 1] : 0u;
-                        const unsigned fym = (y > 0) ? Fp[tid - 1] : 0u;
-                        const unsigned fzp = (z + 1 < TZ) ? Fp[tid + TY] : 0u;
-                        const unsigned fzm = (z > 0) ? Fp[tid - TY] : 0u;
+                        fyp = (y + 1 < TY) ? Fp[row + 1] : 0u;
+                        fym = (y > 0) ? Fp[row - 1] : 0u;
+                        fzp = (z + 1 < TZ) ? Fp[row + TY] : 0u;
+                        fzm = (z > 0) ? Fp[row - TY] : 0u;
+                    }
+                    const int4 a0 = r4[0], a1 = r4[1], a2 = r4[2], a3 = r4[3];
+                    const int any = (a0.x | a0.y | a0.z | a0.w) | (a1.x | a1.y | a1.z | a1.w) |
+                                    (a2.x | a2.y | a2.z | a2.w) | (a3.x | a3.y | a3.z | a3.w);
+                    if (!any) break;
+                    levels++;
+                    unsigned nw = 0u;
+                    if (F | fyp | fym | fzp | fzm) {
                         const unsigned t0 = rk[0] & (F >> 1), t1 = rk[1] & (F << 1);
                         const unsigned t2 = rk[2] & fyp, t3 = rk[3] & fym;
                         const unsigned t4 = rk[4] & fzp, t5 = rk[5] & fzm;
-                        const unsigned nw = ~vis & (t0 | t1 | t2 | t3 | t4 | t5);
+                        nw = ~vis & (t0 | t1 | t2 | t3 | t4 | t5);
                         adm[0] |= nw & t0;
                         adm[1] |= nw & t1;
                         adm[2] |= nw & t2;
@@ -264,60 +338,61 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
                         adm[4] |= nw & t4;
                         adm[5] |= nw & t5;
                         vis |= nw;
-                        F = nw;
                         if (writeMode && nw) store_labels(A.labNew, rowBase, nw, stage);
                     }
+                    F = nw;
                     p ^= 1;
                 }
-                // next stage: smallest d(w) + 1 over residual boundary arcs of unvisited border vertices
+                const long long t1f = wall_clock64();
+                t_flood += t1f - t0f;
+                // next stage: smallest candidate among unvisited border vertices
                 int cand = kInf;
-                for (int i = tid; i < A.nring; i += kRowsNT) {
-                    const int sv = slot[i];
-                    if (sv < 0) continue;
-                    const int l = sv & 0xffff;
-                    const unsigned keep = (unsigned)sv >> 16;
-                    const int row = l >> 5;
-                    const unsigned bit = 1u << (l & 31);
-                    if (Vb[row] & bit) continue;
-                    for (int a = 0; a < 3; a++) {
-                        if (!((keep >> (2 * a)) & 3u)) continue;
-                        const int k = axis_dir(keep, a);
-                        if (resM[k * R + row] & bit) cand = min(cand, halo[faceOff[k] + face_pos(k, l, TY)] + 1);
+                for (int i = tid; i < nring; i += kRowsNT) {
+                    const int c = slotC[i];
+                    if (c == kInf) continue;
+                    const int l = slotL[i];
+                    if (Vb[l >> 5] & (1u << (l & 31))) {
+                        slotC[i] = kInf;  // labelled: no longer a seed candidate in this search
+                        continue;
                     }
+                    cand = min(cand, c);
                 }
                 const int level = block_min(cand, red, rc);
-                if (level == kInf) break;
+                if (level == kInf) {
+                    t_stage += wall_clock64() - t1f;
+                    break;
+                }
                 stages++;
                 stage = level;
-                for (int j = 0, i = tid; i < A.nring; j++, i += kRowsNT) {
-                    const int sv = slot[i];
-                    if (sv < 0) continue;
-                    const int l = sv & 0xffff;
-                    const unsigned keep = (unsigned)sv >> 16;
-                    const int row = l >> 5;
+                for (int j = 0, i = tid; i < nring; j++, i += kRowsNT) {
+                    if (slotC[i] != level) continue;
+                    const int l = slotL[i];
+                    const unsigned mm = A.ringM[i];
+                    const int rw = l >> 5;
                     const unsigned bit = 1u << (l & 31);
-                    if (Vb[row] & bit) continue;
                     unsigned match = 0u;
-                    for (int a = 0; a < 3; a++) {
-                        if (!((keep >> (2 * a)) & 3u)) continue;
-                        const int k = axis_dir(keep, a);
-                        if ((resM[k * R + row] & bit) && halo[faceOff[k] + face_pos(k, l, TY)] + 1 == level)
-                            match |= 1u << a;
+                    for (int k = 0; k < 6; k++) {
+                        if (!((mm >> k) & 1u) || !(resM[k * R + rw] & bit)) continue;
+                        const int d = halo[faceOff[k] + face_pos(k, l, TY)];
+                        if (d < dinf && d + 1 == level) match |= 1u << (k >> 1);
                     }
-                    if (match) {
-                        admB |= (u64)match << (3 * j);
-                        atomicOr(&Fb[p * R + row], bit);  // this buffer is all zero: the flood just ended on it
-                    }
+                    // match != 0: the candidate came from one of these arcs
+                    admB |= (u64)match << (3 * j);
+                    slotC[i] = kInf;
+                    atomicOr(&Fb[p * R + rw], bit);  // this buffer is all zero: the flood just ended on it
                 }
                 __syncthreads();
                 if (myrow) {
-                    F = Fb[p * R + tid] & ~vis;
+                    F = Fb[p * R + row] & ~vis;
                     vis |= F;
                     if (writeMode && F) store_labels(A.labNew, rowBase, F, level);
                 }
+                t_stage += wall_clock64() - t1f;
             }
             // any excess vertex that reaches a target?
             const int found = block_any(myrow && (exM & vis) != 0u, red, rc);
+            const long long t1s = wall_clock64();
+            t_search += t1s - t0s;
             if (writeMode) {
                 if (myrow) store_labels(A.labNew, rowBase, ~vis, dinf);
                 break;
@@ -333,47 +408,72 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
             }
 
             // ---------------- push along admissible arcs until nothing moves ----------------
-            const unsigned canPush = admT | adm[0] | adm[1] | adm[2] | adm[3] | adm[4] | adm[5];
+            unsigned canPush = 0u;
+            if (myrow) {
+#pragma unroll
+                for (int k = 0; k < 6; k++) admL[k * R + row] = adm[k];
+                admL[6 * R + row] = admT;
+                canPush = admT | adm[0] | adm[1] | adm[2] | adm[3] | adm[4] | adm[5];
+            }
+            __syncthreads();
             int q = 0;
             for (;;) {
                 int pushed = 0;
-                if (myrow) {
-                    unsigned P = exM & canPush;
-                    while (P) {
-                        const int x = __ffs(P) - 1;
+                // the excess vertices of the wave's rows, spread over its lanes
+                const unsigned P = exM & canPush;
+                const int cnt = __popc(P);
+                const int incl = wave_incl_scan(cnt, lane);
+                const int total = __shfl(incl, 63, 64);
+                for (int w0 = 0; w0 < total; w0 += kListCap) {
+                    int idx = incl - cnt;
+                    if (cnt && idx < w0 + kListCap && idx + cnt > w0) {
+                        unsigned m = P;
+                        while (m) {
+                            const int x = __ffs(m) - 1;
+                            m &= m - 1;
+                            if (idx >= w0 && idx < w0 + kListCap) wlist[idx - w0] = (unsigned short)(row * 32 + x);
+                            idx++;
+                        }
+                    }
+                    wave_lds_sync();
+                    const int nItems = min(total - w0, kListCap);
+                    for (int it = lane; it < nItems; it += 64) {
+                        const int u = wlist[it];
+                        const int ur = u >> 5, x = u & 31;
                         const unsigned bit = 1u << x;
-                        P &= P - 1;
-                        const int u = tid * 32 + x;
-                        const size_t gu = base + u;
+                        unsigned a[7];
+#pragma unroll
+                        for (int k = 0; k < 7; k++) a[k] = admL[k * R + ur] & bit;
+                        int *const exU = A.ex + base + u;
                         int c[6];
 #pragma unroll
-                        for (int k = 0; k < 6; k++) c[k] = (adm[k] & bit) ? A.res[(size_t)k * N + gu] : 0;
-                        const int cT = (admT & bit) ? A.rt[gu] : 0;
-                        const int e = A.ex[gu];
+                        for (int k = 0; k < 6; k++) c[k] = a[k] ? A.res[(size_t)k * N + base + u] : 0;
+                        const int cT = a[6] ? A.rt[base + u] : 0;
+                        const int e = *exU;
                         if (e <= 0) {
-                            // a later receipt in this iteration sets the bit again
-                            exM &= ~bit;
+                            // a receipt in this iteration sets the bit again at the merge
+                            atomicOr(&clrB[q * R + ur], bit);
                             continue;
                         }
                         int rem = e;
-                        if (admT & bit) {
+                        if (a[6]) {
                             const int d = min(rem, cT);
                             if (d > 0) {
-                                A.rt[gu] = cT - d;
+                                A.rt[base + u] = cT - d;
                                 rem -= d;
                                 if (A.trace) atomicAdd((unsigned long long *)&s_tr[1], (u64)d);
                             }
                             if (cT == d) {
-                                admT &= ~bit;
-                                rtM &= ~bit;
+                                atomicAnd(&admL[6 * R + ur], ~bit);
+                                atomicAnd(&rtmL[ur], ~bit);
                             }
                         }
 #pragma unroll
                         for (int k = 0; k < 6; k++) {
-                            if (!(adm[k] & bit) || rem <= 0) continue;
+                            if (!a[k] || rem <= 0) continue;
                             const int d = min(rem, c[k]);
                             if (d > 0) {
-                                A.res[(size_t)k * N + gu] = c[k] - d;
+                                A.res[(size_t)k * N + base + u] = c[k] - d;
                                 const int v = u + ((k & 1) ? -1 : 1) * (k < 2 ? 1 : (k < 4 ? 32 : 32 * TY));
                                 const unsigned vbit = 1u << (v & 31);
                                 atomicAdd(&A.res[(size_t)(k ^ 1) * N + base + v], d);
@@ -383,37 +483,40 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
                                 rem -= d;
                             }
                             if (c[k] == d) {
-                                adm[k] &= ~bit;
-                                atomicAnd(&resM[k * R + tid], ~bit);
+                                atomicAnd(&admL[k * R + ur], ~bit);
+                                atomicAnd(&resM[k * R + ur], ~bit);
                             }
                         }
                         if (rem < e) {
-                            const int D = e - rem;
-                            if (atomicAdd(&A.ex[gu], -D) == D) atomicOr(&clrB[q * R + tid], bit);
+                            // drained what it saw: cleared, unless a receipt in this
+                            // iteration sets the bit again at the merge
+                            atomicAdd(exU, rem - e);
+                            if (rem == 0) atomicOr(&clrB[q * R + ur], bit);
                             pushed = 1;
                         }
                     }
+                    wave_lds_sync();
                 }
                 // first-level vertices of stages k > 0 push over boundary arcs
                 if (admB) {
                     for (int j = 0; (admB >> (3 * j)) != 0ull; j++) {
                         const unsigned ab = (unsigned)(admB >> (3 * j)) & 7u;
                         if (!ab) continue;
-                        const int sv = slot[tid + j * kRowsNT];
-                        const int l = sv & 0xffff;
-                        const unsigned keep = (unsigned)sv >> 16;
+                        const int i = tid + j * kRowsNT;
+                        const int l = slotL[i];
+                        const unsigned mm = A.ringM[i];
                         const size_t gu = base + l;
-                        const int row = l >> 5;
+                        const int rw = l >> 5;
                         const unsigned bit = 1u << (l & 31);
                         const int e = A.ex[gu];
                         if (e <= 0) {
-                            atomicOr(&clrB[q * R + row], bit);
+                            atomicOr(&clrB[q * R + rw], bit);
                             continue;
                         }
                         int rem = e;
                         for (int a = 0; a < 3; a++) {
                             if (!((ab >> a) & 1u) || rem <= 0) continue;
-                            const int k = axis_dir(keep, a);
+                            const int k = axis_dir_m(mm, a);
                             const int c = A.res[(size_t)k * N + gu];
                             const int d = min(rem, c);
                             if (d > 0) {
@@ -424,32 +527,37 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
                             }
                             if (c == d) {
                                 admB &= ~(1ull << (3 * j + a));
-                                atomicAnd(&resM[k * R + row], ~bit);
+                                atomicAnd(&resM[k * R + rw], ~bit);
                             }
                         }
                         if (rem < e) {
-                            const int D = e - rem;
-                            if (atomicAdd(&A.ex[gu], -D) == D) atomicOr(&clrB[q * R + row], bit);
+                            atomicAdd(&A.ex[gu], rem - e);
+                            if (rem == 0) atomicOr(&clrB[q * R + rw], bit);
                             pushed = 1;
                         }
                     }
                 }
                 const int any = block_any(pushed, red, rc);
+                pushIters++;
                 if (myrow) {
-                    const unsigned rv = recvB[q * R + tid], cl = clrB[q * R + tid];
-                    recvB[q * R + tid] = 0u;
-                    clrB[q * R + tid] = 0u;
+                    const unsigned rv = recvB[q * R + row], cl = clrB[q * R + row];
+                    recvB[q * R + row] = 0u;
+                    clrB[q * R + row] = 0u;
                     exM = (exM & ~cl) | rv;
+                    canPush = admL[6 * R + row];
+#pragma unroll
+                    for (int k = 0; k < 6; k++) canPush |= admL[k * R + row];
                 }
                 q ^= 1;
                 if (!any) break;
             }
+            t_push += wall_clock64() - t1s;
         }
         __syncthreads();
         if (A.trace) {
             long long ex_out = 0, lsum = 0;
             for (int l = tid; l < V; l += kRowsNT) ex_out += A.ex[base + l];
-            for (int i = tid; i < A.nring; i += kRowsNT) lsum += min(A.labNew[base + A.ringL[i]], 65535);
+            for (int i = tid; i < nring; i += kRowsNT) lsum += min(A.labNew[base + A.ringL[i]], 65535);
             atomicAdd((unsigned long long *)&s_tr[0], (u64)ex_out);
             atomicAdd((unsigned long long *)&s_tr[3], (u64)lsum);
         }
@@ -460,6 +568,11 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
             atomicAdd(&A.stats[2], (u64)(iter + 1));
             atomicAdd(&A.stats[3], (u64)levels);
             atomicAdd(&A.stats[4], (u64)stages);
+            atomicAdd(&A.stats[6], (u64)t_search);
+            atomicAdd(&A.stats[7], (u64)t_push);
+            atomicAdd(&A.stats[8], (u64)t_stage);
+            atomicAdd(&A.stats[9], (u64)t_flood);
+            atomicAdd(&A.stats[10], (u64)pushIters);
             if (A.trace) {
                 const unsigned long long idx = atomicAdd(&A.stats[5], 1ull);
                 if ((long long)idx < A.traceCap) {

@@ -65,9 +65,12 @@ __global__ void k_validate(Geo G, const int *cs, const int *ct, const int *nbr, 
     // largest pair sum and t-link, one atomic per wavefront
     maxpair = wave_max_i(maxpair);
     const int mct = wave_max_i(ct[v] > 0 ? ct[v] : 0);
+    // c(s,v) + sum_u c(u,v) bounds the excess of v in every preflow
+    const int min_ = wave_max_i((int)(inflow < 0x7fffffffLL ? inflow : 0x7fffffffLL));
     if ((threadIdx.x & 63) == 0) {
         if (maxpair > 0) atomicMax(&err[1], maxpair);
         if (mct > 0) atomicMax(&err[2], mct);
+        if (min_ > 0) atomicMax(&err[3], min_);
     }
 }
 
