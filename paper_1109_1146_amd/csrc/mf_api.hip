@@ -630,10 +630,14 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     const bool narrowOk = g->maxPair <= 32767 && g->maxCt <= 32767;
     size_t waveLds = 0, groupLds = 0;
     int waveNarrow = 0, groupNarrow = 0;
-    if (g->ndim == 2 && G.tz == 1 && G.tx <= 64 && G.ty <= 64) {
+    if (g->ndim == 2 && G.tz == 1 && G.tx <= 64 && G.ty <= 64 && g->nring <= 256) {
+        // 8-bit residuals and t-links with 16-bit excess, else 16-bit residuals, else 32-bit
+        const bool narrow8 = g->maxPair <= 255 && g->maxCt <= 255 && g->maxIn <= 32767;
+        size_t b8 = mfd::discharge_wave_bytes(G.V, G.K, g->nring, 2);
         size_t b16 = mfd::discharge_wave_bytes(G.V, G.K, g->nring, 1);
         size_t b32 = mfd::discharge_wave_bytes(G.V, G.K, g->nring, 0);
-        if (narrowOk && b16 <= ldsBudget) { waveLds = b16; waveNarrow = 1; }
+        if (narrow8 && b8 <= ldsBudget) { waveLds = b8; waveNarrow = 2; }
+        else if (narrowOk && b16 <= ldsBudget) { waveLds = b16; waveNarrow = 1; }
         else if (b32 <= ldsBudget) { waveLds = b32; }
     }
     if (G.V <= 32767) {
@@ -760,7 +764,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
             // the graph is rebuilt when their order changed)
             const long long key = ((long long)check_every << 8) | (o.gap ? 1 : 0) << 1 |
                                   (long long)(regionMode << 2) | (long long)(regionNarrow << 4) |
-                                  (long long)((g->lab[0] < g->lab[1]) ? 1 : 0) << 5;
+                                  (long long)((g->lab[0] < g->lab[1]) ? 1 : 0) << 6;
             if (!g->graph_exec || g->graph_key != key) {
                 if (g->graph_exec) { (void)hipGraphExecDestroy(g->graph_exec); g->graph_exec = nullptr; }
                 hipGraph_t graph = nullptr;

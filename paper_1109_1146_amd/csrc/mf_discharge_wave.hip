@@ -1,16 +1,20 @@
 // Single-wavefront region discharge for 2D tiles of at most 64 x 64 vertices
 // (Proc. ARD of Sec. 4.2 with the region relabel of Alg. 3; same method as
-// k_discharge_lds, different execution).
+// k_discharge, different execution).
 //
 // One wave64 owns a region.  Lane y holds row y of the tile as 64-bit masks:
-// residual arc present in each direction, residual t-link, visited, frontier,
-// and the 12 bit-planes of each vertex's search level.  One level of the
-// multi-level breadth-first search from the targets is then a handful of
-// shifts, cross-lane row exchanges and ORs in registers, with no LDS traffic
-// and no workgroup barrier.  The integer state (residuals as int16 K-vectors,
-// excess, t-links, halo labels, boundary pushes) stays in LDS; the push pass
-// walks the levels from the last to the first, each lane handling the
-// vertices of its row at that level.
+// residual arc present in each direction, residual t-link, excess present,
+// visited, frontier, and the arcs by which the search reached each vertex (its
+// admissible arcs, pointing one search level down).  A search level is a
+// handful of shifts, two cross-lane row exchanges and ORs in registers, with no
+// LDS traffic and no barrier.  The integer state (residuals, t-links, excess,
+// halo labels, boundary pushes) is staged in LDS, in 8-bit residuals and 16-bit
+// excess when the capacities allow it (two regions per compute unit), else in
+// 16- or 32-bit residuals.  The push phase moves excess along admissible arcs:
+// in every iteration each excess vertex pushes as much as it can, the excess
+// vertices are spread over the 64 lanes through a work list, and iterations
+// repeat until nothing moves.  Search and push alternate until no excess
+// vertex reaches a target; the last search is run again to write the labels.
 #include "mf_device.h"
 #include "mf_launch.h"
 
@@ -20,25 +24,27 @@ typedef unsigned long long u64;
 
 namespace {
 
-constexpr int kPlanes = 12;  // search steps < 4096 = 64 * 64
+constexpr int kWaveList = 256;  // work-list entries per pass
 
 __host__ __device__ inline size_t al16w(size_t x) { return (x + 15) & ~(size_t)15; }
 
 struct WaveLayout {
-    size_t res, ex, rt, S, stepLevel, ringIdx, halo, push, total;
+    size_t res, ex, rt, halo, push, resM, admM, rows, list, total;  // byte offsets
 };
 
-__host__ __device__ inline WaveLayout wave_layout(int V, int K, int nring, int rtBytes) {
+// rtBytes: residual and t-link width (1, 2, 4); exBytes: excess width (2, 4)
+__host__ __device__ inline WaveLayout wave_layout(int V, int K, int nring, int rtBytes, int exBytes) {
     WaveLayout L;
     size_t o = 0;
     L.res = o; o = al16w(o + (size_t)V * K * rtBytes);
-    L.ex = o; o = al16w(o + (size_t)V * 4);
+    L.ex = o; o = al16w(o + (size_t)(V + 1) * exBytes);
     L.rt = o; o = al16w(o + (size_t)V * rtBytes);
-    L.S = o; o = al16w(o + (size_t)V * 2);
-    L.stepLevel = o; o = al16w(o + (size_t)V * 4);
-    L.ringIdx = o; o = al16w(o + (size_t)V * 2);
     L.halo = o; o = al16w(o + (size_t)nring * K * 4);
     L.push = o; o = al16w(o + (size_t)nring * K * 4);
+    L.resM = o; o = al16w(o + (size_t)K * 64 * 8);        // residual arc inside the tile, per direction
+    L.admM = o; o = al16w(o + (size_t)(K + 1) * 64 * 8);  // admissible arcs of the round, then t
+    L.rows = o; o = al16w(o + (size_t)3 * 64 * 8);        // residual t-link, received, drained rows
+    L.list = o; o = al16w(o + (size_t)kWaveList * 2);
     L.total = o;
     return L;
 }
@@ -78,34 +84,77 @@ __device__ __forceinline__ int wave_min_int(int v) {
     return v;
 }
 
-}  // namespace
-
-size_t discharge_wave_bytes(int V, int K, int nring, int narrow) {
-    return wave_layout(V, K, nring, narrow ? 2 : 4).total;
+__device__ __forceinline__ int wave_scan_incl(int v, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(v, off, 64);
+        if (lane >= off) v += t;
+    }
+    return v;
 }
 
-template <int K, typename RT>
+// LDS written by one lane and read by another lane of the same wave.
+__device__ __forceinline__ void lane_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Excess in LDS: 32-bit, or 16-bit packed two to a word (every excess is at
+// most c(s,v) + sum_u c(u,v) <= 32767 then, so a half never carries or borrows).
+__device__ __forceinline__ int ex_get(const int *e, int i) { return e[i]; }
+__device__ __forceinline__ int ex_get(const short *e, int i) { return e[i]; }
+__device__ __forceinline__ void ex_add(int *e, int i, int d) { atomicAdd(&e[i], d); }
+__device__ __forceinline__ void ex_add(short *e, int i, int d) {
+    atomicAdd((unsigned *)(e + (i & ~1)), (unsigned)d << ((i & 1) * 16));
+}
+// subtract d and return the value before
+__device__ __forceinline__ int ex_sub(int *e, int i, int d) { return atomicSub(&e[i], d); }
+__device__ __forceinline__ int ex_sub(short *e, int i, int d) {
+    const int sh = (i & 1) * 16;
+    const unsigned old = atomicSub((unsigned *)(e + (i & ~1)), (unsigned)d << sh);
+    return (int)((old >> sh) & 0xffffu);
+}
+
+__device__ __forceinline__ void store_row_labels(int *lab, int rowBase, u64 bits, int val) {
+    while (bits) {
+        const int x = __ffsll(bits) - 1;
+        bits &= bits - 1;
+        lab[rowBase + x] = val;
+    }
+}
+
+}  // namespace
+
+size_t discharge_wave_bytes(int V, int K, int nring, int mode) {
+    // mode 2: 8-bit residuals, 16-bit excess; 1: 16-bit residuals; 0: 32-bit
+    return wave_layout(V, K, nring, mode == 2 ? 1 : (mode == 1 ? 2 : 4), mode == 2 ? 2 : 4).total;
+}
+
+template <int K, typename RT, typename ET>
 __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ long long s_tr[4];
     __shared__ u64 seedRows[64];
-    __shared__ u64 exRows[64];  // push pass: bit x of row y set iff vertex (x, y) holds excess
     if (*A.actIn == 0ull) return;
-    seedRows[threadIdx.x] = 0ull;
     const Geo &G = A.G;
     const int V = G.V, N = G.N, nring = A.nring;
     const int TX = G.tx, TY = G.ty;
     const int lane = threadIdx.x;
     const int y = lane;  // the row this lane owns (idle lanes: y >= TY)
-    const WaveLayout L = wave_layout(V, K, nring, (int)sizeof(RT));
+    seedRows[lane] = 0ull;
+    const WaveLayout L = wave_layout(V, K, nring, (int)sizeof(RT), (int)sizeof(ET));
     RT *resL = (RT *)(smem + L.res);
-    int *exL = (int *)(smem + L.ex);
+    ET *exL = (ET *)(smem + L.ex);
     RT *rtL = (RT *)(smem + L.rt);
-    unsigned short *S = (unsigned short *)(smem + L.S);
-    int *stepLevel = (int *)(smem + L.stepLevel);
-    short *ringIdx = (short *)(smem + L.ringIdx);
     int *halo = (int *)(smem + L.halo);
     int *pushL = (int *)(smem + L.push);
+    u64 *resM = (u64 *)(smem + L.resM);
+    u64 *admM = (u64 *)(smem + L.admM);
+    u64 *rtRows = (u64 *)(smem + L.rows);
+    u64 *recvRows = rtRows + 64;
+    u64 *clrRows = rtRows + 128;
+    unsigned short *wl = (unsigned short *)(smem + L.list);
     const int dinf = A.dinf;
     const u64 rowmask = TX == 64 ? ~0ull : ((1ull << TX) - 1);
     const bool myrow = y < TY;
@@ -124,6 +173,14 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
         if (dx[k] > 0) m &= rowmask >> dx[k];
         if (dx[k] < 0) m &= (rowmask << (-dx[k])) & rowmask;
         inside[k] = m;
+    }
+    // border vertices of this lane: i = lane + 64 j (at most 4 * 64 >= 4 * 63 for 64 x 64 tiles)
+    const int nslot = (nring + 63) / 64;
+    int slotL[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int i = lane + 64 * j;
+        slotL[j] = (j < nslot && i < nring) ? A.ringL[i] : -1;
     }
 
     for (;;) {
@@ -153,15 +210,13 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
         for (int l = lane; l < V; l += 64) {
 #pragma unroll
             for (int k = 0; k < K; k++) resL[l * K + k] = (RT)A.res[(size_t)k * N + base + l];
-            exL[l] = A.ex[base + l];
+            exL[l] = (ET)A.ex[base + l];
             rtL[l] = (RT)A.rt[base + l];
-            ringIdx[l] = -1;
         }
-        __syncthreads();
+        if (lane == 0) exL[V] = 0;  // pad of the last packed word
         for (int i = lane; i < nring; i += 64) {
             const int l = A.ringL[i];
             const unsigned m = A.ringM[i];
-            ringIdx[l] = (short)i;
             int lz, ly, lx;
             local_xyz(G, l, lz, ly, lx);
 #pragma unroll
@@ -176,223 +231,282 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
             }
         }
         __syncthreads();
-
-        int iter = 0;
-        long long bfs_steps = 0, classes = 0, t_search = 0, t_push = 0;
-        u64 VIS = 0, P[kPlanes];
-        int nsteps = 0;
-        for (;;) {
-            const long long t_round = wall_clock64();
-            // ---------------- row masks from the LDS state (coalesced, by ballot) ----------------
-            u64 R[K], RTm = 0, EXm = 0;
+        // ---------------- row masks from LDS (coalesced, by ballot), once per discharge ----------------
+        u64 EXm = 0;
+        {
+            u64 Rk[K], RTm = 0;
 #pragma unroll
-            for (int k = 0; k < K; k++) R[k] = 0;
+            for (int k = 0; k < K; k++) Rk[k] = 0;
             for (int row = 0; row < TY; row++) {
                 const int l = row * TX + lane;
                 const bool ok = lane < TX;
-                RT c[K];
-                if (ok) {
-#pragma unroll
-                    for (int k = 0; k < K; k++) c[k] = resL[l * K + k];
-                } else {
-#pragma unroll
-                    for (int k = 0; k < K; k++) c[k] = 0;
-                }
 #pragma unroll
                 for (int k = 0; k < K; k++) {
-                    const u64 b = __ballot(c[k] > 0);
-                    if (lane == row) R[k] = b;
+                    const u64 b = __ballot(ok && resL[l * K + k] > 0);
+                    if (lane == row) Rk[k] = b;
                 }
                 const u64 bt = __ballot(ok && rtL[l] > 0);
-                const u64 be = __ballot(ok && exL[l] > 0);
+                const u64 be = __ballot(ok && ex_get(exL, l) > 0);
                 if (lane == row) { RTm = bt; EXm = be; }
             }
 #pragma unroll
-            for (int k = 0; k < K; k++) R[k] &= inside[k];
+            for (int k = 0; k < K; k++) resM[k * 64 + lane] = Rk[k] & inside[k];
+            rtRows[lane] = myrow ? RTm : 0ull;
+            recvRows[lane] = 0ull;
+            clrRows[lane] = 0ull;
+        }
+        lane_sync();
+
+        int iter = 0;
+        long long levels = 0, stages = 0, pushIters = 0, t_search = 0, t_push = 0;
+        bool writeMode = false;
+        const int rowBase = base + y * TX;
+        for (;;) {
+            const long long t_round = wall_clock64();
             // ---------------- multi-level search from the targets ----------------
+            u64 R[K], adm[K];
 #pragma unroll
-            for (int j = 0; j < kPlanes; j++) P[j] = 0;
-            VIS = RTm;  // step 0: residual t-links
-            u64 F = RTm;
-            nsteps = 0;
-            int lvl = 0;
-            if (__ballot(F != 0ull)) {
-                if (lane == 0) stepLevel[0] = 0;
-                nsteps = 1;
+            for (int k = 0; k < K; k++) {
+                R[k] = resM[k * 64 + lane];
+                adm[k] = 0ull;
             }
-            for (;;) {
-                // flood: u unvisited with a residual arc (u, v) to a frontier vertex v
-                for (;;) {
-                    u64 nw = 0;
-                    const Rows3 FR = rows3(F, y, TY);
+            const u64 RT0 = rtRows[lane];
+            u64 VIS = RT0, F = RT0;
+            const u64 admT = RT0;
+            unsigned admB = 0u;  // border slot j: bit K j + k, boundary arc k to push over
+            // stage candidate of each border slot: smallest d(w) + 1 over its residual boundary arcs
+            int slotC[4];
 #pragma unroll
-                    for (int k = 0; k < K; k++) nw |= R[k] & shift_dx(FR.at(dy[k]), dx[k]);
+            for (int j = 0; j < 4; j++) {
+                int c = kInf;
+                const int l = slotL[j];
+                if (l >= 0) {
+                    const int i = lane + 64 * j;
+#pragma unroll
+                    for (int k = 0; k < K; k++) {
+                        const int h = halo[i * K + k];
+                        if (h < dinf && resL[l * K + k] > 0) c = min(c, h + 1);
+                    }
+                }
+                slotC[j] = c;
+            }
+            if (writeMode && myrow) store_row_labels(A.labNew, rowBase, F, 0);
+            int stage = 0;
+            for (;;) {
+                // flood: u unvisited with a residual arc (u, u + o_k) into the frontier
+                for (;;) {
+                    const Rows3 FR = rows3(F, y, TY);
+                    u64 t[K], nw = 0ull;
+#pragma unroll
+                    for (int k = 0; k < K; k++) {
+                        t[k] = R[k] & shift_dx(FR.at(dy[k]), dx[k]);
+                        nw |= t[k];
+                    }
                     nw &= ~VIS;
                     if (!__ballot(nw != 0ull)) break;
-                    const int st = nsteps;
-                    VIS |= nw;
+                    levels++;
 #pragma unroll
-                    for (int j = 0; j < kPlanes; j++)
-                        if ((st >> j) & 1) P[j] |= nw;
-                    if (lane == 0) stepLevel[st] = lvl;
-                    nsteps = st + 1;
+                    for (int k = 0; k < K; k++) adm[k] |= nw & t[k];
+                    VIS |= nw;
                     F = nw;
+                    if (writeMode && nw) store_row_labels(A.labNew, rowBase, nw, stage);
                 }
-                // next stage: smallest d(w) + 1 over residual boundary arcs of
-                // unvisited border vertices; border entries are spread over the lanes
+                // next stage: smallest candidate over unvisited border vertices
                 int best = kInf;
-                for (int i0 = 0; i0 < nring; i0 += 64) {
-                    const int i = i0 + lane;
-                    const int l = i < nring ? A.ringL[i] : 0;
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    if (j >= nslot) break;
+                    const int l = slotL[j] >= 0 ? slotL[j] : 0;
                     const int ry = l / TX, rx = l - ry * TX;
                     const u64 vrow = shfl64(VIS, ry);
-                    if (i < nring && !((vrow >> rx) & 1ull)) {
-#pragma unroll
-                        for (int k = 0; k < K; k++) {
-                            const int h = halo[i * K + k];
-                            if (h < dinf && resL[l * K + k] > 0) best = min(best, h + 1);
-                        }
+                    if (slotC[j] != kInf) {
+                        if ((vrow >> rx) & 1ull) slotC[j] = kInf;  // labelled in this search
+                        else best = min(best, slotC[j]);
                     }
                 }
                 const int level = wave_min_int(best);
                 if (level == kInf) break;
-                classes++;
-                for (int i0 = 0; i0 < nring; i0 += 64) {
-                    const int i = i0 + lane;
-                    const int l = i < nring ? A.ringL[i] : 0;
+                stages++;
+                stage = level;
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    if (j >= nslot) break;
+                    if (slotC[j] != level) continue;
+                    const int l = slotL[j];
+                    const int i = lane + 64 * j;
                     const int ry = l / TX, rx = l - ry * TX;
-                    const u64 vrow = shfl64(VIS, ry);
-                    if (i < nring && !((vrow >> rx) & 1ull)) {
-                        bool hit = false;
+                    unsigned match = 0u;
 #pragma unroll
-                        for (int k = 0; k < K; k++) {
-                            const int h = halo[i * K + k];
-                            if (h < dinf && h + 1 == level && resL[l * K + k] > 0) hit = true;
-                        }
-                        if (hit) atomicOr(&seedRows[ry], 1ull << rx);
+                    for (int k = 0; k < K; k++) {
+                        const int h = halo[i * K + k];
+                        if (h < dinf && h + 1 == level && resL[l * K + k] > 0) match |= 1u << k;
                     }
+                    admB |= match << (K * j);
+                    slotC[j] = kInf;
+                    atomicOr(&seedRows[ry], 1ull << rx);
                 }
-                __syncthreads();
-                u64 seed = 0;
-                if (myrow) {
-                    seed = seedRows[y];
-                    seedRows[y] = 0ull;
-                }
-                __syncthreads();
-                const int st = nsteps;
+                lane_sync();
+                u64 seed = seedRows[lane];
+                seedRows[lane] = 0ull;
+                lane_sync();
+                seed &= ~VIS;
                 VIS |= seed;
-#pragma unroll
-                for (int j = 0; j < kPlanes; j++)
-                    if ((st >> j) & 1) P[j] |= seed;
-                if (lane == 0) stepLevel[st] = level;
-                nsteps = st + 1;
-                lvl = level;
                 F = seed;
+                if (writeMode && seed) store_row_labels(A.labNew, rowBase, seed, level);
             }
-            bfs_steps += nsteps;
             const long long t_mid = wall_clock64();
             t_search += t_mid - t_round;
-            if (!__ballot((EXm & VIS) != 0ull)) break;
-            if (++iter > A.maxIter) {
-                if (lane == 0) atomicOr(A.err, 4);
+            const bool found = __ballot((EXm & VIS) != 0ull) != 0ull;
+            if (writeMode) {
+                if (myrow) store_row_labels(A.labNew, rowBase, ~VIS & rowmask, dinf);
                 break;
             }
-            exRows[lane] = EXm;
-            __syncthreads();  // stepLevel and exRows visible
-            // ---------------- push excess down the search levels ----------------
-            for (int s = nsteps - 1; s >= 0; s--) {
-                // members of level s and s - 1 in this row
-                u64 Ms = VIS, Mp = (s > 0) ? VIS : 0ull;
+            if (!found) {
+                writeMode = true;  // run the last search again, writing the region relabel
+                continue;
+            }
+            if (++iter > A.maxIter) {
+                if (lane == 0) atomicOr(A.err, 4);
+                writeMode = true;
+                continue;
+            }
+            // ---------------- push along admissible arcs until nothing moves ----------------
 #pragma unroll
-                for (int j = 0; j < kPlanes; j++) {
-                    Ms &= ((s >> j) & 1) ? P[j] : ~P[j];
-                    if (s > 0) Mp &= (((s - 1) >> j) & 1) ? P[j] : ~P[j];
-                }
-                u64 m = Ms & exRows[lane];
-                if (!__ballot(m != 0ull)) continue;  // no excess on this level: nothing moves
-                const int Lv = stepLevel[s];
-                const bool seedstep = (s == 0) || (stepLevel[s - 1] != Lv);
-                u64 Adm[K];
-                {
-                    const Rows3 MR = rows3(Mp, y, TY);  // all lanes take part in the exchange
+            for (int k = 0; k < K; k++) admM[k * 64 + lane] = adm[k];
+            admM[K * 64 + lane] = admT;
+            u64 canPush = admT;
 #pragma unroll
-                    for (int k = 0; k < K; k++) Adm[k] = seedstep ? 0ull : (R[k] & shift_dx(MR.at(dy[k]), dx[k]));
-                }
-                u64 drained = 0;
-                while (m) {
-                    const int x = __ffsll(m) - 1;
-                    m &= m - 1;
-                    const int u = y * TX + x;
-                    int e = exL[u];
-                    if (e <= 0) continue;
-                    if (seedstep) {
-                        if (Lv == 0) {
-                            const int t = rtL[u];
-                            if (t > 0) {
-                                const int d = min(e, t);
-                                rtL[u] = (RT)(t - d);
-                                e -= d;
-                                if (A.trace) atomicAdd((unsigned long long *)&s_tr[1], (u64)d);
-                            }
-                        } else {
-                            const int ri = ringIdx[u];
-#pragma unroll
-                            for (int k = 0; k < K; k++) {
-                                if (e <= 0 || ri < 0) break;
-                                const int h = halo[ri * K + k];
-                                if (h >= dinf || h + 1 != Lv) continue;
-                                const int c = resL[u * K + k];
-                                if (c <= 0) continue;
-                                const int d = min(e, c);
-                                resL[u * K + k] = (RT)(c - d);
-                                pushL[ri * K + k] += d;
-                                e -= d;
-                            }
-                        }
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < K; k++) {
-                            if (e <= 0 || !((Adm[k] >> x) & 1ull)) continue;
-                            const int v = u + dy[k] * TX + dx[k];
-                            const int c = resL[u * K + k];
-                            if (c <= 0) continue;
-                            const int d = min(e, c);
-                            resL[u * K + k] = (RT)(c - d);
-                            resL[v * K + (k ^ 1)] = (RT)(resL[v * K + (k ^ 1)] + d);
-                            atomicAdd(&exL[v], d);
-                            atomicOr(&exRows[y + dy[k]], 1ull << (x + dx[k]));
-                            e -= d;
+            for (int k = 0; k < K; k++) canPush |= adm[k];
+            lane_sync();
+            for (;;) {
+                int pushed = 0;
+                const u64 P = EXm & canPush;
+                const int cnt = __popcll(P);
+                const int incl = wave_scan_incl(cnt, lane);
+                const int total = __shfl(incl, 63, 64);
+                for (int w0 = 0; w0 < total; w0 += kWaveList) {
+                    int idx = incl - cnt;
+                    if (cnt && idx < w0 + kWaveList && idx + cnt > w0) {
+                        u64 m = P;
+                        while (m) {
+                            const int x = __ffsll(m) - 1;
+                            m &= m - 1;
+                            if (idx >= w0 && idx < w0 + kWaveList) wl[idx - w0] = (unsigned short)(y * TX + x);
+                            idx++;
                         }
                     }
-                    exL[u] = e;
-                    if (e == 0) drained |= 1ull << x;
+                    lane_sync();
+                    const int nItems = min(total - w0, kWaveList);
+                    for (int it = lane; it < nItems; it += 64) {
+                        const int u = wl[it];
+                        const int uy = u / TX, ux = u - uy * TX;
+                        const u64 bit = 1ull << ux;
+                        const int e = ex_get(exL, u);
+                        if (e <= 0) {
+                            // a receipt in this iteration sets the bit again at the merge
+                            atomicOr(&clrRows[uy], bit);
+                            continue;
+                        }
+                        int rem = e;
+                        if (admM[K * 64 + uy] & bit) {
+                            const int c = rtL[u];
+                            const int d = min(rem, c);
+                            if (d > 0) {
+                                rtL[u] = (RT)(c - d);
+                                rem -= d;
+                                if (A.trace) atomicAdd((unsigned long long *)&s_tr[1], (u64)d);
+                            }
+                            if (c == d) {
+                                atomicAnd(&admM[K * 64 + uy], ~bit);
+                                atomicAnd(&rtRows[uy], ~bit);
+                            }
+                        }
+#pragma unroll
+                        for (int k = 0; k < K; k++) {
+                            if (rem <= 0) break;
+                            if (!(admM[k * 64 + uy] & bit)) continue;
+                            const int c = resL[u * K + k];
+                            const int d = min(rem, c);
+                            if (d > 0) {
+                                const int v = u + dy[k] * TX + dx[k];
+                                const u64 vbit = 1ull << (ux + dx[k]);
+                                resL[u * K + k] = (RT)(c - d);
+                                resL[v * K + (k ^ 1)] = (RT)(resL[v * K + (k ^ 1)] + d);
+                                ex_add(exL, v, d);
+                                atomicOr(&resM[(k ^ 1) * 64 + uy + dy[k]], vbit);
+                                atomicOr(&recvRows[uy + dy[k]], vbit);
+                                rem -= d;
+                            }
+                            if (c == d) {
+                                atomicAnd(&admM[k * 64 + uy], ~bit);
+                                atomicAnd(&resM[k * 64 + uy], ~bit);
+                            }
+                        }
+                        if (rem < e) {
+                            const int D = e - rem;
+                            if (ex_sub(exL, u, D) == D) atomicOr(&clrRows[uy], bit);
+                            pushed = 1;
+                        }
+                    }
+                    lane_sync();
                 }
-                if (drained) atomicAnd(&exRows[y], ~drained);
-                __syncthreads();
+                // first-level vertices of stages k > 0 push over boundary arcs
+                if (admB) {
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const unsigned ab = (admB >> (K * j)) & ((1u << K) - 1u);
+                        if (!ab) continue;
+                        const int l = slotL[j];
+                        const int i = lane + 64 * j;
+                        const int ly = l / TX, lx = l - ly * TX;
+                        const u64 bit = 1ull << lx;
+                        const int e = ex_get(exL, l);
+                        if (e <= 0) {
+                            atomicOr(&clrRows[ly], bit);
+                            continue;
+                        }
+                        int rem = e;
+#pragma unroll
+                        for (int k = 0; k < K; k++) {
+                            if (!((ab >> k) & 1u) || rem <= 0) continue;
+                            const int c = resL[l * K + k];
+                            const int d = min(rem, c);
+                            if (d > 0) {
+                                resL[l * K + k] = (RT)(c - d);
+                                pushL[i * K + k] += d;
+                                rem -= d;
+                                if (A.trace) atomicAdd((unsigned long long *)&s_tr[2], (u64)d);
+                            }
+                            if (c == d) admB &= ~(1u << (K * j + k));
+                        }
+                        if (rem < e) {
+                            const int D = e - rem;
+                            if (ex_sub(exL, l, D) == D) atomicOr(&clrRows[ly], bit);
+                            pushed = 1;
+                        }
+                    }
+                }
+                lane_sync();
+                const bool any = __ballot(pushed != 0) != 0ull;
+                pushIters++;
+                EXm = (EXm & ~clrRows[lane]) | recvRows[lane];
+                clrRows[lane] = 0ull;
+                recvRows[lane] = 0ull;
+                canPush = admM[K * 64 + lane];
+#pragma unroll
+                for (int k = 0; k < K; k++) canPush |= admM[k * 64 + lane];
+                lane_sync();
+                if (!any) break;
             }
             t_push += wall_clock64() - t_mid;
-        }
-        // ---------------- levels of the last search -> labels ----------------
-        // store each vertex's step (or 0xffff when unreached) in S, row by row
-        for (int row = 0; row < TY; row++) {
-            const u64 vis = shfl64(VIS, row);
-            int stp = 0;
-#pragma unroll
-            for (int j = 0; j < kPlanes; j++) {
-                const u64 pj = shfl64(P[j], row);
-                if (lane < TX && ((pj >> lane) & 1ull)) stp |= 1 << j;
-            }
-            if (lane < TX) S[row * TX + lane] = ((vis >> lane) & 1ull) ? (unsigned short)stp : 0xffffu;
         }
         __syncthreads();
         // ---------------- write the region back ----------------
         for (int l = lane; l < V; l += 64) {
 #pragma unroll
             for (int k = 0; k < K; k++) A.res[(size_t)k * N + base + l] = resL[l * K + k];
-            A.ex[base + l] = exL[l];
+            A.ex[base + l] = ex_get(exL, l);
             A.rt[base + l] = rtL[l];
-            const int s = S[l];
-            A.labNew[base + l] = (s == 0xffff) ? dinf : min(stepLevel[s], dinf);
         }
         for (int i = lane; i < nring; i += 64) {
             const int l = A.ringL[i];
@@ -403,16 +517,10 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
             }
         }
         if (A.trace) {
-            long long ex_out = 0, to_b = 0, lsum = 0;
-            for (int l = lane; l < V; l += 64) ex_out += exL[l];
-            for (int i = lane; i < nring; i += 64) {
-#pragma unroll
-                for (int k = 0; k < K; k++) to_b += pushL[i * K + k];
-                const int s = S[A.ringL[i]];
-                lsum += (s == 0xffff) ? 65535 : min(stepLevel[s], 65535);
-            }
+            long long ex_out = 0, lsum = 0;
+            for (int l = lane; l < V; l += 64) ex_out += ex_get(exL, l);
+            for (int i = lane; i < nring; i += 64) lsum += min(A.labNew[base + A.ringL[i]], 65535);
             atomicAdd((unsigned long long *)&s_tr[0], (u64)ex_out);
-            atomicAdd((unsigned long long *)&s_tr[2], (u64)to_b);
             atomicAdd((unsigned long long *)&s_tr[3], (u64)lsum);
         }
         __syncthreads();
@@ -420,22 +528,22 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
             atomicAdd(&A.stats[0], 1ull);
             atomicAdd(&A.stats[1], (u64)A.rvcount[r]);
             atomicAdd(&A.stats[2], (u64)(iter + 1));
-            atomicAdd(&A.stats[3], (u64)bfs_steps);
-            atomicAdd(&A.stats[4], (u64)classes);
+            atomicAdd(&A.stats[3], (u64)levels);
+            atomicAdd(&A.stats[4], (u64)stages);
             atomicAdd(&A.stats[6], (u64)t_search);
             atomicAdd(&A.stats[7], (u64)t_push);
+            atomicAdd(&A.stats[10], (u64)pushIters);
             if (A.trace) {
                 unsigned long long idx = atomicAdd(&A.stats[5], 1ull);
                 if ((long long)idx < A.traceCap) {
                     int *rec = A.trace + idx * 10;
-                    const long long ex_in = s_tr[0] + s_tr[1] + s_tr[2];
                     rec[0] = A.sweep;
                     rec[1] = r;
                     rec[2] = iter + 1;
-                    rec[3] = (int)min(bfs_steps, 0x7fffffffLL);
-                    rec[4] = (int)min(classes, 0x7fffffffLL);
+                    rec[3] = (int)min(levels, 0x7fffffffLL);
+                    rec[4] = (int)min(stages, 0x7fffffffLL);
                     rec[5] = (int)min(wall_clock64() - t_start, 0x7fffffffLL);
-                    rec[6] = (int)min(ex_in, 0x7fffffffLL);
+                    rec[6] = (int)min(s_tr[0] + s_tr[1] + s_tr[2], 0x7fffffffLL);
                     rec[7] = (int)min(s_tr[1], 0x7fffffffLL);
                     rec[8] = (int)min(s_tr[2], 0x7fffffffLL);
                     rec[9] = (int)min(s_tr[3], 0x7fffffffLL);
@@ -446,34 +554,38 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
     }
 }
 
+#define MF_WAVE_KERNELS(X) \
+    X(4, unsigned char, short) X(8, unsigned char, short) X(4, short, int) X(8, short, int) \
+    X(4, int, int) X(8, int, int)
+
 void set_wave_attributes() {
-    (void)hipFuncSetAttribute((const void *)k_discharge_wave<4, short>,
+#define MF_SET(K, RT, ET)                                                                        \
+    (void)hipFuncSetAttribute((const void *)k_discharge_wave<K, RT, ET>,                         \
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute((const void *)k_discharge_wave<8, short>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute((const void *)k_discharge_wave<4, int>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute((const void *)k_discharge_wave<8, int>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    MF_WAVE_KERNELS(MF_SET)
+#undef MF_SET
     (void)hipGetLastError();
 }
 
-template <int K, typename RT>
+template <int K, typename RT, typename ET>
 static hipError_t launch_wave_t(const DischargeArgs &A, int blocks, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((k_discharge_wave<K, RT>), dim3(blocks), dim3(64), lds, s, A);
+    hipLaunchKernelGGL((k_discharge_wave<K, RT, ET>), dim3(blocks), dim3(64), lds, s, A);
     return hipGetLastError();
 }
 
-hipError_t launch_discharge_wave(const DischargeArgs &A, int blocks, size_t lds, int narrow,
+hipError_t launch_discharge_wave(const DischargeArgs &A, int blocks, size_t lds, int mode,
                                  hipStream_t s) {
     const int K = A.G.K;
-    if (A.G.tz != 1 || A.G.tx > 64 || A.G.ty > 64) return hipErrorInvalidValue;
-    if (narrow) {
-        if (K == 4) return launch_wave_t<4, short>(A, blocks, lds, s);
-        if (K == 8) return launch_wave_t<8, short>(A, blocks, lds, s);
+    if (A.G.tz != 1 || A.G.tx > 64 || A.G.ty > 64 || A.nring > 4 * 64) return hipErrorInvalidValue;
+    if (mode == 2) {
+        if (K == 4) return launch_wave_t<4, unsigned char, short>(A, blocks, lds, s);
+        if (K == 8) return launch_wave_t<8, unsigned char, short>(A, blocks, lds, s);
+    } else if (mode == 1) {
+        if (K == 4) return launch_wave_t<4, short, int>(A, blocks, lds, s);
+        if (K == 8) return launch_wave_t<8, short, int>(A, blocks, lds, s);
     } else {
-        if (K == 4) return launch_wave_t<4, int>(A, blocks, lds, s);
-        if (K == 8) return launch_wave_t<8, int>(A, blocks, lds, s);
+        if (K == 4) return launch_wave_t<4, int, int>(A, blocks, lds, s);
+        if (K == 8) return launch_wave_t<8, int, int>(A, blocks, lds, s);
     }
     return hipErrorInvalidValue;
 }

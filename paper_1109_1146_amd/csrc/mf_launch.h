@@ -152,9 +152,10 @@ hipError_t launch_discharge(const DischargeArgs &A, int blocks, int threads, siz
 hipError_t launch_discharge_lds(const DischargeArgs &A, int blocks, size_t lds, int narrow,
                                 hipStream_t s);
 size_t discharge_lds_bytes(int V, int K, int nring, int narrow);
-hipError_t launch_discharge_wave(const DischargeArgs &A, int blocks, size_t lds, int narrow,
+// mode 2: 8-bit residuals and t-links, 16-bit excess; 1: 16-bit residuals; 0: 32-bit
+hipError_t launch_discharge_wave(const DischargeArgs &A, int blocks, size_t lds, int mode,
                                  hipStream_t s);
-size_t discharge_wave_bytes(int V, int K, int nring, int narrow);
+size_t discharge_wave_bytes(int V, int K, int nring, int mode);
 // Row-bitmask workgroup discharge: 3D 6-connected regions with tx == 32,
 // ty, tz >= 2, ty * tz a multiple of 64 and at most 1024, and at most 21 * 1024
 // border vertices (rows_slots() == 0: not applicable).
