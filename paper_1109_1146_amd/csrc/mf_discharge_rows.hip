@@ -419,83 +419,92 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
             int q = 0;
             for (;;) {
                 int pushed = 0;
-                // the excess vertices of the wave's rows, spread over its lanes
+                // push from excess vertex u (local index, row ur) along its admissible arcs
+                auto push_from = [&](int u, int ur) {
+                    const int x = u & 31;
+                    const unsigned bit = 1u << x;
+                    unsigned a[7];
+#pragma unroll
+                    for (int k = 0; k < 7; k++) a[k] = admL[k * R + ur] & bit;
+                    int *const exU = A.ex + base + u;
+                    int c[6];
+#pragma unroll
+                    for (int k = 0; k < 6; k++) c[k] = a[k] ? A.res[(size_t)k * N + base + u] : 0;
+                    const int cT = a[6] ? A.rt[base + u] : 0;
+                    const int e = *exU;
+                    if (e <= 0) {
+                        // a receipt in this iteration sets the bit again at the merge
+                        atomicOr(&clrB[q * R + ur], bit);
+                        return;
+                    }
+                    int rem = e;
+                    if (a[6]) {
+                        const int d = min(rem, cT);
+                        if (d > 0) {
+                            A.rt[base + u] = cT - d;
+                            rem -= d;
+                            if (A.trace) atomicAdd((unsigned long long *)&s_tr[1], (u64)d);
+                        }
+                        if (cT == d) {
+                            atomicAnd(&admL[6 * R + ur], ~bit);
+                            atomicAnd(&rtmL[ur], ~bit);
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < 6; k++) {
+                        if (!a[k] || rem <= 0) continue;
+                        const int d = min(rem, c[k]);
+                        if (d > 0) {
+                            A.res[(size_t)k * N + base + u] = c[k] - d;
+                            const int v = u + ((k & 1) ? -1 : 1) * (k < 2 ? 1 : (k < 4 ? 32 : 32 * TY));
+                            const unsigned vbit = 1u << (v & 31);
+                            atomicAdd(&A.res[(size_t)(k ^ 1) * N + base + v], d);
+                            atomicAdd(&A.ex[base + v], d);
+                            atomicOr(&resM[(k ^ 1) * R + (v >> 5)], vbit);
+                            atomicOr(&recvB[q * R + (v >> 5)], vbit);
+                            rem -= d;
+                        }
+                        if (c[k] == d) {
+                            atomicAnd(&admL[k * R + ur], ~bit);
+                            atomicAnd(&resM[k * R + ur], ~bit);
+                        }
+                    }
+                    if (rem < e) {
+                        // drained what it saw: cleared, unless a receipt in this
+                        // iteration sets the bit again at the merge
+                        atomicAdd(exU, rem - e);
+                        if (rem == 0) atomicOr(&clrB[q * R + ur], bit);
+                        pushed = 1;
+                    }
+                };
                 const unsigned P = exM & canPush;
                 const int cnt = __popc(P);
-                const int incl = wave_incl_scan(cnt, lane);
-                const int total = __shfl(incl, 63, 64);
-                for (int w0 = 0; w0 < total; w0 += kListCap) {
-                    int idx = incl - cnt;
-                    if (cnt && idx < w0 + kListCap && idx + cnt > w0) {
-                        unsigned m = P;
-                        while (m) {
-                            const int x = __ffs(m) - 1;
-                            m &= m - 1;
-                            if (idx >= w0 && idx < w0 + kListCap) wlist[idx - w0] = (unsigned short)(row * 32 + x);
-                            idx++;
+                if (__ballot(cnt > 1) == 0ull) {
+                    // light iteration: each thread pushes from its own row
+                    if (P) push_from(row * 32 + __ffs(P) - 1, row);
+                } else {
+                    // the excess vertices of the wave's rows, spread over its lanes
+                    const int incl = wave_incl_scan(cnt, lane);
+                    const int total = __builtin_amdgcn_readlane(incl, 63);
+                    for (int w0 = 0; w0 < total; w0 += kListCap) {
+                        int idx = incl - cnt;
+                        if (cnt && idx < w0 + kListCap && idx + cnt > w0) {
+                            unsigned m = P;
+                            while (m) {
+                                const int x = __ffs(m) - 1;
+                                m &= m - 1;
+                                if (idx >= w0 && idx < w0 + kListCap) wlist[idx - w0] = (unsigned short)(row * 32 + x);
+                                idx++;
+                            }
                         }
+                        wave_lds_sync();
+                        const int nItems = min(total - w0, kListCap);
+                        for (int it = lane; it < nItems; it += 64) {
+                            const int u = wlist[it];
+                            push_from(u, u >> 5);
+                        }
+                        wave_lds_sync();
                     }
-                    wave_lds_sync();
-                    const int nItems = min(total - w0, kListCap);
-                    for (int it = lane; it < nItems; it += 64) {
-                        const int u = wlist[it];
-                        const int ur = u >> 5, x = u & 31;
-                        const unsigned bit = 1u << x;
-                        unsigned a[7];
-#pragma unroll
-                        for (int k = 0; k < 7; k++) a[k] = admL[k * R + ur] & bit;
-                        int *const exU = A.ex + base + u;
-                        int c[6];
-#pragma unroll
-                        for (int k = 0; k < 6; k++) c[k] = a[k] ? A.res[(size_t)k * N + base + u] : 0;
-                        const int cT = a[6] ? A.rt[base + u] : 0;
-                        const int e = *exU;
-                        if (e <= 0) {
-                            // a receipt in this iteration sets the bit again at the merge
-                            atomicOr(&clrB[q * R + ur], bit);
-                            continue;
-                        }
-                        int rem = e;
-                        if (a[6]) {
-                            const int d = min(rem, cT);
-                            if (d > 0) {
-                                A.rt[base + u] = cT - d;
-                                rem -= d;
-                                if (A.trace) atomicAdd((unsigned long long *)&s_tr[1], (u64)d);
-                            }
-                            if (cT == d) {
-                                atomicAnd(&admL[6 * R + ur], ~bit);
-                                atomicAnd(&rtmL[ur], ~bit);
-                            }
-                        }
-#pragma unroll
-                        for (int k = 0; k < 6; k++) {
-                            if (!a[k] || rem <= 0) continue;
-                            const int d = min(rem, c[k]);
-                            if (d > 0) {
-                                A.res[(size_t)k * N + base + u] = c[k] - d;
-                                const int v = u + ((k & 1) ? -1 : 1) * (k < 2 ? 1 : (k < 4 ? 32 : 32 * TY));
-                                const unsigned vbit = 1u << (v & 31);
-                                atomicAdd(&A.res[(size_t)(k ^ 1) * N + base + v], d);
-                                atomicAdd(&A.ex[base + v], d);
-                                atomicOr(&resM[(k ^ 1) * R + (v >> 5)], vbit);
-                                atomicOr(&recvB[q * R + (v >> 5)], vbit);
-                                rem -= d;
-                            }
-                            if (c[k] == d) {
-                                atomicAnd(&admL[k * R + ur], ~bit);
-                                atomicAnd(&resM[k * R + ur], ~bit);
-                            }
-                        }
-                        if (rem < e) {
-                            // drained what it saw: cleared, unless a receipt in this
-                            // iteration sets the bit again at the merge
-                            atomicAdd(exU, rem - e);
-                            if (rem == 0) atomicOr(&clrB[q * R + ur], bit);
-                            pushed = 1;
-                        }
-                    }
-                    wave_lds_sync();
                 }
                 // first-level vertices of stages k > 0 push over boundary arcs
                 if (admB) {

@@ -380,75 +380,94 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
             lane_sync();
             for (;;) {
                 int pushed = 0;
+                // push from excess vertex u (row uy, column ux) along its admissible arcs
+                auto push_from = [&](int u, int uy, int ux) {
+                    const u64 bit = 1ull << ux;
+                    u64 am[K + 1];
+#pragma unroll
+                    for (int k = 0; k <= K; k++) am[k] = admM[k * 64 + uy];
+                    const int e = ex_get(exL, u);
+                    if (e <= 0) {
+                        // a receipt in this iteration sets the bit again at the merge
+                        atomicOr(&clrRows[uy], bit);
+                        return;
+                    }
+                    int rem = e;
+                    if (am[K] & bit) {
+                        const int c = rtL[u];
+                        const int d = min(rem, c);
+                        if (d > 0) {
+                            rtL[u] = (RT)(c - d);
+                            rem -= d;
+                            if (A.trace) atomicAdd((unsigned long long *)&s_tr[1], (u64)d);
+                        }
+                        if (c == d) {
+                            atomicAnd(&admM[K * 64 + uy], ~bit);
+                            atomicAnd(&rtRows[uy], ~bit);
+                        }
+                    }
+                    int c[K];
+#pragma unroll
+                    for (int k = 0; k < K; k++) c[k] = (am[k] & bit) ? (int)resL[u * K + k] : 0;
+#pragma unroll
+                    for (int k = 0; k < K; k++) {
+                        if (rem <= 0 || !(am[k] & bit)) continue;
+                        const int d = min(rem, c[k]);
+                        if (d > 0) {
+                            const int v = u + dy[k] * TX + dx[k];
+                            const u64 vbit = 1ull << (ux + dx[k]);
+                            resL[u * K + k] = (RT)(c[k] - d);
+                            resL[v * K + (k ^ 1)] = (RT)(resL[v * K + (k ^ 1)] + d);
+                            ex_add(exL, v, d);
+                            atomicOr(&resM[(k ^ 1) * 64 + uy + dy[k]], vbit);
+                            atomicOr(&recvRows[uy + dy[k]], vbit);
+                            rem -= d;
+                        }
+                        if (c[k] == d) {
+                            atomicAnd(&admM[k * 64 + uy], ~bit);
+                            atomicAnd(&resM[k * 64 + uy], ~bit);
+                        }
+                    }
+                    if (rem < e) {
+                        const int D = e - rem;
+                        if (ex_sub(exL, u, D) == D) atomicOr(&clrRows[uy], bit);
+                        pushed = 1;
+                    }
+                };
                 const u64 P = EXm & canPush;
                 const int cnt = __popcll(P);
-                const int incl = wave_scan_incl(cnt, lane);
-                const int total = __shfl(incl, 63, 64);
-                for (int w0 = 0; w0 < total; w0 += kWaveList) {
-                    int idx = incl - cnt;
-                    if (cnt && idx < w0 + kWaveList && idx + cnt > w0) {
-                        u64 m = P;
-                        while (m) {
-                            const int x = __ffsll(m) - 1;
-                            m &= m - 1;
-                            if (idx >= w0 && idx < w0 + kWaveList) wl[idx - w0] = (unsigned short)(y * TX + x);
-                            idx++;
-                        }
+                if (__ballot(cnt > 2) == 0ull) {
+                    // light iteration: every lane pushes from its own row
+                    u64 m = P;
+                    while (m) {
+                        const int x = __ffsll(m) - 1;
+                        m &= m - 1;
+                        push_from(y * TX + x, y, x);
                     }
-                    lane_sync();
-                    const int nItems = min(total - w0, kWaveList);
-                    for (int it = lane; it < nItems; it += 64) {
-                        const int u = wl[it];
-                        const int uy = u / TX, ux = u - uy * TX;
-                        const u64 bit = 1ull << ux;
-                        const int e = ex_get(exL, u);
-                        if (e <= 0) {
-                            // a receipt in this iteration sets the bit again at the merge
-                            atomicOr(&clrRows[uy], bit);
-                            continue;
-                        }
-                        int rem = e;
-                        if (admM[K * 64 + uy] & bit) {
-                            const int c = rtL[u];
-                            const int d = min(rem, c);
-                            if (d > 0) {
-                                rtL[u] = (RT)(c - d);
-                                rem -= d;
-                                if (A.trace) atomicAdd((unsigned long long *)&s_tr[1], (u64)d);
-                            }
-                            if (c == d) {
-                                atomicAnd(&admM[K * 64 + uy], ~bit);
-                                atomicAnd(&rtRows[uy], ~bit);
+                } else {
+                    // the excess vertices of all rows, spread over the lanes by a work list
+                    const int incl = wave_scan_incl(cnt, lane);
+                    const int total = __builtin_amdgcn_readlane(incl, 63);
+                    for (int w0 = 0; w0 < total; w0 += kWaveList) {
+                        int idx = incl - cnt;
+                        if (cnt && idx < w0 + kWaveList && idx + cnt > w0) {
+                            u64 m = P;
+                            while (m) {
+                                const int x = __ffsll(m) - 1;
+                                m &= m - 1;
+                                if (idx >= w0 && idx < w0 + kWaveList) wl[idx - w0] = (unsigned short)(y * TX + x);
+                                idx++;
                             }
                         }
-#pragma unroll
-                        for (int k = 0; k < K; k++) {
-                            if (rem <= 0) break;
-                            if (!(admM[k * 64 + uy] & bit)) continue;
-                            const int c = resL[u * K + k];
-                            const int d = min(rem, c);
-                            if (d > 0) {
-                                const int v = u + dy[k] * TX + dx[k];
-                                const u64 vbit = 1ull << (ux + dx[k]);
-                                resL[u * K + k] = (RT)(c - d);
-                                resL[v * K + (k ^ 1)] = (RT)(resL[v * K + (k ^ 1)] + d);
-                                ex_add(exL, v, d);
-                                atomicOr(&resM[(k ^ 1) * 64 + uy + dy[k]], vbit);
-                                atomicOr(&recvRows[uy + dy[k]], vbit);
-                                rem -= d;
-                            }
-                            if (c == d) {
-                                atomicAnd(&admM[k * 64 + uy], ~bit);
-                                atomicAnd(&resM[k * 64 + uy], ~bit);
-                            }
+                        lane_sync();
+                        const int nItems = min(total - w0, kWaveList);
+                        for (int it = lane; it < nItems; it += 64) {
+                            const int u = wl[it];
+                            const int uy = u / TX;
+                            push_from(u, uy, u - uy * TX);
                         }
-                        if (rem < e) {
-                            const int D = e - rem;
-                            if (ex_sub(exL, u, D) == D) atomicOr(&clrRows[uy], bit);
-                            pushed = 1;
-                        }
+                        lane_sync();
                     }
-                    lane_sync();
                 }
                 // first-level vertices of stages k > 0 push over boundary arcs
                 if (admB) {
