@@ -41,10 +41,10 @@ def measured_traffic(kernel_src, summary):
     return float(rec["traffic_bytes_per_launch"])
 
 WORKLOADS = {
-    "2d": dict(cfg=1, desc="2048x2048 2D 8-connected blob grid, 64 blobs, 10% n-links zeroed, "
+    "2d": dict(cfg=1, tag="grid2d8_2048", desc="2048x2048 2D 8-connected blob grid, 64 blobs, 10% n-links zeroed, "
                            "64x64 regions (1024), seed 1"),
-    "3d": dict(cfg=2, desc="256^3 3D 6-connected blob grid, 32 blobs, 32^3 regions (512), seed 2"),
-    "batch": dict(cfg=3, desc="512 independent 2D blob grids, sides log-uniform in [32,512], "
+    "3d": dict(cfg=2, tag="grid3d6_256", desc="256^3 3D 6-connected blob grid, 32 blobs, 32^3 regions (512), seed 2"),
+    "batch": dict(cfg=3, tag="batch512", desc="512 independent 2D blob grids, sides log-uniform in [32,512], "
                               "half 4- and half 8-connected, seeds 3000+i, one batched solve"),
 }
 
@@ -224,10 +224,12 @@ def main():
     d_launch = sum(s["discharge_launches"] for s in stats)
     d_bytes = sum(s["discharge_bytes"] for s in stats)
     achieved = d_bytes / (d_ms / 1e3) / 1e9 if d_ms > 0 else 0.0
-    traffic = None
-    if args.workload == "2d":
-        traffic = measured_traffic("paper_1109_1146_amd/csrc/mf_discharge_wave.hip",
-                                   "k_discharge_wave_grid2d8_2048_traffic.json")
+    # the region kernel that ran, its source and the counter summary of this workload
+    kname, ksrc = {mf.MF_KERNEL_WAVE: ("k_discharge_wave", "mf_discharge_wave.hip"),
+                   mf.MF_KERNEL_ROWS: ("k_discharge_rows", "mf_discharge_rows.hip"),
+                   mf.MF_KERNEL_LDS: ("k_discharge_lds", "mf_discharge_lds.hip"),
+                   mf.MF_KERNEL_HBM: ("k_discharge", "mf_kernels.hip")}[stats[-1]["region_kernel"]]
+    traffic = measured_traffic("paper_1109_1146_amd/csrc/" + ksrc, f"{kname}_{wl['tag']}_traffic.json")
     rec = {
         "metric": "exact-maxflow solve throughput (plain P-ARD), sweeps, % HBM peak",
         "value": round(value, 3),
@@ -251,7 +253,7 @@ def main():
         "solve_ms": round(sum(s["solve_ms"] for s in stats) / len(stats), 3),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_discharge_wave" if args.workload == "2d" else "k_discharge",
+            "kernel": kname,
             "achieved": round(achieved, 3),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -154,7 +154,8 @@ typedef struct {
     int64_t flood_ticks;        /* part of search_ticks spent in the in-region floods */
     int64_t global_relabels;    /* exact region-distance relabels performed */
     int64_t global_relabel_levels; /* distance levels over all global relabels */
-    int64_t push_iterations;    /* parallel push iterations (MF_KERNEL_ROWS), summed over discharges */
+    int64_t push_iterations;    /* parallel push iterations, summed over discharges */
+    int64_t region_kernel;      /* MF_KERNEL_* that ran the region discharges */
 } mf_solve_stats;
 
 /* Create a solver handle for a grid shape and region partition.

@@ -837,6 +837,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         st->setup_ticks = (int64_t)g->pinned[24];
         st->flood_ticks = (int64_t)g->pinned[25];
         st->push_iterations = (int64_t)g->pinned[26];
+        st->region_kernel = regionMode == 3 ? MF_KERNEL_ROWS
+                            : (regionMode == 2 ? MF_KERNEL_WAVE : (regionMode == 1 ? MF_KERNEL_LDS : MF_KERNEL_HBM));
         st->global_relabels = relabels;
         st->global_relabel_levels = relabel_levels;
         st->boundary_size = g->nB;

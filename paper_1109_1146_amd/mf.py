@@ -54,7 +54,8 @@ class mf_solve_stats(ctypes.Structure):
                 ("trace_records", ctypes.c_int64), ("search_ticks", ctypes.c_int64),
                 ("push_ticks", ctypes.c_int64), ("setup_ticks", ctypes.c_int64),
                 ("flood_ticks", ctypes.c_int64), ("global_relabels", ctypes.c_int64),
-                ("global_relabel_levels", ctypes.c_int64), ("push_iterations", ctypes.c_int64)]
+                ("global_relabel_levels", ctypes.c_int64), ("push_iterations", ctypes.c_int64),
+                ("region_kernel", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
