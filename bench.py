@@ -41,10 +41,10 @@ def measured_traffic(kernel_src, summary):
     return float(rec["traffic_bytes_per_launch"])
 
 WORKLOADS = {
-    "2d": dict(cfg=1, tag="grid2d8_2048", desc="2048x2048 2D 8-connected blob grid, 64 blobs, 10% n-links zeroed, "
+    "2d": dict(cfg=1, tag="grid2d8_2048", relabel=12, desc="2048x2048 2D 8-connected blob grid, 64 blobs, 10% n-links zeroed, "
                            "64x64 regions (1024), seed 1"),
-    "3d": dict(cfg=2, tag="grid3d6_256", desc="256^3 3D 6-connected blob grid, 32 blobs, 32^3 regions (512), seed 2"),
-    "batch": dict(cfg=3, tag="batch512", desc="512 independent 2D blob grids, sides log-uniform in [32,512], "
+    "3d": dict(cfg=2, tag="grid3d6_256", relabel=4, desc="256^3 3D 6-connected blob grid, 32 blobs, 32^3 regions (512), seed 2"),
+    "batch": dict(cfg=3, tag="batch512", relabel=None, desc="512 independent 2D blob grids, sides log-uniform in [32,512], "
                               "half 4- and half 8-connected, seeds 3000+i, one batched solve"),
 }
 
@@ -60,8 +60,9 @@ def parse():
                    help="skip the learned-schedule comparison solves (profiling runs)")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
                    help="CPU work budget of the oracle baseline sample")
-    p.add_argument("--relabel-every", type=int, default=8,
-                   help="exact region-distance relabel every N sweeps (0 = off)")
+    p.add_argument("--relabel-every", type=int, default=None,
+                   help="exact region-distance relabel every N sweeps (0 = off; default: the "
+                        "workload's tuned interval)")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="only run a device-to-device copy of MIB MiB (HBM counter calibration)")
     return p.parse_args()
@@ -187,6 +188,8 @@ def main():
 
     mf.load()
     wl = WORKLOADS[args.workload]
+    if args.relabel_every is None:
+        args.relabel_every = wl["relabel"]
     inst = synth.config(wl["cfg"])
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)

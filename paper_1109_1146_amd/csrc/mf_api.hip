@@ -46,6 +46,8 @@ struct mf_grid {
     u64 *stats = nullptr;         // [0] discharges [1] vertices
     u64 *sums = nullptr;          // [0] sum cs [1] sum ct [2] sum rt
     unsigned int *changed = nullptr;
+    void *gcache = nullptr;        // global relabel: per-region masks (allocated on first use)
+    size_t gcache_bytes = 0;
     int *tmp_plane = nullptr;
     u64 *pinned = nullptr;        // host pinned mailbox
     // instance state
@@ -99,6 +101,7 @@ static void free_all(mf_grid *g) {
     }
     if (g->stage) (void)hipFree(g->stage);
     if (g->instRt) (void)hipFree(g->instRt);
+    if (g->gcache) (void)hipFree(g->gcache);
     if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
     if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
     if (g->pinned) (void)hipHostFree(g->pinned);
@@ -520,9 +523,27 @@ static int global_relabel(mf_grid *g, int *lab, u64 *act, hipStream_t s) {
     A.res = g->res; A.rt = g->rt; A.lab = lab;
     A.ringL = g->ringL; A.ringM = g->ringM; A.nring = g->nring; A.dinf = g->dinf;
     A.scratch = g->scratch;
-    // 2D regions of at most 64 x 64: one wavefront per region, row-bitmask flood
+    // 2D regions of at most 64 x 64: one wavefront per region, row-bitmask flood;
+    // 3D regions with 32-vertex rows: one workgroup per region, row-bitmask flood;
+    // both keep the region's masks in a cache built at level 0
+    const int R = G.ty * G.tz;
     const bool wave = g->ndim == 2 && G.tx <= 64 && G.ty <= 64;
-    const int blocks = wave ? std::min(G.nreg, g->numCU * 8) : std::min(G.nreg, g->nslots * 4);
+    const bool rows = g->ndim == 3 && G.K == 6 && G.tx == 32 && G.ty >= 2 && G.tz >= 2 &&
+                      R % 64 == 0 && R <= 1024;
+    if (wave || rows) {
+        const size_t need = wave ? (size_t)G.nreg * (G.K + 1) * 64 * sizeof(u64)
+                                 : (size_t)G.nreg * 7 * R * sizeof(unsigned);
+        if (g->gcache_bytes < need) {
+            if (g->gcache) (void)hipFree(g->gcache);
+            g->gcache = nullptr;
+            g->gcache_bytes = 0;
+            if (!ok(hipMalloc(&g->gcache, need))) return -1;
+            g->gcache_bytes = need;
+        }
+        A.cache = g->gcache;
+    }
+    const int blocks = wave ? std::min(G.nreg, g->numCU * 8)
+                            : (rows ? std::min(G.nreg, g->numCU * 2) : std::min(G.nreg, g->nslots * 4));
     // levels are launched in batches; a level with no flagged region is a cheap no-op
     const int batch = 4;
     int D = 0;
@@ -535,9 +556,12 @@ static int global_relabel(mf_grid *g, int *lab, u64 *act, hipStream_t s) {
             A.flagIn = g->dirty + (size_t)(lv & 1) * G.nreg;
             A.flagOut = g->dirty + (size_t)((lv + 1) & 1) * G.nreg;
             A.flagged = g->changed + j;
+            A.candBitsIn = (unsigned *)g->cand + (size_t)(lv & 1) * (G.N / 32);
+            A.candBitsOut = (unsigned *)g->cand + (size_t)((lv + 1) & 1) * (G.N / 32);
             if (!ok(hipMemsetAsync(g->changed + j, 0, sizeof(unsigned), s))) return -1;
-            if (!ok(wave ? mfd::launch_grelabel_wave(A, blocks, s) : mfd::launch_grelabel(A, blocks, s)))
-                return -1;
+            hipError_t e = wave ? mfd::launch_grelabel_wave(A, blocks, s)
+                                : (rows ? mfd::launch_grelabel_rows(A, blocks, s) : mfd::launch_grelabel(A, blocks, s));
+            if (!ok(e)) return -1;
         }
         if (!ok(hipMemcpyAsync(g->pinned + 14, g->changed + batch - 1, sizeof(unsigned), hipMemcpyDeviceToHost, s)))
             return -1;

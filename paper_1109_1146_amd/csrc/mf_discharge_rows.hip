@@ -603,9 +603,135 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Global relabel, one distance level D (see k_grelabel in mf_kernels.hip), for
+// the tiles of k_discharge_rows.  At level 0 every region builds its residual-
+// arc masks from HBM into a per-region cache (six directions, then the
+// unlabelled vertices); later levels read the cache.  The flood of a level
+// runs on the row masks with one barrier per step, from t at level 0 and from
+// the seed bits marked by the previous level otherwise; reached vertices get
+// label D, and reached border vertices mark their residual predecessors across
+// the border (unlabelled) as seeds of D + 1 and flag their regions.
+// ---------------------------------------------------------------------------
+size_t grelabel_rows_lds(int ty, int tz) { return (size_t)9 * ty * tz * sizeof(unsigned); }
+
+__global__ __launch_bounds__(kRowsNT) void k_grelabel_rows(GRelabelArgs A) {
+    extern __shared__ __align__(16) unsigned smem_rows[];
+    __shared__ __align__(16) int red[2][kRowsWaves];
+    __shared__ int s_go;
+    const Geo &G = A.G;
+    const int V = G.V, N = G.N, TY = G.ty, TZ = G.tz, R = TY * TZ, D = A.level, dinf = A.dinf;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const bool myrow = tid < R;
+    const int row = tid, y = tid % TY, z = tid / TY;
+    unsigned *tmp = smem_rows;        // [7][R]: masks built at level 0
+    unsigned *Fb = smem_rows + 7 * R; // [2][R]: frontier rows
+    int rc = 0;
+    for (int r = blockIdx.x; r < G.nreg; r += gridDim.x) {
+        if (tid == 0) {
+            s_go = (D == 0) ? 1 : A.flagIn[r];
+            if (D > 0) A.flagIn[r] = 0;
+        }
+        __syncthreads();
+        const int go = s_go;
+        __syncthreads();
+        if (!go) continue;
+        const size_t base = (size_t)r * V;
+        unsigned *cr = (unsigned *)A.cache + (size_t)r * 7 * R;
+        unsigned rk[6], U = 0u, seed = 0u;
+#pragma unroll
+        for (int k = 0; k < 6; k++) rk[k] = 0u;
+        if (D == 0) {
+            const int row0 = wid * 64;
+            if (row0 + 64 <= R) {
+                for (int q = 0; q < 7; q++) {
+                    const int *plane = q < 6 ? A.res + (size_t)q * N : A.rt;
+                    const int *src = plane + base + (size_t)row0 * 32 + lane;
+#pragma unroll 8
+                    for (int i = 0; i < 32; i++) {
+                        const u64 b = __ballot(src[i * 64] > 0);
+                        if (lane == 0) {
+                            tmp[q * R + row0 + 2 * i] = (unsigned)b;
+                            tmp[q * R + row0 + 2 * i + 1] = (unsigned)(b >> 32);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (myrow) {
+#pragma unroll
+                for (int k = 0; k < 6; k++) {
+                    rk[k] = tmp[k * R + row];
+                    cr[k * R + row] = rk[k];
+                }
+                U = ~0u;
+                seed = tmp[6 * R + row];
+            }
+        } else if (myrow) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) rk[k] = cr[k * R + row];
+            U = cr[6 * R + row];
+            unsigned *cw = A.candBitsIn + (base >> 5) + row;
+            seed = *cw & U;
+            *cw = 0u;
+        }
+        unsigned reached = seed, F = seed;
+        int p = 0;
+        for (;;) {
+            if (myrow) Fb[p * R + row] = F;
+            if (!block_any(F != 0u, red, rc)) break;
+            if (myrow) {
+                const unsigned *Fp = Fb + p * R;
+                const unsigned fyp = (y + 1 < TY) ? Fp[row + 1] : 0u;
+                const unsigned fym = (y > 0) ? Fp[row - 1] : 0u;
+                const unsigned fzp = (z + 1 < TZ) ? Fp[row + TY] : 0u;
+                const unsigned fzm = (z > 0) ? Fp[row - TY] : 0u;
+                const unsigned nw = U & ~reached &
+                                    ((rk[0] & (F >> 1)) | (rk[1] & (F << 1)) | (rk[2] & fyp) |
+                                     (rk[3] & fym) | (rk[4] & fzp) | (rk[5] & fzm));
+                reached |= nw;
+                F = nw;
+            }
+            p ^= 1;
+        }
+        // the unlabelled mask of the cache is written by every row at level 0
+        if (myrow && (reached || D == 0)) cr[6 * R + row] = U & ~reached;
+        if (myrow && reached) {
+            store_labels(A.lab, base + (size_t)row * 32, reached, D);
+            // predecessors across the border of the reached border vertices
+            for (int k = 0; k < 6; k++) {
+                // border vertices of this row that direction k leaves the tile from
+                unsigned m;
+                if (k == 0) m = reached & 0x80000000u;
+                else if (k == 1) m = reached & 1u;
+                else if (k == 2) m = (y == TY - 1) ? reached : 0u;
+                else if (k == 3) m = (y == 0) ? reached : 0u;
+                else if (k == 4) m = (z == TZ - 1) ? reached : 0u;
+                else m = (z == 0) ? reached : 0u;
+                while (m) {
+                    const int x = __ffs(m) - 1;
+                    m &= m - 1;
+                    // u = v + o_k across the border, with residual arc (u, v) in direction k ^ 1
+                    const int ug = cross_nbr(G, r, z, y, x, k);
+                    if (ug < 0 || A.res[(size_t)(k ^ 1) * N + ug] <= 0 || A.lab[ug] != dinf) continue;
+                    atomicOr(&A.candBitsOut[ug >> 5], 1u << (ug & 31));
+                    if (atomicExch(&A.flagOut[ug / V], 1) == 0) atomicAdd(A.flagged, 1u);
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_grelabel_rows(const GRelabelArgs &A, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_grelabel_rows, dim3(blocks), dim3(kRowsNT), grelabel_rows_lds(A.G.ty, A.G.tz), s, A);
+    return hipGetLastError();
+}
+
 void set_rows_attributes() {
     (void)hipFuncSetAttribute((const void *)k_discharge_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024);
+    (void)hipFuncSetAttribute((const void *)k_grelabel_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              64 * 1024);
 }
 
 // The boundary pushes keep three bits per border vertex of a thread in 64 bits.

@@ -610,16 +610,21 @@ hipError_t launch_discharge_wave(const DischargeArgs &A, int blocks, size_t lds,
 }
 
 // Global relabel, one distance level (see k_grelabel in mf_kernels.hip), for
-// 2D regions of at most 64 x 64 with the row-bitmask flood of one wavefront:
-// masks are built from HBM by ballot, the flood runs in registers, labels and
-// next-level marks are written back.
+// 2D regions of at most 64 x 64 with the row-bitmask flood of one wavefront.
+// At level 0 the residual-arc masks are built from HBM by ballot and kept in a
+// per-region cache with the mask of unlabelled vertices; later levels read the
+// cache and take their seeds from the border vertices marked by the previous
+// level.  The flood runs in registers; labels and next-level marks are written
+// back.
 template <int K>
 __global__ __launch_bounds__(64) void k_grelabel_wave(GRelabelArgs A) {
+    __shared__ u64 seedRows[64];
     const Geo &G = A.G;
     const int V = G.V, N = G.N, TX = G.tx, TY = G.ty, D = A.level, dinf = A.dinf;
     const int lane = threadIdx.x, y = lane;
     const bool myrow = y < TY;
     const u64 rowmask = TX == 64 ? ~0ull : ((1ull << TX) - 1);
+    seedRows[lane] = 0ull;
     int dy[K], dx[K];
     u64 inside[K];
 #pragma unroll
@@ -643,30 +648,45 @@ __global__ __launch_bounds__(64) void k_grelabel_wave(GRelabelArgs A) {
         }
         if (!go) continue;
         const int base = r * V;
+        u64 *cr = (u64 *)A.cache + (size_t)r * (K + 1) * 64;
         u64 R[K], U = 0, SEED = 0;
-        for (int row = 0; row < TY; row++) {
-            const int l = row * TX + lane;
-            const bool ok = lane < TX;
+        if (D == 0) {
+            for (int row = 0; row < TY; row++) {
+                const int l = row * TX + lane;
+                const bool ok = lane < TX;
+#pragma unroll
+                for (int k = 0; k < K; k++) {
+                    const u64 b = __ballot(ok && A.res[(size_t)k * N + base + l] > 0);
+                    if (lane == row) R[k] = b;
+                }
+                const u64 bs = __ballot(ok && A.rt[base + l] > 0);
+                if (lane == row) SEED = bs;
+            }
+            U = myrow ? rowmask : 0ull;  // every label is d_inf when a relabel starts
 #pragma unroll
             for (int k = 0; k < K; k++) {
-                const u64 b = __ballot(ok && A.res[(size_t)k * N + base + l] > 0);
-                if (lane == row) R[k] = b;
+                R[k] &= inside[k];
+                cr[k * 64 + lane] = R[k];
             }
-            const int lv = ok ? A.lab[base + l] : 0;
-            const bool unl = ok && lv == dinf;
-            bool sd;
-            if (D == 0) {
-                sd = unl && A.rt[base + l] > 0;
-            } else {
-                const bool c = ok && A.candIn[base + l] != 0;
-                if (c) A.candIn[base + l] = 0;
-                sd = unl && c;
-            }
-            const u64 bu = __ballot(unl), bs = __ballot(sd);
-            if (lane == row) { U = bu; SEED = bs; }
-        }
+        } else {
 #pragma unroll
-        for (int k = 0; k < K; k++) R[k] &= inside[k];
+            for (int k = 0; k < K; k++) R[k] = cr[k * 64 + lane];
+            U = cr[K * 64 + lane];
+            // seeds: border vertices marked by the previous level
+            for (int i = lane; i < A.nring; i += 64) {
+                const int l = A.ringL[i];
+                if (A.candIn[base + l]) {
+                    A.candIn[base + l] = 0;
+                    const int ry = l / TX;
+                    atomicOr(&seedRows[ry], 1ull << (l - ry * TX));
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            SEED = seedRows[lane] & U;
+            seedRows[lane] = 0ull;
+        }
         u64 reached = SEED, F = SEED;
         for (;;) {
             const Rows3 FR = rows3(F, y, TY);
@@ -678,9 +698,11 @@ __global__ __launch_bounds__(64) void k_grelabel_wave(GRelabelArgs A) {
             reached |= nw;
             F = nw;
         }
-        for (int row = 0; row < TY; row++) {
-            const u64 m = shfl64(reached, row);
-            if (lane < TX && ((m >> lane) & 1ull)) A.lab[base + row * TX + lane] = D;
+        if (myrow && reached) {
+            store_row_labels(A.lab, base + y * TX, reached, D);
+            cr[K * 64 + lane] = U & ~reached;
+        } else if (D == 0) {
+            cr[K * 64 + lane] = U;
         }
         // marks for D + 1: residual predecessors across the border of reached border vertices
         for (int i0 = 0; i0 < A.nring; i0 += 64) {

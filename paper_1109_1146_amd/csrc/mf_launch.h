@@ -113,9 +113,14 @@ struct GRelabelArgs {
     int nring;
     int dinf;
     int *scratch;         // V ints per workgroup
+    void *cache;          // per-region residual-arc and unlabelled masks, built at level 0
+    unsigned *candBitsIn, *candBitsOut;  // seeds / marks as one bit per vertex (rows kernel)
 };
 
 hipError_t launch_grelabel(const GRelabelArgs &A, int blocks, hipStream_t s);
+// Relabel level for the tiles of the rows discharge; cache: 7 * ty * tz words per region.
+hipError_t launch_grelabel_rows(const GRelabelArgs &A, int blocks, hipStream_t s);
+size_t grelabel_rows_lds(int ty, int tz);
 hipError_t launch_grelabel_wave(const GRelabelArgs &A, int blocks, hipStream_t s);
 hipError_t launch_activity(const Geo &G, const int *ex, const int *lab, int dinf, int *ractive,
                            unsigned long long *act, hipStream_t s);
