@@ -64,7 +64,8 @@ enum {
 enum {
     MF_SCHED_PARD = 0,    /* Alg. 2: all active regions against the previous sweep's labels */
     MF_SCHED_COLORED = 1, /* Alg. 1 as phases of non-interacting regions (reserved) */
-    MF_SCHED_LEARNED = 2, /* region order and deferral from a trained scorer (opts->model) */
+    MF_SCHED_LEARNED = 2, /* deferral from a trained scorer (opts->model); the regions to
+                             discharge are queued longest previous discharge first */
     MF_SCHED_AUTO = 3     /* library's choice (currently MF_SCHED_PARD) */
 };
 

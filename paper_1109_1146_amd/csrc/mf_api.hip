@@ -66,7 +66,7 @@ struct mf_grid {
     u64 *instRt = nullptr;        // per-instance sum of residual t-links
     // learned schedule
     float *feat = nullptr, *score = nullptr;
-    int *defer = nullptr, *deferCount = nullptr, *lorder = nullptr;
+    int *defer = nullptr, *deferCount = nullptr, *lorder = nullptr, *rticks = nullptr;
     // captured sweep batches
     hipStream_t own_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -95,7 +95,7 @@ static void free_all(mf_grid *g) {
         if (p) (void)hipFree(p);
     if (g->reginst) (void)hipFree(g->reginst);
     {
-        void *q[] = {g->feat, g->score, g->defer, g->deferCount, g->lorder};
+        void *q[] = {g->feat, g->score, g->defer, g->deferCount, g->lorder, g->rticks};
         for (void *x : q)
             if (x) (void)hipFree(x);
     }
@@ -593,7 +593,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         const size_t R = (size_t)g->G.nreg;
         if (!g->feat && !(ok(dalloc(&g->feat, R * mfd::kFeat)) && ok(dalloc(&g->score, R)) &&
                           ok(dalloc(&g->defer, R)) && ok(dalloc(&g->deferCount, R)) &&
-                          ok(dalloc(&g->lorder, R))))
+                          ok(dalloc(&g->lorder, R)) && ok(dalloc(&g->rticks, R))))
             return MF_E_NOMEM;
         if (learned && !model_ws(model, g->G.nreg)) return MF_E_NOMEM;
     }
@@ -631,6 +631,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     HIP_TRY(hipMemsetAsync(g->stats, 0, 16 * sizeof(u64), s));
     HIP_TRY(hipMemsetAsync(g->ractive, 0, sizeof(int) * G.nreg, s));
     if (learned) HIP_TRY(hipMemsetAsync(g->deferCount, 0, sizeof(int) * G.nreg, s));
+    if (learned) HIP_TRY(hipMemsetAsync(g->rticks, 0, sizeof(int) * G.nreg, s));
     HIP_TRY(mfd::launch_init(G, g->in_cs, g->in_ct, g->in_nbr, (int)g->n, g->res, g->rt, g->ex,
                              g->lab[0], g->lab[1], g->pushb, g->ractive, g->act, s));
 
@@ -760,6 +761,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                         SA.threshold = (first + j == 0) ? -1.f : (o.defer_threshold > 0.f ? o.defer_threshold : 0.5f);
                         SA.maxDefer = o.max_defer > 0 ? o.max_defer : 2;
                         SA.defer = g->defer; SA.deferCount = g->deferCount; SA.order = g->lorder;
+                        SA.regionTicks = g->rticks;
+                        D.regionTicks = g->rticks;
                         if (!ok(mfd::launch_sched_queue(SA, s))) return false;
                         D.order = g->lorder;
                         D.defer = g->defer;

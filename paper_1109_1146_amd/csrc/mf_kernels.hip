@@ -382,6 +382,7 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
         __syncthreads();
         if (tid == 0) {
             atomicAdd(&A.stats[0], 1ull);
+            if (A.regionTicks) A.regionTicks[r] = (int)min(wall_clock64() - t_start, 0x7fffffffLL);
             atomicAdd(&A.stats[1], (u64)A.rvcount[r]);
             atomicAdd(&A.stats[2], (u64)(iter + 1));
             atomicAdd(&A.stats[3], (u64)bfs_steps);

@@ -30,6 +30,7 @@ struct DischargeArgs {
     long long traceCap;
     int sweep;           // sweep index of this launch
     const int *defer;    // optional: 1 = an active region is deferred this sweep (keeps its flag)
+    int *regionTicks;    // optional: duration of each region's last discharge (100 MHz ticks)
 };
 
 constexpr int kFeat = 6;  // floats per region in the scheduler features
@@ -51,6 +52,7 @@ struct SchedArgs {
     float threshold;      // defer an active region when sigmoid(score) < threshold
     int maxDefer;         // ... unless it was deferred this many sweeps in a row
     int *defer, *deferCount, *order;
+    const int *regionTicks;  // duration of each region's last discharge: longest first
 };
 
 struct FuseArgs {

@@ -246,7 +246,11 @@ __global__ void k_sched_queue(SchedArgs A) {
             if (act && prob < A.threshold && A.deferCount[i] < A.maxDefer) d = 1;
             A.defer[i] = d;
             A.deferCount[i] = d ? A.deferCount[i] + 1 : 0;
-            key[i] = act ? (d ? 1.f + (1.f - prob) : 3.f - prob) : 0.f;  // larger = earlier
+            // larger = earlier: regions to discharge, longest previous discharge
+            // first (a sweep lasts as long as its slowest region), then deferred
+            // ones (skipped at once), then inactive ones
+            const float lt = (float)A.regionTicks[i];
+            key[i] = act ? (d ? 1.f + (1.f - prob) : 2.f + lt / (lt + 100000.f)) : 0.f;
             val[i] = i;
         } else {
             key[i] = -1.f;

@@ -4,19 +4,24 @@ The scheduler CNN (``mf.Model``, kernels in ``csrc/mf_sched.hip``) reads three
 features per region at the start of a sweep (active excess, boundary label
 level, residual degree of the boundary) and predicts whether discharging the
 region in this sweep makes progress: it sends flow to the sink, or the excess
-it pushes out does not come back (a discharge whose region holds at least 90%
-of the same excess at its next discharge, with nothing sent to the sink, only
-bounced excess between regions).  ``MF_SCHED_LEARNED`` discharges
-regions in decreasing order of that score and defers active regions whose
-probability is below a threshold (at most ``max_defer`` sweeps in a row, never
-in the first sweep).  The exact result never depends on the scores.
+it pushes out does not come back (a bounce is a discharge whose region holds
+at least 90% of the same excess at its next discharge, with nothing sent to the
+sink).  ``train --slow-bounce`` marks only the bounces among the slower half of
+their sweep's discharges (a sweep lasts as long as its slowest region).
+``MF_SCHED_LEARNED`` defers active regions whose probability is below a
+threshold (at most ``max_defer`` sweeps in a row, never in the first sweep) and
+queues the others longest previous discharge first.  The exact result never
+depends on the scores.
 
-Training data are plain P-ARD solves (the fallback schedule) of instances from
-the generator families of the 2048^2 8-connected and 256^3 6-connected
-workloads, with training seeds disjoint from the evaluation seeds.  Training
+Training data are plain P-ARD solves (the fallback schedule, relabel every 8
+sweeps, or the bench intervals with ``--slow-bounce``) of instances from the generator families of the 2048^2
+8-connected and 256^3 6-connected workloads, with training seeds (100-105)
+disjoint from the validation seeds of ``tune`` (110, 111) and the bench seeds.  Training
 runs on the GPU with the library's own forward, backward and Adam kernels.
 
     python -m paper_1109_1146_amd.learned train      # writes models/sched_cnn16.npy
+    python -m paper_1109_1146_amd.learned train --slow-bounce [path]
+    python -m paper_1109_1146_amd.learned tune       # deferral threshold on validation instances
     python -m paper_1109_1146_amd.learned evaluate   # plain vs learned on the workloads
 """
 from __future__ import annotations
@@ -54,9 +59,11 @@ def region_dims(inst, tile=None):
     return tuple(-(-a // b) for a, b in zip(d, tile))
 
 
-def progress_targets(rec, bounce=0.9):
+def progress_targets(rec, bounce=0.9, slow_q=None):
     """1 for a discharge that sent flow to the sink or whose excess did not come
-    back by the region's next discharge; 0 for a bounce."""
+    back by the region's next discharge; 0 for a bounce.  With slow_q, only the
+    bounces at or above the slow_q quantile of their sweep's discharge times are
+    0 (a sweep lasts as long as its slowest discharge)."""
     s, r = rec[:, 0], rec[:, 1]
     ex_in = rec[:, 6].astype(np.float64)
     to_sink = rec[:, 7]
@@ -65,7 +72,18 @@ def progress_targets(rec, bounce=0.9):
     for a, b in zip(order[:-1], order[1:]):
         if r[a] == r[b] and to_sink[a] == 0 and ex_in[b] >= bounce * ex_in[a]:
             y[a] = 0.0
+    if slow_q is not None:
+        ticks = rec[:, 5].astype(np.float64)
+        for sw in np.unique(s):
+            m = s == sw
+            cut = np.quantile(ticks[m], slow_q)
+            y[m & (ticks < cut)] = 1.0
     return y
+
+
+# relabel intervals the solves use (those of the bench workloads)
+RELABEL = {"2d": 12, "3d": 4}
+SLOW_Q = 0.5
 
 
 def collect(inst, relabel_every=8, max_sweeps=256, trace_cap=500000, target="progress"):
@@ -83,7 +101,12 @@ def collect(inst, relabel_every=8, max_sweeps=256, trace_cap=500000, target="pro
     n = min(st["trace_records"], trace_cap)
     rec = tr[:n].cpu().numpy()
     S = min(st["sweeps"], max_sweeps)
-    y = progress_targets(rec) if target == "progress" else (rec[:, 7] > 0).astype(np.float32)
+    if target == "progress":
+        y = progress_targets(rec)
+    elif target == "slow_bounce":
+        y = progress_targets(rec, slow_q=SLOW_Q)
+    else:
+        y = (rec[:, 7] > 0).astype(np.float32)
     out = []
     for s in range(1, S):
         m = rec[:, 0] == s
@@ -164,11 +187,16 @@ def main(argv):
     cmd = argv[1] if len(argv) > 1 else "train"
     mf.load()
     if cmd == "train":
+        slow = "--slow-bounce" in argv
+        argv = [a for a in argv if a != "--slow-bounce"]
         examples = []
         for kind, seeds in (("2d", TRAIN_SEEDS_2D), ("3d", TRAIN_SEEDS_3D)):
             for seed in seeds:
                 inst = train_instance(kind, seed)
-                ex, st = collect(inst)
+                if slow:
+                    ex, st = collect(inst, relabel_every=RELABEL[kind], target="slow_bounce")
+                else:
+                    ex, st = collect(inst)
                 print(f"traces {inst.name}: {len(ex)} sweeps, {st['region_discharges']} discharges",
                       flush=True)
                 examples += ex
@@ -182,7 +210,30 @@ def main(argv):
         model = load_model(argv[3] if len(argv) > 3 else MODEL_PATH)
         for cfg in [int(c) for c in (argv[2] if len(argv) > 2 else "1,2").split(",")]:
             inst = synth.config(cfg)
-            print(json.dumps({"workload": inst.name, **compare(inst, model)}), flush=True)
+            rel = RELABEL["2d" if len(inst.dims) == 2 else "3d"]
+            print(json.dumps({"workload": inst.name, **compare(inst, model, relabel_every=rel)}), flush=True)
+    elif cmd == "tune":
+        # deferral threshold and limit, chosen on validation instances (seeds
+        # disjoint from the training and bench instances)
+        model = load_model(argv[2] if len(argv) > 2 else MODEL_PATH)
+        for kind, seed in (("2d", 110), ("3d", 111)):
+            inst = train_instance(kind, seed)
+            rel = RELABEL[kind]
+            with mf.Grid(inst.dims, inst.conn, inst.tile) as g:
+                g.set_caps(inst.cs, inst.ct, inst.nbr)
+                runs = [("plain", {})] + [(f"t{t}_d{d}", dict(schedule=mf.MF_SCHED_LEARNED, model=model,
+                                                              defer_threshold=t, max_defer=d))
+                                          for t in (0.05, 0.1, 0.2, 0.3, 0.5) for d in (1, 2)]
+                for name, kw in runs:
+                    g.solve(global_relabel_every=rel, **kw)
+                    times = []
+                    for _ in range(2):
+                        t0 = time.perf_counter()
+                        st = g.solve(global_relabel_every=rel, **kw)
+                        times.append((time.perf_counter() - t0) * 1e3)
+                    print(json.dumps({"instance": inst.name, "run": name, "ms": round(min(times), 2),
+                                      "sweeps": st["sweeps"], "discharges": st["region_discharges"],
+                                      "flow": g.flow_value()}), flush=True)
     return 0
 
 
