@@ -53,29 +53,38 @@ __device__ __forceinline__ u64 shfl64(u64 v, int src) {
     return __shfl(v, src, 64);
 }
 
-// Row (y + dy) of a per-lane row mask, 0 outside the tile.
-__device__ __forceinline__ u64 row_at(u64 v, int y, int dy, int ty) {
-    const int src = y + dy;
-    const u64 w = shfl64(v, src < 0 ? 0 : (src > 63 ? 63 : src));
-    return (src < 0 || src >= ty) ? 0ull : w;
-}
-
 // Bits of row mask m moved so that bit x holds bit x + dx.
 __device__ __forceinline__ u64 shift_dx(u64 m, int dx) {
     return dx > 0 ? (m >> dx) : (dx < 0 ? (m << (-dx)) : m);
 }
 
-// Rows y-1, y, y+1 of a per-lane row mask (0 outside the tile).
+// Whole-wave lane shifts by DPP (wave_shr:1 / wave_shl:1): lane i reads lane
+// i - 1 / i + 1 of v; lanes without a source read 0.
+__device__ __forceinline__ u64 lane_prev(u64 v) {
+    const unsigned lo = __builtin_amdgcn_update_dpp(0u, (unsigned)v, 0x138, 0xf, 0xf, true);
+    const unsigned hi = __builtin_amdgcn_update_dpp(0u, (unsigned)(v >> 32), 0x138, 0xf, 0xf, true);
+    return ((u64)hi << 32) | lo;
+}
+__device__ __forceinline__ u64 lane_next(u64 v) {
+    const unsigned lo = __builtin_amdgcn_update_dpp(0u, (unsigned)v, 0x130, 0xf, 0xf, true);
+    const unsigned hi = __builtin_amdgcn_update_dpp(0u, (unsigned)(v >> 32), 0x130, 0xf, 0xf, true);
+    return ((u64)hi << 32) | lo;
+}
+
+// Rows y-1, y, y+1 of a per-lane row mask (0 outside the tile).  Lanes at or
+// beyond the tile's last row hold 0, so the shifted-in rows are 0 there.
 struct Rows3 {
     u64 up, mid, dn;  // row y-1, y, y+1
     __device__ __forceinline__ u64 at(int dy) const { return dy < 0 ? up : (dy > 0 ? dn : mid); }
 };
 
 __device__ __forceinline__ Rows3 rows3(u64 v, int y, int ty) {
+    (void)y;
+    (void)ty;
     Rows3 r;
     r.mid = v;
-    r.up = row_at(v, y, -1, ty);
-    r.dn = row_at(v, y, 1, ty);
+    r.up = lane_prev(v);
+    r.dn = lane_next(v);
     return r;
 }
 
