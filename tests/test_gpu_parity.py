@@ -136,6 +136,31 @@ def test_large_capacities(mf):
     _check(mf, inst)
 
 
+@pytest.mark.parametrize("case", ["u8_limits", "i16_pairs", "i16_inflow"])
+def test_wave_kernel_storage_modes(mf, case):
+    """The wavefront kernel's LDS widths at their limits: 8-bit residuals with
+    16-bit excess (pair sum 255, t-link 255, inflow bound up to 32767, excess
+    near the int16 limit), and 16-bit residuals chosen for pair sums above 255
+    or inflow bounds above 32767."""
+    rng = np.random.default_rng(77)
+    dims, tile = (40, 50), (16, 16)
+    if case == "u8_limits":
+        inst = synth.random_grid(dims, 8, 21, tile=tile, cap_hi=127, tlink_hi=255)
+        v = 5 * dims[1] + 7  # one pair with sum exactly 255 (+x arc and its reverse)
+        inst.nbr[0][v], inst.nbr[1][v + 1] = 128, 127
+        # large source links on a few vertices: c(s,v) + sum_u c(u,v) <= 32767
+        # (8 arcs of at most 128 each), so excess gets close to the int16 limit
+        pick = rng.choice(inst.n, 12, replace=False)
+        inst.cs[pick] = 32767 - 8 * 128
+    elif case == "i16_pairs":
+        inst = synth.random_grid(dims, 8, 22, tile=tile, cap_hi=1000, tlink_hi=300)
+    else:
+        inst = synth.random_grid(dims, 8, 23, tile=tile, cap_hi=100, tlink_hi=200)
+        inst.cs[rng.choice(inst.n, 20, replace=False)] = 40000
+    _check(mf, inst, region_kernel=mf.MF_KERNEL_WAVE)
+    _check(mf, inst, region_kernel=mf.MF_KERNEL_WAVE, global_relabel_every=2)
+
+
 @pytest.mark.parametrize("cfg", [1, 2])
 def test_full_size_workloads_exact(mf, cfg):
     inst = synth.config(cfg)
