@@ -125,6 +125,17 @@ __device__ __forceinline__ int ex_sub(short *e, int i, int d) {
     return (int)((old >> sh) & 0xffffu);
 }
 
+// Add d to a residual in LDS without reading it: 8- and 16-bit residuals are
+// added to their containing 32-bit word (a residual never exceeds its pair sum,
+// which fits its width, so no carry leaves it).
+__device__ __forceinline__ void res_add(unsigned char *r, int i, int d) {
+    atomicAdd((unsigned *)(r + (i & ~3)), (unsigned)d << ((i & 3) * 8));
+}
+__device__ __forceinline__ void res_add(short *r, int i, int d) {
+    atomicAdd((unsigned *)(r + (i & ~1)), (unsigned)d << ((i & 1) * 16));
+}
+__device__ __forceinline__ void res_add(int *r, int i, int d) { atomicAdd(&r[i], d); }
+
 __device__ __forceinline__ void store_row_labels(int *lab, int rowBase, u64 bits, int val) {
     while (bits) {
         const int x = __ffsll(bits) - 1;
@@ -426,7 +437,7 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
                             const int v = u + dy[k] * TX + dx[k];
                             const u64 vbit = 1ull << (ux + dx[k]);
                             resL[u * K + k] = (RT)(c[k] - d);
-                            resL[v * K + (k ^ 1)] = (RT)(resL[v * K + (k ^ 1)] + d);
+                            res_add(resL, v * K + (k ^ 1), d);
                             ex_add(exL, v, d);
                             atomicOr(&resM[(k ^ 1) * 64 + uy + dy[k]], vbit);
                             atomicOr(&recvRows[uy + dy[k]], vbit);
@@ -438,8 +449,10 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
                         }
                     }
                     if (rem < e) {
-                        const int D = e - rem;
-                        if (ex_sub(exL, u, D) == D) atomicOr(&clrRows[uy], bit);
+                        // drained what it saw: cleared, unless a receipt in this
+                        // iteration sets the bit again at the merge
+                        ex_add(exL, u, rem - e);
+                        if (rem == 0) atomicOr(&clrRows[uy], bit);
                         pushed = 1;
                     }
                 };
