@@ -561,6 +561,9 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
                 if (!any) break;
             }
             t_push += wall_clock64() - t1s;
+            // no excess left in the region (the masks may only over-report it):
+            // the next search cannot find an excess vertex, so it writes the labels
+            if (!block_any(myrow && exM != 0u, red, rc)) writeMode = true;
         }
         __syncthreads();
         if (A.trace) {

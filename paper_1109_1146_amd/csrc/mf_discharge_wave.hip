@@ -540,6 +540,9 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
                 if (!any) break;
             }
             t_push += wall_clock64() - t_mid;
+            // no excess left in the region (the masks may only over-report it):
+            // the next search cannot find an excess vertex, so it writes the labels
+            if (__ballot(EXm != 0ull) == 0ull) writeMode = true;
         }
         __syncthreads();
         // ---------------- write the region back ----------------
