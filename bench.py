@@ -41,7 +41,7 @@ def measured_traffic(kernel_src, summary):
     return float(rec["traffic_bytes_per_launch"])
 
 WORKLOADS = {
-    "2d": dict(cfg=1, tag="grid2d8_2048", relabel=12, desc="2048x2048 2D 8-connected blob grid, 64 blobs, 10% n-links zeroed, "
+    "2d": dict(cfg=1, tag="grid2d8_2048", relabel=10, desc="2048x2048 2D 8-connected blob grid, 64 blobs, 10% n-links zeroed, "
                            "64x64 regions (1024), seed 1"),
     "3d": dict(cfg=2, tag="grid3d6_256", relabel=4, desc="256^3 3D 6-connected blob grid, 32 blobs, 32^3 regions (512), seed 2"),
     "batch": dict(cfg=3, tag="batch512", relabel=None, desc="512 independent 2D blob grids, sides log-uniform in [32,512], "

@@ -82,7 +82,7 @@ def progress_targets(rec, bounce=0.9, slow_q=None):
 
 
 # relabel intervals the solves use (those of the bench workloads)
-RELABEL = {"2d": 12, "3d": 4}
+RELABEL = {"2d": 10, "3d": 4}
 SLOW_Q = 0.5
 
 
