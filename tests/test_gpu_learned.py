@@ -90,7 +90,8 @@ def _exact(mf, inst, **kw):
 @pytest.mark.parametrize("seed", range(6))
 def test_learned_schedule_exact_with_arbitrary_scores(mf, seed, threshold, max_defer):
     """Whatever the network says, the flow and cuts are the oracle's."""
-    cases = [((40, 36), 8, (8, 8)), ((30, 50), 4, (10, 16)), ((9, 10, 11), 6, (4, 4, 4))]
+    cases = [((40, 36), 8, (8, 8)), ((30, 50), 4, (10, 16)), ((9, 10, 11), 6, (4, 4, 4)),
+             ((8, 40, 70), 6, (4, 16, 32))]  # the last one runs the row-bitmask 3D kernel
     dims, conn, tile = cases[seed % len(cases)]
     inst = synth.random_grid(dims, conn, 700 + seed, tile=tile)
     model = mf.Model(16, seed=seed)  # untrained: arbitrary scores

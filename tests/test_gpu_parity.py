@@ -205,6 +205,14 @@ def test_rows_kernel_tiles(mf, seed):
     _check(mf, inst, region_kernel=mf.MF_KERNEL_ROWS, global_relabel_every=2)
 
 
+def test_hbm_kernel_64_cubed_regions(mf):
+    """64^3 regions (the tile of the 464^3 workload) run on the HBM kernel; ragged grid."""
+    inst = synth.blob_grid((96, 100, 130), 6, 31, 6, 6.0, 20.0, tile=(64, 64, 64), name="blob3d_t64")
+    out, _ = _check(mf, inst, certify=False)
+    assert out["stats"]["region_kernel"] == mf.MF_KERNEL_HBM
+    _check(mf, inst, certify=False, global_relabel_every=4)
+
+
 def test_workload2_hbm_kernel_exact(mf):
     inst = synth.config(2)
     _check(mf, inst, certify=False, region_kernel=mf.MF_KERNEL_HBM)
