@@ -89,7 +89,9 @@ typedef struct {
                                      is discharged anyway; 0 = 2 */
     float defer_threshold;        /* MF_SCHED_LEARNED: defer an active region whose predicted
                                      probability of useful work is below this; 0 = 0.5 */
-    int32_t reserved3;
+    int32_t defer_mode;           /* MF_SCHED_LEARNED: 0 = a deferred region is skipped (labels carried
+                                     over); 1 = it only runs its region relabel (Alg. 3 on the current
+                                     state, no pushes) with the row-bitmask and wavefront kernels */
     float *features;              /* device buffer [features_cap][regions][MF_FEATURES] or NULL:
                                      the scheduler's region features at the start of each sweep */
     int64_t features_cap;         /* sweeps the features buffer holds */
@@ -157,6 +159,7 @@ typedef struct {
     int64_t global_relabel_levels; /* distance levels over all global relabels */
     int64_t push_iterations;    /* parallel push iterations, summed over discharges */
     int64_t region_kernel;      /* MF_KERNEL_* that ran the region discharges */
+    int64_t relabel_only;       /* deferred regions that ran their region relabel only (defer_mode 1) */
 } mf_solve_stats;
 
 /* Create a solver handle for a grid shape and region partition.

@@ -763,6 +763,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                         SA.defer = g->defer; SA.deferCount = g->deferCount; SA.order = g->lorder;
                         SA.regionTicks = g->rticks;
                         D.regionTicks = g->rticks;
+                        D.deferRelabel = o.defer_mode == 1 ? 1 : 0;
                         if (!ok(mfd::launch_sched_queue(SA, s))) return false;
                         D.order = g->lorder;
                         D.defer = g->defer;
@@ -864,6 +865,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         st->setup_ticks = (int64_t)g->pinned[24];
         st->flood_ticks = (int64_t)g->pinned[25];
         st->push_iterations = (int64_t)g->pinned[26];
+        st->relabel_only = (int64_t)g->pinned[27];
         st->region_kernel = regionMode == 3 ? MF_KERNEL_ROWS
                             : (regionMode == 2 ? MF_KERNEL_WAVE : (regionMode == 1 ? MF_KERNEL_LDS : MF_KERNEL_HBM));
         st->global_relabels = relabels;

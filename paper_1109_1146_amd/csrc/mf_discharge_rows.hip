@@ -206,8 +206,9 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
         const size_t base = (size_t)r * V;
         if (tid == 0) {
             s_active = A.ractive[r];
-            // a deferred region keeps its flag and is discharged in a later sweep
-            if (s_active && A.defer && A.defer[r]) s_active = 0;
+            // a deferred region keeps its flag and is discharged in a later sweep;
+            // with deferRelabel it runs its region relabel now (s_active 2)
+            if (s_active && A.defer && A.defer[r]) s_active = A.deferRelabel ? 2 : 0;
             else A.ractive[r] = 0;
         }
         __syncthreads();
@@ -262,7 +263,8 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
 
         int iter = 0;
         long long levels = 0, stages = 0, pushIters = 0, t_search = 0, t_flood = 0, t_stage = 0, t_push = 0;
-        bool writeMode = false;
+        const bool relabelOnly = s_active == 2;
+        bool writeMode = relabelOnly;
         const size_t rowBase = base + (size_t)row * 32;
         for (;;) {
             // ---------------- multi-level search from the targets ----------------
@@ -574,7 +576,9 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
             atomicAdd((unsigned long long *)&s_tr[3], (u64)lsum);
         }
         __syncthreads();
-        if (tid == 0) {
+        if (tid == 0 && relabelOnly) {
+            atomicAdd(&A.stats[11], 1ull);
+        } else if (tid == 0) {
             atomicAdd(&A.stats[0], 1ull);
             if (A.regionTicks) A.regionTicks[r] = (int)min(wall_clock64() - t_start, 0x7fffffffLL);
             atomicAdd(&A.stats[1], (u64)A.rvcount[r]);

@@ -215,8 +215,9 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
         int active = 0;
         if (lane == 0) {
             active = A.ractive[r];
-            // a deferred region keeps its flag and is discharged in a later sweep
-            if (active && A.defer && A.defer[r]) active = 0;
+            // a deferred region keeps its flag and is discharged in a later sweep;
+            // with deferRelabel it runs its region relabel now (active 2)
+            if (active && A.defer && A.defer[r]) active = A.deferRelabel ? 2 : 0;
             else A.ractive[r] = 0;
         }
         active = __shfl(active, 0, 64);
@@ -279,7 +280,8 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
 
         int iter = 0;
         long long levels = 0, stages = 0, pushIters = 0, t_search = 0, t_push = 0;
-        bool writeMode = false;
+        const bool relabelOnly = active == 2;
+        bool writeMode = relabelOnly;
         const int rowBase = base + y * TX;
         for (;;) {
             const long long t_round = wall_clock64();
@@ -568,7 +570,9 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
             atomicAdd((unsigned long long *)&s_tr[3], (u64)lsum);
         }
         __syncthreads();
-        if (lane == 0) {
+        if (lane == 0 && relabelOnly) {
+            atomicAdd(&A.stats[11], 1ull);
+        } else if (lane == 0) {
             atomicAdd(&A.stats[0], 1ull);
             if (A.regionTicks) A.regionTicks[r] = (int)min(wall_clock64() - t_start, 0x7fffffffLL);
             atomicAdd(&A.stats[1], (u64)A.rvcount[r]);

@@ -31,6 +31,7 @@ struct DischargeArgs {
     int sweep;           // sweep index of this launch
     const int *defer;    // optional: 1 = an active region is deferred this sweep (keeps its flag)
     int *regionTicks;    // optional: duration of each region's last discharge (100 MHz ticks)
+    int deferRelabel;    // a deferred region runs its region relabel only (rows and wave kernels)
 };
 
 constexpr int kFeat = 6;  // floats per region in the scheduler features

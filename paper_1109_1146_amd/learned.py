@@ -221,9 +221,10 @@ def main(argv):
             rel = RELABEL[kind]
             with mf.Grid(inst.dims, inst.conn, inst.tile) as g:
                 g.set_caps(inst.cs, inst.ct, inst.nbr)
-                runs = [("plain", {})] + [(f"t{t}_d{d}", dict(schedule=mf.MF_SCHED_LEARNED, model=model,
-                                                              defer_threshold=t, max_defer=d))
-                                          for t in (0.05, 0.1, 0.2, 0.3, 0.5) for d in (1, 2)]
+                runs = [("plain", {})] + [(f"t{t}_d{d}_m{mode}", dict(schedule=mf.MF_SCHED_LEARNED, model=model,
+                                                                      defer_threshold=t, max_defer=d,
+                                                                      defer_mode=mode))
+                                          for mode in (0, 1) for t in (0.1, 0.3, 0.5) for d in (1, 2)]
                 for name, kw in runs:
                     g.solve(global_relabel_every=rel, **kw)
                     times = []
@@ -233,7 +234,7 @@ def main(argv):
                         times.append((time.perf_counter() - t0) * 1e3)
                     print(json.dumps({"instance": inst.name, "run": name, "ms": round(min(times), 2),
                                       "sweeps": st["sweeps"], "discharges": st["region_discharges"],
-                                      "flow": g.flow_value()}), flush=True)
+                                      "relabel_only": st["relabel_only"], "flow": g.flow_value()}), flush=True)
     return 0
 
 

@@ -40,7 +40,7 @@ class mf_solve_opts(ctypes.Structure):
                 ("region_kernel", ctypes.c_int32), ("trace", ctypes.c_void_p),
                 ("trace_cap", ctypes.c_int64), ("graph", ctypes.c_int32),
                 ("max_defer", ctypes.c_int32), ("defer_threshold", ctypes.c_float),
-                ("reserved3", ctypes.c_int32), ("features", ctypes.c_void_p),
+                ("defer_mode", ctypes.c_int32), ("features", ctypes.c_void_p),
                 ("features_cap", ctypes.c_int64)]
 
 
@@ -55,7 +55,7 @@ class mf_solve_stats(ctypes.Structure):
                 ("push_ticks", ctypes.c_int64), ("setup_ticks", ctypes.c_int64),
                 ("flood_ticks", ctypes.c_int64), ("global_relabels", ctypes.c_int64),
                 ("global_relabel_levels", ctypes.c_int64), ("push_iterations", ctypes.c_int64),
-                ("region_kernel", ctypes.c_int64)]
+                ("region_kernel", ctypes.c_int64), ("relabel_only", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -229,7 +229,7 @@ class Grid:
     def solve(self, schedule=MF_SCHED_PARD, gap=True, global_relabel_every=0, check_every=0,
               max_sweeps=0, stream=None, profile=False, region_kernel=MF_KERNEL_AUTO,
               trace=None, graph=False, model=None, max_defer=0, defer_threshold=0.0,
-              features=None):
+              features=None, defer_mode=0):
         """trace: optional int32 device tensor of shape (cap, TRACE_FIELDS)."""
         tptr, tcap = None, 0
         if trace is not None:
@@ -242,7 +242,7 @@ class Grid:
                           model=None, stream=stream, profile=1 if profile else 0,
                           region_kernel=region_kernel, trace=tptr, trace_cap=tcap,
                           graph=1 if graph else 0, max_defer=max_defer,
-                          defer_threshold=defer_threshold, reserved3=0, features=fptr,
+                          defer_threshold=defer_threshold, defer_mode=defer_mode, features=fptr,
                           features_cap=fcap)
         if model is not None:
             o.model = model._h
