@@ -150,6 +150,25 @@ def bench_batch(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
                      "traffic": None, "avg_launch_ms": round(d_ms / max(d_launch, 1), 4)},
     }
+    # the learned schedule on the same batch (not in value): sweeps, discharges, time
+    if not args.no_learned:
+        from paper_1109_1146_amd import learned
+        model = learned.load_model()
+        lkw = dict(schedule=mf.MF_SCHED_LEARNED, model=model, defer_threshold=learned.DEFAULT_THRESHOLD,
+                   max_defer=learned.DEFAULT_MAX_DEFER, global_relabel_every=tune["relabel_every"],
+                   stream=stream.cuda_stream)
+        b.solve(**lkw)
+        lt = []
+        for _ in range(max(1, min(args.steps, 3))):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            lst = b.solve(**lkw)
+            lt.append((time.perf_counter() - t1) * 1e3)
+        lflows = b.flow_values()
+        rec["learned"] = {"solve_ms": round(float(sorted(lt)[len(lt) // 2]), 3), "sweeps": lst["sweeps"],
+                          "region_discharges": lst["region_discharges"],
+                          "flow_equal": bool((lflows == flows).all()), "plain_ms_per_step": round(ms, 3),
+                          "plain_sweeps": st["sweeps"], "plain_region_discharges": st["region_discharges"]}
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)

@@ -458,11 +458,11 @@ static hipError_t model_forward(mf_model *m, const float *x, int xs, int D, int 
                                 int bf16, hipStream_t s) {
     const int C = m->C;
     const float *p = m->params;
-    hipError_t e = mfd::launch_conv3_fwd(x, xs, 3, p + m->off_w1, p + m->off_b1, C, m->h1, D, H, W, 1, bf16, s);
+    hipError_t e = mfd::launch_conv3_fwd(x, xs, 3, p + m->off_w1, p + m->off_b1, C, m->h1, D, H, W, 1, bf16, 1, s);
     if (e != hipSuccess) return e;
-    e = mfd::launch_conv3_fwd(m->h1, C, C, p + m->off_w2, p + m->off_b2, C, m->h2, D, H, W, 1, bf16, s);
+    e = mfd::launch_conv3_fwd(m->h1, C, C, p + m->off_w2, p + m->off_b2, C, m->h2, D, H, W, 1, bf16, 0, s);
     if (e != hipSuccess) return e;
-    return mfd::launch_conv3_fwd(m->h2, C, C, p + m->off_w3, p + m->off_b3, 1, z, D, H, W, 0, bf16, s);
+    return mfd::launch_conv3_fwd(m->h2, C, C, p + m->off_w3, p + m->off_b3, 1, z, D, H, W, 0, bf16, 0, s);
 }
 
 extern "C" mf_status mf_model_forward(mf_model *m, const float *x, int32_t xs, int32_t D, int32_t H,
@@ -746,6 +746,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                     mfd::FeatArgs FA;
                     FA.G = G; FA.ex = g->ex; FA.lab = g->lab[p]; FA.res = g->res;
                     FA.ringL = g->ringL; FA.ringM = g->ringM; FA.nring = g->nring; FA.dinf = g->dinf;
+                    FA.ringOnly = (first + j > 0) ? 1 : 0;
                     FA.out = (o.features && first + j < o.features_cap)
                                  ? o.features + (size_t)(first + j) * G.nreg * mfd::kFeat
                                  : g->feat;

@@ -44,6 +44,7 @@ struct FeatArgs {
     int nring;
     int dinf;
     float *out;  // [nreg][kFeat]
+    int ringOnly;  // read only border vertices (after the first sweep)
 };
 
 struct SchedArgs {
@@ -138,7 +139,7 @@ void set_sched_attributes();
 
 hipError_t launch_region_features(const FeatArgs &A, hipStream_t s);
 hipError_t launch_conv3_fwd(const float *x, int xs, int cin, const float *w, const float *b, int cout,
-                            float *y, int D, int H, int W, int relu, int bf16, hipStream_t s);
+                            float *y, int D, int H, int W, int relu, int bf16, int roundIn, hipStream_t s);
 hipError_t launch_conv3_bwd(const float *x, int xs, int cin, const float *w, const float *gy, int cout,
                             float *gx, float *gw, float *gb, int D, int H, int W, hipStream_t s);
 hipError_t launch_relu_bwd(float *g, const float *y, int n, hipStream_t s);

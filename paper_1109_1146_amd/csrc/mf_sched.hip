@@ -29,17 +29,29 @@ __global__ void k_region_features(FeatArgs A) {
     const int base = r * V;
     double ex_act = 0, lsum = 0, lcnt = 0, arcs = 0, open = 0, ring_clip = 0;
     int any = 0;
-    for (int l = tid; l < V; l += blockDim.x) {
-        const int e = A.ex[base + l];
-        const int d = A.lab[base + l];
-        if (e > 0 && d < A.dinf) {
-            ex_act += e;
-            any = 1;
+    // after the first sweep only border vertices can be active: every region has
+    // been discharged once, a discharge leaves no active vertex inside, and only
+    // the fusion adds excess (at border vertices); labels never decrease
+    if (!A.ringOnly) {
+        for (int l = tid; l < V; l += blockDim.x) {
+            const int e = A.ex[base + l];
+            const int d = A.lab[base + l];
+            if (e > 0 && d < A.dinf) {
+                ex_act += e;
+                any = 1;
+            }
         }
     }
     for (int i = tid; i < A.nring; i += blockDim.x) {
         const int l = A.ringL[i];
         const int d = A.lab[base + l];
+        if (A.ringOnly) {
+            const int e = A.ex[base + l];
+            if (e > 0 && d < A.dinf) {
+                ex_act += e;
+                any = 1;
+            }
+        }
         ring_clip += d < 65535 ? d : 65535;
         if (d < A.dinf) {
             lsum += d;
@@ -100,12 +112,19 @@ __device__ __forceinline__ float bf16_round(float x) {
 
 // y[v][co] = b[co] + sum_ci sum_tap w[co][ci][tap] * x[v + tap][ci]; optional ReLU;
 // bf16: weights and inputs rounded to bfloat16, products accumulated in fp32,
-// the output rounded to bfloat16.
+// the output rounded to bfloat16.  The block stages the (rounded) weights in
+// LDS; inputs already rounded by the previous layer (roundIn == 0) are used as
+// they are (rounding is idempotent).
 __global__ void k_conv3_fwd(const float *x, int xs, int cin, const float *w, const float *b, int cout,
-                            float *y, int D, int H, int W, int relu, int bf16) {
+                            float *y, int D, int H, int W, int relu, int bf16, int roundIn) {
+    extern __shared__ float wl[];  // [cout][cin][27]
+    const int nw = cout * cin * 27;
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) wl[i] = bf16 ? bf16_round(w[i]) : w[i];
+    __syncthreads();
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const int nv = D * H * W;
     if (idx >= nv * cout) return;
+    const bool rin = bf16 && roundIn;
     const int co = idx % cout, v = idx / cout;
     const int z = v / (H * W), t = v - z * H * W, yy = t / W, xx = t - yy * W;
     float acc = b[co];
@@ -120,11 +139,10 @@ __global__ void k_conv3_fwd(const float *x, int xs, int cin, const float *w, con
                 if (x2 < 0 || x2 >= W) continue;
                 const int tap = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
                 const float *xv = x + (size_t)((zz * H + y2) * W + x2) * xs;
-                const float *wv = w + (size_t)co * cin * 27 + tap;
+                const float *wv = wl + co * cin * 27 + tap;
                 for (int ci = 0; ci < cin; ci++) {
-                    float a = xv[ci], ww = wv[ci * 27];
-                    if (bf16) { a = bf16_round(a); ww = bf16_round(ww); }
-                    acc += a * ww;
+                    const float a = rin ? bf16_round(xv[ci]) : xv[ci];
+                    acc += a * wv[ci * 27];
                 }
             }
         }
@@ -230,59 +248,53 @@ __global__ void k_adam(float *p, const float *g, float *m, float *v, int n, floa
 // Queue for a learned sweep: regions sorted by score, descending, active
 // first; an active region scoring below the threshold is deferred unless it
 // was deferred max_defer times in a row.  One workgroup (bitonic sort in LDS).
+// Queue of the sweep, by counting sort over classes (largest first): regions to
+// discharge by their previous discharge time (log2 buckets, longest first),
+// then deferred regions (skipped at once), then inactive ones.  Order inside a
+// class is arbitrary; the result of a sweep does not depend on the order.
+constexpr int kQueueBuckets = 34;  // 0 inactive, 1 deferred, 2 + log2(ticks) active
+
 __global__ void k_sched_queue(SchedArgs A) {
     extern __shared__ unsigned char smem[];
+    __shared__ int hist[kQueueBuckets], off[kQueueBuckets];
     const int n = A.nreg;
-    int P = 1;
-    while (P < n) P <<= 1;
-    float *key = (float *)smem;
-    int *val = (int *)(smem + sizeof(float) * P);
-    for (int i = threadIdx.x; i < P; i += blockDim.x) {
-        if (i < n) {
-            const bool act = A.feat[(size_t)i * kFeat + 3] > 0.5f;
-            float sc = A.score[i];
-            const float prob = 1.f / (1.f + expf(-sc));
-            int d = 0;
-            if (act && prob < A.threshold && A.deferCount[i] < A.maxDefer) d = 1;
-            A.defer[i] = d;
-            A.deferCount[i] = d ? A.deferCount[i] + 1 : 0;
-            // larger = earlier: regions to discharge, longest previous discharge
-            // first (a sweep lasts as long as its slowest region), then deferred
-            // ones (skipped at once), then inactive ones
-            const float lt = (float)A.regionTicks[i];
-            key[i] = act ? (d ? 1.f + (1.f - prob) : 2.f + lt / (lt + 100000.f)) : 0.f;
-            val[i] = i;
-        } else {
-            key[i] = -1.f;
-            val[i] = -1;
+    unsigned char *cls = smem;
+    for (int i = threadIdx.x; i < kQueueBuckets; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const bool act = A.feat[(size_t)i * kFeat + 3] > 0.5f;
+        const float prob = 1.f / (1.f + expf(-A.score[i]));
+        int d = 0;
+        if (act && prob < A.threshold && A.deferCount[i] < A.maxDefer) d = 1;
+        A.defer[i] = d;
+        A.deferCount[i] = d ? A.deferCount[i] + 1 : 0;
+        int c = 0;
+        if (act) {
+            const unsigned lt = (unsigned)max(A.regionTicks[i], 0);
+            c = d ? 1 : 2 + (lt ? 32 - __clz(lt) : 0);
+        }
+        cls[i] = (unsigned char)c;
+        atomicAdd(&hist[c], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int c = kQueueBuckets - 1; c >= 0; c--) {
+            off[c] = acc;
+            acc += hist[c];
         }
     }
     __syncthreads();
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < P; i += blockDim.x) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const bool desc = (i & k) == 0;
-                    const float a = key[i], b = key[ixj];
-                    if ((desc && a < b) || (!desc && a > b)) {
-                        key[i] = b; key[ixj] = a;
-                        const int t = val[i]; val[i] = val[ixj]; val[ixj] = t;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) A.order[i] = val[i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) A.order[atomicAdd(&off[cls[i]], 1)] = i;
 }
 
 static inline int cdiv_s(long long a, int b) { return (int)((a + b - 1) / b); }
 
 hipError_t launch_conv3_fwd(const float *x, int xs, int cin, const float *w, const float *b, int cout,
-                            float *y, int D, int H, int W, int relu, int bf16, hipStream_t s) {
-    hipLaunchKernelGGL(k_conv3_fwd, dim3(cdiv_s((long long)D * H * W * cout, 256)), dim3(256), 0, s, x,
-                       xs, cin, w, b, cout, y, D, H, W, relu, bf16);
+                            float *y, int D, int H, int W, int relu, int bf16, int roundIn, hipStream_t s) {
+    const size_t lds = sizeof(float) * (size_t)cout * cin * 27;
+    hipLaunchKernelGGL(k_conv3_fwd, dim3(cdiv_s((long long)D * H * W * cout, 256)), dim3(256), lds, s, x,
+                       xs, cin, w, b, cout, y, D, H, W, relu, bf16, roundIn);
     return hipGetLastError();
 }
 
@@ -320,9 +332,7 @@ void set_sched_attributes() {
 }
 
 hipError_t launch_sched_queue(const SchedArgs &A, hipStream_t s) {
-    int P = 1;
-    while (P < A.nreg) P <<= 1;
-    const size_t lds = (size_t)P * (sizeof(float) + sizeof(int));
+    const size_t lds = (size_t)A.nreg;  // one class byte per region
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_sched_queue, dim3(1), dim3(1024), lds, s, A);
     return hipGetLastError();
