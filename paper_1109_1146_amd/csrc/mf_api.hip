@@ -29,6 +29,7 @@ struct mf_grid {
     int *pushb = nullptr, *ractive = nullptr, *order = nullptr, *bidx = nullptr;
     int *ringL = nullptr, *rvcount = nullptr, *mark = nullptr, *dirty = nullptr;
     unsigned char *ringM = nullptr, *cutbuf = nullptr, *cand = nullptr;  // cand: 2 x N
+    unsigned char *ringX = nullptr;  // per border vertex and leaving direction: region offset (2 bits per axis)
     int *in_cs = nullptr, *in_ct = nullptr, *in_nbr = nullptr;
     int *scratch = nullptr;
     int nslots = 0;
@@ -87,7 +88,7 @@ static hipError_t dalloc(T **p, size_t count) {
 
 static void free_all(mf_grid *g) {
     void *ptrs[] = {g->res, g->rt, g->ex, g->lab[0], g->lab[1], g->pushb, g->ractive, g->order,
-                    g->bidx, g->ringL, g->rvcount, g->mark, g->dirty, g->ringM, g->cutbuf,
+                    g->bidx, g->ringL, g->rvcount, g->mark, g->dirty, g->ringM, g->ringX, g->cutbuf,
                     g->in_cs, g->in_ct, g->in_nbr, g->scratch, g->act, g->qhead, g->hist,
                     g->maxlab, g->gap, g->err, g->counters, g->stats, g->sums, g->changed,
                     g->tmp_plane, g->cand};
@@ -197,15 +198,24 @@ static mf_status create_impl(int32_t ndim, const int64_t *dims, int32_t connecti
 
     // tile border ("ring"): local vertices with a direction leaving the tile
     std::vector<int> ringL;
-    std::vector<unsigned char> ringM;
+    std::vector<unsigned char> ringM, ringX;
     for (int l = 0; l < G.V; l++) {
         int lx = l % G.tx, tt = l / G.tx, ly = tt % G.ty, lz = tt / G.ty;
         unsigned m = 0;
+        unsigned char xo[mfd::kMaxK] = {0};
         for (int k = 0; k < G.K; k++) {
             int z = lz + G.oz[k], y = ly + G.oy[k], x = lx + G.ox[k];
-            if (x < 0 || x >= G.tx || y < 0 || y >= G.ty || z < 0 || z >= G.tz) m |= 1u << k;
+            if (x < 0 || x >= G.tx || y < 0 || y >= G.ty || z < 0 || z >= G.tz) {
+                m |= 1u << k;
+                auto code = [](int c, int t) { return c < 0 ? 2 : (c >= t ? 1 : 0); };
+                xo[k] = (unsigned char)(code(x, G.tx) | code(y, G.ty) << 2 | code(z, G.tz) << 4);
+            }
         }
-        if (m) { ringL.push_back(l); ringM.push_back((unsigned char)m); }
+        if (m) {
+            ringL.push_back(l);
+            ringM.push_back((unsigned char)m);
+            for (int k = 0; k < G.K; k++) ringX.push_back(xo[k]);
+        }
     }
     g->nring = (int)ringL.size();
     // boundary set B (Sec. 4.1): real vertices with a real grid neighbour in another region
@@ -261,7 +271,8 @@ static mf_status create_impl(int32_t ndim, const int64_t *dims, int32_t connecti
                 ok(dalloc(&g->ractive, (size_t)G.nreg)) && ok(dalloc(&g->order, (size_t)G.nreg)) &&
                 ok(dalloc(&g->rvcount, (size_t)G.nreg)) && ok(dalloc(&g->dirty, 2 * (size_t)G.nreg)) &&
                 ok(dalloc(&g->bidx, (size_t)g->nB)) && ok(dalloc(&g->ringL, (size_t)g->nring)) &&
-                ok(dalloc(&g->ringM, (size_t)g->nring)) && ok(dalloc(&g->cutbuf, (size_t)n)) &&
+                ok(dalloc(&g->ringM, (size_t)g->nring)) && ok(dalloc(&g->ringX, (size_t)g->nring * G.K)) &&
+                ok(dalloc(&g->cutbuf, (size_t)n)) &&
                 ok(dalloc(&g->cand, 2 * N)) &&
                 ok(dalloc(&g->in_cs, (size_t)n)) && ok(dalloc(&g->in_ct, (size_t)n)) &&
                 ok(dalloc(&g->in_nbr, K * (size_t)n)) && ok(dalloc(&g->tmp_plane, (size_t)n)) &&
@@ -283,7 +294,8 @@ static mf_status create_impl(int32_t ndim, const int64_t *dims, int32_t connecti
            ok(hipMemcpy(g->rvcount, rvcount.data(), sizeof(int) * G.nreg, hipMemcpyHostToDevice)) &&
            (bidx.empty() || ok(hipMemcpy(g->bidx, bidx.data(), sizeof(int) * bidx.size(), hipMemcpyHostToDevice))) &&
            (ringL.empty() || ok(hipMemcpy(g->ringL, ringL.data(), sizeof(int) * ringL.size(), hipMemcpyHostToDevice))) &&
-           (ringM.empty() || ok(hipMemcpy(g->ringM, ringM.data(), ringM.size(), hipMemcpyHostToDevice)));
+           (ringM.empty() || ok(hipMemcpy(g->ringM, ringM.data(), ringM.size(), hipMemcpyHostToDevice))) &&
+           (ringX.empty() || ok(hipMemcpy(g->ringX, ringX.data(), ringX.size(), hipMemcpyHostToDevice)));
     if (!good) {
         free_all(g);
         delete g;
@@ -747,6 +759,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                     FA.G = G; FA.ex = g->ex; FA.lab = g->lab[p]; FA.res = g->res;
                     FA.ringL = g->ringL; FA.ringM = g->ringM; FA.nring = g->nring; FA.dinf = g->dinf;
                     FA.ringOnly = (first + j > 0) ? 1 : 0;
+                    FA.ringX = g->ringX;
                     FA.out = (o.features && first + j < o.features_cap)
                                  ? o.features + (size_t)(first + j) * G.nreg * mfd::kFeat
                                  : g->feat;

@@ -45,6 +45,7 @@ struct FeatArgs {
     int dinf;
     float *out;  // [nreg][kFeat]
     int ringOnly;  // read only border vertices (after the first sweep)
+    const unsigned char *ringX;  // [nring][K] region offset of each leaving arc, 2 bits per axis (x, y, z)
 };
 
 struct SchedArgs {

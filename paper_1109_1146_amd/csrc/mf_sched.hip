@@ -29,6 +29,8 @@ __global__ void k_region_features(FeatArgs A) {
     const int base = r * V;
     double ex_act = 0, lsum = 0, lcnt = 0, arcs = 0, open = 0, ring_clip = 0;
     int any = 0;
+    int rz, ry, rx;
+    region_xyz(G, r, rz, ry, rx);
     // after the first sweep only border vertices can be active: every region has
     // been discharged once, a discharge leaves no active vertex inside, and only
     // the fusion adds excess (at border vertices); labels never decrease
@@ -58,11 +60,15 @@ __global__ void k_region_features(FeatArgs A) {
             lcnt += 1;
         }
         const unsigned m = A.ringM[i];
-        int lz, ly, lx;
-        local_xyz(G, l, lz, ly, lx);
         for (int k = 0; k < G.K; k++) {
             if (!((m >> k) & 1u)) continue;
-            if (cross_nbr(G, r, lz, ly, lx, k) < 0) continue;
+            // the arc counts if it leads into a region of the grid
+            const unsigned c = A.ringX[(size_t)i * G.K + k];
+            const int nx = rx + ((c & 3u) == 1u) - ((c & 3u) == 2u);
+            const int ny = ry + (((c >> 2) & 3u) == 1u) - (((c >> 2) & 3u) == 2u);
+            const int nz = rz + (((c >> 4) & 3u) == 1u) - (((c >> 4) & 3u) == 2u);
+            if ((unsigned)nx >= (unsigned)G.rx || (unsigned)ny >= (unsigned)G.ry || (unsigned)nz >= (unsigned)G.rz)
+                continue;
             arcs += 1;
             open += A.res[(size_t)k * N + base + l] > 0 ? 1 : 0;
         }

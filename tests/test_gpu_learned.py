@@ -132,3 +132,60 @@ def test_trained_network_gain_over_skeleton(mf):
     print("ablation (sweeps, region discharges):", res, flush=True)
     assert res["trained"][0] <= res["untrained"][0]
     assert res["trained"][1] < res["plain"][1]
+
+
+def _features_sweep0_reference(inst, tile):
+    """Region features at the start of sweep 0 (after Init: excess = c(s,v), all labels 0)."""
+    dims = tuple(inst.dims)
+    nd = len(dims)
+    t3 = (1,) * (3 - nd) + tuple(tile)
+    d3 = (1,) * (3 - nd) + dims
+    offs = synth.offsets_for(nd, inst.conn)
+    offs3 = [(0,) * (3 - nd) + tuple(o) for o in offs]
+    rg = tuple(-(-d // t) for d, t in zip(d3, t3))
+    cs = inst.cs.reshape(d3).astype(np.float64)
+    nbr = [inst.nbr[k].reshape(d3) for k in range(len(offs))]
+    out = np.zeros(rg + (6,))
+    for rz in range(rg[0]):
+        for ry in range(rg[1]):
+            for rx in range(rg[2]):
+                o = (rz * t3[0], ry * t3[1], rx * t3[2])
+                ex = 0.0
+                arcs = opened = 0
+                for lz in range(t3[0]):
+                    for ly in range(t3[1]):
+                        for lx in range(t3[2]):
+                            g = (o[0] + lz, o[1] + ly, o[2] + lx)
+                            real = all(a < b for a, b in zip(g, d3))
+                            if real and cs[g] > 0:
+                                ex += cs[g]
+                            for k, (dz, dy, dx) in enumerate(offs3):
+                                l2 = (lz + dz, ly + dy, lx + dx)
+                                if all(0 <= a < b for a, b in zip(l2, t3)):
+                                    continue  # stays in the tile
+                                r2 = tuple(r + (a < 0) * -1 + (a >= b) * 1 for r, a, b in zip((rz, ry, rx), l2, t3))
+                                if not all(0 <= a < b for a, b in zip(r2, rg)):
+                                    continue  # no region there
+                                arcs += 1
+                                opened += int(real and nbr[k][g] > 0)
+                out[rz, ry, rx] = (np.log1p(ex) / 8, 0.0, opened / arcs if arcs else 0.0, float(ex > 0), 0.0, ex)
+    return out.reshape(-1, 6)
+
+
+@pytest.mark.parametrize("case", ["2d", "3d_rows"])
+def test_region_features_sweep0(mf, case):
+    """Region features (the scheduler's input) at sweep 0 against a NumPy recomputation."""
+    import torch
+    if case == "2d":
+        inst = synth.random_grid((70, 90), 8, 41, tile=(32, 32))
+    else:
+        inst = synth.random_grid((6, 20, 45), 6, 42, tile=(4, 16, 32))
+    tile = inst.tile
+    ref = _features_sweep0_reference(inst, tile)
+    with mf.Grid(inst.dims, inst.conn, tile) as g:
+        g.set_caps(inst.cs, inst.ct, inst.nbr)
+        R = ref.shape[0]
+        ft = torch.zeros((64, R, mf.FEATURES), dtype=torch.float32, device="cuda")
+        g.solve(features=ft)
+        f0 = ft[0].cpu().numpy()
+    np.testing.assert_allclose(f0, ref, rtol=1e-5, atol=1e-5)
