@@ -63,6 +63,8 @@ def parse():
     p.add_argument("--relabel-every", type=int, default=None,
                    help="exact region-distance relabel every N sweeps (0 = off; default: the "
                         "workload's tuned interval)")
+    p.add_argument("--partial", action="store_true",
+                   help="partial discharges (sweep s runs only the stages k <= s of ARD)")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="only run a device-to-device copy of MIB MiB (HBM counter calibration)")
     return p.parse_args()
@@ -116,7 +118,7 @@ def bench_batch(args):
 
     def step(profile):
         st = b.solve(global_relabel_every=tune["relabel_every"], graph=not profile,
-                     profile=profile, stream=stream.cuda_stream)
+                     profile=profile, stream=stream.cuda_stream, partial=args.partial)
         flows = b.flow_values()
         cut = b.min_cut(mf.MF_CUT_MIN_SOURCE)
         return st, flows, cut
@@ -141,7 +143,8 @@ def bench_batch(args):
         "data": "synthetic",
         "config": {"workload": WORKLOADS["batch"]["desc"], "instances": len(insts), "n": total_n,
                    "canvas": list(b.dims), "region_shape": list(tune["region_shape"]),
-                   "global_relabel_every": tune["relabel_every"], "graph": True},
+                   "global_relabel_every": tune["relabel_every"], "graph": True,
+                   "partial_discharges": args.partial},
         "instances_per_s": round(len(insts) / (ms / 1e3), 1),
         "sweeps": st["sweeps"], "region_discharges": st["region_discharges"],
         "flow": int(flows.sum()),
@@ -152,23 +155,26 @@ def bench_batch(args):
     }
     # the learned schedule on the same batch (not in value): sweeps, discharges, time
     if not args.no_learned:
-        from paper_1109_1146_amd import learned
-        model = learned.load_model()
-        lkw = dict(schedule=mf.MF_SCHED_LEARNED, model=model, defer_threshold=learned.DEFAULT_THRESHOLD,
-                   max_defer=learned.DEFAULT_MAX_DEFER, global_relabel_every=tune["relabel_every"],
-                   stream=stream.cuda_stream)
-        b.solve(**lkw)
-        lt = []
-        for _ in range(max(1, min(args.steps, 3))):
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            lst = b.solve(**lkw)
-            lt.append((time.perf_counter() - t1) * 1e3)
-        lflows = b.flow_values()
-        rec["learned"] = {"solve_ms": round(float(sorted(lt)[len(lt) // 2]), 3), "sweeps": lst["sweeps"],
-                          "region_discharges": lst["region_discharges"],
-                          "flow_equal": bool((lflows == flows).all()), "plain_ms_per_step": round(ms, 3),
-                          "plain_sweeps": st["sweeps"], "plain_region_discharges": st["region_discharges"]}
+        try:
+            from paper_1109_1146_amd import learned
+            model = learned.load_model()
+            lkw = dict(schedule=mf.MF_SCHED_LEARNED, model=model, defer_threshold=learned.DEFAULT_THRESHOLD,
+                       max_defer=learned.DEFAULT_MAX_DEFER, global_relabel_every=tune["relabel_every"],
+                       stream=stream.cuda_stream, partial=args.partial)
+            b.solve(**lkw)
+            lt = []
+            for _ in range(max(1, min(args.steps, 3))):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                lst = b.solve(**lkw)
+                lt.append((time.perf_counter() - t1) * 1e3)
+            lflows = b.flow_values()
+            rec["learned"] = {"solve_ms": round(float(sorted(lt)[len(lt) // 2]), 3), "sweeps": lst["sweeps"],
+                              "region_discharges": lst["region_discharges"],
+                              "flow_equal": bool((lflows == flows).all()), "plain_ms_per_step": round(ms, 3),
+                              "plain_sweeps": st["sweeps"], "plain_region_discharges": st["region_discharges"]}
+        except (OSError, ValueError, mf.MFError) as e:  # no trained model, or a schedule limit
+            rec["learned"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
@@ -223,7 +229,7 @@ def main():
 
     def step(profile):
         st = g.solve(stream=stream.cuda_stream, profile=profile,
-                     global_relabel_every=args.relabel_every)
+                     global_relabel_every=args.relabel_every, partial=args.partial)
         cut = g.min_cut(mf.MF_CUT_MIN_SOURCE)
         return st, cut
 
@@ -268,7 +274,7 @@ def main():
         "config": {"workload": wl["desc"], "n": inst.n, "regions": info["regions"],
                    "region_shape": list(info["region_shape"]), "boundary_size": info["boundary_size"],
                    "schedule": "P-ARD", "connectivity": inst.conn,
-                   "global_relabel_every": args.relabel_every},
+                   "global_relabel_every": args.relabel_every, "partial_discharges": args.partial},
         "sweeps": stats[-1]["sweeps"],
         "region_discharges": stats[-1]["region_discharges"],
         "flow": flow,
@@ -294,7 +300,7 @@ def main():
         model = learned.load_model()
         lkw = dict(schedule=mf.MF_SCHED_LEARNED, model=model, defer_threshold=learned.DEFAULT_THRESHOLD,
                    max_defer=learned.DEFAULT_MAX_DEFER, global_relabel_every=args.relabel_every,
-                   stream=stream.cuda_stream)
+                   stream=stream.cuda_stream, partial=args.partial)
         g.solve(**lkw)
         times = []
         for _ in range(max(1, min(args.steps, 3))):

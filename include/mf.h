@@ -65,7 +65,8 @@ enum {
     MF_SCHED_PARD = 0,    /* Alg. 2: all active regions against the previous sweep's labels */
     MF_SCHED_COLORED = 1, /* Alg. 1 as phases of non-interacting regions (reserved) */
     MF_SCHED_LEARNED = 2, /* deferral from a trained scorer (opts->model); the regions to
-                             discharge are queued longest previous discharge first */
+                             discharge are queued longest previous discharge first; at most
+                             65536 regions, else MF_E_INVAL */
     MF_SCHED_AUTO = 3     /* library's choice (currently MF_SCHED_PARD) */
 };
 
@@ -95,6 +96,11 @@ typedef struct {
     float *features;              /* device buffer [features_cap][regions][MF_FEATURES] or NULL:
                                      the scheduler's region features at the start of each sweep */
     int64_t features_cap;         /* sweeps the features buffer holds */
+    int32_t partial;              /* 1 = partial discharges (Sec. 6.2): in sweep s a region discharge
+                                     runs only the stages k <= s of Proc. ARD (sweep 0 augments to
+                                     t only), the region relabel stays complete, and excess the cap
+                                     holds back stays active for later sweeps; the flow and cuts are
+                                     the same, sweeps can be more and cheaper.  0 = off */
 } mf_solve_opts;
 
 /* region features (floats) written per region and sweep, see mf_solve_opts.features */

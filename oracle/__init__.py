@@ -64,7 +64,7 @@ def _load():
         lib.orc_cuts.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P, P, P, P, P]
         lib.orc_cuts.restype = ctypes.c_int
         lib.orc_ard.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P, P, P, P,
-                                ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                 P, P, P, P, P, P, P, P, P, P, P]
         lib.orc_ard.restype = ctypes.c_int
         _lib = lib
@@ -172,8 +172,16 @@ def cuts_of_state(n, pu, pv, r_uv, r_vu, rt, ex):
 
 
 def ard_pairs(n, pu, pv, cuv, cvu, cs, ct, region, parallel=True, checks=CHK_ALL,
-              max_sweeps=None):
+              max_sweeps=None, partial=False, stop_early=False):
+    """Reference ARD.  With partial=True sweep s runs only the stages k <= s
+    (partial discharges, Sec. 6.2): excess may then stay inside a region, so the
+    checks that only boundary vertices are active after the first sweep and that
+    a discharge leaves no active vertex do not apply and are dropped.  With
+    stop_early, reaching max_sweeps returns the state after that many sweeps
+    (complete=False) instead of raising."""
     lib = _load()
+    if partial:
+        checks &= ~(CHK_ACTIVE_B | CHK_DISCHARGE)
     pu, pv, cuv, cvu, cs, ct, region = map(_c32, (pu, pv, cuv, cvu, cs, ct, region))
     m = pu.shape[0]
     r_uv = np.zeros(m, dtype=np.int64)
@@ -190,23 +198,29 @@ def ard_pairs(n, pu, pv, cuv, cvu, cs, ct, region, parallel=True, checks=CHK_ALL
     if max_sweeps is None:
         max_sweeps = (1 << 62)
     rc = lib.orc_ard(n, m, _p(pu), _p(pv), _p(cuv), _p(cvu), _p(cs), _p(ct), _p(region),
-                     1 if parallel else 0, int(max_sweeps), int(checks), _p(r_uv), _p(r_vu),
+                     1 if parallel else 0, 1 if partial else 0, int(max_sweeps), int(checks),
+                     _p(r_uv), _p(r_vu),
                      _p(rt), _p(ex), _p(flow), _p(smin), _p(smax), _p(labels), _p(sweeps),
                      _p(bsize), _p(failed))
     if rc == 3:
         raise AssertionError(f"reference ARD invariant check {int(failed[0])} failed")
+    if rc == 4 and stop_early:
+        # max_sweeps sweeps ran and active vertices remain: the state at that point, no cuts
+        return dict(flow=int(flow[0]), r_uv=r_uv, r_vu=r_vu, rt=rt, ex=ex, labels=labels,
+                    sweeps=int(sweeps[0]), bsize=int(bsize[0]), complete=False)
     if rc != 0:
         raise RuntimeError(f"orc_ard failed with code {rc}")
     return dict(flow=int(flow[0]), smin=smin, smax=smax, r_uv=r_uv, r_vu=r_vu, rt=rt, ex=ex,
-                labels=labels, sweeps=int(sweeps[0]), bsize=int(bsize[0]))
+                labels=labels, sweeps=int(sweeps[0]), bsize=int(bsize[0]), complete=True)
 
 
-def ard_grid(inst, tile=None, parallel=True, checks=CHK_ALL, max_sweeps=None):
+def ard_grid(inst, tile=None, parallel=True, checks=CHK_ALL, max_sweeps=None, partial=False,
+             stop_early=False):
     tile = tuple(tile if tile is not None else inst.tile)
     pu, pv, cuv, cvu = grid_pairs(inst.dims, inst.nbr, _offsets(inst))
     region = grid_regions(inst.dims, tile)
     out = ard_pairs(inst.n, pu, pv, cuv, cvu, inst.cs, inst.ct, region, parallel=parallel,
-                    checks=checks, max_sweeps=max_sweeps)
+                    checks=checks, max_sweeps=max_sweeps, partial=partial, stop_early=stop_early)
     out["pairs"] = (pu, pv, cuv, cvu)
     return out
 

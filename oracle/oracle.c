@@ -21,7 +21,8 @@
  *                    (P-ARD, label and flow fusion), Proc. ARD with Augment
  *                    (Sec. 4.2), region relabel (Alg. 3, ARD variant) and the
  *                    global gap heuristic (Sec. 5.1) over boundary labels, with
- *                    optional per-sweep checks of the statements of Sec. 4.
+ *                    optional per-sweep checks of the statements of Sec. 4;
+ *                    optionally with partial discharges (Sec. 6.2).
  *
  * Input network format (all entry points): n non-terminal vertices 0..n-1 and
  * np vertex pairs {pu[i], pv[i]} with capacities c(pu,pv)=cuv[i] and
@@ -649,8 +650,10 @@ static int cmp_i32(const void *a, const void *b) {
 /* Proc. ARD: stages k in {0} u {d(w)+1 : w in B^R, d(w) < dinf}, ascending (the
  * targets T_k only change at these values), then region relabel.  dold holds
  * the labels the discharge reads (boundary labels stay fixed).  Pushes over
- * outgoing boundary arcs are accumulated in A->push. */
-static int64_t ard_discharge(ard_t *A, int32_t rk, const int32_t *dold) {
+ * outgoing boundary arcs are accumulated in A->push.  Stages above cap are not
+ * run (partial discharge, Sec. 6.2: cap = the sweep index); the region relabel
+ * is always complete. */
+static int64_t ard_discharge(ard_t *A, int32_t rk, const int32_t *dold, int32_t cap) {
     net_t *g = A->g;
     int64_t lo = A->first_r[rk], hi = A->first_r[rk + 1];
     int64_t cnt = 0;
@@ -673,6 +676,7 @@ static int64_t ard_discharge(ard_t *A, int32_t rk, const int32_t *dold) {
     int64_t to_t = 0;
     for (int64_t i = 0; i < nl; i++) {
         if (i > 0 && lv[i] == lv[i - 1]) continue;
+        if (lv[i] > cap) break;
         to_t += ard_augment(A, rk, lv[i], dold);
     }
     free(lv);
@@ -762,7 +766,8 @@ static int ard_valid(const ard_t *A, const int32_t *d) {
 
 int orc_ard(int32_t n, int64_t np, const int32_t *pu, const int32_t *pv, const int32_t *cuv,
             const int32_t *cvu, const int32_t *cs, const int32_t *ct, const int32_t *region,
-            int32_t parallel, int64_t max_sweeps, int32_t checks, int64_t *r_uv, int64_t *r_vu,
+            int32_t parallel, int32_t partial, int64_t max_sweeps, int32_t checks, int64_t *r_uv,
+            int64_t *r_vu,
             int64_t *rt_out, int64_t *ex_out, int64_t *flow_out, uint8_t *smin, uint8_t *smax,
             int32_t *labels_out, int64_t *sweeps_out, int64_t *bsize_out, int32_t *failed_check) {
     net_t g;
@@ -827,7 +832,14 @@ int orc_ard(int32_t n, int64_t np, const int32_t *pu, const int32_t *pv, const i
         for (int32_t v = 0; v < n && !any_active; v++)
             if (A.ex[v] > 0 && A.d[v] < A.dinf) any_active = 1;
         if (!any_active) break;
-        if (sweeps >= max_sweeps) { rc = ORC_ESWEEPS; goto done; }
+        if (sweeps >= max_sweeps) {
+            /* stopped early: the state after max_sweeps sweeps (no cuts) */
+            if (sweeps_out) *sweeps_out = sweeps;
+            if (labels_out) memcpy(labels_out, A.d, sizeof(int32_t) * (size_t)n);
+            write_outputs(&g, np, A.rt, A.ex, ct, r_uv, r_vu, rt_out, ex_out, flow_out);
+            rc = ORC_ESWEEPS;
+            goto done;
+        }
         if (sweeps > 0 && (checks & ORC_CHK_ACTIVE_B)) {
             for (int32_t v = 0; v < n; v++)
                 if (A.ex[v] > 0 && A.d[v] < A.dinf && !A.inB[v]) {
@@ -835,6 +847,8 @@ int orc_ard(int32_t n, int64_t np, const int32_t *pu, const int32_t *pv, const i
                 }
         }
         memcpy(dprev, A.d, sizeof(int32_t) * nn);
+        /* partial discharges: sweep s runs stages up to s only */
+        const int32_t cap = partial ? (int32_t)(sweeps < INT32_MAX ? sweeps : INT32_MAX) : INT32_MAX;
         sweeps++;
         if (parallel) {
             /* Alg. 2: all regions discharge against the labels of the sweep start */
@@ -847,7 +861,7 @@ int orc_ard(int32_t n, int64_t np, const int32_t *pu, const int32_t *pv, const i
                     if (A.ex[v] > 0 && dsnap[v] < A.dinf) { has_active = 1; break; }
                 }
                 if (!has_active) continue; /* a region with no active vertex is skipped */
-                ard_discharge(&A, rk, dsnap);
+                ard_discharge(&A, rk, dsnap, cap);
                 for (int64_t i = A.first_r[rk]; i < A.first_r[rk + 1]; i++) {
                     int32_t v = A.members[i];
                     A.d[v] = A.newd[v]; /* fuse labels */
@@ -881,7 +895,7 @@ int orc_ard(int32_t n, int64_t np, const int32_t *pu, const int32_t *pv, const i
                 }
                 if (!has_active) continue;
                 memset(A.push, 0, sizeof(int64_t) * (size_t)(g.m ? g.m : 1));
-                ard_discharge(&A, rk, A.d);
+                ard_discharge(&A, rk, A.d, cap);
                 for (int64_t i = A.first_r[rk]; i < A.first_r[rk + 1]; i++) {
                     int32_t v = A.members[i];
                     A.d[v] = A.newd[v];

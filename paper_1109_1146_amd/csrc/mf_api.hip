@@ -599,7 +599,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     if (o.schedule == MF_SCHED_COLORED) return MF_E_INVAL;
     const bool learned = o.schedule == MF_SCHED_LEARNED;
     mf_model *model = (mf_model *)o.model;
-    if (learned && (!model || g->G.nreg > 16384)) return MF_E_INVAL;
+    // the scheduler's queue kernel keeps one class byte per region in LDS
+    if (learned && (!model || g->G.nreg > 65536)) return MF_E_INVAL;
     const bool feats = learned || (o.features && o.features_cap > 0);
     if (feats) {
         const size_t R = (size_t)g->G.nreg;
@@ -613,6 +614,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     if (feats) o.graph = 0;
     int check_every = o.check_every > 0 ? o.check_every : 8;
     if (o.global_relabel_every < 0) return MF_E_INVAL;
+    if (o.partial != 0 && o.partial != 1) return MF_E_INVAL;
     if (o.global_relabel_every > 0) check_every = o.global_relabel_every;
     long long B = g->nB > 0 ? g->nB : 1;
     long long bound = (B > 2000000000LL) ? (1LL << 62) : 2 * B * B + 1;
@@ -658,6 +660,9 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     D.maxIter = 1 << 18;
     D.trace = o.trace;
     D.traceCap = o.trace ? o.trace_cap : 0;
+    D.partial = o.partial;
+    D.sweepCount = g->counters;
+    D.actCarry = o.partial ? g->counters + 1 : nullptr;
     size_t lds = g->useLDS ? (size_t)16 * G.V : 0;
     // Region kernels: a single wavefront with row bitmasks for 2D regions of
     // at most 64 x 64 (WAVE), one workgroup with the whole region in LDS
@@ -721,6 +726,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     mfd::GapArgs P;
     P.hist = g->hist; P.maxlab = g->maxlab; P.gap = g->gap; P.gapOn = o.gap ? 1 : 0;
     P.counters = g->counters;
+    P.actCarry = D.actCarry;
 
     mfd::GapApplyArgs Q;
     memset(&Q, 0, sizeof(Q));
@@ -758,7 +764,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                     mfd::FeatArgs FA;
                     FA.G = G; FA.ex = g->ex; FA.lab = g->lab[p]; FA.res = g->res;
                     FA.ringL = g->ringL; FA.ringM = g->ringM; FA.nring = g->nring; FA.dinf = g->dinf;
-                    FA.ringOnly = (first + j > 0) ? 1 : 0;
+                    // with partial discharges excess can stay inside a region
+                    FA.ringOnly = (first + j > 0 && !o.partial) ? 1 : 0;
                     FA.ringX = g->ringX;
                     FA.out = (o.features && first + j < o.features_cap)
                                  ? o.features + (size_t)(first + j) * G.nreg * mfd::kFeat
@@ -806,7 +813,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
             // the graph is rebuilt when their order changed)
             const long long key = ((long long)check_every << 8) | (o.gap ? 1 : 0) << 1 |
                                   (long long)(regionMode << 2) | (long long)(regionNarrow << 4) |
-                                  (long long)((g->lab[0] < g->lab[1]) ? 1 : 0) << 6;
+                                  (long long)((g->lab[0] < g->lab[1]) ? 1 : 0) << 6 |
+                                  (long long)(o.partial ? 1 : 0) << 7;
             if (!g->graph_exec || g->graph_key != key) {
                 if (g->graph_exec) { (void)hipGraphExecDestroy(g->graph_exec); g->graph_exec = nullptr; }
                 hipGraph_t graph = nullptr;

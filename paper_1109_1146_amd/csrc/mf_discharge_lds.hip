@@ -112,6 +112,7 @@ __global__ __launch_bounds__(NT) void k_discharge_lds(DischargeArgs A) {
     __shared__ int s_wmin[NT / 64];
     __shared__ long long s_tr[4];  // excess in, to sink, to boundary, label sum
     if (*A.actIn == 0ull) return;
+    const int stageCap = stage_cap(A);
     const Geo &G = A.G;
     const int V = G.V, N = G.N, tid = threadIdx.x, nring = A.nring;
     const LdsLayout L = lds_layout(V, K, nring, (int)sizeof(RT));
@@ -147,8 +148,12 @@ __global__ __launch_bounds__(NT) void k_discharge_lds(DischargeArgs A) {
         if (tid == 0) {
             s_active = A.ractive[r];
             // a deferred region keeps its flag and is discharged in a later sweep
-            if (s_active && A.defer && A.defer[r]) s_active = 0;
-            else A.ractive[r] = 0;
+            if (s_active && A.defer && A.defer[r]) {
+                s_active = 0;
+                if (A.actCarry) atomicAdd(A.actCarry, 1ull);  // still active
+            } else {
+                A.ractive[r] = 0;
+            }
         }
         __syncthreads();
         if (!s_active) {
@@ -189,8 +194,12 @@ __global__ __launch_bounds__(NT) void k_discharge_lds(DischargeArgs A) {
         int iter = 0;
         long long bfs_steps = 0, classes = 0, t_search = 0, t_push = 0, t_setup = 0, t_flood = 0;
         int nsteps = 0;
+        // partial discharge: the searches of the push rounds stop at the stage
+        // cap; the labels come from a complete search (full)
+        bool full = !A.partial;
         for (;;) {
             const long long t_round = wall_clock64();
+            bool capped = false;
             // ---------------- multi-level search from the targets ----------------
             // Every thread keeps identical copies of qtail / nsteps / fs; new
             // vertices of step st are appended through counter s_cnt[st % 3], so
@@ -300,6 +309,10 @@ __global__ __launch_bounds__(NT) void k_discharge_lds(DischargeArgs A) {
                 __syncthreads();
                 const int level = s_min;
                 if (level == kInf) break;
+                if (!full && level > stageCap) {
+                    capped = true;
+                    break;
+                }
                 classes++;
                 {
                     const int st = nsteps;
@@ -341,7 +354,22 @@ __global__ __launch_bounds__(NT) void k_discharge_lds(DischargeArgs A) {
             __syncthreads();
             const long long t_mid = wall_clock64();
             t_search += t_mid - t_round;
-            if (!s_found) break;
+            if (!s_found) {
+                if (capped) {
+                    full = true;  // search again, complete, for the region relabel
+                    continue;
+                }
+                break;
+            }
+            if (full && A.partial) {
+                // complete search after capped rounds: the excess it reaches lies
+                // beyond the cap and stays; the region stays active
+                if (tid == 0) {
+                    A.ractive[r] = 1;
+                    atomicAdd(A.actCarry, 1ull);
+                }
+                break;
+            }
             if (++iter > A.maxIter) {
                 if (tid == 0) atomicOr(A.err, 4);
                 break;

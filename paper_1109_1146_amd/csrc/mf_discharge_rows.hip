@@ -167,6 +167,7 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
     __shared__ int s_r, s_active;
     __shared__ long long s_tr[4];  // trace: excess out, to sink, to boundary, label sum
     if (*A.actIn == 0ull) return;
+    const int stageCap = stage_cap(A);
     const int V = A.G.V, N = A.G.N, TY = A.G.ty, TZ = A.G.tz, R = TY * TZ;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const RowsLayout L = rows_layout(R, TY, TZ, A.nring);
@@ -208,8 +209,12 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
             s_active = A.ractive[r];
             // a deferred region keeps its flag and is discharged in a later sweep;
             // with deferRelabel it runs its region relabel now (s_active 2)
-            if (s_active && A.defer && A.defer[r]) s_active = A.deferRelabel ? 2 : 0;
-            else A.ractive[r] = 0;
+            if (s_active && A.defer && A.defer[r]) {
+                s_active = A.deferRelabel ? 2 : 0;
+                if (!s_active && A.actCarry) atomicAdd(A.actCarry, 1ull);  // still active
+            } else {
+                A.ractive[r] = 0;
+            }
         }
         __syncthreads();
         if (!s_active) {
@@ -360,7 +365,8 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
                     cand = min(cand, c);
                 }
                 const int level = block_min(cand, red, rc);
-                if (level == kInf) {
+                // partial discharge: stages above the cap wait for later sweeps
+                if (level == kInf || (level > stageCap && !writeMode)) {
                     t_stage += wall_clock64() - t1f;
                     break;
                 }
@@ -397,6 +403,11 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
             t_search += t1s - t0s;
             if (writeMode) {
                 if (myrow) store_labels(A.labNew, rowBase, ~vis, dinf);
+                // excess left beyond the stage cap: the region stays active
+                if (found && A.actCarry && tid == 0) {
+                    A.ractive[r] = 1;
+                    atomicAdd(A.actCarry, 1ull);
+                }
                 break;
             }
             if (!found) {

@@ -157,6 +157,7 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
     __shared__ long long s_tr[4];
     __shared__ u64 seedRows[64];
     if (*A.actIn == 0ull) return;
+    const int stageCap = stage_cap(A);
     const Geo &G = A.G;
     const int V = G.V, N = G.N, nring = A.nring;
     const int TX = G.tx, TY = G.ty;
@@ -217,8 +218,12 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
             active = A.ractive[r];
             // a deferred region keeps its flag and is discharged in a later sweep;
             // with deferRelabel it runs its region relabel now (active 2)
-            if (active && A.defer && A.defer[r]) active = A.deferRelabel ? 2 : 0;
-            else A.ractive[r] = 0;
+            if (active && A.defer && A.defer[r]) {
+                active = A.deferRelabel ? 2 : 0;
+                if (!active && A.actCarry) atomicAdd(A.actCarry, 1ull);  // still active
+            } else {
+                A.ractive[r] = 0;
+            }
         }
         active = __shfl(active, 0, 64);
         if (!active) {
@@ -347,7 +352,8 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
                     }
                 }
                 const int level = wave_min_int(best);
-                if (level == kInf) break;
+                // partial discharge: stages above the cap wait for later sweeps
+                if (level == kInf || (level > stageCap && !writeMode)) break;
                 stages++;
                 stage = level;
 #pragma unroll
@@ -381,6 +387,11 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
             const bool found = __ballot((EXm & VIS) != 0ull) != 0ull;
             if (writeMode) {
                 if (myrow) store_row_labels(A.labNew, rowBase, ~VIS & rowmask, dinf);
+                // excess left beyond the stage cap: the region stays active
+                if (found && A.actCarry && lane == 0) {
+                    A.ractive[r] = 1;
+                    atomicAdd(A.actCarry, 1ull);
+                }
                 break;
             }
             if (!found) {

@@ -145,6 +145,7 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
     __shared__ int s_wmin[NT / 64];
     __shared__ long long s_tr[4];  // trace: excess out, to sink, to boundary, label sum
     if (*A.actIn == 0ull) return;
+    const int stageCap = stage_cap(A);
     const Geo &G = A.G;
     const int V = G.V, N = G.N, tid = threadIdx.x;
     int *S, *Q, *stepEnd, *stepLevel;
@@ -172,8 +173,12 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
         if (tid == 0) {
             s_active = A.ractive[r];
             // a deferred region keeps its flag and is discharged in a later sweep
-            if (s_active && A.defer && A.defer[r]) s_active = 0;
-            else A.ractive[r] = 0;
+            if (s_active && A.defer && A.defer[r]) {
+                s_active = 0;
+                if (A.actCarry) atomicAdd(A.actCarry, 1ull);  // still active
+            } else {
+                A.ractive[r] = 0;
+            }
         }
         __syncthreads();
         if (!s_active) {
@@ -187,7 +192,11 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
         long long bfs_steps = 0, classes = 0;
         const long long t_start = wall_clock64();
         if (tid < 4) s_tr[tid] = 0;
+        // partial discharge: the searches of the push rounds stop at the stage
+        // cap; the labels come from a complete search (full)
+        bool full = !A.partial;
         for (;;) {
+            bool capped = false;
             // ---------------- multi-level search from the targets ----------------
             for (int l = tid; l < V; l += NT) S[l] = kInf;
             if (tid == 0) {
@@ -265,6 +274,10 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
                 __syncthreads();
                 const int level = s_min;
                 if (level == kInf) break;
+                if (!full && level > stageCap) {
+                    capped = true;
+                    break;
+                }
                 classes++;
                 const int step = s_nsteps;
                 for (int i = tid; i < A.nring; i += NT) {
@@ -302,7 +315,22 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
                 if (S[l] != kInf && ex[base + l] > 0) found = 1;
             if (found) s_found = 1;
             __syncthreads();
-            if (!s_found) break;
+            if (!s_found) {
+                if (capped) {
+                    full = true;  // search again, complete, for the region relabel
+                    continue;
+                }
+                break;
+            }
+            if (full && A.partial) {
+                // complete search after capped rounds: the excess it reaches lies
+                // beyond the cap and stays; the region stays active
+                if (tid == 0) {
+                    A.ractive[r] = 1;
+                    atomicAdd(A.actCarry, 1ull);
+                }
+                break;
+            }
             if (++iter > A.maxIter) {
                 if (tid == 0) atomicOr(A.err, 4);
                 break;
@@ -499,7 +527,14 @@ __global__ void k_gap_find(GapArgs A) {
         int b = kInf;
         for (int w = 0; w < (int)(blockDim.x >> 6); w++) b = min(b, s_wmin[w]);
         *A.gap = (b == kInf) ? -1 : b;
-        *A.actOut = 0ull;
+        // the boundary kernel adds the active boundary vertices; regions that a
+        // partial discharge left active come from the carry
+        if (A.actCarry) {
+            *A.actOut = *A.actCarry;
+            *A.actCarry = 0ull;
+        } else {
+            *A.actOut = 0ull;
+        }
         *A.qheadNext = 0u;
         *A.maxlab = -1;
         A.counters[0] += 1ull;  // sweeps

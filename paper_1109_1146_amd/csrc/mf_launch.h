@@ -32,7 +32,22 @@ struct DischargeArgs {
     const int *defer;    // optional: 1 = an active region is deferred this sweep (keeps its flag)
     int *regionTicks;    // optional: duration of each region's last discharge (100 MHz ticks)
     int deferRelabel;    // a deferred region runs its region relabel only (rows and wave kernels)
+    // Partial discharges (Sec. 6.2): sweep s runs only the stages k <= s, s read
+    // from sweepCount (the completed sweeps, so a captured graph replays it
+    // right); the region relabel stays complete.  Excess may then stay inside a
+    // region: such a region keeps its flag and counts itself in actCarry, which
+    // the sweep's gap kernel moves into the next sweep's active count.
+    int partial;
+    const unsigned long long *sweepCount;
+    unsigned long long *actCarry;  // null unless partial
 };
+
+// stage cap of a discharge launch (no cap: INT_MAX)
+__device__ __forceinline__ int stage_cap(const DischargeArgs &A) {
+    if (!A.partial) return 0x7fffffff;
+    const unsigned long long s = *A.sweepCount;
+    return s < 0x7fffffffull ? (int)s : 0x7fffffff;
+}
 
 constexpr int kFeat = 6;  // floats per region in the scheduler features
 
@@ -79,6 +94,7 @@ struct GapArgs {
     unsigned long long *actOut;
     unsigned int *qheadNext;
     unsigned long long *counters;  // [0] sweeps
+    unsigned long long *actCarry;  // partial discharges: regions left active, or null
 };
 
 struct GapApplyArgs {

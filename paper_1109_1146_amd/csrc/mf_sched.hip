@@ -339,7 +339,7 @@ void set_sched_attributes() {
 
 hipError_t launch_sched_queue(const SchedArgs &A, hipStream_t s) {
     const size_t lds = (size_t)A.nreg;  // one class byte per region
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    if (lds > 64 * 1024) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_sched_queue, dim3(1), dim3(1024), lds, s, A);
     return hipGetLastError();
 }

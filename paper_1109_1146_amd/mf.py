@@ -41,7 +41,7 @@ class mf_solve_opts(ctypes.Structure):
                 ("trace_cap", ctypes.c_int64), ("graph", ctypes.c_int32),
                 ("max_defer", ctypes.c_int32), ("defer_threshold", ctypes.c_float),
                 ("defer_mode", ctypes.c_int32), ("features", ctypes.c_void_p),
-                ("features_cap", ctypes.c_int64)]
+                ("features_cap", ctypes.c_int64), ("partial", ctypes.c_int32)]
 
 
 class mf_solve_stats(ctypes.Structure):
@@ -229,8 +229,9 @@ class Grid:
     def solve(self, schedule=MF_SCHED_PARD, gap=True, global_relabel_every=0, check_every=0,
               max_sweeps=0, stream=None, profile=False, region_kernel=MF_KERNEL_AUTO,
               trace=None, graph=False, model=None, max_defer=0, defer_threshold=0.0,
-              features=None, defer_mode=0):
-        """trace: optional int32 device tensor of shape (cap, TRACE_FIELDS)."""
+              features=None, defer_mode=0, partial=False):
+        """trace: optional int32 device tensor of shape (cap, TRACE_FIELDS);
+        partial: partial discharges (sweep s runs the stages k <= s only)."""
         tptr, tcap = None, 0
         if trace is not None:
             tptr, tcap = trace.data_ptr(), int(trace.shape[0])
@@ -243,7 +244,7 @@ class Grid:
                           region_kernel=region_kernel, trace=tptr, trace_cap=tcap,
                           graph=1 if graph else 0, max_defer=max_defer,
                           defer_threshold=defer_threshold, defer_mode=defer_mode, features=fptr,
-                          features_cap=fcap)
+                          features_cap=fcap, partial=1 if partial else 0)
         if model is not None:
             o.model = model._h
         s = mf_solve_stats()

@@ -66,3 +66,28 @@ def test_no_cpu_fallback_when_library_missing(tmp_path):
             mf.load(str(tmp_path / "nope.so"))
     finally:
         mf._lib = saved
+
+
+def _c_layout(tmp_path, struct, fields):
+    """offsetof of each field and sizeof of a struct of include/mf.h, by gcc."""
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mf.h"', 'int main(void) {']
+    for f in fields:
+        lines.append(f'    printf("%zu\\n", offsetof({struct}, {f}));')
+    lines += [f'    printf("%zu\\n", sizeof({struct}));', '    return 0;', '}']
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    return [int(x) for x in out]
+
+
+@pytest.mark.parametrize("name", ["mf_solve_opts", "mf_solve_stats"])
+def test_binding_structs_match_the_header(tmp_path, name):
+    """The ctypes structures of the binding have the C layout of include/mf.h."""
+    from paper_1109_1146_amd import mf
+    cls = getattr(mf, name)
+    fields = [f[0] for f in cls._fields_]
+    c = _c_layout(tmp_path, name, fields)
+    py = [getattr(cls, f).offset for f in fields] + [ctypes.sizeof(cls)]
+    assert c == py, dict(zip(fields + ["sizeof"], zip(c, py)))

@@ -189,3 +189,11 @@ def test_region_features_sweep0(mf, case):
         g.solve(features=ft)
         f0 = ft[0].cpu().numpy()
     np.testing.assert_allclose(f0, ref, rtol=1e-5, atol=1e-5)
+
+
+def test_learned_schedule_many_regions(mf):
+    """More than 16384 regions (tiny tiles): the scheduler's queue and the CNN
+    cover the whole region grid; the result is the oracle's."""
+    inst = synth.random_grid((300, 300), 4, 77, tile=(2, 2))
+    model = mf.Model(16, seed=2)
+    _exact(mf, inst, schedule=mf.MF_SCHED_LEARNED, model=model, defer_threshold=0.5, max_defer=1)

@@ -225,3 +225,62 @@ def test_reference_ard_boundary_size_closed_form():
             inner *= int((~edge).sum())
         assert a["bsize"] == int(np.prod(dims)) - inner
     assert oracle.ard_grid(synth.config(0), checks=0)["bsize"] == 252
+
+
+# ---------------------------------------------------------------------------
+# Partial discharges (Sec. 6.2): sweep s runs only the stages k <= s
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(24))
+def test_reference_ard_partial_exact_and_invariants(seed):
+    """Same flow and cuts as the textbook solvers; the labeling stays valid,
+    monotone and below the exact region distance after every sweep."""
+    dims, conn, tile = CASES[seed % len(CASES)]
+    inst = synth.random_grid(dims, conn, 300 + seed, tile=tile)
+    r = oracle.solve_grid(inst)
+    for parallel in (True, False):
+        a = oracle.ard_grid(inst, parallel=parallel, checks=oracle.CHK_ALL, partial=True)
+        assert a["flow"] == r["flow"]
+        assert (a["smin"] == r["smin"]).all() and (a["smax"] == r["smax"]).all()
+        # the cap reaches d_inf after d_inf sweeps, from there on the sweeps are full
+        B = max(a["bsize"], 1)
+        assert a["sweeps"] <= B + 2 * B ** 2 + 1
+        pu, pv, cuv, cvu = a["pairs"]
+        oracle.certify(inst.n, pu, pv, cuv, cvu, inst.cs, inst.ct, a["r_uv"], a["r_vu"],
+                       a["rt"], a["ex"], a["flow"], a["smin"], a["smax"])
+
+
+def _region_flow_sum(inst, tile):
+    """Sum over regions of the max flow of the region alone (its inner pairs and
+    its t-links; pairs to other regions dropped), by the textbook solver."""
+    pu, pv, cuv, cvu = oracle.grid_pairs(inst.dims, inst.nbr, oracle._offsets(inst))
+    region = oracle.grid_regions(inst.dims, tile)
+    total = 0
+    for rk in np.unique(region):
+        vs = np.flatnonzero(region == rk)
+        idx = -np.ones(inst.n, np.int64)
+        idx[vs] = np.arange(len(vs))
+        keep = (region[pu] == rk) & (region[pv] == rk)
+        total += oracle.solve_pairs(len(vs), idx[pu[keep]], idx[pv[keep]], cuv[keep], cvu[keep],
+                                    inst.cs[vs], inst.ct[vs])["flow"]
+    return total
+
+
+def test_reference_ard_partial_first_sweep_is_regionwise_maxflow():
+    """With partial discharges sweep 0 runs stage 0 only: paths to the sink.
+    No flow crosses a region border, and the flow after the sweep is the sum of
+    the regions' own max flows.  Without the cap some flow does cross."""
+    crossed_full = 0
+    for seed in range(8):
+        dims, conn, tile = CASES[seed % len(CASES)]
+        inst = synth.random_grid(dims, conn, 400 + seed, tile=tile)
+        pu, pv, cuv, cvu = oracle.grid_pairs(inst.dims, inst.nbr, oracle._offsets(inst))
+        region = oracle.grid_regions(inst.dims, tile)
+        cross = region[pu] != region[pv]
+        a = oracle.ard_grid(inst, partial=True, max_sweeps=1, stop_early=True)
+        assert a["sweeps"] == 1
+        assert (a["r_uv"][cross] == cuv[cross]).all() and (a["r_vu"][cross] == cvu[cross]).all()
+        assert a["flow"] == _region_flow_sum(inst, tile)
+        f = oracle.ard_grid(inst, partial=False, max_sweeps=1, stop_early=True)
+        crossed_full += int((f["r_uv"][cross] != cuv[cross]).any())
+    assert crossed_full > 0
