@@ -41,10 +41,10 @@ def measured_traffic(kernel_src, summary):
     return float(rec["traffic_bytes_per_launch"])
 
 WORKLOADS = {
-    "2d": dict(cfg=1, tag="grid2d8_2048", relabel=10, desc="2048x2048 2D 8-connected blob grid, 64 blobs, 10% n-links zeroed, "
+    "2d": dict(cfg=1, tag="grid2d8_2048", relabel=10, partial=False, desc="2048x2048 2D 8-connected blob grid, 64 blobs, 10% n-links zeroed, "
                            "64x64 regions (1024), seed 1"),
-    "3d": dict(cfg=2, tag="grid3d6_256", relabel=4, desc="256^3 3D 6-connected blob grid, 32 blobs, 32^3 regions (512), seed 2"),
-    "batch": dict(cfg=3, tag="batch512", relabel=None, desc="512 independent 2D blob grids, sides log-uniform in [32,512], "
+    "3d": dict(cfg=2, tag="grid3d6_256", relabel=4, partial=True, desc="256^3 3D 6-connected blob grid, 32 blobs, 32^3 regions (512), seed 2"),
+    "batch": dict(cfg=3, tag="batch512", relabel=None, partial=None, desc="512 independent 2D blob grids, sides log-uniform in [32,512], "
                               "half 4- and half 8-connected, seeds 3000+i, one batched solve"),
 }
 
@@ -63,8 +63,9 @@ def parse():
     p.add_argument("--relabel-every", type=int, default=None,
                    help="exact region-distance relabel every N sweeps (0 = off; default: the "
                         "workload's tuned interval)")
-    p.add_argument("--partial", action="store_true",
-                   help="partial discharges (sweep s runs only the stages k <= s of ARD)")
+    p.add_argument("--partial", choices=("auto", "on", "off"), default="auto",
+                   help="partial discharges (sweep s runs only the stages k <= s of ARD); auto: "
+                        "the workload's tuned setting (the autotuner's for the batch)")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="only run a device-to-device copy of MIB MiB (HBM counter calibration)")
     return p.parse_args()
@@ -112,7 +113,9 @@ def bench_batch(args):
     mf.load()
     insts = synth.config3_instances(512)
     total_n = sum(inst.n for inst in insts)
-    tune = autotune.autotune_batch(insts, calib=48, reps=1)
+    forced = {"on": (True,), "off": (False,)}.get(args.partial, autotune.PARTIAL)
+    tune = autotune.autotune_batch(insts, calib=48, reps=1, partial=forced)
+    args.partial = tune["partial"]
     b = mf.load_batch(insts, region_shape=tune["region_shape"])
     stream = torch.cuda.Stream()
 
@@ -215,6 +218,7 @@ def main():
     wl = WORKLOADS[args.workload]
     if args.relabel_every is None:
         args.relabel_every = wl["relabel"]
+    args.partial = {"on": True, "off": False}.get(args.partial, wl["partial"])
     inst = synth.config(wl["cfg"])
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
@@ -273,7 +277,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "n": inst.n, "regions": info["regions"],
                    "region_shape": list(info["region_shape"]), "boundary_size": info["boundary_size"],
-                   "schedule": "P-ARD", "connectivity": inst.conn,
+                   "schedule": "P-ARD" + (", partial discharges" if args.partial else ""),
+                   "connectivity": inst.conn,
                    "global_relabel_every": args.relabel_every, "partial_discharges": args.partial},
         "sweeps": stats[-1]["sweeps"],
         "region_discharges": stats[-1]["region_discharges"],

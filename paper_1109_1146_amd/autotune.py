@@ -1,4 +1,5 @@
-"""Autotuner for batched solves: region shape and relabel interval.
+"""Autotuner for batched solves: region shape, relabel interval and partial
+discharges (Sec. 6.2).
 
 It only calls the C ABI (through the binding): it builds a batch of a
 calibration subset for each candidate region shape, solves it with each relabel
@@ -16,6 +17,7 @@ from . import mf
 
 TILES = ((16, 16), (32, 32), (64, 64))
 RELABEL = (0, 4, 8)
+PARTIAL = (False, True)
 
 
 def calibration_subset(instances, size=48, seed=0):
@@ -27,38 +29,44 @@ def calibration_subset(instances, size=48, seed=0):
     return [instances[int(order[p])] for p in picks]
 
 
-def autotune_batch(instances, tiles=TILES, relabel=RELABEL, calib=48, reps=2, graph=True):
-    """Return dict(region_shape, relabel_every, timings) for this batch."""
+def autotune_batch(instances, tiles=TILES, relabel=RELABEL, partial=PARTIAL, calib=48, reps=2,
+                   graph=True):
+    """Return dict(region_shape, relabel_every, partial, timings) for this batch."""
     sample = calibration_subset(instances, calib)
     timings = []
     for tile in tiles:
         b = mf.load_batch(sample, region_shape=tile)
         try:
             for ev in relabel:
-                b.solve(global_relabel_every=ev, graph=graph)  # warm-up, graph capture
-                best = float("inf")
-                for _ in range(reps):
-                    t0 = time.perf_counter()
-                    b.solve(global_relabel_every=ev, graph=graph)
-                    best = min(best, time.perf_counter() - t0)
-                timings.append(dict(region_shape=list(tile), relabel_every=ev, ms=best * 1e3))
+                for pd in partial:
+                    kw = dict(global_relabel_every=ev, graph=graph, partial=pd)
+                    b.solve(**kw)  # warm-up, graph capture
+                    best = float("inf")
+                    for _ in range(reps):
+                        t0 = time.perf_counter()
+                        b.solve(**kw)
+                        best = min(best, time.perf_counter() - t0)
+                    timings.append(dict(region_shape=list(tile), relabel_every=ev, partial=pd,
+                                        ms=best * 1e3))
         finally:
             b.close()
     win = min(timings, key=lambda t: t["ms"])
     return dict(region_shape=tuple(win["region_shape"]), relabel_every=win["relabel_every"],
-                timings=timings)
+                partial=win["partial"], timings=timings)
 
 
-def solve_batch(instances, region_shape=None, relabel_every=None, graph=True, tune=None):
+def solve_batch(instances, region_shape=None, relabel_every=None, graph=True, tune=None,
+                partial=None):
     """Solve all instances in one batch; returns (flows, batch handle, tuning)."""
-    if region_shape is None or relabel_every is None:
+    if region_shape is None or relabel_every is None or partial is None:
         tune = tune or autotune_batch(instances, graph=graph)
         region_shape = region_shape or tune["region_shape"]
         relabel_every = tune["relabel_every"] if relabel_every is None else relabel_every
+        partial = tune["partial"] if partial is None else partial
     b = mf.load_batch(instances, region_shape=region_shape)
-    st = b.solve(global_relabel_every=relabel_every, graph=graph)
+    st = b.solve(global_relabel_every=relabel_every, graph=graph, partial=partial)
     return b.flow_values(), b, dict(region_shape=tuple(region_shape), relabel_every=relabel_every,
-                                    stats=st, tune=tune)
+                                    partial=partial, stats=st, tune=tune)
 
 
 if __name__ == "__main__":
