@@ -271,6 +271,11 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
         const bool relabelOnly = s_active == 2;
         bool writeMode = relabelOnly;
         const size_t rowBase = base + (size_t)row * 32;
+        // Vertices a complete search did not reach cannot reach a target for the
+        // rest of the discharge (pushes only add residual arcs between reached
+        // vertices), so later push-round searches stop once every excess vertex
+        // outside this set is labelled; only the final search must be complete.
+        unsigned dead = 0u;
         for (;;) {
             // ---------------- multi-level search from the targets ----------------
             const long long t0s = wall_clock64();
@@ -301,6 +306,7 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
             }
             int p = 0;
             int stage = 0;
+            bool early = false;  // stopped with every live excess vertex labelled
             if (writeMode && myrow) store_labels(A.labNew, rowBase, F, 0);
             for (;;) {
                 // flood inside the region: u with c_f(u, u + o_k) > 0 and u + o_k in the frontier
@@ -310,11 +316,13 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
                         Fb[p * R + row] = F;
                         Vb[row] = vis;
                     }
-                    // one barrier; the OR of the waves' flags and the neighbour
-                    // rows are read in the same LDS round trip
+                    // one barrier; the OR of the waves' flags (bit 0: a frontier,
+                    // bit 1: a live excess vertex not labelled yet) and the
+                    // neighbour rows are read in the same LDS round trip
                     {
                         const u64 b = __ballot(F != 0u);
-                        if (lane == 0) red[rc & 1][wid] = (b != 0ull) ? 1 : 0;
+                        const u64 e = __ballot((exM & ~vis & ~dead) != 0u);
+                        if (lane == 0) red[rc & 1][wid] = ((b != 0ull) ? 1 : 0) | ((e != 0ull) ? 2 : 0);
                     }
                     __syncthreads();
                     const int4 *r4 = (const int4 *)red[rc & 1];
@@ -330,7 +338,11 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
                     const int4 a0 = r4[0], a1 = r4[1], a2 = r4[2], a3 = r4[3];
                     const int any = (a0.x | a0.y | a0.z | a0.w) | (a1.x | a1.y | a1.z | a1.w) |
                                     (a2.x | a2.y | a2.z | a2.w) | (a3.x | a3.y | a3.z | a3.w);
-                    if (!any) break;
+                    if (!writeMode && !(any & 2)) {
+                        early = true;
+                        break;
+                    }
+                    if (!(any & 1)) break;
                     levels++;
                     unsigned nw = 0u;
                     if (F | fyp | fym | fzp | fzm) {
@@ -352,6 +364,7 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
                 }
                 const long long t1f = wall_clock64();
                 t_flood += t1f - t0f;
+                if (early) break;
                 // next stage: smallest candidate among unvisited border vertices
                 int cand = kInf;
                 for (int i = tid; i < nring; i += kRowsNT) {
@@ -397,6 +410,8 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
                 }
                 t_stage += wall_clock64() - t1f;
             }
+            // a search that ended by itself (under the same stage cap) leaves the dead set
+            if (!early && !writeMode) dead = ~vis;
             // any excess vertex that reaches a target?
             const int found = block_any(myrow && (exM & vis) != 0u, red, rc);
             const long long t1s = wall_clock64();

@@ -288,6 +288,11 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
         const bool relabelOnly = active == 2;
         bool writeMode = relabelOnly;
         const int rowBase = base + y * TX;
+        // Vertices a complete search did not reach cannot reach a target for the
+        // rest of the discharge (pushes only add residual arcs between reached
+        // vertices), so later push-round searches stop once every excess vertex
+        // outside this set is labelled; only the final search must be complete.
+        u64 dead = 0ull;
         for (;;) {
             const long long t_round = wall_clock64();
             // ---------------- multi-level search from the targets ----------------
@@ -319,9 +324,14 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
             }
             if (writeMode && myrow) store_row_labels(A.labNew, rowBase, F, 0);
             int stage = 0;
+            bool early = false;  // stopped with every live excess vertex labelled
             for (;;) {
                 // flood: u unvisited with a residual arc (u, u + o_k) into the frontier
                 for (;;) {
+                    if (!writeMode && __ballot((EXm & ~VIS & ~dead) != 0ull) == 0ull) {
+                        early = true;
+                        break;
+                    }
                     const Rows3 FR = rows3(F, y, TY);
                     u64 t[K], nw = 0ull;
 #pragma unroll
@@ -338,6 +348,7 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
                     F = nw;
                     if (writeMode && nw) store_row_labels(A.labNew, rowBase, nw, stage);
                 }
+                if (early) break;
                 // next stage: smallest candidate over unvisited border vertices
                 int best = kInf;
 #pragma unroll
@@ -384,6 +395,8 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
             }
             const long long t_mid = wall_clock64();
             t_search += t_mid - t_round;
+            // a search that ended by itself (under the same stage cap) leaves the dead set
+            if (!early && !writeMode) dead = ~VIS & rowmask;
             const bool found = __ballot((EXm & VIS) != 0ull) != 0ull;
             if (writeMode) {
                 if (myrow) store_row_labels(A.labNew, rowBase, ~VIS & rowmask, dinf);
