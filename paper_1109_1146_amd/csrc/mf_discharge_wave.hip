@@ -136,6 +136,28 @@ __device__ __forceinline__ void res_add(short *r, int i, int d) {
 }
 __device__ __forceinline__ void res_add(int *r, int i, int d) { atomicAdd(&r[i], d); }
 
+// The K residuals of one vertex (contiguous, K * sizeof(RT) bytes at a multiple
+// of that size) in one or two vector loads.
+template <int K, typename RT>
+__device__ __forceinline__ void load_res_row(const RT *p, RT (&out)[K]) {
+    constexpr int B = K * (int)sizeof(RT);
+    static_assert(B == 4 || B == 8 || B == 16 || B == 32, "residual row of 4, 8, 16 or 32 bytes");
+    if constexpr (B == 4) {
+        const unsigned w = *(const unsigned *)p;
+        __builtin_memcpy(out, &w, 4);
+    } else if constexpr (B == 8) {
+        const uint2 w = *(const uint2 *)p;
+        __builtin_memcpy(out, &w, 8);
+    } else if constexpr (B == 16) {
+        const uint4 w = *(const uint4 *)p;
+        __builtin_memcpy(out, &w, 16);
+    } else {
+        const uint4 a = ((const uint4 *)p)[0], b = ((const uint4 *)p)[1];
+        __builtin_memcpy(out, &a, 16);
+        __builtin_memcpy((char *)out + 16, &b, 16);
+    }
+}
+
 __device__ __forceinline__ void store_row_labels(int *lab, int rowBase, u64 bits, int val) {
     while (bits) {
         const int x = __ffsll(bits) - 1;
@@ -266,9 +288,13 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
             for (int row = 0; row < TY; row++) {
                 const int l = row * TX + lane;
                 const bool ok = lane < TX;
+                RT rv[K];
+#pragma unroll
+                for (int k = 0; k < K; k++) rv[k] = 0;
+                if (ok) load_res_row<K, RT>(resL + l * K, rv);
 #pragma unroll
                 for (int k = 0; k < K; k++) {
-                    const u64 b = __ballot(ok && resL[l * K + k] > 0);
+                    const u64 b = __ballot(rv[k] > 0);
                     if (lane == row) Rk[k] = b;
                 }
                 const u64 bt = __ballot(ok && rtL[l] > 0);
@@ -314,10 +340,12 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
                 const int l = slotL[j];
                 if (l >= 0) {
                     const int i = lane + 64 * j;
+                    RT rv[K];
+                    load_res_row<K, RT>(resL + l * K, rv);
 #pragma unroll
                     for (int k = 0; k < K; k++) {
                         const int h = halo[i * K + k];
-                        if (h < dinf && resL[l * K + k] > 0) c = min(c, h + 1);
+                        if (h < dinf && rv[k] > 0) c = min(c, h + 1);
                     }
                 }
                 slotC[j] = c;
@@ -375,10 +403,12 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
                     const int i = lane + 64 * j;
                     const int ry = l / TX, rx = l - ry * TX;
                     unsigned match = 0u;
+                    RT rv[K];
+                    load_res_row<K, RT>(resL + l * K, rv);
 #pragma unroll
                     for (int k = 0; k < K; k++) {
                         const int h = halo[i * K + k];
-                        if (h < dinf && h + 1 == level && resL[l * K + k] > 0) match |= 1u << k;
+                        if (h < dinf && h + 1 == level && rv[k] > 0) match |= 1u << k;
                     }
                     admB |= match << (K * j);
                     slotC[j] = kInf;
@@ -452,9 +482,14 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
                             atomicAnd(&rtRows[uy], ~bit);
                         }
                     }
+                    // the residuals of u only fall through u's own pushes (an
+                    // admissible arc is never pushed from both ends), so one
+                    // vector load of all K is as good as K separate ones
+                    RT rv[K];
+                    load_res_row<K, RT>(resL + u * K, rv);
                     int c[K];
 #pragma unroll
-                    for (int k = 0; k < K; k++) c[k] = (am[k] & bit) ? (int)resL[u * K + k] : 0;
+                    for (int k = 0; k < K; k++) c[k] = (am[k] & bit) ? (int)rv[k] : 0;
 #pragma unroll
                     for (int k = 0; k < K; k++) {
                         if (rem <= 0 || !(am[k] & bit)) continue;
@@ -533,10 +568,12 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
                             continue;
                         }
                         int rem = e;
+                        RT rv[K];
+                        load_res_row<K, RT>(resL + l * K, rv);
 #pragma unroll
                         for (int k = 0; k < K; k++) {
                             if (!((ab >> k) & 1u) || rem <= 0) continue;
-                            const int c = resL[l * K + k];
+                            const int c = rv[k];
                             const int d = min(rem, c);
                             if (d > 0) {
                                 resL[l * K + k] = (RT)(c - d);
