@@ -24,7 +24,6 @@ typedef unsigned long long u64;
 
 namespace {
 
-constexpr int kWaveList = 256;  // work-list entries per pass
 
 __host__ __device__ inline size_t al16w(size_t x) { return (x + 15) & ~(size_t)15; }
 
@@ -44,7 +43,7 @@ __host__ __device__ inline WaveLayout wave_layout(int V, int K, int nring, int r
     L.resM = o; o = al16w(o + (size_t)K * 64 * 8);        // residual arc inside the tile, per direction
     L.admM = o; o = al16w(o + (size_t)(K + 1) * 64 * 8);  // admissible arcs of the round, then t
     L.rows = o; o = al16w(o + (size_t)3 * 64 * 8);        // residual t-link, received, drained rows
-    L.list = o; o = al16w(o + (size_t)kWaveList * 2);
+    L.list = o; o = al16w(o + (size_t)V * 2);              // work list: room for every vertex
     L.total = o;
     return L;
 }
@@ -158,6 +157,31 @@ __device__ __forceinline__ void load_res_row(const RT *p, RT (&out)[K]) {
     }
 }
 
+template <int K, typename RT>
+__device__ __forceinline__ void store_res_row(RT *p, const RT (&in)[K]) {
+    constexpr int B = K * (int)sizeof(RT);
+    static_assert(B == 4 || B == 8 || B == 16 || B == 32, "residual row of 4, 8, 16 or 32 bytes");
+    if constexpr (B == 4) {
+        unsigned w;
+        __builtin_memcpy(&w, in, 4);
+        *(unsigned *)p = w;
+    } else if constexpr (B == 8) {
+        uint2 w;
+        __builtin_memcpy(&w, in, 8);
+        *(uint2 *)p = w;
+    } else if constexpr (B == 16) {
+        uint4 w;
+        __builtin_memcpy(&w, in, 16);
+        *(uint4 *)p = w;
+    } else {
+        uint4 a, b;
+        __builtin_memcpy(&a, in, 16);
+        __builtin_memcpy(&b, (const char *)in + 16, 16);
+        ((uint4 *)p)[0] = a;
+        ((uint4 *)p)[1] = b;
+    }
+}
+
 __device__ __forceinline__ void store_row_labels(int *lab, int rowBase, u64 bits, int val) {
     while (bits) {
         const int x = __ffsll(bits) - 1;
@@ -256,8 +280,10 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
         if (lane < 4) s_tr[lane] = 0;
         // ---------------- stage the region into LDS ----------------
         for (int l = lane; l < V; l += 64) {
+            RT rv[K];
 #pragma unroll
-            for (int k = 0; k < K; k++) resL[l * K + k] = (RT)A.res[(size_t)k * N + base + l];
+            for (int k = 0; k < K; k++) rv[k] = (RT)A.res[(size_t)k * N + base + l];
+            store_res_row<K, RT>(resL + l * K, rv);
             exL[l] = (ET)A.ex[base + l];
             rtL[l] = (RT)A.rt[base + l];
         }
@@ -529,28 +555,23 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
                     }
                 } else {
                     // the excess vertices of all rows, spread over the lanes by a work list
+                    // (the list has room for every vertex of the tile: one pass)
                     const int incl = wave_scan_incl(cnt, lane);
                     const int total = __builtin_amdgcn_readlane(incl, 63);
-                    for (int w0 = 0; w0 < total; w0 += kWaveList) {
-                        int idx = incl - cnt;
-                        if (cnt && idx < w0 + kWaveList && idx + cnt > w0) {
-                            u64 m = P;
-                            while (m) {
-                                const int x = __ffsll(m) - 1;
-                                m &= m - 1;
-                                if (idx >= w0 && idx < w0 + kWaveList) wl[idx - w0] = (unsigned short)(y * TX + x);
-                                idx++;
-                            }
-                        }
-                        lane_sync();
-                        const int nItems = min(total - w0, kWaveList);
-                        for (int it = lane; it < nItems; it += 64) {
-                            const int u = wl[it];
-                            const int uy = u / TX;
-                            push_from(u, uy, u - uy * TX);
-                        }
-                        lane_sync();
+                    int idx = incl - cnt;
+                    u64 m = P;
+                    while (m) {
+                        const int x = __ffsll(m) - 1;
+                        m &= m - 1;
+                        wl[idx++] = (unsigned short)(y * TX + x);
                     }
+                    lane_sync();
+                    for (int it = lane; it < total; it += 64) {
+                        const int u = wl[it];
+                        const int uy = u / TX;
+                        push_from(u, uy, u - uy * TX);
+                    }
+                    lane_sync();
                 }
                 // first-level vertices of stages k > 0 push over boundary arcs
                 if (admB) {
@@ -610,8 +631,10 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
         __syncthreads();
         // ---------------- write the region back ----------------
         for (int l = lane; l < V; l += 64) {
+            RT rv[K];
+            load_res_row<K, RT>(resL + l * K, rv);
 #pragma unroll
-            for (int k = 0; k < K; k++) A.res[(size_t)k * N + base + l] = resL[l * K + k];
+            for (int k = 0; k < K; k++) A.res[(size_t)k * N + base + l] = rv[k];
             A.ex[base + l] = ex_get(exL, l);
             A.rt[base + l] = rtL[l];
         }
