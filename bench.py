@@ -201,7 +201,7 @@ def bench_batch(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU; multi-GPU runs are not supported, --gpus must be 1"}))
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)

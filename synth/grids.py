@@ -10,9 +10,8 @@ Layout contract (shared with the C ABI):
 * ``cs[v] = c(s, v)`` and ``ct[v] = c(v, t)``, all int32 and >= 0.
 
 The generator recipe (blob image -> contrast-sensitive n-links, intensity
-t-links) follows the configuration text of the workloads this solver is
-measured on; every free choice it leaves open is fixed here and restated in
-DESIGN.md.
+t-links) follows the stated configurations of the measured workloads; every
+free choice they leave open is fixed here, in the functions below.
 """
 from __future__ import annotations
 
