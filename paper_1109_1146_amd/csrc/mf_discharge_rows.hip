@@ -164,6 +164,12 @@ __device__ __forceinline__ int axis_dir_m(unsigned mm, int a) {
 __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
     extern __shared__ __align__(16) unsigned smem_rows[];
     __shared__ __align__(16) int red[2][kRowsWaves];
+    // flood level flags (bit 0: a frontier, bit 1: a live excess vertex not
+    // labelled yet), OR-ed by the waves into one of three words in rotation: the
+    // word of level l is read after the level's barrier, and thread 0 clears
+    // the word of level l + 2 then (its readers passed this barrier, its
+    // writers come after the next one)
+    __shared__ int s_flood[3];
     __shared__ int s_r, s_active;
     __shared__ long long s_tr[4];  // trace: excess out, to sink, to boundary, label sum
     if (*A.actIn == 0ull) return;
@@ -192,6 +198,8 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
     const int dinf = A.dinf;
     const int nring = A.nring;
     int rc = 0;
+    int fl = 0;  // flood word of the next level (0, 1, 2 in rotation)
+    if (tid < 3) s_flood[tid] = 0;
 
     // recv and clr are contiguous and return to zero after every use
     for (int i = tid; i < 4 * R; i += kRowsNT) recvB[i] = 0u;
@@ -316,17 +324,18 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
                         Fb[p * R + row] = F;
                         Vb[row] = vis;
                     }
-                    // one barrier; the OR of the waves' flags (bit 0: a frontier,
-                    // bit 1: a live excess vertex not labelled yet) and the
-                    // neighbour rows are read in the same LDS round trip
+                    // one barrier; the level's flag word and the neighbour rows
+                    // are read in the same LDS round trip
                     {
                         const u64 b = __ballot(F != 0u);
                         const u64 e = __ballot((exM & ~vis & ~dead) != 0u);
-                        if (lane == 0) red[rc & 1][wid] = ((b != 0ull) ? 1 : 0) | ((e != 0ull) ? 2 : 0);
+                        const int f = ((b != 0ull) ? 1 : 0) | ((e != 0ull) ? 2 : 0);
+                        if (lane == 0 && f) atomicOr(&s_flood[fl], f);
                     }
                     __syncthreads();
-                    const int4 *r4 = (const int4 *)red[rc & 1];
-                    rc++;
+                    const int any = s_flood[fl];
+                    if (tid == 0) s_flood[fl == 0 ? 2 : fl - 1] = 0;  // the word of level l + 2
+                    fl = fl == 2 ? 0 : fl + 1;
                     const unsigned *Fp = Fb + p * R;
                     unsigned fyp = 0u, fym = 0u, fzp = 0u, fzm = 0u;
                     if (myrow) {
@@ -335,9 +344,6 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
                         fzp = (z + 1 < TZ) ? Fp[row + TY] : 0u;
                         fzm = (z > 0) ? Fp[row - TY] : 0u;
                     }
-                    const int4 a0 = r4[0], a1 = r4[1], a2 = r4[2], a3 = r4[3];
-                    const int any = (a0.x | a0.y | a0.z | a0.w) | (a1.x | a1.y | a1.z | a1.w) |
-                                    (a2.x | a2.y | a2.z | a2.w) | (a3.x | a3.y | a3.z | a3.w);
                     if (!writeMode && !(any & 2)) {
                         early = true;
                         break;
