@@ -76,19 +76,19 @@ __device__ __forceinline__ int wave_min_rows(int v) {
     return v;
 }
 
-// Workgroup-wide OR / MIN with one barrier.  The two halves of red[] alternate
-// between consecutive calls, so a call never overwrites values that a slower
-// wave may still read from the previous one.
-__device__ __forceinline__ int block_any(int pred, int (*red)[kRowsWaves], int &rc) {
+// Workgroup-wide OR / MIN with one barrier.  The two halves of red[] / anyB[]
+// alternate between consecutive calls, so a call never overwrites values that a
+// slower wave may still read from the previous one.  The OR keeps one byte per
+// wave, read back as one 16-byte word.
+static_assert(kRowsWaves == 16, "one byte per wave in a 16-byte word");
+__device__ __forceinline__ int block_any(int pred, unsigned char (*anyB)[kRowsWaves], int &rc) {
     const u64 b = __ballot(pred);
     const int p = rc & 1;
     rc++;
-    if ((threadIdx.x & 63) == 0) red[p][threadIdx.x >> 6] = (b != 0ull) ? 1 : 0;
+    if ((threadIdx.x & 63) == 0) anyB[p][threadIdx.x >> 6] = (b != 0ull) ? 1 : 0;
     __syncthreads();
-    int a = 0;
-#pragma unroll
-    for (int w = 0; w < kRowsWaves; w++) a |= red[p][w];
-    return a;
+    const uint4 v = *(const uint4 *)anyB[p];
+    return (v.x | v.y | v.z | v.w) != 0u;
 }
 
 __device__ __forceinline__ int block_min(int v, int (*red)[kRowsWaves], int &rc) {
@@ -170,6 +170,7 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
     // the word of level l + 2 then (its readers passed this barrier, its
     // writers come after the next one)
     __shared__ int s_flood[3];
+    __shared__ __align__(16) unsigned char anyB[2][kRowsWaves];  // block_any bytes
     __shared__ int s_r, s_active;
     __shared__ long long s_tr[4];  // trace: excess out, to sink, to boundary, label sum
     if (*A.actIn == 0ull) return;
@@ -419,7 +420,7 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
             // a search that ended by itself (under the same stage cap) leaves the dead set
             if (!early && !writeMode) dead = ~vis;
             // any excess vertex that reaches a target?
-            const int found = block_any(myrow && (exM & vis) != 0u, red, rc);
+            const int found = block_any(myrow && (exM & vis) != 0u, anyB, rc);
             const long long t1s = wall_clock64();
             t_search += t1s - t0s;
             if (writeMode) {
@@ -580,7 +581,7 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
                         }
                     }
                 }
-                const int any = block_any(pushed, red, rc);
+                const int any = block_any(pushed, anyB, rc);
                 pushIters++;
                 if (myrow) {
                     const unsigned rv = recvB[q * R + row], cl = clrB[q * R + row];
@@ -597,7 +598,7 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
             t_push += wall_clock64() - t1s;
             // no excess left in the region (the masks may only over-report it):
             // the next search cannot find an excess vertex, so it writes the labels
-            if (!block_any(myrow && exM != 0u, red, rc)) writeMode = true;
+            if (!block_any(myrow && exM != 0u, anyB, rc)) writeMode = true;
         }
         __syncthreads();
         if (A.trace) {
@@ -657,7 +658,7 @@ size_t grelabel_rows_lds(int ty, int tz) { return (size_t)9 * ty * tz * sizeof(u
 
 __global__ __launch_bounds__(kRowsNT) void k_grelabel_rows(GRelabelArgs A) {
     extern __shared__ __align__(16) unsigned smem_rows[];
-    __shared__ __align__(16) int red[2][kRowsWaves];
+    __shared__ __align__(16) unsigned char anyB[2][kRowsWaves];  // block_any bytes
     __shared__ int s_go;
     const Geo &G = A.G;
     const int V = G.V, N = G.N, TY = G.ty, TZ = G.tz, R = TY * TZ, D = A.level, dinf = A.dinf;
@@ -719,7 +720,7 @@ __global__ __launch_bounds__(kRowsNT) void k_grelabel_rows(GRelabelArgs A) {
         int p = 0;
         for (;;) {
             if (myrow) Fb[p * R + row] = F;
-            if (!block_any(F != 0u, red, rc)) break;
+            if (!block_any(F != 0u, anyB, rc)) break;
             if (myrow) {
                 const unsigned *Fp = Fb + p * R;
                 const unsigned fyp = (y + 1 < TY) ? Fp[row + 1] : 0u;
