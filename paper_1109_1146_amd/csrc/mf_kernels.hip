@@ -7,6 +7,8 @@
 //   lab[p][g]      labels, two buffers: a sweep reads p and writes p ^ 1
 //   pushb[k*N + g] flow a discharge sent over the boundary arc (g, g + o_k),
 //                  consumed (and zeroed) by the fuse kernel
+#include <algorithm>
+
 #include "mf_device.h"
 #include "mf_launch.h"
 
@@ -92,12 +94,26 @@ __global__ void k_sum_links(const int *cs, const int *ct, int n, u64 *out2) {
 // ---------------------------------------------------------------------------
 // Init (Sec. 2): saturate s-links into the excess, f := 0, d := 0.
 // ---------------------------------------------------------------------------
+// Grid-stride loops with one atomic per workgroup for the active count (one
+// per wave made the launch wait on same-address atomics).
+constexpr int kCountBlocks = 2048;
+
+__device__ __forceinline__ void block_count_add(int v, u64 *out) {
+    __shared__ int s_w[4];  // blockDim.x == 256
+    v = wave_sum_i(v);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int t = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        if (t) atomicAdd(out, (u64)t);
+    }
+}
+
 __global__ void k_init(Geo G, const int *cs, const int *ct, const int *nbr, int n, int *res,
                        int *rt, int *ex, int *lab0, int *lab1, int *pushb, int *ractive,
                        u64 *act0) {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
     int active = 0;
-    if (g < G.N) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G.N; g += gridDim.x * blockDim.x) {
         int z, y, x;
         bool real = blocked_to_grid(G, g, z, y, x);
         int e = 0, t = 0;
@@ -115,12 +131,11 @@ __global__ void k_init(Geo G, const int *cs, const int *ct, const int *nbr, int 
         lab0[g] = 0;
         lab1[g] = 0;
         if (e > 0) {
-            active = 1;
+            active++;
             ractive[g / G.V] = 1;
         }
     }
-    active = wave_sum_i(active);
-    if ((threadIdx.x & 63) == 0 && active) atomicAdd(act0, (u64)active);
+    block_count_add(active, act0);
 }
 
 // ---------------------------------------------------------------------------
@@ -699,8 +714,8 @@ hipError_t launch_sum_links(const int *cs, const int *ct, int n, unsigned long l
 hipError_t launch_init(const Geo &G, const int *cs, const int *ct, const int *nbr, int n, int *res,
                        int *rt, int *ex, int *lab0, int *lab1, int *pushb, int *ractive,
                        unsigned long long *act0, hipStream_t s) {
-    hipLaunchKernelGGL(k_init, dim3(cdiv(G.N, 256)), dim3(256), 0, s, G, cs, ct, nbr, n, res, rt,
-                       ex, lab0, lab1, pushb, ractive, act0);
+    hipLaunchKernelGGL(k_init, dim3(std::min(cdiv(G.N, 256), kCountBlocks)), dim3(256), 0, s, G, cs, ct,
+                       nbr, n, res, rt, ex, lab0, lab1, pushb, ractive, act0);
     return hipGetLastError();
 }
 
@@ -851,20 +866,14 @@ __global__ __launch_bounds__(NT) void k_grelabel(GRelabelArgs A) {
 // Active regions and the active-vertex count after new labels.
 __global__ void k_activity(Geo G, const int *ex, const int *lab, int dinf, int *ractive,
                            unsigned long long *act) {
-    __shared__ int s_w[4];
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
     int a = 0;
-    if (g < G.N && ex[g] > 0 && lab[g] < dinf) {
-        a = 1;
-        ractive[g / G.V] = 1;
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G.N; g += gridDim.x * blockDim.x) {
+        if (ex[g] > 0 && lab[g] < dinf) {
+            a++;
+            ractive[g / G.V] = 1;
+        }
     }
-    a = wave_sum_i(a);
-    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = a;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int t = s_w[0] + s_w[1] + s_w[2] + s_w[3];
-        if (t) atomicAdd(act, (unsigned long long)t);
-    }
+    block_count_add(a, act);
 }
 
 hipError_t launch_grelabel(const GRelabelArgs &A, int blocks, hipStream_t s) {
@@ -874,7 +883,8 @@ hipError_t launch_grelabel(const GRelabelArgs &A, int blocks, hipStream_t s) {
 
 hipError_t launch_activity(const Geo &G, const int *ex, const int *lab, int dinf, int *ractive,
                            unsigned long long *act, hipStream_t s) {
-    hipLaunchKernelGGL(k_activity, dim3(cdiv(G.N, 256)), dim3(256), 0, s, G, ex, lab, dinf, ractive, act);
+    hipLaunchKernelGGL(k_activity, dim3(std::min(cdiv(G.N, 256), kCountBlocks)), dim3(256), 0, s, G, ex, lab,
+                       dinf, ractive, act);
     return hipGetLastError();
 }
 
