@@ -108,7 +108,14 @@ static void free_all(mf_grid *g) {
     if (g->pinned) (void)hipHostFree(g->pinned);
 }
 
-static const int8_t OFF2D[8][2] = {{0, 1}, {0, -1}, {1, 0}, {-1, 0}, {1, 1}, {-1, -1}, {-1, 1}, {1, -1}};
+static constexpr int8_t OFF2D[8][2] = {{0, 1}, {0, -1}, {1, 0}, {-1, 0}, {1, 1}, {-1, -1}, {-1, 1}, {1, -1}};
+// the 2D kernels use the same order as compile-time constants
+static constexpr bool off2d_matches() {
+    for (int k = 0; k < 8; k++)
+        if (OFF2D[k][0] != mfd::off2d_dy(k) || OFF2D[k][1] != mfd::off2d_dx(k)) return false;
+    return true;
+}
+static_assert(off2d_matches(), "2D direction table and the kernels' constants differ");
 static const int8_t OFF3D[6][3] = {{0, 0, 1}, {0, 0, -1}, {0, 1, 0}, {0, -1, 0}, {1, 0, 0}, {-1, 0, 0}};
 
 extern "C" const char *mf_status_str(mf_status s) {

@@ -10,6 +10,17 @@ constexpr int32_t kInf = 0x7fffffff;
 constexpr int kHistBins = 1 << 16;  // boundary-label histogram bins (labels beyond are not gap candidates)
 constexpr int kHistLds = 1024;      // per-block privatised histogram bins
 
+// The canonical 2D directions k = 0..7 as (dy, dx): +x, -x, +y, -y, then the
+// diagonals (+y+x), (-y-x), (-y+x), (+y-x); the reverse of direction k is k ^ 1
+// and 4-connected grids use k < 4.  Kernels that only run on 2D grids take the
+// offsets from here, so that they are compile-time constants.
+__host__ __device__ constexpr int off2d_dy(int k) {
+    return (k == 2 || k == 4 || k == 7) ? 1 : ((k == 3 || k == 5 || k == 6) ? -1 : 0);
+}
+__host__ __device__ constexpr int off2d_dx(int k) {
+    return (k == 0 || k == 4 || k == 6) ? 1 : ((k == 1 || k == 5 || k == 7) ? -1 : 0);
+}
+
 // Grid geometry in blocked (region-major) layout.  2D grids are stored as
 // depth-1 3D grids.  A region is a tz x ty x tx box; its V vertices are
 // contiguous, x fastest; regions are numbered z-major over the region grid.

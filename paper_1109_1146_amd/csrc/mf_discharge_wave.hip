@@ -225,11 +225,12 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
     const int dinf = A.dinf;
     const u64 rowmask = TX == 64 ? ~0ull : ((1ull << TX) - 1);
     const bool myrow = y < TY;
+    // 2D grids only: the canonical direction offsets, constants after unrolling
     int dy[K], dx[K];
 #pragma unroll
     for (int k = 0; k < K; k++) {
-        dy[k] = G.oy[k];
-        dx[k] = G.ox[k];
+        dy[k] = off2d_dy(k);
+        dx[k] = off2d_dx(k);
     }
     // arcs of direction k that stay inside the tile, as a row mask of this lane
     u64 inside[K];
@@ -739,12 +740,13 @@ __global__ __launch_bounds__(64) void k_grelabel_wave(GRelabelArgs A) {
     const bool myrow = y < TY;
     const u64 rowmask = TX == 64 ? ~0ull : ((1ull << TX) - 1);
     seedRows[lane] = 0ull;
+    // 2D grids only: the canonical direction offsets, constants after unrolling
     int dy[K], dx[K];
     u64 inside[K];
 #pragma unroll
     for (int k = 0; k < K; k++) {
-        dy[k] = G.oy[k];
-        dx[k] = G.ox[k];
+        dy[k] = off2d_dy(k);
+        dx[k] = off2d_dx(k);
         const bool rowok = myrow && y + dy[k] >= 0 && y + dy[k] < TY;
         u64 m = rowok ? rowmask : 0ull;
         if (dx[k] > 0) m &= rowmask >> dx[k];
