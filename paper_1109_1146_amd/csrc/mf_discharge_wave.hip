@@ -244,11 +244,14 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
     }
     // border vertices of this lane: i = lane + 64 j (at most 4 * 64 >= 4 * 63 for 64 x 64 tiles)
     const int nslot = (nring + 63) / 64;
-    int slotL[4];
+    int slotL[4], slotY[4], slotX[4];  // local index, row and column (0 for no slot)
 #pragma unroll
     for (int j = 0; j < 4; j++) {
         const int i = lane + 64 * j;
         slotL[j] = (j < nslot && i < nring) ? A.ringL[i] : -1;
+        const int l = slotL[j] >= 0 ? slotL[j] : 0;
+        slotY[j] = l / TX;
+        slotX[j] = l - slotY[j] * TX;
     }
 
     for (;;) {
@@ -409,8 +412,7 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
 #pragma unroll
                 for (int j = 0; j < 4; j++) {
                     if (j >= nslot) break;
-                    const int l = slotL[j] >= 0 ? slotL[j] : 0;
-                    const int ry = l / TX, rx = l - ry * TX;
+                    const int ry = slotY[j], rx = slotX[j];
                     const u64 vrow = shfl64(VIS, ry);
                     if (slotC[j] != kInf) {
                         if ((vrow >> rx) & 1ull) slotC[j] = kInf;  // labelled in this search
@@ -428,7 +430,7 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
                     if (slotC[j] != level) continue;
                     const int l = slotL[j];
                     const int i = lane + 64 * j;
-                    const int ry = l / TX, rx = l - ry * TX;
+                    const int ry = slotY[j], rx = slotX[j];
                     unsigned match = 0u;
                     RT rv[K];
                     load_res_row<K, RT>(resL + l * K, rv);
@@ -564,13 +566,13 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
                     while (m) {
                         const int x = __ffsll(m) - 1;
                         m &= m - 1;
-                        wl[idx++] = (unsigned short)(y * TX + x);
+                        wl[idx++] = (unsigned short)((y << 6) | x);  // row and column (TX <= 64)
                     }
                     lane_sync();
                     for (int it = lane; it < total; it += 64) {
-                        const int u = wl[it];
-                        const int uy = u / TX;
-                        push_from(u, uy, u - uy * TX);
+                        const int w = wl[it];
+                        const int uy = w >> 6, ux = w & 63;
+                        push_from(uy * TX + ux, uy, ux);
                     }
                     lane_sync();
                 }
@@ -582,7 +584,7 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
                         if (!ab) continue;
                         const int l = slotL[j];
                         const int i = lane + 64 * j;
-                        const int ly = l / TX, lx = l - ly * TX;
+                        const int ly = slotY[j], lx = slotX[j];
                         const u64 bit = 1ull << lx;
                         const int e = ex_get(exL, l);
                         if (e <= 0) {
@@ -753,6 +755,17 @@ __global__ __launch_bounds__(64) void k_grelabel_wave(GRelabelArgs A) {
         if (dx[k] < 0) m &= (rowmask << (-dx[k])) & rowmask;
         inside[k] = m;
     }
+    // border vertices of this lane: i = lane + 64 j (a tile of at most 64 x 64
+    // has at most 252), with their rows and columns
+    int slotL[4], slotY[4], slotX[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int i = lane + 64 * j;
+        slotL[j] = i < A.nring ? A.ringL[i] : -1;
+        const int l = slotL[j] >= 0 ? slotL[j] : 0;
+        slotY[j] = l / TX;
+        slotX[j] = l - slotY[j] * TX;
+    }
     for (int r = blockIdx.x; r < G.nreg; r += gridDim.x) {
         int go = 1;
         if (D > 0) {
@@ -789,12 +802,12 @@ __global__ __launch_bounds__(64) void k_grelabel_wave(GRelabelArgs A) {
             for (int k = 0; k < K; k++) R[k] = cr[k * 64 + lane];
             U = cr[K * 64 + lane];
             // seeds: border vertices marked by the previous level
-            for (int i = lane; i < A.nring; i += 64) {
-                const int l = A.ringL[i];
-                if (A.candIn[base + l]) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int l = slotL[j];
+                if (l >= 0 && A.candIn[base + l]) {
                     A.candIn[base + l] = 0;
-                    const int ry = l / TX;
-                    atomicOr(&seedRows[ry], 1ull << (l - ry * TX));
+                    atomicOr(&seedRows[slotY[j]], 1ull << slotX[j]);
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -821,12 +834,13 @@ __global__ __launch_bounds__(64) void k_grelabel_wave(GRelabelArgs A) {
             cr[K * 64 + lane] = U;
         }
         // marks for D + 1: residual predecessors across the border of reached border vertices
-        for (int i0 = 0; i0 < A.nring; i0 += 64) {
-            const int i = i0 + lane;
-            const int l = i < A.nring ? A.ringL[i] : 0;
-            const int ry = l / TX, rx = l - ry * TX;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (64 * j >= A.nring) break;  // uniform: every lane takes part in the row exchange
+            const int i = lane + 64 * j;
+            const int ry = slotY[j], rx = slotX[j];
             const u64 m = shfl64(reached, ry);
-            if (i < A.nring && ((m >> rx) & 1ull)) {
+            if (slotL[j] >= 0 && ((m >> rx) & 1ull)) {
                 const unsigned lm = A.ringM[i];
 #pragma unroll
                 for (int k = 0; k < K; k++) {
