@@ -856,6 +856,147 @@ __global__ __launch_bounds__(64) void k_grelabel_wave(GRelabelArgs A) {
     }
 }
 
+// Residual reachability for the cuts (the region floods of k_flood, same
+// marks) on 2D tiles of at most 64 x 64: one wavefront per region, lane y holds
+// row y as 64-bit masks.  dir 0 floods forward from the excess vertices along
+// arcs with c_f > 0 (the masks hold, at the head w of each arc, whether the arc
+// w - o_k -> w is residual), dir 1 backward from t.  Reached border vertices
+// mark their neighbours across the border (atomic exchange, as k_flood) and
+// flag the neighbouring region for the next round.
+template <int K>
+__global__ __launch_bounds__(64) void k_flood_wave(FloodArgs A) {
+    const Geo &G = A.G;
+    const int V = G.V, N = G.N, TX = G.tx, TY = G.ty;
+    const int lane = threadIdx.x, y = lane;
+    const bool myrow = y < TY;
+    const u64 rowmask = TX == 64 ? ~0ull : ((1ull << TX) - 1);
+    // 2D grids only: the canonical direction offsets, constants after unrolling
+    int dy[K], dx[K];
+    u64 inside[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        dy[k] = off2d_dy(k);
+        dx[k] = off2d_dx(k);
+        const bool rowok = myrow && y + dy[k] >= 0 && y + dy[k] < TY;
+        u64 m = rowok ? rowmask : 0ull;
+        if (dx[k] > 0) m &= rowmask >> dx[k];
+        if (dx[k] < 0) m &= (rowmask << (-dx[k])) & rowmask;
+        inside[k] = m;
+    }
+    int slotL[4], slotY[4], slotX[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int i = lane + 64 * j;
+        slotL[j] = i < A.nring ? A.ringL[i] : -1;
+        const int l = slotL[j] >= 0 ? slotL[j] : 0;
+        slotY[j] = l / TX;
+        slotX[j] = l - slotY[j] * TX;
+    }
+    for (int r = blockIdx.x; r < G.nreg; r += gridDim.x) {
+        int go = 1;
+        if (lane == 0) {
+            go = (A.round == 0) ? 1 : A.dirtyIn[r];
+            A.dirtyIn[r] = 0;
+        }
+        go = __shfl(go, 0, 64);
+        if (!go) continue;
+        const int base = r * V;
+        // row masks: residual arcs inside the tile, the marks already stored
+        // (M0) and with the round-0 seeds (M)
+        u64 R[K], M = 0, M0 = 0;
+#pragma unroll
+        for (int k = 0; k < K; k++) R[k] = 0;
+        for (int row = 0; row < TY; row++) {
+            const int l = row * TX + lane;
+            const bool ok = lane < TX;
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const u64 b = __ballot(ok && A.res[(size_t)k * N + base + l] > 0);
+                if (lane == row) R[k] = b;
+            }
+            const bool m0 = ok && A.mark[base + l] != 0;
+            const bool sd = A.round == 0 && ok && (A.dir == 0 ? A.ex[base + l] > 0 : A.rt[base + l] > 0);
+            const u64 b0 = __ballot(m0), bm = __ballot(m0 || sd);
+            if (lane == row) {
+                M0 = b0;
+                M = bm;
+            }
+        }
+        u64 Rf[K];  // the arcs the flood follows, at the vertex it reaches
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            R[k] &= inside[k];
+            // forward: w is reached over w - o_k -> w, residual at row y - dy, column x - dx
+            Rf[k] = A.dir == 0 ? (shift_dx(rows3(R[k], y, TY).at(-dy[k]), -dx[k]) & (myrow ? rowmask : 0ull))
+                               : R[k];
+        }
+        u64 reached = myrow ? M : 0ull, F = reached;
+        for (;;) {
+            const Rows3 FR = rows3(F, y, TY);
+            u64 nw = 0;
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const int sy = A.dir == 0 ? -dy[k] : dy[k], sx = A.dir == 0 ? -dx[k] : dx[k];
+                nw |= Rf[k] & shift_dx(FR.at(sy), sx);
+            }
+            nw &= ~reached;
+            if (!__ballot(nw != 0ull)) break;
+            reached |= nw;
+            F = nw;
+        }
+        // marks of this round, seeds included (stores of 1 race harmlessly with
+        // the neighbours' exchanges)
+        if (myrow) {
+            u64 nb = reached & ~M0;
+            const int rowBase = base + y * TX;
+            while (nb) {
+                const int x = __ffsll(nb) - 1;
+                nb &= nb - 1;
+                A.mark[rowBase + x] = 1;
+            }
+        }
+        // across the border
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (64 * j >= A.nring) break;  // uniform: every lane takes part in the row exchange
+            const int i = lane + 64 * j;
+            const int ry = slotY[j], rx = slotX[j];
+            const u64 m = shfl64(reached, ry);
+            if (slotL[j] < 0 || !((m >> rx) & 1ull)) continue;
+            const unsigned lm = A.ringM[i];
+            const int v = slotL[j];
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                if (A.dir == 0) {
+                    // forward: arc (v, v + o_k) with c_f > 0 that leaves the tile
+                    if (!((lm >> k) & 1u) || A.res[(size_t)k * N + base + v] <= 0) continue;
+                    const int wg = cross_nbr(G, r, 0, ry, rx, k);
+                    if (wg >= 0 && atomicExch(&A.mark[wg], 1) == 0) {
+                        A.dirtyOut[wg / V] = 1;
+                        atomicAdd(A.changed, 1u);
+                    }
+                } else {
+                    // backward: u = v - o_k across the border with c_f(u, v) > 0
+                    if (!((lm >> (k ^ 1)) & 1u)) continue;
+                    const int wg = cross_nbr(G, r, 0, ry, rx, k ^ 1);
+                    if (wg >= 0 && A.res[(size_t)k * N + wg] > 0 && atomicExch(&A.mark[wg], 1) == 0) {
+                        A.dirtyOut[wg / V] = 1;
+                        atomicAdd(A.changed, 1u);
+                    }
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_flood_wave(const FloodArgs &A, int blocks, hipStream_t s) {
+    if (A.G.tz != 1 || A.G.tx > 64 || A.G.ty > 64 || A.nring > 256) return hipErrorInvalidValue;
+    if (A.G.K == 4) hipLaunchKernelGGL(k_flood_wave<4>, dim3(blocks), dim3(64), 0, s, A);
+    else if (A.G.K == 8) hipLaunchKernelGGL(k_flood_wave<8>, dim3(blocks), dim3(64), 0, s, A);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_grelabel_wave(const GRelabelArgs &A, int blocks, hipStream_t s) {
     if (A.G.tz != 1 || A.G.tx > 64 || A.G.ty > 64) return hipErrorInvalidValue;
     if (A.G.K == 4) hipLaunchKernelGGL(k_grelabel_wave<4>, dim3(blocks), dim3(64), 0, s, A);
