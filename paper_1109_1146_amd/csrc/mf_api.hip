@@ -936,14 +936,20 @@ static mf_status compute_marks(mf_grid *g, int32_t kind) {
     A.ringL = g->ringL; A.ringM = g->ringM; A.nring = g->nring;
     // 2D tiles of at most 64 x 64: one wavefront per region with row bitmasks
     const bool wave = g->ndim == 2 && G.tz == 1 && G.tx <= 64 && G.ty <= 64 && g->nring <= 256;
+    // 3D 6-connected tiles with 32-vertex rows: one workgroup per region, row bitmasks
+    const int Rr = G.ty * G.tz;
+    const bool rows = g->ndim == 3 && G.K == 6 && G.tx == 32 && G.ty >= 2 && G.tz >= 2 &&
+                      Rr % 64 == 0 && Rr <= 1024;
     int blocks = wave ? std::min(G.nreg, g->numCU * 16)
-                      : std::min(G.nreg, g->nslots * 4);  // scratch holds 4V ints per slot
+                      : (rows ? std::min(G.nreg, g->numCU * 2)
+                              : std::min(G.nreg, g->nslots * 4));  // scratch holds 4V ints per slot
     for (int round = 0;; round++) {
         A.round = round;
         A.dirtyIn = g->dirty + (size_t)(round & 1) * G.nreg;
         A.dirtyOut = g->dirty + (size_t)((round + 1) & 1) * G.nreg;
         HIP_TRY(hipMemsetAsync(g->changed, 0, sizeof(unsigned), s));
-        HIP_TRY(wave ? mfd::launch_flood_wave(A, blocks, s) : mfd::launch_flood(A, blocks, s));
+        HIP_TRY(wave ? mfd::launch_flood_wave(A, blocks, s)
+                     : (rows ? mfd::launch_flood_rows(A, blocks, s) : mfd::launch_flood(A, blocks, s)));
         HIP_TRY(hipMemcpyAsync(g->pinned, g->changed, sizeof(unsigned), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (*(unsigned *)g->pinned == 0u) break;

@@ -763,6 +763,140 @@ __global__ __launch_bounds__(kRowsNT) void k_grelabel_rows(GRelabelArgs A) {
     }
 }
 
+// Residual reachability for the cuts (the region floods of k_flood, same
+// marks) on the tiles of k_discharge_rows: one workgroup per region, one 32-bit
+// row per thread.  dir 0 floods forward from the excess vertices along arcs
+// with c_f > 0 (the masks are moved to the head of each arc), dir 1 backward
+// from t.  Reached border vertices mark their neighbours across the border
+// (atomic exchange, as k_flood) and flag the neighbouring region.
+__global__ __launch_bounds__(kRowsNT) void k_flood_rows(FloodArgs A) {
+    extern __shared__ __align__(16) unsigned smem_rows[];
+    __shared__ __align__(16) unsigned char anyB[2][kRowsWaves];  // block_any bytes
+    __shared__ int s_go;
+    const Geo &G = A.G;
+    const int V = G.V, N = G.N, TY = G.ty, TZ = G.tz, R = TY * TZ;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const bool myrow = tid < R;
+    const int row = tid, y = tid % TY, z = tid / TY;
+    unsigned *tmp = smem_rows;        // [7][R]: residual masks, then marks (or round-0 seeds)
+    unsigned *Fb = smem_rows + 7 * R; // [2][R]: frontier rows
+    int rc = 0;
+    for (int r = blockIdx.x; r < G.nreg; r += gridDim.x) {
+        if (tid == 0) {
+            s_go = (A.round == 0) ? 1 : A.dirtyIn[r];
+            A.dirtyIn[r] = 0;
+        }
+        __syncthreads();
+        const int go = s_go;
+        __syncthreads();
+        if (!go) continue;
+        const size_t base = (size_t)r * V;
+        // masks from HBM: plane q < 6 residual arcs, plane 6 the marks (all zero
+        // in round 0, when it holds the seeds instead)
+        {
+            const int row0 = wid * 64;
+            if (row0 + 64 <= R) {
+                for (int q = 0; q < 7; q++) {
+                    const int *plane = q < 6 ? A.res + (size_t)q * N
+                                             : (A.round > 0 ? A.mark : (A.dir == 0 ? A.ex : A.rt));
+                    const int *src = plane + base + (size_t)row0 * 32 + lane;
+#pragma unroll 8
+                    for (int i = 0; i < 32; i++) {
+                        const u64 b = __ballot(src[i * 64] > 0);
+                        if (lane == 0) {
+                            tmp[q * R + row0 + 2 * i] = (unsigned)b;
+                            tmp[q * R + row0 + 2 * i + 1] = (unsigned)(b >> 32);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        unsigned rk[6], rf[6], M = 0u;
+#pragma unroll
+        for (int k = 0; k < 6; k++) rk[k] = rf[k] = 0u;
+        if (myrow) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) rk[k] = tmp[k * R + row];
+            M = tmp[6 * R + row];
+            if (A.dir == 0) {
+                // at the head w: is the arc w - o_k -> w residual (inside the tile)
+                rf[0] = rk[0] << 1;
+                rf[1] = rk[1] >> 1;
+                rf[2] = (y > 0) ? tmp[2 * R + row - 1] : 0u;
+                rf[3] = (y + 1 < TY) ? tmp[3 * R + row + 1] : 0u;
+                rf[4] = (z > 0) ? tmp[4 * R + row - TY] : 0u;
+                rf[5] = (z + 1 < TZ) ? tmp[5 * R + row + TY] : 0u;
+            }
+        }
+        const unsigned M0 = A.round > 0 ? M : 0u;  // marks already stored
+        unsigned reached = M, F = M;
+        int p = 0;
+        for (;;) {
+            if (myrow) Fb[p * R + row] = F;
+            if (!block_any(F != 0u, anyB, rc)) break;
+            if (myrow) {
+                const unsigned *Fp = Fb + p * R;
+                const unsigned fyp = (y + 1 < TY) ? Fp[row + 1] : 0u;
+                const unsigned fym = (y > 0) ? Fp[row - 1] : 0u;
+                const unsigned fzp = (z + 1 < TZ) ? Fp[row + TY] : 0u;
+                const unsigned fzm = (z > 0) ? Fp[row - TY] : 0u;
+                unsigned nw;
+                if (A.dir == 0)
+                    nw = (rf[0] & (F << 1)) | (rf[1] & (F >> 1)) | (rf[2] & fym) | (rf[3] & fyp) |
+                         (rf[4] & fzm) | (rf[5] & fzp);
+                else
+                    nw = (rk[0] & (F >> 1)) | (rk[1] & (F << 1)) | (rk[2] & fyp) | (rk[3] & fym) |
+                         (rk[4] & fzp) | (rk[5] & fzm);
+                nw &= ~reached;
+                reached |= nw;
+                F = nw;
+            }
+            p ^= 1;
+        }
+        if (myrow && reached) {
+            // marks of this round, seeds included (stores of 1 race harmlessly
+            // with the neighbours' exchanges)
+            unsigned nb = reached & ~M0;
+            while (nb) {
+                const int x = __ffs(nb) - 1;
+                nb &= nb - 1;
+                A.mark[base + (size_t)row * 32 + x] = 1;
+            }
+            for (int k = 0; k < 6; k++) {
+                // reached border vertices of this row that direction k leaves the tile from
+                unsigned m;
+                if (k == 0) m = reached & 0x80000000u;
+                else if (k == 1) m = reached & 1u;
+                else if (k == 2) m = (y == TY - 1) ? reached : 0u;
+                else if (k == 3) m = (y == 0) ? reached : 0u;
+                else if (k == 4) m = (z == TZ - 1) ? reached : 0u;
+                else m = (z == 0) ? reached : 0u;
+                if (A.dir == 0) m &= rk[k];  // forward: the arc (v, v + o_k) is residual
+                while (m) {
+                    const int x = __ffs(m) - 1;
+                    m &= m - 1;
+                    const int wg = cross_nbr(G, r, z, y, x, k);
+                    if (wg < 0) continue;
+                    // backward: the arc (u, v) from u = v + o_k, in direction k ^ 1, is residual
+                    if (A.dir == 1 && A.res[(size_t)(k ^ 1) * N + wg] <= 0) continue;
+                    if (atomicExch(&A.mark[wg], 1) == 0) {
+                        A.dirtyOut[wg / V] = 1;
+                        atomicAdd(A.changed, 1u);
+                    }
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_flood_rows(const FloodArgs &A, int blocks, hipStream_t s) {
+    const int R = A.G.ty * A.G.tz;
+    if (A.G.K != 6 || A.G.tx != 32 || R % 64 != 0 || R > kRowsNT) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_flood_rows, dim3(blocks), dim3(kRowsNT), grelabel_rows_lds(A.G.ty, A.G.tz), s, A);
+    return hipGetLastError();
+}
+
 hipError_t launch_grelabel_rows(const GRelabelArgs &A, int blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_grelabel_rows, dim3(blocks), dim3(kRowsNT), grelabel_rows_lds(A.G.ty, A.G.tz), s, A);
     return hipGetLastError();

@@ -198,6 +198,7 @@ hipError_t launch_sum_i32(const int *a, int n, unsigned long long *out, hipStrea
 hipError_t launch_gather_plane(const Geo &G, const int *src, int *dst, int n, hipStream_t s);
 hipError_t launch_flood(const FloodArgs &A, int blocks, hipStream_t s);
 hipError_t launch_flood_wave(const FloodArgs &A, int blocks, hipStream_t s);
+hipError_t launch_flood_rows(const FloodArgs &A, int blocks, hipStream_t s);
 hipError_t launch_cut_out(const Geo &G, const int *mark, unsigned char *out, int n, int invert,
                           hipStream_t s);
 hipError_t launch_fill_i32(int *p, int n, int val, hipStream_t s);
