@@ -656,6 +656,23 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
 // ---------------------------------------------------------------------------
 size_t grelabel_rows_lds(int ty, int tz) { return (size_t)9 * ty * tz * sizeof(unsigned); }
 
+// The 64 row masks (32-bit, "value > 0") of 64 consecutive rows of one plane,
+// built by one wave: src points at this lane's vertex of the first two rows.
+// All 32 loads are issued before the first ballot, so they are in flight together.
+__device__ __forceinline__ void build_row_masks(const int *src, unsigned *dst, int lane) {
+    int v[32];
+#pragma unroll
+    for (int i = 0; i < 32; i++) v[i] = src[i * 64];
+#pragma unroll
+    for (int i = 0; i < 32; i++) {
+        const u64 b = __ballot(v[i] > 0);
+        if (lane == 0) {
+            dst[2 * i] = (unsigned)b;
+            dst[2 * i + 1] = (unsigned)(b >> 32);
+        }
+    }
+}
+
 __global__ __launch_bounds__(kRowsNT) void k_grelabel_rows(GRelabelArgs A) {
     extern __shared__ __align__(16) unsigned smem_rows[];
     __shared__ __align__(16) unsigned char anyB[2][kRowsWaves];  // block_any bytes
@@ -687,15 +704,7 @@ __global__ __launch_bounds__(kRowsNT) void k_grelabel_rows(GRelabelArgs A) {
             if (row0 + 64 <= R) {
                 for (int q = 0; q < 7; q++) {
                     const int *plane = q < 6 ? A.res + (size_t)q * N : A.rt;
-                    const int *src = plane + base + (size_t)row0 * 32 + lane;
-#pragma unroll 8
-                    for (int i = 0; i < 32; i++) {
-                        const u64 b = __ballot(src[i * 64] > 0);
-                        if (lane == 0) {
-                            tmp[q * R + row0 + 2 * i] = (unsigned)b;
-                            tmp[q * R + row0 + 2 * i + 1] = (unsigned)(b >> 32);
-                        }
-                    }
+                    build_row_masks(plane + base + (size_t)row0 * 32 + lane, tmp + q * R + row0, lane);
                 }
             }
             __syncthreads();
@@ -799,15 +808,7 @@ __global__ __launch_bounds__(kRowsNT) void k_flood_rows(FloodArgs A) {
                 for (int q = 0; q < 7; q++) {
                     const int *plane = q < 6 ? A.res + (size_t)q * N
                                              : (A.round > 0 ? A.mark : (A.dir == 0 ? A.ex : A.rt));
-                    const int *src = plane + base + (size_t)row0 * 32 + lane;
-#pragma unroll 8
-                    for (int i = 0; i < 32; i++) {
-                        const u64 b = __ballot(src[i * 64] > 0);
-                        if (lane == 0) {
-                            tmp[q * R + row0 + 2 * i] = (unsigned)b;
-                            tmp[q * R + row0 + 2 * i + 1] = (unsigned)(b >> 32);
-                        }
-                    }
+                    build_row_masks(plane + base + (size_t)row0 * 32 + lane, tmp + q * R + row0, lane);
                 }
             }
         }

@@ -780,16 +780,29 @@ __global__ __launch_bounds__(64) void k_grelabel_wave(GRelabelArgs A) {
         u64 *cr = (u64 *)A.cache + (size_t)r * (K + 1) * 64;
         u64 R[K], U = 0, SEED = 0;
         if (D == 0) {
-            for (int row = 0; row < TY; row++) {
-                const int l = row * TX + lane;
-                const bool ok = lane < TX;
+            // four rows of loads in flight at a time (addresses clamped, not predicated)
+            for (int row0 = 0; row0 < TY; row0 += 4) {
+                int v[4][K + 1];
 #pragma unroll
-                for (int k = 0; k < K; k++) {
-                    const u64 b = __ballot(ok && A.res[(size_t)k * N + base + l] > 0);
-                    if (lane == row) R[k] = b;
+                for (int j = 0; j < 4; j++) {
+                    const bool ok = lane < TX && row0 + j < TY;
+                    const int l = ok ? (row0 + j) * TX + lane : 0;
+#pragma unroll
+                    for (int k = 0; k < K; k++) v[j][k] = A.res[(size_t)k * N + base + l];
+                    v[j][K] = A.rt[base + l];
                 }
-                const u64 bs = __ballot(ok && A.rt[base + l] > 0);
-                if (lane == row) SEED = bs;
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const int row = row0 + j;
+                    const bool ok = lane < TX && row < TY;
+#pragma unroll
+                    for (int k = 0; k < K; k++) {
+                        const u64 b = __ballot(ok && v[j][k] > 0);
+                        if (lane == row) R[k] = b;
+                    }
+                    const u64 bs = __ballot(ok && v[j][K] > 0);
+                    if (lane == row) SEED = bs;
+                }
             }
             U = myrow ? rowmask : 0ull;  // every label is d_inf when a relabel starts
 #pragma unroll
@@ -906,20 +919,35 @@ __global__ __launch_bounds__(64) void k_flood_wave(FloodArgs A) {
         u64 R[K], M = 0, M0 = 0;
 #pragma unroll
         for (int k = 0; k < K; k++) R[k] = 0;
-        for (int row = 0; row < TY; row++) {
-            const int l = row * TX + lane;
-            const bool ok = lane < TX;
+        // four rows of loads in flight at a time (addresses clamped, not predicated)
+        const int *seedPlane = A.dir == 0 ? A.ex : A.rt;
+        for (int row0 = 0; row0 < TY; row0 += 4) {
+            int v[4][K + 2];
 #pragma unroll
-            for (int k = 0; k < K; k++) {
-                const u64 b = __ballot(ok && A.res[(size_t)k * N + base + l] > 0);
-                if (lane == row) R[k] = b;
+            for (int j = 0; j < 4; j++) {
+                const bool ok = lane < TX && row0 + j < TY;
+                const int l = ok ? (row0 + j) * TX + lane : 0;
+#pragma unroll
+                for (int k = 0; k < K; k++) v[j][k] = A.res[(size_t)k * N + base + l];
+                v[j][K] = A.mark[base + l];
+                v[j][K + 1] = A.round == 0 ? seedPlane[base + l] : 0;
             }
-            const bool m0 = ok && A.mark[base + l] != 0;
-            const bool sd = A.round == 0 && ok && (A.dir == 0 ? A.ex[base + l] > 0 : A.rt[base + l] > 0);
-            const u64 b0 = __ballot(m0), bm = __ballot(m0 || sd);
-            if (lane == row) {
-                M0 = b0;
-                M = bm;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int row = row0 + j;
+                const bool ok = lane < TX && row < TY;
+#pragma unroll
+                for (int k = 0; k < K; k++) {
+                    const u64 b = __ballot(ok && v[j][k] > 0);
+                    if (lane == row) R[k] = b;
+                }
+                const bool m0 = ok && v[j][K] != 0;
+                const bool sd = ok && v[j][K + 1] > 0;
+                const u64 b0 = __ballot(m0), bm = __ballot(m0 || sd);
+                if (lane == row) {
+                    M0 = b0;
+                    M = bm;
+                }
             }
         }
         u64 Rf[K];  // the arcs the flood follows, at the vertex it reaches
