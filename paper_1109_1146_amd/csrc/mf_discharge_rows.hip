@@ -248,12 +248,19 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
                     const int *plane = q < 6 ? A.res + (size_t)q * N : (q == 6 ? A.rt : A.ex);
                     unsigned *dst = q < 6 ? resM + q * R : (q == 6 ? rtmL : Fb);
                     const int *src = plane + base + (size_t)row0 * 32 + lane;
-#pragma unroll 8
-                    for (int i = 0; i < 32; i++) {
-                        const u64 b = __ballot(src[i * 64] > 0);
-                        if (lane == 0) {
-                            dst[row0 + 2 * i] = (unsigned)b;
-                            dst[row0 + 2 * i + 1] = (unsigned)(b >> 32);
+                    // eight loads in flight before their ballots (a load
+                    // followed at once by its ballot waits for each in turn)
+                    for (int i0 = 0; i0 < 32; i0 += 8) {
+                        int v[8];
+#pragma unroll
+                        for (int i = 0; i < 8; i++) v[i] = src[(i0 + i) * 64];
+#pragma unroll
+                        for (int i = 0; i < 8; i++) {
+                            const u64 b = __ballot(v[i] > 0);
+                            if (lane == 0) {
+                                dst[row0 + 2 * (i0 + i)] = (unsigned)b;
+                                dst[row0 + 2 * (i0 + i) + 1] = (unsigned)(b >> 32);
+                            }
                         }
                     }
                 }
