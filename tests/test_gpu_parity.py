@@ -395,3 +395,24 @@ def test_batch_workload_512_exact(mf):
     st = _batch_check(mf, insts, tune["region_shape"], global_relabel_every=tune["relabel_every"],
                       partial=tune["partial"], graph=True)
     assert st["sweeps"] > 0
+
+
+SERPENTINE_CASES = [
+    ((40, 48), 8, (8, 8)),        # wave floods, a path through 30 regions
+    ((37, 45), 4, (8, 16)),       # wave floods, ragged tiles
+    ((8, 32, 64), 6, (4, 16, 32)),  # rows floods
+    ((9, 10, 11), 6, (3, 4, 5)),  # queue floods (k_flood)
+]
+
+
+@pytest.mark.parametrize("case", range(len(SERPENTINE_CASES)))
+def test_serpentine_path_many_flood_rounds(mf, case):
+    """One residual path snaking across region borders: the flow has to cross
+    every border along it, and the cut floods need one round per crossing."""
+    from tests.helpers import serpentine_instance
+    dims, conn, tile = SERPENTINE_CASES[case]
+    inst, path = serpentine_instance(dims, conn, tile)
+    out, ref = _check(mf, inst, certify=False)
+    want = np.zeros(inst.n, np.uint8)
+    want[path] = 1
+    assert out["flow"] == 30 and (out["smin"] == want).all() and (out["smax"] == 1).all()

@@ -284,3 +284,22 @@ def test_reference_ard_partial_first_sweep_is_regionwise_maxflow():
         f = oracle.ard_grid(inst, partial=False, max_sweeps=1, stop_early=True)
         crossed_full += int((f["r_uv"][cross] != cuv[cross]).any())
     assert crossed_full > 0
+
+
+@pytest.mark.parametrize("dims,conn", [((12, 10), 4), ((9, 7), 8), ((4, 5, 6), 6)])
+def test_serpentine_closed_form(dims, conn):
+    """A single residual path through every vertex: flow = c(last, t), the
+    minimal source side is the path, the maximal source side is everything."""
+    from tests.helpers import serpentine_instance
+    inst, path = serpentine_instance(dims, conn, tile=dims)
+    assert len(set(path.tolist())) == len(path) and 0 < len(path) < inst.n
+    r = oracle.solve_grid(inst)
+    assert r["flow"] == 30
+    want = np.zeros(inst.n, np.uint8)
+    want[path] = 1
+    assert (r["smin"] == want).all()
+    assert (r["smax"] == 1).all()
+    for tile in ((3,) * len(dims), tuple(max(1, d // 2) for d in dims)):
+        inst.tile = tile
+        a = oracle.ard_grid(inst, checks=oracle.CHK_ALL)
+        assert a["flow"] == 30 and (a["smin"] == want).all() and (a["smax"] == 1).all()
