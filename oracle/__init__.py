@@ -14,7 +14,10 @@ What it computes (all integer, int64 accumulators):
 * ``ard_grid`` -- the paper's own method run step by step on the CPU: Init,
   Alg. 2 (P-ARD) or Alg. 1 (S-ARD), Proc. ARD with Augment (Sec. 4.2), region
   relabel (Alg. 3) and the global gap (Sec. 5.1), with the per-sweep checks of
-  the statements of Sec. 4 switched on by ``checks``.
+  the statements of Sec. 4 switched on by ``checks``; optionally with the
+  partial discharges (Sec. 6.2) and the boundary relabel heuristic (Sec. 6.1).
+* ``boundary_relabel`` -- the heuristic of Sec. 6.1 on a given state, written
+  separately in Python (groups, the two kinds of arcs, Dijkstra by heapq).
 * ``brute_force`` -- every cut of a network of at most ~20 vertices.
 * ``certify`` -- feasibility, conservation and max-flow = min-cut duality of a
   residual state, from the original capacities.
@@ -67,6 +70,9 @@ def _load():
                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                 P, P, P, P, P, P, P, P, P, P, P]
         lib.orc_ard.restype = ctypes.c_int
+        lib.orc_boundary_relabel.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P, P,
+                                             ctypes.c_int32, P]
+        lib.orc_boundary_relabel.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -172,13 +178,14 @@ def cuts_of_state(n, pu, pv, r_uv, r_vu, rt, ex):
 
 
 def ard_pairs(n, pu, pv, cuv, cvu, cs, ct, region, parallel=True, checks=CHK_ALL,
-              max_sweeps=None, partial=False, stop_early=False):
+              max_sweeps=None, partial=False, stop_early=False, boundary_relabel=False):
     """Reference ARD.  With partial=True sweep s runs only the stages k <= s
     (partial discharges, Sec. 6.2): excess may then stay inside a region, so the
     checks that only boundary vertices are active after the first sweep and that
     a discharge leaves no active vertex do not apply and are dropped.  With
-    stop_early, reaching max_sweeps returns the state after that many sweeps
-    (complete=False) instead of raising."""
+    boundary_relabel=True the heuristic of Sec. 6.1 runs after the flow fusion of
+    every sweep, before the gap.  With stop_early, reaching max_sweeps returns the
+    state after that many sweeps (complete=False) instead of raising."""
     lib = _load()
     if partial:
         checks &= ~(CHK_ACTIVE_B | CHK_DISCHARGE)
@@ -198,7 +205,8 @@ def ard_pairs(n, pu, pv, cuv, cvu, cs, ct, region, parallel=True, checks=CHK_ALL
     if max_sweeps is None:
         max_sweeps = (1 << 62)
     rc = lib.orc_ard(n, m, _p(pu), _p(pv), _p(cuv), _p(cvu), _p(cs), _p(ct), _p(region),
-                     1 if parallel else 0, 1 if partial else 0, int(max_sweeps), int(checks),
+                     1 if parallel else 0, (1 if partial else 0) | (2 if boundary_relabel else 0),
+                     int(max_sweeps), int(checks),
                      _p(r_uv), _p(r_vu),
                      _p(rt), _p(ex), _p(flow), _p(smin), _p(smax), _p(labels), _p(sweeps),
                      _p(bsize), _p(failed))
@@ -215,14 +223,84 @@ def ard_pairs(n, pu, pv, cuv, cvu, cs, ct, region, parallel=True, checks=CHK_ALL
 
 
 def ard_grid(inst, tile=None, parallel=True, checks=CHK_ALL, max_sweeps=None, partial=False,
-             stop_early=False):
+             stop_early=False, boundary_relabel=False):
     tile = tuple(tile if tile is not None else inst.tile)
     pu, pv, cuv, cvu = grid_pairs(inst.dims, inst.nbr, _offsets(inst))
     region = grid_regions(inst.dims, tile)
     out = ard_pairs(inst.n, pu, pv, cuv, cvu, inst.cs, inst.ct, region, parallel=parallel,
-                    checks=checks, max_sweeps=max_sweeps, partial=partial, stop_early=stop_early)
+                    checks=checks, max_sweeps=max_sweeps, partial=partial, stop_early=stop_early,
+                    boundary_relabel=boundary_relabel)
     out["pairs"] = (pu, pv, cuv, cvu)
     return out
+
+
+def boundary_relabel_c(n, pu, pv, r_uv, r_vu, region, labels, dinf):
+    """The C oracle's boundary relabel (the one orc_ard runs) on a given state."""
+    lib = _load()
+    pu, pv, r_uv, r_vu, region = map(_c32, (pu, pv, r_uv, r_vu, region))
+    out = np.array(labels, dtype=np.int32, copy=True)
+    rc = lib.orc_boundary_relabel(int(n), int(pu.shape[0]), _p(pu), _p(pv), _p(r_uv), _p(r_vu),
+                                  _p(region), int(dinf), _p(out))
+    if rc != 0:
+        raise RuntimeError(f"orc_boundary_relabel failed with code {rc}")
+    return out
+
+
+def boundary_relabel(n, pu, pv, r_uv, r_vu, region, labels, dinf):
+    """Boundary relabel heuristic of Sec. 6.1 on a residual state (pairs form).
+
+    Vertices with a label below dinf are grouped by (region, label); each group
+    gets an arc of length 0 to the group of the next larger label of its region
+    and the group of u an arc of length 1 to that of w for every residual arc
+    (u, w) between regions (r_uv for pu -> pv, r_vu for pv -> pu).  d' is the
+    distance from a vertex's group to the nearest group of label 0 (Dijkstra
+    over the reversed arcs from all label-0 groups, heapq); the result is
+    max(labels, d'), dinf where no label-0 group is reachable.  Interior
+    vertices are grouped with the rest (they have no arcs of length 1), so the
+    result is a valid labeling of all vertices.  Returns int32 labels."""
+    import heapq
+    labels = np.asarray(labels, dtype=np.int64)
+    region = np.asarray(region, dtype=np.int64)
+    part = np.flatnonzero(labels < dinf)
+    groups = {}
+    for v in part:
+        groups.setdefault((int(region[v]), int(labels[v])), len(groups))
+    rev = [[] for _ in range(len(groups))]  # reversed arcs: head group -> (tail group, length)
+    by_region = {}
+    for (rg, lab), q in groups.items():
+        by_region.setdefault(rg, []).append((lab, q))
+    for rg, lst in by_region.items():
+        lst.sort()
+        for (la, qa), (lb, qb) in zip(lst, lst[1:]):
+            rev[qb].append((qa, 0))  # arc qa -> qb of length 0
+    pu = np.asarray(pu, np.int64)
+    pv = np.asarray(pv, np.int64)
+    for a, b, r_ab, r_ba in zip(pu, pv, np.asarray(r_uv), np.asarray(r_vu)):
+        if region[a] == region[b] or labels[a] >= dinf or labels[b] >= dinf:
+            continue
+        ga = groups[(int(region[a]), int(labels[a]))]
+        gb = groups[(int(region[b]), int(labels[b]))]
+        if r_ab > 0:
+            rev[gb].append((ga, 1))
+        if r_ba > 0:
+            rev[ga].append((gb, 1))
+    dist = [None] * len(groups)
+    heap = [(0, q) for (rg, lab), q in groups.items() if lab == 0]
+    heapq.heapify(heap)
+    while heap:
+        d, q = heapq.heappop(heap)
+        if dist[q] is not None:
+            continue
+        dist[q] = d
+        for p, ln in rev[q]:
+            if dist[p] is None:
+                heapq.heappush(heap, (d + ln, p))
+    out = labels.copy()
+    for v in part:
+        dq = dist[groups[(int(region[v]), int(labels[v]))]]
+        dp = dinf if dq is None else min(dq, dinf)
+        out[v] = max(out[v], dp)
+    return out.astype(np.int32)
 
 
 # ---------------------------------------------------------------------------

@@ -17,12 +17,14 @@
  *   orc_cuts         residual reachability: S_max = V \ {v : v -> t} (Sec. 2,
  *                    max-preflow test) and S_min = {v : some excess vertex
  *                    reaches v}.
+ *   orc_boundary_relabel  the heuristic of Sec. 6.1 alone on a residual state.
  *   orc_ard          reference region discharge: Init, Alg. 1 (S-ARD) or Alg. 2
  *                    (P-ARD, label and flow fusion), Proc. ARD with Augment
  *                    (Sec. 4.2), region relabel (Alg. 3, ARD variant) and the
  *                    global gap heuristic (Sec. 5.1) over boundary labels, with
  *                    optional per-sweep checks of the statements of Sec. 4;
- *                    optionally with partial discharges (Sec. 6.2).
+ *                    optionally with partial discharges (Sec. 6.2) and the
+ *                    boundary relabel heuristic (Sec. 6.1) after every sweep.
  *
  * Input network format (all entry points): n non-terminal vertices 0..n-1 and
  * np vertex pairs {pu[i], pv[i]} with capacities c(pu,pv)=cuv[i] and
@@ -742,6 +744,175 @@ static void ard_region_distance(ard_t *A, int32_t *dist) {
     free(cur); free(nxt);
 }
 
+/* Boundary relabel heuristic (Sec. 6.1), with the auxiliary graph built as
+ * the section describes:
+ *   - nodes: the vertices of every region grouped by label, labels below dinf
+ *     only (vertices labelled dinf take no part);
+ *   - an arc of length 0 from each group to the group of the next larger label
+ *     of the same region (a vertex may reach a higher-labelled one inside its
+ *     region, never a lower-labelled one: validity);
+ *   - an arc of length 1 from the group of u to the group of w for every
+ *     residual arc (u, w) between regions.
+ * d'(u) is the length of a shortest path from the group of u to a group of
+ * label 0, by Dijkstra's algorithm (run from the label-0 groups over the
+ * reversed arcs), and the labels become max(d, d'), with dinf where no label-0
+ * group is reached.  The section groups the boundary vertices; interior
+ * vertices are grouped too, so the whole labeling stays valid (an interior
+ * group has no arc of length 1, so it only passes on the distance of the next
+ * larger label of its region, and the boundary groups' distances are the same
+ * either way).  Returns 0 or ORC_ENOMEM. */
+typedef struct { int64_t key; int32_t v; } brl_item_t;
+
+static int brl_cmp(const void *a, const void *b) {
+    int64_t x = ((const brl_item_t *)a)->key, y = ((const brl_item_t *)b)->key;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static int ard_boundary_relabel(ard_t *A) {
+    net_t *g = A->g;
+    const int32_t n = g->n;
+    const int64_t INF = INT64_MAX;
+    int rc = ORC_OK;
+    brl_item_t *it = malloc(sizeof(brl_item_t) * (size_t)(n ? n : 1));
+    int32_t *grp = malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    int32_t *glab = malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    int32_t *greg = malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    int64_t *first = NULL, *dist = NULL, *heap = NULL;
+    int32_t *to = NULL, *len = NULL, *afrom = NULL, *ato = NULL, *alen = NULL;
+    if (!it || !grp || !glab || !greg) { rc = ORC_ENOMEM; goto out; }
+    /* groups: vertices with d < dinf sorted by (region, label) */
+    int32_t cnt = 0;
+    for (int32_t v = 0; v < n; v++) {
+        grp[v] = -1;
+        if (A->d[v] >= A->dinf) continue;
+        it[cnt].key = (int64_t)A->region[v] * ((int64_t)A->dinf + 1) + A->d[v];
+        it[cnt].v = v;
+        cnt++;
+    }
+    qsort(it, (size_t)cnt, sizeof(brl_item_t), brl_cmp);
+    int32_t ng = 0;
+    for (int32_t i = 0; i < cnt; i++) {
+        if (i == 0 || it[i].key != it[i - 1].key) {
+            glab[ng] = A->d[it[i].v];
+            greg[ng] = A->region[it[i].v];
+            ng++;
+        }
+        grp[it[i].v] = ng - 1;
+    }
+    /* arcs of the auxiliary graph, (from, to, length) */
+    int64_t cap = (int64_t)ng + g->m + 1, na = 0;
+    afrom = malloc(sizeof(int32_t) * (size_t)cap);
+    ato = malloc(sizeof(int32_t) * (size_t)cap);
+    alen = malloc(sizeof(int32_t) * (size_t)cap);
+    if (!afrom || !ato || !alen) { rc = ORC_ENOMEM; goto out; }
+    for (int32_t q = 0; q + 1 < ng; q++)
+        if (greg[q] == greg[q + 1]) { afrom[na] = q; ato[na] = q + 1; alen[na] = 0; na++; }
+    for (int64_t a = 0; a < g->m; a++) {
+        if (g->res[a] <= 0) continue;
+        int32_t u = g->tail[a], w = g->head[a];
+        if (A->region[u] == A->region[w] || grp[u] < 0 || grp[w] < 0) continue;
+        afrom[na] = grp[u]; ato[na] = grp[w]; alen[na] = 1; na++;
+    }
+    /* reversed adjacency (CSR over the arc heads) */
+    first = calloc((size_t)ng + 1, sizeof(int64_t));
+    to = malloc(sizeof(int32_t) * (size_t)(na ? na : 1));
+    len = malloc(sizeof(int32_t) * (size_t)(na ? na : 1));
+    dist = malloc(sizeof(int64_t) * (size_t)(ng ? ng : 1));
+    heap = malloc(sizeof(int64_t) * (size_t)(na + ng + 1));
+    if (!first || !to || !len || !dist || !heap) { rc = ORC_ENOMEM; goto out; }
+    for (int64_t e = 0; e < na; e++) first[ato[e] + 1]++;
+    for (int32_t q = 0; q < ng; q++) first[q + 1] += first[q];
+    {
+        int64_t *fill = malloc(sizeof(int64_t) * ((size_t)ng + 1));
+        if (!fill) { rc = ORC_ENOMEM; goto out; }
+        memcpy(fill, first, sizeof(int64_t) * ((size_t)ng + 1));
+        for (int64_t e = 0; e < na; e++) {
+            int64_t k = fill[ato[e]]++;
+            to[k] = afrom[e];
+            len[k] = alen[e];
+        }
+        free(fill);
+    }
+    /* Dijkstra from every label-0 group; heap entries are dist * 2^31 + group */
+    int64_t hn = 0;
+    for (int32_t q = 0; q < ng; q++) {
+        dist[q] = INF;
+        if (glab[q] == 0) {
+            dist[q] = 0;
+            heap[hn++] = q; /* distance 0: key = group */
+        }
+    }
+    /* heapify (keys are distinct: the group is part of the key) */
+    for (int64_t i = hn / 2 - 1; i >= 0; i--) {
+        int64_t j = i;
+        for (;;) {
+            int64_t l = 2 * j + 1, r = l + 1, m = j;
+            if (l < hn && heap[l] < heap[m]) m = l;
+            if (r < hn && heap[r] < heap[m]) m = r;
+            if (m == j) break;
+            int64_t t = heap[j]; heap[j] = heap[m]; heap[m] = t; j = m;
+        }
+    }
+    while (hn > 0) {
+        int64_t top = heap[0];
+        heap[0] = heap[--hn];
+        for (int64_t j = 0;;) {
+            int64_t l = 2 * j + 1, r = l + 1, m = j;
+            if (l < hn && heap[l] < heap[m]) m = l;
+            if (r < hn && heap[r] < heap[m]) m = r;
+            if (m == j) break;
+            int64_t t = heap[j]; heap[j] = heap[m]; heap[m] = t; j = m;
+        }
+        int64_t du = top >> 31;
+        int32_t q = (int32_t)(top & 0x7fffffff);
+        if (du != dist[q]) continue; /* stale entry */
+        for (int64_t k = first[q]; k < first[q + 1]; k++) {
+            int32_t p = to[k];
+            int64_t nd = du + len[k];
+            if (nd < dist[p]) {
+                dist[p] = nd;
+                int64_t j = hn++;
+                heap[j] = (nd << 31) | p;
+                while (j > 0 && heap[(j - 1) / 2] > heap[j]) {
+                    int64_t t = heap[j]; heap[j] = heap[(j - 1) / 2]; heap[(j - 1) / 2] = t;
+                    j = (j - 1) / 2;
+                }
+            }
+        }
+    }
+    /* d := max(d, d') */
+    for (int32_t v = 0; v < n; v++) {
+        if (grp[v] < 0) continue;
+        int64_t dp = dist[grp[v]];
+        if (dp > A->dinf) dp = A->dinf;
+        if (dp > A->d[v]) A->d[v] = (int32_t)dp;
+    }
+out:
+    free(it); free(grp); free(glab); free(greg); free(first); free(dist); free(heap);
+    free(to); free(len); free(afrom); free(ato); free(alen);
+    return rc;
+}
+
+/* The heuristic alone on a given residual state: c(pu, pv) = r_uv[i] and
+ * c(pv, pu) = r_vu[i] are the residuals, labels (n entries, values in
+ * 0..dinf) are raised in place. */
+int orc_boundary_relabel(int32_t n, int64_t np, const int32_t *pu, const int32_t *pv,
+                         const int32_t *r_uv, const int32_t *r_vu, const int32_t *region,
+                         int32_t dinf, int32_t *labels) {
+    net_t g;
+    int rc = net_build(&g, n, np, pu, pv, r_uv, r_vu);
+    if (rc) return rc;
+    ard_t A;
+    memset(&A, 0, sizeof(A));
+    A.g = &g;
+    A.region = region;
+    A.d = labels;
+    A.dinf = dinf;
+    rc = ard_boundary_relabel(&A);
+    net_free(&g);
+    return rc;
+}
+
 /* Validity of a labeling w.r.t. the region distance (Sec. 4.1). */
 static int ard_valid(const ard_t *A, const int32_t *d) {
     net_t *g = A->g;
@@ -764,9 +935,13 @@ static int ard_valid(const ard_t *A, const int32_t *d) {
 #define ORC_CHK_LOWER 8     /* labels never exceed the exact region distance */
 #define ORC_CHK_DISCHARGE 16 /* no active vertex left in a region right after its discharge */
 
+/* heuristics of Sec. 6 (bits of orc_ard's heur) */
+#define ORC_HEUR_PARTIAL 1  /* partial discharges (Sec. 6.2) */
+#define ORC_HEUR_BRL 2      /* boundary relabel after every sweep (Sec. 6.1) */
+
 int orc_ard(int32_t n, int64_t np, const int32_t *pu, const int32_t *pv, const int32_t *cuv,
             const int32_t *cvu, const int32_t *cs, const int32_t *ct, const int32_t *region,
-            int32_t parallel, int32_t partial, int64_t max_sweeps, int32_t checks, int64_t *r_uv,
+            int32_t parallel, int32_t heur, int64_t max_sweeps, int32_t checks, int64_t *r_uv,
             int64_t *r_vu,
             int64_t *rt_out, int64_t *ex_out, int64_t *flow_out, uint8_t *smin, uint8_t *smax,
             int32_t *labels_out, int64_t *sweeps_out, int64_t *bsize_out, int32_t *failed_check) {
@@ -848,7 +1023,8 @@ int orc_ard(int32_t n, int64_t np, const int32_t *pu, const int32_t *pv, const i
         }
         memcpy(dprev, A.d, sizeof(int32_t) * nn);
         /* partial discharges: sweep s runs stages up to s only */
-        const int32_t cap = partial ? (int32_t)(sweeps < INT32_MAX ? sweeps : INT32_MAX) : INT32_MAX;
+        const int32_t cap = (heur & ORC_HEUR_PARTIAL) ? (int32_t)(sweeps < INT32_MAX ? sweeps : INT32_MAX)
+                                                      : INT32_MAX;
         sweeps++;
         if (parallel) {
             /* Alg. 2: all regions discharge against the labels of the sweep start */
@@ -884,6 +1060,8 @@ int orc_ard(int32_t n, int64_t np, const int32_t *pu, const int32_t *pv, const i
                     A.ex[u] += p;
                 }
             }
+            /* boundary relabel on the fused state, then the gap over its labels */
+            if ((heur & ORC_HEUR_BRL) && (rc = ard_boundary_relabel(&A)) != ORC_OK) goto done;
             ard_gap(&A);
         } else {
             /* Alg. 1: regions one by one, each sees the current state */
@@ -914,6 +1092,7 @@ int orc_ard(int32_t n, int64_t np, const int32_t *pu, const int32_t *pv, const i
                 }
                 ard_gap(&A);
             }
+            if ((heur & ORC_HEUR_BRL) && (rc = ard_boundary_relabel(&A)) != ORC_OK) goto done;
         }
         if (checks & ORC_CHK_MONO)
             for (int32_t v = 0; v < n; v++)

@@ -79,3 +79,16 @@ def serpentine_instance(dims, conn, tile, fwd=50, src=100, sink=30, frac=2 / 3):
     inst = synth.GridInstance(dims=dims, conn=conn, cs=cs, ct=ct, nbr=nbr, tile=tuple(tile),
                               name=f"serpentine{nd}d{conn}_{'x'.join(map(str, dims))}")
     return inst, np.array(path, np.int64)
+
+
+def region_chain_instance(L, w, excess=10, big=1000):
+    """A 1 x (L w) 4-connected grid cut into L regions of width w: arcs of
+    capacity big to the right, excess at the first vertex of every region and
+    c(last, t) = big.  After the first P-ARD sweep every region but the last
+    is labelled 1 (it reaches only its right neighbour's boundary, labelled 0
+    at the start) and the last one 0; the exact region distance of region j is
+    L - 1 - j, and the flow is L * excess."""
+    inst, _ = serpentine_instance((1, L * w), 4, (1, w), fwd=big, src=excess, sink=big, frac=1.0)
+    inst.cs[::w] = excess
+    inst.name = f"regionchain_{L}x{w}"
+    return inst

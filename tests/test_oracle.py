@@ -303,3 +303,128 @@ def test_serpentine_closed_form(dims, conn):
         inst.tile = tile
         a = oracle.ard_grid(inst, checks=oracle.CHK_ALL)
         assert a["flow"] == 30 and (a["smin"] == want).all() and (a["smax"] == 1).all()
+
+
+# ---------------------------------------------------------------------------
+# Boundary relabel heuristic (Sec. 6.1)
+# ---------------------------------------------------------------------------
+
+def _region_distance(n, pu, pv, r_uv, r_vu, region, rt, dinf):
+    """Exact d*B (Sec. 4.1) by 0-1 breadth-first search towards t: an arc
+    between regions has length 1, one inside a region length 0."""
+    from collections import deque
+    rev = [[] for _ in range(n)]  # v -> (u, length) for residual arcs u -> v
+    for a, b, x, y in zip(pu, pv, r_uv, r_vu):
+        ln = int(region[a] != region[b])
+        if x > 0:
+            rev[b].append((a, ln))
+        if y > 0:
+            rev[a].append((b, ln))
+    dist = np.full(n, dinf, np.int64)
+    dq = deque()
+    for v in np.flatnonzero(rt > 0):
+        dist[v] = 0
+        dq.append(v)
+    while dq:
+        v = dq.popleft()
+        for u, ln in rev[v]:
+            if dist[v] + ln < dist[u]:
+                dist[u] = dist[v] + ln
+                (dq.appendleft if ln == 0 else dq.append)(u)
+    return dist
+
+
+def _assert_valid(pu, pv, r_uv, r_vu, region, rt, d):
+    """Validity of Sec. 4.1 on every residual arc, and d = 0 wherever r_t > 0."""
+    ln = (region[pu] != region[pv]).astype(np.int64)
+    d = d.astype(np.int64)
+    assert (d[pu][r_uv > 0] <= (d[pv] + ln)[r_uv > 0]).all()
+    assert (d[pv][r_vu > 0] <= (d[pu] + ln)[r_vu > 0]).all()
+    assert (d[rt > 0] == 0).all()
+
+
+@pytest.mark.parametrize("L,w", [(6, 8), (3, 5), (9, 4)])
+def test_boundary_relabel_region_chain_closed_form(L, w):
+    """After the first sweep the labels are 1 in every region but the last;
+    the heuristic lifts region j to L - 1 - j, its exact region distance."""
+    from tests.helpers import region_chain_instance
+    inst = region_chain_instance(L, w)
+    j = np.repeat(np.arange(L), w)
+    plain = oracle.ard_grid(inst, max_sweeps=1, stop_early=True)
+    assert (plain["labels"] == np.where(j < L - 1, 1, 0)).all()
+    brl = oracle.ard_grid(inst, max_sweeps=1, stop_early=True, boundary_relabel=True)
+    assert (brl["labels"] == L - 1 - j).all()
+    # the stand-alone heuristics (C and Python) on the plain state agree
+    pu, pv, _, _ = plain["pairs"]
+    region = oracle.grid_regions(inst.dims, inst.tile)
+    for f in (oracle.boundary_relabel, oracle.boundary_relabel_c):
+        got = f(inst.n, pu, pv, plain["r_uv"], plain["r_vu"], region, plain["labels"], plain["bsize"])
+        assert (got == L - 1 - j).all()
+    full = oracle.ard_grid(inst, boundary_relabel=True)
+    assert full["flow"] == L * 10 == oracle.solve_grid(inst)["flow"]
+
+
+BRL_CASES = [((12, 13), 4, (4, 5)), ((16, 16), 8, (4, 8)), ((6, 7, 8), 6, (3, 4, 4)),
+             ((20, 9), 8, (5, 3)), ((5, 9, 13), 6, (5, 4, 6)), ((30, 30), 4, (6, 6))]
+
+
+@pytest.mark.parametrize("seed", range(18))
+def test_boundary_relabel_valid_lower_bound_and_two_implementations(seed):
+    """On the state after s plain sweeps: the C heuristic and the separate
+    Python one give the same labels, which never decrease, form a valid
+    labeling and never exceed the exact region distance d*B."""
+    dims, conn, tile = BRL_CASES[seed % len(BRL_CASES)]
+    maker = synth.blob_grid if seed % 2 else synth.random_grid
+    inst = (maker(dims, conn, 1500 + seed, 3, 2.0, 6.0, tile=tile) if seed % 2
+            else maker(dims, conn, 1500 + seed, tile=tile))
+    region = oracle.grid_regions(inst.dims, tile)
+    lifted = 0
+    for s in (1, 2, 3):
+        a = oracle.ard_grid(inst, max_sweeps=s, stop_early=True)
+        pu, pv, _, _ = a["pairs"]
+        d0 = a["labels"]
+        dinf = a["bsize"] if a["bsize"] > 0 else 1
+        py = oracle.boundary_relabel(inst.n, pu, pv, a["r_uv"], a["r_vu"], region, d0, dinf)
+        c = oracle.boundary_relabel_c(inst.n, pu, pv, a["r_uv"], a["r_vu"], region, d0, dinf)
+        assert (py == c).all()
+        assert (c >= d0).all() and (c <= dinf).all()
+        _assert_valid(pu, pv, a["r_uv"], a["r_vu"], region, a["rt"], c)
+        dstar = _region_distance(inst.n, pu, pv, a["r_uv"], a["r_vu"], region, a["rt"], dinf)
+        assert (c <= dstar).all()
+        lifted += int((c > d0).sum())
+        if a["complete"]:
+            break
+    print(f"{inst.name}: {lifted} labels lifted", flush=True)
+
+
+def test_boundary_relabel_lifts_labels_somewhere():
+    """The heuristic is not the identity on the random families above."""
+    lifted = 0
+    for seed in range(6):
+        dims, conn, tile = BRL_CASES[seed]
+        inst = synth.random_grid(dims, conn, 1600 + seed, tile=tile)
+        region = oracle.grid_regions(inst.dims, tile)
+        a = oracle.ard_grid(inst, max_sweeps=1, stop_early=True)
+        pu, pv, _, _ = a["pairs"]
+        c = oracle.boundary_relabel_c(inst.n, pu, pv, a["r_uv"], a["r_vu"], region, a["labels"],
+                                      max(a["bsize"], 1))
+        lifted += int((c > a["labels"]).sum())
+    assert lifted > 0
+
+
+@pytest.mark.parametrize("partial", [False, True])
+@pytest.mark.parametrize("seed", range(12))
+def test_reference_ard_boundary_relabel_exact_and_invariants(seed, partial):
+    """P-ARD with the heuristic after every sweep: the flow is the textbook
+    maximum, the per-sweep checks (validity, monotone labels, labels below the
+    exact region distance) hold, and the sweep count stays within 2|B|^2+1."""
+    dims, conn, tile = BRL_CASES[seed % len(BRL_CASES)]
+    inst = synth.random_grid(dims, conn, 1700 + seed, tile=tile)
+    ref = oracle.solve_grid(inst)
+    a = oracle.ard_grid(inst, partial=partial, boundary_relabel=True, checks=oracle.CHK_ALL)
+    assert a["flow"] == ref["flow"]
+    assert (a["smin"] == ref["smin"]).all() and (a["smax"] == ref["smax"]).all()
+    assert a["sweeps"] <= 2 * max(a["bsize"], 1) ** 2 + 1
+    s = oracle.ard_grid(inst, parallel=False, partial=partial, boundary_relabel=True,
+                        checks=oracle.CHK_ALL)
+    assert s["flow"] == ref["flow"]
