@@ -101,6 +101,12 @@ typedef struct {
                                      t only), the region relabel stays complete, and excess the cap
                                      holds back stays active for later sweeps; the flow and cuts are
                                      the same, sweeps can be more and cheaper.  0 = off */
+    int32_t boundary_relabel;     /* n in 1..4096: the boundary relabel heuristic (Sec. 6.1, see
+                                     mf_boundary_relabel) after the flow fusion of every sweep,
+                                     before the gap, with at most n levels of its search per sweep
+                                     (labels it has not reached by then are lifted to n + 1 at most,
+                                     which keeps them valid); n level kernels are launched per sweep
+                                     (those after the search ended exit at once).  0 = off */
 } mf_solve_opts;
 
 /* region features (floats) written per region and sweep, see mf_solve_opts.features */
@@ -214,10 +220,28 @@ mf_status mf_flow_value(const mf_grid *g, int64_t *out);
  * MF_E_INVAL, MF_E_DEVICE. */
 mf_status mf_min_cut(const mf_grid *g, int32_t kind, uint8_t *out_source_side);
 
-/* Final state of the last solve in the row-major layout of the inputs, for
- * certification: residuals [K][n] (c_f(v, v+o_k)), residual t-links [n],
- * excess [n], labels [n].  Any pointer may be NULL.  Host arrays. */
+/* State after the last solve (completed, or stopped by max_sweeps with
+ * MF_E_SWEEPS) in the row-major layout of the inputs, for certification:
+ * residuals [K][n] (c_f(v, v+o_k)), residual t-links [n], excess [n], labels
+ * [n].  Any pointer may be NULL.  Host arrays.  Errors: MF_E_STATE if no solve
+ * has left a state, MF_E_DEVICE. */
 mf_status mf_get_state(const mf_grid *g, int32_t *res, int32_t *rt, int32_t *ex, int32_t *labels);
+
+/* Boundary relabel heuristic (Sec. 6.1) on the state the last solve left
+ * (see mf_get_state).  The labels of the boundary vertices B with d(u) < dinf
+ * are grouped by region and label; a group reaches the group of the next larger
+ * label of its region at length 0, and the group of u reaches the group of w at
+ * length 1 for every residual arc (u, w) between regions.  d'(u) is the distance
+ * from u's group to a group of label 0 and the labels of B become
+ * max(d(u), min(d'(u), dinf)); interior labels are left as they are (the next
+ * discharge of a region recomputes them before anything reads them).
+ *   max_levels  n > 0: at most n levels of the search (unreached labels are
+ *               lifted to n + 1 at most, a valid lower bound)
+ *   levels_out  receives the number of levels that assigned a distance (may be NULL)
+ * Runs on the device (one workgroup per region and level, levels launched in
+ * batches of eight until the search ends).  Errors: MF_E_INVAL, MF_E_STATE,
+ * MF_E_DEVICE. */
+mf_status mf_boundary_relabel(mf_grid *g, int32_t max_levels, int64_t *levels_out);
 
 /* Shape facts of a handle: number of vertices, K, regions, |B|, region shape. */
 mf_status mf_get_info(const mf_grid *g, int64_t *n, int32_t *K, int64_t *regions,

@@ -246,7 +246,7 @@ def boundary_relabel_c(n, pu, pv, r_uv, r_vu, region, labels, dinf):
     return out
 
 
-def boundary_relabel(n, pu, pv, r_uv, r_vu, region, labels, dinf):
+def boundary_relabel(n, pu, pv, r_uv, r_vu, region, labels, dinf, distances=False):
     """Boundary relabel heuristic of Sec. 6.1 on a residual state (pairs form).
 
     Vertices with a label below dinf are grouped by (region, label); each group
@@ -257,7 +257,9 @@ def boundary_relabel(n, pu, pv, r_uv, r_vu, region, labels, dinf):
     over the reversed arcs from all label-0 groups, heapq); the result is
     max(labels, d'), dinf where no label-0 group is reachable.  Interior
     vertices are grouped with the rest (they have no arcs of length 1), so the
-    result is a valid labeling of all vertices.  Returns int32 labels."""
+    result is a valid labeling of all vertices.  Returns int32 labels, and with
+    distances=True also d' itself (int64, -1 where no label-0 group is reached
+    or the vertex takes no part)."""
     import heapq
     labels = np.asarray(labels, dtype=np.int64)
     region = np.asarray(region, dtype=np.int64)
@@ -296,10 +298,15 @@ def boundary_relabel(n, pu, pv, r_uv, r_vu, region, labels, dinf):
             if dist[p] is None:
                 heapq.heappush(heap, (d + ln, p))
     out = labels.copy()
+    dprime = np.full(len(labels), -1, np.int64)
     for v in part:
         dq = dist[groups[(int(region[v]), int(labels[v]))]]
         dp = dinf if dq is None else min(dq, dinf)
         out[v] = max(out[v], dp)
+        if dq is not None:
+            dprime[v] = dq
+    if distances:
+        return out.astype(np.int32), dprime
     return out.astype(np.int32)
 
 

@@ -27,6 +27,8 @@ struct mf_grid {
     // device state
     int *res = nullptr, *rt = nullptr, *ex = nullptr, *lab[2] = {nullptr, nullptr};
     int *pushb = nullptr, *ractive = nullptr, *order = nullptr, *bidx = nullptr;
+    int *bstart = nullptr;        // [nreg + 1]: the boundary vertices of region r are bidx[bstart[r]..bstart[r+1])
+    unsigned int *brlctl = nullptr;  // boundary relabel control words
     int *ringL = nullptr, *rvcount = nullptr, *mark = nullptr, *dirty = nullptr;
     unsigned char *ringM = nullptr, *cutbuf = nullptr, *cand = nullptr;  // cand: 2 x N
     unsigned char *ringX = nullptr;  // per border vertex and leaving direction: region offset (2 bits per axis)
@@ -53,6 +55,7 @@ struct mf_grid {
     u64 *pinned = nullptr;        // host pinned mailbox
     // instance state
     bool has_caps = false, solved = false;
+    bool has_state = false;       // a solve left a state (completed, or stopped by max_sweeps)
     long long sum_cs = 0, sum_ct = 0, flow = 0;
     int final_parity = 0;
     int cut_kind_cached = -1;     // kind whose reachability marks g->mark holds
@@ -91,7 +94,7 @@ static void free_all(mf_grid *g) {
                     g->bidx, g->ringL, g->rvcount, g->mark, g->dirty, g->ringM, g->ringX, g->cutbuf,
                     g->in_cs, g->in_ct, g->in_nbr, g->scratch, g->act, g->qhead, g->hist,
                     g->maxlab, g->gap, g->err, g->counters, g->stats, g->sums, g->changed,
-                    g->tmp_plane, g->cand};
+                    g->tmp_plane, g->cand, g->bstart, g->brlctl};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (g->reginst) (void)hipFree(g->reginst);
@@ -228,7 +231,9 @@ static mf_status create_impl(int32_t ndim, const int64_t *dims, int32_t connecti
     // boundary set B (Sec. 4.1): real vertices with a real grid neighbour in another region
     std::vector<int> bidx;
     std::vector<int> rvcount(G.nreg);
+    std::vector<int> bstart(G.nreg + 1, 0);
     for (int r = 0; r < G.nreg; r++) {
+        bstart[r] = (int)bidx.size();
         int rx = r % G.rx, tt = r / G.rx, ry = tt % G.ry, rz = tt / G.ry;
         int oz = rz * G.tz, oy = ry * G.ty, ox = rx * G.tx;
         rvcount[r] = std::min(G.tz, G.dz - oz) * std::min(G.ty, G.dy - oy) * std::min(G.tx, G.dx - ox);
@@ -246,6 +251,7 @@ static mf_status create_impl(int32_t ndim, const int64_t *dims, int32_t connecti
             if (inB) bidx.push_back(r * G.V + l);
         }
     }
+    bstart[G.nreg] = (int)bidx.size();
     g->nB = (long long)bidx.size();
     g->dinf = g->nB > 0 ? (int)g->nB : 1;
 
@@ -287,7 +293,8 @@ static mf_status create_impl(int32_t ndim, const int64_t *dims, int32_t connecti
                 ok(dalloc(&g->qhead, 4)) && ok(dalloc(&g->hist, (size_t)mfd::kHistBins)) &&
                 ok(dalloc(&g->maxlab, 1)) && ok(dalloc(&g->gap, 1)) && ok(dalloc(&g->err, 4)) &&
                 ok(dalloc(&g->counters, 4)) && ok(dalloc(&g->stats, 16)) && ok(dalloc(&g->sums, 4)) &&
-                ok(dalloc(&g->changed, 8)) &&
+                ok(dalloc(&g->changed, 8)) && ok(dalloc(&g->bstart, (size_t)G.nreg + 1)) &&
+                ok(dalloc(&g->brlctl, 8)) &&
                 ok(hipHostMalloc((void **)&g->pinned, 32 * sizeof(u64), hipHostMallocDefault));
     if (!good) {
         (void)hipGetLastError();
@@ -299,6 +306,7 @@ static mf_status create_impl(int32_t ndim, const int64_t *dims, int32_t connecti
     for (int r = 0; r < G.nreg; r++) order[r] = r;
     good = ok(hipMemcpy(g->order, order.data(), sizeof(int) * G.nreg, hipMemcpyHostToDevice)) &&
            ok(hipMemcpy(g->rvcount, rvcount.data(), sizeof(int) * G.nreg, hipMemcpyHostToDevice)) &&
+           ok(hipMemcpy(g->bstart, bstart.data(), sizeof(int) * (G.nreg + 1), hipMemcpyHostToDevice)) &&
            (bidx.empty() || ok(hipMemcpy(g->bidx, bidx.data(), sizeof(int) * bidx.size(), hipMemcpyHostToDevice))) &&
            (ringL.empty() || ok(hipMemcpy(g->ringL, ringL.data(), sizeof(int) * ringL.size(), hipMemcpyHostToDevice))) &&
            (ringM.empty() || ok(hipMemcpy(g->ringM, ringM.data(), ringM.size(), hipMemcpyHostToDevice))) &&
@@ -622,6 +630,9 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     int check_every = o.check_every > 0 ? o.check_every : 8;
     if (o.global_relabel_every < 0) return MF_E_INVAL;
     if (o.partial != 0 && o.partial != 1) return MF_E_INVAL;
+    // the level budget is also the number of level launches per sweep
+    if (o.boundary_relabel < 0 || o.boundary_relabel > 4096) return MF_E_INVAL;
+    const int brl = o.boundary_relabel;
     if (o.global_relabel_every > 0) check_every = o.global_relabel_every;
     long long B = g->nB > 0 ? g->nB : 1;
     long long bound = (B > 2000000000LL) ? (1LL << 62) : 2 * B * B + 1;
@@ -637,6 +648,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         check_every += check_every & 1;  // whole even/odd sweep pairs
     }
     g->solved = false;
+    g->has_state = false;
     g->cut_kind_cached = -1;
     const Geo &G = g->G;
     auto t0 = std::chrono::high_resolution_clock::now();
@@ -729,6 +741,15 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     memset(&F, 0, sizeof(F));
     F.G = G; F.bidx = g->bidx; F.nB = (int)g->nB; F.res = g->res; F.ex = g->ex; F.pushb = g->pushb;
     F.dinf = g->dinf; F.hist = g->hist; F.maxlab = g->maxlab;
+    // with the boundary relabel the histogram is built from its lifted labels
+    F.histOn = brl > 0 ? 0 : 1;
+    // boundary relabel after the fusion; its distances use the cut marks' buffer
+    // (free during a solve)
+    mfd::BrlArgs BA;
+    memset(&BA, 0, sizeof(BA));
+    BA.G = G; BA.bidx = g->bidx; BA.bstart = g->bstart; BA.nB = (int)g->nB; BA.res = g->res;
+    BA.dist = g->mark; BA.ctl = g->brlctl; BA.dinf = g->dinf; BA.levels = brl;
+    BA.hist = g->hist; BA.maxlab = g->maxlab;
 
     mfd::GapArgs P;
     P.hist = g->hist; P.maxlab = g->maxlab; P.gap = g->gap; P.gapOn = o.gap ? 1 : 0;
@@ -807,6 +828,13 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                 if (o.profile && !ok(hipEventRecord(ev[2 * j + 1], s))) return false;
                 F.lab = g->lab[p ^ 1]; F.actIn = g->act + p;
                 if (!ok(mfd::launch_fuse(F, s))) return false;
+                if (brl > 0) {
+                    BA.lab = g->lab[p ^ 1]; BA.actIn = g->act + p;
+                    if (!ok(mfd::launch_boundary_relabel(BA, 0, 0, 0, s)) ||
+                        !ok(mfd::launch_boundary_relabel(BA, 1, 0, brl, s)) ||
+                        !ok(mfd::launch_boundary_relabel(BA, 2, 0, 0, s)))
+                        return false;
+                }
                 P.actIn = g->act + p; P.actOut = g->act + (p ^ 1); P.qheadNext = g->qhead + (p ^ 1);
                 if (!ok(mfd::launch_gap_find(P, s))) return false;
                 Q.lab = g->lab[p ^ 1]; Q.actIn = g->act + p; Q.actOut = g->act + (p ^ 1);
@@ -821,7 +849,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
             const long long key = ((long long)check_every << 8) | (o.gap ? 1 : 0) << 1 |
                                   (long long)(regionMode << 2) | (long long)(regionNarrow << 4) |
                                   (long long)((g->lab[0] < g->lab[1]) ? 1 : 0) << 6 |
-                                  (long long)(o.partial ? 1 : 0) << 7;
+                                  (long long)(o.partial ? 1 : 0) << 7 | (long long)brl << 40;
             if (!g->graph_exec || g->graph_key != key) {
                 if (g->graph_exec) { (void)hipGraphExecDestroy(g->graph_exec); g->graph_exec = nullptr; }
                 hipGraph_t graph = nullptr;
@@ -860,6 +888,11 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         if ((long long)g->pinned[1] >= max_sweeps) { status = MF_E_SWEEPS; break; }
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
+    if (status == MF_E_SWEEPS) {
+        // the state after the sweeps run so far stays readable
+        g->final_parity = (int)(g->pinned[1] & 1ull);
+        g->has_state = true;
+    }
     if (status != MF_OK) return status;
     long long sweeps = (long long)g->pinned[1];
     g->final_parity = (int)(sweeps & 1);
@@ -879,6 +912,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         for (int i = 0; i < g->batch; i++) g->iflow[i] = g->isum_ct[i] - (long long)rts[i];
     }
     g->solved = true;
+    g->has_state = true;
     auto t1 = std::chrono::high_resolution_clock::now();
     if (st) {
         memset(st, 0, sizeof(*st));
@@ -1165,7 +1199,7 @@ extern "C" mf_status mf_get_state(const mf_grid *gc, int32_t *res, int32_t *rt, 
                                   int32_t *labels) {
     mf_grid *g = const_cast<mf_grid *>(gc);
     if (!g) return MF_E_INVAL;
-    if (!g->solved) return MF_E_STATE;
+    if (!g->has_state) return MF_E_STATE;
     const Geo &G = g->G;
     size_t n = (size_t)g->n;
     hipStream_t s = nullptr;
@@ -1179,5 +1213,35 @@ extern "C" mf_status mf_get_state(const mf_grid *gc, int32_t *res, int32_t *rt, 
         for (int k = 0; k < g->K; k++)
             if (!one(g->res + (size_t)k * G.N, res + (size_t)k * n)) return MF_E_DEVICE;
     if (!one(g->rt, rt) || !one(g->ex, ex) || !one(g->lab[g->final_parity], labels)) return MF_E_DEVICE;
+    return MF_OK;
+}
+
+extern "C" mf_status mf_boundary_relabel(mf_grid *g, int32_t max_levels, int64_t *levels_out) {
+    if (!g || max_levels <= 0) return MF_E_INVAL;
+    if (!g->has_state) return MF_E_STATE;
+    hipStream_t s = nullptr;
+    mfd::BrlArgs BA;
+    memset(&BA, 0, sizeof(BA));
+    BA.G = g->G; BA.bidx = g->bidx; BA.bstart = g->bstart; BA.nB = (int)g->nB; BA.res = g->res;
+    BA.lab = g->lab[g->final_parity]; BA.dist = g->mark; BA.ctl = g->brlctl; BA.dinf = g->dinf;
+    g->cut_kind_cached = -1;  // the distances overwrite the cut marks
+    unsigned int ctl[8] = {0};
+    if (g->nB > 0) {
+        // levels in batches of eight until the search ends or the budget is spent
+        HIP_TRY(mfd::launch_boundary_relabel(BA, 0, 0, 0, s));
+        int run = 0;
+        while (run < max_levels) {
+            const int c = std::min(8, max_levels - run);
+            HIP_TRY(mfd::launch_boundary_relabel(BA, 1, run, c, s));
+            run += c;
+            HIP_TRY(hipMemcpyAsync(ctl, g->brlctl, 5 * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (ctl[3] || ctl[(run + 2) % 3] == 0u) break;
+        }
+        BA.levels = run;
+        HIP_TRY(mfd::launch_boundary_relabel(BA, 2, 0, 0, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    if (levels_out) *levels_out = (int64_t)ctl[4];
     return MF_OK;
 }

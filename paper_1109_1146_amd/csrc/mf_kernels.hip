@@ -458,6 +458,27 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
 // directions, so every pair has exactly one owner.  Also builds the histogram
 // of boundary labels for the gap heuristic.
 // ---------------------------------------------------------------------------
+// Adds one label per thread (-1: none) to the boundary-label histogram of the
+// gap heuristic through block-privatised bins in LDS (zeroed and synchronised
+// by the caller), and the block's largest label to maxlab.  256 threads.
+__device__ void boundary_hist(unsigned int *lh, int *s_wmax, int mylab, unsigned int *hist,
+                              int *maxlab) {
+    if (mylab >= 0) {
+        if (mylab < kHistLds) atomicAdd(&lh[mylab], 1u);
+        else if (mylab < kHistBins) atomicAdd(&hist[mylab], 1u);
+    }
+    int m = wave_max_i(mylab);
+    if ((threadIdx.x & 63) == 0) s_wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    for (int b = threadIdx.x; b < kHistLds; b += blockDim.x)
+        if (lh[b]) atomicAdd(&hist[b], lh[b]);
+    if (threadIdx.x == 0) {
+        int mm = -1;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) mm = max(mm, s_wmax[w]);
+        if (mm >= 0) atomicMax(maxlab, mm);
+    }
+}
+
 __global__ void k_fuse(FuseArgs A) {
     __shared__ unsigned int lh[kHistLds];
     __shared__ int s_wmax[4];
@@ -497,22 +518,9 @@ __global__ void k_fuse(FuseArgs A) {
             if (addv) atomicAdd(&A.ex[v], addv);
         }
         if (addu) atomicAdd(&A.ex[u], addu);
-        if (du < A.dinf) {
-            mylab = du;
-            if (du < kHistLds) atomicAdd(&lh[du], 1u);
-            else if (du < kHistBins) atomicAdd(&A.hist[du], 1u);
-        }
+        if (du < A.dinf) mylab = du;
     }
-    int m = wave_max_i(mylab);
-    if ((threadIdx.x & 63) == 0) s_wmax[threadIdx.x >> 6] = m;
-    __syncthreads();
-    for (int b = threadIdx.x; b < kHistLds; b += blockDim.x)
-        if (lh[b]) atomicAdd(&A.hist[b], lh[b]);
-    if (threadIdx.x == 0) {
-        int mm = -1;
-        for (int w = 0; w < (int)(blockDim.x >> 6); w++) mm = max(mm, s_wmax[w]);
-        if (mm >= 0) atomicMax(A.maxlab, mm);
-    }
+    if (A.histOn) boundary_hist(lh, s_wmax, mylab, A.hist, A.maxlab);
 }
 
 // Global gap (Sec. 5.1, over boundary labels): the smallest g >= 1 below the
@@ -586,6 +594,120 @@ __global__ void k_gap_apply(GapApplyArgs A) {
         for (int w = 0; w < (int)(blockDim.x >> 6); w++) t += s_w[w];
         if (t) atomicAdd(A.actOut, (u64)t);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Boundary relabel heuristic (Sec. 6.1).  Groups are the (region, label)
+// classes of the boundary vertices labelled below dinf; a group reaches the
+// group of every larger label of its region at length 0 (a chain of
+// consecutive labels) and, through each residual arc (u, w) between regions,
+// the group of w at length 1.  d' is the distance to a label-0 group.
+// Searched level by level from the label-0 vertices: level D + 1 of region R
+// is every unreached vertex of R labelled at most M, where M is the largest
+// label of an unreached vertex of R with a residual arc into a vertex at
+// distance D (the zero-length arcs lead from a label to all larger ones).
+// ctl: [0..2] vertices reached per level, rotating (level D counts into D % 3,
+// reads D - 1 from (D + 2) % 3 and clears (D + 1) % 3 for the next level);
+// [3] the search has ended; [4] levels that reached a vertex.
+// ---------------------------------------------------------------------------
+__global__ void k_brl_init(BrlArgs A) {
+    if (A.actIn && *A.actIn == 0ull) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0)
+        for (int c = 0; c < 5; c++) A.ctl[c] = 0u;
+    if (i < A.nB) {
+        const int u = A.bidx[i];
+        A.dist[u] = A.lab[u] == 0 ? 0 : kInf;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_brl_level(BrlArgs A, int D) {
+    __shared__ int s_m, s_c;
+    if (A.actIn && *A.actIn == 0ull) return;
+    if (A.ctl[3]) return;
+    if (D > 0 && A.ctl[(D + 2) % 3] == 0u) {
+        // the previous level reached nothing: no vertex is at distance D
+        if (threadIdx.x == 0) A.ctl[3] = 1u;
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) A.ctl[(D + 1) % 3] = 0u;
+    const Geo &G = A.G;
+    const int r = blockIdx.x;
+    const int b0 = A.bstart[r], b1 = A.bstart[r + 1];
+    if (b0 == b1) return;
+    if (threadIdx.x == 0) {
+        s_m = -1;
+        s_c = 0;
+    }
+    __syncthreads();
+    int m = -1;
+    for (int i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+        const int u = A.bidx[i];
+        if (A.dist[u] != kInf) continue;
+        const int du = A.lab[u];
+        if (du >= A.dinf || du <= m) continue;  // only a larger label can raise M
+        int lz, ly, lx;
+        local_xyz(G, u - r * G.V, lz, ly, lx);
+        for (int k = 0; k < G.K; k++) {
+            if (local_nbr(G, lz, ly, lx, k) >= 0) continue;
+            const int w = cross_nbr(G, r, lz, ly, lx, k);
+            if (w < 0) continue;
+            if (A.res[(size_t)k * G.N + u] > 0 && A.dist[w] == D) {
+                m = du;
+                break;
+            }
+        }
+    }
+    m = wave_max_i(m);
+    if ((threadIdx.x & 63) == 0 && m >= 0) atomicMax(&s_m, m);
+    __syncthreads();
+    const int M = s_m;
+    if (M < 0) return;
+    int c = 0;
+    for (int i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+        const int u = A.bidx[i];
+        if (A.dist[u] != kInf) continue;
+        const int du = A.lab[u];
+        if (du <= M) {  // M < dinf, so du < dinf
+            A.dist[u] = D + 1;
+            c++;
+        }
+    }
+    c = wave_sum_i(c);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&s_c, c);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_c) {
+        atomicAdd(&A.ctl[D % 3], (unsigned)s_c);
+        atomicMax(&A.ctl[4], (unsigned)(D + 1));
+    }
+}
+
+// d := max(d, d') on B, with d' = dinf where the search ended without reaching
+// the vertex and levels + 1 where the level budget ran out first; optionally
+// builds the boundary-label histogram of the gap heuristic.
+__global__ __launch_bounds__(256) void k_brl_apply(BrlArgs A) {
+    __shared__ unsigned int lh[kHistLds];
+    __shared__ int s_wmax[4];
+    if (A.actIn && *A.actIn == 0ull) return;
+    if (A.hist) {
+        for (int b = threadIdx.x; b < kHistLds; b += blockDim.x) lh[b] = 0u;
+        __syncthreads();
+    }
+    const bool ended = A.ctl[3] != 0u || A.ctl[(A.levels + 2) % 3] == 0u;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int mylab = -1;
+    if (i < A.nB) {
+        const int u = A.bidx[i];
+        const int d = A.lab[u];
+        if (d < A.dinf) {
+            int dp = A.dist[u];
+            if (dp == kInf) dp = ended ? A.dinf : A.levels + 1;
+            const int nd = max(d, min(dp, A.dinf));
+            if (nd != d) A.lab[u] = nd;
+            if (nd < A.dinf) mylab = nd;
+        }
+    }
+    if (A.hist) boundary_hist(lh, s_wmax, mylab, A.hist, A.maxlab);
 }
 
 // ---------------------------------------------------------------------------
@@ -741,6 +863,21 @@ hipError_t launch_discharge(const DischargeArgs &A, int blocks, int threads, siz
 hipError_t launch_fuse(const FuseArgs &A, hipStream_t s) {
     if (A.nB == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fuse, dim3(cdiv(A.nB, 256)), dim3(256), 0, s, A);
+    return hipGetLastError();
+}
+
+// stage 0: init; 1: levels [first, first + count); 2: apply with A.levels levels run
+hipError_t launch_boundary_relabel(const BrlArgs &A, int stage, int first, int count, hipStream_t s) {
+    if (A.nB == 0) return hipSuccess;
+    if (stage == 0) {
+        hipLaunchKernelGGL(k_brl_init, dim3(cdiv(A.nB, 256)), dim3(256), 0, s, A);
+    } else if (stage == 1) {
+        for (int D = first; D < first + count; D++)
+            hipLaunchKernelGGL(k_brl_level, dim3(A.G.nreg), dim3(256), 0, s, A, D);
+    } else {
+        if (A.levels <= 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_brl_apply, dim3(cdiv(A.nB, 256)), dim3(256), 0, s, A);
+    }
     return hipGetLastError();
 }
 

@@ -83,6 +83,25 @@ struct FuseArgs {
     unsigned int *hist;
     int *maxlab;
     const unsigned long long *actIn;
+    int histOn;  // 0: the boundary relabel builds the label histogram instead
+};
+
+// Boundary relabel heuristic (Sec. 6.1): level-synchronous search over the
+// boundary vertices, one workgroup per region and level.
+struct BrlArgs {
+    Geo G;
+    const int *bidx;
+    const int *bstart;   // [nreg + 1]: region r holds bidx[bstart[r] .. bstart[r+1])
+    int nB;
+    const int *res;
+    int *lab;            // labels of the sweep (raised in place by the apply step)
+    int *dist;           // [N]: d' of the boundary vertices (kInf: not reached yet)
+    unsigned int *ctl;   // [4]: level counters (rotating, 3) and the ended flag
+    int dinf;
+    int levels;          // level launches of this run
+    const unsigned long long *actIn;  // null: always run
+    unsigned int *hist;  // null: no histogram
+    int *maxlab;
 };
 
 struct GapArgs {
@@ -192,6 +211,7 @@ hipError_t launch_discharge_rows(const DischargeArgs &A, int blocks, size_t lds,
 size_t discharge_rows_bytes(int ty, int tz, int nring);
 int rows_slots(int nring);
 hipError_t launch_fuse(const FuseArgs &A, hipStream_t s);
+hipError_t launch_boundary_relabel(const BrlArgs &A, int stage, int first, int count, hipStream_t s);
 hipError_t launch_gap_find(const GapArgs &A, hipStream_t s);
 hipError_t launch_gap_apply(const GapApplyArgs &A, hipStream_t s);
 hipError_t launch_sum_i32(const int *a, int n, unsigned long long *out, hipStream_t s);

@@ -29,7 +29,7 @@ EXPORTED = ("mf_create_grid", "mf_set_caps", "mf_solve", "mf_flow_value", "mf_mi
             "mf_status_str", "mf_create_batch", "mf_batch_info", "mf_batch_set_caps",
             "mf_batch_flow_values", "mf_batch_min_cut", "mf_model_create", "mf_model_destroy",
             "mf_model_num_params", "mf_model_get_params", "mf_model_set_params", "mf_model_forward",
-            "mf_model_loss_grad", "mf_model_adam_step")
+            "mf_model_loss_grad", "mf_model_adam_step", "mf_boundary_relabel")
 
 
 class mf_solve_opts(ctypes.Structure):
@@ -41,7 +41,8 @@ class mf_solve_opts(ctypes.Structure):
                 ("trace_cap", ctypes.c_int64), ("graph", ctypes.c_int32),
                 ("max_defer", ctypes.c_int32), ("defer_threshold", ctypes.c_float),
                 ("defer_mode", ctypes.c_int32), ("features", ctypes.c_void_p),
-                ("features_cap", ctypes.c_int64), ("partial", ctypes.c_int32)]
+                ("features_cap", ctypes.c_int64), ("partial", ctypes.c_int32),
+                ("boundary_relabel", ctypes.c_int32)]
 
 
 class mf_solve_stats(ctypes.Structure):
@@ -99,6 +100,8 @@ def load(path: str = LIB_PATH):
     lib.mf_min_cut.restype = ctypes.c_int
     lib.mf_get_state.argtypes = [P, P, P, P, P]
     lib.mf_get_state.restype = ctypes.c_int
+    lib.mf_boundary_relabel.argtypes = [P, ctypes.c_int32, P]
+    lib.mf_boundary_relabel.restype = ctypes.c_int
     lib.mf_get_info.argtypes = [P, P, P, P, P, P]
     lib.mf_get_info.restype = ctypes.c_int
     lib.mf_discharge_bytes_per_vertex.argtypes = [ctypes.c_int32]
@@ -229,9 +232,11 @@ class Grid:
     def solve(self, schedule=MF_SCHED_PARD, gap=True, global_relabel_every=0, check_every=0,
               max_sweeps=0, stream=None, profile=False, region_kernel=MF_KERNEL_AUTO,
               trace=None, graph=False, model=None, max_defer=0, defer_threshold=0.0,
-              features=None, defer_mode=0, partial=False):
+              features=None, defer_mode=0, partial=False, boundary_relabel=0):
         """trace: optional int32 device tensor of shape (cap, TRACE_FIELDS);
-        partial: partial discharges (sweep s runs the stages k <= s only)."""
+        partial: partial discharges (sweep s runs the stages k <= s only);
+        boundary_relabel: n > 0 runs the boundary relabel heuristic after every
+        sweep with at most n levels of its search."""
         tptr, tcap = None, 0
         if trace is not None:
             tptr, tcap = trace.data_ptr(), int(trace.shape[0])
@@ -244,7 +249,8 @@ class Grid:
                           region_kernel=region_kernel, trace=tptr, trace_cap=tcap,
                           graph=1 if graph else 0, max_defer=max_defer,
                           defer_threshold=defer_threshold, defer_mode=defer_mode, features=fptr,
-                          features_cap=fcap, partial=1 if partial else 0)
+                          features_cap=fcap, partial=1 if partial else 0,
+                          boundary_relabel=int(boundary_relabel))
         if model is not None:
             o.model = model._h
         s = mf_solve_stats()
@@ -270,6 +276,14 @@ class Grid:
         P = lambda a: ctypes.c_void_p(a.ctypes.data)
         _check(load().mf_get_state(self._h, P(res), P(rt), P(ex), P(lab)), "mf_get_state")
         return dict(res=res, rt=rt, ex=ex, labels=lab)
+
+    def boundary_relabel(self, max_levels=1 << 30):
+        """Boundary relabel heuristic on the state of the last solve (also one
+        stopped by max_sweeps); returns the number of levels that reached a vertex."""
+        lv = ctypes.c_int64()
+        _check(load().mf_boundary_relabel(self._h, int(max_levels), ctypes.byref(lv)),
+               "mf_boundary_relabel")
+        return int(lv.value)
 
 
 class Batch(Grid):

@@ -1,0 +1,214 @@
+"""Boundary relabel heuristic on the GPU (Sec. 6.1): the stand-alone entry
+point gives the oracle's lifted labels on the boundary vertices of a solver
+state, exactly, also with a truncated level budget; solves with the heuristic
+after every sweep keep the oracle's flow and both extremal cuts on every region
+kernel, with partial discharges, captured sweep batches and batches."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.helpers import certify_solver_state, region_chain_instance, state_to_pairs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mf():
+    from paper_1109_1146_amd import mf as _mf
+    _mf.load()
+    return _mf
+
+
+def _stop_after(mf, g, sweeps, **kw):
+    """Solve for exactly `sweeps` sweeps; returns False if the solve converged first."""
+    try:
+        g.solve(max_sweeps=sweeps, check_every=1, **kw)
+        return False
+    except mf.MFError as e:
+        assert e.status == mf.MF_E_SWEEPS
+        return True
+
+
+def _boundary_mask(inst, tile):
+    pu, pv, _, _ = oracle.grid_pairs(inst.dims, inst.nbr, oracle._offsets(inst))
+    region = oracle.grid_regions(inst.dims, tile)
+    inB = np.zeros(inst.n, bool)
+    cross = region[pu] != region[pv]
+    inB[pu[cross]] = True
+    inB[pv[cross]] = True
+    return inB
+
+
+@pytest.mark.parametrize("L,w", [(6, 8), (9, 4), (5, 32)])
+def test_region_chain_closed_form(mf, L, w):
+    """After the first sweep every region but the last is labelled 1; the
+    heuristic lifts the boundary vertices of region j to L - 1 - j, in the
+    solve and from the stand-alone entry point."""
+    inst = region_chain_instance(L, w)
+    j = np.repeat(np.arange(L), w)
+    inB = _boundary_mask(inst, inst.tile)
+    with mf.Grid(inst.dims, inst.conn, inst.tile) as g:
+        g.set_caps(inst.cs, inst.ct, inst.nbr)
+        assert _stop_after(mf, g, 1)
+        plain = g.state()["labels"]
+        assert (plain == np.where(j < L - 1, 1, 0)).all()
+        assert g.boundary_relabel() == L - 1
+        lifted = g.state()["labels"]
+        assert (lifted[inB] == (L - 1 - j)[inB]).all()
+        assert (lifted[~inB] == plain[~inB]).all()
+        assert _stop_after(mf, g, 1, boundary_relabel=64)
+        assert (g.state()["labels"][inB] == (L - 1 - j)[inB]).all()
+        st = g.solve(boundary_relabel=64)
+        assert g.flow_value() == L * 10
+        print(f"chain {L}x{w}: sweeps {st['sweeps']} with the heuristic", flush=True)
+
+
+CASES = [((12, 13), 4, (4, 5)), ((16, 16), 8, (4, 8)), ((6, 7, 8), 6, (3, 4, 4)),
+         ((40, 36), 8, (8, 8)), ((8, 40, 70), 6, (4, 16, 32)), ((70, 90), 4, (32, 32)),
+         ((9, 10, 11), 6, (4, 4, 4)), ((130, 70), 8, (64, 64))]
+
+
+def _oracle_lift(inst, tile, st, dinf):
+    pu, pv, _, _ = oracle.grid_pairs(inst.dims, inst.nbr, oracle._offsets(inst))
+    region = oracle.grid_regions(inst.dims, tile)
+    r_uv, r_vu = state_to_pairs(inst, st)
+    return oracle.boundary_relabel(inst.n, pu, pv, r_uv, r_vu, region, st["labels"], dinf,
+                                   distances=True)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_standalone_matches_oracle(mf, seed):
+    dims, conn, tile = CASES[seed % len(CASES)]
+    inst = (synth.blob_grid(dims, conn, 2000 + seed, 4, 3.0, 9.0, tile=tile) if seed % 2
+            else synth.random_grid(dims, conn, 2000 + seed, tile=tile))
+    inB = _boundary_mask(inst, tile)
+    print(f"case {inst.name} dims={dims} tile={tile}", flush=True)
+    lifted_total = 0
+    with mf.Grid(inst.dims, inst.conn, tile) as g:
+        g.set_caps(inst.cs, inst.ct, inst.nbr)
+        dinf = max(g.info()["boundary_size"], 1)
+        for s in (1, 2, 3, 5):
+            if not _stop_after(mf, g, s, partial=bool(seed % 3 == 0)):
+                break
+            st = g.state()
+            want, dprime = _oracle_lift(inst, tile, st, dinf)
+            levels = g.boundary_relabel()
+            got = g.state()["labels"]
+            assert (got[inB] == want[inB]).all(), (s, np.flatnonzero(got[inB] != want[inB])[:10])
+            assert (got[~inB] == st["labels"][~inB]).all()
+            reached = dprime[inB & (st["labels"] < dinf)]
+            assert levels == (max(int(reached.max()), 0) if reached.size else 0)
+            lifted_total += int((want[inB] > st["labels"][inB]).sum())
+    print(f"  lifted {lifted_total}", flush=True)
+
+
+@pytest.mark.parametrize("budget", [1, 2, 3])
+@pytest.mark.parametrize("seed", range(4))
+def test_standalone_truncated_budget(mf, seed, budget):
+    """With a budget of n levels, distances up to n are exact and the others
+    are lifted to n + 1 (or dinf when the search ended within the budget)."""
+    dims, conn, tile = CASES[(seed * 3) % len(CASES)]
+    inst = synth.random_grid(dims, conn, 2100 + seed, tile=tile)
+    inB = _boundary_mask(inst, tile)
+    with mf.Grid(inst.dims, inst.conn, tile) as g:
+        g.set_caps(inst.cs, inst.ct, inst.nbr)
+        dinf = max(g.info()["boundary_size"], 1)
+        if not _stop_after(mf, g, 2):
+            pytest.skip("converged in fewer sweeps")
+        st = g.state()
+        d0 = st["labels"]
+        _, dprime = _oracle_lift(inst, tile, st, dinf)
+        part = inB & (d0 < dinf)
+        dmax = int(dprime[part].max()) if (dprime[part] >= 0).any() else 0
+        if dmax < budget:
+            dcap = np.where(dprime < 0, dinf, dprime)
+        else:
+            dcap = np.where((dprime < 0) | (dprime > budget), budget + 1, dprime)
+        want = np.where(part, np.maximum(d0, np.minimum(dcap, dinf)), d0)
+        g.boundary_relabel(budget)
+        got = g.state()["labels"]
+        assert (got[inB] == want[inB]).all()
+
+
+@pytest.mark.parametrize("kernel", ["auto", "hbm", "lds"])
+@pytest.mark.parametrize("seed", range(8))
+def test_solve_with_heuristic_exact(mf, seed, kernel):
+    dims, conn, tile = CASES[seed % len(CASES)]
+    inst = synth.random_grid(dims, conn, 2200 + seed, tile=tile)
+    rk = {"auto": mf.MF_KERNEL_AUTO, "hbm": mf.MF_KERNEL_HBM, "lds": mf.MF_KERNEL_LDS}[kernel]
+    ref = oracle.solve_grid(inst)
+    for budget, partial in ((64, False), (2, True), (512, True)):
+        try:
+            out = mf.solve_instance(inst, tile=tile, region_kernel=rk, boundary_relabel=budget,
+                                    partial=partial, max_sweeps=100000)
+        except mf.MFError as e:
+            if kernel == "lds" and e.status == mf.MF_E_INVAL:
+                pytest.skip("region does not fit the LDS kernel")
+            raise
+        assert out["flow"] == ref["flow"]
+        assert (out["smin"] == ref["smin"]).all() and (out["smax"] == ref["smax"]).all()
+        certify_solver_state(inst, out)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_solve_with_heuristic_rows_and_wave(mf, seed):
+    cases = [((8, 64, 70), 6, (4, 32, 32), mf.MF_KERNEL_ROWS), ((4, 40, 65), 6, (2, 32, 32), mf.MF_KERNEL_ROWS),
+             ((150, 140), 8, (64, 64), mf.MF_KERNEL_WAVE), ((100, 90), 4, (32, 64), mf.MF_KERNEL_WAVE)]
+    dims, conn, tile, rk = cases[seed]
+    inst = synth.blob_grid(dims, conn, 2300 + seed, 5, 4.0, 12.0, zero_frac=0.1, tile=tile)
+    ref = oracle.solve_grid(inst)
+    for partial in (False, True):
+        out = mf.solve_instance(inst, tile=tile, region_kernel=rk, boundary_relabel=32,
+                                partial=partial, global_relabel_every=4 if partial else 0,
+                                max_sweeps=100000)
+        assert out["stats"]["region_kernel"] == rk
+        assert out["flow"] == ref["flow"]
+        assert (out["smin"] == ref["smin"]).all() and (out["smax"] == ref["smax"]).all()
+
+
+def test_graph_replay_with_heuristic(mf):
+    inst = synth.blob_grid((256, 192), 8, 2400, 8, 8.0, 30.0, zero_frac=0.1, tile=(32, 32))
+    ref = oracle.solve_grid(inst)
+    with mf.Grid(inst.dims, inst.conn, inst.tile) as g:
+        g.set_caps(inst.cs, inst.ct, inst.nbr)
+        eager = g.solve(boundary_relabel=16, max_sweeps=2000)
+        assert g.flow_value() == ref["flow"]
+        for rep in range(3):
+            st = g.solve(boundary_relabel=16, graph=True, check_every=4, max_sweeps=2000)
+            print(f"replay {rep}: sweeps {st['sweeps']} (eager {eager['sweeps']})", flush=True)
+            assert g.flow_value() == ref["flow"]
+            assert (g.min_cut(mf.MF_CUT_MIN_SOURCE) == ref["smin"]).all()
+            g.solve(max_sweeps=2000)  # eager, no heuristic, in between
+            assert g.flow_value() == ref["flow"]
+
+
+def test_batch_with_heuristic_exact(mf):
+    insts = synth.config3_instances(40)
+    b = mf.load_batch(insts, region_shape=(32, 32))
+    try:
+        b.solve(boundary_relabel=16, max_sweeps=100000)
+        flows = b.flow_values()
+        for i, inst in enumerate(insts):
+            ref = oracle.solve_grid(inst)
+            assert flows[i] == ref["flow"], (i, inst.name)
+            assert (b.instance_cut(i, mf.MF_CUT_MIN_SOURCE) == ref["smin"]).all(), (i, inst.name)
+    finally:
+        b.close()
+
+
+def test_invalid_arguments(mf):
+    inst = synth.random_grid((16, 16), 4, 2500, tile=(8, 8))
+    with mf.Grid(inst.dims, inst.conn, inst.tile) as g:
+        g.set_caps(inst.cs, inst.ct, inst.nbr)
+        with pytest.raises(mf.MFError) as e:
+            g.boundary_relabel()  # no state yet
+        assert e.value.status == mf.MF_E_STATE
+        g.solve()
+        with pytest.raises(mf.MFError) as e:
+            g.boundary_relabel(0)
+        assert e.value.status == mf.MF_E_INVAL
+        for bad in (-1, 4097):
+            with pytest.raises(mf.MFError) as e:
+                g.solve(boundary_relabel=bad)
+            assert e.value.status == mf.MF_E_INVAL
