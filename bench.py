@@ -66,6 +66,10 @@ def parse():
     p.add_argument("--partial", choices=("auto", "on", "off"), default="auto",
                    help="partial discharges (sweep s runs only the stages k <= s of ARD); auto: "
                         "the workload's tuned setting (the autotuner's for the batch)")
+    p.add_argument("--boundary-relabel", type=int, default=None, metavar="N",
+                   help="boundary relabel heuristic after every sweep with at most N levels "
+                        "(0 = off); default: off for the single grids, the autotuner's choice "
+                        "for the batch")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="only run a device-to-device copy of MIB MiB (HBM counter calibration)")
     return p.parse_args()
@@ -114,14 +118,17 @@ def bench_batch(args):
     insts = synth.config3_instances(512)
     total_n = sum(inst.n for inst in insts)
     forced = {"on": (True,), "off": (False,)}.get(args.partial, autotune.PARTIAL)
-    tune = autotune.autotune_batch(insts, calib=48, reps=1, partial=forced)
+    brl = autotune.BRL if args.boundary_relabel is None else (args.boundary_relabel,)
+    tune = autotune.autotune_batch(insts, calib=48, reps=1, partial=forced, brl=brl)
     args.partial = tune["partial"]
+    args.boundary_relabel = tune["boundary_relabel"]
     b = mf.load_batch(insts, region_shape=tune["region_shape"])
     stream = torch.cuda.Stream()
 
     def step(profile):
         st = b.solve(global_relabel_every=tune["relabel_every"], graph=not profile,
-                     profile=profile, stream=stream.cuda_stream, partial=args.partial)
+                     profile=profile, stream=stream.cuda_stream, partial=args.partial,
+                     boundary_relabel=args.boundary_relabel)
         flows = b.flow_values()
         cut = b.min_cut(mf.MF_CUT_MIN_SOURCE)
         return st, flows, cut
@@ -147,7 +154,7 @@ def bench_batch(args):
         "config": {"workload": WORKLOADS["batch"]["desc"], "instances": len(insts), "n": total_n,
                    "canvas": list(b.dims), "region_shape": list(tune["region_shape"]),
                    "global_relabel_every": tune["relabel_every"], "graph": True,
-                   "partial_discharges": args.partial},
+                   "partial_discharges": args.partial, "boundary_relabel": args.boundary_relabel},
         "instances_per_s": round(len(insts) / (ms / 1e3), 1),
         "sweeps": st["sweeps"], "region_discharges": st["region_discharges"],
         "flow": int(flows.sum()),
@@ -163,7 +170,8 @@ def bench_batch(args):
             model = learned.load_model()
             lkw = dict(schedule=mf.MF_SCHED_LEARNED, model=model, defer_threshold=learned.DEFAULT_THRESHOLD,
                        max_defer=learned.DEFAULT_MAX_DEFER, global_relabel_every=tune["relabel_every"],
-                       stream=stream.cuda_stream, partial=args.partial)
+                       stream=stream.cuda_stream, partial=args.partial,
+                       boundary_relabel=args.boundary_relabel)
             b.solve(**lkw)
             lt = []
             for _ in range(max(1, min(args.steps, 3))):
@@ -219,6 +227,8 @@ def main():
     if args.relabel_every is None:
         args.relabel_every = wl["relabel"]
     args.partial = {"on": True, "off": False}.get(args.partial, wl["partial"])
+    if args.boundary_relabel is None:
+        args.boundary_relabel = 0
     inst = synth.config(wl["cfg"])
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
@@ -233,7 +243,8 @@ def main():
 
     def step(profile):
         st = g.solve(stream=stream.cuda_stream, profile=profile,
-                     global_relabel_every=args.relabel_every, partial=args.partial)
+                     global_relabel_every=args.relabel_every, partial=args.partial,
+                     boundary_relabel=args.boundary_relabel)
         cut = g.min_cut(mf.MF_CUT_MIN_SOURCE)
         return st, cut
 
@@ -277,9 +288,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "n": inst.n, "regions": info["regions"],
                    "region_shape": list(info["region_shape"]), "boundary_size": info["boundary_size"],
-                   "schedule": "P-ARD" + (", partial discharges" if args.partial else ""),
+                   "schedule": "P-ARD" + (", partial discharges" if args.partial else "")
+                               + (", boundary relabel" if args.boundary_relabel else ""),
                    "connectivity": inst.conn,
-                   "global_relabel_every": args.relabel_every, "partial_discharges": args.partial},
+                   "global_relabel_every": args.relabel_every, "partial_discharges": args.partial,
+                   "boundary_relabel": args.boundary_relabel},
         "sweeps": stats[-1]["sweeps"],
         "region_discharges": stats[-1]["region_discharges"],
         "flow": flow,
@@ -305,7 +318,8 @@ def main():
         model = learned.load_model()
         lkw = dict(schedule=mf.MF_SCHED_LEARNED, model=model, defer_threshold=learned.DEFAULT_THRESHOLD,
                    max_defer=learned.DEFAULT_MAX_DEFER, global_relabel_every=args.relabel_every,
-                   stream=stream.cuda_stream, partial=args.partial)
+                   stream=stream.cuda_stream, partial=args.partial,
+                   boundary_relabel=args.boundary_relabel)
         g.solve(**lkw)
         times = []
         for _ in range(max(1, min(args.steps, 3))):

@@ -391,9 +391,10 @@ def test_batch_workload_512_exact(mf):
     from paper_1109_1146_amd import autotune
     insts = synth.config3_instances(512)
     tune = autotune.autotune_batch(insts, calib=24, reps=1)
-    print("autotuned", tune["region_shape"], tune["relabel_every"], tune["partial"], flush=True)
+    print("autotuned", tune["region_shape"], tune["relabel_every"], tune["partial"],
+          tune["boundary_relabel"], flush=True)
     st = _batch_check(mf, insts, tune["region_shape"], global_relabel_every=tune["relabel_every"],
-                      partial=tune["partial"], graph=True)
+                      partial=tune["partial"], boundary_relabel=tune["boundary_relabel"], graph=True)
     assert st["sweeps"] > 0
 
 
