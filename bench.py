@@ -22,10 +22,11 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
 
 
-def measured_traffic(kernel_src, summary):
+def measured_traffic(kernel_src, summary, config=None):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated), or None when
-    the summary is missing or the kernel source changed since it was taken."""
+    the summary is missing, the kernel source changed since it was taken, or
+    (with config) it was taken with other solve settings."""
     import hashlib
     path = os.path.join(ROOT, "profiles", summary)
     src = os.path.join(ROOT, kernel_src)
@@ -37,6 +38,8 @@ def measured_traffic(kernel_src, summary):
     except OSError:
         return None
     if rec.get("source_sha256") != sha:
+        return None
+    if config is not None and rec.get("config") != config:
         return None
     return float(rec["traffic_bytes_per_launch"])
 
@@ -70,6 +73,10 @@ def parse():
                    help="boundary relabel heuristic after every sweep with at most N levels "
                         "(0 = off); default: off for the single grids, the autotuner's choice "
                         "for the batch")
+    p.add_argument("--region-shape", type=int, nargs=2, default=None, metavar=("H", "W"),
+                   help="batch only: solve with this region shape and the given relabel, "
+                        "partial and boundary-relabel settings instead of autotuning "
+                        "(defaults: no relabel, full discharges, no boundary relabel)")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="only run a device-to-device copy of MIB MiB (HBM counter calibration)")
     return p.parse_args()
@@ -119,7 +126,13 @@ def bench_batch(args):
     total_n = sum(inst.n for inst in insts)
     forced = {"on": (True,), "off": (False,)}.get(args.partial, autotune.PARTIAL)
     brl = autotune.BRL if args.boundary_relabel is None else (args.boundary_relabel,)
-    tune = autotune.autotune_batch(insts, calib=48, reps=1, partial=forced, brl=brl)
+    if args.region_shape:
+        # fixed settings (profiling runs): no tuning solves
+        tune = dict(region_shape=tuple(args.region_shape), relabel_every=args.relabel_every or 0,
+                    partial=args.partial == "on", boundary_relabel=args.boundary_relabel or 0,
+                    timings=[])
+    else:
+        tune = autotune.autotune_batch(insts, calib=48, reps=1, partial=forced, brl=brl)
     args.partial = tune["partial"]
     args.boundary_relabel = tune["boundary_relabel"]
     b = mf.load_batch(insts, region_shape=tune["region_shape"])
@@ -145,6 +158,12 @@ def bench_batch(args):
     ms = elapsed * 1e3 / args.steps
     d_ms, d_launch, d_bytes = pst["discharge_ms"], pst["discharge_launches"], pst["discharge_bytes"]
     achieved = d_bytes / (d_ms / 1e3) / 1e9 if d_ms > 0 else 0.0
+    traffic = measured_traffic("paper_1109_1146_amd/csrc/mf_discharge_wave.hip",
+                               "k_discharge_wave_batch512_traffic.json",
+                               config=dict(region_shape=list(tune["region_shape"]),
+                                           relabel_every=tune["relabel_every"],
+                                           partial=bool(args.partial),
+                                           boundary_relabel=args.boundary_relabel))
     rec = {
         "metric": "exact-maxflow solve throughput (batched plain P-ARD), % HBM peak",
         "value": round(total_n / (ms / 1e3) / 1e6, 3), "unit": "Mvertices/s",
@@ -161,7 +180,8 @@ def bench_batch(args):
         "autotune": tune["timings"],
         "roofline": {"bound": "hbm", "kernel": "k_discharge_wave", "achieved": round(achieved, 3),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                     "traffic": None, "avg_launch_ms": round(d_ms / max(d_launch, 1), 4)},
+                     "traffic": traffic, "avg_launch_ms": round(d_ms / max(d_launch, 1), 4),
+                     "algorithmic_bytes_per_launch": round(d_bytes / max(d_launch, 1), 1)},
     }
     # the learned schedule on the same batch (not in value): sweeps, discharges, time
     if not args.no_learned:
