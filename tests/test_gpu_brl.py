@@ -212,3 +212,33 @@ def test_invalid_arguments(mf):
             with pytest.raises(mf.MFError) as e:
                 g.solve(boundary_relabel=bad)
             assert e.value.status == mf.MF_E_INVAL
+
+
+@pytest.mark.parametrize("defer_mode", [0, 1])
+@pytest.mark.parametrize("seed", range(3))
+def test_heuristic_with_learned_schedule_exact(mf, seed, defer_mode):
+    """The heuristic after every sweep next to the learned schedule's deferrals
+    (an untrained network: arbitrary scores) and its region features."""
+    cases = [((40, 36), 8, (8, 8)), ((9, 10, 11), 6, (4, 4, 4)), ((100, 90), 4, (32, 32))]
+    dims, conn, tile = cases[seed]
+    inst = synth.random_grid(dims, conn, 2600 + seed, tile=tile)
+    ref = oracle.solve_grid(inst)
+    model = mf.Model(16, seed=seed)
+    for partial in (False, True):
+        out = mf.solve_instance(inst, tile=tile, schedule=mf.MF_SCHED_LEARNED, model=model,
+                                defer_threshold=0.6, max_defer=2, defer_mode=defer_mode,
+                                boundary_relabel=8, partial=partial, max_sweeps=100000)
+        assert out["flow"] == ref["flow"]
+        assert (out["smin"] == ref["smin"]).all() and (out["smax"] == ref["smax"]).all()
+
+
+def test_heuristic_on_full_size_workloads(mf):
+    """Both full-size single-grid workloads with the heuristic: exact flow and cuts."""
+    for cfg, relabel, partial in ((1, 10, False), (2, 4, True)):
+        inst = synth.config(cfg)
+        out = mf.solve_instance(inst, boundary_relabel=16, global_relabel_every=relabel,
+                                partial=partial, max_sweeps=100000)
+        ref = oracle.solve_grid(inst)
+        print(f"{inst.name}: sweeps {out['stats']['sweeps']}", flush=True)
+        assert out["flow"] == ref["flow"]
+        assert (out["smin"] == ref["smin"]).all() and (out["smax"] == ref["smax"]).all()
