@@ -156,8 +156,13 @@ __global__ void k_init(Geo G, const int *cs, const int *ct, const int *nbr, int 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
     extern __shared__ int smem[];
-    __shared__ int s_r, s_active, s_qtail, s_nsteps, s_min, s_found;
+    __shared__ int s_r, s_active, s_qtail, s_nsteps, s_min, s_found, s_live, s_hit;
     __shared__ int s_wmin[NT / 64];
+    // search marks: a step index, kInf (not reached yet) or kDead (not reached by
+    // a complete search earlier in this discharge: it cannot reach a target for
+    // the rest of the discharge, since pushes only add residual arcs between
+    // reached vertices)
+    constexpr int kDead = kInf - 1;
     __shared__ long long s_tr[4];  // trace: excess out, to sink, to boundary, label sum
     if (*A.actIn == 0ull) return;
     const int stageCap = stage_cap(A);
@@ -210,20 +215,40 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
         // partial discharge: the searches of the push rounds stop at the stage
         // cap; the labels come from a complete search (full)
         bool full = !A.partial;
+        bool firstSearch = true, lastComplete = false;
         for (;;) {
-            bool capped = false;
+            bool capped = false, early = false;
+            // a push-round search stops once every live excess vertex is labelled;
+            // the search whose labels are written must be complete (with partial
+            // discharges that is the full one after the capped rounds)
+            const bool earlyOk = !(A.partial && full);
             // ---------------- multi-level search from the targets ----------------
-            for (int l = tid; l < V; l += NT) S[l] = kInf;
             if (tid == 0) {
                 s_qtail = 0;
                 s_nsteps = 0;
                 s_found = 0;
+                s_live = 0;
+                s_hit = 0;
             }
             __syncthreads();
+            int live = 0;
             for (int l = tid; l < V; l += NT) {
-                if (rt[base + l] > 0) {
+                const int prev = firstSearch ? kInf : S[l];
+                const bool dead = prev == kDead || (lastComplete && prev == kInf);
+                S[l] = dead ? kDead : kInf;
+                if (!dead && ex[base + l] > 0) live++;
+            }
+            live = wave_sum_i(live);
+            if ((tid & 63) == 0 && live) atomicAdd(&s_live, live);
+            __syncthreads();
+            for (int l = tid; l < V; l += NT) {
+                if (rt[base + l] > 0 && S[l] == kInf) {
                     S[l] = 0;
                     Q[atomicAdd(&s_qtail, 1)] = l;
+                    if (ex[base + l] > 0) {
+                        atomicSub(&s_live, 1);
+                        s_hit = 1;
+                    }
                 }
             }
             __syncthreads();
@@ -237,6 +262,10 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
             for (;;) {
                 // flood inside the region: u with c_f(u, v) > 0 to a frontier v
                 for (;;) {
+                    if (earlyOk && s_hit && s_live == 0) {
+                        early = true;
+                        break;
+                    }
                     const int fe = s_qtail;
                     if (fs == fe) break;
                     const int step = s_nsteps;
@@ -248,7 +277,13 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
                             int u = local_nbr(G, vz, vy, vx, k ^ 1);  // u + o_k = v
                             if (u < 0) continue;
                             if (res[(size_t)k * N + base + u] > 0 && S[u] == kInf) {
-                                if (atomicCAS(&S[u], kInf, step) == kInf) Q[atomicAdd(&s_qtail, 1)] = u;
+                                if (atomicCAS(&S[u], kInf, step) == kInf) {
+                                    Q[atomicAdd(&s_qtail, 1)] = u;
+                                    if (ex[base + u] > 0) {
+                                        atomicSub(&s_live, 1);
+                                        s_hit = 1;
+                                    }
+                                }
                             }
                         }
                     }
@@ -261,6 +296,7 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
                     fs = fe;
                     __syncthreads();
                 }
+                if (early) break;
                 // next stage: smallest d(w) + 1 over residual boundary arcs of unlabeled u
                 int best = kInf;
                 for (int i = tid; i < A.nring; i += NT) {
@@ -310,6 +346,10 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
                         if (d < dinf && d + 1 == level) {
                             S[l] = step;
                             Q[atomicAdd(&s_qtail, 1)] = l;
+                            if (ex[base + l] > 0) {
+                                atomicSub(&s_live, 1);
+                                s_hit = 1;
+                            }
                             break;
                         }
                     }
@@ -324,10 +364,12 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
                 __syncthreads();
             }
             bfs_steps += s_nsteps;
+            firstSearch = false;
+            lastComplete = !early && !capped;
             // ---------------- any excess vertex that reaches a target? ----------------
             int found = 0;
             for (int l = tid; l < V; l += NT)
-                if (S[l] != kInf && ex[base + l] > 0) found = 1;
+                if (S[l] < kDead && ex[base + l] > 0) found = 1;
             if (found) s_found = 1;
             __syncthreads();
             if (!s_found) {
@@ -410,14 +452,14 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
         // ---------------- region relabel result ----------------
         for (int l = tid; l < V; l += NT) {
             int s = S[l];
-            A.labNew[base + l] = (s == kInf) ? dinf : min(stepLevel[s], dinf);
+            A.labNew[base + l] = (s >= kDead) ? dinf : min(stepLevel[s], dinf);
         }
         if (A.trace) {
             long long ex_out = 0, lsum = 0;
             for (int l = tid; l < V; l += NT) ex_out += ex[base + l];
             for (int i = tid; i < A.nring; i += NT) {
                 const int s = S[A.ringL[i]];
-                lsum += (s == kInf) ? 65535 : min(stepLevel[s], 65535);
+                lsum += (s >= kDead) ? 65535 : min(stepLevel[s], 65535);
             }
             atomicAdd((unsigned long long *)&s_tr[0], (u64)ex_out);
             atomicAdd((unsigned long long *)&s_tr[3], (u64)lsum);
@@ -855,6 +897,8 @@ hipError_t launch_discharge(const DischargeArgs &A, int blocks, int threads, siz
         hipLaunchKernelGGL(k_discharge<256>, dim3(blocks), dim3(256), lds, s, A);
     else if (threads == 512)
         hipLaunchKernelGGL(k_discharge<512>, dim3(blocks), dim3(512), lds, s, A);
+    else if (threads == 1024)
+        hipLaunchKernelGGL(k_discharge<1024>, dim3(blocks), dim3(1024), lds, s, A);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
