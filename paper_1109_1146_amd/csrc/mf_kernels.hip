@@ -231,26 +231,25 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
                 s_hit = 0;
             }
             __syncthreads();
-            int live = 0;
+            // one pass: dead marks, live excess count, and the first level (r_t > 0;
+            // such a vertex is reached by every search, so it is never dead)
+            int live = 0, hit = 0;
             for (int l = tid; l < V; l += NT) {
                 const int prev = firstSearch ? kInf : S[l];
                 const bool dead = prev == kDead || (lastComplete && prev == kInf);
-                S[l] = dead ? kDead : kInf;
-                if (!dead && ex[base + l] > 0) live++;
+                const bool lv = !dead && ex[base + l] > 0;
+                if (!dead && rt[base + l] > 0) {
+                    S[l] = 0;
+                    Q[atomicAdd(&s_qtail, 1)] = l;
+                    hit |= lv ? 1 : 0;
+                } else {
+                    S[l] = dead ? kDead : kInf;
+                    live += lv ? 1 : 0;
+                }
             }
             live = wave_sum_i(live);
             if ((tid & 63) == 0 && live) atomicAdd(&s_live, live);
-            __syncthreads();
-            for (int l = tid; l < V; l += NT) {
-                if (rt[base + l] > 0 && S[l] == kInf) {
-                    S[l] = 0;
-                    Q[atomicAdd(&s_qtail, 1)] = l;
-                    if (ex[base + l] > 0) {
-                        atomicSub(&s_live, 1);
-                        s_hit = 1;
-                    }
-                }
-            }
+            if (hit) s_hit = 1;
             __syncthreads();
             if (tid == 0 && s_qtail > 0) {
                 stepEnd[0] = s_qtail;
@@ -368,8 +367,12 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
             lastComplete = !early && !capped;
             // ---------------- any excess vertex that reaches a target? ----------------
             int found = 0;
-            for (int l = tid; l < V; l += NT)
-                if (S[l] < kDead && ex[base + l] > 0) found = 1;
+            if (early) {
+                found = 1;  // every live excess vertex is labelled
+            } else {
+                for (int l = tid; l < V; l += NT)
+                    if (S[l] < kDead && ex[base + l] > 0) found = 1;
+            }
             if (found) s_found = 1;
             __syncthreads();
             if (!s_found) {
