@@ -16,6 +16,10 @@ What it computes (all integer, int64 accumulators):
   relabel (Alg. 3) and the global gap (Sec. 5.1), with the per-sweep checks of
   the statements of Sec. 4 switched on by ``checks``; optionally with the
   partial discharges (Sec. 6.2) and the boundary relabel heuristic (Sec. 6.1).
+* ``prd_grid`` -- the push-relabel region discharge of Sec. 3 (Proc. PRD,
+  first-in first-out Push/Relabel on each region network) under Alg. 2
+  (P-PRD) or Alg. 1 (S-PRD), with the global gap over all labels and per-sweep
+  checks of label validity and monotonicity.
 * ``boundary_relabel`` -- the heuristic of Sec. 6.1 on a given state, written
   separately in Python (groups, the two kinds of arcs, Dijkstra by heapq).
 * ``brute_force`` -- every cut of a network of at most ~20 vertices.
@@ -73,6 +77,10 @@ def _load():
         lib.orc_boundary_relabel.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P, P,
                                              ctypes.c_int32, P]
         lib.orc_boundary_relabel.restype = ctypes.c_int
+        lib.orc_prd.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P, P, P, P,
+                                ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                P, P, P, P, P, P, P, P, P, P]
+        lib.orc_prd.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -220,6 +228,42 @@ def ard_pairs(n, pu, pv, cuv, cvu, cs, ct, region, parallel=True, checks=CHK_ALL
         raise RuntimeError(f"orc_ard failed with code {rc}")
     return dict(flow=int(flow[0]), smin=smin, smax=smax, r_uv=r_uv, r_vu=r_vu, rt=rt, ex=ex,
                 labels=labels, sweeps=int(sweeps[0]), bsize=int(bsize[0]), complete=True)
+
+
+def prd_grid(inst, tile=None, parallel=True, gap=True, checks=CHK_VALID | CHK_MONO,
+             max_sweeps=None):
+    """Reference P-PRD (parallel=True) or S-PRD: distance labels of Sec. 2
+    (d(t) = 0, every arc of length 1, dinf = n), Proc. PRD per region, the
+    flow fusion of Alg. 2, the global gap over all labels."""
+    lib = _load()
+    tile = tuple(tile if tile is not None else inst.tile)
+    pu, pv, cuv, cvu = grid_pairs(inst.dims, inst.nbr, _offsets(inst))
+    region = grid_regions(inst.dims, tile)
+    n = inst.n
+    pu, pv, cuv, cvu, cs, ct, region = map(_c32, (pu, pv, cuv, cvu, inst.cs, inst.ct, region))
+    m = pu.shape[0]
+    r_uv = np.zeros(m, dtype=np.int64)
+    r_vu = np.zeros(m, dtype=np.int64)
+    rt = np.zeros(n, dtype=np.int64)
+    ex = np.zeros(n, dtype=np.int64)
+    flow = np.zeros(1, dtype=np.int64)
+    smin = np.zeros(n, dtype=np.uint8)
+    smax = np.zeros(n, dtype=np.uint8)
+    labels = np.zeros(n, dtype=np.int32)
+    sweeps = np.zeros(1, dtype=np.int64)
+    failed = np.zeros(1, dtype=np.int32)
+    if max_sweeps is None:
+        max_sweeps = 2 * n * n + 1
+    rc = lib.orc_prd(n, m, _p(pu), _p(pv), _p(cuv), _p(cvu), _p(cs), _p(ct), _p(region),
+                     1 if parallel else 0, 1 if gap else 0, int(max_sweeps), int(checks),
+                     _p(r_uv), _p(r_vu), _p(rt), _p(ex), _p(flow), _p(smin), _p(smax),
+                     _p(labels), _p(sweeps), _p(failed))
+    if rc == 3:
+        raise AssertionError(f"reference PRD invariant check {int(failed[0])} failed")
+    if rc != 0:
+        raise RuntimeError(f"orc_prd failed with code {rc}")
+    return dict(flow=int(flow[0]), smin=smin, smax=smax, r_uv=r_uv, r_vu=r_vu, rt=rt, ex=ex,
+                labels=labels, sweeps=int(sweeps[0]), pairs=(pu, pv, cuv, cvu))
 
 
 def ard_grid(inst, tile=None, parallel=True, checks=CHK_ALL, max_sweeps=None, partial=False,

@@ -1121,3 +1121,247 @@ done:
     net_free(&g);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Push-relabel region discharge (Sec. 3, Proc. PRD) with the generic       */
+/* drivers: Alg. 1 (S-PRD) and Alg. 2 (P-PRD, label and flow fusion).       */
+/* Labels are the distance labels of Sec. 2: d(t) = 0, every arc has length */
+/* 1, valid iff d(u) <= d(v) + 1 on every residual arc; dinf = n.           */
+/* ------------------------------------------------------------------------ */
+
+/* Proc. PRD on the region network of region rk: Push and Relabel, first in
+ * first out over the active vertices of the region, until none is left.  The
+ * labels of the boundary vertices outside the region (dold) stay fixed; a
+ * push over an arc (u, w) leaving the region is recorded in push[] and
+ * removed from c_f(u, w) (the arcs (w, u) belong to the neighbour's network).
+ * New labels of the region's vertices go to newd. */
+static void prd_discharge(ard_t *A, int32_t rk, const int32_t *dold) {
+    net_t *g = A->g;
+    const int64_t lo = A->first_r[rk], hi = A->first_r[rk + 1];
+    int32_t *d = A->newd;
+    for (int64_t i = lo; i < hi; i++) d[A->members[i]] = dold[A->members[i]];
+    /* FIFO of active vertices; a vertex is queued at most once at a time */
+    const int64_t cap = hi - lo + 1;
+    int64_t qh = 0, qt = 0;
+    for (int64_t i = lo; i < hi; i++) {
+        int32_t v = A->members[i];
+        A->seen[v] = 0;
+        if (A->ex[v] > 0 && d[v] < A->dinf) { A->queue[qt++ % cap] = v; A->seen[v] = 1; }
+    }
+    while (qh != qt) {
+        int32_t u = A->queue[qh++ % cap];
+        A->seen[u] = 0;
+        while (A->ex[u] > 0 && d[u] < A->dinf) {
+            int pushed = 0;
+            /* Push: to t if d(u) = 1, else along (u, v) with d(u) = d(v) + 1 */
+            if (A->rt[u] > 0 && d[u] == 1) {
+                int64_t delta = A->ex[u] < A->rt[u] ? A->ex[u] : A->rt[u];
+                A->rt[u] -= delta;
+                A->ex[u] -= delta;
+                pushed = 1;
+            }
+            for (int64_t a = g->first[u]; a < g->first[u + 1] && A->ex[u] > 0; a++) {
+                if (g->res[a] <= 0) continue;
+                int32_t v = g->head[a];
+                const int inside = A->region[v] == rk;
+                const int32_t dv = inside ? d[v] : dold[v];
+                if (d[u] != dv + 1) continue;
+                int64_t delta = A->ex[u] < g->res[a] ? A->ex[u] : g->res[a];
+                g->res[a] -= delta;
+                A->ex[u] -= delta;
+                if (inside) {
+                    g->res[g->rev[a]] += delta;
+                    A->ex[v] += delta;
+                    if (!A->seen[v] && d[v] < A->dinf) { A->queue[qt++ % cap] = v; A->seen[v] = 1; }
+                } else {
+                    A->push[a] += delta;
+                }
+                pushed = 1;
+            }
+            if (A->ex[u] <= 0) break;
+            if (!pushed || A->ex[u] > 0) {
+                /* Relabel: 1 + the smallest label over residual arcs (t counts 0) */
+                int64_t best = A->rt[u] > 0 ? 1 : (int64_t)A->dinf;
+                for (int64_t a = g->first[u]; a < g->first[u + 1]; a++) {
+                    if (g->res[a] <= 0) continue;
+                    int32_t v = g->head[a];
+                    const int32_t dv = A->region[v] == rk ? d[v] : dold[v];
+                    if ((int64_t)dv + 1 < best) best = (int64_t)dv + 1;
+                }
+                if (best > A->dinf) best = A->dinf;
+                if (best <= d[u]) best = d[u] + 1; /* no admissible arc left: strictly up */
+                if (best > A->dinf) best = A->dinf;
+                d[u] = (int32_t)best;
+            }
+        }
+    }
+}
+
+/* Global gap over all labels (Sec. 5.1): the smallest g >= 1 below the largest
+ * finite label with no vertex labelled g; labels above it go to dinf. */
+static void prd_gap(ard_t *A) {
+    int32_t n = A->g->n, top = -1;
+    for (int32_t v = 0; v < n; v++)
+        if (A->d[v] < A->dinf && A->d[v] > top) top = A->d[v];
+    if (top < 2) return;
+    uint8_t *present = calloc((size_t)top + 1, 1);
+    if (!present) return;
+    for (int32_t v = 0; v < n; v++)
+        if (A->d[v] < A->dinf) present[A->d[v]] = 1;
+    int32_t gap = -1;
+    for (int32_t l = 1; l < top; l++)
+        if (!present[l]) { gap = l; break; }
+    free(present);
+    if (gap < 0) return;
+    for (int32_t v = 0; v < n; v++)
+        if (A->d[v] > gap && A->d[v] < A->dinf) A->d[v] = A->dinf;
+}
+
+/* Validity of distance labels (Sec. 2): d(u) <= d(v) + 1 on residual arcs,
+ * d(u) <= 1 where c_f(u, t) > 0. */
+static int prd_valid(const ard_t *A) {
+    net_t *g = A->g;
+    for (int32_t u = 0; u < g->n; u++) {
+        if (A->rt[u] > 0 && A->d[u] > 1) return 0;
+        for (int64_t a = g->first[u]; a < g->first[u + 1]; a++)
+            if (g->res[a] > 0 && A->d[u] > A->d[g->head[a]] + 1) return 0;
+    }
+    return 1;
+}
+
+int orc_prd(int32_t n, int64_t np, const int32_t *pu, const int32_t *pv, const int32_t *cuv,
+            const int32_t *cvu, const int32_t *cs, const int32_t *ct, const int32_t *region,
+            int32_t parallel, int32_t gap_on, int64_t max_sweeps, int32_t checks, int64_t *r_uv,
+            int64_t *r_vu, int64_t *rt_out, int64_t *ex_out, int64_t *flow_out, uint8_t *smin,
+            uint8_t *smax, int32_t *labels_out, int64_t *sweeps_out, int32_t *failed_check) {
+    net_t g;
+    int rc = net_build(&g, n, np, pu, pv, cuv, cvu);
+    if (rc) return rc;
+    ard_t A;
+    memset(&A, 0, sizeof(A));
+    A.g = &g;
+    A.region = region;
+    int32_t nreg = 0;
+    for (int32_t v = 0; v < n; v++) {
+        if (region[v] < 0) { net_free(&g); return ORC_EINVAL; }
+        if (region[v] + 1 > nreg) nreg = region[v] + 1;
+    }
+    A.nreg = nreg;
+    A.dinf = n > 0 ? n : 1;
+    size_t nn = (size_t)(n ? n : 1);
+    A.ex = malloc(sizeof(int64_t) * nn);
+    A.rt = malloc(sizeof(int64_t) * nn);
+    A.d = malloc(sizeof(int32_t) * nn);
+    A.first_r = calloc((size_t)nreg + 1, sizeof(int64_t));
+    A.members = malloc(sizeof(int32_t) * nn);
+    A.queue = malloc(sizeof(int32_t) * (nn + 1));
+    A.seen = malloc(nn);
+    A.newd = malloc(sizeof(int32_t) * nn);
+    A.push = calloc((size_t)(g.m ? g.m : 1), sizeof(int64_t));
+    int32_t *dsnap = malloc(sizeof(int32_t) * nn);
+    int32_t *dprev = malloc(sizeof(int32_t) * nn);
+    if (!A.ex || !A.rt || !A.d || !A.first_r || !A.members || !A.queue || !A.seen || !A.newd ||
+        !A.push || !dsnap || !dprev) {
+        rc = ORC_ENOMEM;
+        goto done;
+    }
+    if (failed_check) *failed_check = 0;
+    for (int32_t v = 0; v < n; v++) A.first_r[region[v] + 1]++;
+    for (int32_t k = 0; k < nreg; k++) A.first_r[k + 1] += A.first_r[k];
+    {
+        int64_t *fill = malloc(sizeof(int64_t) * ((size_t)nreg + 1));
+        if (!fill) { rc = ORC_ENOMEM; goto done; }
+        memcpy(fill, A.first_r, sizeof(int64_t) * ((size_t)nreg + 1));
+        for (int32_t v = 0; v < n; v++) A.members[fill[region[v]]++] = v;
+        free(fill);
+    }
+    for (int32_t v = 0; v < n; v++) {
+        if (cs[v] < 0 || ct[v] < 0) { rc = ORC_EINVAL; goto done; }
+        A.ex[v] = cs[v];
+        A.rt[v] = ct[v];
+        A.d[v] = 0;
+    }
+    int64_t sweeps = 0;
+    for (;;) {
+        int any_active = 0;
+        for (int32_t v = 0; v < n && !any_active; v++)
+            if (A.ex[v] > 0 && A.d[v] < A.dinf) any_active = 1;
+        if (!any_active) break;
+        if (sweeps >= max_sweeps) { rc = ORC_ESWEEPS; goto done; }
+        memcpy(dprev, A.d, sizeof(int32_t) * nn);
+        sweeps++;
+        if (parallel) {
+            memcpy(dsnap, A.d, sizeof(int32_t) * nn);
+            memset(A.push, 0, sizeof(int64_t) * (size_t)(g.m ? g.m : 1));
+            for (int32_t rk = 0; rk < nreg; rk++) {
+                int has_active = 0;
+                for (int64_t i = A.first_r[rk]; i < A.first_r[rk + 1] && !has_active; i++) {
+                    int32_t v = A.members[i];
+                    if (A.ex[v] > 0 && dsnap[v] < A.dinf) has_active = 1;
+                }
+                if (!has_active) continue;
+                prd_discharge(&A, rk, dsnap);
+                for (int64_t i = A.first_r[rk]; i < A.first_r[rk + 1]; i++) {
+                    int32_t v = A.members[i];
+                    A.d[v] = A.newd[v];
+                }
+            }
+            /* flow fusion of Alg. 2: a push over (u,v) between regions stays iff
+             * d'(v) <= d'(u) + 1, otherwise it returns to u */
+            for (int64_t a = 0; a < g.m; a++) {
+                if (A.push[a] == 0) continue;
+                int32_t u = g.tail[a], v = g.head[a];
+                int64_t p = A.push[a];
+                if (A.d[v] <= A.d[u] + 1) {
+                    g.res[g.rev[a]] += p;
+                    A.ex[v] += p;
+                } else {
+                    g.res[a] += p;
+                    A.ex[u] += p;
+                }
+            }
+            if (gap_on) prd_gap(&A);
+        } else {
+            for (int32_t rk = 0; rk < nreg; rk++) {
+                int has_active = 0;
+                for (int64_t i = A.first_r[rk]; i < A.first_r[rk + 1] && !has_active; i++) {
+                    int32_t v = A.members[i];
+                    if (A.ex[v] > 0 && A.d[v] < A.dinf) has_active = 1;
+                }
+                if (!has_active) continue;
+                memset(A.push, 0, sizeof(int64_t) * (size_t)(g.m ? g.m : 1));
+                prd_discharge(&A, rk, A.d);
+                for (int64_t i = A.first_r[rk]; i < A.first_r[rk + 1]; i++) {
+                    int32_t v = A.members[i];
+                    A.d[v] = A.newd[v];
+                }
+                for (int64_t i = A.first_r[rk]; i < A.first_r[rk + 1]; i++) {
+                    int32_t u = A.members[i];
+                    for (int64_t a = g.first[u]; a < g.first[u + 1]; a++) {
+                        if (A.push[a] == 0) continue;
+                        g.res[g.rev[a]] += A.push[a];
+                        A.ex[g.head[a]] += A.push[a];
+                    }
+                }
+                if (gap_on) prd_gap(&A);
+            }
+        }
+        if (checks & ORC_CHK_MONO)
+            for (int32_t v = 0; v < n; v++)
+                if (A.d[v] < dprev[v]) {
+                    rc = ORC_ECHECK; if (failed_check) *failed_check = ORC_CHK_MONO; goto done;
+                }
+        if ((checks & ORC_CHK_VALID) && !prd_valid(&A)) {
+            rc = ORC_ECHECK; if (failed_check) *failed_check = ORC_CHK_VALID; goto done;
+        }
+    }
+    if (sweeps_out) *sweeps_out = sweeps;
+    if (labels_out) memcpy(labels_out, A.d, sizeof(int32_t) * (size_t)n);
+    write_outputs(&g, np, A.rt, A.ex, ct, r_uv, r_vu, rt_out, ex_out, flow_out);
+    rc = cuts_from_residual(&g, A.rt, A.ex, smin, smax);
+done:
+    free(A.ex); free(A.rt); free(A.d); free(A.first_r); free(A.members); free(A.queue);
+    free(A.seen); free(A.newd); free(A.push); free(dsnap); free(dprev);
+    net_free(&g);
+    return rc;
+}

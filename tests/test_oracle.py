@@ -428,3 +428,48 @@ def test_reference_ard_boundary_relabel_exact_and_invariants(seed, partial):
     s = oracle.ard_grid(inst, parallel=False, partial=partial, boundary_relabel=True,
                         checks=oracle.CHK_ALL)
     assert s["flow"] == ref["flow"]
+
+
+# ---------------------------------------------------------------------------
+# Push-relabel region discharge (Sec. 3, Proc. PRD; Alg. 1 and 2)
+# ---------------------------------------------------------------------------
+
+PRD_CASES = [((12, 13), 4, (4, 5)), ((16, 16), 8, (4, 8)), ((6, 7, 8), 6, (3, 4, 4)),
+             ((20, 9), 8, (5, 3)), ((5, 9, 13), 6, (5, 4, 6)), ((30, 30), 4, (6, 6))]
+
+
+@pytest.mark.parametrize("parallel", [True, False])
+@pytest.mark.parametrize("seed", range(12))
+def test_reference_prd_exact_and_invariants(seed, parallel):
+    """P-PRD / S-PRD: the textbook flow and both cuts, distance labels valid and
+    monotone after every sweep, at most 2n^2 sweeps."""
+    dims, conn, tile = PRD_CASES[seed % len(PRD_CASES)]
+    inst = synth.random_grid(dims, conn, 1800 + seed, tile=tile)
+    ref = oracle.solve_grid(inst)
+    p = oracle.prd_grid(inst, parallel=parallel)
+    assert p["flow"] == ref["flow"]
+    assert (p["smin"] == ref["smin"]).all() and (p["smax"] == ref["smax"]).all()
+    assert p["sweeps"] <= 2 * inst.n ** 2
+    # without the gap it still ends, with the same result
+    q = oracle.prd_grid(inst, parallel=parallel, gap=False)
+    assert q["flow"] == ref["flow"]
+
+
+def test_reference_prd_single_region_is_one_sweep():
+    """With one region Proc. PRD is plain push-relabel: one sweep solves it."""
+    inst = synth.random_grid((14, 15), 8, 1850, tile=(14, 15))
+    p = oracle.prd_grid(inst)
+    assert p["sweeps"] == 1 and p["flow"] == oracle.solve_grid(inst)["flow"]
+
+
+def test_ard_sweeps_below_prd_sweeps():
+    """The paper's comparison (Tables 1 and 2): on the same partition ARD needs
+    fewer sweeps than PRD, here summed over a family of random grids."""
+    ard = prd = 0
+    for seed in range(6):
+        dims, conn, tile = PRD_CASES[seed]
+        inst = synth.random_grid(dims, conn, 1900 + seed, tile=tile)
+        ard += oracle.ard_grid(inst)["sweeps"]
+        prd += oracle.prd_grid(inst)["sweeps"]
+    print(f"P-ARD {ard} sweeps, P-PRD {prd} sweeps", flush=True)
+    assert ard < prd
