@@ -107,7 +107,17 @@ typedef struct {
                                      (labels it has not reached by then are lifted to n + 1 at most,
                                      which keeps them valid); n level kernels are launched per sweep
                                      (those after the search ended exit at once).  0 = off */
+    int32_t method;               /* MF_METHOD_ARD (0): augmented-path region discharge (Sec. 4);
+                                     MF_METHOD_PRD (1): push-relabel region discharge (Sec. 3,
+                                     Proc. PRD) under the same parallel driver (Alg. 2), with the
+                                     distance labels of Sec. 2 (every arc counts, d_inf = n), the
+                                     global gap over all labels and the HBM region kernel; not
+                                     combined with partial, boundary_relabel, global_relabel_every,
+                                     features or MF_SCHED_LEARNED (MF_E_INVAL) */
 } mf_solve_opts;
+
+/* region discharge operation, see mf_solve_opts.method */
+enum { MF_METHOD_ARD = 0, MF_METHOD_PRD = 1 };
 
 /* region features (floats) written per region and sweep, see mf_solve_opts.features */
 enum {
@@ -239,8 +249,9 @@ mf_status mf_get_state(const mf_grid *g, int32_t *res, int32_t *rt, int32_t *ex,
  *               lifted to n + 1 at most, a valid lower bound)
  *   levels_out  receives the number of levels that assigned a distance (may be NULL)
  * Runs on the device (one workgroup per region and level, levels launched in
- * batches of eight until the search ends).  Errors: MF_E_INVAL, MF_E_STATE,
- * MF_E_DEVICE. */
+ * batches of eight until the search ends).  Errors: MF_E_INVAL, MF_E_STATE
+ * (also for a state left by MF_METHOD_PRD, whose labels are not region
+ * distances), MF_E_DEVICE. */
 mf_status mf_boundary_relabel(mf_grid *g, int32_t max_levels, int64_t *levels_out);
 
 /* Shape facts of a handle: number of vertices, K, regions, |B|, region shape. */

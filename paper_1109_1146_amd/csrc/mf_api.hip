@@ -56,6 +56,7 @@ struct mf_grid {
     // instance state
     bool has_caps = false, solved = false;
     bool has_state = false;       // a solve left a state (completed, or stopped by max_sweeps)
+    bool state_prd = false;       // that state carries distance labels (MF_METHOD_PRD)
     long long sum_cs = 0, sum_ct = 0, flow = 0;
     int final_parity = 0;
     int cut_kind_cached = -1;     // kind whose reachability marks g->mark holds
@@ -614,6 +615,14 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     if (opts) o = *opts;
     if (o.schedule < 0 || o.schedule > MF_SCHED_AUTO) return MF_E_INVAL;
     if (o.schedule == MF_SCHED_COLORED) return MF_E_INVAL;
+    if (o.method != MF_METHOD_ARD && o.method != MF_METHOD_PRD) return MF_E_INVAL;
+    const bool prd = o.method == MF_METHOD_PRD;
+    // push-relabel region discharge: distance labels over every arc; the
+    // heuristics and the exact relabel here are those of region distances
+    if (prd && (o.schedule == MF_SCHED_LEARNED || o.partial || o.boundary_relabel ||
+                o.global_relabel_every || (o.features && o.features_cap > 0) ||
+                (o.region_kernel != MF_KERNEL_AUTO && o.region_kernel != MF_KERNEL_HBM)))
+        return MF_E_INVAL;
     const bool learned = o.schedule == MF_SCHED_LEARNED;
     mf_model *model = (mf_model *)o.model;
     // the scheduler's queue kernel keeps one class byte per region in LDS
@@ -636,7 +645,9 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     if (o.boundary_relabel < 0 || o.boundary_relabel > 4096) return MF_E_INVAL;
     const int brl = o.boundary_relabel;
     if (o.global_relabel_every > 0) check_every = o.global_relabel_every;
-    long long B = g->nB > 0 ? g->nB : 1;
+    // labels: region distances below dinf = |B| (ARD), or distances below dinf = n (PRD)
+    const int dinf = prd ? (int)std::max<long long>(g->n, 1) : g->dinf;
+    long long B = prd ? (long long)dinf : (g->nB > 0 ? g->nB : 1);
     long long bound = (B > 2000000000LL) ? (1LL << 62) : 2 * B * B + 1;
     long long max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : bound;
     hipStream_t s = (hipStream_t)o.stream;
@@ -651,6 +662,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     }
     g->solved = false;
     g->has_state = false;
+    g->state_prd = prd;
     g->cut_kind_cached = -1;
     const Geo &G = g->G;
     auto t0 = std::chrono::high_resolution_clock::now();
@@ -675,7 +687,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     D.G = G;
     D.res = g->res; D.rt = g->rt; D.ex = g->ex; D.pushb = g->pushb;
     D.ractive = g->ractive; D.order = g->order; D.nwork = G.nreg;
-    D.dinf = g->dinf; D.scratch = g->scratch; D.ringL = g->ringL; D.ringM = g->ringM;
+    D.dinf = dinf; D.scratch = g->scratch; D.ringL = g->ringL; D.ringM = g->ringM;
+    D.prd = prd ? 1 : 0;
     D.nring = g->nring; D.stats = g->stats; D.rvcount = g->rvcount; D.err = g->err;
     D.useLDS = g->useLDS ? 1 : 0;
     D.maxIter = 1 << 18;
@@ -721,7 +734,9 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     }
     int regionMode = 0;  // 0: HBM, 1: LDS workgroup, 2: wavefront, 3: row-bitmask workgroup
     switch (o.region_kernel) {
-        case MF_KERNEL_AUTO: regionMode = waveLds ? 2 : (rowsLds ? 3 : (groupLds ? 1 : 0)); break;
+        case MF_KERNEL_AUTO:
+            regionMode = prd ? 0 : (waveLds ? 2 : (rowsLds ? 3 : (groupLds ? 1 : 0)));
+            break;
         case MF_KERNEL_HBM: regionMode = 0; break;
         case MF_KERNEL_LDS: if (!groupLds) return MF_E_INVAL; regionMode = 1; break;
         case MF_KERNEL_WAVE: if (!waveLds) return MF_E_INVAL; regionMode = 2; break;
@@ -742,9 +757,10 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     mfd::FuseArgs F;
     memset(&F, 0, sizeof(F));
     F.G = G; F.bidx = g->bidx; F.nB = (int)g->nB; F.res = g->res; F.ex = g->ex; F.pushb = g->pushb;
-    F.dinf = g->dinf; F.hist = g->hist; F.maxlab = g->maxlab;
-    // with the boundary relabel the histogram is built from its lifted labels
-    F.histOn = brl > 0 ? 0 : 1;
+    F.dinf = dinf; F.hist = g->hist; F.maxlab = g->maxlab;
+    // with the boundary relabel the histogram is built from its lifted labels;
+    // with push-relabel region discharge over all labels
+    F.histOn = (brl > 0 || prd) ? 0 : 1;
     // boundary relabel after the fusion; its distances use the cut marks' buffer
     // (free during a solve)
     mfd::BrlArgs BA;
@@ -761,7 +777,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     mfd::GapApplyArgs Q;
     memset(&Q, 0, sizeof(Q));
     Q.G = G; Q.bidx = g->bidx; Q.nB = (int)g->nB; Q.ex = g->ex; Q.ractive = g->ractive;
-    Q.gap = g->gap; Q.dinf = g->dinf;
+    Q.gap = g->gap; Q.dinf = dinf;
 
     std::vector<hipEvent_t> ev;
     if (o.profile) {
@@ -830,6 +846,9 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                 if (o.profile && !ok(hipEventRecord(ev[2 * j + 1], s))) return false;
                 F.lab = g->lab[p ^ 1]; F.actIn = g->act + p;
                 if (!ok(mfd::launch_fuse(F, s))) return false;
+                if (prd && !ok(mfd::launch_label_hist(g->lab[p ^ 1], G.N, dinf, g->hist, g->maxlab,
+                                                      g->act + p, s)))
+                    return false;
                 if (brl > 0) {
                     BA.lab = g->lab[p ^ 1]; BA.actIn = g->act + p;
                     if (!ok(mfd::launch_boundary_relabel(BA, 0, 0, 0, s)) ||
@@ -839,6 +858,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                 }
                 P.actIn = g->act + p; P.actOut = g->act + (p ^ 1); P.qheadNext = g->qhead + (p ^ 1);
                 if (!ok(mfd::launch_gap_find(P, s))) return false;
+                if (prd && !ok(mfd::launch_gap_raise_all(g->lab[p ^ 1], G.N, g->gap, dinf, g->act + p, s)))
+                    return false;
                 Q.lab = g->lab[p ^ 1]; Q.actIn = g->act + p; Q.actOut = g->act + (p ^ 1);
                 if (!ok(mfd::launch_gap_apply(Q, s))) return false;
             }
@@ -851,7 +872,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
             const long long key = ((long long)check_every << 8) | (o.gap ? 1 : 0) << 1 |
                                   (long long)(regionMode << 2) | (long long)(regionNarrow << 4) |
                                   (long long)((g->lab[0] < g->lab[1]) ? 1 : 0) << 6 |
-                                  (long long)(o.partial ? 1 : 0) << 7 | (long long)brl << 40;
+                                  (long long)(o.partial ? 1 : 0) << 7 | (long long)brl << 40 |
+                                  (long long)(prd ? 1 : 0) << 56;
             if (!g->graph_exec || g->graph_key != key) {
                 if (g->graph_exec) { (void)hipGraphExecDestroy(g->graph_exec); g->graph_exec = nullptr; }
                 hipGraph_t graph = nullptr;
@@ -936,7 +958,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         st->global_relabels = relabels;
         st->global_relabel_levels = relabel_levels;
         st->boundary_size = g->nB;
-        st->d_inf = g->dinf;
+        st->d_inf = dinf;
         st->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
         st->discharge_ms = discharge_ms;
         st->discharge_launches = timed;
@@ -1220,7 +1242,7 @@ extern "C" mf_status mf_get_state(const mf_grid *gc, int32_t *res, int32_t *rt, 
 
 extern "C" mf_status mf_boundary_relabel(mf_grid *g, int32_t max_levels, int64_t *levels_out) {
     if (!g || max_levels <= 0) return MF_E_INVAL;
-    if (!g->has_state) return MF_E_STATE;
+    if (!g->has_state || g->state_prd) return MF_E_STATE;
     hipStream_t s = nullptr;
     mfd::BrlArgs BA;
     memset(&BA, 0, sizeof(BA));

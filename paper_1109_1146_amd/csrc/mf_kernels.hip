@@ -251,32 +251,94 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
             if ((tid & 63) == 0 && live) atomicAdd(&s_live, live);
             if (hit) s_hit = 1;
             __syncthreads();
-            if (tid == 0 && s_qtail > 0) {
-                stepEnd[0] = s_qtail;
-                stepLevel[0] = 0;
-                s_nsteps = 1;
-            }
-            __syncthreads();
-            int fs = 0;
-            for (;;) {
-                // flood inside the region: u with c_f(u, v) > 0 to a frontier v
+            if (A.prd) {
+                // Proc. PRD: exact distance labels of the region network, d(t) = 0
+                // and every arc of length 1, with the boundary labels fixed: a
+                // border vertex is a seed at d(w) + 1 over its residual boundary
+                // arcs.  Steps are consecutive distances, with a jump to the next
+                // seed distance when the frontier runs dry.
+                auto seed_dist = [&](int i) -> int {
+                    const int l = A.ringL[i];
+                    const unsigned m = A.ringM[i];
+                    int lz, ly, lx;
+                    local_xyz(G, l, lz, ly, lx);
+                    int best = kInf;
+                    for (int k = 0; k < G.K; k++) {
+                        if (!((m >> k) & 1u)) continue;
+                        if (res[(size_t)k * N + base + l] <= 0) continue;
+                        const int w = cross_nbr(G, r, lz, ly, lx, k);
+                        if (w < 0) continue;
+                        const int d = labOld[w];
+                        if (d < dinf) best = min(best, d + 1);
+                    }
+                    return best;
+                };
+                // smallest seed distance of a border vertex not reached yet (block-uniform)
+                auto ring_min = [&]() -> int {
+                    int best = kInf;
+                    for (int i = tid; i < A.nring; i += NT)
+                        if (S[A.ringL[i]] == kInf) best = min(best, seed_dist(i));
+                    best = wave_min_i(best);
+                    if ((tid & 63) == 0) s_wmin[tid >> 6] = best;
+                    __syncthreads();
+                    if (tid == 0) {
+                        int b = kInf;
+                        for (int w = 0; w < NT / 64; w++) b = min(b, s_wmin[w]);
+                        s_min = b;
+                    }
+                    __syncthreads();
+                    return s_min;
+                };
+                auto add_seeds = [&](int dist, int step) {
+                    for (int i = tid; i < A.nring; i += NT) {
+                        const int l = A.ringL[i];
+                        if (S[l] != kInf || seed_dist(i) != dist) continue;
+                        if (atomicCAS(&S[l], kInf, step) == kInf) {
+                            Q[atomicAdd(&s_qtail, 1)] = l;
+                            if (ex[base + l] > 0) {
+                                atomicSub(&s_live, 1);
+                                s_hit = 1;
+                            }
+                        }
+                    }
+                };
+                // step 0 is distance 1: the vertices with c_f(u, t) > 0 (queued by the
+                // pass above) and the seeds at distance 1
+                int nextSeed = ring_min();
+                if (nextSeed == 1) {
+                    add_seeds(1, 0);
+                    __syncthreads();
+                    nextSeed = ring_min();
+                }
+                if (tid == 0 && s_qtail > 0) {
+                    stepEnd[0] = s_qtail;
+                    stepLevel[0] = 1;
+                    s_nsteps = 1;
+                }
+                __syncthreads();
+                int fs = 0;
                 for (;;) {
                     if (earlyOk && s_hit && s_live == 0) {
                         early = true;
                         break;
                     }
                     const int fe = s_qtail;
-                    if (fs == fe) break;
                     const int step = s_nsteps;
-                    for (int i = fs + tid; i < fe; i += NT) {
-                        int v = Q[i];
-                        int vz, vy, vx;
-                        local_xyz(G, v, vz, vy, vx);
-                        for (int k = 0; k < G.K; k++) {
-                            int u = local_nbr(G, vz, vy, vx, k ^ 1);  // u + o_k = v
-                            if (u < 0) continue;
-                            if (res[(size_t)k * N + base + u] > 0 && S[u] == kInf) {
-                                if (atomicCAS(&S[u], kInf, step) == kInf) {
+                    int Dn;
+                    if (fs == fe) {
+                        if (nextSeed == kInf) break;
+                        Dn = nextSeed;  // jump to the next seed distance
+                    } else {
+                        Dn = stepLevel[step - 1] + 1;
+                        for (int i = fs + tid; i < fe; i += NT) {
+                            const int v = Q[i];
+                            int vz, vy, vx;
+                            local_xyz(G, v, vz, vy, vx);
+                            for (int k = 0; k < G.K; k++) {
+                                const int u = local_nbr(G, vz, vy, vx, k ^ 1);  // u + o_k = v
+                                if (u < 0) continue;
+                                if (res[(size_t)k * N + base + u] > 0 && S[u] == kInf &&
+                                    atomicCAS(&S[u], kInf, step) == kInf) {
                                     Q[atomicAdd(&s_qtail, 1)] = u;
                                     if (ex[base + u] > 0) {
                                         atomicSub(&s_live, 1);
@@ -286,81 +348,129 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
                             }
                         }
                     }
+                    if (nextSeed == Dn) add_seeds(Dn, step);
                     __syncthreads();
                     if (tid == 0 && s_qtail > fe) {
                         stepEnd[step] = s_qtail;
-                        stepLevel[step] = step > 0 ? stepLevel[step - 1] : 0;
+                        stepLevel[step] = Dn;
                         s_nsteps = step + 1;
                     }
+                    if (nextSeed == Dn) nextSeed = ring_min();
                     fs = fe;
                     __syncthreads();
                 }
-                if (early) break;
-                // next stage: smallest d(w) + 1 over residual boundary arcs of unlabeled u
-                int best = kInf;
-                for (int i = tid; i < A.nring; i += NT) {
-                    int l = A.ringL[i];
-                    if (S[l] != kInf) continue;
-                    unsigned m = A.ringM[i];
-                    int lz, ly, lx;
-                    local_xyz(G, l, lz, ly, lx);
-                    for (int k = 0; k < G.K; k++) {
-                        if (!((m >> k) & 1u)) continue;
-                        if (res[(size_t)k * N + base + l] <= 0) continue;
-                        int w = cross_nbr(G, r, lz, ly, lx, k);
-                        if (w < 0) continue;
-                        int d = labOld[w];
-                        if (d < dinf) best = min(best, d + 1);
-                    }
-                }
-                best = wave_min_i(best);
-                if ((tid & 63) == 0) s_wmin[tid >> 6] = best;
-                __syncthreads();
-                if (tid == 0) {
-                    int b = kInf;
-                    for (int w = 0; w < NT / 64; w++) b = min(b, s_wmin[w]);
-                    s_min = b;
+            } else {
+                if (tid == 0 && s_qtail > 0) {
+                    stepEnd[0] = s_qtail;
+                    stepLevel[0] = 0;
+                    s_nsteps = 1;
                 }
                 __syncthreads();
-                const int level = s_min;
-                if (level == kInf) break;
-                if (!full && level > stageCap) {
-                    capped = true;
-                    break;
-                }
-                classes++;
-                const int step = s_nsteps;
-                for (int i = tid; i < A.nring; i += NT) {
-                    int l = A.ringL[i];
-                    if (S[l] != kInf) continue;
-                    unsigned m = A.ringM[i];
-                    int lz, ly, lx;
-                    local_xyz(G, l, lz, ly, lx);
-                    for (int k = 0; k < G.K; k++) {
-                        if (!((m >> k) & 1u)) continue;
-                        if (res[(size_t)k * N + base + l] <= 0) continue;
-                        int w = cross_nbr(G, r, lz, ly, lx, k);
-                        if (w < 0) continue;
-                        int d = labOld[w];
-                        if (d < dinf && d + 1 == level) {
-                            S[l] = step;
-                            Q[atomicAdd(&s_qtail, 1)] = l;
-                            if (ex[base + l] > 0) {
-                                atomicSub(&s_live, 1);
-                                s_hit = 1;
-                            }
+                int fs = 0;
+                for (;;) {
+                    // flood inside the region: u with c_f(u, v) > 0 to a frontier v
+                    for (;;) {
+                        if (earlyOk && s_hit && s_live == 0) {
+                            early = true;
                             break;
                         }
+                        const int fe = s_qtail;
+                        if (fs == fe) break;
+                        const int step = s_nsteps;
+                        for (int i = fs + tid; i < fe; i += NT) {
+                            int v = Q[i];
+                            int vz, vy, vx;
+                            local_xyz(G, v, vz, vy, vx);
+                            for (int k = 0; k < G.K; k++) {
+                                int u = local_nbr(G, vz, vy, vx, k ^ 1);  // u + o_k = v
+                                if (u < 0) continue;
+                                if (res[(size_t)k * N + base + u] > 0 && S[u] == kInf) {
+                                    if (atomicCAS(&S[u], kInf, step) == kInf) {
+                                        Q[atomicAdd(&s_qtail, 1)] = u;
+                                        if (ex[base + u] > 0) {
+                                            atomicSub(&s_live, 1);
+                                            s_hit = 1;
+                                        }
+                                    }
+                                }
+                            }
+                        }
+                        __syncthreads();
+                        if (tid == 0 && s_qtail > fe) {
+                            stepEnd[step] = s_qtail;
+                            stepLevel[step] = step > 0 ? stepLevel[step - 1] : 0;
+                            s_nsteps = step + 1;
+                        }
+                        fs = fe;
+                        __syncthreads();
                     }
+                    if (early) break;
+                    // next stage: smallest d(w) + 1 over residual boundary arcs of unlabeled u
+                    int best = kInf;
+                    for (int i = tid; i < A.nring; i += NT) {
+                        int l = A.ringL[i];
+                        if (S[l] != kInf) continue;
+                        unsigned m = A.ringM[i];
+                        int lz, ly, lx;
+                        local_xyz(G, l, lz, ly, lx);
+                        for (int k = 0; k < G.K; k++) {
+                            if (!((m >> k) & 1u)) continue;
+                            if (res[(size_t)k * N + base + l] <= 0) continue;
+                            int w = cross_nbr(G, r, lz, ly, lx, k);
+                            if (w < 0) continue;
+                            int d = labOld[w];
+                            if (d < dinf) best = min(best, d + 1);
+                        }
+                    }
+                    best = wave_min_i(best);
+                    if ((tid & 63) == 0) s_wmin[tid >> 6] = best;
+                    __syncthreads();
+                    if (tid == 0) {
+                        int b = kInf;
+                        for (int w = 0; w < NT / 64; w++) b = min(b, s_wmin[w]);
+                        s_min = b;
+                    }
+                    __syncthreads();
+                    const int level = s_min;
+                    if (level == kInf) break;
+                    if (!full && level > stageCap) {
+                        capped = true;
+                        break;
+                    }
+                    classes++;
+                    const int step = s_nsteps;
+                    for (int i = tid; i < A.nring; i += NT) {
+                        int l = A.ringL[i];
+                        if (S[l] != kInf) continue;
+                        unsigned m = A.ringM[i];
+                        int lz, ly, lx;
+                        local_xyz(G, l, lz, ly, lx);
+                        for (int k = 0; k < G.K; k++) {
+                            if (!((m >> k) & 1u)) continue;
+                            if (res[(size_t)k * N + base + l] <= 0) continue;
+                            int w = cross_nbr(G, r, lz, ly, lx, k);
+                            if (w < 0) continue;
+                            int d = labOld[w];
+                            if (d < dinf && d + 1 == level) {
+                                S[l] = step;
+                                Q[atomicAdd(&s_qtail, 1)] = l;
+                                if (ex[base + l] > 0) {
+                                    atomicSub(&s_live, 1);
+                                    s_hit = 1;
+                                }
+                                break;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                    if (tid == 0) {
+                        // at least one seed exists: level came from an unlabeled ring vertex
+                        stepEnd[step] = s_qtail;
+                        stepLevel[step] = level;
+                        s_nsteps = step + 1;
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
-                if (tid == 0) {
-                    // at least one seed exists: level came from an unlabeled ring vertex
-                    stepEnd[step] = s_qtail;
-                    stepLevel[step] = level;
-                    s_nsteps = step + 1;
-                }
-                __syncthreads();
             }
             bfs_steps += s_nsteps;
             firstSearch = false;
@@ -400,6 +510,55 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
             for (int s = nsteps - 1; s >= 0; s--) {
                 const int lo = s > 0 ? stepEnd[s - 1] : 0, hi = stepEnd[s];
                 const int L = stepLevel[s];
+                if (A.prd) {
+                    // Push along admissible arcs, d(u) = d(v) + 1: into t at distance
+                    // 1, to the previous step when it is distance L - 1, and over
+                    // boundary arcs to w with d(w) + 1 = L
+                    const bool adjPrev = s > 0 && stepLevel[s - 1] == L - 1;
+                    for (int i = lo + tid; i < hi; i += NT) {
+                        const int u = Q[i];
+                        int e = ex[base + u];
+                        if (e <= 0) continue;
+                        int uz, uy, ux;
+                        local_xyz(G, u, uz, uy, ux);
+                        if (L == 1) {
+                            const int t = rt[base + u];
+                            if (t > 0) {
+                                const int d = min(e, t);
+                                rt[base + u] = t - d;
+                                e -= d;
+                                if (A.trace) atomicAdd((unsigned long long *)&s_tr[1], (u64)d);
+                            }
+                        }
+                        for (int k = 0; k < G.K && e > 0; k++) {
+                            const size_t a = (size_t)k * N + base + u;
+                            const int c = res[a];
+                            if (c <= 0) continue;
+                            const int v = local_nbr(G, uz, uy, ux, k);
+                            if (v >= 0) {
+                                if (!adjPrev || S[v] != s - 1) continue;
+                                const int d = min(e, c);
+                                res[a] = c - d;
+                                res[(size_t)(k ^ 1) * N + base + v] += d;
+                                atomicAdd(&ex[base + v], d);
+                                e -= d;
+                            } else {
+                                const int w = cross_nbr(G, r, uz, uy, ux, k);
+                                if (w < 0) continue;
+                                const int dw = labOld[w];
+                                if (dw >= dinf || dw + 1 != L) continue;
+                                const int d = min(e, c);
+                                res[a] = c - d;
+                                pushb[a] += d;
+                                e -= d;
+                                if (A.trace) atomicAdd((unsigned long long *)&s_tr[2], (u64)d);
+                            }
+                        }
+                        ex[base + u] = e;
+                    }
+                    __syncthreads();
+                    continue;
+                }
                 const bool seed = (s == 0) || (stepLevel[s - 1] != L);
                 for (int i = lo + tid; i < hi; i += NT) {
                     const int u = Q[i];
@@ -638,6 +797,50 @@ __global__ void k_gap_apply(GapApplyArgs A) {
         int t = 0;
         for (int w = 0; w < (int)(blockDim.x >> 6); w++) t += s_w[w];
         if (t) atomicAdd(A.actOut, (u64)t);
+    }
+}
+
+// Histogram of all labels below dinf (the global gap of push-relabel region
+// discharge, whose labels count every arc: a gap must be empty over all
+// vertices, not only over B) and the largest such label.
+__global__ void k_label_hist(const int *lab, int N, int dinf, unsigned int *hist, int *maxlab,
+                             const unsigned long long *actIn) {
+    __shared__ unsigned int lh[kHistLds];
+    __shared__ int s_wmax[4];
+    if (*actIn == 0ull) return;
+    for (int b = threadIdx.x; b < kHistLds; b += blockDim.x) lh[b] = 0u;
+    __syncthreads();
+    int mx = -1;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        const int d = lab[i];
+        if (d >= dinf) continue;
+        if (d < kHistLds) atomicAdd(&lh[d], 1u);
+        else if (d < kHistBins) atomicAdd(&hist[d], 1u);
+        mx = max(mx, d);
+    }
+    mx = wave_max_i(mx);
+    if ((threadIdx.x & 63) == 0) s_wmax[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    for (int b = threadIdx.x; b < kHistLds; b += blockDim.x)
+        if (lh[b]) atomicAdd(&hist[b], lh[b]);
+    if (threadIdx.x == 0) {
+        int mm = -1;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) mm = max(mm, s_wmax[w]);
+        if (mm >= 0) atomicMax(maxlab, mm);
+    }
+}
+
+// The gap over all vertices (push-relabel region discharge): with distance
+// labels a raised boundary vertex may have a residual arc into an interior
+// vertex above the gap, which must be raised too for the labeling to stay valid.
+__global__ void k_gap_raise_all(int *lab, int N, const int *gap, int dinf,
+                                const unsigned long long *actIn) {
+    if (*actIn == 0ull) return;
+    const int g = *gap;
+    if (g < 0) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        const int d = lab[i];
+        if (d > g && d < dinf) lab[i] = dinf;
     }
 }
 
@@ -925,6 +1128,20 @@ hipError_t launch_boundary_relabel(const BrlArgs &A, int stage, int first, int c
         if (A.levels <= 0) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_brl_apply, dim3(cdiv(A.nB, 256)), dim3(256), 0, s, A);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_label_hist(const int *lab, int N, int dinf, unsigned int *hist, int *maxlab,
+                             const unsigned long long *actIn, hipStream_t s) {
+    hipLaunchKernelGGL(k_label_hist, dim3(min(cdiv(N, 256), 1024)), dim3(256), 0, s, lab, N, dinf,
+                       hist, maxlab, actIn);
+    return hipGetLastError();
+}
+
+hipError_t launch_gap_raise_all(int *lab, int N, const int *gap, int dinf,
+                                const unsigned long long *actIn, hipStream_t s) {
+    hipLaunchKernelGGL(k_gap_raise_all, dim3(min(cdiv(N, 256), 1024)), dim3(256), 0, s, lab, N, gap,
+                       dinf, actIn);
     return hipGetLastError();
 }
 

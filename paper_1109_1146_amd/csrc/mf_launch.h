@@ -40,6 +40,10 @@ struct DischargeArgs {
     int partial;
     const unsigned long long *sweepCount;
     unsigned long long *actCarry;  // null unless partial
+    // Push-relabel region discharge (Sec. 3, Proc. PRD; HBM kernel only): labels
+    // are the distance labels of Sec. 2 (d(t) = 0, every arc of length 1, dinf =
+    // n) instead of region distances
+    int prd;
 };
 
 // stage cap of a discharge launch (no cap: INT_MAX)
@@ -212,6 +216,10 @@ size_t discharge_rows_bytes(int ty, int tz, int nring);
 int rows_slots(int nring);
 hipError_t launch_fuse(const FuseArgs &A, hipStream_t s);
 hipError_t launch_boundary_relabel(const BrlArgs &A, int stage, int first, int count, hipStream_t s);
+hipError_t launch_label_hist(const int *lab, int N, int dinf, unsigned int *hist, int *maxlab,
+                             const unsigned long long *actIn, hipStream_t s);
+hipError_t launch_gap_raise_all(int *lab, int N, const int *gap, int dinf,
+                                const unsigned long long *actIn, hipStream_t s);
 hipError_t launch_gap_find(const GapArgs &A, hipStream_t s);
 hipError_t launch_gap_apply(const GapApplyArgs &A, hipStream_t s);
 hipError_t launch_sum_i32(const int *a, int n, unsigned long long *out, hipStream_t s);

@@ -19,6 +19,7 @@ MF_OK, MF_E_INVAL, MF_E_NOMEM, MF_E_DEVICE, MF_E_STATE, MF_E_OVERFLOW, MF_E_SWEE
 MF_CUT_MIN_SOURCE, MF_CUT_MAX_SOURCE = 0, 1
 MF_SCHED_PARD, MF_SCHED_COLORED, MF_SCHED_LEARNED, MF_SCHED_AUTO = 0, 1, 2, 3
 MF_KERNEL_AUTO, MF_KERNEL_HBM, MF_KERNEL_LDS, MF_KERNEL_WAVE, MF_KERNEL_ROWS = 0, 1, 2, 3, 4
+MF_METHOD_ARD, MF_METHOD_PRD = 0, 1
 TRACE_FIELDS = 10
 FEATURES = 6
 TRACE_NAMES = ("sweep", "region", "rounds", "levels", "stages", "ticks", "excess_in", "to_sink",
@@ -42,7 +43,7 @@ class mf_solve_opts(ctypes.Structure):
                 ("max_defer", ctypes.c_int32), ("defer_threshold", ctypes.c_float),
                 ("defer_mode", ctypes.c_int32), ("features", ctypes.c_void_p),
                 ("features_cap", ctypes.c_int64), ("partial", ctypes.c_int32),
-                ("boundary_relabel", ctypes.c_int32)]
+                ("boundary_relabel", ctypes.c_int32), ("method", ctypes.c_int32)]
 
 
 class mf_solve_stats(ctypes.Structure):
@@ -232,11 +233,13 @@ class Grid:
     def solve(self, schedule=MF_SCHED_PARD, gap=True, global_relabel_every=0, check_every=0,
               max_sweeps=0, stream=None, profile=False, region_kernel=MF_KERNEL_AUTO,
               trace=None, graph=False, model=None, max_defer=0, defer_threshold=0.0,
-              features=None, defer_mode=0, partial=False, boundary_relabel=0):
+              features=None, defer_mode=0, partial=False, boundary_relabel=0,
+              method=MF_METHOD_ARD):
         """trace: optional int32 device tensor of shape (cap, TRACE_FIELDS);
         partial: partial discharges (sweep s runs the stages k <= s only);
         boundary_relabel: n > 0 runs the boundary relabel heuristic after every
-        sweep with at most n levels of its search."""
+        sweep with at most n levels of its search;
+        method: MF_METHOD_ARD or MF_METHOD_PRD (push-relabel region discharge)."""
         tptr, tcap = None, 0
         if trace is not None:
             tptr, tcap = trace.data_ptr(), int(trace.shape[0])
@@ -250,7 +253,7 @@ class Grid:
                           graph=1 if graph else 0, max_defer=max_defer,
                           defer_threshold=defer_threshold, defer_mode=defer_mode, features=fptr,
                           features_cap=fcap, partial=1 if partial else 0,
-                          boundary_relabel=int(boundary_relabel))
+                          boundary_relabel=int(boundary_relabel), method=int(method))
         if model is not None:
             o.model = model._h
         s = mf_solve_stats()
