@@ -242,3 +242,15 @@ def test_heuristic_on_full_size_workloads(mf):
         print(f"{inst.name}: sweeps {out['stats']['sweeps']}", flush=True)
         assert out["flow"] == ref["flow"]
         assert (out["smin"] == ref["smin"]).all() and (out["smax"] == ref["smax"]).all()
+
+
+def test_heuristic_single_region_and_no_boundary(mf):
+    """One region: no boundary vertices, so the heuristic does nothing (0 levels)."""
+    inst = synth.random_grid((20, 18), 8, 2700, tile=(20, 18))
+    ref = oracle.solve_grid(inst)
+    with mf.Grid(inst.dims, inst.conn, inst.tile) as g:
+        g.set_caps(inst.cs, inst.ct, inst.nbr)
+        st = g.solve(boundary_relabel=8)
+        assert st["boundary_size"] == 0 and g.flow_value() == ref["flow"]
+        assert g.boundary_relabel() == 0
+        assert (g.min_cut(mf.MF_CUT_MIN_SOURCE) == ref["smin"]).all()

@@ -122,3 +122,34 @@ def test_prd_rejected_combinations(mf):
         with pytest.raises(mf.MFError) as e:
             g.boundary_relabel()  # a PRD state has no region-distance labels
         assert e.value.status == mf.MF_E_STATE
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_prd_degenerate_inputs(mf, case):
+    """One region (plain push-relabel: one sweep), no n-links, no t-links, no s-links."""
+    dims, conn, tile = [((20, 18), 8, (20, 18)), ((9, 10, 11), 6, (4, 4, 4)),
+                        ((30, 31), 4, (8, 8)), ((15, 16), 8, (4, 4))][case]
+    inst = synth.random_grid(dims, conn, 3800 + case, tile=tile)
+    if case == 1:
+        inst.nbr[:] = 0
+    elif case == 2:
+        inst.ct[:] = 0
+    elif case == 3:
+        inst.cs[:] = 0
+    ref = oracle.solve_grid(inst)
+    out = mf.solve_instance(inst, method=mf.MF_METHOD_PRD, max_sweeps=1000000)
+    assert out["flow"] == ref["flow"]
+    assert (out["smin"] == ref["smin"]).all() and (out["smax"] == ref["smax"]).all()
+    if case == 0:
+        assert out["stats"]["sweeps"] == 1
+
+
+def test_prd_stops_at_max_sweeps(mf):
+    inst = synth.random_grid((40, 36), 8, 3900, tile=(8, 8))
+    with mf.Grid(inst.dims, inst.conn, inst.tile) as g:
+        g.set_caps(inst.cs, inst.ct, inst.nbr)
+        with pytest.raises(mf.MFError) as e:
+            g.solve(method=mf.MF_METHOD_PRD, max_sweeps=2, check_every=1)
+        assert e.value.status == mf.MF_E_SWEEPS
+        st = g.state()  # the state after two sweeps stays readable
+        assert st["labels"].max() <= inst.n
