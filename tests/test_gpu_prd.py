@@ -153,3 +153,13 @@ def test_prd_stops_at_max_sweeps(mf):
         assert e.value.status == mf.MF_E_SWEEPS
         st = g.state()  # the state after two sweeps stays readable
         assert st["labels"].max() <= inst.n
+
+
+def test_prd_full_size_2048_exact(mf):
+    """The 2048^2 workload by push-relabel region discharge: the oracle's flow and cuts."""
+    inst = synth.config(1)
+    out = mf.solve_instance(inst, method=mf.MF_METHOD_PRD, max_sweeps=1000000)
+    ref = oracle.solve_grid(inst)
+    print(f"{inst.name}: PRD sweeps {out['stats']['sweeps']}", flush=True)
+    assert out["flow"] == ref["flow"]
+    assert (out["smin"] == ref["smin"]).all() and (out["smax"] == ref["smax"]).all()
