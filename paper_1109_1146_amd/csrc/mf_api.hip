@@ -272,9 +272,9 @@ static mf_status create_impl(int32_t ndim, const int64_t *dims, int32_t connecti
     }
     g->numCU = prop.multiProcessorCount;
     g->ldsMax = (size_t)prop.sharedMemPerBlock;
-    // regions of 64K vertices and more (64^3) keep their state in HBM and are
-    // bound by memory latency: a 1024-thread workgroup keeps more loads in flight
-    g->threads = G.V >= 65536 ? 1024 : 256;
+    // regions of 8K vertices and more on the HBM kernel are bound by memory
+    // latency: a 1024-thread workgroup keeps more loads in flight
+    g->threads = G.V >= 8192 ? 1024 : 256;
     // the four search arrays (16 B per vertex) live in LDS when they fit beside
     // the kernel's static shared words; otherwise in per-workgroup HBM scratch
     g->useLDS = (size_t)16 * G.V + 1024 <= (size_t)prop.sharedMemPerBlock;

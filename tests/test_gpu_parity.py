@@ -213,14 +213,16 @@ def test_hbm_kernel_64_cubed_regions(mf):
     _check(mf, inst, certify=False, global_relabel_every=4)
 
 
-@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("case", range(6))
 def test_hbm_kernel_large_regions_1024_threads(mf, case):
-    """Regions of 64K vertices and more run the HBM kernel with 1024-thread
-    workgroups: 2D 256x256 and 3D 64^3 tiles, ragged, with partial discharges and
-    the exact relabel."""
+    """Regions of 8K vertices and more run the HBM kernel with 1024-thread
+    workgroups: 2D 128x128 and 256x256, 3D 24^3 and 64^3 tiles, ragged, with
+    partial discharges, the exact relabel and the boundary relabel."""
     cases = [((300, 280), 8, (256, 256), {}), ((270, 513), 4, (256, 256), dict(partial=True)),
              ((70, 66, 130), 6, (64, 64, 64), dict(partial=True, global_relabel_every=4)),
-             ((65, 128, 64), 6, (64, 64, 64), dict(boundary_relabel=16))]
+             ((65, 128, 64), 6, (64, 64, 64), dict(boundary_relabel=16)),
+             ((300, 250), 8, (128, 128), dict(global_relabel_every=6)),
+             ((50, 49, 60), 6, (24, 24, 24), dict(partial=True))]
     dims, conn, tile, kw = cases[case]
     inst = synth.blob_grid(dims, conn, 3100 + case, 6, 6.0, 24.0, zero_frac=0.1, tile=tile)
     out, _ = _check(mf, inst, certify=(case < 2), region_kernel=mf.MF_KERNEL_HBM, **kw)
