@@ -78,6 +78,9 @@ def parse():
                    help="boundary relabel heuristic after every sweep with at most N levels "
                         "(0 = off); default: off for the single grids, the autotuner's choice "
                         "for the batch")
+    p.add_argument("--schedule", choices=("parallel", "colored"), default="parallel",
+                   help="sweep driver: parallel (Alg. 2, all regions at once) or colored (Alg. 1 "
+                        "as phases of non-interacting regions)")
     p.add_argument("--method", choices=("ard", "prd"), default="ard",
                    help="region discharge: ard (augmented paths, Sec. 4) or prd (push-relabel, "
                         "Sec. 3; no exact relabel, partial discharges or boundary relabel, and no "
@@ -280,6 +283,9 @@ def main():
     if args.boundary_relabel is None:
         args.boundary_relabel = 0
     method = mf.MF_METHOD_PRD if args.method == "prd" else mf.MF_METHOD_ARD
+    schedule = mf.MF_SCHED_COLORED if args.schedule == "colored" else mf.MF_SCHED_PARD
+    if args.schedule == "colored":
+        args.boundary_relabel, args.no_learned = 0, True
     if args.method == "prd":
         # the exact relabel and the heuristics are those of region distances
         args.relabel_every, args.partial, args.boundary_relabel, args.no_learned = 0, False, 0, True
@@ -299,7 +305,7 @@ def main():
         st = g.solve(stream=stream.cuda_stream, profile=profile,
                      global_relabel_every=args.relabel_every, partial=args.partial,
                      boundary_relabel=args.boundary_relabel, method=method,
-                     max_sweeps=1 << 40)
+                     schedule=schedule, max_sweeps=1 << 40)
         cut = g.min_cut(mf.MF_CUT_MIN_SOURCE)
         return st, cut
 
@@ -327,11 +333,12 @@ def main():
                    mf.MF_KERNEL_ROWS: ("k_discharge_rows", "mf_discharge_rows.hip"),
                    mf.MF_KERNEL_LDS: ("k_discharge_lds", "mf_discharge_lds.hip"),
                    mf.MF_KERNEL_HBM: ("k_discharge", "mf_kernels.hip")}[stats[-1]["region_kernel"]]
-    # the committed counter summaries cover the ARD solves
-    traffic = (None if args.method == "prd" else
+    # the committed counter summaries cover the parallel ARD solves
+    traffic = (None if args.method == "prd" or args.schedule == "colored" else
                measured_traffic("paper_1109_1146_amd/csrc/" + ksrc, f"{kname}_{wl['tag']}_traffic.json"))
     rec = {
-        "metric": "exact-maxflow solve throughput (plain P-%s), sweeps, %% HBM peak" % args.method.upper(),
+        "metric": "exact-maxflow solve throughput (plain %s-%s), sweeps, %% HBM peak" % (
+            "S" if args.schedule == "colored" else "P", args.method.upper()),
         "value": round(value, 3),
         "unit": "Mvertices/s",
         "n_gpus": 1,
@@ -345,7 +352,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "n": inst.n, "regions": info["regions"],
                    "region_shape": list(info["region_shape"]), "boundary_size": info["boundary_size"],
-                   "schedule": "P-" + args.method.upper() + (", partial discharges" if args.partial else "")
+                   "schedule": ("S-" if args.schedule == "colored" else "P-") + args.method.upper()
+                               + (" (colour phases)" if args.schedule == "colored" else "")
+                               + (", partial discharges" if args.partial else "")
                                + (", boundary relabel" if args.boundary_relabel else ""),
                    "connectivity": inst.conn,
                    "global_relabel_every": args.relabel_every, "partial_discharges": args.partial,

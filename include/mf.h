@@ -63,7 +63,11 @@ enum {
 /* region schedule inside a sweep */
 enum {
     MF_SCHED_PARD = 0,    /* Alg. 2: all active regions against the previous sweep's labels */
-    MF_SCHED_COLORED = 1, /* Alg. 1 as phases of non-interacting regions (reserved) */
+    MF_SCHED_COLORED = 1, /* Alg. 1 as phases of non-interacting regions: one colour class
+                             (2 for 4- and 6-connected grids, 4 for 2D 8-connected) per
+                             phase, its flow and labels applied before the next phase; a
+                             sweep is one phase per colour.  Not with boundary_relabel or
+                             features (MF_E_INVAL) */
     MF_SCHED_LEARNED = 2, /* deferral from a trained scorer (opts->model); the regions to
                              discharge are queued longest previous discharge first; at most
                              65536 regions, else MF_E_INVAL */

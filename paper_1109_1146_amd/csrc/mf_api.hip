@@ -28,6 +28,9 @@ struct mf_grid {
     int *res = nullptr, *rt = nullptr, *ex = nullptr, *lab[2] = {nullptr, nullptr};
     int *pushb = nullptr, *ractive = nullptr, *order = nullptr, *bidx = nullptr;
     int *bstart = nullptr;        // [nreg + 1]: the boundary vertices of region r are bidx[bstart[r]..bstart[r+1])
+    int *corder = nullptr;        // regions grouped by colour (MF_SCHED_COLORED), built on first use
+    int corder_ncol = 0;
+    std::vector<int> cstart;      // colour c holds corder[cstart[c] .. cstart[c+1])
     unsigned int *brlctl = nullptr;  // boundary relabel control words
     int *ringL = nullptr, *rvcount = nullptr, *mark = nullptr, *dirty = nullptr;
     unsigned char *ringM = nullptr, *cutbuf = nullptr, *cand = nullptr;  // cand: 2 x N
@@ -95,7 +98,7 @@ static void free_all(mf_grid *g) {
                     g->bidx, g->ringL, g->rvcount, g->mark, g->dirty, g->ringM, g->ringX, g->cutbuf,
                     g->in_cs, g->in_ct, g->in_nbr, g->scratch, g->act, g->qhead, g->hist,
                     g->maxlab, g->gap, g->err, g->counters, g->stats, g->sums, g->changed,
-                    g->tmp_plane, g->cand, g->bstart, g->brlctl};
+                    g->tmp_plane, g->cand, g->bstart, g->brlctl, g->corder};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (g->reginst) (void)hipFree(g->reginst);
@@ -614,9 +617,13 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     o.gap = 1;
     if (opts) o = *opts;
     if (o.schedule < 0 || o.schedule > MF_SCHED_AUTO) return MF_E_INVAL;
-    if (o.schedule == MF_SCHED_COLORED) return MF_E_INVAL;
     if (o.method != MF_METHOD_ARD && o.method != MF_METHOD_PRD) return MF_E_INVAL;
     const bool prd = o.method == MF_METHOD_PRD;
+    // Alg. 1 as phases of non-interacting regions: one colour class per phase,
+    // each phase's flow applied before the next (the boundary relabel and the
+    // learned schedule are built for Alg. 2)
+    const bool colored = o.schedule == MF_SCHED_COLORED;
+    if (colored && (o.boundary_relabel || (o.features && o.features_cap > 0))) return MF_E_INVAL;
     // push-relabel region discharge: distance labels over every arc; the
     // heuristics and the exact relabel here are those of region distances
     if (prd && (o.schedule == MF_SCHED_LEARNED || o.partial || o.boundary_relabel ||
@@ -645,11 +652,37 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     if (o.boundary_relabel < 0 || o.boundary_relabel > 4096) return MF_E_INVAL;
     const int brl = o.boundary_relabel;
     if (o.global_relabel_every > 0) check_every = o.global_relabel_every;
+    // colour classes: regions that share no arc.  Checkerboard for 4- and
+    // 6-connected grids; 2D 8-connected grids need four (diagonal neighbours)
+    const int ncol = colored ? ((g->ndim == 2 && g->G.K == 8) ? 4 : 2) : 1;
+    if (colored && g->corder_ncol != ncol) {
+        const Geo &Gc = g->G;
+        std::vector<int> ord;
+        std::vector<int> cs(ncol + 1, 0);
+        for (int c = 0; c < ncol; c++) {
+            cs[c] = (int)ord.size();
+            for (int r = 0; r < Gc.nreg; r++) {
+                const int rx = r % Gc.rx, t = r / Gc.rx, ry = t % Gc.ry, rz = t / Gc.ry;
+                const int cr = ncol == 4 ? ((rx & 1) | ((ry & 1) << 1)) : ((rx + ry + rz) & 1);
+                if (cr == c) ord.push_back(r);
+            }
+        }
+        cs[ncol] = (int)ord.size();
+        if (!g->corder && !ok(dalloc(&g->corder, (size_t)Gc.nreg))) return MF_E_NOMEM;
+        if (!ok(hipMemcpy(g->corder, ord.data(), sizeof(int) * ord.size(), hipMemcpyHostToDevice)))
+            return MF_E_DEVICE;
+        g->cstart = cs;
+        g->corder_ncol = ncol;
+    }
+    // a check interval counts sweeps; a sweep of the colour schedule is ncol phases
+    check_every *= ncol;
     // labels: region distances below dinf = |B| (ARD), or distances below dinf = n (PRD)
     const int dinf = prd ? (int)std::max<long long>(g->n, 1) : g->dinf;
     long long B = prd ? (long long)dinf : (g->nB > 0 ? g->nB : 1);
     long long bound = (B > 2000000000LL) ? (1LL << 62) : 2 * B * B + 1;
     long long max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : bound;
+    // the device counts steps: sweeps (Alg. 2) or colour phases (Alg. 1)
+    const long long max_steps = max_sweeps > (1LL << 60) / ncol ? max_sweeps : max_sweeps * ncol;
     hipStream_t s = (hipStream_t)o.stream;
     const bool use_graph = o.graph && !o.profile && !o.trace;
     if (use_graph) {
@@ -689,6 +722,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     D.ractive = g->ractive; D.order = g->order; D.nwork = G.nreg;
     D.dinf = dinf; D.scratch = g->scratch; D.ringL = g->ringL; D.ringM = g->ringM;
     D.prd = prd ? 1 : 0;
+    // partial discharges count sweeps, which are ncol steps in colour phases
+    D.capShift = ncol == 4 ? 2 : (ncol == 2 ? 1 : 0);
     D.nring = g->nring; D.stats = g->stats; D.rvcount = g->rvcount; D.err = g->err;
     D.useLDS = g->useLDS ? 1 : 0;
     D.maxIter = 1 << 18;
@@ -792,7 +827,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     for (;;) {
         if (o.global_relabel_every > 0) {
             const int p = (int)(sweep & 1);
-            int lv = global_relabel(g, g->lab[p], g->act + p, s);
+            int lv = global_relabel(g, g->lab[colored ? 0 : p], g->act + p, s);
             if (lv < 0) return MF_E_DEVICE;
             relabels++;
             relabel_levels += lv;
@@ -801,9 +836,17 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         auto enqueue_batch = [&](long long first) -> bool {
             for (int j = 0; j < check_every; j++) {
                 const int p = (int)((first + j) & 1);
-                D.labOld = g->lab[p]; D.labNew = g->lab[p ^ 1];
+                // one label buffer in colour phases: a phase writes its own
+                // regions and reads the labels of other colours
+                int *labIn = g->lab[colored ? 0 : p], *labOut = g->lab[colored ? 0 : p ^ 1];
+                D.labOld = labIn; D.labNew = labOut;
                 D.actIn = g->act + p; D.qhead = g->qhead + p;
                 D.sweep = (int)(first + j);
+                if (colored) {
+                    const int c = (int)((first + j) % ncol);
+                    D.order = g->corder + g->cstart[c];
+                    D.nwork = g->cstart[c + 1] - g->cstart[c];
+                }
                 if (feats) {
                     // region features at the start of the sweep; the learned
                     // schedule scores them (BF16) and builds the queue
@@ -844,13 +887,13 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                 else e = mfd::launch_discharge(D, g->nslots, g->threads, lds, s);
                 if (!ok(e)) return false;
                 if (o.profile && !ok(hipEventRecord(ev[2 * j + 1], s))) return false;
-                F.lab = g->lab[p ^ 1]; F.actIn = g->act + p;
+                F.lab = labOut; F.actIn = g->act + p;
                 if (!ok(mfd::launch_fuse(F, s))) return false;
-                if (prd && !ok(mfd::launch_label_hist(g->lab[p ^ 1], G.N, dinf, g->hist, g->maxlab,
+                if (prd && !ok(mfd::launch_label_hist(labOut, G.N, dinf, g->hist, g->maxlab,
                                                       g->act + p, s)))
                     return false;
                 if (brl > 0) {
-                    BA.lab = g->lab[p ^ 1]; BA.actIn = g->act + p;
+                    BA.lab = labOut; BA.actIn = g->act + p;
                     if (!ok(mfd::launch_boundary_relabel(BA, 0, 0, 0, s)) ||
                         !ok(mfd::launch_boundary_relabel(BA, 1, 0, brl, s)) ||
                         !ok(mfd::launch_boundary_relabel(BA, 2, 0, 0, s)))
@@ -858,10 +901,15 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                 }
                 P.actIn = g->act + p; P.actOut = g->act + (p ^ 1); P.qheadNext = g->qhead + (p ^ 1);
                 if (!ok(mfd::launch_gap_find(P, s))) return false;
-                if (prd && !ok(mfd::launch_gap_raise_all(g->lab[p ^ 1], G.N, g->gap, dinf, g->act + p, s)))
+                if (prd && !ok(mfd::launch_gap_raise_all(labOut, G.N, g->gap, dinf, g->act + p, s)))
                     return false;
-                Q.lab = g->lab[p ^ 1]; Q.actIn = g->act + p; Q.actOut = g->act + (p ^ 1);
+                Q.lab = labOut; Q.actIn = g->act + p; Q.actOut = g->act + (p ^ 1);
                 if (!ok(mfd::launch_gap_apply(Q, s))) return false;
+                // regions of colours not yet discharged may still hold excess
+                // inside (from Init): count every active vertex, not only B
+                if (colored && !ok(mfd::launch_activity(G, g->ex, labOut, dinf, g->ractive,
+                                                        g->act + (p ^ 1), s)))
+                    return false;
             }
             return true;
         };
@@ -873,7 +921,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                                   (long long)(regionMode << 2) | (long long)(regionNarrow << 4) |
                                   (long long)((g->lab[0] < g->lab[1]) ? 1 : 0) << 6 |
                                   (long long)(o.partial ? 1 : 0) << 7 | (long long)brl << 40 |
-                                  (long long)(prd ? 1 : 0) << 56;
+                                  (long long)(prd ? 1 : 0) << 56 | (long long)(colored ? 1 : 0) << 57;
             if (!g->graph_exec || g->graph_key != key) {
                 if (g->graph_exec) { (void)hipGraphExecDestroy(g->graph_exec); g->graph_exec = nullptr; }
                 hipGraph_t graph = nullptr;
@@ -909,17 +957,18 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         }
         if (*(int *)(g->pinned + 2) & 4) { status = MF_E_DEVICE; break; }
         if (g->pinned[0] == 0ull) break;
-        if ((long long)g->pinned[1] >= max_sweeps) { status = MF_E_SWEEPS; break; }
+        if ((long long)g->pinned[1] >= max_steps) { status = MF_E_SWEEPS; break; }
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
     if (status == MF_E_SWEEPS) {
         // the state after the sweeps run so far stays readable
-        g->final_parity = (int)(g->pinned[1] & 1ull);
+        g->final_parity = colored ? 0 : (int)(g->pinned[1] & 1ull);
         g->has_state = true;
     }
     if (status != MF_OK) return status;
-    long long sweeps = (long long)g->pinned[1];
-    g->final_parity = (int)(sweeps & 1);
+    const long long steps = (long long)g->pinned[1];
+    g->final_parity = colored ? 0 : (int)(steps & 1);
+    const long long sweeps = (steps + ncol - 1) / ncol;
     // flow value |f| = sum (c_t - c_f(., t))
     HIP_TRY(hipMemsetAsync(g->sums + 2, 0, sizeof(u64), s));
     HIP_TRY(mfd::launch_sum_i32(g->rt, G.N, g->sums + 2, s));

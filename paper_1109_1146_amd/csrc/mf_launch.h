@@ -39,6 +39,7 @@ struct DischargeArgs {
     // the sweep's gap kernel moves into the next sweep's active count.
     int partial;
     const unsigned long long *sweepCount;
+    int capShift;        // log2 of the steps per sweep (colour phases of Alg. 1: 2 or 4 steps)
     unsigned long long *actCarry;  // null unless partial
     // Push-relabel region discharge (Sec. 3, Proc. PRD; HBM kernel only): labels
     // are the distance labels of Sec. 2 (d(t) = 0, every arc of length 1, dinf =
@@ -49,7 +50,7 @@ struct DischargeArgs {
 // stage cap of a discharge launch (no cap: INT_MAX)
 __device__ __forceinline__ int stage_cap(const DischargeArgs &A) {
     if (!A.partial) return 0x7fffffff;
-    const unsigned long long s = *A.sweepCount;
+    const unsigned long long s = *A.sweepCount >> A.capShift;
     return s < 0x7fffffffull ? (int)s : 0x7fffffff;
 }
 
