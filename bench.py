@@ -400,6 +400,30 @@ def main():
                           "plain_region_discharges": rec["region_discharges"]}
     except (OSError, ValueError) as e:  # no trained model in the tree
         rec["learned"] = {"error": str(e)}
+    # the learned schedule driving the colour phases of Alg. 1 (phase order by
+    # the network, no deferral), and the same phases in fixed order (ablation)
+    if not args.no_learned:
+        try:
+            from paper_1109_1146_amd import learned
+            model = learned.load_model()
+            variants = (("learned_colored", dict(schedule=mf.MF_SCHED_LEARNED_COLORED, model=model,
+                                                 defer_threshold=1e-9, max_defer=1)),
+                        ("colored_fixed_order", dict(schedule=mf.MF_SCHED_COLORED)))
+            for key, kw in variants:
+                kw.update(global_relabel_every=args.relabel_every, stream=stream.cuda_stream,
+                          partial=args.partial)
+                g.solve(**kw)
+                times = []
+                for _ in range(max(1, min(args.steps, 3))):
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    vst = g.solve(**kw)
+                    times.append((time.perf_counter() - t1) * 1e3)
+                rec[key] = {"solve_ms": round(float(np.median(times)), 3), "sweeps": vst["sweeps"],
+                            "region_discharges": vst["region_discharges"],
+                            "flow_equal": g.flow_value() == flow}
+        except (OSError, ValueError, mf.MFError) as e:
+            rec["learned_colored"] = {"error": str(e)}
     if not args.no_cpu_baseline and "crop" in wl:
         # too large for the oracle within the bench: time it on a corner block
         sample = crop_instance(inst, wl["crop"])

@@ -71,7 +71,12 @@ enum {
     MF_SCHED_LEARNED = 2, /* deferral from a trained scorer (opts->model); the regions to
                              discharge are queued longest previous discharge first; at most
                              65536 regions, else MF_E_INVAL */
-    MF_SCHED_AUTO = 3     /* library's choice (currently MF_SCHED_PARD) */
+    MF_SCHED_AUTO = 3,    /* library's choice (currently MF_SCHED_PARD) */
+    MF_SCHED_LEARNED_COLORED = 4 /* the learned scheduler driving the colour phases of
+                             MF_SCHED_COLORED: at the start of each sweep the network scores
+                             the regions, the phases run in descending order of the predicted
+                             progress summed over each colour's active regions, and the
+                             deferral rule of MF_SCHED_LEARNED applies inside a phase */
 };
 
 typedef struct {

@@ -31,6 +31,7 @@ struct mf_grid {
     int *corder = nullptr;        // regions grouped by colour (MF_SCHED_COLORED), built on first use
     int corder_ncol = 0;
     std::vector<int> cstart;      // colour c holds corder[cstart[c] .. cstart[c+1])
+    std::vector<int> corder_host;
     unsigned int *brlctl = nullptr;  // boundary relabel control words
     int *ringL = nullptr, *rvcount = nullptr, *mark = nullptr, *dirty = nullptr;
     unsigned char *ringM = nullptr, *cutbuf = nullptr, *cand = nullptr;  // cand: 2 x N
@@ -616,21 +617,21 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     memset(&o, 0, sizeof(o));
     o.gap = 1;
     if (opts) o = *opts;
-    if (o.schedule < 0 || o.schedule > MF_SCHED_AUTO) return MF_E_INVAL;
+    if (o.schedule < 0 || o.schedule > MF_SCHED_LEARNED_COLORED) return MF_E_INVAL;
     if (o.method != MF_METHOD_ARD && o.method != MF_METHOD_PRD) return MF_E_INVAL;
     const bool prd = o.method == MF_METHOD_PRD;
+    const bool learned = o.schedule == MF_SCHED_LEARNED || o.schedule == MF_SCHED_LEARNED_COLORED;
     // Alg. 1 as phases of non-interacting regions: one colour class per phase,
-    // each phase's flow applied before the next (the boundary relabel and the
-    // learned schedule are built for Alg. 2)
-    const bool colored = o.schedule == MF_SCHED_COLORED;
+    // each phase's flow applied before the next (the boundary relabel is built
+    // for Alg. 2)
+    const bool colored = o.schedule == MF_SCHED_COLORED || o.schedule == MF_SCHED_LEARNED_COLORED;
     if (colored && (o.boundary_relabel || (o.features && o.features_cap > 0))) return MF_E_INVAL;
     // push-relabel region discharge: distance labels over every arc; the
     // heuristics and the exact relabel here are those of region distances
-    if (prd && (o.schedule == MF_SCHED_LEARNED || o.partial || o.boundary_relabel ||
+    if (prd && (learned || o.partial || o.boundary_relabel ||
                 o.global_relabel_every || (o.features && o.features_cap > 0) ||
                 (o.region_kernel != MF_KERNEL_AUTO && o.region_kernel != MF_KERNEL_HBM)))
         return MF_E_INVAL;
-    const bool learned = o.schedule == MF_SCHED_LEARNED;
     mf_model *model = (mf_model *)o.model;
     // the scheduler's queue kernel keeps one class byte per region in LDS
     if (learned && (!model || g->G.nreg > 65536)) return MF_E_INVAL;
@@ -672,6 +673,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         if (!ok(hipMemcpy(g->corder, ord.data(), sizeof(int) * ord.size(), hipMemcpyHostToDevice)))
             return MF_E_DEVICE;
         g->cstart = cs;
+        g->corder_host = ord;
         g->corder_ncol = ncol;
     }
     // a check interval counts sweeps; a sweep of the colour schedule is ncol phases
@@ -833,8 +835,17 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
             relabel_levels += lv;
         }
         // one batch of check_every sweeps; sweep parity selects the buffers
+        // colour phase order of the current sweep (colour mode): fixed, or by
+        // the learned scores when the learned schedule drives the phases
+        const std::vector<int> &corderHost = g->corder_host;
+        std::vector<int> cperm(ncol);
+        for (int c = 0; c < ncol; c++) cperm[c] = c;
         auto enqueue_batch = [&](long long first) -> bool {
             for (int j = 0; j < check_every; j++) {
+                const int phase = (int)((first + j) % ncol);
+                // features and scores once per sweep: every step of Alg. 2, the
+                // first phase of a sweep in colour mode
+                const bool sweepStart = phase == 0;
                 const int p = (int)((first + j) & 1);
                 // one label buffer in colour phases: a phase writes its own
                 // regions and reads the labels of other colours
@@ -842,19 +853,15 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                 D.labOld = labIn; D.labNew = labOut;
                 D.actIn = g->act + p; D.qhead = g->qhead + p;
                 D.sweep = (int)(first + j);
-                if (colored) {
-                    const int c = (int)((first + j) % ncol);
-                    D.order = g->corder + g->cstart[c];
-                    D.nwork = g->cstart[c + 1] - g->cstart[c];
-                }
-                if (feats) {
+                if (feats && sweepStart) {
                     // region features at the start of the sweep; the learned
                     // schedule scores them (BF16) and builds the queue
                     mfd::FeatArgs FA;
                     FA.G = G; FA.ex = g->ex; FA.lab = g->lab[p]; FA.res = g->res;
                     FA.ringL = g->ringL; FA.ringM = g->ringM; FA.nring = g->nring; FA.dinf = g->dinf;
-                    // with partial discharges excess can stay inside a region
-                    FA.ringOnly = (first + j > 0 && !o.partial) ? 1 : 0;
+                    // with partial discharges excess can stay inside a region, and
+                    // so it can during the first sweep of colour phases
+                    FA.ringOnly = (first + j >= ncol && !o.partial) ? 1 : 0;
                     FA.ringX = g->ringX;
                     FA.out = (o.features && first + j < o.features_cap)
                                  ? o.features + (size_t)(first + j) * G.nreg * mfd::kFeat
@@ -868,16 +875,42 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                         // no deferral in the first sweep: every initially active
                         // region is discharged once, so afterwards only boundary
                         // vertices can be active and the active count sees them all
-                        SA.threshold = (first + j == 0) ? -1.f : (o.defer_threshold > 0.f ? o.defer_threshold : 0.5f);
+                        SA.threshold = (first + j < ncol) ? -1.f : (o.defer_threshold > 0.f ? o.defer_threshold : 0.5f);
                         SA.maxDefer = o.max_defer > 0 ? o.max_defer : 2;
                         SA.defer = g->defer; SA.deferCount = g->deferCount; SA.order = g->lorder;
                         SA.regionTicks = g->rticks;
                         D.regionTicks = g->rticks;
                         D.deferRelabel = o.defer_mode == 1 ? 1 : 0;
                         if (!ok(mfd::launch_sched_queue(SA, s))) return false;
-                        D.order = g->lorder;
                         D.defer = g->defer;
+                        if (!colored) {
+                            D.order = g->lorder;
+                        } else {
+                            // Alg. 1 lets the order matter: the colours run in
+                            // descending predicted progress of their active regions
+                            std::vector<float> sc(G.nreg);
+                            std::vector<int> act(G.nreg);
+                            if (!ok(hipMemcpyAsync(sc.data(), g->score, sizeof(float) * G.nreg,
+                                                   hipMemcpyDeviceToHost, s)) ||
+                                !ok(hipMemcpyAsync(act.data(), g->ractive, sizeof(int) * G.nreg,
+                                                   hipMemcpyDeviceToHost, s)) ||
+                                !ok(hipStreamSynchronize(s)))
+                                return false;
+                            std::vector<double> prog(ncol, 0.0);
+                            for (int c = 0; c < ncol; c++)
+                                for (int i = g->cstart[c]; i < g->cstart[c + 1]; i++) {
+                                    int r = corderHost[i];
+                                    if (act[r]) prog[c] += 1.0 / (1.0 + std::exp(-(double)sc[r]));
+                                }
+                            std::stable_sort(cperm.begin(), cperm.end(),
+                                             [&](int a, int b) { return prog[a] > prog[b]; });
+                        }
                     }
+                }
+                if (colored) {
+                    const int c = cperm[phase];
+                    D.order = g->corder + g->cstart[c];
+                    D.nwork = g->cstart[c + 1] - g->cstart[c];
                 }
                 if (o.profile && !ok(hipEventRecord(ev[2 * j], s))) return false;
                 hipError_t e;

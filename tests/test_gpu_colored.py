@@ -150,3 +150,23 @@ def test_colored_partial_full_size_256_exact(mf):
     print(f"{inst.name}: colour-phase sweeps {out['stats']['sweeps']}", flush=True)
     assert out["flow"] == ref["flow"]
     assert (out["smin"] == ref["smin"]).all() and (out["smax"] == ref["smax"]).all()
+
+
+@pytest.mark.parametrize("defer_mode", [0, 1])
+@pytest.mark.parametrize("seed", range(4))
+def test_colored_learned_exact(mf, seed, defer_mode):
+    """The learned schedule driving the colour phases (phase order by predicted
+    progress, deferrals inside a phase), with an untrained network: arbitrary
+    scores, same exact result."""
+    cases = [((40, 36), 8, (8, 8)), ((9, 10, 11), 6, (4, 4, 4)), ((8, 40, 70), 6, (4, 16, 32)),
+             ((100, 90), 4, (32, 32))]
+    dims, conn, tile = cases[seed]
+    inst = synth.random_grid(dims, conn, 4600 + seed, tile=tile)
+    ref = oracle.solve_grid(inst)
+    model = mf.Model(16, seed=seed)
+    for partial in (False, True):
+        out = mf.solve_instance(inst, schedule=mf.MF_SCHED_LEARNED_COLORED, model=model,
+                                defer_threshold=0.6, max_defer=2, defer_mode=defer_mode,
+                                partial=partial, max_sweeps=100000)
+        assert out["flow"] == ref["flow"]
+        assert (out["smin"] == ref["smin"]).all() and (out["smax"] == ref["smax"]).all()
