@@ -852,7 +852,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                 int *labIn = g->lab[colored ? 0 : p], *labOut = g->lab[colored ? 0 : p ^ 1];
                 D.labOld = labIn; D.labNew = labOut;
                 D.actIn = g->act + p; D.qhead = g->qhead + p;
-                D.sweep = (int)(first + j);
+                D.sweep = (int)((first + j) / ncol);  // trace records: the sweep, also in colour phases
                 if (feats && sweepStart) {
                     // region features at the start of the sweep; the learned
                     // schedule scores them (BF16) and builds the queue

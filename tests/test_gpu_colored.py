@@ -170,3 +170,18 @@ def test_colored_learned_exact(mf, seed, defer_mode):
                                 partial=partial, max_sweeps=100000)
         assert out["flow"] == ref["flow"]
         assert (out["smin"] == ref["smin"]).all() and (out["smax"] == ref["smax"]).all()
+
+
+def test_colored_trace_records_sweeps(mf):
+    """Per-discharge trace records carry the sweep (one phase per colour), and
+    every region is discharged at most once per sweep."""
+    import torch
+    inst = synth.random_grid((48, 40), 8, 4700, tile=(8, 8))
+    with mf.Grid(inst.dims, inst.conn, inst.tile) as g:
+        g.set_caps(inst.cs, inst.ct, inst.nbr)
+        tr = torch.zeros((100000, mf.TRACE_FIELDS), dtype=torch.int32, device="cuda")
+        st = g.solve(schedule=mf.MF_SCHED_COLORED, trace=tr, max_sweeps=100000)
+        rec = tr[:min(st["trace_records"], tr.shape[0])].cpu().numpy()
+        assert rec[:, 0].max() == st["sweeps"] - 1
+        pairs = rec[:, 0].astype(np.int64) * 1000003 + rec[:, 1]
+        assert len(np.unique(pairs)) == len(pairs)
