@@ -1168,7 +1168,11 @@ hipError_t launch_gather_plane(const Geo &G, const int *src, int *dst, int n, hi
 }
 
 hipError_t launch_flood(const FloodArgs &A, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_flood<256>, dim3(blocks), dim3(256), 0, s, A);
+    // regions of 8K vertices and more: bound by memory latency, more loads in flight
+    if (A.G.V >= 8192)
+        hipLaunchKernelGGL(k_flood<1024>, dim3(blocks), dim3(1024), 0, s, A);
+    else
+        hipLaunchKernelGGL(k_flood<256>, dim3(blocks), dim3(256), 0, s, A);
     return hipGetLastError();
 }
 
@@ -1278,7 +1282,11 @@ __global__ void k_activity(Geo G, const int *ex, const int *lab, int dinf, int *
 }
 
 hipError_t launch_grelabel(const GRelabelArgs &A, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_grelabel<256>, dim3(blocks), dim3(256), 0, s, A);
+    // regions of 8K vertices and more: bound by memory latency, more loads in flight
+    if (A.G.V >= 8192)
+        hipLaunchKernelGGL(k_grelabel<1024>, dim3(blocks), dim3(1024), 0, s, A);
+    else
+        hipLaunchKernelGGL(k_grelabel<256>, dim3(blocks), dim3(256), 0, s, A);
     return hipGetLastError();
 }
 
