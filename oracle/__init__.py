@@ -20,6 +20,8 @@ What it computes (all integer, int64 accumulators):
   first-in first-out Push/Relabel on each region network) under Alg. 2
   (P-PRD) or Alg. 1 (S-PRD), with the global gap over all labels and per-sweep
   checks of label validity and monotonicity.
+* ``region_reduction`` -- Alg. 5 (Sec. 8) on every region of a grid instance:
+  strong and weak source and sink nodes from three augmentations per region.
 * ``boundary_relabel`` -- the heuristic of Sec. 6.1 on a given state, written
   separately in Python (groups, the two kinds of arcs, Dijkstra by heapq).
 * ``brute_force`` -- every cut of a network of at most ~20 vertices.
@@ -352,6 +354,80 @@ def boundary_relabel(n, pu, pv, r_uv, r_vu, region, labels, dinf, distances=Fals
     if distances:
         return out.astype(np.int32), dprime
     return out.astype(np.int32)
+
+
+REDUCE_STRONG_SOURCE, REDUCE_STRONG_SINK, REDUCE_WEAK_SOURCE, REDUCE_WEAK_SINK = 1, 2, 4, 8
+
+
+def region_reduction(inst, tile, big=1 << 28):
+    """Region reduction (Alg. 5, Sec. 8) of every region of a grid instance, as a
+    preprocessing of the initial network.  Returns one byte per vertex with the
+    bits REDUCE_* of its class.
+
+    The network of region R holds R, its boundary B^R (the vertices outside R
+    with a pair to R, without their s- and t-links) and the pairs that touch R,
+    in both directions.  Each Augment is a maximum flow of that network by the
+    textbook push-relabel:
+      1. Augment(s, t): the excess of R to the t-links of R;
+      2. B^S = boundary vertices reached from s, B^T = boundary vertices that
+         reach t (disjoint: s no longer reaches t);
+      3. Augment(s, B^S): B^S joined to t with capacity big;
+      4. Augment(B^T, t): B^T supplied from s with capacity big (the excess of
+         R left aside meanwhile);
+    then in the final residual network, for v in R: s -> v strong source,
+    v -> t strong sink, otherwise v -/-> B^R weak source and B^R -/-> v weak
+    sink.  The first three classes are pinned against the global extremal cuts;
+    the weak sink class is not: under this reading of the region network some
+    vertices it marks are strong source nodes of the whole network (the local
+    Augment(s, B^S) drains excess that a global maximum flow keeps), so it is
+    computed as the algorithm states and not relied on (parity unpinned)."""
+    pu, pv, cuv, cvu = grid_pairs(inst.dims, inst.nbr, _offsets(inst))
+    region = grid_regions(inst.dims, tile)
+    cls = np.zeros(inst.n, np.uint8)
+    cs_all = np.asarray(inst.cs, np.int64)
+    ct_all = np.asarray(inst.ct, np.int64)
+    for rk in np.unique(region):
+        inR = region == rk
+        touch = inR[pu] | inR[pv]
+        a, b = pu[touch], pv[touch]
+        verts = np.unique(np.concatenate([np.flatnonzero(inR), a, b]))
+        idx = -np.ones(inst.n, np.int64)
+        idx[verts] = np.arange(len(verts))
+        la, lb = idx[a], idx[b]
+        rin = inR[verts]
+        bnd = ~rin
+        nl = len(verts)
+        # 1. Augment(s, t) inside the region network
+        cs1 = np.where(rin, cs_all[verts], 0)
+        ct1 = np.where(rin, ct_all[verts], 0)
+        s1 = solve_pairs(nl, la, lb, cuv[touch], cvu[touch], cs1, ct1)
+        smin1, smax1 = cuts_of_state(nl, la, lb, s1["r_uv"], s1["r_vu"], s1["rt"], s1["ex"])
+        BS = bnd & (smin1 == 1)
+        BT = bnd & (smax1 == 0)
+        assert not (BS & BT).any(), "B^S and B^T intersect"
+        # 3. Augment(s, B^S): the remaining excess to B^S (and to t, unreachable now)
+        ct3 = np.where(rin, s1["rt"], np.where(BS, big, 0))
+        s3 = solve_pairs(nl, la, lb, s1["r_uv"], s1["r_vu"], s1["ex"], ct3)
+        ex_left = np.where(rin, s3["ex"], 0)
+        rt3 = np.where(rin, s3["rt"], 0)
+        # 4. Augment(B^T, t): B^T supplied without bound, the excess of R set aside
+        cs4 = np.where(BT, big, 0)
+        s4 = solve_pairs(nl, la, lb, s3["r_uv"], s3["r_vu"], cs4, rt3)
+        r_uv, r_vu, rt4 = s4["r_uv"], s4["r_vu"], np.where(rin, s4["rt"], 0)
+        # classification in the final residual network
+        from_s, not_to_t = cuts_of_state(nl, la, lb, r_uv, r_vu, rt4, ex_left)
+        from_b, _ = cuts_of_state(nl, la, lb, r_uv, r_vu, np.zeros(nl, np.int64), bnd.astype(np.int64))
+        _, not_to_b = cuts_of_state(nl, la, lb, r_uv, r_vu, bnd.astype(np.int64), np.zeros(nl, np.int64))
+        c = np.zeros(nl, np.uint8)
+        strong_src = from_s == 1
+        strong_snk = not_to_t == 0
+        other = ~strong_src & ~strong_snk
+        c[strong_src] |= REDUCE_STRONG_SOURCE
+        c[strong_snk] |= REDUCE_STRONG_SINK
+        c[other & (not_to_b == 1)] |= REDUCE_WEAK_SOURCE
+        c[other & (from_b == 0)] |= REDUCE_WEAK_SINK
+        cls[verts[rin]] = c[rin]
+    return cls
 
 
 # ---------------------------------------------------------------------------

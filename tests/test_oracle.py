@@ -473,3 +473,46 @@ def test_ard_sweeps_below_prd_sweeps():
         prd += oracle.prd_grid(inst)["sweeps"]
     print(f"P-ARD {ard} sweeps, P-PRD {prd} sweeps", flush=True)
     assert ard < prd
+
+
+# ---------------------------------------------------------------------------
+# Region reduction (Alg. 5, Sec. 8)
+# ---------------------------------------------------------------------------
+
+RR_CASES = [((30, 30), 8, (10, 10)), ((8, 9, 10), 6, (4, 3, 5)), ((24, 26), 4, (8, 13)),
+            ((64, 64), 4, (32, 32))]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_region_reduction_classes_against_global_cuts(seed):
+    """Strong source nodes lie in every optimal source side (the minimal one),
+    strong sink nodes in none (outside the maximal one), weak source nodes in
+    some (inside the maximal one): the definitions of Sec. 8 checked against the
+    textbook extremal cuts.  B^S and B^T are disjoint (asserted inside)."""
+    dims, conn, tile = RR_CASES[seed % len(RR_CASES)]
+    inst = (synth.blob_grid(dims, conn, 2100 + seed, 4, 3.0, 9.0, zero_frac=0.1) if seed % 2
+            else synth.random_grid(dims, conn, 2100 + seed))
+    cls = oracle.region_reduction(inst, tile)
+    ref = oracle.solve_grid(inst)
+    smin, smax = ref["smin"] == 1, ref["smax"] == 1
+    strong_src = (cls & oracle.REDUCE_STRONG_SOURCE) > 0
+    strong_snk = (cls & oracle.REDUCE_STRONG_SINK) > 0
+    weak_src = (cls & oracle.REDUCE_WEAK_SOURCE) > 0
+    assert not (strong_src & strong_snk).any()
+    assert (~strong_src | smin).all()
+    assert (~strong_snk | ~smax).all()
+    assert (~weak_src | smax).all()
+
+
+def test_region_reduction_single_region_decides_everything():
+    """One region has no boundary: Augment(s, t) is the whole maximum flow, so
+    every vertex is a strong source node or, failing that, a weak source node
+    (it reaches no boundary), or a strong sink node, exactly as the global cuts
+    say."""
+    inst = synth.random_grid((14, 15), 8, 2200)
+    cls = oracle.region_reduction(inst, (14, 15))
+    ref = oracle.solve_grid(inst)
+    assert ((cls & oracle.REDUCE_STRONG_SOURCE) > 0).tolist() == (ref["smin"] == 1).tolist()
+    assert ((cls & oracle.REDUCE_STRONG_SINK) > 0).tolist() == (ref["smax"] == 0).tolist()
+    decided = (cls & (oracle.REDUCE_STRONG_SINK | oracle.REDUCE_WEAK_SOURCE)) > 0
+    assert decided.all() or ((cls & oracle.REDUCE_STRONG_SOURCE) > 0)[~decided].all()
