@@ -483,36 +483,144 @@ RR_CASES = [((30, 30), 8, (10, 10)), ((8, 9, 10), 6, (4, 3, 5)), ((24, 26), 4, (
             ((64, 64), 4, (32, 32))]
 
 
+def _region_networks(inst, tile):
+    """Yield, per region, the region network of Sec. 8: R, its boundary B^R and
+    every pair touching R, as (global ids, in-R mask, pair arrays, s- and t-links
+    of R)."""
+    pu, pv, cuv, cvu = oracle.grid_pairs(inst.dims, inst.nbr,
+                                         synth.offsets_for(len(inst.dims), inst.conn))
+    region = oracle.grid_regions(inst.dims, tile)
+    for rk in np.unique(region):
+        inR = region == rk
+        touch = inR[pu] | inR[pv]
+        verts = np.unique(np.concatenate([np.flatnonzero(inR), pu[touch], pv[touch]]))
+        idx = -np.ones(inst.n, np.int64)
+        idx[verts] = np.arange(len(verts))
+        rin = inR[verts]
+        cs = np.where(rin, inst.cs[verts], 0)
+        ct = np.where(rin, inst.ct[verts], 0)
+        yield verts, rin, idx[pu[touch]], idx[pv[touch]], cuv[touch], cvu[touch], cs, ct
+
+
+def _two_auxiliary_problems(inst, tile, solve, big=1 << 20):
+    """The classes of Sec. 8 from the two auxiliary problems the section starts
+    from: every boundary vertex joined to t without bound (N_t), or supplied
+    from s without bound (N_s), each solved on its own by ``solve`` (returning
+    the extremal cuts).  Strong source = minimal source side of N_t; strong sink
+    = outside the maximal source side of N_s; weak source = in the maximal but
+    not the minimal source side of N_t (it reaches neither t nor B^R in a
+    maximum flow of N_t); weak sink = the same for N_s (neither s nor B^R
+    reaches it).  Alg. 5 finds one flow whose residual network gives these four
+    sets (its steps 1+3 are a maximum flow of N_t, its steps 1+4 one of N_s)."""
+    cls = np.zeros(inst.n, np.uint8)
+    for verts, rin, la, lb, cuv, cvu, cs, ct in _region_networks(inst, tile):
+        bnd = ~rin
+        nt = solve(len(verts), la, lb, cuv, cvu, cs, np.where(bnd, big, ct))
+        ns = solve(len(verts), la, lb, cuv, cvu, np.where(bnd, big, cs), ct)
+        c = np.zeros(len(verts), np.uint8)
+        c[nt["smin"] == 1] |= oracle.REDUCE_STRONG_SOURCE
+        c[ns["smax"] == 0] |= oracle.REDUCE_STRONG_SINK
+        c[(nt["smax"] == 1) & (nt["smin"] == 0)] |= oracle.REDUCE_WEAK_SOURCE
+        c[(ns["smax"] == 1) & (ns["smin"] == 0)] |= oracle.REDUCE_WEAK_SINK
+        cls[verts[rin]] = c[rin]
+    return cls
+
+
+def _semantics_hold(cls, smin, smax):
+    """The definitions of Sec. 8 against the extremal optimal cuts of the whole
+    network: a strong source node is in every optimal source side (so in the
+    minimal one), a strong sink node in none (not in the maximal one), a weak
+    source node in some (the maximal one), a weak sink node outside some (not in
+    the minimal one)."""
+    ss = (cls & oracle.REDUCE_STRONG_SOURCE) > 0
+    st = (cls & oracle.REDUCE_STRONG_SINK) > 0
+    ws = (cls & oracle.REDUCE_WEAK_SOURCE) > 0
+    wk = (cls & oracle.REDUCE_WEAK_SINK) > 0
+    return bool((~ss | smin).all() and (~st | ~smax).all() and (~ws | smax).all()
+                and (~wk | ~smin).all() and not (ss & st).any()
+                and not ((ss | st) & (ws | wk)).any())
+
+
+RR_TINY = [((4, 4), 4, (2, 2)), ((4, 4), 8, (2, 2)), ((4, 4), 4, (4, 2)), ((2, 2, 4), 6, (2, 2, 2)),
+           ((3, 5), 8, (3, 2))]
+
+
+def _brute(n, pu, pv, cuv, cvu, cs, ct):
+    return oracle.brute_force(n, pu, pv, cuv, cvu, cs, ct)
+
+
+@pytest.mark.parametrize("seed", range(100))
+def test_region_reduction_tiny_against_brute_force(seed):
+    """Networks of at most 16 vertices: the four classes of Alg. 5 equal the
+    auxiliary problems solved by enumerating every cut of each region network,
+    and agree with every optimal cut of the whole network (enumerated too)."""
+    dims, conn, tile = RR_TINY[seed % len(RR_TINY)]
+    inst = synth.random_grid(dims, conn, 2300 + seed)
+    cls = oracle.region_reduction(inst, tile)
+    assert (cls == _two_auxiliary_problems(inst, tile, _brute)).all()
+    pu, pv, cuv, cvu = oracle.grid_pairs(inst.dims, inst.nbr,
+                                         synth.offsets_for(len(inst.dims), inst.conn))
+    bf = oracle.brute_force(inst.n, pu, pv, cuv, cvu, inst.cs, inst.ct)
+    assert _semantics_hold(cls, bf["smin"] == 1, bf["smax"] == 1)
+
+
+RR_FUZZ = [((4, 4), 4, (2, 2)), ((6, 5), 8, (3, 2)), ((8, 8), 4, (4, 3)), ((5, 6, 4), 6, (2, 3, 2)),
+           ((12, 10), 8, (5, 4))]
+
+
+def test_region_reduction_fuzz_against_auxiliary_problems():
+    """600 random tilings: Alg. 5 (Dinic augmentations) gives exactly the
+    classes of the two auxiliary problems solved by push-relabel, and they obey
+    the definitions against the whole network's extremal cuts."""
+    for seed in range(600):
+        dims, conn, tile = RR_FUZZ[seed % len(RR_FUZZ)]
+        inst = synth.random_grid(dims, conn, 5000 + seed)
+        cls = oracle.region_reduction(inst, tile)
+        aux = _two_auxiliary_problems(inst, tile, oracle.solve_pairs)
+        assert (cls == aux).all(), seed
+        ref = oracle.solve_grid(inst)
+        assert _semantics_hold(cls, ref["smin"] == 1, ref["smax"] == 1), seed
+
+
+def test_region_reduction_preflow_augment_is_caught():
+    """Planted mistake: Augment as a maximum preflow (excess parked inside R and
+    then ignored) is not a flow; the pins above reject it."""
+    caught = 0
+    for seed in range(60):
+        dims, conn, tile = RR_FUZZ[seed % len(RR_FUZZ)]
+        inst = synth.random_grid(dims, conn, 5000 + seed)
+        wrong = oracle.region_reduction(inst, tile, augment="pr")
+        ref = oracle.solve_grid(inst)
+        if (not (wrong == _two_auxiliary_problems(inst, tile, oracle.solve_pairs)).all()
+                or not _semantics_hold(wrong, ref["smin"] == 1, ref["smax"] == 1)):
+            caught += 1
+    assert caught >= 30
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_region_reduction_classes_against_global_cuts(seed):
-    """Strong source nodes lie in every optimal source side (the minimal one),
-    strong sink nodes in none (outside the maximal one), weak source nodes in
-    some (inside the maximal one): the definitions of Sec. 8 checked against the
-    textbook extremal cuts.  B^S and B^T are disjoint (asserted inside)."""
+    """All four classes obey the definitions of Sec. 8 against the textbook
+    extremal cuts and equal the two auxiliary problems, on blob grids and random
+    grids in 2D and 3D.  B^S and B^T are disjoint (asserted inside)."""
     dims, conn, tile = RR_CASES[seed % len(RR_CASES)]
     inst = (synth.blob_grid(dims, conn, 2100 + seed, 4, 3.0, 9.0, zero_frac=0.1) if seed % 2
             else synth.random_grid(dims, conn, 2100 + seed))
     cls = oracle.region_reduction(inst, tile)
     ref = oracle.solve_grid(inst)
-    smin, smax = ref["smin"] == 1, ref["smax"] == 1
-    strong_src = (cls & oracle.REDUCE_STRONG_SOURCE) > 0
-    strong_snk = (cls & oracle.REDUCE_STRONG_SINK) > 0
-    weak_src = (cls & oracle.REDUCE_WEAK_SOURCE) > 0
-    assert not (strong_src & strong_snk).any()
-    assert (~strong_src | smin).all()
-    assert (~strong_snk | ~smax).all()
-    assert (~weak_src | smax).all()
+    assert _semantics_hold(cls, ref["smin"] == 1, ref["smax"] == 1)
+    assert (cls == _two_auxiliary_problems(inst, tile, oracle.solve_pairs)).all()
 
 
 def test_region_reduction_single_region_decides_everything():
     """One region has no boundary: Augment(s, t) is the whole maximum flow, so
-    every vertex is a strong source node or, failing that, a weak source node
-    (it reaches no boundary), or a strong sink node, exactly as the global cuts
-    say."""
+    the strong source nodes are the minimal source side, the strong sink nodes
+    the complement of the maximal one, and every other vertex reaches no
+    boundary and is reached from none: weak source and weak sink at once."""
     inst = synth.random_grid((14, 15), 8, 2200)
     cls = oracle.region_reduction(inst, (14, 15))
     ref = oracle.solve_grid(inst)
-    assert ((cls & oracle.REDUCE_STRONG_SOURCE) > 0).tolist() == (ref["smin"] == 1).tolist()
-    assert ((cls & oracle.REDUCE_STRONG_SINK) > 0).tolist() == (ref["smax"] == 0).tolist()
-    decided = (cls & (oracle.REDUCE_STRONG_SINK | oracle.REDUCE_WEAK_SOURCE)) > 0
-    assert decided.all() or ((cls & oracle.REDUCE_STRONG_SOURCE) > 0)[~decided].all()
+    smin, smax = ref["smin"] == 1, ref["smax"] == 1
+    both = oracle.REDUCE_WEAK_SOURCE | oracle.REDUCE_WEAK_SINK
+    want = np.where(smin, oracle.REDUCE_STRONG_SOURCE,
+                    np.where(~smax, oracle.REDUCE_STRONG_SINK, both)).astype(np.uint8)
+    assert (cls == want).all()
