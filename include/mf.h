@@ -156,16 +156,21 @@ enum {
 
 /* region_kernel values */
 enum {
-    MF_KERNEL_AUTO = 0, /* WAVE for 2D regions up to 64 x 64, else ROWS when applicable, else LDS
-                           when it fits, else HBM */
+    MF_KERNEL_AUTO = 0, /* WAVE for 2D regions up to 64 x 64, else ROWS or ROWS64 when
+                           applicable, else LDS when it fits, else HBM */
     MF_KERNEL_HBM = 1,  /* region state stays in HBM; search arrays in LDS or HBM scratch */
     MF_KERNEL_LDS = 2,  /* whole region in LDS, one workgroup; MF_E_INVAL if it does not fit */
     MF_KERNEL_WAVE = 3, /* 2D region of at most 64 x 64 in LDS, one wavefront, row-bitmask
                            search; MF_E_INVAL if not applicable */
-    MF_KERNEL_ROWS = 4  /* 3D 6-connected region with rows of 32 along x, 2 <= ty, 2 <= tz,
+    MF_KERNEL_ROWS = 4, /* 3D 6-connected region with rows of 32 along x, 2 <= ty, 2 <= tz,
                            ty * tz a multiple of 64 and at most 1024: one 1024-thread
                            workgroup, row-bitmask search and parallel pushes, state in HBM;
                            MF_E_INVAL if not applicable */
+    MF_KERNEL_ROWS64 = 5 /* 3D 6-connected region with rows of 64 along x (64^3 regions), 2 <= ty,
+                           2 <= tz, ty * tz a multiple of 64 and at most 4096: one 512-thread
+                           workgroup with eight rows per thread in registers, row-bitmask
+                           search, masks and admissible arcs in per-workgroup scratch, state
+                           in HBM; MF_E_INVAL if not applicable */
 };
 
 typedef struct {

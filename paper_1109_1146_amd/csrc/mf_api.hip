@@ -264,6 +264,7 @@ static mf_status create_impl(int32_t ndim, const int64_t *dims, int32_t connecti
     if (!attributes_set) {
         mfd::set_wave_attributes();
         mfd::set_rows_attributes();
+        mfd::set_rows64_attributes();
         mfd::set_lds_attributes();
         mfd::set_hbm_attributes();
         mfd::set_sched_attributes();
@@ -769,21 +770,33 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
             rowsLds = mfd::discharge_rows_bytes(G.ty, G.tz, g->nring);
         }
     }
-    int regionMode = 0;  // 0: HBM, 1: LDS workgroup, 2: wavefront, 3: row-bitmask workgroup
+    // 3D 6-connected regions with 64-vertex rows (64^3): one workgroup, rows in
+    // registers, masks and admissible arcs in per-workgroup scratch (ROWS64)
+    size_t rows64Lds = 0;
+    if (g->ndim == 3 && mfd::rows64_applicable(G.K, G.tx, G.ty, G.tz) &&
+        mfd::discharge_rows64_bytes(G.ty, G.tz) <= ldsBudget &&
+        mfd::rows64_scratch_bytes(G.ty, G.tz, g->nring) <= (size_t)16 * G.V)
+        rows64Lds = mfd::discharge_rows64_bytes(G.ty, G.tz);
+    int regionMode = 0;  // 0: HBM, 1: LDS workgroup, 2: wavefront, 3: row-bitmask workgroup, 4: 64-bit rows
     switch (o.region_kernel) {
         case MF_KERNEL_AUTO:
-            regionMode = prd ? 0 : (waveLds ? 2 : (rowsLds ? 3 : (groupLds ? 1 : 0)));
+            regionMode = prd ? 0 : (waveLds ? 2 : (rowsLds ? 3 : (rows64Lds ? 4 : (groupLds ? 1 : 0))));
             break;
         case MF_KERNEL_HBM: regionMode = 0; break;
         case MF_KERNEL_LDS: if (!groupLds) return MF_E_INVAL; regionMode = 1; break;
         case MF_KERNEL_WAVE: if (!waveLds) return MF_E_INVAL; regionMode = 2; break;
         case MF_KERNEL_ROWS: if (!rowsLds) return MF_E_INVAL; regionMode = 3; break;
+        case MF_KERNEL_ROWS64: if (!rows64Lds) return MF_E_INVAL; regionMode = 4; break;
         default: return MF_E_INVAL;
     }
-    const size_t regionLds = regionMode == 3 ? rowsLds : (regionMode == 2 ? waveLds : groupLds);
+    const size_t regionLds = regionMode == 4 ? rows64Lds
+                             : (regionMode == 3 ? rowsLds : (regionMode == 2 ? waveLds : groupLds));
     const int regionNarrow = regionMode == 2 ? waveNarrow : groupNarrow;
     int regionBlocks = g->nslots;
-    if (regionMode == 3) {
+    if (regionMode == 4) {
+        // one workgroup per compute unit, each with its own scratch slot
+        regionBlocks = std::max(1, std::min(std::min(G.nreg, g->numCU), g->nslots));
+    } else if (regionMode == 3) {
         // at most two 1024-thread workgroups fit the wave slots of a compute unit
         int occ = (int)std::max<size_t>(1, std::min<size_t>(2, g->ldsMax / (regionLds + 256)));
         regionBlocks = std::max(1, std::min(G.nreg, g->numCU * occ));
@@ -914,7 +927,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                 }
                 if (o.profile && !ok(hipEventRecord(ev[2 * j], s))) return false;
                 hipError_t e;
-                if (regionMode == 3) e = mfd::launch_discharge_rows(D, regionBlocks, regionLds, s);
+                if (regionMode == 4) e = mfd::launch_discharge_rows64(D, regionBlocks, regionLds, s);
+                else if (regionMode == 3) e = mfd::launch_discharge_rows(D, regionBlocks, regionLds, s);
                 else if (regionMode == 2) e = mfd::launch_discharge_wave(D, regionBlocks, regionLds, regionNarrow, s);
                 else if (regionMode == 1) e = mfd::launch_discharge_lds(D, regionBlocks, regionLds, regionNarrow, s);
                 else e = mfd::launch_discharge(D, g->nslots, g->threads, lds, s);
@@ -1035,7 +1049,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         st->flood_ticks = (int64_t)g->pinned[25];
         st->push_iterations = (int64_t)g->pinned[26];
         st->relabel_only = (int64_t)g->pinned[27];
-        st->region_kernel = regionMode == 3 ? MF_KERNEL_ROWS
+        st->region_kernel = regionMode == 4 ? MF_KERNEL_ROWS64 : regionMode == 3 ? MF_KERNEL_ROWS
                             : (regionMode == 2 ? MF_KERNEL_WAVE : (regionMode == 1 ? MF_KERNEL_LDS : MF_KERNEL_HBM));
         st->global_relabels = relabels;
         st->global_relabel_levels = relabel_levels;

@@ -215,6 +215,15 @@ size_t discharge_wave_bytes(int V, int K, int nring, int mode);
 hipError_t launch_discharge_rows(const DischargeArgs &A, int blocks, size_t lds, hipStream_t s);
 size_t discharge_rows_bytes(int ty, int tz, int nring);
 int rows_slots(int nring);
+// Row-bitmask workgroup discharge for 3D 6-connected regions with tx == 64,
+// ty, tz >= 2, ty * tz a multiple of 64 and at most 4096 (64^3 regions): one
+// 512-thread workgroup, rows in registers, rows64_scratch_bytes() of scratch
+// per workgroup at A.scratch + blockIdx.x * 16 * V bytes.
+bool rows64_applicable(int K, int tx, int ty, int tz);
+size_t discharge_rows64_bytes(int ty, int tz);
+size_t rows64_scratch_bytes(int ty, int tz, int nring);
+hipError_t launch_discharge_rows64(const DischargeArgs &A, int blocks, size_t lds, hipStream_t s);
+void set_rows64_attributes();
 hipError_t launch_fuse(const FuseArgs &A, hipStream_t s);
 hipError_t launch_boundary_relabel(const BrlArgs &A, int stage, int first, int count, hipStream_t s);
 hipError_t launch_label_hist(const int *lab, int N, int dinf, unsigned int *hist, int *maxlab,

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libmfard.so")
 MF_OK, MF_E_INVAL, MF_E_NOMEM, MF_E_DEVICE, MF_E_STATE, MF_E_OVERFLOW, MF_E_SWEEPS = range(7)
 MF_CUT_MIN_SOURCE, MF_CUT_MAX_SOURCE = 0, 1
 MF_SCHED_PARD, MF_SCHED_COLORED, MF_SCHED_LEARNED, MF_SCHED_AUTO, MF_SCHED_LEARNED_COLORED = 0, 1, 2, 3, 4
-MF_KERNEL_AUTO, MF_KERNEL_HBM, MF_KERNEL_LDS, MF_KERNEL_WAVE, MF_KERNEL_ROWS = 0, 1, 2, 3, 4
+MF_KERNEL_AUTO, MF_KERNEL_HBM, MF_KERNEL_LDS, MF_KERNEL_WAVE, MF_KERNEL_ROWS, MF_KERNEL_ROWS64 = 0, 1, 2, 3, 4, 5
 MF_METHOD_ARD, MF_METHOD_PRD = 0, 1
 TRACE_FIELDS = 10
 FEATURES = 6

@@ -205,12 +205,15 @@ def test_rows_kernel_tiles(mf, seed):
     _check(mf, inst, region_kernel=mf.MF_KERNEL_ROWS, global_relabel_every=2)
 
 
-def test_hbm_kernel_64_cubed_regions(mf):
-    """64^3 regions (the tile of the 464^3 workload) run on the HBM kernel; ragged grid."""
+def test_64_cubed_regions_auto_and_hbm(mf):
+    """64^3 regions (the tile of the 464^3 workload): the default picks the
+    64-vertex-row kernel; the HBM kernel gives the same result; ragged grid."""
     inst = synth.blob_grid((96, 100, 130), 6, 31, 6, 6.0, 20.0, tile=(64, 64, 64), name="blob3d_t64")
     out, _ = _check(mf, inst, certify=False)
-    assert out["stats"]["region_kernel"] == mf.MF_KERNEL_HBM
+    assert out["stats"]["region_kernel"] == mf.MF_KERNEL_ROWS64
     _check(mf, inst, certify=False, global_relabel_every=4)
+    out, _ = _check(mf, inst, certify=False, region_kernel=mf.MF_KERNEL_HBM)
+    assert out["stats"]["region_kernel"] == mf.MF_KERNEL_HBM
 
 
 @pytest.mark.parametrize("case", range(6))
@@ -230,7 +233,7 @@ def test_hbm_kernel_large_regions_1024_threads(mf, case):
 
 
 def test_full_size_464_certified(mf):
-    """The 464^3 workload (10^8 vertices, 64^3 regions on the HBM kernel) is too
+    """The 464^3 workload (10^8 vertices, 64^3 regions) is too
     large for the oracle's solver inside a test; its state is certified at full
     size instead, from the original capacities: residuals feasible, conservation,
     flow = sum (c_t - r_t), both returned cuts of cost equal to the flow
