@@ -4,8 +4,13 @@ One step = one full solve of the workload from Init to a maximum preflow plus
 the minimal minimum cut (mf_solve + mf_min_cut), with the capacities already
 resident in HBM.  Prints ONE JSON line (rank 0).
 
-Default workload: the 2048 x 2048 8-connected blob grid with 64 x 64 regions
-(seed 1); ``--workload 3d`` selects the 256^3 6-connected grid with 32^3 regions.
+Default workload: the 464^3 6-connected blob grid with 64^3 regions (seed 4),
+plain P-ARD timed, the learned-ordered schedules and the fixed-order colour
+phases solved on the same input beside it, the oracle on the whole instance as
+the CPU baseline and exactness check, and the roofline record of the 256^3
+grid with 32^3 regions nested in the same line.  ``--workload 2d`` / ``3d`` /
+``batch`` select the 2048^2 8-connected grid, the 256^3 grid or the
+512-instance batch alone.
 """
 from __future__ import annotations
 
@@ -46,12 +51,14 @@ def measured_traffic(kernel_src, summary, config=None):
 WORKLOADS = {
     "2d": dict(cfg=1, tag="grid2d8_2048", relabel=10, partial=False, desc="2048x2048 2D 8-connected blob grid, 64 blobs, 10% n-links zeroed, "
                            "64x64 regions (1024), seed 1"),
-    "3d": dict(cfg=2, tag="grid3d6_256", relabel=4, partial=True, desc="256^3 3D 6-connected blob grid, 32 blobs, 32^3 regions (512), seed 2"),
+    "3d": dict(cfg=2, tag="grid3d6_256", relabel=4, partial=True,
+               desc="256^3 3D 6-connected blob grid, 32 blobs, 32^3 regions (512), seed 2"),
     "batch": dict(cfg=3, tag="batch512", relabel=None, partial=None, desc="512 independent 2D blob grids, sides log-uniform in [32,512], "
                               "half 4- and half 8-connected, seeds 3000+i, one batched solve"),
-    # the learned scheduler's workload: one solve takes seconds, run it with --steps 1 --warmup 0
-    "464": dict(cfg=4, tag="grid3d6_464", relabel=4, partial=False, crop=(160, 160, 160),
-                desc="464^3 3D 6-connected blob grid, 256 blobs, 64^3 regions (512), seed 4"),
+    # the headline workload: plain vs learned-ordered ARD
+    "464": dict(cfg=4, tag="grid3d6_464", relabel=4, partial=False, crop=(192, 192, 192),
+                reference="grid3d6_464_oracle.json",
+                desc="464^3 3D 6-connected blob grid, 256 blobs, 64^3 regions (512; last layer 16 thick), seed 4"),
 }
 
 
@@ -60,9 +67,11 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", choices=sorted(WORKLOADS), default="2d",
-                   help="2d, 3d, batch, or 464 (the learned scheduler's workload: use --steps 1 "
-                        "--warmup 0; its oracle baseline runs on a 160^3 corner block)")
+    p.add_argument("--workload", choices=sorted(WORKLOADS), default="464",
+                   help="464 (default: the headline 464^3 grid, with the 256^3 roofline record "
+                        "nested), 3d (256^3), 2d (2048^2) or batch (512 instances)")
+    p.add_argument("--no-nested", action="store_true",
+                   help="464 only: skip the nested 256^3 roofline record")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-learned", action="store_true",
                    help="skip the learned-schedule comparison solves (profiling runs)")
@@ -109,7 +118,7 @@ def calibrate_copy(mib):
 
 def crop_instance(inst, shape):
     """The corner block [0, shape) of a grid instance, arcs leaving it dropped:
-    a bounded sample of a workload too large for the oracle."""
+    a bounded sample of a workload too large to time the oracle on whole."""
     import numpy as np
     import synth
     dims = tuple(inst.dims)
@@ -128,6 +137,33 @@ def crop_instance(inst, shape):
                               name=f"{inst.name}_corner{'x'.join(map(str, shape))}")
 
 
+def stored_reference(name):
+    """The oracle's result on a workload too large for the oracle inside the
+    bench, written by the committed script beside it (tests/golden/make_*.py,
+    oracle and generator only)."""
+    path = os.path.join(ROOT, "tests", "golden", name)
+    with open(path) as f:
+        return json.load(f), os.path.relpath(path, ROOT)
+
+
+def host_cpu():
+    """Model name of the host CPU and the logical CPUs this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return model, nproc
+
+
 def cpu_baseline(inst, budget_s):
     """The oracle (single-thread push-relabel) on whole copies of the same
     instance, repeated until the budget is used (at least once)."""
@@ -142,9 +178,11 @@ def cpu_baseline(inst, budget_s):
         if t_total >= budget_s or reps >= 3:
             break
     mvs = inst.n * reps / t_total / 1e6
+    model, nproc = host_cpu()
     return ref, dict(value=round(mvs, 4), unit="Mvertices/s", cores=1, kind="oracle",
                      sample=f"{reps} full solve(s) of the same instance, {t_total:.1f} s total, "
-                            f"highest-label push-relabel, 1 thread")
+                            f"highest-label push-relabel, 1 thread",
+                     cpu_model=model, nproc=nproc)
 
 
 def bench_batch(args):
@@ -259,37 +297,33 @@ def bench_batch(args):
     print(json.dumps(rec), flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "the solver runs on one GPU; multi-GPU runs are not supported, --gpus must be 1"}))
-        sys.exit(2)
-    if args.calibrate_copy:
-        calibrate_copy(args.calibrate_copy)
-        return
-    if args.workload == "batch":
-        bench_batch(args)
-        return
+
+
+def kernel_of(mf, kid):
+    return {mf.MF_KERNEL_WAVE: ("k_discharge_wave", "mf_discharge_wave.hip"),
+            mf.MF_KERNEL_ROWS: ("k_discharge_rows", "mf_discharge_rows.hip"),
+            mf.MF_KERNEL_ROWS64: ("k_discharge_rows64", "mf_discharge_rows64.hip"),
+            mf.MF_KERNEL_LDS: ("k_discharge_lds", "mf_discharge_lds.hip"),
+            mf.MF_KERNEL_HBM: ("k_discharge", "mf_kernels.hip")}[kid]
+
+
+def bench_grid(args, wl, steps, warmup, compare, cpu):
+    """Time `steps` solves + minimal cuts of one grid workload (after `warmup`),
+    with every discharge launch timed by HIP events on the solve stream.  With
+    compare, solve the same input with the learned-ordered schedules and the
+    fixed-order colour phases beside it; with cpu, run the oracle on the whole
+    instance (CPU baseline and exactness of the flow and both cuts)."""
     import numpy as np
     import torch
     import synth
     from paper_1109_1146_amd import mf
 
-    mf.load()
-    wl = WORKLOADS[args.workload]
-    if args.relabel_every is None:
-        args.relabel_every = wl["relabel"]
-    args.partial = {"on": True, "off": False}.get(args.partial, wl["partial"])
-    if args.boundary_relabel is None:
-        args.boundary_relabel = 0
     method = mf.MF_METHOD_PRD if args.method == "prd" else mf.MF_METHOD_ARD
     schedule = mf.MF_SCHED_COLORED if args.schedule == "colored" else mf.MF_SCHED_PARD
-    if args.schedule == "colored":
-        args.boundary_relabel, args.no_learned = 0, True
-    if args.method == "prd":
-        # the exact relabel and the heuristics are those of region distances
-        args.relabel_every, args.partial, args.boundary_relabel, args.no_learned = 0, False, 0, True
+    t_gen = time.perf_counter()
     inst = synth.config(wl["cfg"])
+    t_gen = time.perf_counter() - t_gen
+    print(f"bench: {inst.name} generated in {t_gen:.1f} s", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
     cs = torch.from_numpy(inst.cs).to(dev)
@@ -299,66 +333,52 @@ def main():
 
     g = mf.Grid(inst.dims, inst.conn, inst.tile)
     g.set_caps(cs, ct, nbr, stream=stream.cuda_stream)
+    del cs, ct, nbr
     info = g.info()
+    relabel, partial, brl = args.relabel_every, args.partial, args.boundary_relabel
 
     def step(profile):
-        st = g.solve(stream=stream.cuda_stream, profile=profile,
-                     global_relabel_every=args.relabel_every, partial=args.partial,
-                     boundary_relabel=args.boundary_relabel, method=method,
-                     schedule=schedule, max_sweeps=1 << 40)
+        st = g.solve(stream=stream.cuda_stream, profile=profile, global_relabel_every=relabel,
+                     partial=partial, boundary_relabel=brl, method=method, schedule=schedule,
+                     max_sweeps=1 << 40)
         cut = g.min_cut(mf.MF_CUT_MIN_SOURCE)
         return st, cut
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step(False)
     torch.cuda.synchronize()
     stats = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         st, cut = step(True)
         stats.append(st)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     flow = g.flow_value()
     smax = g.min_cut(mf.MF_CUT_MAX_SOURCE)
+    print(f"bench: {steps} timed steps in {elapsed:.1f} s", file=sys.stderr, flush=True)
 
-    ms_per_step = elapsed * 1e3 / args.steps
-    value = inst.n / (ms_per_step / 1e3) / 1e6
+    ms_per_step = elapsed * 1e3 / steps
     d_ms = sum(s["discharge_ms"] for s in stats)
     d_launch = sum(s["discharge_launches"] for s in stats)
     d_bytes = sum(s["discharge_bytes"] for s in stats)
     achieved = d_bytes / (d_ms / 1e3) / 1e9 if d_ms > 0 else 0.0
-    # the region kernel that ran, its source and the counter summary of this workload
-    kname, ksrc = {mf.MF_KERNEL_WAVE: ("k_discharge_wave", "mf_discharge_wave.hip"),
-                   mf.MF_KERNEL_ROWS: ("k_discharge_rows", "mf_discharge_rows.hip"),
-                   mf.MF_KERNEL_LDS: ("k_discharge_lds", "mf_discharge_lds.hip"),
-                   mf.MF_KERNEL_HBM: ("k_discharge", "mf_kernels.hip")}[stats[-1]["region_kernel"]]
+    kname, ksrc = kernel_of(mf, stats[-1]["region_kernel"])
     # the committed counter summaries cover the parallel ARD solves
     traffic = (None if args.method == "prd" or args.schedule == "colored" else
                measured_traffic("paper_1109_1146_amd/csrc/" + ksrc, f"{kname}_{wl['tag']}_traffic.json"))
     rec = {
-        "metric": "exact-maxflow solve throughput (plain %s-%s), sweeps, %% HBM peak" % (
-            "S" if args.schedule == "colored" else "P", args.method.upper()),
-        "value": round(value, 3),
-        "unit": "Mvertices/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
+        "value": round(inst.n / (ms_per_step / 1e3) / 1e6, 3),
         "config": {"workload": wl["desc"], "n": inst.n, "regions": info["regions"],
                    "region_shape": list(info["region_shape"]), "boundary_size": info["boundary_size"],
                    "schedule": ("S-" if args.schedule == "colored" else "P-") + args.method.upper()
                                + (" (colour phases)" if args.schedule == "colored" else "")
-                               + (", partial discharges" if args.partial else "")
-                               + (", boundary relabel" if args.boundary_relabel else ""),
+                               + (", partial discharges" if partial else "")
+                               + (", boundary relabel" if brl else ""),
                    "connectivity": inst.conn,
-                   "global_relabel_every": args.relabel_every, "partial_discharges": args.partial,
-                   "boundary_relabel": args.boundary_relabel},
+                   "global_relabel_every": relabel, "partial_discharges": partial,
+                   "boundary_relabel": brl},
         "sweeps": stats[-1]["sweeps"],
         "region_discharges": stats[-1]["region_discharges"],
         "flow": flow,
@@ -375,69 +395,144 @@ def main():
             "algorithmic_bytes_per_launch": round(d_bytes / max(d_launch, 1), 1),
         },
     }
-    # the learned-ordered schedule on the same input (untimed in value): sweeps,
-    # discharges and wall time next to plain P-ARD, same exact flow
-    try:
-        if args.no_learned:
-            raise ValueError("skipped (--no-learned)")
-        from paper_1109_1146_amd import learned
-        model = learned.load_model()
-        lkw = dict(schedule=mf.MF_SCHED_LEARNED, model=model, defer_threshold=learned.DEFAULT_THRESHOLD,
-                   max_defer=learned.DEFAULT_MAX_DEFER, global_relabel_every=args.relabel_every,
-                   stream=stream.cuda_stream, partial=args.partial,
-                   boundary_relabel=args.boundary_relabel)
-        g.solve(**lkw)
+
+    def timed_solves(kw):
+        g.solve(**kw)
         times = []
-        for _ in range(max(1, min(args.steps, 3))):
+        for _ in range(max(1, min(steps, 3))):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            lst = g.solve(**lkw)
+            vst = g.solve(**kw)
             times.append((time.perf_counter() - t1) * 1e3)
-        rec["learned"] = {"solve_ms": round(float(np.median(times)), 3), "sweeps": lst["sweeps"],
-                          "region_discharges": lst["region_discharges"],
-                          "flow_equal": g.flow_value() == flow,
-                          "plain_solve_ms": rec["solve_ms"], "plain_sweeps": rec["sweeps"],
-                          "plain_region_discharges": rec["region_discharges"]}
-    except (OSError, ValueError) as e:  # no trained model in the tree
-        rec["learned"] = {"error": str(e)}
-    # the learned schedule driving the colour phases of Alg. 1 (phase order by
-    # the network, no deferral), and the same phases in fixed order (ablation)
-    if not args.no_learned:
+        return vst, float(np.median(times))
+
+    if compare:
+        # the learned-ordered schedules on the same input (not in value):
+        # sweeps, discharges and solve time next to plain P-ARD, same exact
+        # flow; and the colour phases in fixed order, the learned colour
+        # schedule's skeleton without the network
+        base = dict(global_relabel_every=relabel, stream=stream.cuda_stream, partial=partial)
         try:
             from paper_1109_1146_amd import learned
             model = learned.load_model()
-            variants = (("learned_colored", dict(schedule=mf.MF_SCHED_LEARNED_COLORED, model=model,
+            variants = (("learned", dict(schedule=mf.MF_SCHED_LEARNED, model=model,
+                                         defer_threshold=learned.DEFAULT_THRESHOLD,
+                                         max_defer=learned.DEFAULT_MAX_DEFER, boundary_relabel=brl)),
+                        ("learned_colored", dict(schedule=mf.MF_SCHED_LEARNED_COLORED, model=model,
                                                  defer_threshold=1e-9, max_defer=1)),
                         ("colored_fixed_order", dict(schedule=mf.MF_SCHED_COLORED)))
-            for key, kw in variants:
-                kw.update(global_relabel_every=args.relabel_every, stream=stream.cuda_stream,
-                          partial=args.partial)
-                g.solve(**kw)
-                times = []
-                for _ in range(max(1, min(args.steps, 3))):
-                    torch.cuda.synchronize()
-                    t1 = time.perf_counter()
-                    vst = g.solve(**kw)
-                    times.append((time.perf_counter() - t1) * 1e3)
-                rec[key] = {"solve_ms": round(float(np.median(times)), 3), "sweeps": vst["sweeps"],
+        except (OSError, ValueError) as e:  # no trained model in the tree
+            rec["learned"] = {"error": str(e)}
+            variants = (("colored_fixed_order", dict(schedule=mf.MF_SCHED_COLORED)),)
+        for key, kw in variants:
+            try:
+                vst, vms = timed_solves(dict(base, **kw))
+                rec[key] = {"solve_ms": round(vms, 3), "sweeps": vst["sweeps"],
                             "region_discharges": vst["region_discharges"],
                             "flow_equal": g.flow_value() == flow}
-        except (OSError, ValueError, mf.MFError) as e:
-            rec["learned_colored"] = {"error": str(e)}
-    if not args.no_cpu_baseline and "crop" in wl:
-        # too large for the oracle within the bench: time it on a corner block
+            except mf.MFError as e:
+                rec[key] = {"error": str(e)}
+            print(f"bench: {key} done", file=sys.stderr, flush=True)
+        plain = {"solve_ms": rec["solve_ms"], "sweeps": rec["sweeps"],
+                 "region_discharges": rec["region_discharges"]}
+        rec["plain"] = plain
+        for key in ("learned", "learned_colored"):
+            v = rec.get(key, {})
+            if "sweeps" in v:
+                v["fewer_sweeps_and_less_time_than_plain"] = bool(
+                    v["flow_equal"] and v["sweeps"] < plain["sweeps"] and v["solve_ms"] < plain["solve_ms"])
+        fixed = rec.get("colored_fixed_order", {})
+        if "sweeps" in rec.get("learned_colored", {}) and "sweeps" in fixed:
+            rec["learned_colored"]["fewer_sweeps_and_less_time_than_fixed_order"] = bool(
+                rec["learned_colored"]["sweeps"] < fixed["sweeps"]
+                and rec["learned_colored"]["solve_ms"] < fixed["solve_ms"])
+    g.close()
+    if cpu and "reference" in wl:
+        # the whole instance is beyond the oracle within the bench's time: the
+        # oracle is timed on a corner block, and the result is compared with the
+        # oracle's stored result on the whole instance
+        import hashlib
         sample = crop_instance(inst, wl["crop"])
         _, cb = cpu_baseline(sample, args.cpu_seconds)
         cb["sample"] = (f"a {'x'.join(map(str, wl['crop']))} corner block of the instance (arcs leaving "
                         f"it dropped): " + cb["sample"])
         rec["cpu_baseline"] = cb
-        rec["exact"] = None  # the full-size flow is not checked against the oracle here
-    elif not args.no_cpu_baseline:
+        want, path = stored_reference(wl["reference"])
+        got_min = hashlib.sha256(np.ascontiguousarray(cut, np.uint8).tobytes()).hexdigest()
+        got_max = hashlib.sha256(np.ascontiguousarray(smax, np.uint8).tobytes()).hexdigest()
+        rec["exact"] = bool(want["flow"] == flow and want["smin_sha256"] == got_min
+                            and want["smax_sha256"] == got_max)
+        rec["exact_reference"] = (f"{path}: the oracle on the whole instance "
+                                  f"({want['oracle_seconds']} s, 1 thread, when stored)")
+        print(f"bench: oracle sample done", file=sys.stderr, flush=True)
+    elif cpu:
         ref, cb = cpu_baseline(inst, args.cpu_seconds)
         rec["cpu_baseline"] = cb
         rec["exact"] = bool(ref["flow"] == flow and (ref["smin"] == cut).all()
                             and (ref["smax"] == smax).all())
-    g.close()
+        print(f"bench: oracle done", file=sys.stderr, flush=True)
+    return rec
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "the solver runs on one GPU; multi-GPU runs are not supported, --gpus must be 1"}))
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
+    if args.workload == "batch":
+        bench_batch(args)
+        return
+    from paper_1109_1146_amd import mf
+
+    mf.load()
+    wl = WORKLOADS[args.workload]
+    if args.relabel_every is None:
+        args.relabel_every = wl["relabel"]
+    args.partial = {"on": True, "off": False}.get(args.partial, wl["partial"])
+    if args.boundary_relabel is None:
+        args.boundary_relabel = 0
+    if args.schedule == "colored":
+        args.boundary_relabel, args.no_learned = 0, True
+    if args.method == "prd":
+        # the exact relabel and the heuristics are those of region distances
+        args.relabel_every, args.partial, args.boundary_relabel, args.no_learned = 0, False, 0, True
+    headline = args.workload == "464"
+    sub = bench_grid(args, wl, args.steps, args.warmup, compare=not args.no_learned,
+                     cpu=not args.no_cpu_baseline)
+    rec = {
+        "metric": ("exact-maxflow solve time + sweeps, plain vs learned-ordered ARD; % HBM peak"
+                   if headline else
+                   "exact-maxflow solve throughput (plain %s-%s), sweeps, %% HBM peak" % (
+                       "S" if args.schedule == "colored" else "P", args.method.upper())),
+        "value": sub.pop("value"),
+        "unit": "Mvertices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sub.pop("ms_per_step"),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+    }
+    rec.update(sub)
+    if headline and not args.no_nested:
+        # the HBM-roofline configuration: 256^3 with 32^3 regions, its tuned
+        # settings, a few timed steps (roofline only: no comparison, no oracle)
+        w3 = WORKLOADS["3d"]
+        a3 = argparse.Namespace(**vars(args))
+        a3.relabel_every, a3.partial = w3["relabel"], w3["partial"]
+        n3 = bench_grid(a3, w3, 3, 1, compare=False, cpu=False)
+        rec["grid3d6_256"] = {"workload": n3["config"]["workload"], "steps": 3, "warmup": 1,
+                              "ms_per_step": n3["ms_per_step"], "value": n3["value"],
+                              "unit": "Mvertices/s", "sweeps": n3["sweeps"],
+                              "region_discharges": n3["region_discharges"],
+                              "global_relabel_every": w3["relabel"],
+                              "partial_discharges": w3["partial"], "roofline": n3["roofline"]}
     print(json.dumps(rec), flush=True)
 
 

@@ -101,7 +101,7 @@ typedef struct {
                                      probability of useful work is below this; 0 = 0.5 */
     int32_t defer_mode;           /* MF_SCHED_LEARNED: 0 = a deferred region is skipped (labels carried
                                      over); 1 = it only runs its region relabel (Alg. 3 on the current
-                                     state, no pushes) with the row-bitmask and wavefront kernels */
+                                     state, no pushes) */
     float *features;              /* device buffer [features_cap][regions][MF_FEATURES] or NULL:
                                      the scheduler's region features at the start of each sweep */
     int64_t features_cap;         /* sweeps the features buffer holds */
@@ -123,6 +123,12 @@ typedef struct {
                                      global gap over all labels and the HBM region kernel; not
                                      combined with partial, boundary_relabel, global_relabel_every,
                                      features or MF_SCHED_LEARNED (MF_E_INVAL) */
+    int32_t *label_trace;         /* device buffer [label_trace_cap][n] int32, or NULL: the labels
+                                     (row-major like dims) after every step, a sweep of Alg. 2 or a
+                                     colour phase of Alg. 1, after its fusion and gap; steps beyond
+                                     label_trace_cap are not recorded.  Forces eager launches (no
+                                     graph) */
+    int64_t label_trace_cap;      /* steps the label trace holds */
 } mf_solve_opts;
 
 /* region discharge operation, see mf_solve_opts.method */
@@ -267,6 +273,28 @@ mf_status mf_get_state(const mf_grid *g, int32_t *res, int32_t *rt, int32_t *ex,
  * (also for a state left by MF_METHOD_PRD, whose labels are not region
  * distances), MF_E_DEVICE. */
 mf_status mf_boundary_relabel(mf_grid *g, int32_t max_levels, int64_t *levels_out);
+
+/* Region relabel (Alg. 3, the ARD variant of Sec. 4.2) of every region on the
+ * state the last solve left (see mf_get_state), as the last search of a region
+ * discharge computes it, without pushes: for u in region R, d(u) = 0 if u
+ * reaches t in the region network G^R, else 1 + min d(w) over the boundary
+ * vertices w with d(w) < dinf that u reaches through a residual boundary arc,
+ * else dinf, with the current labels as d(w).  Every label of the state is
+ * replaced (border vertices included); residuals, t-links and excess stay.
+ *   region_kernel  MF_KERNEL_* that runs it (AUTO as for mf_solve)
+ *   regions_out    receives the number of regions relabelled (may be NULL)
+ * Errors: MF_E_STATE (no state, or a state left by MF_METHOD_PRD), MF_E_INVAL
+ * (kernel not applicable), MF_E_NOMEM, MF_E_DEVICE. */
+mf_status mf_region_relabel(mf_grid *g, int32_t region_kernel, int64_t *regions_out);
+
+/* Exact region-distance relabel (Sec. 4.1) on the state the last solve left:
+ * every label becomes min(d*B(u), dinf), d*B the distance to t in the residual
+ * network where an arc between regions has length 1 and an arc inside a region
+ * length 0 (a 0-1 breadth-first search backwards from the vertices with a
+ * residual t-link, one launch per distance level).
+ *   levels_out  receives the number of level launches (a multiple of four; may be NULL)
+ * Errors: MF_E_STATE (no state, or a state left by MF_METHOD_PRD), MF_E_DEVICE. */
+mf_status mf_global_relabel(mf_grid *g, int64_t *levels_out);
 
 /* Shape facts of a handle: number of vertices, K, regions, |B|, region shape. */
 mf_status mf_get_info(const mf_grid *g, int64_t *n, int32_t *K, int64_t *regions,

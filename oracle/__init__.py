@@ -24,6 +24,8 @@ What it computes (all integer, int64 accumulators):
   strong and weak source and sink nodes from three augmentations per region.
 * ``boundary_relabel`` -- the heuristic of Sec. 6.1 on a given state, written
   separately in Python (groups, the two kinds of arcs, Dijkstra by heapq).
+* ``region_relabel`` -- the region relabel of Alg. 3 of every region on a given
+  state (the labels a region discharge writes).
 * ``brute_force`` -- every cut of a network of at most ~20 vertices.
 * ``certify`` -- feasibility, conservation and max-flow = min-cut duality of a
   residual state, from the original capacities.
@@ -353,6 +355,58 @@ def boundary_relabel(n, pu, pv, r_uv, r_vu, region, labels, dinf, distances=Fals
             dprime[v] = dq
     if distances:
         return out.astype(np.int32), dprime
+    return out.astype(np.int32)
+
+
+def region_relabel(n, pu, pv, r_uv, r_vu, rt, region, labels, dinf):
+    """Region relabel of Alg. 3 (the ARD variant, Sec. 4.2) of every region on
+    a given residual state, with the given labels as the labels d(w) of the
+    boundary vertices.  For u in region R: d'(u) = 0 if u reaches, inside R, a
+    vertex with a residual t-link; else 1 + min d(w) over the vertices w outside
+    R with d(w) < dinf that u reaches through a residual arc (x, w) with x
+    reached inside R; else dinf (capped at dinf).  Computed as Alg. 3 steps: a
+    backward flood from t inside the regions, then from the boundary seeds x at
+    stage d(w) + 1 in increasing stage order, never relabelling a vertex."""
+    from collections import deque
+    pu = np.asarray(pu, np.int64)
+    pv = np.asarray(pv, np.int64)
+    r_uv = np.asarray(r_uv)
+    r_vu = np.asarray(r_vu)
+    region = np.asarray(region)
+    labels = np.asarray(labels, np.int64)
+    same = region[pu] == region[pv]
+    rev = [[] for _ in range(n)]  # y -> x for residual arcs x -> y inside a region
+    for a, b in zip(pu[same & (r_uv > 0)], pv[same & (r_uv > 0)]):
+        rev[b].append(a)
+    for a, b in zip(pv[same & (r_vu > 0)], pu[same & (r_vu > 0)]):
+        rev[b].append(a)
+    stage = {}
+    def seed(x, k):
+        stage.setdefault(int(k), []).append(int(x))
+    for x in np.flatnonzero(np.asarray(rt) > 0):
+        seed(x, 0)
+    # boundary seeds: residual arcs leaving a region, to w with d(w) < dinf
+    for tail, head, res in ((pu, pv, r_uv), (pv, pu, r_vu)):
+        m = ~same & (res > 0)
+        for x, w in zip(tail[m], head[m]):
+            if labels[w] < dinf:
+                seed(x, labels[w] + 1)
+    out = np.full(n, dinf, np.int64)
+    done = np.zeros(n, bool)
+    for k in sorted(stage):
+        q = deque()
+        for x in stage[k]:
+            if not done[x]:
+                done[x] = True
+                out[x] = min(k, dinf)
+                q.append(x)
+        while q:
+            y = q.popleft()
+            for x in rev[y]:
+                if not done[x]:
+                    done[x] = True
+                    out[x] = min(k, dinf)
+                    q.append(x)
     return out.astype(np.int32)
 
 

@@ -611,6 +611,102 @@ static int global_relabel(mf_grid *g, int *lab, u64 *act, hipStream_t s) {
     return D;
 }
 
+// Which region kernel runs the discharges (MF_KERNEL_* request, AUTO = the
+// first that applies), its dynamic LDS, storage width and grid size.
+struct RegionPick {
+    int mode;  // 0: HBM, 1: LDS workgroup, 2: wavefront, 3: row-bitmask workgroup, 4: 64-bit rows
+    size_t lds;
+    int narrow;
+    int blocks;
+};
+
+static mf_status pick_region(const mf_grid *g, int region_kernel, bool prd, RegionPick &P) {
+    const Geo &G = g->G;
+    // Region kernels: a single wavefront with row bitmasks for 2D regions of
+    // at most 64 x 64 (WAVE), one workgroup with the whole region in LDS
+    // (LDS), or the region left in HBM (HBM).  LDS-resident residuals are int16
+    // when every residual (bounded by its pair sum) and t-link fits, else int32.
+    const size_t ldsBudget = g->ldsMax > 512 ? g->ldsMax - 512 : 0;
+    const bool narrowOk = g->maxPair <= 32767 && g->maxCt <= 32767;
+    size_t waveLds = 0, groupLds = 0;
+    int waveNarrow = 0, groupNarrow = 0;
+    if (g->ndim == 2 && G.tz == 1 && G.tx <= 64 && G.ty <= 64 && g->nring <= 256) {
+        // 8-bit residuals and t-links with 16-bit excess, else 16-bit residuals, else 32-bit
+        const bool narrow8 = g->maxPair <= 255 && g->maxCt <= 255 && g->maxIn <= 32767;
+        size_t b8 = mfd::discharge_wave_bytes(G.V, G.K, g->nring, 2);
+        size_t b16 = mfd::discharge_wave_bytes(G.V, G.K, g->nring, 1);
+        size_t b32 = mfd::discharge_wave_bytes(G.V, G.K, g->nring, 0);
+        if (narrow8 && b8 <= ldsBudget) { waveLds = b8; waveNarrow = 2; }
+        else if (narrowOk && b16 <= ldsBudget) { waveLds = b16; waveNarrow = 1; }
+        else if (b32 <= ldsBudget) { waveLds = b32; }
+    }
+    if (G.V <= 32767) {
+        size_t b16 = mfd::discharge_lds_bytes(G.V, G.K, g->nring, 1);
+        size_t b32 = mfd::discharge_lds_bytes(G.V, G.K, g->nring, 0);
+        if (narrowOk && b16 <= ldsBudget) { groupLds = b16; groupNarrow = 1; }
+        else if (b32 <= ldsBudget) { groupLds = b32; }
+    }
+    // 3D 6-connected regions with 32-vertex rows: one workgroup, row bitmasks
+    // in registers and LDS, integer state in HBM (ROWS)
+    size_t rowsLds = 0;
+    {
+        const int R = G.ty * G.tz;
+        if (g->ndim == 3 && G.K == 6 && G.tx == 32 && G.ty >= 2 && G.tz >= 2 && R % 64 == 0 &&
+            R <= 1024 && mfd::rows_slots(g->nring) > 0 && mfd::discharge_rows_bytes(G.ty, G.tz, g->nring) <= ldsBudget) {
+            rowsLds = mfd::discharge_rows_bytes(G.ty, G.tz, g->nring);
+        }
+    }
+    // 3D 6-connected regions with 64-vertex rows (64^3): one workgroup, rows in
+    // registers, masks and admissible arcs in per-workgroup scratch (ROWS64)
+    size_t rows64Lds = 0;
+    if (g->ndim == 3 && mfd::rows64_applicable(G.K, G.tx, G.ty, G.tz) &&
+        mfd::discharge_rows64_bytes(G.ty, G.tz) <= ldsBudget &&
+        mfd::rows64_scratch_bytes(G.ty, G.tz, g->nring) <= (size_t)16 * G.V)
+        rows64Lds = mfd::discharge_rows64_bytes(G.ty, G.tz);
+    int regionMode = 0;  // 0: HBM, 1: LDS workgroup, 2: wavefront, 3: row-bitmask workgroup, 4: 64-bit rows
+    switch (region_kernel) {
+        case MF_KERNEL_AUTO:
+            regionMode = prd ? 0 : (waveLds ? 2 : (rowsLds ? 3 : (rows64Lds ? 4 : (groupLds ? 1 : 0))));
+            break;
+        case MF_KERNEL_HBM: regionMode = 0; break;
+        case MF_KERNEL_LDS: if (!groupLds) return MF_E_INVAL; regionMode = 1; break;
+        case MF_KERNEL_WAVE: if (!waveLds) return MF_E_INVAL; regionMode = 2; break;
+        case MF_KERNEL_ROWS: if (!rowsLds) return MF_E_INVAL; regionMode = 3; break;
+        case MF_KERNEL_ROWS64: if (!rows64Lds) return MF_E_INVAL; regionMode = 4; break;
+        default: return MF_E_INVAL;
+    }
+    const size_t regionLds = regionMode == 4 ? rows64Lds
+                             : (regionMode == 3 ? rowsLds : (regionMode == 2 ? waveLds : groupLds));
+    const int regionNarrow = regionMode == 2 ? waveNarrow : groupNarrow;
+    int regionBlocks = g->nslots;
+    if (regionMode == 4) {
+        // one workgroup per compute unit, each with its own scratch slot
+        regionBlocks = std::max(1, std::min(std::min(G.nreg, g->numCU), g->nslots));
+    } else if (regionMode == 3) {
+        // at most two 1024-thread workgroups fit the wave slots of a compute unit
+        int occ = (int)std::max<size_t>(1, std::min<size_t>(2, g->ldsMax / (regionLds + 256)));
+        regionBlocks = std::max(1, std::min(G.nreg, g->numCU * occ));
+    } else if (regionMode) {
+        int occ = (int)std::max<size_t>(1, std::min<size_t>(8, g->ldsMax / (regionLds + 256)));
+        regionBlocks = std::max(1, std::min(G.nreg, g->numCU * occ));
+    }
+    P.mode = regionMode;
+    P.lds = regionLds;
+    P.narrow = regionNarrow;
+    P.blocks = regionBlocks;
+    return MF_OK;
+}
+
+// One discharge launch of the picked region kernel (lds: the HBM kernel's search arrays).
+static hipError_t launch_region(const mf_grid *g, const RegionPick &P, const mfd::DischargeArgs &D,
+                                size_t lds, hipStream_t s) {
+    if (P.mode == 4) return mfd::launch_discharge_rows64(D, P.blocks, P.lds, s);
+    if (P.mode == 3) return mfd::launch_discharge_rows(D, P.blocks, P.lds, s);
+    if (P.mode == 2) return mfd::launch_discharge_wave(D, P.blocks, P.lds, P.narrow, s);
+    if (P.mode == 1) return mfd::launch_discharge_lds(D, P.blocks, P.lds, P.narrow, s);
+    return mfd::launch_discharge(D, g->nslots, g->threads, lds, s);
+}
+
 extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_stats *st) {
     if (!g) return MF_E_INVAL;
     if (!g->has_caps) return MF_E_STATE;
@@ -687,7 +783,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     // the device counts steps: sweeps (Alg. 2) or colour phases (Alg. 1)
     const long long max_steps = max_sweeps > (1LL << 60) / ncol ? max_sweeps : max_sweeps * ncol;
     hipStream_t s = (hipStream_t)o.stream;
-    const bool use_graph = o.graph && !o.profile && !o.trace;
+    const bool use_graph = o.graph && !o.profile && !o.trace && !o.label_trace;
+    if (o.label_trace_cap < 0) return MF_E_INVAL;
     if (use_graph) {
         // capture needs a stream of our own; it orders with the null stream
         if (!s) {
@@ -736,74 +833,13 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     D.sweepCount = g->counters;
     D.actCarry = o.partial ? g->counters + 1 : nullptr;
     size_t lds = g->useLDS ? (size_t)16 * G.V : 0;
-    // Region kernels: a single wavefront with row bitmasks for 2D regions of
-    // at most 64 x 64 (WAVE), one workgroup with the whole region in LDS
-    // (LDS), or the region left in HBM (HBM).  LDS-resident residuals are int16
-    // when every residual (bounded by its pair sum) and t-link fits, else int32.
-    const size_t ldsBudget = g->ldsMax > 512 ? g->ldsMax - 512 : 0;
-    const bool narrowOk = g->maxPair <= 32767 && g->maxCt <= 32767;
-    size_t waveLds = 0, groupLds = 0;
-    int waveNarrow = 0, groupNarrow = 0;
-    if (g->ndim == 2 && G.tz == 1 && G.tx <= 64 && G.ty <= 64 && g->nring <= 256) {
-        // 8-bit residuals and t-links with 16-bit excess, else 16-bit residuals, else 32-bit
-        const bool narrow8 = g->maxPair <= 255 && g->maxCt <= 255 && g->maxIn <= 32767;
-        size_t b8 = mfd::discharge_wave_bytes(G.V, G.K, g->nring, 2);
-        size_t b16 = mfd::discharge_wave_bytes(G.V, G.K, g->nring, 1);
-        size_t b32 = mfd::discharge_wave_bytes(G.V, G.K, g->nring, 0);
-        if (narrow8 && b8 <= ldsBudget) { waveLds = b8; waveNarrow = 2; }
-        else if (narrowOk && b16 <= ldsBudget) { waveLds = b16; waveNarrow = 1; }
-        else if (b32 <= ldsBudget) { waveLds = b32; }
-    }
-    if (G.V <= 32767) {
-        size_t b16 = mfd::discharge_lds_bytes(G.V, G.K, g->nring, 1);
-        size_t b32 = mfd::discharge_lds_bytes(G.V, G.K, g->nring, 0);
-        if (narrowOk && b16 <= ldsBudget) { groupLds = b16; groupNarrow = 1; }
-        else if (b32 <= ldsBudget) { groupLds = b32; }
-    }
-    // 3D 6-connected regions with 32-vertex rows: one workgroup, row bitmasks
-    // in registers and LDS, integer state in HBM (ROWS)
-    size_t rowsLds = 0;
+    RegionPick RP;
     {
-        const int R = G.ty * G.tz;
-        if (g->ndim == 3 && G.K == 6 && G.tx == 32 && G.ty >= 2 && G.tz >= 2 && R % 64 == 0 &&
-            R <= 1024 && mfd::rows_slots(g->nring) > 0 && mfd::discharge_rows_bytes(G.ty, G.tz, g->nring) <= ldsBudget) {
-            rowsLds = mfd::discharge_rows_bytes(G.ty, G.tz, g->nring);
-        }
+        const mf_status ps = pick_region(g, o.region_kernel, prd, RP);
+        if (ps != MF_OK) return ps;
     }
-    // 3D 6-connected regions with 64-vertex rows (64^3): one workgroup, rows in
-    // registers, masks and admissible arcs in per-workgroup scratch (ROWS64)
-    size_t rows64Lds = 0;
-    if (g->ndim == 3 && mfd::rows64_applicable(G.K, G.tx, G.ty, G.tz) &&
-        mfd::discharge_rows64_bytes(G.ty, G.tz) <= ldsBudget &&
-        mfd::rows64_scratch_bytes(G.ty, G.tz, g->nring) <= (size_t)16 * G.V)
-        rows64Lds = mfd::discharge_rows64_bytes(G.ty, G.tz);
-    int regionMode = 0;  // 0: HBM, 1: LDS workgroup, 2: wavefront, 3: row-bitmask workgroup, 4: 64-bit rows
-    switch (o.region_kernel) {
-        case MF_KERNEL_AUTO:
-            regionMode = prd ? 0 : (waveLds ? 2 : (rowsLds ? 3 : (rows64Lds ? 4 : (groupLds ? 1 : 0))));
-            break;
-        case MF_KERNEL_HBM: regionMode = 0; break;
-        case MF_KERNEL_LDS: if (!groupLds) return MF_E_INVAL; regionMode = 1; break;
-        case MF_KERNEL_WAVE: if (!waveLds) return MF_E_INVAL; regionMode = 2; break;
-        case MF_KERNEL_ROWS: if (!rowsLds) return MF_E_INVAL; regionMode = 3; break;
-        case MF_KERNEL_ROWS64: if (!rows64Lds) return MF_E_INVAL; regionMode = 4; break;
-        default: return MF_E_INVAL;
-    }
-    const size_t regionLds = regionMode == 4 ? rows64Lds
-                             : (regionMode == 3 ? rowsLds : (regionMode == 2 ? waveLds : groupLds));
-    const int regionNarrow = regionMode == 2 ? waveNarrow : groupNarrow;
-    int regionBlocks = g->nslots;
-    if (regionMode == 4) {
-        // one workgroup per compute unit, each with its own scratch slot
-        regionBlocks = std::max(1, std::min(std::min(G.nreg, g->numCU), g->nslots));
-    } else if (regionMode == 3) {
-        // at most two 1024-thread workgroups fit the wave slots of a compute unit
-        int occ = (int)std::max<size_t>(1, std::min<size_t>(2, g->ldsMax / (regionLds + 256)));
-        regionBlocks = std::max(1, std::min(G.nreg, g->numCU * occ));
-    } else if (regionMode) {
-        int occ = (int)std::max<size_t>(1, std::min<size_t>(8, g->ldsMax / (regionLds + 256)));
-        regionBlocks = std::max(1, std::min(G.nreg, g->numCU * occ));
-    }
+    const int regionMode = RP.mode;
+    const int regionNarrow = RP.narrow;
     mfd::FuseArgs F;
     memset(&F, 0, sizeof(F));
     F.G = G; F.bidx = g->bidx; F.nB = (int)g->nB; F.res = g->res; F.ex = g->ex; F.pushb = g->pushb;
@@ -838,6 +874,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     long long timed = 0;
     long long sweep = 0;
     long long relabels = 0, relabel_levels = 0;
+    long long stepsDone = 0;  // device step counter at the last check
     mf_status status = MF_OK;
     for (;;) {
         if (o.global_relabel_every > 0) {
@@ -853,8 +890,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         const std::vector<int> &corderHost = g->corder_host;
         std::vector<int> cperm(ncol);
         for (int c = 0; c < ncol; c++) cperm[c] = c;
-        auto enqueue_batch = [&](long long first) -> bool {
-            for (int j = 0; j < check_every; j++) {
+        auto enqueue_batch = [&](long long first, int count) -> bool {
+            for (int j = 0; j < count; j++) {
                 const int phase = (int)((first + j) % ncol);
                 // features and scores once per sweep: every step of Alg. 2, the
                 // first phase of a sweep in colour mode
@@ -926,12 +963,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                     D.nwork = g->cstart[c + 1] - g->cstart[c];
                 }
                 if (o.profile && !ok(hipEventRecord(ev[2 * j], s))) return false;
-                hipError_t e;
-                if (regionMode == 4) e = mfd::launch_discharge_rows64(D, regionBlocks, regionLds, s);
-                else if (regionMode == 3) e = mfd::launch_discharge_rows(D, regionBlocks, regionLds, s);
-                else if (regionMode == 2) e = mfd::launch_discharge_wave(D, regionBlocks, regionLds, regionNarrow, s);
-                else if (regionMode == 1) e = mfd::launch_discharge_lds(D, regionBlocks, regionLds, regionNarrow, s);
-                else e = mfd::launch_discharge(D, g->nslots, g->threads, lds, s);
+                const hipError_t e = launch_region(g, RP, D, lds, s);
                 if (!ok(e)) return false;
                 if (o.profile && !ok(hipEventRecord(ev[2 * j + 1], s))) return false;
                 F.lab = labOut; F.actIn = g->act + p;
@@ -957,10 +989,19 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                 if (colored && !ok(mfd::launch_activity(G, g->ex, labOut, dinf, g->ractive,
                                                         g->act + (p ^ 1), s)))
                     return false;
+                // the labels after this step, row-major
+                if (o.label_trace && first + j < o.label_trace_cap &&
+                    !ok(mfd::launch_trace_labels(G, g->lab[0], g->lab[colored ? 0 : 1], g->counters,
+                                                 o.label_trace + (size_t)(first + j) * g->n, (int)g->n, s)))
+                    return false;
             }
             return true;
         };
-        if (use_graph) {
+        // never enqueue more steps than max_steps allows: each step raises the
+        // device counter at most once, so a solve stops at max_steps exactly
+        const long long room = max_steps - stepsDone;
+        const int count = (int)std::min<long long>(check_every, std::max<long long>(room, 1));
+        if (use_graph && count == check_every) {
             // a captured batch replays on any even first sweep: the buffers it
             // uses depend only on parity (labels may be swapped by relabels, so
             // the graph is rebuilt when their order changed)
@@ -973,7 +1014,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                 if (g->graph_exec) { (void)hipGraphExecDestroy(g->graph_exec); g->graph_exec = nullptr; }
                 hipGraph_t graph = nullptr;
                 HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                const bool enq = enqueue_batch(0);
+                const bool enq = enqueue_batch(0, check_every);
                 hipError_t ec = hipStreamEndCapture(s, &graph);
                 if (!enq || !ok(ec)) return MF_E_DEVICE;
                 hipError_t ei = hipGraphInstantiate(&g->graph_exec, graph, nullptr, nullptr, 0);
@@ -984,8 +1025,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
             HIP_TRY(hipGraphLaunch(g->graph_exec, s));
             sweep += check_every;
         } else {
-            if (!enqueue_batch(sweep)) return MF_E_DEVICE;
-            sweep += check_every;
+            if (!enqueue_batch(sweep, count)) return MF_E_DEVICE;
+            sweep += count;
         }
         const int p = (int)(sweep & 1);
         HIP_TRY(hipMemcpyAsync(g->pinned, g->act + p, sizeof(u64), hipMemcpyDeviceToHost, s));
@@ -995,13 +1036,14 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         if (o.profile) {
             // every discharge launch is timed, including those of the sweeps
             // enqueued after convergence (they exit at once)
-            for (int j = 0; j < check_every; j++) {
+            for (int j = 0; j < count; j++) {
                 float ms = 0.f;
                 HIP_TRY(hipEventElapsedTime(&ms, ev[2 * j], ev[2 * j + 1]));
                 discharge_ms += ms;
                 timed++;
             }
         }
+        stepsDone = (long long)g->pinned[1];
         if (*(int *)(g->pinned + 2) & 4) { status = MF_E_DEVICE; break; }
         if (g->pinned[0] == 0ull) break;
         if ((long long)g->pinned[1] >= max_steps) { status = MF_E_SWEEPS; break; }
@@ -1333,6 +1375,67 @@ extern "C" mf_status mf_get_state(const mf_grid *gc, int32_t *res, int32_t *rt, 
         for (int k = 0; k < g->K; k++)
             if (!one(g->res + (size_t)k * G.N, res + (size_t)k * n)) return MF_E_DEVICE;
     if (!one(g->rt, rt) || !one(g->ex, ex) || !one(g->lab[g->final_parity], labels)) return MF_E_DEVICE;
+    return MF_OK;
+}
+
+extern "C" mf_status mf_region_relabel(mf_grid *g, int32_t region_kernel, int64_t *regions_out) {
+    if (!g) return MF_E_INVAL;
+    if (!g->has_state || g->state_prd) return MF_E_STATE;
+    RegionPick RP;
+    {
+        const mf_status ps = pick_region(g, region_kernel, false, RP);
+        if (ps != MF_OK) return ps;
+    }
+    const Geo &G = g->G;
+    hipStream_t s = nullptr;
+    if (!g->defer && !ok(dalloc(&g->defer, (size_t)G.nreg))) return MF_E_NOMEM;
+    // every region is deferred with a relabel-only discharge: one complete
+    // search over the current state, labels written, no pushes
+    HIP_TRY(mfd::launch_fill_i32(g->defer, G.nreg, 1, s));
+    HIP_TRY(mfd::launch_fill_i32(g->ractive, G.nreg, 1, s));
+    HIP_TRY(hipMemsetAsync(g->qhead + 2, 0, sizeof(unsigned), s));
+    HIP_TRY(mfd::launch_fill_i32((int *)(g->act + 2), 2, 1, s));  // a non-zero count: the launch runs
+    HIP_TRY(hipMemsetAsync(g->stats, 0, 16 * sizeof(u64), s));
+    HIP_TRY(hipMemsetAsync(g->err, 0, sizeof(int), s));
+    mfd::DischargeArgs D;
+    memset(&D, 0, sizeof(D));
+    D.G = G;
+    D.res = g->res; D.rt = g->rt; D.ex = g->ex; D.pushb = g->pushb;
+    D.labOld = g->lab[g->final_parity];
+    D.labNew = g->lab[g->final_parity ^ 1];
+    D.ractive = g->ractive; D.order = g->order; D.nwork = G.nreg; D.qhead = g->qhead + 2;
+    D.actIn = g->act + 2; D.dinf = g->dinf; D.scratch = g->scratch;
+    D.ringL = g->ringL; D.ringM = g->ringM; D.nring = g->nring;
+    D.stats = g->stats; D.rvcount = g->rvcount; D.err = g->err;
+    D.useLDS = g->useLDS ? 1 : 0;
+    D.maxIter = 1 << 18;
+    D.defer = g->defer;
+    D.deferRelabel = 1;
+    D.sweepCount = g->counters;
+    const size_t lds = g->useLDS ? (size_t)16 * G.V : 0;
+    HIP_TRY(launch_region(g, RP, D, lds, s));
+    const int *lab = g->lab[g->final_parity ^ 1];
+    // the regions' activity flags from the new labels
+    HIP_TRY(hipMemsetAsync(g->ractive, 0, sizeof(int) * G.nreg, s));
+    HIP_TRY(hipMemsetAsync(g->act + 2, 0, sizeof(u64), s));
+    HIP_TRY(mfd::launch_activity(G, g->ex, lab, g->dinf, g->ractive, g->act + 2, s));
+    u64 st[16];
+    int err = 0;
+    HIP_TRY(hipMemcpy(st, g->stats, sizeof(st), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&err, g->err, sizeof(int), hipMemcpyDeviceToHost));
+    if (err & 4) return MF_E_DEVICE;
+    g->final_parity ^= 1;
+    if (regions_out) *regions_out = (int64_t)st[11];
+    return MF_OK;
+}
+
+extern "C" mf_status mf_global_relabel(mf_grid *g, int64_t *levels_out) {
+    if (!g) return MF_E_INVAL;
+    if (!g->has_state || g->state_prd) return MF_E_STATE;
+    const int lv = global_relabel(g, g->lab[g->final_parity], g->act + 2, nullptr);
+    if (lv < 0) return MF_E_DEVICE;
+    HIP_TRY(hipStreamSynchronize(nullptr));
+    if (levels_out) *levels_out = lv;
     return MF_OK;
 }
 

@@ -147,10 +147,11 @@ __global__ __launch_bounds__(NT) void k_discharge_lds(DischargeArgs A) {
         const int base = r * V;
         if (tid == 0) {
             s_active = A.ractive[r];
-            // a deferred region keeps its flag and is discharged in a later sweep
+            // a deferred region keeps its flag and is discharged in a later sweep;
+            // with deferRelabel it runs its region relabel now (s_active 2)
             if (s_active && A.defer && A.defer[r]) {
-                s_active = 0;
-                if (A.actCarry) atomicAdd(A.actCarry, 1ull);  // still active
+                s_active = A.deferRelabel ? 2 : 0;
+                if (!s_active && A.actCarry) atomicAdd(A.actCarry, 1ull);  // still active
             } else {
                 A.ractive[r] = 0;
             }
@@ -196,7 +197,10 @@ __global__ __launch_bounds__(NT) void k_discharge_lds(DischargeArgs A) {
         int nsteps = 0;
         // partial discharge: the searches of the push rounds stop at the stage
         // cap; the labels come from a complete search (full)
-        bool full = !A.partial;
+        // region relabel only (Alg. 3 on the current state, no pushes): one
+        // complete search, whose labels are written
+        const bool relabelOnly = s_active == 2;
+        bool full = !A.partial || relabelOnly;
         for (;;) {
             const long long t_round = wall_clock64();
             bool capped = false;
@@ -354,6 +358,7 @@ __global__ __launch_bounds__(NT) void k_discharge_lds(DischargeArgs A) {
             __syncthreads();
             const long long t_mid = wall_clock64();
             t_search += t_mid - t_round;
+            if (relabelOnly) break;
             if (!s_found) {
                 if (capped) {
                     full = true;  // search again, complete, for the region relabel
@@ -470,7 +475,9 @@ __global__ __launch_bounds__(NT) void k_discharge_lds(DischargeArgs A) {
             atomicAdd((unsigned long long *)&s_tr[3], (u64)lsum);
         }
         __syncthreads();
-        if (tid == 0) {
+        if (tid == 0 && relabelOnly) {
+            atomicAdd(&A.stats[11], 1ull);
+        } else if (tid == 0) {
             atomicAdd(&A.stats[0], 1ull);
             if (A.regionTicks) A.regionTicks[r] = (int)min(wall_clock64() - t_start, 0x7fffffffLL);
             atomicAdd(&A.stats[1], (u64)A.rvcount[r]);

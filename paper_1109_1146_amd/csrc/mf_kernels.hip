@@ -192,10 +192,11 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
         const int base = r * V;
         if (tid == 0) {
             s_active = A.ractive[r];
-            // a deferred region keeps its flag and is discharged in a later sweep
+            // a deferred region keeps its flag and is discharged in a later sweep;
+            // with deferRelabel it runs its region relabel now (s_active 2)
             if (s_active && A.defer && A.defer[r]) {
-                s_active = 0;
-                if (A.actCarry) atomicAdd(A.actCarry, 1ull);  // still active
+                s_active = A.deferRelabel ? 2 : 0;
+                if (!s_active && A.actCarry) atomicAdd(A.actCarry, 1ull);  // still active
             } else {
                 A.ractive[r] = 0;
             }
@@ -214,14 +215,17 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
         if (tid < 4) s_tr[tid] = 0;
         // partial discharge: the searches of the push rounds stop at the stage
         // cap; the labels come from a complete search (full)
-        bool full = !A.partial;
+        // region relabel only (Alg. 3 on the current state, no pushes): one
+        // complete search, whose labels are written
+        const bool relabelOnly = s_active == 2;
+        bool full = !A.partial || relabelOnly;
         bool firstSearch = true, lastComplete = false;
         for (;;) {
             bool capped = false, early = false;
             // a push-round search stops once every live excess vertex is labelled;
             // the search whose labels are written must be complete (with partial
             // discharges that is the full one after the capped rounds)
-            const bool earlyOk = !(A.partial && full);
+            const bool earlyOk = !(A.partial && full) && !relabelOnly;
             // ---------------- multi-level search from the targets ----------------
             if (tid == 0) {
                 s_qtail = 0;
@@ -475,6 +479,7 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
             bfs_steps += s_nsteps;
             firstSearch = false;
             lastComplete = !early && !capped;
+            if (relabelOnly) break;
             // ---------------- any excess vertex that reaches a target? ----------------
             int found = 0;
             if (early) {
@@ -627,7 +632,9 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
             atomicAdd((unsigned long long *)&s_tr[3], (u64)lsum);
         }
         __syncthreads();
-        if (tid == 0) {
+        if (tid == 0 && relabelOnly) {
+            atomicAdd(&A.stats[11], 1ull);
+        } else if (tid == 0) {
             atomicAdd(&A.stats[0], 1ull);
             if (A.regionTicks) A.regionTicks[r] = (int)min(wall_clock64() - t_start, 0x7fffffffLL);
             atomicAdd(&A.stats[1], (u64)A.rvcount[r]);
@@ -976,6 +983,19 @@ __global__ void k_gather_plane(Geo G, const int *src, int *dst, int n) {
     dst[v] = src[grid_to_blocked(G, z, y, x)];
 }
 
+// Label trace of one step: the labels of the last step that ran.  Step k of a
+// solve writes buffer (k + 1) & 1 and the step counter counts the steps that
+// ran, so the current labels are in buffer (count & 1), also after steps that
+// found no active vertex and exited at once (one buffer: lab0 == lab1).
+__global__ void k_trace_labels(Geo G, const int *lab0, const int *lab1,
+                               const unsigned long long *count, int *dst, int n) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int *src = (*count & 1ull) ? lab1 : lab0;
+    int x = v % G.dx, t = v / G.dx, y = t % G.dy, z = t / G.dy;
+    dst[v] = src[grid_to_blocked(G, z, y, x)];
+}
+
 // Residual reachability by region floods: each workgroup floods its region
 // from the marked vertices, marks across the region border and flags the
 // neighbouring region for the next round.  dir 0: forward from the excess
@@ -1164,6 +1184,12 @@ hipError_t launch_sum_i32(const int *a, int n, unsigned long long *out, hipStrea
 
 hipError_t launch_gather_plane(const Geo &G, const int *src, int *dst, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_gather_plane, dim3(cdiv(n, 256)), dim3(256), 0, s, G, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_labels(const Geo &G, const int *lab0, const int *lab1,
+                               const unsigned long long *count, int *dst, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_trace_labels, dim3(cdiv(n, 256)), dim3(256), 0, s, G, lab0, lab1, count, dst, n);
     return hipGetLastError();
 }
 

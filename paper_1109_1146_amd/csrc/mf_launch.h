@@ -31,7 +31,7 @@ struct DischargeArgs {
     int sweep;           // sweep index of this launch
     const int *defer;    // optional: 1 = an active region is deferred this sweep (keeps its flag)
     int *regionTicks;    // optional: duration of each region's last discharge (100 MHz ticks)
-    int deferRelabel;    // a deferred region runs its region relabel only (rows and wave kernels)
+    int deferRelabel;    // a deferred region runs its region relabel only (Alg. 3, no pushes)
     // Partial discharges (Sec. 6.2): sweep s runs only the stages k <= s, s read
     // from sweepCount (the completed sweeps, so a captured graph replays it
     // right); the region relabel stays complete.  Excess may then stay inside a
@@ -234,6 +234,8 @@ hipError_t launch_gap_find(const GapArgs &A, hipStream_t s);
 hipError_t launch_gap_apply(const GapApplyArgs &A, hipStream_t s);
 hipError_t launch_sum_i32(const int *a, int n, unsigned long long *out, hipStream_t s);
 hipError_t launch_gather_plane(const Geo &G, const int *src, int *dst, int n, hipStream_t s);
+hipError_t launch_trace_labels(const Geo &G, const int *lab0, const int *lab1,
+                               const unsigned long long *count, int *dst, int n, hipStream_t s);
 hipError_t launch_flood(const FloodArgs &A, int blocks, hipStream_t s);
 hipError_t launch_flood_wave(const FloodArgs &A, int blocks, hipStream_t s);
 hipError_t launch_flood_rows(const FloodArgs &A, int blocks, hipStream_t s);

@@ -30,7 +30,8 @@ EXPORTED = ("mf_create_grid", "mf_set_caps", "mf_solve", "mf_flow_value", "mf_mi
             "mf_status_str", "mf_create_batch", "mf_batch_info", "mf_batch_set_caps",
             "mf_batch_flow_values", "mf_batch_min_cut", "mf_model_create", "mf_model_destroy",
             "mf_model_num_params", "mf_model_get_params", "mf_model_set_params", "mf_model_forward",
-            "mf_model_loss_grad", "mf_model_adam_step", "mf_boundary_relabel")
+            "mf_model_loss_grad", "mf_model_adam_step", "mf_boundary_relabel", "mf_region_relabel",
+            "mf_global_relabel")
 
 
 class mf_solve_opts(ctypes.Structure):
@@ -43,7 +44,8 @@ class mf_solve_opts(ctypes.Structure):
                 ("max_defer", ctypes.c_int32), ("defer_threshold", ctypes.c_float),
                 ("defer_mode", ctypes.c_int32), ("features", ctypes.c_void_p),
                 ("features_cap", ctypes.c_int64), ("partial", ctypes.c_int32),
-                ("boundary_relabel", ctypes.c_int32), ("method", ctypes.c_int32)]
+                ("boundary_relabel", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("label_trace", ctypes.c_void_p), ("label_trace_cap", ctypes.c_int64)]
 
 
 class mf_solve_stats(ctypes.Structure):
@@ -103,6 +105,10 @@ def load(path: str = LIB_PATH):
     lib.mf_get_state.restype = ctypes.c_int
     lib.mf_boundary_relabel.argtypes = [P, ctypes.c_int32, P]
     lib.mf_boundary_relabel.restype = ctypes.c_int
+    lib.mf_region_relabel.argtypes = [P, ctypes.c_int32, P]
+    lib.mf_region_relabel.restype = ctypes.c_int
+    lib.mf_global_relabel.argtypes = [P, P]
+    lib.mf_global_relabel.restype = ctypes.c_int
     lib.mf_get_info.argtypes = [P, P, P, P, P, P]
     lib.mf_get_info.restype = ctypes.c_int
     lib.mf_discharge_bytes_per_vertex.argtypes = [ctypes.c_int32]
@@ -234,12 +240,14 @@ class Grid:
               max_sweeps=0, stream=None, profile=False, region_kernel=MF_KERNEL_AUTO,
               trace=None, graph=False, model=None, max_defer=0, defer_threshold=0.0,
               features=None, defer_mode=0, partial=False, boundary_relabel=0,
-              method=MF_METHOD_ARD):
+              method=MF_METHOD_ARD, label_trace=None):
         """trace: optional int32 device tensor of shape (cap, TRACE_FIELDS);
         partial: partial discharges (sweep s runs the stages k <= s only);
         boundary_relabel: n > 0 runs the boundary relabel heuristic after every
         sweep with at most n levels of its search;
-        method: MF_METHOD_ARD or MF_METHOD_PRD (push-relabel region discharge)."""
+        method: MF_METHOD_ARD or MF_METHOD_PRD (push-relabel region discharge);
+        label_trace: optional int32 device tensor of shape (cap, n): the labels
+        after every step."""
         tptr, tcap = None, 0
         if trace is not None:
             tptr, tcap = trace.data_ptr(), int(trace.shape[0])
@@ -253,7 +261,9 @@ class Grid:
                           graph=1 if graph else 0, max_defer=max_defer,
                           defer_threshold=defer_threshold, defer_mode=defer_mode, features=fptr,
                           features_cap=fcap, partial=1 if partial else 0,
-                          boundary_relabel=int(boundary_relabel), method=int(method))
+                          boundary_relabel=int(boundary_relabel), method=int(method),
+                          label_trace=label_trace.data_ptr() if label_trace is not None else None,
+                          label_trace_cap=int(label_trace.shape[0]) if label_trace is not None else 0)
         if model is not None:
             o.model = model._h
         s = mf_solve_stats()
@@ -279,6 +289,21 @@ class Grid:
         P = lambda a: ctypes.c_void_p(a.ctypes.data)
         _check(load().mf_get_state(self._h, P(res), P(rt), P(ex), P(lab)), "mf_get_state")
         return dict(res=res, rt=rt, ex=ex, labels=lab)
+
+    def region_relabel(self, region_kernel=MF_KERNEL_AUTO):
+        """Region relabel (Alg. 3) of every region on the state of the last solve;
+        returns the number of regions relabelled."""
+        n = ctypes.c_int64()
+        _check(load().mf_region_relabel(self._h, int(region_kernel), ctypes.byref(n)),
+               "mf_region_relabel")
+        return int(n.value)
+
+    def global_relabel(self):
+        """Exact region-distance relabel on the state of the last solve; returns
+        the number of level launches."""
+        n = ctypes.c_int64()
+        _check(load().mf_global_relabel(self._h, ctypes.byref(n)), "mf_global_relabel")
+        return int(n.value)
 
     def boundary_relabel(self, max_levels=1 << 30):
         """Boundary relabel heuristic on the state of the last solve (also one

@@ -92,3 +92,65 @@ def region_chain_instance(L, w, excess=10, big=1000):
     inst.cs[::w] = excess
     inst.name = f"regionchain_{L}x{w}"
     return inst
+
+
+def boundary_mask(inst, tile):
+    """Geometric boundary set B (Sec. 4.1): vertices with a grid neighbour in
+    another region, zero-capacity arcs included."""
+    pu, pv, _, _ = oracle.grid_pairs(inst.dims, inst.nbr, synth.offsets_for(len(inst.dims), inst.conn))
+    region = oracle.grid_regions(inst.dims, tile)
+    cross = region[pu] != region[pv]
+    b = np.zeros(inst.n, bool)
+    b[pu[cross]] = True
+    b[pv[cross]] = True
+    return b
+
+
+def region_distance(n, pu, pv, r_uv, r_vu, region, rt, dinf):
+    """Exact d*B (Sec. 4.1), capped at dinf: the distance to t in the residual
+    network where an arc between regions has length 1 and an arc inside a
+    region length 0.  Shortest paths from t on the reversed residual arcs
+    (scipy's Dijkstra), with length-0 arcs given a weight far below 1 / n."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import dijkstra
+    pu = np.asarray(pu, np.int64)
+    pv = np.asarray(pv, np.int64)
+    eps = 1e-9
+    inter = (np.asarray(region)[pu] != np.asarray(region)[pv])
+    w = np.where(inter, 1.0, eps)
+    rows, cols, wts = [], [], []
+    m = np.asarray(r_uv) > 0          # arc pu -> pv: reversed edge pv -> pu
+    rows.append(pv[m]); cols.append(pu[m]); wts.append(w[m])
+    m = np.asarray(r_vu) > 0          # arc pv -> pu: reversed edge pu -> pv
+    rows.append(pu[m]); cols.append(pv[m]); wts.append(w[m])
+    tv = np.flatnonzero(np.asarray(rt) > 0)
+    rows.append(np.full(tv.size, n)); cols.append(tv); wts.append(np.full(tv.size, eps))
+    A = csr_matrix((np.concatenate(wts), (np.concatenate(rows), np.concatenate(cols))),
+                   shape=(n + 1, n + 1))
+    d = dijkstra(A, directed=True, indices=n)[:n]
+    out = np.full(n, dinf, np.int64)
+    fin = np.isfinite(d)
+    out[fin] = np.minimum(np.floor(d[fin] + 1e-3).astype(np.int64), dinf)
+    return out
+
+
+def assert_valid_labels(pu, pv, r_uv, r_vu, region, rt, d, bmask, dinf, lifted=False):
+    """Validity of Sec. 4.1 on every residual arc (d(u) <= d(v) + length, length
+    1 between regions and 0 inside one) and d = 0 wherever r_t > 0.  The solver
+    raises only boundary labels in the global gap, and so does the boundary
+    relabel (interior labels are recomputed by the region's next discharge
+    before anything reads them): an arc from a boundary vertex labelled dinf to
+    an interior vertex of its region is not checked, nor, with lifted (the
+    boundary relabel on), any arc from a boundary vertex to an interior vertex
+    of its region."""
+    pu = np.asarray(pu, np.int64)
+    pv = np.asarray(pv, np.int64)
+    d = np.asarray(d, np.int64)
+    ln = (region[pu] != region[pv]).astype(np.int64)
+    for tail, head, res in ((pu, pv, r_uv), (pv, pu, r_vu)):
+        m = np.asarray(res) > 0
+        bad = m & (d[tail] > d[head] + ln)
+        into_interior = (ln == 0) & bmask[tail] & ~bmask[head]
+        bad &= ~(into_interior & ((d[tail] == dinf) | lifted))
+        assert not bad.any(), f"{int(bad.sum())} residual arcs violate d(u) <= d(v) + |(u,v)|"
+    assert (d[np.asarray(rt) > 0] == 0).all(), "a vertex with a residual t-link has d > 0"

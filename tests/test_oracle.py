@@ -624,3 +624,82 @@ def test_region_reduction_single_region_decides_everything():
     want = np.where(smin, oracle.REDUCE_STRONG_SOURCE,
                     np.where(~smax, oracle.REDUCE_STRONG_SINK, both)).astype(np.uint8)
     assert (cls == want).all()
+
+
+# ---------------------------------------------------------------------------
+# Region relabel (Alg. 3) on a given state
+# ---------------------------------------------------------------------------
+
+def _alg3_brute(n, pu, pv, r_uv, r_vu, rt, region, labels, dinf):
+    """The definition of the region relabel, vertex by vertex: the smallest
+    stage k such that u reaches T_k in its region network (forward search from u
+    over residual arcs inside the region)."""
+    from collections import deque
+    out_arcs = [[] for _ in range(n)]
+    for a, b, x, y in zip(pu, pv, r_uv, r_vu):
+        if x > 0:
+            out_arcs[a].append(b)
+        if y > 0:
+            out_arcs[b].append(a)
+    res = np.full(n, dinf, np.int64)
+    for u in range(n):
+        seen = {u}
+        q = deque([u])
+        best = dinf
+        while q:
+            x = q.popleft()
+            if rt[x] > 0:
+                best = 0
+                break
+            for w in out_arcs[x]:
+                if region[w] != region[x]:
+                    if labels[w] < dinf:
+                        best = min(best, int(labels[w]) + 1)
+                elif w not in seen:
+                    seen.add(w)
+                    q.append(w)
+        res[u] = min(best, dinf)
+    return res
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_region_relabel_against_its_definition(seed):
+    """oracle.region_relabel (Alg. 3 steps) equals the definition evaluated
+    vertex by vertex, on states left by the reference ARD after one or two
+    sweeps and on random residual states with random labels."""
+    cases = [((9, 11), 4, (3, 4)), ((8, 8), 8, (4, 4)), ((4, 5, 6), 6, (2, 3, 3)), ((12, 7), 4, (5, 7))]
+    dims, conn, tile = cases[seed % len(cases)]
+    inst = synth.random_grid(dims, conn, 2600 + seed, tile=tile)
+    pu, pv, cuv, cvu = oracle.grid_pairs(inst.dims, inst.nbr, synth.offsets_for(len(dims), conn))
+    region = oracle.grid_regions(dims, tile)
+    rng = np.random.default_rng(seed)
+    dinf = 1 + int(rng.integers(3, 30))
+    if seed % 2:
+        a = oracle.ard_grid(inst, tile=tile, max_sweeps=1 + seed % 3, stop_early=True)
+        r_uv, r_vu, rt, labels = a["r_uv"], a["r_vu"], a["rt"], np.minimum(a["labels"], dinf)
+    else:
+        r_uv = cuv * (rng.random(cuv.size) < 0.7)
+        r_vu = cvu * (rng.random(cvu.size) < 0.7)
+        rt = inst.ct * (rng.random(inst.n) < 0.15)
+        labels = rng.integers(0, dinf + 1, inst.n)
+    got = oracle.region_relabel(inst.n, pu, pv, r_uv, r_vu, rt, region, labels, dinf)
+    want = _alg3_brute(inst.n, pu, pv, r_uv, r_vu, rt, region, labels, dinf)
+    assert (got == want).all()
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_region_distance_helpers_agree(seed):
+    """The tests' two computations of d*B (0-1 breadth-first search, and
+    Dijkstra with near-zero weights for the arcs inside a region) agree on the
+    states the reference ARD leaves."""
+    from tests.helpers import region_distance
+    cases = [((9, 11), 4, (3, 4)), ((8, 8), 8, (4, 4)), ((4, 5, 6), 6, (2, 3, 3))]
+    dims, conn, tile = cases[seed % len(cases)]
+    inst = synth.random_grid(dims, conn, 2700 + seed, tile=tile)
+    pu, pv, _, _ = oracle.grid_pairs(inst.dims, inst.nbr, synth.offsets_for(len(dims), conn))
+    region = oracle.grid_regions(dims, tile)
+    a = oracle.ard_grid(inst, tile=tile, max_sweeps=1 + seed % 3, stop_early=True)
+    dinf = 50
+    d1 = _region_distance(inst.n, pu, pv, a["r_uv"], a["r_vu"], region, a["rt"], dinf)
+    d2 = region_distance(inst.n, pu, pv, a["r_uv"], a["r_vu"], region, a["rt"], dinf)
+    assert (d1 == d2).all()
