@@ -362,6 +362,17 @@ mf_status mf_model_forward(mf_model *m, const float *x, int32_t xs, int32_t D, i
 mf_status mf_model_loss_grad(mf_model *m, const float *x, int32_t xs, const float *target,
                              const float *mask, int32_t D, int32_t H, int32_t W, float *loss,
                              float *grads_out, void *stream);
+/* mf_model_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and result, with the hidden activations in a fixed 4 MiB device
+ * array of the library (one per GPU, kept until the process ends) instead of
+ * the model's workspace.  Allocates nothing.  Limit: 2 * channels * D * H * W
+ * <= 2^20 floats (32768 voxels with 16 channels), else MF_E_INVAL.  Every call
+ * on a GPU uses that GPU's array: calls that overlap on one GPU (other host
+ * threads, or other streams) race and must not run concurrently.
+ * Errors: MF_E_INVAL, MF_E_DEVICE. */
+mf_status mf_model_forward_noalloc(const mf_model *m, const float *x, int32_t xs, int32_t D, int32_t H,
+                                   int32_t W, float *logits, int32_t bf16, void *stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the last gradients. */
 mf_status mf_model_adam_step(mf_model *m, float lr, void *stream);
 

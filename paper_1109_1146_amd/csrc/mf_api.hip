@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <mutex>
 #include <vector>
 
 #include "mf.h"
@@ -489,15 +490,21 @@ extern "C" mf_status mf_model_set_params(mf_model *m, const float *host_in) {
     return MF_OK;
 }
 
-static hipError_t model_forward(mf_model *m, const float *x, int xs, int D, int H, int W, float *z,
-                                int bf16, hipStream_t s) {
+// The three convolutions, with the hidden activations in h1 and h2 (C floats per voxel each).
+static hipError_t model_forward_in(const mf_model *m, const float *x, int xs, int D, int H, int W, float *z,
+                                   int bf16, float *h1, float *h2, hipStream_t s) {
     const int C = m->C;
     const float *p = m->params;
-    hipError_t e = mfd::launch_conv3_fwd(x, xs, 3, p + m->off_w1, p + m->off_b1, C, m->h1, D, H, W, 1, bf16, 1, s);
+    hipError_t e = mfd::launch_conv3_fwd(x, xs, 3, p + m->off_w1, p + m->off_b1, C, h1, D, H, W, 1, bf16, 1, s);
     if (e != hipSuccess) return e;
-    e = mfd::launch_conv3_fwd(m->h1, C, C, p + m->off_w2, p + m->off_b2, C, m->h2, D, H, W, 1, bf16, 0, s);
+    e = mfd::launch_conv3_fwd(h1, C, C, p + m->off_w2, p + m->off_b2, C, h2, D, H, W, 1, bf16, 0, s);
     if (e != hipSuccess) return e;
-    return mfd::launch_conv3_fwd(m->h2, C, C, p + m->off_w3, p + m->off_b3, 1, z, D, H, W, 0, bf16, 0, s);
+    return mfd::launch_conv3_fwd(h2, C, C, p + m->off_w3, p + m->off_b3, 1, z, D, H, W, 0, bf16, 0, s);
+}
+
+static hipError_t model_forward(mf_model *m, const float *x, int xs, int D, int H, int W, float *z,
+                                int bf16, hipStream_t s) {
+    return model_forward_in(m, x, xs, D, H, W, z, bf16, m->h1, m->h2, s);
 }
 
 extern "C" mf_status mf_model_forward(mf_model *m, const float *x, int32_t xs, int32_t D, int32_t H,
@@ -505,6 +512,45 @@ extern "C" mf_status mf_model_forward(mf_model *m, const float *x, int32_t xs, i
     if (!m || !x || !logits || xs < 3 || D < 1 || H < 1 || W < 1) return MF_E_INVAL;
     if (!model_ws(m, D * H * W)) return MF_E_NOMEM;
     HIP_TRY(model_forward(m, x, xs, D, H, W, logits, bf16 ? 1 : 0, (hipStream_t)stream));
+    return MF_OK;
+}
+
+// ---- Scheduler inference without allocation ----
+// The hidden activations of mf_model_forward_noalloc live in a fixed device
+// array (4 MiB), one copy per GPU, held until the process ends and shared by
+// every call on that GPU.  Host code uses the array only through the address
+// hipGetSymbolAddress returns for the current device (taken once per device).
+constexpr size_t kNoAllocFloats = (size_t)1 << 20;
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+constexpr int kNoAllocDevices = 64;
+static std::mutex g_noalloc_mu;
+static float *g_noalloc_ptr[kNoAllocDevices] = {};
+
+static mf_status noalloc_scratch(float **out) {
+    int dev = 0;
+    if (!ok(hipGetDevice(&dev)) || dev < 0 || dev >= kNoAllocDevices) return MF_E_DEVICE;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        if (!ok(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) || !p) return MF_E_DEVICE;
+        g_noalloc_ptr[dev] = (float *)p;
+    }
+    *out = g_noalloc_ptr[dev];
+    return MF_OK;
+}
+
+extern "C" mf_status mf_model_forward_noalloc(const mf_model *m, const float *x, int32_t xs, int32_t D,
+                                              int32_t H, int32_t W, float *logits, int32_t bf16,
+                                              void *stream) {
+    if (!m || !x || !logits || xs < 3 || D < 1 || H < 1 || W < 1) return MF_E_INVAL;
+    const long long nv = (long long)D * H * W;
+    if (nv > (long long)(kNoAllocFloats / 2) / m->C) return MF_E_INVAL;  // two hidden layers must fit
+    float *ws = nullptr;
+    const mf_status st = noalloc_scratch(&ws);
+    if (st != MF_OK) return st;
+    // every activation is written before it is read: nothing to clear
+    HIP_TRY(model_forward_in(m, x, xs, D, H, W, logits, bf16 ? 1 : 0, ws, ws + (size_t)m->C * nv,
+                             (hipStream_t)stream));
     return MF_OK;
 }
 

@@ -31,7 +31,7 @@ EXPORTED = ("mf_create_grid", "mf_set_caps", "mf_solve", "mf_flow_value", "mf_mi
             "mf_batch_flow_values", "mf_batch_min_cut", "mf_model_create", "mf_model_destroy",
             "mf_model_num_params", "mf_model_get_params", "mf_model_set_params", "mf_model_forward",
             "mf_model_loss_grad", "mf_model_adam_step", "mf_boundary_relabel", "mf_region_relabel",
-            "mf_global_relabel")
+            "mf_global_relabel", "mf_model_forward_noalloc")
 
 
 class mf_solve_opts(ctypes.Structure):
@@ -140,6 +140,9 @@ def load(path: str = LIB_PATH):
     lib.mf_model_forward.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                      ctypes.c_int32, P, ctypes.c_int32, P]
     lib.mf_model_forward.restype = ctypes.c_int
+    lib.mf_model_forward_noalloc.argtypes = [P, P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_int32, P, ctypes.c_int32, P]
+    lib.mf_model_forward_noalloc.restype = ctypes.c_int
     lib.mf_model_loss_grad.argtypes = [P, P, ctypes.c_int32, P, P, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_float), P, P]
     lib.mf_model_loss_grad.restype = ctypes.c_int
@@ -415,6 +418,16 @@ class Model:
         _check(load().mf_model_forward(self._h, ctypes.c_void_p(x.data_ptr()), int(x.shape[1]), D, H, W,
                                        ctypes.c_void_p(out.data_ptr()), 1 if bf16 else 0,
                                        ctypes.c_void_p(stream) if stream else None), "forward")
+        return out
+
+    def forward_noalloc(self, x, out, dims, bf16=True, stream=None):
+        """mf_model_forward_noalloc: logits of the D*H*W grid x into the caller's
+        float32 tensor out, with no device allocation."""
+        D, H, W = dims
+        _check(load().mf_model_forward_noalloc(self._h, ctypes.c_void_p(x.data_ptr()), int(x.shape[1]), D, H, W,
+                                               ctypes.c_void_p(out.data_ptr()), 1 if bf16 else 0,
+                                               ctypes.c_void_p(stream) if stream else None),
+               "forward_noalloc")
         return out
 
     def loss_grad(self, x, target, mask, dims, want_grads=False, stream=None):
