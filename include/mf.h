@@ -296,6 +296,36 @@ mf_status mf_region_relabel(mf_grid *g, int32_t region_kernel, int64_t *regions_
  * Errors: MF_E_STATE (no state, or a state left by MF_METHOD_PRD), MF_E_DEVICE. */
 mf_status mf_global_relabel(mf_grid *g, int64_t *levels_out);
 
+/* Region reduction (Alg. 5, Sec. 8) of every region of the loaded instance: one
+ * class byte per vertex (row-major like dims), the OR of
+ *   MF_REDUCE_STRONG_SOURCE  in the source side of every minimum cut
+ *   MF_REDUCE_STRONG_SINK    in the sink side of every minimum cut
+ *   MF_REDUCE_WEAK_SOURCE    in the source side of some minimum cut
+ *   MF_REDUCE_WEAK_SINK      in the sink side of some minimum cut
+ * as Alg. 5 decides them from the region network alone (R, its boundary B^R
+ * without s- and t-links, the arcs touching R); a vertex none of them marks is
+ * undecided.  Alg. 5's single flow gives the classes of the two auxiliary
+ * problems the section starts from, each boundary vertex joined to t without
+ * bound (strong source = its minimal source side, weak source = its maximal
+ * minus its minimal source side) or supplied from s without bound (strong
+ * sink = outside its maximal source side, weak sink = its maximal minus its
+ * minimal source side); they are computed that way, for all regions at once:
+ * Init, a full discharge of every region with the boundary labels 0 (every
+ * residual boundary arc a target) or dinf after saturating every arc into the
+ * region, and a forward search from the remaining excess inside each region.
+ *   region_kernel  MF_KERNEL_* that runs the discharges (AUTO as for mf_solve)
+ *   out_class      [n] host array
+ * Overwrites the solver state (call mf_solve again before mf_flow_value,
+ * mf_min_cut or mf_get_state).  Errors: MF_E_STATE (no instance loaded),
+ * MF_E_INVAL (batch handle, kernel not applicable), MF_E_DEVICE. */
+enum {
+    MF_REDUCE_STRONG_SOURCE = 1,
+    MF_REDUCE_STRONG_SINK = 2,
+    MF_REDUCE_WEAK_SOURCE = 4,
+    MF_REDUCE_WEAK_SINK = 8
+};
+mf_status mf_region_reduction(mf_grid *g, int32_t region_kernel, uint8_t *out_class);
+
 /* Shape facts of a handle: number of vertices, K, regions, |B|, region shape. */
 mf_status mf_get_info(const mf_grid *g, int64_t *n, int32_t *K, int64_t *regions,
                       int64_t *boundary_size, int32_t *region_shape3);

@@ -21,7 +21,9 @@ What it computes (all integer, int64 accumulators):
   (P-PRD) or Alg. 1 (S-PRD), with the global gap over all labels and per-sweep
   checks of label validity and monotonicity.
 * ``region_reduction`` -- Alg. 5 (Sec. 8) on every region of a grid instance:
-  strong and weak source and sink nodes from three augmentations per region.
+  strong and weak source and sink nodes from three augmentations per region;
+  ``region_reduction_union`` the same classes for large grids from the two
+  auxiliary problems of the section, all regions in one network.
 * ``boundary_relabel`` -- the heuristic of Sec. 6.1 on a given state, written
   separately in Python (groups, the two kinds of arcs, Dijkstra by heapq).
 * ``region_relabel`` -- the region relabel of Alg. 3 of every region on a given
@@ -485,6 +487,43 @@ def region_reduction(inst, tile, big=1 << 28, augment="dinic"):
         c[other & (not_to_b == 1)] |= REDUCE_WEAK_SOURCE
         c[other & (from_b == 0)] |= REDUCE_WEAK_SINK
         cls[verts[rin]] = c[rin]
+    return cls
+
+
+def region_reduction_union(inst, tile):
+    """The classes of region_reduction for every region at once, from the two
+    auxiliary problems of Sec. 8 (each boundary vertex joined to t, or supplied
+    from s, without bound), for large grids.  In the auxiliary problem of region
+    R a boundary vertex w is a terminal, so an arc (u, w) leaving R acts as a
+    t-link of u of capacity c(u, w) (or an arc (w, u) entering R as an s-link of
+    u of capacity c(w, u)); the networks of all regions together are then one
+    network with every arc between regions replaced that way, whose components
+    are the regions.  Two textbook max flows (push-relabel) give the extremal
+    cuts: strong source = minimal source side with boundary sinks, weak source =
+    maximal minus minimal there; strong sink = outside the maximal source side
+    with boundary sources, weak sink = maximal minus minimal there.  Pinned
+    against the steps of Alg. 5 (region_reduction) in the tests."""
+    pu, pv, cuv, cvu = grid_pairs(inst.dims, inst.nbr, _offsets(inst))
+    region = grid_regions(inst.dims, tile)
+    cross = region[pu] != region[pv]
+    n = inst.n
+    cs = np.asarray(inst.cs, np.int64).copy()
+    ct = np.asarray(inst.ct, np.int64).copy()
+    out_t = np.zeros(n, np.int64)   # capacity of the arcs leaving each vertex's region
+    in_s = np.zeros(n, np.int64)    # capacity of the arcs entering it
+    np.add.at(out_t, pu[cross], cuv[cross].astype(np.int64))
+    np.add.at(out_t, pv[cross], cvu[cross].astype(np.int64))
+    np.add.at(in_s, pu[cross], cvu[cross].astype(np.int64))
+    np.add.at(in_s, pv[cross], cuv[cross].astype(np.int64))
+    keep = ~cross
+    a, b, c1, c2 = pu[keep], pv[keep], cuv[keep], cvu[keep]
+    nt = solve_pairs(n, a, b, c1, c2, cs, ct + out_t)
+    ns = solve_pairs(n, a, b, c1, c2, cs + in_s, ct)
+    cls = np.zeros(n, np.uint8)
+    cls[nt["smin"] == 1] |= REDUCE_STRONG_SOURCE
+    cls[(nt["smax"] == 1) & (nt["smin"] == 0)] |= REDUCE_WEAK_SOURCE
+    cls[ns["smax"] == 0] |= REDUCE_STRONG_SINK
+    cls[(ns["smax"] == 1) & (ns["smin"] == 0)] |= REDUCE_WEAK_SINK
     return cls
 
 

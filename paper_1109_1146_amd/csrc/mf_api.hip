@@ -1475,6 +1475,88 @@ extern "C" mf_status mf_region_relabel(mf_grid *g, int32_t region_kernel, int64_
     return MF_OK;
 }
 
+// One auxiliary problem of region reduction for every region at once: Init,
+// optionally every boundary vertex a source without bound (inflow), the halo
+// labels set to `halo` (0: every residual boundary arc is a target, so every
+// boundary vertex is a sink without bound; dinf: only t is a target), one full
+// discharge of every region, then the in-region forward search from the
+// remaining excess.  Adds the problem's class bits to g->cand.
+static mf_status reduction_pass(mf_grid *g, const RegionPick &RP, bool inflow, int halo) {
+    const Geo &G = g->G;
+    hipStream_t s = nullptr;
+    HIP_TRY(hipMemsetAsync(g->act, 0, 4 * sizeof(u64), s));
+    HIP_TRY(hipMemsetAsync(g->qhead, 0, 4 * sizeof(unsigned), s));
+    HIP_TRY(hipMemsetAsync(g->counters, 0, 4 * sizeof(u64), s));
+    HIP_TRY(hipMemsetAsync(g->stats, 0, 16 * sizeof(u64), s));
+    HIP_TRY(mfd::launch_init(G, g->in_cs, g->in_ct, g->in_nbr, (int)g->n, g->res, g->rt, g->ex, g->lab[0],
+                             g->lab[1], g->pushb, g->ractive, g->act, s));
+    if (inflow) HIP_TRY(mfd::launch_saturate_inflow(G, g->in_nbr, (int)g->n, g->res, g->ex, s));
+    HIP_TRY(mfd::launch_fill_i32(g->lab[0], G.N, halo, s));
+    HIP_TRY(mfd::launch_fill_i32(g->ractive, G.nreg, 1, s));
+    HIP_TRY(mfd::launch_fill_i32((int *)(g->act + 2), 2, 1, s));  // a non-zero count: the launch runs
+    mfd::DischargeArgs D;
+    memset(&D, 0, sizeof(D));
+    D.G = G;
+    D.res = g->res; D.rt = g->rt; D.ex = g->ex; D.pushb = g->pushb;
+    D.labOld = g->lab[0]; D.labNew = g->lab[1];
+    D.ractive = g->ractive; D.order = g->order; D.nwork = G.nreg; D.qhead = g->qhead + 2;
+    D.actIn = g->act + 2; D.dinf = g->dinf; D.scratch = g->scratch;
+    D.ringL = g->ringL; D.ringM = g->ringM; D.nring = g->nring;
+    D.stats = g->stats; D.rvcount = g->rvcount; D.err = g->err;
+    D.useLDS = g->useLDS ? 1 : 0;
+    D.maxIter = 1 << 18;
+    D.sweepCount = g->counters;
+    const size_t lds = g->useLDS ? (size_t)16 * G.V : 0;
+    HIP_TRY(launch_region(g, RP, D, lds, s));
+    // minimal source side of the auxiliary problem: forward from the excess,
+    // inside each region (the boundary vertices are terminals there)
+    HIP_TRY(hipMemsetAsync(g->mark, 0, sizeof(int) * (size_t)G.N, s));
+    mfd::FloodArgs A;
+    memset(&A, 0, sizeof(A));
+    A.G = G;
+    A.dir = 0;
+    A.round = 0;
+    A.noCross = 1;
+    A.mark = g->mark;
+    A.res = g->res; A.ex = g->ex; A.rt = g->rt;
+    A.scratch = g->scratch;
+    A.changed = g->changed;
+    A.dirtyIn = g->dirty;
+    A.dirtyOut = g->dirty + G.nreg;
+    A.ringL = g->ringL; A.ringM = g->ringM; A.nring = g->nring;
+    HIP_TRY(mfd::launch_flood(A, std::min(G.nreg, g->nslots * 4), s));  // scratch holds 4V ints per slot
+    HIP_TRY(mfd::launch_reduce_classes(G, g->lab[1], g->mark, g->cand, g->dinf, inflow ? 1 : 0, s));
+    return MF_OK;
+}
+
+extern "C" mf_status mf_region_reduction(mf_grid *g, int32_t region_kernel, uint8_t *out_class) {
+    if (!g || !out_class) return MF_E_INVAL;
+    if (g->batch) return MF_E_INVAL;
+    if (!g->has_caps) return MF_E_STATE;
+    RegionPick RP;
+    {
+        const mf_status ps = pick_region(g, region_kernel, false, RP);
+        if (ps != MF_OK) return ps;
+    }
+    // the passes overwrite the solver state
+    g->solved = false;
+    g->has_state = false;
+    g->cut_kind_cached = -1;
+    hipStream_t s = nullptr;
+    HIP_TRY(hipMemsetAsync(g->err, 0, sizeof(int), s));
+    mf_status st = reduction_pass(g, RP, false, 0);  // every boundary vertex a sink
+    if (st != MF_OK) return st;
+    st = reduction_pass(g, RP, true, g->dinf);  // every boundary vertex a source
+    if (st != MF_OK) return st;
+    HIP_TRY(mfd::launch_gather_bytes(g->G, g->cand, g->cutbuf, (int)g->n, s));
+    HIP_TRY(hipMemcpyAsync(out_class, g->cutbuf, (size_t)g->n, hipMemcpyDeviceToHost, s));
+    int err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, g->err, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (err & 4) return MF_E_DEVICE;
+    return MF_OK;
+}
+
 extern "C" mf_status mf_global_relabel(mf_grid *g, int64_t *levels_out) {
     if (!g) return MF_E_INVAL;
     if (!g->has_state || g->state_prd) return MF_E_STATE;

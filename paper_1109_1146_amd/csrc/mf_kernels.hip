@@ -1039,7 +1039,7 @@ __global__ __launch_bounds__(NT) void k_flood(FloodArgs A) {
                         int w = local_nbr(G, vz, vy, vx, k);
                         if (w >= 0) {
                             if (atomicExch(&A.mark[base + w], 1) == 0) Q[atomicAdd(&s_qtail, 1)] = w;
-                        } else {
+                        } else if (!A.noCross) {
                             int wg = cross_nbr(G, r, vz, vy, vx, k);
                             if (wg >= 0 && atomicExch(&A.mark[wg], 1) == 0) {
                                 A.dirtyOut[wg / V] = 1;
@@ -1052,7 +1052,7 @@ __global__ __launch_bounds__(NT) void k_flood(FloodArgs A) {
                         if (w >= 0) {
                             if (A.res[(size_t)k * N + base + w] > 0 && atomicExch(&A.mark[base + w], 1) == 0)
                                 Q[atomicAdd(&s_qtail, 1)] = w;
-                        } else {
+                        } else if (!A.noCross) {
                             int wg = cross_nbr(G, r, vz, vy, vx, k ^ 1);
                             if (wg >= 0 && A.res[(size_t)k * N + wg] > 0 && atomicExch(&A.mark[wg], 1) == 0) {
                                 A.dirtyOut[wg / V] = 1;
@@ -1067,6 +1067,65 @@ __global__ __launch_bounds__(NT) void k_flood(FloodArgs A) {
             __syncthreads();
         }
     }
+}
+
+// Region reduction (Alg. 5, Sec. 8): the auxiliary problem with every boundary
+// vertex a source without bound, for every region at once.  After Init, each
+// vertex u with a neighbour w in another region takes the whole capacity
+// c(w, u) into its excess, and its residual c_f(u, w) becomes c(u, w) + c(w, u).
+// Each thread changes only its own vertex, and a region discharge never reads
+// the residuals of arcs entering its region, so every region sees its own
+// network.
+__global__ void k_saturate_inflow(Geo G, const int *nbr, int n, int *res, int *ex) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G.N; g += gridDim.x * blockDim.x) {
+        int z, y, x;
+        if (!blocked_to_grid(G, g, z, y, x)) continue;
+        const int r = g / G.V;
+        const int v = (z * G.dy + y) * G.dx + x;
+        int add = 0;
+        for (int k = 0; k < G.K; k++) {
+            const int wz = z + G.oz[k], wy = y + G.oy[k], wx = x + G.ox[k];
+            if ((unsigned)wz >= (unsigned)G.dz || (unsigned)wy >= (unsigned)G.dy || (unsigned)wx >= (unsigned)G.dx)
+                continue;
+            if (grid_to_blocked(G, wz, wy, wx) / G.V == r) continue;
+            const int w = (wz * G.dy + wy) * G.dx + wx;
+            const int cwu = nbr[(size_t)(k ^ 1) * n + w];
+            add += cwu;
+            res[(size_t)k * G.N + g] = nbr[(size_t)k * n + v] + cwu;
+        }
+        ex[g] += add;
+    }
+}
+
+// Class bits of one auxiliary problem from its maximum preflow: the region
+// labels (dinf = reaches no target) and the marks of the in-region forward
+// search from the excess vertices (the minimal source side).
+__global__ void k_reduce_classes(Geo G, const int *lab, const int *mark, unsigned char *cls, int dinf,
+                                 int sinkSide) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G.N; g += gridDim.x * blockDim.x) {
+        const bool reached = mark[g] != 0, noTarget = lab[g] >= dinf;
+        unsigned c = sinkSide ? cls[g] : 0u;
+        if (!sinkSide) {
+            // boundary joined to t: strong source = minimal source side; weak
+            // source = maximal minus minimal source side
+            if (reached) c |= 1u;
+            if (noTarget && !reached) c |= 4u;
+        } else {
+            // boundary supplied from s: strong sink = outside the maximal source
+            // side; weak sink = maximal minus minimal source side
+            if (!noTarget) c |= 2u;
+            if (noTarget && !reached) c |= 8u;
+        }
+        cls[g] = (unsigned char)c;
+    }
+}
+
+// blocked bytes -> row-major bytes
+__global__ void k_gather_bytes(Geo G, const unsigned char *src, unsigned char *out, int n) {
+    int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int x = v % G.dx, t = v / G.dx, y = t % G.dy, z = t / G.dy;
+    out[v] = src[grid_to_blocked(G, z, y, x)];
 }
 
 // blocked marks -> row-major source-side indicator
@@ -1190,6 +1249,25 @@ hipError_t launch_gather_plane(const Geo &G, const int *src, int *dst, int n, hi
 hipError_t launch_trace_labels(const Geo &G, const int *lab0, const int *lab1,
                                const unsigned long long *count, int *dst, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_trace_labels, dim3(cdiv(n, 256)), dim3(256), 0, s, G, lab0, lab1, count, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_saturate_inflow(const Geo &G, const int *nbr, int n, int *res, int *ex, hipStream_t s) {
+    hipLaunchKernelGGL(k_saturate_inflow, dim3(std::min(cdiv(G.N, 256), kCountBlocks)), dim3(256), 0, s, G,
+                       nbr, n, res, ex);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_classes(const Geo &G, const int *lab, const int *mark, unsigned char *cls,
+                                 int dinf, int sinkSide, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_classes, dim3(std::min(cdiv(G.N, 256), kCountBlocks)), dim3(256), 0, s, G,
+                       lab, mark, cls, dinf, sinkSide);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_bytes(const Geo &G, const unsigned char *src, unsigned char *out, int n,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_bytes, dim3(cdiv(n, 256)), dim3(256), 0, s, G, src, out, n);
     return hipGetLastError();
 }
 

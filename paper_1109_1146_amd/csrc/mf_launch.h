@@ -146,6 +146,7 @@ struct FloodArgs {
     const int *ringL;            // tile border list (row-bitmask flood)
     const unsigned char *ringM;
     int nring;
+    int noCross;  // generic flood only: search inside each region, mark nothing across its border
 };
 
 struct GRelabelArgs {
@@ -239,6 +240,11 @@ hipError_t launch_trace_labels(const Geo &G, const int *lab0, const int *lab1,
 hipError_t launch_flood(const FloodArgs &A, int blocks, hipStream_t s);
 hipError_t launch_flood_wave(const FloodArgs &A, int blocks, hipStream_t s);
 hipError_t launch_flood_rows(const FloodArgs &A, int blocks, hipStream_t s);
+hipError_t launch_saturate_inflow(const Geo &G, const int *nbr, int n, int *res, int *ex, hipStream_t s);
+hipError_t launch_reduce_classes(const Geo &G, const int *lab, const int *mark, unsigned char *cls,
+                                 int dinf, int sinkSide, hipStream_t s);
+hipError_t launch_gather_bytes(const Geo &G, const unsigned char *src, unsigned char *out, int n,
+                               hipStream_t s);
 hipError_t launch_cut_out(const Geo &G, const int *mark, unsigned char *out, int n, int invert,
                           hipStream_t s);
 hipError_t launch_fill_i32(int *p, int n, int val, hipStream_t s);

@@ -20,6 +20,7 @@ MF_CUT_MIN_SOURCE, MF_CUT_MAX_SOURCE = 0, 1
 MF_SCHED_PARD, MF_SCHED_COLORED, MF_SCHED_LEARNED, MF_SCHED_AUTO, MF_SCHED_LEARNED_COLORED = 0, 1, 2, 3, 4
 MF_KERNEL_AUTO, MF_KERNEL_HBM, MF_KERNEL_LDS, MF_KERNEL_WAVE, MF_KERNEL_ROWS, MF_KERNEL_ROWS64 = 0, 1, 2, 3, 4, 5
 MF_METHOD_ARD, MF_METHOD_PRD = 0, 1
+MF_REDUCE_STRONG_SOURCE, MF_REDUCE_STRONG_SINK, MF_REDUCE_WEAK_SOURCE, MF_REDUCE_WEAK_SINK = 1, 2, 4, 8
 TRACE_FIELDS = 10
 FEATURES = 6
 TRACE_NAMES = ("sweep", "region", "rounds", "levels", "stages", "ticks", "excess_in", "to_sink",
@@ -31,7 +32,7 @@ EXPORTED = ("mf_create_grid", "mf_set_caps", "mf_solve", "mf_flow_value", "mf_mi
             "mf_batch_flow_values", "mf_batch_min_cut", "mf_model_create", "mf_model_destroy",
             "mf_model_num_params", "mf_model_get_params", "mf_model_set_params", "mf_model_forward",
             "mf_model_loss_grad", "mf_model_adam_step", "mf_boundary_relabel", "mf_region_relabel",
-            "mf_global_relabel", "mf_model_forward_noalloc")
+            "mf_global_relabel", "mf_model_forward_noalloc", "mf_region_reduction")
 
 
 class mf_solve_opts(ctypes.Structure):
@@ -107,6 +108,8 @@ def load(path: str = LIB_PATH):
     lib.mf_boundary_relabel.restype = ctypes.c_int
     lib.mf_region_relabel.argtypes = [P, ctypes.c_int32, P]
     lib.mf_region_relabel.restype = ctypes.c_int
+    lib.mf_region_reduction.argtypes = [P, ctypes.c_int32, P]
+    lib.mf_region_reduction.restype = ctypes.c_int
     lib.mf_global_relabel.argtypes = [P, P]
     lib.mf_global_relabel.restype = ctypes.c_int
     lib.mf_get_info.argtypes = [P, P, P, P, P, P]
@@ -300,6 +303,14 @@ class Grid:
         _check(load().mf_region_relabel(self._h, int(region_kernel), ctypes.byref(n)),
                "mf_region_relabel")
         return int(n.value)
+
+    def region_reduction(self, region_kernel=MF_KERNEL_AUTO):
+        """Region reduction (Alg. 5) of every region of the loaded instance: one
+        class byte per vertex (MF_REDUCE_* bits); overwrites the solver state."""
+        out = np.zeros(self.n, dtype=np.uint8)
+        _check(load().mf_region_reduction(self._h, int(region_kernel), ctypes.c_void_p(out.ctypes.data)),
+               "mf_region_reduction")
+        return out
 
     def global_relabel(self):
         """Exact region-distance relabel on the state of the last solve; returns

@@ -703,3 +703,17 @@ def test_region_distance_helpers_agree(seed):
     d1 = _region_distance(inst.n, pu, pv, a["r_uv"], a["r_vu"], region, a["rt"], dinf)
     d2 = region_distance(inst.n, pu, pv, a["r_uv"], a["r_vu"], region, a["rt"], dinf)
     assert (d1 == d2).all()
+
+
+def test_region_reduction_union_matches_alg5():
+    """The all-regions-at-once form (two textbook max flows over the regions
+    with their arcs to other regions turned into terminal links) gives the
+    classes of Alg. 5's steps on every case of the fuzz family and on blob
+    grids."""
+    for seed in range(300):
+        dims, conn, tile = RR_FUZZ[seed % len(RR_FUZZ)]
+        inst = synth.random_grid(dims, conn, 5000 + seed)
+        assert (oracle.region_reduction_union(inst, tile) == oracle.region_reduction(inst, tile)).all(), seed
+    for seed, (dims, conn, tile) in enumerate(RR_CASES):
+        inst = synth.blob_grid(dims, conn, 2150 + seed, 4, 3.0, 9.0, zero_frac=0.1)
+        assert (oracle.region_reduction_union(inst, tile) == oracle.region_reduction(inst, tile)).all()
