@@ -233,18 +233,29 @@ def test_hbm_kernel_large_regions_1024_threads(mf, case):
 
 
 def test_full_size_464_certified(mf):
-    """The 464^3 workload (10^8 vertices, 64^3 regions) is too
-    large for the oracle's solver inside a test; its state is certified at full
-    size instead, from the original capacities: residuals feasible, conservation,
-    flow = sum (c_t - r_t), both returned cuts of cost equal to the flow
-    (max-flow/min-cut duality, Sec. 2), and both cuts equal to the oracle's
-    residual reachability on the returned state."""
+    """The 464^3 workload (10^8 vertices, 64^3 regions): the flow and both cuts
+    equal the oracle's result on the whole instance (stored: the oracle takes
+    minutes and tens of GB for it), and the state is certified at full size from
+    the original capacities: residuals feasible, conservation, flow = sum (c_t -
+    r_t), both returned cuts of cost equal to the flow (max-flow/min-cut
+    duality, Sec. 2), and both cuts equal to the oracle's residual reachability
+    on the returned state."""
     import time
     t0 = time.perf_counter()
     inst = synth.config(4)
     out = mf.solve_instance(inst, global_relabel_every=4, max_sweeps=100000)
     print(f"{inst.name}: flow {out['flow']} sweeps {out['stats']['sweeps']} "
           f"({time.perf_counter() - t0:.0f} s with the generator)", flush=True)
+    assert out["stats"]["region_kernel"] == mf.MF_KERNEL_ROWS64
+    # the oracle's result on the whole instance, stored by tests/golden/make_grid3d6_464.py
+    import hashlib
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "grid3d6_464_oracle.json")) as f:
+        ref = json.load(f)
+    assert out["flow"] == ref["flow"]
+    assert hashlib.sha256(out["smin"].astype(np.uint8).tobytes()).hexdigest() == ref["smin_sha256"]
+    assert hashlib.sha256(out["smax"].astype(np.uint8).tobytes()).hexdigest() == ref["smax_sha256"]
     certify_solver_state(inst, out)
     print(f"certified ({time.perf_counter() - t0:.0f} s)", flush=True)
 
