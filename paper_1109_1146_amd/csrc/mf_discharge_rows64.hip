@@ -49,8 +49,9 @@ constexpr int kNT = 512;                // threads per workgroup
 constexpr int kW = kNT / 64;            // waves
 constexpr int kRPT = 8;                 // rows per thread
 constexpr int kMaxRows = kNT * kRPT;    // 4096
-constexpr int kListAll = 4096;          // work-list entries per pass (whole workgroup)
+constexpr int kListAll = 2048;          // work-list entries per pass (whole workgroup)
 constexpr int kInFlight = 4;            // push vertices per lane with loads issued together
+constexpr int kRingBatch = 8;           // border vertices per thread with loads issued together
 
 // Per-workgroup scratch in HBM (byte offsets).
 struct R64Scratch {
@@ -99,6 +100,15 @@ __device__ __forceinline__ int r64_block_min(int v, int (*red)[kW], int &rc) {
     return m;
 }
 
+// Workgroup barrier that orders LDS only: the global stores and atomics issued
+// before it (admissible arcs, labels) need not have completed, since nothing
+// reads them before a full barrier.
+__device__ __forceinline__ void r64_lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ int r64_incl_scan(int v, int lane) {
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -108,13 +118,31 @@ __device__ __forceinline__ int r64_incl_scan(int v, int lane) {
     return v;
 }
 
-// A uniform pointer the compiler must treat as redefined here: keeps it from
-// hoisting per-row addresses out of the loops (they would stay live in
+// Global-memory pointers: the scratch and label accesses stay global (not flat)
+// instructions, so that the waits for LDS results never wait on them.
+#define GA __attribute__((address_space(1)))
+
+// A uniform global pointer the compiler must treat as redefined here: keeps it
+// from hoisting per-row addresses out of the loops (they would stay live in
 // registers across the whole discharge).
 template <typename T>
-__device__ __forceinline__ T *r64_opaque(T *p) {
+__device__ __forceinline__ GA T *r64_opaque(T *p) {
+    GA T *q = (GA T *)p;
+    asm volatile("" : "+s"(q));
+    return q;
+}
+template <typename T>
+__device__ __forceinline__ GA T *r64_opaque(GA T *p) {
     asm volatile("" : "+s"(p));
     return p;
+}
+
+// Non-returning relaxed atomics on global words.
+__device__ __forceinline__ void g_or(GA u64 *p, u64 v) {
+    __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void g_and(GA u64 *p, u64 v) {
+    __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Labels val for the set bits of one row per lane (slot rows rowBase + lane),
@@ -122,7 +150,7 @@ __device__ __forceinline__ T *r64_opaque(T *p) {
 // every row is one coalesced store however many of its bits are set.  Called
 // with all lanes active; lab is the region's first label.
 __device__ __forceinline__ void r64_store_labels(int *lab, int rowBase, u64 bits, int val, int lane) {
-    int *b = r64_opaque(lab);
+    GA int *b = r64_opaque(lab);
     u64 pend = __ballot(bits != 0ull);
     while (pend) {
         const int l = __builtin_ctzll(pend);
@@ -148,7 +176,7 @@ __device__ __forceinline__ int r64_axis_dir(unsigned mm, int a) {
 constexpr int kFaceWords = 2 * 2 * kW * 64;
 
 size_t discharge_rows64_bytes(int ty, int tz) {
-    return ((size_t)kFaceWords + (size_t)3 * ty * tz) * 8 + (size_t)kListAll * 4;
+    return ((size_t)kFaceWords + (size_t)4 * ty * tz) * 8 + (size_t)kListAll * 4;
 }
 
 size_t rows64_scratch_bytes(int ty, int tz, int nring) { return r64_scratch(ty * tz, nring).total; }
@@ -191,14 +219,15 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
     u64 *recvB = smem64 + kFaceWords;      // [R] received excess (push); visited rows (search)
     u64 *clrB = recvB + R;                 // [R] drained (push); stage seeds (search)
     u64 *deadB = clrB + R;                 // [R] not reached by the last complete search
-    unsigned *wlist = (unsigned *)(deadB + R);  // [kListAll]
+    u64 *stuckB = deadB + R;               // [R] excess vertices with no admissible arc left (push)
+    unsigned *wlist = (unsigned *)(stuckB + R);  // [kListAll]
     const R64Scratch S = r64_scratch(R, A.nring);
     unsigned char *ws = (unsigned char *)A.scratch + (size_t)blockIdx.x * 16 * (size_t)V;
-    u64 *resG = (u64 *)(ws + S.resG);
-    u64 *rtG = (u64 *)(ws + S.rtG);
-    int *haloG = (int *)(ws + S.halo);
-    int *slotC = (int *)(ws + S.slot);
-    u64 *admG = (u64 *)(ws + S.adm);
+    GA u64 *resG = (GA u64 *)(ws + S.resG);
+    GA u64 *rtG = (GA u64 *)(ws + S.rtG);
+    GA int *haloG = (GA int *)(ws + S.halo);
+    GA int *slotC = (GA int *)(ws + S.slot);
+    GA u64 *admG = (GA u64 *)(ws + S.adm);
     const int dinf = A.dinf;
     const int nring = A.nring;
     // row of slot j of this thread: y = lane, z = 8 wid + j
@@ -303,11 +332,45 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
         for (;;) {
             // ---------------- multi-level search from the targets ----------------
             const long long t0s = wall_clock64();
+            // stage candidate of each border vertex: smallest d(w) + 1 over its
+            // residual boundary arcs (fixed during a search)
+            // (eight border vertices per thread at a time, their loads issued together)
+            for (int i0 = tid; i0 < nring; i0 += kNT * kRingBatch) {
+                int ll[kRingBatch], hh[kRingBatch][3];
+                unsigned mmb[kRingBatch];
+                u64 rr[kRingBatch][3];
+#pragma unroll
+                for (int b = 0; b < kRingBatch; b++) {
+                    const int i = i0 + b * kNT;
+                    const bool in = i < nring;
+                    ll[b] = in ? A.ringL[i] : 0;
+                    mmb[b] = in ? A.ringM[i] : 0u;
+#pragma unroll
+                    for (int a = 0; a < 3; a++) hh[b][a] = in ? haloG[3 * i + a] : kInf;
+                }
+#pragma unroll
+                for (int b = 0; b < kRingBatch; b++)
+#pragma unroll
+                    for (int a = 0; a < 3; a++)
+                        rr[b][a] = ((mmb[b] >> (2 * a)) & 3u)
+                                       ? resG[(size_t)r64_axis_dir(mmb[b], a) * R + (ll[b] >> 6)] : 0ull;
+#pragma unroll
+                for (int b = 0; b < kRingBatch; b++) {
+                    const int i = i0 + b * kNT;
+                    if (i >= nring) continue;
+                    const u64 bit = 1ull << (ll[b] & 63);
+                    int c = kInf;
+#pragma unroll
+                    for (int a = 0; a < 3; a++)
+                        if ((rr[b][a] & bit) && hh[b][a] < dinf) c = min(c, hh[b][a] + 1);
+                    slotC[i] = c;
+                }
+            }
             int cnt = 0;  // this thread's live excess vertices not labelled yet
             {
-                const u64 *rg = r64_opaque(resG);
-                const u64 *tg = r64_opaque(rtG);
-                u64 *ag = r64_opaque(admG);
+                const GA u64 *rg = r64_opaque(resG);
+                const GA u64 *tg = r64_opaque(rtG);
+                GA u64 *ag = r64_opaque(admG);
 #pragma unroll
                 for (int j = 0; j < kRPT; j++) {
                     const int row = row0 + 64 * j;
@@ -325,24 +388,6 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
             if (writeMode) {
 #pragma unroll
                 for (int j = 0; j < kRPT; j++) r64_store_labels(A.labNew + base, 64 * (kRPT * wid + j), F[j], 0, lane);
-            }
-            // stage candidate of each border vertex: smallest d(w) + 1 over its
-            // residual boundary arcs (fixed during a search)
-            for (int i = tid; i < nring; i += kNT) {
-                const int l = A.ringL[i];
-                const unsigned mm = A.ringM[i];
-                const int rw = l >> 6;
-                const u64 bit = 1ull << (l & 63);
-                int c = kInf;
-#pragma unroll
-                for (int a = 0; a < 3; a++) {
-                    if (!((mm >> (2 * a)) & 3u)) continue;
-                    const int k = r64_axis_dir(mm, a);
-                    if (!(resG[(size_t)k * R + rw] & bit)) continue;
-                    const int d = haloG[3 * i + a];
-                    if (d < dinf) c = min(c, d + 1);
-                }
-                slotC[i] = c;
             }
             int p = 0;
             int stage = 0;
@@ -362,7 +407,7 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                         const int f = ((b != 0ull) ? 1 : 0) | ((e != 0ull) ? 2 : 0);
                         if (lane == 0 && f) atomicOr(&s_flood[fl], f);
                     }
-                    __syncthreads();
+                    r64_lds_barrier();
                     const int any = s_flood[fl];
                     if (tid == 0) s_flood[fl == 0 ? 2 : fl - 1] = 0;  // the word of level l + 2
                     fl = fl == 2 ? 0 : fl + 1;
@@ -373,48 +418,51 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                     if (!(any & 1)) break;
                     levels++;
                     // z = 8w - 1 (top face of the wave below) and z = 8w + 8 (bottom face of the wave above)
-                    u64 *admL = r64_opaque(admG);
+                    GA u64 *admL = r64_opaque(admG);
                     u64 prev = wid > 0 ? zF[((p * 2 + 1) * kW + wid - 1) * 64 + lane] : 0ull;
                     const u64 above = wid < kW - 1 ? zF[((p * 2 + 0) * kW + wid + 1) * 64 + lane] : 0ull;
-                    // slots with work, uniform over the wave: a slot's own frontier rows or
-                    // those of its z neighbours (its y neighbours are lanes of this wave)
-                    unsigned act = 0u;
+                    // Pass 1, every slot without branches (the eight slots are
+                    // independent, so their instructions interleave): the new
+                    // vertices nw of each row, u with c_f(u, u + o_k) > 0 and
+                    // u + o_k in the frontier (y +- 1 from the neighbouring lanes,
+                    // z +- 1 from the neighbouring slots or waves).
+                    u64 old[kRPT];
 #pragma unroll
-                    for (int j = 0; j < kRPT; j++) act |= (__ballot(F[j] != 0ull) != 0ull ? 1u : 0u) << j;
-                    act |= (act << 1) | (act >> 1);
-                    if (__ballot(prev != 0ull) != 0ull) act |= 1u;
-                    if (__ballot(above != 0ull) != 0ull) act |= 1u << (kRPT - 1);
+                    for (int j = 0; j < kRPT; j++) old[j] = F[j];
 #pragma unroll
                     for (int j = 0; j < kRPT; j++) {
-                        const u64 cur = F[j];
-                        const u64 fzp = j < kRPT - 1 ? F[j + 1] : above;  // not yet updated
-                        const u64 fzm = prev;
-                        if (!((act >> j) & 1u)) {
-                            // no frontier bit in this slot or next to it in any lane
-                            prev = cur;
-                            continue;
-                        }
+                        const u64 cur = old[j];
+                        const u64 fzp = j < kRPT - 1 ? old[j + 1] : above;
+                        const u64 fzm = j > 0 ? old[j - 1] : prev;
                         const u64 fyp = r64_from_next_lane(cur), fym = r64_from_prev_lane(cur);
-                        prev = cur;
-                        F[j] = 0ull;
-                        if (!(cur | fyp | fym | fzp | fzm)) continue;
-                        const u64 t0 = rk[j][0] & (cur >> 1), t1 = rk[j][1] & (cur << 1);
-                        const u64 t2 = rk[j][2] & fyp, t3 = rk[j][3] & fym;
-                        const u64 t4 = rk[j][4] & fzp, t5 = rk[j][5] & fzm;
-                        const u64 nw = ~vis[j] & (t0 | t1 | t2 | t3 | t4 | t5);
+                        const u64 reach = (rk[j][0] & (cur >> 1)) | (rk[j][1] & (cur << 1)) | (rk[j][2] & fyp) |
+                                          (rk[j][3] & fym) | (rk[j][4] & fzp) | (rk[j][5] & fzm);
+                        F[j] = reach & ~vis[j];
+                        vis[j] |= F[j];
+                    }
+                    // Pass 2, slots with new vertices in some lane: the arcs by which
+                    // the new vertices were reached are their admissible arcs
+#pragma unroll
+                    for (int j = 0; j < kRPT; j++) {
+                        const u64 nw = F[j];
+                        if (__ballot(nw != 0ull) == 0ull) continue;
+                        const u64 cur = old[j];
+                        const u64 fzp = j < kRPT - 1 ? old[j + 1] : above;
+                        const u64 fzm = j > 0 ? old[j - 1] : prev;
+                        const u64 fyp = r64_from_next_lane(cur), fym = r64_from_prev_lane(cur);
                         if (!nw) continue;
                         const int row = row0 + 64 * j;
-                        F[j] = nw;
-                        vis[j] |= nw;
                         if (nw & exM[j]) cnt -= __popcll(nw & exM[j] & ~deadB[row]);
-                        // the arcs by which the new vertices were reached: their admissible arcs
-                        u64 *ad = admL + (unsigned)row;
-                        if (nw & t0) atomicOr(ad, nw & t0);
-                        if (nw & t1) atomicOr(ad + R, nw & t1);
-                        if (nw & t2) atomicOr(ad + 2 * R, nw & t2);
-                        if (nw & t3) atomicOr(ad + 3 * R, nw & t3);
-                        if (nw & t4) atomicOr(ad + 4 * R, nw & t4);
-                        if (nw & t5) atomicOr(ad + 5 * R, nw & t5);
+                        GA u64 *ad = admL + (unsigned)row;
+                        const u64 t0 = nw & rk[j][0] & (cur >> 1), t1 = nw & rk[j][1] & (cur << 1);
+                        const u64 t2 = nw & rk[j][2] & fyp, t3 = nw & rk[j][3] & fym;
+                        const u64 t4 = nw & rk[j][4] & fzp, t5 = nw & rk[j][5] & fzm;
+                        if (t0) g_or(ad, t0);
+                        if (t1) g_or(ad + R, t1);
+                        if (t2) g_or(ad + 2 * R, t2);
+                        if (t3) g_or(ad + 3 * R, t3);
+                        if (t4) g_or(ad + 4 * R, t4);
+                        if (t5) g_or(ad + 5 * R, t5);
                     }
                     if (writeMode) {
 #pragma unroll
@@ -432,15 +480,23 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                 for (int j = 0; j < kRPT; j++) recvB[row0 + 64 * j] = vis[j];
                 __syncthreads();
                 int cand = kInf;
-                for (int i = tid; i < nring; i += kNT) {
-                    const int c = slotC[i];
-                    if (c == kInf) continue;
-                    const int l = A.ringL[i];
-                    if ((recvB[l >> 6] >> (l & 63)) & 1ull) {
-                        slotC[i] = kInf;  // labelled: no longer a seed candidate in this search
-                        continue;
+                for (int i0 = tid; i0 < nring; i0 += kNT * kRingBatch) {
+                    int cc[kRingBatch], ll[kRingBatch];
+#pragma unroll
+                    for (int b = 0; b < kRingBatch; b++) {
+                        const int i = i0 + b * kNT;
+                        cc[b] = i < nring ? slotC[i] : kInf;
+                        ll[b] = i < nring ? A.ringL[i] : 0;
                     }
-                    cand = min(cand, c);
+#pragma unroll
+                    for (int b = 0; b < kRingBatch; b++) {
+                        if (cc[b] == kInf) continue;
+                        if ((recvB[ll[b] >> 6] >> (ll[b] & 63)) & 1ull) {
+                            slotC[i0 + b * kNT] = kInf;  // labelled: no longer a seed candidate in this search
+                            continue;
+                        }
+                        cand = min(cand, cc[b]);
+                    }
                 }
                 const int level = r64_block_min(cand, red, rc);
                 // partial discharge: stages above the cap wait for later sweeps
@@ -450,8 +506,14 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                 }
                 stages++;
                 stage = level;
-                for (int i = tid; i < nring; i += kNT) {
-                    if (slotC[i] != level) continue;
+                for (int i0 = tid; i0 < nring; i0 += kNT * kRingBatch) {
+                  int cc[kRingBatch];
+#pragma unroll
+                  for (int b = 0; b < kRingBatch; b++) cc[b] = (i0 + b * kNT < nring) ? slotC[i0 + b * kNT] : kInf;
+#pragma unroll
+                  for (int b = 0; b < kRingBatch; b++) {
+                    const int i = i0 + b * kNT;
+                    if (cc[b] != level) continue;
                     const int l = A.ringL[i];
                     const unsigned mm = A.ringM[i];
                     const int rw = l >> 6;
@@ -468,9 +530,10 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                     // the candidate came from one of these boundary arcs
 #pragma unroll
                     for (int k = 0; k < 6; k++)
-                        if ((match >> k) & 1u) atomicOr(&admG[(size_t)k * R + rw], bit);
+                        if ((match >> k) & 1u) g_or(admG + (size_t)k * R + rw, bit);
                     slotC[i] = kInf;
                     atomicOr(&clrB[rw], bit);  // seeds (clr is all zero during a search)
+                  }
                 }
                 __syncthreads();
 #pragma unroll
@@ -524,7 +587,10 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
             // ---------------- push along admissible arcs until nothing moves ----------------
             // recv held the visited rows: clear it for the pushes (clr is zero)
 #pragma unroll
-            for (int j = 0; j < kRPT; j++) recvB[row0 + 64 * j] = 0ull;
+            for (int j = 0; j < kRPT; j++) {
+                recvB[row0 + 64 * j] = 0ull;
+                stuckB[row0 + 64 * j] = 0ull;
+            }
             __syncthreads();
             // Push from excess vertex u (local index) along its admissible arcs, with
             // its t-link bits, admissible-arc byte, excess and residuals loaded.
@@ -540,8 +606,13 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                 // a vertex with a residual t-link was a stage-0 seed: t is its only admissible arc
                 const bool tseed = (rtw & bit) != 0ull;
                 const unsigned a = tseed ? 0u : a0;
-                if (!tseed && !a) return 0;  // every admissible arc saturated: waits for the next search
+                if (!tseed && !a) {
+                    // every admissible arc saturated: out of the lists until the next search
+                    atomicOr(&stuckB[row], bit);
+                    return 0;
+                }
                 int rem = e;
+                bool left = false;  // admissible arcs left after the pushes
                 if (tseed) {
                     const int d = min(rem, cT);
                     if (d > 0) {
@@ -549,7 +620,8 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                         rem -= d;
                         if (A.trace) atomicAdd((unsigned long long *)&s_tr[1], (u64)d);
                     }
-                    if (cT == d) atomicAnd(&rtG[row], ~bit);  // no admissible arc left
+                    if (cT == d) g_and(rtG + row, ~bit);  // no admissible arc left
+                    left = cT > d;
                 } else {
                     const int y = row & 63, z = row >> 6;
 #pragma unroll
@@ -570,17 +642,20 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                                 const u64 vbit = 1ull << (v & 63);
                                 atomicAdd(&A.res[(size_t)(k ^ 1) * N + gv], d);
                                 atomicAdd(&A.ex[gv], d);
-                                atomicOr(&resG[(size_t)(k ^ 1) * R + (v >> 6)], vbit);
+                                g_or(resG + (size_t)(k ^ 1) * R + (v >> 6), vbit);
                                 atomicOr(&recvB[v >> 6], vbit);
                             }
                             rem -= d;
                         }
                         if (c[k] == d) {
-                            atomicAnd(&admG[(size_t)k * R + row], ~bit);
-                            atomicAnd(&resG[(size_t)k * R + row], ~bit);
+                            g_and(admG + (size_t)k * R + row, ~bit);
+                            g_and(resG + (size_t)k * R + row, ~bit);
+                        } else {
+                            left = true;
                         }
                     }
                 }
+                if (rem > 0 && !left) atomicOr(&stuckB[row], bit);
                 if (rem < e) {
                     // drained what it saw: cleared, unless a receipt in this
                     // iteration sets the bit again at the merge
@@ -595,8 +670,12 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                 // one workgroup-wide list of the reached excess vertices (a
                 // wave's rows may hold far more of them than another's)
                 int cntP = 0;
+                u64 sel[kRPT];
 #pragma unroll
-                for (int j = 0; j < kRPT; j++) cntP += __popcll(exM[j] & vis[j]);
+                for (int j = 0; j < kRPT; j++) {
+                    sel[j] = exM[j] & vis[j] & ~stuckB[row0 + 64 * j];
+                    cntP += __popcll(sel[j]);
+                }
                 const int incl = r64_incl_scan(cntP, lane);
                 if (lane == 63) s_wtot[wid] = incl;
                 __syncthreads();
@@ -612,7 +691,7 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                         int idx = first;
 #pragma unroll
                         for (int j = 0; j < kRPT; j++) {
-                            u64 m = exM[j] & vis[j];
+                            u64 m = sel[j];
                             const int row = row0 + 64 * j;
                             while (m) {
                                 const int x = __builtin_ctzll(m);
