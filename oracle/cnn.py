@@ -105,3 +105,43 @@ def loss_and_grad(p, x, t, m, C):
     ga1 = gh1 * (c["a1"] > 0)
     _, gw1, gb1 = conv3_backward(c["x"], q["w1"], ga1)
     return loss, pack(dict(w1=gw1, b1=gb1, w2=gw2, b2=gb2, w3=gw3, b3=gb3))
+
+
+def bf16_round(x):
+    """Round float32 values to bfloat16 (8 significant bits, ties to even),
+    kept as float32.  Written from the definition: split x = m * 2^e with
+    0.5 <= |m| < 1, scale the significand to 8 bits, round half to even
+    (np.rint), scale back.  Finite inputs."""
+    x = np.asarray(x, dtype=np.float32).astype(np.float64)
+    m, e = np.frexp(x)
+    return np.ldexp(np.rint(m * 256.0), e - 8).astype(np.float32)
+
+
+def conv3_bf16(x, w, b):
+    """The bf16 form of conv3: x and w are bfloat16 values (already rounded),
+    the bias is float32, and every sum is a float32 sum taken in one fixed
+    order: the bias, then the taps in TAPS order, and within a tap the input
+    channels in increasing order.  A product of two bfloat16 values is exact in
+    float32, so this order fixes every bit of the result."""
+    x = np.asarray(x, dtype=np.float32)
+    w = np.asarray(w, dtype=np.float32)
+    cout, cin = w.shape[0], w.shape[1]
+    y = np.empty(x.shape[:3] + (cout,), np.float32)
+    y[...] = np.asarray(b, dtype=np.float32)
+    for t, (dz, dy, dx) in enumerate(TAPS):
+        xs = _shift(x, dz, dy, dx)
+        for ci in range(cin):
+            y += xs[..., ci:ci + 1] * w[:, ci, t]
+    return y
+
+
+def forward_bf16(p, x, C):
+    """Logits of the bf16 inference path: inputs and weights rounded to
+    bfloat16, float32 sums (conv3_bf16), ReLU, and every layer's output
+    rounded to bfloat16."""
+    q = unpack(p, C)
+    r = lambda a: bf16_round(np.asarray(a, np.float32))
+    x = r(np.asarray(x, np.float32)[..., :3])
+    h1 = r(np.maximum(conv3_bf16(x, r(q["w1"]), q["b1"]), 0.0))
+    h2 = r(np.maximum(conv3_bf16(h1, r(q["w2"]), q["b2"]), 0.0))
+    return r(conv3_bf16(h2, r(q["w3"]), q["b3"]))[..., 0]
