@@ -410,6 +410,83 @@ mf_status mf_model_adam_step(mf_model *m, float lr, void *stream);
  * t-link and excess are read and written, its label is written. */
 int64_t mf_discharge_bytes_per_vertex(int32_t connectivity);
 
+/* ------------------------------------------------------------------------
+ * General networks in region pages (Sec. 5.3).
+ *
+ * Any network given as vertex pairs, with any partition into regions, solved
+ * by the same parallel region discharge (Alg. 2 with Proc. ARD, the region
+ * relabel of Alg. 3, the flow fusion of Alg. 2 and the global gap of Sec. 5.1).
+ * The splitter of Sec. 5.3 (host code inside mf_create_graph) numbers the
+ * vertices region by region and writes one page per region: the region's arcs
+ * with 32-bit offsets inside the page and its part of the preflow state.
+ * Pairs between two regions stay in a resident boundary table of
+ * O(|B| + |(B, B)|) words.  The pages either all live in HBM or are streamed:
+ * they stay in pinned host memory and pass through device_pages page slots,
+ * the next batch loaded while the current one is discharged (the streaming
+ * mode of Sec. 5.3, with host memory in the role of the disk).
+ * ------------------------------------------------------------------------ */
+typedef struct mf_graph mf_graph; /* opaque, owned by the library */
+
+typedef struct {
+    int64_t n, npairs;           /* vertices and pairs of the network */
+    int64_t regions;             /* 1 + the largest region number */
+    int64_t boundary_size;       /* |B|: vertices with a pair into another region; d_inf = max(|B|, 1) */
+    int64_t boundary_pairs;      /* pairs between two regions */
+    int64_t page_words;          /* int32 words per page slot (the largest region's page) */
+    int64_t device_pages;        /* page slots in device memory */
+    int32_t resident;            /* 1: every page lives in device memory */
+    int32_t max_region_vertices;
+} mf_graph_info;
+
+typedef struct {
+    int64_t max_sweeps;          /* guard; 0 = 2|B|^2 + 1 (the bound of Sec. 4.3-4.4) */
+    int32_t gap;                 /* global gap heuristic: 1 = on (the default with opts NULL), 0 = off */
+    int32_t check_every;         /* resident pages: sweeps enqueued between termination checks; 0 = 8 */
+} mf_graph_opts;
+
+typedef struct {
+    int64_t sweeps;              /* sweeps of Alg. 2 since the handle was created */
+    int64_t discharges, push_rounds, search_steps;  /* this call's region discharges and their work */
+    int64_t pages_in, pages_out; /* streamed pages: page loads and state write-backs of this call */
+    int64_t bytes_h2d, bytes_d2h;
+    double ms;                   /* device time of this call's sweeps (HIP events) */
+} mf_graph_stats;
+
+/* Build a handle for the network with n vertices and npairs pairs (host
+ * arrays, read during the call only): pair i joins pu[i] != pv[i] (both in
+ * [0, n)) with c(pu, pv) = cuv[i] and c(pv, pu) = cvu[i]; cs[v] = c(s, v) and
+ * ct[v] = c(v, t); all int32 >= 0; several pairs may join the same vertices.
+ * region[v] >= 0 is the region of v (any assignment), or region == NULL for
+ * regions of region_size consecutive vertex numbers.  device_pages: 0 (or at
+ * least the number of regions) keeps every page in device memory; 1 or more
+ * streams the pages through that many device page slots.  The initial preflow
+ * (Sec. 2: every s-link saturated, labels 0) is written into the pages.
+ * Errors: MF_E_INVAL (a vertex out of range, a pair joining a vertex to
+ * itself, a negative capacity or region, a page beyond 32-bit offsets, more
+ * than 2^30 pairs), MF_E_OVERFLOW (c(u, v) + c(v, u), or c(s, v) plus the
+ * capacities into v, above 2^31 - 1), MF_E_NOMEM, MF_E_DEVICE.  Validation
+ * comes before any device call. */
+mf_status mf_create_graph(int32_t n, int64_t npairs, const int32_t *pu, const int32_t *pv,
+                          const int32_t *cuv, const int32_t *cvu, const int32_t *cs, const int32_t *ct,
+                          const int32_t *region, int32_t region_size, int64_t device_pages,
+                          mf_graph **out);
+mf_status mf_graph_get_info(const mf_graph *g, mf_graph_info *info);
+/* Sweeps of Alg. 2 until no vertex is active (Sec. 4.4); the preflow is then
+ * maximum.  Synchronous.  opts may be NULL.  Errors: MF_E_SWEEPS (the guard
+ * was reached; the state stays and a later call continues), MF_E_DEVICE. */
+mf_status mf_graph_solve(mf_graph *g, const mf_graph_opts *opts, mf_graph_stats *stats);
+/* |f| = sum_v f(v, t) after a completed solve, else MF_E_STATE. */
+mf_status mf_graph_flow_value(const mf_graph *g, int64_t *out);
+/* One byte per vertex (host array of n) in the caller's numbering: 1 on the
+ * source side of the cut `kind` (MF_CUT_*), after a completed solve. */
+mf_status mf_graph_min_cut(mf_graph *g, int32_t kind, uint8_t *out_source_side);
+/* The state in the caller's numbering (host arrays, each may be NULL):
+ * residuals of both arcs of every pair, residual t-links, excesses and
+ * labels (int32 in [0, d_inf]). */
+mf_status mf_graph_state(mf_graph *g, int64_t *r_uv, int64_t *r_vu, int64_t *rt, int64_t *ex,
+                         int32_t *labels);
+void mf_graph_destroy(mf_graph *g);
+
 void mf_destroy(mf_grid *g);
 const char *mf_status_str(mf_status s);
 

@@ -6,7 +6,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libmfard.so")
-SOURCES = [os.path.join(PKG, "csrc", f) for f in ("mf_kernels.hip", "mf_discharge_lds.hip", "mf_discharge_wave.hip", "mf_discharge_rows.hip", "mf_discharge_rows64.hip", "mf_sched.hip", "mf_api.hip")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("mf_kernels.hip", "mf_discharge_lds.hip", "mf_discharge_wave.hip", "mf_discharge_rows.hip", "mf_discharge_rows64.hip", "mf_sched.hip", "mf_graph.hip", "mf_api.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

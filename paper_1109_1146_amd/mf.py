@@ -32,7 +32,9 @@ EXPORTED = ("mf_create_grid", "mf_set_caps", "mf_solve", "mf_flow_value", "mf_mi
             "mf_batch_flow_values", "mf_batch_min_cut", "mf_model_create", "mf_model_destroy",
             "mf_model_num_params", "mf_model_get_params", "mf_model_set_params", "mf_model_forward",
             "mf_model_loss_grad", "mf_model_adam_step", "mf_boundary_relabel", "mf_region_relabel",
-            "mf_global_relabel", "mf_model_forward_noalloc", "mf_region_reduction")
+            "mf_global_relabel", "mf_model_forward_noalloc", "mf_region_reduction",
+            "mf_create_graph", "mf_graph_get_info", "mf_graph_solve", "mf_graph_flow_value",
+            "mf_graph_min_cut", "mf_graph_state", "mf_graph_destroy")
 
 
 class mf_solve_opts(ctypes.Structure):
@@ -64,6 +66,24 @@ class mf_solve_stats(ctypes.Structure):
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class mf_graph_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("npairs", ctypes.c_int64), ("regions", ctypes.c_int64),
+                ("boundary_size", ctypes.c_int64), ("boundary_pairs", ctypes.c_int64),
+                ("page_words", ctypes.c_int64), ("device_pages", ctypes.c_int64),
+                ("resident", ctypes.c_int32), ("max_region_vertices", ctypes.c_int32)]
+
+
+class mf_graph_opts(ctypes.Structure):
+    _fields_ = [("max_sweeps", ctypes.c_int64), ("gap", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+class mf_graph_stats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("discharges", ctypes.c_int64),
+                ("push_rounds", ctypes.c_int64), ("search_steps", ctypes.c_int64),
+                ("pages_in", ctypes.c_int64), ("pages_out", ctypes.c_int64),
+                ("bytes_h2d", ctypes.c_int64), ("bytes_d2h", ctypes.c_int64), ("ms", ctypes.c_double)]
 
 
 class MFError(RuntimeError):
@@ -151,6 +171,21 @@ def load(path: str = LIB_PATH):
     lib.mf_model_loss_grad.restype = ctypes.c_int
     lib.mf_model_adam_step.argtypes = [P, ctypes.c_float, P]
     lib.mf_model_adam_step.restype = ctypes.c_int
+    lib.mf_create_graph.argtypes = [ctypes.c_int32, ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_int32,
+                                    ctypes.c_int64, ctypes.POINTER(P)]
+    lib.mf_create_graph.restype = ctypes.c_int
+    lib.mf_graph_get_info.argtypes = [P, ctypes.POINTER(mf_graph_info)]
+    lib.mf_graph_get_info.restype = ctypes.c_int
+    lib.mf_graph_solve.argtypes = [P, ctypes.POINTER(mf_graph_opts), ctypes.POINTER(mf_graph_stats)]
+    lib.mf_graph_solve.restype = ctypes.c_int
+    lib.mf_graph_flow_value.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+    lib.mf_graph_flow_value.restype = ctypes.c_int
+    lib.mf_graph_min_cut.argtypes = [P, ctypes.c_int32, P]
+    lib.mf_graph_min_cut.restype = ctypes.c_int
+    lib.mf_graph_state.argtypes = [P, P, P, P, P, P]
+    lib.mf_graph_state.restype = ctypes.c_int
+    lib.mf_graph_destroy.argtypes = [P]
+    lib.mf_graph_destroy.restype = None
     _lib = lib
     return lib
 
@@ -475,5 +510,94 @@ def solve_instance(inst, tile=None, **solve_kw):
         st = g.solve(**solve_kw)
         out = dict(flow=g.flow_value(), smin=g.min_cut(MF_CUT_MIN_SOURCE),
                    smax=g.min_cut(MF_CUT_MAX_SOURCE), stats=st, info=g.info())
+        out["state"] = g.state()
+    return out
+
+
+def _host_i32(a, n, what):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    if a.shape != (n,):
+        raise ValueError(f"{what} must have shape ({n},)")
+    return a
+
+
+class Graph:
+    """A general network in region pages (mf_create_graph ... mf_graph_destroy).
+
+    Pairs (pu, pv, cuv, cvu) and t-links (cs, ct) are host int32 arrays; region
+    is an int32 array of region numbers or None for blocks of region_size
+    consecutive vertices; device_pages 0 keeps every page in device memory,
+    k >= 1 streams them through k device page slots."""
+
+    def __init__(self, n, pu, pv, cuv, cvu, cs, ct, region=None, region_size=4096, device_pages=0):
+        lib = load()
+        n = int(n)
+        m = int(np.asarray(pu).shape[0])
+        arrs = [_host_i32(a, m, w) for a, w in ((pu, "pu"), (pv, "pv"), (cuv, "cuv"), (cvu, "cvu"))]
+        arrs += [_host_i32(a, n, w) for a, w in ((cs, "cs"), (ct, "ct"))]
+        reg = None if region is None else _host_i32(region, n, "region")
+        self.n, self.npairs = n, m
+        h = ctypes.c_void_p()
+        ptrs = [ctypes.c_void_p(a.ctypes.data) for a in arrs]
+        _check(lib.mf_create_graph(n, m, *ptrs, ctypes.c_void_p(reg.ctypes.data) if reg is not None else None,
+                                   int(region_size), int(device_pages), ctypes.byref(h)), "mf_create_graph")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mf_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def info(self):
+        i = mf_graph_info()
+        _check(load().mf_graph_get_info(self._h, ctypes.byref(i)), "mf_graph_get_info")
+        return {f: getattr(i, f) for f, _ in mf_graph_info._fields_}
+
+    def solve(self, max_sweeps=0, gap=True, check_every=0):
+        o = mf_graph_opts(int(max_sweeps), 1 if gap else 0, int(check_every))
+        st = mf_graph_stats()
+        _check(load().mf_graph_solve(self._h, ctypes.byref(o), ctypes.byref(st)), "mf_graph_solve")
+        return {f: getattr(st, f) for f, _ in mf_graph_stats._fields_}
+
+    def flow_value(self):
+        v = ctypes.c_int64()
+        _check(load().mf_graph_flow_value(self._h, ctypes.byref(v)), "mf_graph_flow_value")
+        return int(v.value)
+
+    def min_cut(self, kind=MF_CUT_MIN_SOURCE):
+        out = np.zeros(max(self.n, 1), dtype=np.uint8)
+        _check(load().mf_graph_min_cut(self._h, int(kind), ctypes.c_void_p(out.ctypes.data)), "mf_graph_min_cut")
+        return out[:self.n]
+
+    def state(self):
+        m, n = max(self.npairs, 1), max(self.n, 1)
+        r_uv, r_vu = np.zeros(m, np.int64), np.zeros(m, np.int64)
+        rt, ex, lab = np.zeros(n, np.int64), np.zeros(n, np.int64), np.zeros(n, np.int32)
+        _check(load().mf_graph_state(self._h, *[ctypes.c_void_p(a.ctypes.data) for a in (r_uv, r_vu, rt, ex, lab)]),
+               "mf_graph_state")
+        return dict(r_uv=r_uv[:self.npairs], r_vu=r_vu[:self.npairs], rt=rt[:self.n], ex=ex[:self.n],
+                    labels=lab[:self.n])
+
+
+def solve_graph(inst, region=None, region_size=4096, device_pages=0, **solve_kw):
+    """Solve a synth.GraphInstance; returns dict(flow, smin, smax, stats, info, state)."""
+    region = region if region is not None else inst.region
+    with Graph(inst.n, inst.pu, inst.pv, inst.cuv, inst.cvu, inst.cs, inst.ct, region=region,
+               region_size=region_size, device_pages=device_pages) as g:
+        st = g.solve(**solve_kw)
+        out = dict(flow=g.flow_value(), smin=g.min_cut(MF_CUT_MIN_SOURCE), smax=g.min_cut(MF_CUT_MAX_SOURCE),
+                   stats=st, info=g.info())
         out["state"] = g.state()
     return out

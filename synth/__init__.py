@@ -9,3 +9,6 @@ from .grids import (  # noqa: F401
     blob_grid, config, config3_instances, random_grid, paper_e1_grid,
     random_digraph,
 )
+from .graphs import (  # noqa: F401
+    GraphInstance, random_graph, grid26_graph, block_regions, index_regions, random_regions,
+)

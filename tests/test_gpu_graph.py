@@ -1,0 +1,151 @@
+"""GPU parity of the general-network solver (Sec. 5.3: region pages, resident or
+streamed through a few device page slots) against the CPU oracle: the int64
+flow value and both extremal minimum cuts identical, the final state certified
+from the original capacities, the labels valid (Sec. 4.1) and the sweeps within
+2|B|^2 + 1, on random sparse networks with consecutive, scattered, single and
+one-vertex regions, and on 26-connected volumes cut into boxes."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.helpers import assert_valid_labels
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mf():
+    from paper_1109_1146_amd import mf as _mf
+    _mf.load()
+    return _mf
+
+
+def _region_of(inst, region, region_size):
+    if region is not None:
+        return np.asarray(region, np.int64)
+    return np.arange(inst.n) // region_size
+
+
+def _check(mf, inst, region=None, region_size=4096, device_pages=0, **kw):
+    print(f"case {inst.name} n={inst.n} pairs={inst.npairs} regions="
+          f"{'given' if region is not None else f'blocks of {region_size}'} pages={device_pages}", flush=True)
+    out = mf.solve_graph(inst, region=region, region_size=region_size, device_pages=device_pages, **kw)
+    ref = oracle.solve_pairs(inst.n, *inst.arrays())
+    assert out["flow"] == ref["flow"]
+    assert (out["smin"] == ref["smin"]).all(), f"{int((out['smin'] != ref['smin']).sum())} smin vertices differ"
+    assert (out["smax"] == ref["smax"]).all(), f"{int((out['smax'] != ref['smax']).sum())} smax vertices differ"
+    st = out["state"]
+    oracle.certify(inst.n, *inst.arrays(), st["r_uv"], st["r_vu"], st["rt"], st["ex"], out["flow"],
+                   out["smin"], out["smax"])
+    info = out["info"]
+    reg = _region_of(inst, region, region_size)
+    bmask = np.zeros(inst.n, bool)
+    cross = reg[inst.pu] != reg[inst.pv]
+    bmask[inst.pu[cross]] = True
+    bmask[inst.pv[cross]] = True
+    assert info["boundary_size"] == int(bmask.sum())
+    dinf = max(info["boundary_size"], 1)
+    lab = st["labels"].astype(np.int64)
+    assert (lab >= 0).all() and (lab <= dinf).all()
+    assert_valid_labels(inst.pu, inst.pv, st["r_uv"], st["r_vu"], reg, st["rt"], lab, bmask, dinf)
+    assert out["stats"]["sweeps"] <= 2 * info["boundary_size"] ** 2 + 1
+    return out
+
+
+RANDOM = [
+    (300, 4, "blocks", 40), (2000, 6, "blocks", 256), (2000, 3, "scattered", 8),
+    (5000, 8, "blocks", 700), (1500, 6, "single", 0), (400, 4, "singletons", 0),
+    (20000, 6, "blocks", 2048), (8000, 5, "scattered", 40), (3000, 10, "blocks", 100),
+]
+
+
+@pytest.mark.parametrize("case", range(len(RANDOM)))
+def test_random_networks(mf, case):
+    n, deg, kind, size = RANDOM[case]
+    inst = synth.random_graph(n, deg, 8000 + case, long_frac=0.05 if case % 2 else 0.2)
+    if kind == "blocks":
+        _check(mf, inst, region_size=size)
+    elif kind == "scattered":
+        _check(mf, inst, region=synth.random_regions(n, size, 8100 + case))
+    elif kind == "single":
+        out = _check(mf, inst, region_size=n)
+        assert out["info"]["boundary_size"] == 0 and out["stats"]["sweeps"] <= 1
+    else:
+        _check(mf, inst, region_size=1)
+
+
+@pytest.mark.parametrize("pages", [1, 2, 3, 7])
+def test_streamed_pages(mf, pages):
+    """Pages streamed through a few device slots: the same flow and cuts, every
+    discharge loads its page and writes its state back."""
+    inst = synth.random_graph(6000, 6, 8200 + pages, long_frac=0.1)
+    out = _check(mf, inst, region_size=400, device_pages=pages)
+    info, st = out["info"], out["stats"]
+    assert info["resident"] == 0 and info["device_pages"] == pages
+    assert st["pages_in"] >= st["discharges"] and st["pages_out"] >= st["discharges"] > 0
+    assert st["bytes_h2d"] > 0 and st["bytes_d2h"] > 0
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_26_connected_volumes(mf, case):
+    dims, tile = [((16, 16, 16), (8, 8, 8)), ((20, 24, 18), (8, 8, 8)), ((12, 40, 30), (12, 16, 16)),
+                  ((32, 32, 32), (16, 16, 16))][case]
+    inst = synth.grid26_graph(dims, 8300 + case)
+    reg = synth.block_regions(dims, tile)
+    _check(mf, inst, region=reg, device_pages=3 if case == 2 else 0)
+
+
+def test_26_connected_volume_full_size(mf):
+    """A 64^3 volume with the 26-neighbourhood (3.4 M pairs) in 16^3 boxes,
+    resident and streamed through 16 page slots."""
+    dims = (64, 64, 64)
+    inst = synth.grid26_graph(dims, 8400)
+    reg = synth.block_regions(dims, (16, 16, 16))
+    a = _check(mf, inst, region=reg)
+    b = mf.solve_graph(inst, region=reg, device_pages=16)
+    assert b["flow"] == a["flow"] and (b["smin"] == a["smin"]).all() and (b["smax"] == a["smax"]).all()
+
+
+def test_edge_cases(mf):
+    # no pairs: the flow is sum min(c(s, v), c(v, t))
+    cs = np.array([5, 0, 7, 3], np.int32)
+    ct = np.array([2, 4, 9, 0], np.int32)
+    e = np.zeros(0, np.int32)
+    with mf.Graph(4, e, e, e, e, cs, ct, region_size=2) as g:
+        with pytest.raises(mf.MFError) as err:
+            g.flow_value()
+        assert err.value.status == mf.MF_E_STATE
+        g.solve()
+        assert g.flow_value() == 2 + 7
+        assert (g.min_cut(mf.MF_CUT_MIN_SOURCE) == np.array([1, 0, 0, 1])).all()
+        assert (g.min_cut(mf.MF_CUT_MAX_SOURCE) == np.array([1, 0, 0, 1])).all()
+    # an empty network
+    with mf.Graph(0, e, e, e, e, e, e) as g:
+        g.solve()
+        assert g.flow_value() == 0 and g.min_cut().shape == (0,)
+    # zero capacities everywhere, duplicate pairs, isolated vertices
+    inst = synth.random_graph(500, 4, 8500)
+    inst.cuv[:] = 0
+    _check(mf, inst, region_size=50)
+    inst = synth.random_graph(300, 4, 8501)
+    dup = synth.GraphInstance(n=inst.n, pu=np.concatenate([inst.pu, inst.pv]), pv=np.concatenate([inst.pv, inst.pu]),
+                              cuv=np.concatenate([inst.cuv, inst.cvu]), cvu=np.concatenate([inst.cvu, inst.cuv]),
+                              cs=inst.cs, ct=inst.ct, name="duplicated_pairs")
+    _check(mf, dup, region_size=30)
+    iso = synth.random_graph(2000, 1, 8502, window=4)  # many isolated vertices
+    _check(mf, iso, region_size=100)
+
+
+def test_sweep_guard_then_resume(mf):
+    """A solve stopped by max_sweeps keeps its state; a later solve finishes exactly."""
+    inst = synth.random_graph(4000, 6, 8600, long_frac=0.3)
+    ref = oracle.solve_pairs(inst.n, *inst.arrays())
+    with mf.Graph(inst.n, *inst.arrays(), region_size=100) as g:
+        with pytest.raises(mf.MFError) as e:
+            g.solve(max_sweeps=1)
+        assert e.value.status == mf.MF_E_SWEEPS
+        st = g.solve()
+        assert st["sweeps"] >= 2
+        assert g.flow_value() == ref["flow"]
+        assert (g.min_cut(mf.MF_CUT_MAX_SOURCE) == ref["smax"]).all()
