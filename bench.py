@@ -7,10 +7,12 @@ resident in HBM.  Prints ONE JSON line (rank 0).
 Default workload: the 464^3 6-connected blob grid with 64^3 regions (seed 4),
 plain P-ARD timed, the learned-ordered schedules and the fixed-order colour
 phases solved on the same input beside it, the oracle on the whole instance as
-the CPU baseline and exactness check, and the roofline record of the 256^3
-grid with 32^3 regions nested in the same line.  ``--workload 2d`` / ``3d`` /
-``batch`` select the 2048^2 8-connected grid, the 256^3 grid or the
-512-instance batch alone.
+the CPU baseline and exactness check, and nested in the same line the
+roofline record of the 256^3 grid with 32^3 regions and the general-network
+record (a 128^3 volume with the 26-neighbourhood in region pages, resident and
+streamed).  ``--workload 2d`` / ``3d`` / ``batch`` / ``graph`` select the
+2048^2 8-connected grid, the 256^3 grid, the 512-instance batch or the
+general network alone.
 """
 from __future__ import annotations
 
@@ -67,11 +69,12 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", choices=sorted(WORKLOADS), default="464",
+    p.add_argument("--workload", choices=sorted(WORKLOADS) + ["graph"], default="464",
                    help="464 (default: the headline 464^3 grid, with the 256^3 roofline record "
-                        "nested), 3d (256^3), 2d (2048^2) or batch (512 instances)")
+                        "and the general-network record nested), 3d (256^3), 2d (2048^2), batch "
+                        "(512 instances) or graph (128^3 26-connected volume in region pages)")
     p.add_argument("--no-nested", action="store_true",
-                   help="464 only: skip the nested 256^3 roofline record")
+                   help="464 only: skip the nested 256^3 and general-network records")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-learned", action="store_true",
                    help="skip the learned-schedule comparison solves (profiling runs)")
@@ -201,7 +204,7 @@ def bench_batch(args):
         # fixed settings (profiling runs): no tuning solves
         tune = dict(region_shape=tuple(args.region_shape), relabel_every=args.relabel_every or 0,
                     partial=args.partial == "on", boundary_relabel=args.boundary_relabel or 0,
-                    timings=[])
+                    schedule=mf.MF_SCHED_PARD, region_kernel=mf.MF_KERNEL_AUTO, timings=[])
     else:
         tune = autotune.autotune_batch(insts, calib=48, reps=1, partial=forced, brl=brl)
     args.partial = tune["partial"]
@@ -212,7 +215,8 @@ def bench_batch(args):
     def step(profile):
         st = b.solve(global_relabel_every=tune["relabel_every"], graph=not profile,
                      profile=profile, stream=stream.cuda_stream, partial=args.partial,
-                     boundary_relabel=args.boundary_relabel)
+                     boundary_relabel=args.boundary_relabel, schedule=tune["schedule"],
+                     region_kernel=tune["region_kernel"])
         flows = b.flow_values()
         cut = b.min_cut(mf.MF_CUT_MIN_SOURCE)
         return st, flows, cut
@@ -229,8 +233,9 @@ def bench_batch(args):
     ms = elapsed * 1e3 / args.steps
     d_ms, d_launch, d_bytes = pst["discharge_ms"], pst["discharge_launches"], pst["discharge_bytes"]
     achieved = d_bytes / (d_ms / 1e3) / 1e9 if d_ms > 0 else 0.0
-    traffic = measured_traffic("paper_1109_1146_amd/csrc/mf_discharge_wave.hip",
-                               "k_discharge_wave_batch512_traffic.json",
+    kname, ksrc = kernel_of(mf, pst["region_kernel"])
+    traffic = measured_traffic(f"paper_1109_1146_amd/csrc/{ksrc}",
+                               f"{kname}_batch512_traffic.json",
                                config=dict(region_shape=list(tune["region_shape"]),
                                            relabel_every=tune["relabel_every"],
                                            partial=bool(args.partial),
@@ -244,12 +249,14 @@ def bench_batch(args):
         "config": {"workload": WORKLOADS["batch"]["desc"], "instances": len(insts), "n": total_n,
                    "canvas": list(b.dims), "region_shape": list(tune["region_shape"]),
                    "global_relabel_every": tune["relabel_every"], "graph": True,
-                   "partial_discharges": args.partial, "boundary_relabel": args.boundary_relabel},
+                   "partial_discharges": args.partial, "boundary_relabel": args.boundary_relabel,
+                   "schedule": "colour phases (Alg. 1)" if tune["schedule"] == mf.MF_SCHED_COLORED
+                   else "P-ARD (Alg. 2)", "region_kernel": kname},
         "instances_per_s": round(len(insts) / (ms / 1e3), 1),
         "sweeps": st["sweeps"], "region_discharges": st["region_discharges"],
         "flow": int(flows.sum()),
         "autotune": tune["timings"],
-        "roofline": {"bound": "hbm", "kernel": "k_discharge_wave", "achieved": round(achieved, 3),
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 3),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
                      "traffic": traffic, "avg_launch_ms": round(d_ms / max(d_launch, 1), 4),
                      "algorithmic_bytes_per_launch": round(d_bytes / max(d_launch, 1), 1)},
@@ -297,6 +304,90 @@ def bench_batch(args):
     print(json.dumps(rec), flush=True)
 
 
+
+
+GRAPH = dict(dims=(128, 128, 128), seed=9000, tile=(16, 16, 16), pages=64,
+             desc="128^3 volume with the 26-neighbourhood (26.8 M pairs, capacities <= 100), "
+                  "4 blobs with sharp borders, 16^3 box regions (512), seed 9000")
+
+
+def bench_graph(args, steps, warmup, cpu):
+    """The general-network path (region pages, Sec. 5.3) on a 26-connected
+    volume: `steps` solves + both cuts with every page resident in HBM (a fresh
+    handle per step, built before the timed region), then the same with the
+    pages streamed from pinned host memory through 64 device page slots (the
+    PCIe transfers are part of that path).  Flow and both cuts compared with
+    the oracle on the whole instance, which is also the CPU baseline."""
+    import torch
+    import synth
+    from paper_1109_1146_amd import mf
+
+    mf.load()
+    inst = synth.grid26_graph(GRAPH["dims"], GRAPH["seed"])
+    reg = synth.block_regions(GRAPH["dims"], GRAPH["tile"])
+
+    def run(pages, nsteps, nwarm):
+        times, out = [], None
+        for i in range(nwarm + nsteps):
+            g = mf.Graph(inst.n, *inst.arrays(), region=reg, device_pages=pages)
+            try:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = g.solve()
+                smin = g.min_cut(mf.MF_CUT_MIN_SOURCE)
+                smax = g.min_cut(mf.MF_CUT_MAX_SOURCE)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if i >= nwarm:
+                    times.append(dt)
+                out = dict(flow=g.flow_value(), smin=smin, smax=smax, stats=st, info=g.info())
+            finally:
+                g.close()
+        return sum(times) / len(times), out
+
+    ms_res, res = run(0, steps, warmup)
+    ms_str, stre = run(GRAPH["pages"], max(1, steps // 2), 0)
+    # one profiled solve: the discharge launches timed by HIP events on the solve stream
+    g = mf.Graph(inst.n, *inst.arrays(), region=reg)
+    try:
+        pst = g.solve(profile=True)
+    finally:
+        g.close()
+    D, V, A = pst["discharges"], pst["discharged_vertices"], pst["discharged_arcs"]
+    d_bytes = mf.graph_discharge_bytes(V, A) + 4 * (D - 1) if D else 0
+    d_ms, d_launch = pst["discharge_ms"], max(pst["discharge_launches"], 1)
+    achieved = d_bytes / (d_ms / 1e3) / 1e9 if d_ms > 0 else 0.0
+    rec = {"workload": GRAPH["desc"], "n": inst.n, "pairs": inst.npairs, "steps": steps, "warmup": warmup,
+           "ms_per_step": round(ms_res * 1e3, 3), "value": round(inst.n / ms_res / 1e6, 3),
+           "unit": "Mvertices/s", "sweeps": res["stats"]["sweeps"],
+           "region_discharges": res["stats"]["discharges"], "boundary_size": res["info"]["boundary_size"],
+           "flow": res["flow"],
+           "streamed": {"device_pages": GRAPH["pages"], "regions": res["info"]["regions"],
+                        "ms_per_step": round(ms_str * 1e3, 3), "value": round(inst.n / ms_str / 1e6, 3),
+                        "unit": "Mvertices/s (PCIe transfers included)",
+                        "sweeps": stre["stats"]["sweeps"], "pages_in": stre["stats"]["pages_in"],
+                        "pages_out": stre["stats"]["pages_out"],
+                        "bytes_h2d": stre["stats"]["bytes_h2d"], "bytes_d2h": stre["stats"]["bytes_d2h"],
+                        "same_result": bool(stre["flow"] == res["flow"] and (stre["smin"] == res["smin"]).all()
+                                            and (stre["smax"] == res["smax"]).all())},
+           "roofline": {"bound": "hbm", "kernel": "k_gdischarge", "achieved": round(achieved, 3),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
+                        "traffic": None, "avg_launch_ms": round(d_ms / d_launch, 4),
+                        "algorithmic_bytes_per_launch": round(d_bytes / d_launch, 1)}}
+    if cpu:
+        import oracle
+        oracle.build(force=False)
+        t0 = time.perf_counter()
+        ref = oracle.solve_pairs(inst.n, *inst.arrays())
+        t_cpu = time.perf_counter() - t0
+        model, nproc = host_cpu()
+        rec["exact"] = bool(ref["flow"] == res["flow"] and (ref["smin"] == res["smin"]).all()
+                            and (ref["smax"] == res["smax"]).all())
+        rec["cpu_baseline"] = dict(value=round(inst.n / t_cpu / 1e6, 4), unit="Mvertices/s", cores=1,
+                                   kind="oracle", sample=f"1 full solve of the same instance, {t_cpu:.1f} s, "
+                                                         "highest-label push-relabel, 1 thread",
+                                   cpu_model=model, nproc=nproc)
+    return rec
 
 
 def kernel_of(mf, kid):
@@ -485,6 +576,16 @@ def main():
     if args.workload == "batch":
         bench_batch(args)
         return
+    if args.workload == "graph":
+        sub = bench_graph(args, args.steps, args.warmup, cpu=not args.no_cpu_baseline)
+        rec = {"metric": "exact-maxflow solve throughput, general network in region pages (P-ARD)",
+               "value": sub.pop("value"), "unit": sub.pop("unit"), "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": sub.pop("ms_per_step"), "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+               "config": {"workload": sub.pop("workload")}}
+        rec.update(sub)
+        print(json.dumps(rec), flush=True)
+        return
     from paper_1109_1146_amd import mf
 
     mf.load()
@@ -533,6 +634,8 @@ def main():
                               "region_discharges": n3["region_discharges"],
                               "global_relabel_every": w3["relabel"],
                               "partial_discharges": w3["partial"], "roofline": n3["roofline"]}
+        # the general-network path (region pages) on a 26-connected volume
+        rec["graph26_128"] = bench_graph(args, 2, 1, cpu=not args.no_cpu_baseline)
     print(json.dumps(rec), flush=True)
 
 

@@ -442,6 +442,7 @@ typedef struct {
     int64_t max_sweeps;          /* guard; 0 = 2|B|^2 + 1 (the bound of Sec. 4.3-4.4) */
     int32_t gap;                 /* global gap heuristic: 1 = on (the default with opts NULL), 0 = off */
     int32_t check_every;         /* resident pages: sweeps enqueued between termination checks; 0 = 8 */
+    int32_t profile;             /* 1 = time every discharge launch with HIP events */
 } mf_graph_opts;
 
 typedef struct {
@@ -450,7 +451,15 @@ typedef struct {
     int64_t pages_in, pages_out; /* streamed pages: page loads and state write-backs of this call */
     int64_t bytes_h2d, bytes_d2h;
     double ms;                   /* device time of this call's sweeps (HIP events) */
+    int64_t discharged_vertices, discharged_arcs;  /* summed over this call's region discharges */
+    int64_t discharge_launches;  /* with opts->profile: discharge kernel launches and their */
+    double discharge_ms;         /* summed duration (HIP events on the solve stream) */
 } mf_graph_stats;
+
+/* Algorithmic bytes of one region discharge of a page with nv vertices and na
+ * arcs: its row offsets, heads and reverse indices read; residuals, excesses
+ * and residual t-links read and written; labels written. */
+int64_t mf_graph_discharge_bytes(int64_t nv, int64_t na);
 
 /* Build a handle for the network with n vertices and npairs pairs (host
  * arrays, read during the call only): pair i joins pu[i] != pv[i] (both in

@@ -81,7 +81,7 @@ struct Args {
     int nvmax;
     int dinf, maxIter;
     int *err;
-    u64 *stats;         // [0] discharges [1] push rounds [2] search steps
+    u64 *stats;         // [0] discharges [1] push rounds [2] search steps [3] vertices [4] arcs
     const u64 *actIn;
     int mode;           // flood: 0 = backward from t, 1 = forward from the excess
     int first;          // flood: first round
@@ -371,6 +371,8 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
             atomicAdd(&A.stats[0], 1ull);
             atomicAdd(&A.stats[1], (u64)(iter + 1));
             atomicAdd(&A.stats[2], (u64)steps);
+            atomicAdd(&A.stats[3], (u64)nv);
+            atomicAdd(&A.stats[4], (u64)na);
         }
         __syncthreads();
     }
@@ -632,6 +634,9 @@ struct mf_graph {
     int cut_cached = -1;
     bool solved = false;
     long long pages_in = 0, pages_out = 0, bytes_h2d = 0, bytes_d2h = 0;
+    bool profile = false;             // time every discharge launch with HIP events
+    std::vector<hipEvent_t> evProf;   // start and end event per launch
+    size_t nprof = 0;
 };
 
 namespace {
@@ -657,6 +662,7 @@ void free_graph(mf_graph *g) {
         if (p) (void)hipFree(p);
     if (g->hpages) (void)hipHostFree(g->hpages);
     if (g->pinned) (void)hipHostFree(g->pinned);
+    for (hipEvent_t e : g->evProf) (void)hipEventDestroy(e);
     for (int h = 0; h < 2; h++) {
         if (g->evLoad[h]) (void)hipEventDestroy(g->evLoad[h]);
         if (g->evComp[h]) (void)hipEventDestroy(g->evComp[h]);
@@ -760,6 +766,16 @@ mf_status page_pass(mf_graph *g, const int *dlist, const int *hlist, int n, bool
 
 mf_status launch_discharge(mf_graph *g, const mfg::Args &base, const int *dlist, int lo, int n,
                            int slotBase, hipStream_t s) {
+    if (g->profile) {
+        if (g->evProf.size() < 2 * (g->nprof + 1)) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            GTRY(hipEventCreate(&e0));
+            GTRY(hipEventCreate(&e1));
+            g->evProf.push_back(e0);
+            g->evProf.push_back(e1);
+        }
+        GTRY(hipEventRecord(g->evProf[2 * g->nprof], s));
+    }
     mfg::Args A = base;
     A.order = dlist;
     A.cnt = g->cnt;
@@ -769,7 +785,12 @@ mf_status launch_discharge(mf_graph *g, const mfg::Args &base, const int *dlist,
     A.qhead = g->qhead;
     const int blocks = n >= 0 ? std::max(1, std::min(n, g->blocks)) : g->blocks;
     hipLaunchKernelGGL(mfg::k_gdischarge<mfg::kNT>, dim3(blocks), dim3(mfg::kNT), 0, s, A);
-    return ok(hipGetLastError()) ? MF_OK : MF_E_DEVICE;
+    if (!ok(hipGetLastError())) return MF_E_DEVICE;
+    if (g->profile) {
+        GTRY(hipEventRecord(g->evProf[2 * g->nprof + 1], s));
+        g->nprof++;
+    }
+    return MF_OK;
 }
 
 // One sweep of Alg. 2 over the active regions.  Resident pages: enqueued
@@ -1091,7 +1112,7 @@ extern "C" mf_status mf_create_graph(int32_t n, int64_t npairs, const int32_t *p
            ok(dalloc(&g->err, 4)) && ok(dalloc(&g->maxlab, 1)) && ok(dalloc(&g->gap, 1)) &&
            ok(dalloc(&g->qhead, 2)) && ok(dalloc(&g->changed, 1)) &&
            ok(dalloc(&g->hist, (size_t)mfd::kHistBins)) && ok(dalloc(&g->act, 2)) &&
-           ok(dalloc(&g->counters, 4)) && ok(dalloc(&g->stats, 4)) && ok(dalloc(&g->sum, 1)) &&
+           ok(dalloc(&g->counters, 4)) && ok(dalloc(&g->stats, 8)) && ok(dalloc(&g->sum, 1)) &&
            ok(dalloc(&g->cutbuf, (size_t)n)) &&
            ok(hipHostMalloc(&g->pinned, sizeof(int) * (16 + (size_t)K), 0));
     if (!good) {
@@ -1122,7 +1143,7 @@ extern "C" mf_status mf_create_graph(int32_t n, int64_t npairs, const int32_t *p
            ok(hipMemsetAsync(g->hist, 0, sizeof(unsigned) * (size_t)mfd::kHistBins, s)) &&
            ok(hipMemcpyAsync(g->act, actInit, sizeof(actInit), hipMemcpyHostToDevice, s)) &&
            ok(hipMemsetAsync(g->counters, 0, sizeof(u64) * 4, s)) &&
-           ok(hipMemsetAsync(g->stats, 0, sizeof(u64) * 4, s));
+           ok(hipMemsetAsync(g->stats, 0, sizeof(u64) * 8, s));
     if (good && g->resident && storeWords > 0)
         good = ok(hipMemcpyAsync(g->pool, hp, storeWords * sizeof(int), hipMemcpyHostToDevice, s));
     good = good && ok(hipStreamSynchronize(s));
@@ -1170,6 +1191,10 @@ extern "C" mf_status mf_graph_solve(mf_graph *g, const mf_graph_opts *opts, mf_g
     const long long maxSweeps = o.max_sweeps > 0 ? o.max_sweeps : bound;
     const int every = o.check_every > 0 ? o.check_every : 8;
     const long long pin0 = g->pages_in, pout0 = g->pages_out, h2d0 = g->bytes_h2d, d2h0 = g->bytes_d2h;
+    g->profile = o.profile != 0;
+    g->nprof = 0;
+    u64 stt0[8];
+    GTRY(hipMemcpy(stt0, g->stats, sizeof(stt0), hipMemcpyDeviceToHost));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     GTRY(hipEventCreate(&e0));
     GTRY(hipEventCreate(&e1));
@@ -1216,9 +1241,18 @@ extern "C" mf_status mf_graph_solve(mf_graph *g, const mf_graph_opts *opts, mf_g
     (void)hipEventElapsedTime(&ms, e0, e1);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    u64 ctl[4], stt[4];
+    u64 ctl[4], stt[8];
     GTRY(hipMemcpy(ctl, g->counters, sizeof(ctl), hipMemcpyDeviceToHost));
     GTRY(hipMemcpy(stt, g->stats, sizeof(stt), hipMemcpyDeviceToHost));
+    for (int i = 0; i < 8; i++) stt[i] -= stt0[i];
+    double dms = 0.0;
+    for (size_t i = 0; i < g->nprof; i++) {
+        float t = 0.f;
+        if (ok(hipEventElapsedTime(&t, g->evProf[2 * i], g->evProf[2 * i + 1]))) dms += t;
+    }
+    const long long nlaunch = (long long)g->nprof;
+    g->profile = false;
+    g->nprof = 0;
     g->sweeps = (long long)ctl[0];
     g->cur = (int)(g->sweeps & 1);
     g->cut_cached = -1;
@@ -1234,6 +1268,10 @@ extern "C" mf_status mf_graph_solve(mf_graph *g, const mf_graph_opts *opts, mf_g
         st->bytes_h2d = g->bytes_h2d - h2d0;
         st->bytes_d2h = g->bytes_d2h - d2h0;
         st->ms = ms;
+        st->discharged_vertices = (int64_t)stt[3];
+        st->discharged_arcs = (int64_t)stt[4];
+        st->discharge_launches = nlaunch;
+        st->discharge_ms = dms;
     }
     if (status != MF_OK) {
         g->solved = false;
@@ -1324,4 +1362,11 @@ extern "C" mf_status mf_graph_state(mf_graph *g, int64_t *r_uv, int64_t *r_vu, i
         }
     }
     return MF_OK;
+}
+
+extern "C" int64_t mf_graph_discharge_bytes(int64_t nv, int64_t na) {
+    if (nv < 0 || na < 0) return 0;
+    // read: off (nv + 1), head and rev (2 na); read and written: res (na), ex and rt (2 nv);
+    // written: lab (nv)
+    return 4 * ((nv + 1) + 2 * na + 2 * (na + 2 * nv) + nv);
 }

@@ -322,12 +322,15 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
                 __syncthreads();
                 int fs = 0;
                 for (;;) {
-                    if (earlyOk && s_hit && s_live == 0) {
+                    // every thread reads the level's bounds before any thread appends
+                    const bool stop = earlyOk && s_hit && s_live == 0;
+                    const int fe = s_qtail;
+                    const int step = s_nsteps;
+                    __syncthreads();
+                    if (stop) {
                         early = true;
                         break;
                     }
-                    const int fe = s_qtail;
-                    const int step = s_nsteps;
                     int Dn;
                     if (fs == fe) {
                         if (nextSeed == kInf) break;
@@ -374,11 +377,14 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
                 for (;;) {
                     // flood inside the region: u with c_f(u, v) > 0 to a frontier v
                     for (;;) {
-                        if (earlyOk && s_hit && s_live == 0) {
+                        // every thread reads the level's bounds before any thread appends
+                        const bool stop = earlyOk && s_hit && s_live == 0;
+                        const int fe = s_qtail;
+                        __syncthreads();
+                        if (stop) {
                             early = true;
                             break;
                         }
-                        const int fe = s_qtail;
                         if (fs == fe) break;
                         const int step = s_nsteps;
                         for (int i = fs + tid; i < fe; i += NT) {
@@ -1027,6 +1033,7 @@ __global__ __launch_bounds__(NT) void k_flood(FloodArgs A) {
         int fs = 0;
         for (;;) {
             const int fe = s_qtail;
+            __syncthreads();  // every thread has the level's end before any thread appends
             if (fs == fe) break;
             for (int i = fs + tid; i < fe; i += NT) {
                 const int v = Q[i];
@@ -1344,6 +1351,7 @@ __global__ __launch_bounds__(NT) void k_grelabel(GRelabelArgs A) {
         int fs = 0;
         for (;;) {
             const int fe = s_qtail;
+            __syncthreads();  // every thread has the level's end before any thread appends
             if (fs == fe) break;
             for (int i = fs + tid; i < fe; i += NT) {
                 const int v = Q[i];

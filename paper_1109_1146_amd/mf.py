@@ -34,7 +34,7 @@ EXPORTED = ("mf_create_grid", "mf_set_caps", "mf_solve", "mf_flow_value", "mf_mi
             "mf_model_loss_grad", "mf_model_adam_step", "mf_boundary_relabel", "mf_region_relabel",
             "mf_global_relabel", "mf_model_forward_noalloc", "mf_region_reduction",
             "mf_create_graph", "mf_graph_get_info", "mf_graph_solve", "mf_graph_flow_value",
-            "mf_graph_min_cut", "mf_graph_state", "mf_graph_destroy")
+            "mf_graph_min_cut", "mf_graph_state", "mf_graph_destroy", "mf_graph_discharge_bytes")
 
 
 class mf_solve_opts(ctypes.Structure):
@@ -76,14 +76,17 @@ class mf_graph_info(ctypes.Structure):
 
 
 class mf_graph_opts(ctypes.Structure):
-    _fields_ = [("max_sweeps", ctypes.c_int64), ("gap", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+    _fields_ = [("max_sweeps", ctypes.c_int64), ("gap", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("profile", ctypes.c_int32)]
 
 
 class mf_graph_stats(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int64), ("discharges", ctypes.c_int64),
                 ("push_rounds", ctypes.c_int64), ("search_steps", ctypes.c_int64),
                 ("pages_in", ctypes.c_int64), ("pages_out", ctypes.c_int64),
-                ("bytes_h2d", ctypes.c_int64), ("bytes_d2h", ctypes.c_int64), ("ms", ctypes.c_double)]
+                ("bytes_h2d", ctypes.c_int64), ("bytes_d2h", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("discharged_vertices", ctypes.c_int64), ("discharged_arcs", ctypes.c_int64),
+                ("discharge_launches", ctypes.c_int64), ("discharge_ms", ctypes.c_double)]
 
 
 class MFError(RuntimeError):
@@ -186,6 +189,8 @@ def load(path: str = LIB_PATH):
     lib.mf_graph_state.restype = ctypes.c_int
     lib.mf_graph_destroy.argtypes = [P]
     lib.mf_graph_destroy.restype = None
+    lib.mf_graph_discharge_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64]
+    lib.mf_graph_discharge_bytes.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -565,8 +570,8 @@ class Graph:
         _check(load().mf_graph_get_info(self._h, ctypes.byref(i)), "mf_graph_get_info")
         return {f: getattr(i, f) for f, _ in mf_graph_info._fields_}
 
-    def solve(self, max_sweeps=0, gap=True, check_every=0):
-        o = mf_graph_opts(int(max_sweeps), 1 if gap else 0, int(check_every))
+    def solve(self, max_sweeps=0, gap=True, check_every=0, profile=False):
+        o = mf_graph_opts(int(max_sweeps), 1 if gap else 0, int(check_every), 1 if profile else 0)
         st = mf_graph_stats()
         _check(load().mf_graph_solve(self._h, ctypes.byref(o), ctypes.byref(st)), "mf_graph_solve")
         return {f: getattr(st, f) for f, _ in mf_graph_stats._fields_}
@@ -601,3 +606,7 @@ def solve_graph(inst, region=None, region_size=4096, device_pages=0, **solve_kw)
                    stats=st, info=g.info())
         out["state"] = g.state()
     return out
+
+
+def graph_discharge_bytes(nv, na) -> int:
+    return int(load().mf_graph_discharge_bytes(int(nv), int(na)))

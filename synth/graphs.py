@@ -88,11 +88,12 @@ OFFSETS_26 = tuple(o for o in itertools.product((-1, 0, 1), repeat=3) if o > (0,
 
 def grid26_graph(dims, seed, nblobs=4, cap=100, tlink_hi=100, name=None):
     """3D volume with the 26-neighbourhood (13 pairs per interior vertex) and
-    capacities up to ``cap``: a sum of Gaussian blobs gives each voxel an
-    intensity in [0, 1]; a pair gets ``cap * exp(-(dI / 0.1)^2) / |offset|``
-    (contrast-sensitive, rounded), its reverse the same; the t-links put
-    intensities above 0.5 on the source side, below it on the sink side, with a
-    strength of up to ``tlink_hi``."""
+    capacities up to ``cap``: a sum of Gaussian blobs, normalised and passed
+    through a steep sigmoid (objects with sharp borders) plus Gaussian noise of
+    0.08, gives each voxel an intensity in [0, 1]; a pair gets
+    ``cap * exp(-(dI / 0.1)^2) / |offset|`` (contrast-sensitive, rounded), its
+    reverse the same; the t-links put intensities above 0.5 on the source side,
+    below it on the sink side, with a strength of up to ``tlink_hi``."""
     D, H, W = (int(d) for d in dims)
     n = D * H * W
     rng = np.random.default_rng(seed)
@@ -103,8 +104,10 @@ def grid26_graph(dims, seed, nblobs=4, cap=100, tlink_hi=100, name=None):
         sig = rng.uniform(0.1, 0.3) * max(D, H, W)
         img += rng.uniform(0.5, 1.0) * np.exp(-((z - c[0]) ** 2 + (y - c[1]) ** 2 + (x - c[2]) ** 2)
                                               / (2 * sig * sig))
-    img = np.clip(img + rng.normal(scale=0.05, size=img.shape), 0, None)
+    # objects with sharp borders: a steep sigmoid of the blob sum, then noise
     img = img / max(img.max(), 1e-9)
+    img = 1.0 / (1.0 + np.exp(-(img - 0.35) * 25.0))
+    img = np.clip(img + rng.normal(scale=0.08, size=img.shape), 0, 1)
     idx = np.arange(n).reshape(D, H, W)
     pus, pvs, cs_ = [], [], []
     for dz, dy, dx in OFFSETS_26:

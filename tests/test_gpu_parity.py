@@ -439,10 +439,21 @@ def test_batch_workload_512_exact(mf):
     insts = synth.config3_instances(512)
     tune = autotune.autotune_batch(insts, calib=24, reps=1)
     print("autotuned", tune["region_shape"], tune["relabel_every"], tune["partial"],
-          tune["boundary_relabel"], flush=True)
+          tune["boundary_relabel"], tune["schedule"], tune["region_kernel"], flush=True)
+    # every dimension was searched: both schedules and both workgroup shapes were timed
+    sub = [t for t in tune["timings"] if t["stage"] == "subset"]
+    assert {t["schedule"] for t in sub} == {mf.MF_SCHED_PARD, mf.MF_SCHED_COLORED}
+    assert {t["region_kernel"] for t in sub} == {mf.MF_KERNEL_WAVE, mf.MF_KERNEL_LDS}
     st = _batch_check(mf, insts, tune["region_shape"], global_relabel_every=tune["relabel_every"],
-                      partial=tune["partial"], boundary_relabel=tune["boundary_relabel"], graph=True)
+                      partial=tune["partial"], boundary_relabel=tune["boundary_relabel"],
+                      schedule=tune["schedule"], region_kernel=tune["region_kernel"], graph=True)
     assert st["sweeps"] > 0
+    # the other schedule and workgroup shape are exact too
+    other = dict(schedule=mf.MF_SCHED_COLORED if tune["schedule"] == mf.MF_SCHED_PARD else mf.MF_SCHED_PARD,
+                 region_kernel=mf.MF_KERNEL_LDS if tune["region_kernel"] == mf.MF_KERNEL_WAVE
+                 else mf.MF_KERNEL_WAVE)
+    _batch_check(mf, insts[:128], tune["region_shape"], global_relabel_every=tune["relabel_every"],
+                 partial=tune["partial"], graph=True, **other)
 
 
 SERPENTINE_CASES = [
