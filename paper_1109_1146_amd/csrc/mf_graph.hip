@@ -77,7 +77,7 @@ struct Args {
     int listLo, listN;
     int slotBase;       // < 0: region r lives in slot r; else the i-th region in slot slotBase + i
     unsigned *qhead;
-    int *scratch;       // 4 * nvmax ints per workgroup
+    int *scratch;       // kScratchInts * nvmax ints per workgroup
     int nvmax;
     int dinf, maxIter;
     int *err;
@@ -114,6 +114,23 @@ __device__ __forceinline__ int next_region(const Args &A, int *s_r, int *s_slot)
     return *s_r;
 }
 
+// Sums and minima over a group of G consecutive lanes (G divides 64).
+template <int G>
+__device__ __forceinline__ long long gscan(long long x, int lane) {
+    for (int o = 1; o < G; o <<= 1) {
+        const long long y = __shfl_up(x, o, G);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+template <int G>
+__device__ __forceinline__ int gmin(int x) {
+    for (int o = G / 2; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, G));
+    return x;
+}
+
+constexpr int kScratchInts = 5;  // per vertex of the largest region, per workgroup
+
 // ---------------------------------------------------------------------------
 // Region discharge, Proc. ARD (Sec. 4.2) on a region page.  As on grids, the
 // staged Augment(R, T_k) runs as pushes along the levels of a multi-level
@@ -124,16 +141,38 @@ __device__ __forceinline__ int next_region(const Args &A, int *s_r, int *s_slot)
 // and push rounds alternate until no excess vertex of the region reaches a
 // target.  Arcs from other regions into R are not used (capacity 0 in G^R);
 // flow sent over a boundary arc waits in cp for the fusion.
+//
+// A group of G lanes takes one vertex and its arcs G at a time: in the search
+// every lane tests one arc; in a push the lanes split the vertex's excess over
+// its admissible arcs in arc order by a prefix sum of their capacities.  The
+// search marks S, the queue Q, the smallest halo level M of every boundary
+// vertex (fixed during a search) and the row offsets live in LDS when the
+// region fits (LDS), else in per-workgroup scratch.
 // ---------------------------------------------------------------------------
-template <int NT>
+template <int NT, int G, bool LDS>
 __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
+    extern __shared__ int smem[];
     __shared__ int s_r, s_slot, s_qtail, s_fe, s_nsteps, s_min, s_found, s_live, s_hit, s_stop;
     __shared__ int s_wmin[NT / 64];
     constexpr int kDead = kInf - 1;  // not reached by a complete search of this discharge
+    constexpr int NG = NT / G;
     if (*A.actIn == 0ull) return;
-    const int tid = threadIdx.x;
-    int *S = A.scratch + (size_t)blockIdx.x * 4 * A.nvmax;
-    int *Q = S + A.nvmax, *stepEnd = Q + A.nvmax, *stepLevel = stepEnd + A.nvmax;
+    const int tid = threadIdx.x, lane = tid % G, grp = tid / G;
+    const int nvmax = A.nvmax;
+    int *gs = A.scratch + (size_t)blockIdx.x * kScratchInts * nvmax;
+    int *stepEnd = gs, *stepLevel = gs + nvmax;
+    int *S, *Q, *M, *offL;
+    if (LDS) {
+        S = smem;
+        Q = S + nvmax;
+        M = Q + nvmax;
+        offL = M + nvmax;
+    } else {
+        S = gs + 2 * nvmax;
+        Q = gs + 3 * nvmax;
+        M = gs + 4 * nvmax;
+        offL = nullptr;
+    }
     const int dinf = A.dinf;
     const int *labOld = A.labOld, *cslot = A.cslot, *blocal = A.blocal;
     int *cr = A.cr, *cp = A.cp;
@@ -144,8 +183,13 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
         const int nv = info.x, na = info.y, b0 = info.z, nb = info.w;
         const Layout L = layout_of(nv, na);
         int *P = A.pool + (long long)s_slot * A.stride;
-        const int *off = P + L.off, *head = P + L.head, *rev = P + L.rev;
+        const int *head = P + L.head, *rev = P + L.rev;
         int *res = P + L.res, *ex = P + L.ex, *rt = P + L.rt, *lab = P + L.lab;
+        const int *off = P + L.off;
+        if (LDS) {
+            for (int l = tid; l <= nv; l += NT) offL[l] = off[l];
+            off = offL;
+        }
         for (int i = tid; i < nb; i += NT) {
             const int e = A.exIn[b0 + i];
             if (e) {
@@ -184,6 +228,22 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
             live = wsum(live);
             if ((tid & 63) == 0 && live) atomicAdd(&s_live, live);
             if (hit) s_hit = 1;
+            // every boundary vertex: the smallest d(w) + 1 over its residual boundary arcs
+            for (int i = grp; i < nb; i += NG) {
+                const int l = blocal[b0 + i];
+                int best = kInf;
+                const int a1 = off[l + 1];
+                for (int a = off[l] + lane; a < a1; a += G) {
+                    const int h = head[a];
+                    if (h >= 0) continue;
+                    const int x = -h - 1;
+                    if (cr[x] <= 0) continue;
+                    const int d = labOld[cslot[x ^ 1]];
+                    if (d < dinf) best = min(best, d + 1);
+                }
+                best = gmin<G>(best);
+                if (lane == 0) M[i] = best;
+            }
             __syncthreads();
             if (tid == 0) {
                 if (s_qtail > 0) {
@@ -207,10 +267,10 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
                     }
                     if (fs == fe) break;
                     const int step = s_nsteps;
-                    for (int i = fs + tid; i < fe; i += NT) {
+                    for (int i = fs + grp; i < fe; i += NG) {
                         const int v = Q[i];
                         const int a1 = off[v + 1];
-                        for (int a = off[v]; a < a1; a++) {
+                        for (int a = off[v] + lane; a < a1; a += G) {
                             const int u = head[a];
                             if (u < 0 || S[u] != kInf) continue;
                             if (res[rev[a]] > 0 && atomicCAS(&S[u], kInf, step) == kInf) {
@@ -236,22 +296,10 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
                     __syncthreads();
                 }
                 if (early) break;
-                // next stage: the smallest d(w) + 1 over residual boundary arcs (u, w)
-                // of vertices u without a level
+                // next stage: the smallest halo level of a boundary vertex without a level
                 int best = kInf;
-                for (int i = tid; i < nb; i += NT) {
-                    const int l = blocal[b0 + i];
-                    if (S[l] != kInf) continue;
-                    const int a1 = off[l + 1];
-                    for (int a = off[l]; a < a1; a++) {
-                        const int h = head[a];
-                        if (h >= 0) continue;
-                        const int x = -h - 1;
-                        if (cr[x] <= 0) continue;
-                        const int d = labOld[cslot[x ^ 1]];
-                        if (d < dinf) best = min(best, d + 1);
-                    }
-                }
+                for (int i = tid; i < nb; i += NT)
+                    if (S[blocal[b0 + i]] == kInf) best = min(best, M[i]);
                 best = wmin(best);
                 if ((tid & 63) == 0) s_wmin[tid >> 6] = best;
                 __syncthreads();
@@ -266,23 +314,12 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
                 const int step = s_nsteps;
                 for (int i = tid; i < nb; i += NT) {
                     const int l = blocal[b0 + i];
-                    if (S[l] != kInf) continue;
-                    const int a1 = off[l + 1];
-                    for (int a = off[l]; a < a1; a++) {
-                        const int h = head[a];
-                        if (h >= 0) continue;
-                        const int x = -h - 1;
-                        if (cr[x] <= 0) continue;
-                        const int d = labOld[cslot[x ^ 1]];
-                        if (d < dinf && d + 1 == level) {
-                            S[l] = step;
-                            Q[atomicAdd(&s_qtail, 1)] = l;
-                            if (ex[l] > 0) {
-                                atomicSub(&s_live, 1);
-                                s_hit = 1;
-                            }
-                            break;
-                        }
+                    if (S[l] != kInf || M[i] != level) continue;
+                    S[l] = step;
+                    Q[atomicAdd(&s_qtail, 1)] = l;
+                    if (ex[l] > 0) {
+                        atomicSub(&s_live, 1);
+                        s_hit = 1;
                     }
                 }
                 __syncthreads();
@@ -316,46 +353,57 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
                 const int lo = s > 0 ? stepEnd[s - 1] : 0, hi = stepEnd[s];
                 const int Lv = stepLevel[s];
                 const bool seed = s == 0 || stepLevel[s - 1] != Lv;
-                for (int i = lo + tid; i < hi; i += NT) {
+                for (int i = lo + grp; i < hi; i += NG) {
                     const int u = Q[i];
                     int e = ex[u];
-                    if (e <= 0) continue;
-                    const int a1 = off[u + 1];
+                    if (e <= 0) continue;  // uniform over the group
                     if (seed && Lv == 0) {
-                        const int t = rt[u];
-                        if (t > 0) {
+                        if (lane == 0) {
+                            const int t = rt[u];
                             const int d = min(e, t);
                             rt[u] = t - d;
-                            e -= d;
+                            ex[u] = e - d;
                         }
-                    } else if (seed) {
-                        for (int a = off[u]; a < a1 && e > 0; a++) {
-                            const int h = head[a];
-                            if (h >= 0) continue;
-                            const int x = -h - 1;
-                            const int c = cr[x];
-                            if (c <= 0) continue;
-                            const int dw = labOld[cslot[x ^ 1]];
-                            if (dw >= dinf || dw + 1 != Lv) continue;
-                            const int d = min(e, c);
-                            cr[x] = c - d;
-                            cp[x] += d;
-                            e -= d;
-                        }
-                    } else {
-                        for (int a = off[u]; a < a1 && e > 0; a++) {
-                            const int v = head[a];
-                            if (v < 0) continue;
-                            const int c = res[a];
-                            if (c <= 0 || S[v] != s - 1) continue;
-                            const int d = min(e, c);
-                            res[a] = c - d;
-                            res[rev[a]] += d;
-                            atomicAdd(&ex[v], d);
-                            e -= d;
-                        }
+                        continue;
                     }
-                    ex[u] = e;
+                    const int a1 = off[u + 1];
+                    for (int base = off[u]; base < a1 && e > 0; base += G) {
+                        const int a = base + lane;
+                        int c = 0, x = -1, h = -1;
+                        if (a < a1) {
+                            h = head[a];
+                            if (seed) {
+                                if (h < 0) {
+                                    x = -h - 1;
+                                    const int cc = cr[x];
+                                    if (cc > 0) {
+                                        const int dw = labOld[cslot[x ^ 1]];
+                                        if (dw < dinf && dw + 1 == Lv) c = cc;
+                                    }
+                                }
+                            } else if (h >= 0) {
+                                const int cc = res[a];
+                                if (cc > 0 && S[h] == s - 1) c = cc;
+                            }
+                        }
+                        // the lanes take the excess in arc order
+                        const long long incl = gscan<G>((long long)c, lane);
+                        const long long before = incl - c;
+                        const int d = (int)std::min<long long>(c, std::max<long long>(0, (long long)e - before));
+                        if (d > 0) {
+                            if (seed) {
+                                cr[x] -= d;
+                                cp[x] += d;
+                            } else {
+                                res[a] -= d;
+                                res[rev[a]] += d;
+                                atomicAdd(&ex[h], d);
+                            }
+                        }
+                        const long long tot = __shfl(incl, G - 1, G);
+                        e -= (int)std::min<long long>(e, tot);
+                    }
+                    if (lane == 0) ex[u] = e;
                 }
                 __syncthreads();
             }
@@ -474,7 +522,7 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_gflood(Args A) {
     __shared__ int s_r, s_slot, s_qtail, s_fe;
     const int tid = threadIdx.x;
-    int *Q = A.scratch + (size_t)blockIdx.x * 4 * A.nvmax;
+    int *Q = A.scratch + (size_t)blockIdx.x * kScratchInts * A.nvmax;
     const int *cslot = A.cslot, *blocal = A.blocal;
     const int *cr = A.cr;
     const bool back = A.mode == 0;
@@ -634,6 +682,8 @@ struct mf_graph {
     int cut_cached = -1;
     bool solved = false;
     long long pages_in = 0, pages_out = 0, bytes_h2d = 0, bytes_d2h = 0;
+    int group = 8;                    // lanes per vertex in the discharge (8 or 32, from the mean degree)
+    size_t ldsBytes = 0;              // dynamic LDS of the discharge, 0: search arrays in scratch
     bool profile = false;             // time every discharge launch with HIP events
     std::vector<hipEvent_t> evProf;   // start and end event per launch
     size_t nprof = 0;
@@ -784,7 +834,14 @@ mf_status launch_discharge(mf_graph *g, const mfg::Args &base, const int *dlist,
     A.slotBase = slotBase;
     A.qhead = g->qhead;
     const int blocks = n >= 0 ? std::max(1, std::min(n, g->blocks)) : g->blocks;
-    hipLaunchKernelGGL(mfg::k_gdischarge<mfg::kNT>, dim3(blocks), dim3(mfg::kNT), 0, s, A);
+    const size_t lds = g->ldsBytes;
+    if (g->group == 32) {
+        if (lds) hipLaunchKernelGGL((mfg::k_gdischarge<mfg::kNT, 32, true>), dim3(blocks), dim3(mfg::kNT), lds, s, A);
+        else hipLaunchKernelGGL((mfg::k_gdischarge<mfg::kNT, 32, false>), dim3(blocks), dim3(mfg::kNT), 0, s, A);
+    } else {
+        if (lds) hipLaunchKernelGGL((mfg::k_gdischarge<mfg::kNT, 8, true>), dim3(blocks), dim3(mfg::kNT), lds, s, A);
+        else hipLaunchKernelGGL((mfg::k_gdischarge<mfg::kNT, 8, false>), dim3(blocks), dim3(mfg::kNT), 0, s, A);
+    }
     if (!ok(hipGetLastError())) return MF_E_DEVICE;
     if (g->profile) {
         GTRY(hipEventRecord(g->evProf[2 * g->nprof + 1], s));
@@ -1089,8 +1146,24 @@ extern "C" mf_status mf_create_graph(int32_t n, int64_t npairs, const int32_t *p
         return MF_E_DEVICE;
     }
     g->numCU = prop.multiProcessorCount;
+    // a group of lanes per vertex: 32 when vertices have a dozen arcs or more
+    g->group = (n > 0 && 2 * npairs >= 12LL * n) ? 32 : 8;
+    // the search arrays and row offsets in LDS while two workgroups fit a compute unit
+    {
+        const size_t need = sizeof(int) * (4 * (size_t)std::max(g->nvmax, 1) + 1);
+        const size_t cap = std::min<size_t>(80 * 1024, (size_t)prop.sharedMemPerBlock);
+        g->ldsBytes = need <= cap ? need : 0;
+        static bool attrs = false;
+        if (!attrs) {
+            (void)hipFuncSetAttribute((const void *)mfg::k_gdischarge<mfg::kNT, 32, true>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024);
+            (void)hipFuncSetAttribute((const void *)mfg::k_gdischarge<mfg::kNT, 8, true>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024);
+            attrs = true;
+        }
+    }
     // workgroups: two per compute unit, as many as the scratch budget allows
-    const long long perBlock = 16LL * std::max(g->nvmax, 1);
+    const long long perBlock = 4LL * mfg::kScratchInts * std::max(g->nvmax, 1);
     const int budgetBlocks = (int)std::max(1LL, (1LL << 30) / perBlock);
     const int listMax = g->resident ? K : g->half;
     g->blocks = std::max(1, std::min({std::max(listMax, 1), 2 * g->numCU, budgetBlocks}));
@@ -1108,7 +1181,7 @@ extern "C" mf_status mf_create_graph(int32_t n, int64_t npairs, const int32_t *p
            ok(dalloc(&g->cslot, (size_t)(2 * nC))) && ok(dalloc(&g->order, (size_t)K)) &&
            ok(dalloc(&g->allreg, (size_t)K)) && ok(dalloc(&g->cnt, 1)) &&
            ok(dalloc(&g->ractive, (size_t)K)) &&
-           ok(dalloc(&g->scratch, (size_t)g->blocks * 4 * (size_t)std::max(g->nvmax, 1))) &&
+           ok(dalloc(&g->scratch, (size_t)g->blocks * mfg::kScratchInts * (size_t)std::max(g->nvmax, 1))) &&
            ok(dalloc(&g->err, 4)) && ok(dalloc(&g->maxlab, 1)) && ok(dalloc(&g->gap, 1)) &&
            ok(dalloc(&g->qhead, 2)) && ok(dalloc(&g->changed, 1)) &&
            ok(dalloc(&g->hist, (size_t)mfd::kHistBins)) && ok(dalloc(&g->act, 2)) &&
