@@ -361,6 +361,8 @@ def bench_graph(args, steps, warmup, cpu):
            "ms_per_step": round(ms_res * 1e3, 3), "value": round(inst.n / ms_res / 1e6, 3),
            "unit": "Mvertices/s", "sweeps": res["stats"]["sweeps"],
            "region_discharges": res["stats"]["discharges"], "boundary_size": res["info"]["boundary_size"],
+           "push_rounds_per_discharge": round(res["stats"]["push_rounds"] / max(res["stats"]["discharges"], 1), 2),
+           "search_levels_per_discharge": round(res["stats"]["search_steps"] / max(res["stats"]["discharges"], 1), 1),
            "flow": res["flow"],
            "streamed": {"device_pages": GRAPH["pages"], "regions": res["info"]["regions"],
                         "ms_per_step": round(ms_str * 1e3, 3), "value": round(inst.n / ms_str / 1e6, 3),

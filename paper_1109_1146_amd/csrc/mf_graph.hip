@@ -787,14 +787,19 @@ mf_status page_pass(mf_graph *g, const int *dlist, const int *hlist, int n, bool
         if (st != MF_OK) return st;
         // the slots of this half are free once the kernel that used them ended
         GTRY(hipStreamWaitEvent(g->sc, g->evComp[h], 0));
-        for (int i = 0; i < cnt; i++) {
-            const int r = hlist[lo + i];
-            const Layout L = layout_of(g->rinfo[r].x, g->rinfo[r].y);
+        for (int i = 0; i < cnt;) {
+            // consecutive regions in consecutive slots: one copy (the last page without its padding)
+            int j = i + 1;
+            while (j < cnt && hlist[lo + j] == hlist[lo + j - 1] + 1) j++;
+            const int r0 = hlist[lo + i], rl = hlist[lo + j - 1];
+            const Layout L = layout_of(g->rinfo[rl].x, g->rinfo[rl].y);
             const size_t slot = (size_t)h * g->half + i;
-            GTRY(hipMemcpyAsync(g->pool + slot * g->stride, g->hpages + (size_t)r * g->stride,
-                                (size_t)L.words * sizeof(int), hipMemcpyHostToDevice, g->sc));
-            g->pages_in++;
-            g->bytes_h2d += (long long)L.words * sizeof(int);
+            const size_t words = (size_t)(j - 1 - i) * g->stride + L.words;
+            GTRY(hipMemcpyAsync(g->pool + slot * g->stride, g->hpages + (size_t)r0 * g->stride,
+                                words * sizeof(int), hipMemcpyHostToDevice, g->sc));
+            g->pages_in += j - i;
+            g->bytes_h2d += (long long)(words * sizeof(int));
+            i = j;
         }
         GTRY(hipEventRecord(g->evLoad[h], g->sc));
         GTRY(hipStreamWaitEvent(g->s, g->evLoad[h], 0));
@@ -880,6 +885,9 @@ mf_status enqueue_sweep(mf_graph *g, long long i, bool gapOn, int *regionsOut) {
         const int n = a ? mb[0] : 0;
         if (regionsOut) *regionsOut = n;
         if (n > 0) {
+            // regions in increasing order: neighbouring pages load in one copy
+            std::sort(mb + 16, mb + 16 + n);
+            GTRY(hipMemcpyAsync(g->order, mb + 16, sizeof(int) * (size_t)n, hipMemcpyHostToDevice, s));
             mf_status st = page_pass(g, g->order, mb + 16, n, true,
                                      [&](const int *dl, int lo, int cnt, int sb, hipStream_t ss) {
                                          return launch_discharge(g, A, dl, lo, cnt, sb, ss) == MF_OK
