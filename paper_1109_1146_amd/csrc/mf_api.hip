@@ -954,6 +954,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                     // schedule scores them (BF16) and builds the queue
                     mfd::FeatArgs FA;
                     FA.G = G; FA.ex = g->ex; FA.lab = g->lab[p]; FA.res = g->res;
+                    FA.lab2 = colored ? nullptr : g->lab[p ^ 1];
                     FA.ringL = g->ringL; FA.ringM = g->ringM; FA.nring = g->nring; FA.dinf = g->dinf;
                     // with partial discharges excess can stay inside a region, and
                     // so it can during the first sweep of colour phases
@@ -1099,10 +1100,15 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         // the state after the sweeps run so far stays readable
         g->final_parity = colored ? 0 : (int)(g->pinned[1] & 1ull);
         g->has_state = true;
+        // skipped regions refreshed only their border labels: the current labels
+        // are the larger entry of the two buffers
+        if (!colored) HIP_TRY(mfd::launch_label_max(g->lab[g->final_parity], g->lab[g->final_parity ^ 1], G.N, s));
+        HIP_TRY(hipStreamSynchronize(s));
     }
     if (status != MF_OK) return status;
     const long long steps = (long long)g->pinned[1];
     g->final_parity = colored ? 0 : (int)(steps & 1);
+    if (!colored) HIP_TRY(mfd::launch_label_max(g->lab[g->final_parity], g->lab[g->final_parity ^ 1], G.N, s));
     const long long sweeps = (steps + ncol - 1) / ncol;
     // flow value |f| = sum (c_t - c_f(., t))
     HIP_TRY(hipMemsetAsync(g->sums + 2, 0, sizeof(u64), s));

@@ -158,7 +158,12 @@ __global__ __launch_bounds__(NT) void k_discharge_lds(DischargeArgs A) {
         }
         __syncthreads();
         if (!s_active) {
-            for (int l = tid; l < V; l += NT) A.labNew[base + l] = A.labOld[base + l];
+            // border labels only: the interior is recomputed by the next discharge
+            if (A.labNew != A.labOld)
+                for (int i = tid; i < A.nring; i += NT) {
+                    const int l = A.ringL[i];
+                    A.labNew[base + l] = A.labOld[base + l];
+                }
             __syncthreads();
             continue;
         }

@@ -227,10 +227,13 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
         }
         __syncthreads();
         if (!s_active) {
-            // skipped region (no active vertex): labels carry over unchanged
-            const int4 *src = (const int4 *)(A.labOld + base);
-            int4 *dst = (int4 *)(A.labNew + base);
-            for (int i = tid; i < V / 4; i += kRowsNT) dst[i] = src[i];
+            // skipped region (no active vertex): its border labels carry over;
+            // the interior is recomputed by its next discharge
+            if (A.labNew != A.labOld)
+                for (int i = tid; i < A.nring; i += kRowsNT) {
+                    const int l = A.ringL[i];
+                    A.labNew[base + l] = A.labOld[base + l];
+                }
             __syncthreads();
             continue;
         }

@@ -260,10 +260,13 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
         }
         __syncthreads();
         if (!s_active) {
-            // skipped region (no active vertex): labels carry over unchanged
-            const int4 *src = (const int4 *)(A.labOld + base);
-            int4 *dst = (int4 *)(A.labNew + base);
-            for (int i = tid; i < V / 4; i += kNT) dst[i] = src[i];
+            // skipped region (no active vertex): its border labels carry over;
+            // the interior is recomputed by its next discharge
+            if (A.labNew != A.labOld)
+                for (int i = tid; i < A.nring; i += kNT) {
+                    const int l = A.ringL[i];
+                    A.labNew[base + l] = A.labOld[base + l];
+                }
             __syncthreads();
             continue;
         }

@@ -277,7 +277,12 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
         }
         active = __shfl(active, 0, 64);
         if (!active) {
-            for (int l = lane; l < V; l += 64) A.labNew[base + l] = A.labOld[base + l];
+            // border labels only: the interior is recomputed by the next discharge
+            if (A.labNew != A.labOld)
+                for (int i = lane; i < A.nring; i += 64) {
+                    const int l = A.ringL[i];
+                    A.labNew[base + l] = A.labOld[base + l];
+                }
             continue;
         }
         const long long t_start = wall_clock64();

@@ -203,8 +203,21 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
         }
         __syncthreads();
         if (!s_active) {
-            // skipped region (no active vertex): labels carry over unchanged
-            for (int l = tid; l < V; l += NT) A.labNew[base + l] = labOld[base + l];
+            // skipped region (no active vertex): labels carry over unchanged.
+            // Other regions read only its border labels, and its own next
+            // discharge recomputes the rest, so ARD copies the border only (the
+            // other buffer holds older, never larger labels; the solve ends by
+            // merging the two buffers).  The PRD gap reads every label.
+            if (A.labNew != labOld) {
+                if (A.prd) {
+                    for (int l = tid; l < V; l += NT) A.labNew[base + l] = labOld[base + l];
+                } else {
+                    for (int i = tid; i < A.nring; i += NT) {
+                        const int l = A.ringL[i];
+                        A.labNew[base + l] = labOld[base + l];
+                    }
+                }
+            }
             __syncthreads();
             continue;
         }
@@ -993,13 +1006,25 @@ __global__ void k_gather_plane(Geo G, const int *src, int *dst, int n) {
 // solve writes buffer (k + 1) & 1 and the step counter counts the steps that
 // ran, so the current labels are in buffer (count & 1), also after steps that
 // found no active vertex and exited at once (one buffer: lab0 == lab1).
+// The labels after a step: the larger entry of the two buffers (labels never
+// decrease, and a region skipped by a sweep refreshes only its border labels
+// in the new buffer, so the other buffer may hold its current interior).
 __global__ void k_trace_labels(Geo G, const int *lab0, const int *lab1,
                                const unsigned long long *count, int *dst, int n) {
     int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
-    const int *src = (*count & 1ull) ? lab1 : lab0;
+    (void)count;
     int x = v % G.dx, t = v / G.dx, y = t % G.dy, z = t / G.dy;
-    dst[v] = src[grid_to_blocked(G, z, y, x)];
+    const int g = grid_to_blocked(G, z, y, x);
+    dst[v] = max(lab0[g], lab1[g]);
+}
+
+// dst[g] = max(dst[g], other[g]): the current labels into one buffer.
+__global__ void k_label_max(int *dst, const int *other, int N) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
+        const int o = other[g];
+        if (o > dst[g]) dst[g] = o;
+    }
 }
 
 // Residual reachability by region floods: each workgroup floods its region
@@ -1256,6 +1281,12 @@ hipError_t launch_gather_plane(const Geo &G, const int *src, int *dst, int n, hi
 hipError_t launch_trace_labels(const Geo &G, const int *lab0, const int *lab1,
                                const unsigned long long *count, int *dst, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_trace_labels, dim3(cdiv(n, 256)), dim3(256), 0, s, G, lab0, lab1, count, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_label_max(int *dst, const int *other, int N, hipStream_t s) {
+    if (N <= 0 || dst == other) return hipSuccess;
+    hipLaunchKernelGGL(k_label_max, dim3(std::min(cdiv(N, 256), kCountBlocks)), dim3(256), 0, s, dst, other, N);
     return hipGetLastError();
 }
 

@@ -59,6 +59,7 @@ constexpr int kFeat = 6;  // floats per region in the scheduler features
 struct FeatArgs {
     Geo G;
     const int *ex, *lab, *res;
+    const int *lab2;  // the other label buffer (labels are the larger entry), or null
     const int *ringL;
     const unsigned char *ringM;
     int nring;
@@ -241,6 +242,7 @@ hipError_t launch_flood(const FloodArgs &A, int blocks, hipStream_t s);
 hipError_t launch_flood_wave(const FloodArgs &A, int blocks, hipStream_t s);
 hipError_t launch_flood_rows(const FloodArgs &A, int blocks, hipStream_t s);
 hipError_t launch_saturate_inflow(const Geo &G, const int *nbr, int n, int *res, int *ex, hipStream_t s);
+hipError_t launch_label_max(int *dst, const int *other, int N, hipStream_t s);
 hipError_t launch_reduce_classes(const Geo &G, const int *lab, const int *mark, unsigned char *cls,
                                  int dinf, int sinkSide, hipStream_t s);
 hipError_t launch_gather_bytes(const Geo &G, const unsigned char *src, unsigned char *out, int n,

@@ -37,7 +37,7 @@ __global__ void k_region_features(FeatArgs A) {
     if (!A.ringOnly) {
         for (int l = tid; l < V; l += blockDim.x) {
             const int e = A.ex[base + l];
-            const int d = A.lab[base + l];
+            const int d = A.lab2 ? max(A.lab[base + l], A.lab2[base + l]) : A.lab[base + l];
             if (e > 0 && d < A.dinf) {
                 ex_act += e;
                 any = 1;
