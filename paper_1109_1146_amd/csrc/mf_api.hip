@@ -31,6 +31,8 @@ struct mf_grid {
     int *bstart = nullptr;        // [nreg + 1]: the boundary vertices of region r are bidx[bstart[r]..bstart[r+1])
     int *corder = nullptr;        // regions grouped by colour (MF_SCHED_COLORED), built on first use
     int corder_ncol = 0;
+    int *plists = nullptr;        // learned colour phases: [ncol][phase_maxc] region lists by phase
+    int phase_maxc = 0;
     std::vector<int> cstart;      // colour c holds corder[cstart[c] .. cstart[c+1])
     std::vector<int> corder_host;
     unsigned int *brlctl = nullptr;  // boundary relabel control words
@@ -100,7 +102,7 @@ static void free_all(mf_grid *g) {
                     g->bidx, g->ringL, g->rvcount, g->mark, g->dirty, g->ringM, g->ringX, g->cutbuf,
                     g->in_cs, g->in_ct, g->in_nbr, g->scratch, g->act, g->qhead, g->hist,
                     g->maxlab, g->gap, g->err, g->counters, g->stats, g->sums, g->changed,
-                    g->tmp_plane, g->cand, g->bstart, g->brlctl, g->corder};
+                    g->tmp_plane, g->cand, g->bstart, g->brlctl, g->corder, g->plists};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (g->reginst) (void)hipFree(g->reginst);
@@ -819,6 +821,13 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         g->corder_host = ord;
         g->corder_ncol = ncol;
     }
+    if (colored && learned) {
+        // phase lists of the learned colour phases: every colour padded to the longest
+        int maxc = 0;
+        for (int c = 0; c < ncol; c++) maxc = std::max(maxc, g->cstart[c + 1] - g->cstart[c]);
+        if (!g->plists && !ok(dalloc(&g->plists, (size_t)mfd::kMaxColours * g->G.nreg))) return MF_E_NOMEM;
+        g->phase_maxc = maxc;
+    }
     // a check interval counts sweeps; a sweep of the colour schedule is ncol phases
     check_every *= ncol;
     // labels: region distances below dinf = |B| (ARD), or distances below dinf = n (PRD)
@@ -932,8 +941,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         }
         // one batch of check_every sweeps; sweep parity selects the buffers
         // colour phase order of the current sweep (colour mode): fixed, or by
-        // the learned scores when the learned schedule drives the phases
-        const std::vector<int> &corderHost = g->corder_host;
+        // the learned scores when the learned schedule drives the phases (then
+        // the phase lists are built on the device)
         std::vector<int> cperm(ncol);
         for (int c = 0; c < ncol; c++) cperm[c] = c;
         auto enqueue_batch = [&](long long first, int count) -> bool {
@@ -984,27 +993,25 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                             D.order = g->lorder;
                         } else {
                             // Alg. 1 lets the order matter: the colours run in
-                            // descending predicted progress of their active regions
-                            std::vector<float> sc(G.nreg);
-                            std::vector<int> act(G.nreg);
-                            if (!ok(hipMemcpyAsync(sc.data(), g->score, sizeof(float) * G.nreg,
-                                                   hipMemcpyDeviceToHost, s)) ||
-                                !ok(hipMemcpyAsync(act.data(), g->ractive, sizeof(int) * G.nreg,
-                                                   hipMemcpyDeviceToHost, s)) ||
-                                !ok(hipStreamSynchronize(s)))
-                                return false;
-                            std::vector<double> prog(ncol, 0.0);
-                            for (int c = 0; c < ncol; c++)
-                                for (int i = g->cstart[c]; i < g->cstart[c + 1]; i++) {
-                                    int r = corderHost[i];
-                                    if (act[r]) prog[c] += 1.0 / (1.0 + std::exp(-(double)sc[r]));
-                                }
-                            std::stable_sort(cperm.begin(), cperm.end(),
-                                             [&](int a, int b) { return prog[a] > prog[b]; });
+                            // descending predicted progress of their active regions,
+                            // ordered on the device (no host round trip per sweep)
+                            mfd::PhaseArgs PA;
+                            memset(&PA, 0, sizeof(PA));
+                            PA.ncol = ncol;
+                            for (int c = 0; c <= ncol; c++) PA.cstart[c] = g->cstart[c];
+                            PA.maxC = g->phase_maxc;
+                            PA.corder = g->corder;
+                            PA.ractive = g->ractive;
+                            PA.score = g->score;
+                            PA.out = g->plists;
+                            if (!ok(mfd::launch_phase_lists(PA, s))) return false;
                         }
                     }
                 }
-                if (colored) {
+                if (colored && learned) {
+                    D.order = g->plists + (size_t)phase * g->phase_maxc;
+                    D.nwork = g->phase_maxc;
+                } else if (colored) {
                     const int c = cperm[phase];
                     D.order = g->corder + g->cstart[c];
                     D.nwork = g->cstart[c + 1] - g->cstart[c];

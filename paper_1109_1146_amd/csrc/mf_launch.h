@@ -79,6 +79,18 @@ struct SchedArgs {
     const int *regionTicks;  // duration of each region's last discharge: longest first
 };
 
+constexpr int kMaxColours = 4;  // colour classes of the region grid (Alg. 1 as phases)
+
+struct PhaseArgs {
+    int ncol;
+    int cstart[kMaxColours + 1];  // colour c holds corder[cstart[c] .. cstart[c + 1])
+    int maxC;                     // the longest colour: entries per phase list
+    const int *corder;
+    const int *ractive;
+    const float *score;           // [nreg] logits of the learned schedule
+    int *out;                     // [ncol][maxC] region lists by phase
+};
+
 struct FuseArgs {
     Geo G;
     const int *bidx;
@@ -194,6 +206,7 @@ hipError_t launch_bce(const float *z, const float *t, const float *m, int n, flo
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, int n, float lr, float b1, float b2,
                        float eps, float c1, float c2, hipStream_t s);
 hipError_t launch_sched_queue(const SchedArgs &A, hipStream_t s);
+hipError_t launch_phase_lists(const PhaseArgs &A, hipStream_t s);
 
 hipError_t launch_validate(const Geo &G, const int *cs, const int *ct, const int *nbr, int n,
                            int *err, hipStream_t s);

@@ -251,13 +251,13 @@ __global__ void k_adam(float *p, const float *g, float *m, float *v, int n, floa
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// Queue for a learned sweep: regions sorted by score, descending, active
-// first; an active region scoring below the threshold is deferred unless it
-// was deferred max_defer times in a row.  One workgroup (bitonic sort in LDS).
-// Queue of the sweep, by counting sort over classes (largest first): regions to
-// discharge by their previous discharge time (log2 buckets, longest first),
-// then deferred regions (skipped at once), then inactive ones.  Order inside a
-// class is arbitrary; the result of a sweep does not depend on the order.
+// Queue of a learned sweep, one workgroup: an active region whose predicted
+// probability of progress is below the threshold is deferred, unless it was
+// deferred max_defer times in a row.  A counting sort over classes (largest
+// first) then lists the regions to discharge by their previous discharge time
+// (log2 buckets, longest first), then the deferred regions (skipped at once),
+// then the inactive ones.  Order inside a class is arbitrary; the result of a
+// sweep does not depend on the order.
 constexpr int kQueueBuckets = 34;  // 0 inactive, 1 deferred, 2 + log2(ticks) active
 
 __global__ void k_sched_queue(SchedArgs A) {
@@ -294,7 +294,58 @@ __global__ void k_sched_queue(SchedArgs A) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) A.order[atomicAdd(&off[cls[i]], 1)] = i;
 }
 
+// Phase lists of the learned colour phases (Alg. 1), one workgroup: the
+// colours in descending order of the predicted progress summed over their
+// active regions (ties keep the colour order), and for phase q the regions of
+// its colour followed by -1 up to the longest colour (a region kernel stops at
+// the first -1).  Sums in a fixed order, so the phase order is reproducible.
+__global__ void k_phase_lists(PhaseArgs A) {
+    __shared__ float s_part[kMaxColours][16];
+    __shared__ int s_perm[kMaxColours];
+    const int tid = threadIdx.x, nw = blockDim.x >> 6;
+    for (int c = 0; c < A.ncol; c++) {
+        float acc = 0.f;
+        for (int i = A.cstart[c] + tid; i < A.cstart[c + 1]; i += blockDim.x) {
+            const int r = A.corder[i];
+            if (A.ractive[r]) acc += 1.f / (1.f + expf(-A.score[r]));
+        }
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if ((tid & 63) == 0) s_part[c][tid >> 6] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float prog[kMaxColours];
+        for (int c = 0; c < A.ncol; c++) {
+            float t = 0.f;
+            for (int w = 0; w < nw; w++) t += s_part[c][w];
+            prog[c] = t;
+            s_perm[c] = c;
+        }
+        // insertion sort, descending, stable
+        for (int a = 1; a < A.ncol; a++) {
+            const int c = s_perm[a];
+            int b = a - 1;
+            while (b >= 0 && prog[s_perm[b]] < prog[c]) {
+                s_perm[b + 1] = s_perm[b];
+                b--;
+            }
+            s_perm[b + 1] = c;
+        }
+    }
+    __syncthreads();
+    for (int q = 0; q < A.ncol; q++) {
+        const int c = s_perm[q], lo = A.cstart[c], len = A.cstart[c + 1] - lo;
+        for (int i = tid; i < A.maxC; i += blockDim.x) A.out[q * A.maxC + i] = i < len ? A.corder[lo + i] : -1;
+    }
+}
+
 static inline int cdiv_s(long long a, int b) { return (int)((a + b - 1) / b); }
+
+hipError_t launch_phase_lists(const PhaseArgs &A, hipStream_t s) {
+    if (A.ncol < 1 || A.ncol > kMaxColours) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_phase_lists, dim3(1), dim3(1024), 0, s, A);
+    return hipGetLastError();
+}
 
 hipError_t launch_conv3_fwd(const float *x, int xs, int cin, const float *w, const float *b, int cout,
                             float *y, int D, int H, int W, int relu, int bf16, int roundIn, hipStream_t s) {
