@@ -19,6 +19,8 @@
 //   gid[nv]      the vertex's number in the caller's network
 //   -- state (written back when a streamed page leaves the device) --
 //   res[na]      residual capacity of an arc inside the region
+//   rres[na]     residual capacity of its reverse arc (res[rev[a]], kept beside
+//                the arc so that a backward search reads it with the head)
 //   ex[nv], rt[nv], lab[nv], mk[nv]  excess, residual t-link, label, cut mark
 //
 // Boundary table: boundary vertices get slots numbered region by region; pair
@@ -44,7 +46,7 @@ using mfd::kInf;
 typedef unsigned long long u64;
 
 struct Layout {
-    int off, head, rev, gid, res, ex, rt, lab, mk, words;
+    int off, head, rev, gid, res, rres, ex, rt, lab, mk, words;
 };
 
 __host__ __device__ inline Layout layout_of(int nv, int na) {
@@ -54,7 +56,8 @@ __host__ __device__ inline Layout layout_of(int nv, int na) {
     L.rev = L.head + na;
     L.gid = L.rev + na;
     L.res = L.gid + nv;
-    L.ex = L.res + na;
+    L.rres = L.res + na;
+    L.ex = L.rres + na;
     L.rt = L.ex + nv;
     L.lab = L.rt + nv;
     L.mk = L.lab + nv;
@@ -129,7 +132,7 @@ __device__ __forceinline__ int gmin(int x) {
     return x;
 }
 
-constexpr int kScratchInts = 5;  // per vertex of the largest region, per workgroup
+constexpr int kScratchInts = 6;  // per vertex of the largest region, per workgroup
 
 // ---------------------------------------------------------------------------
 // Region discharge, Proc. ARD (Sec. 4.2) on a region page.  As on grids, the
@@ -162,16 +165,19 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
     int *gs = A.scratch + (size_t)blockIdx.x * kScratchInts * nvmax;
     int *stepEnd = gs, *stepLevel = gs + nvmax;
     int *S, *Q, *M, *offL;
+    unsigned *XB;  // excess vertices at the start of the search, one bit each
     if (LDS) {
         S = smem;
         Q = S + nvmax;
         M = Q + nvmax;
         offL = M + nvmax;
+        XB = (unsigned *)(offL + nvmax + 1);
     } else {
         S = gs + 2 * nvmax;
         Q = gs + 3 * nvmax;
         M = gs + 4 * nvmax;
         offL = nullptr;
+        XB = (unsigned *)(gs + 5 * nvmax);
     }
     const int dinf = A.dinf;
     const int *labOld = A.labOld, *cslot = A.cslot, *blocal = A.blocal;
@@ -184,7 +190,7 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
         const Layout L = layout_of(nv, na);
         int *P = A.pool + (long long)s_slot * A.stride;
         const int *head = P + L.head, *rev = P + L.rev;
-        int *res = P + L.res, *ex = P + L.ex, *rt = P + L.rt, *lab = P + L.lab;
+        int *res = P + L.res, *rres = P + L.rres, *ex = P + L.ex, *rt = P + L.rt, *lab = P + L.lab;
         const int *off = P + L.off;
         if (LDS) {
             for (int l = tid; l <= nv; l += NT) offL[l] = off[l];
@@ -210,12 +216,17 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
                 s_hit = 0;
             }
             __syncthreads();
-            // first level (c_f(u, t) > 0), dead marks, live excess count
+            // first level (c_f(u, t) > 0), dead marks, live excess count, and the
+            // excess bitmap (the excess does not change during a search)
+            for (int i = tid; i < (nv + 31) / 32; i += NT) XB[i] = 0u;
+            __syncthreads();
             int live = 0, hit = 0;
             for (int l = tid; l < nv; l += NT) {
                 const int prev = firstSearch ? kInf : S[l];
                 const bool dead = prev == kDead || (lastComplete && prev == kInf);
-                const bool lv = !dead && ex[l] > 0;
+                const bool hasEx = ex[l] > 0;
+                if (hasEx) atomicOr(&XB[l >> 5], 1u << (l & 31));
+                const bool lv = !dead && hasEx;
                 if (!dead && rt[l] > 0) {
                     S[l] = 0;
                     Q[atomicAdd(&s_qtail, 1)] = l;
@@ -273,9 +284,9 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
                         for (int a = off[v] + lane; a < a1; a += G) {
                             const int u = head[a];
                             if (u < 0 || S[u] != kInf) continue;
-                            if (res[rev[a]] > 0 && atomicCAS(&S[u], kInf, step) == kInf) {
+                            if (rres[a] > 0 && atomicCAS(&S[u], kInf, step) == kInf) {
                                 Q[atomicAdd(&s_qtail, 1)] = u;
-                                if (ex[u] > 0) {
+                                if ((XB[u >> 5] >> (u & 31)) & 1u) {
                                     atomicSub(&s_live, 1);
                                     s_hit = 1;
                                 }
@@ -317,7 +328,7 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
                     if (S[l] != kInf || M[i] != level) continue;
                     S[l] = step;
                     Q[atomicAdd(&s_qtail, 1)] = l;
-                    if (ex[l] > 0) {
+                    if ((XB[l >> 5] >> (l & 31)) & 1u) {
                         atomicSub(&s_live, 1);
                         s_hit = 1;
                     }
@@ -395,8 +406,11 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
                                 cr[x] -= d;
                                 cp[x] += d;
                             } else {
+                                const int ra = rev[a];
                                 res[a] -= d;
-                                res[rev[a]] += d;
+                                rres[a] += d;
+                                res[ra] += d;
+                                rres[ra] -= d;
                                 atomicAdd(&ex[h], d);
                             }
                         }
@@ -533,8 +547,8 @@ __global__ __launch_bounds__(NT) void k_gflood(Args A) {
         const int nv = info.x, na = info.y, b0 = info.z, nb = info.w;
         const Layout L = layout_of(nv, na);
         int *P = A.pool + (long long)s_slot * A.stride;
-        const int *off = P + L.off, *head = P + L.head, *rev = P + L.rev;
-        const int *res = P + L.res, *ex = P + L.ex, *rt = P + L.rt;
+        const int *off = P + L.off, *head = P + L.head;
+        const int *res = P + L.res, *rres = P + L.rres, *ex = P + L.ex, *rt = P + L.rt;
         int *mk = P + L.mk;
         if (tid == 0) s_qtail = 0;
         __syncthreads();
@@ -581,7 +595,7 @@ __global__ __launch_bounds__(NT) void k_gflood(Args A) {
                 for (int a = off[v]; a < a1; a++) {
                     const int w = head[a];
                     if (w < 0 || mk[w]) continue;
-                    const int c = back ? res[rev[a]] : res[a];
+                    const int c = back ? rres[a] : res[a];
                     if (c > 0 && atomicCAS(&mk[w], 0, 1) == 0) Q[atomicAdd(&s_qtail, 1)] = w;
                 }
             }
@@ -1131,6 +1145,8 @@ extern "C" mf_status mf_create_graph(int32_t n, int64_t npairs, const int32_t *p
             pgu[Lu.rev + av] = au;
             pgu[Lu.res + au] = cuv[i];
             pgu[Lu.res + av] = cvu[i];
+            pgu[Lu.rres + au] = cvu[i];
+            pgu[Lu.rres + av] = cuv[i];
             g->pair_loc[i] = ((long long)ru << 32) | (long long)au;
         } else {
             pgu[Lu.head + au] = -(int)(2 * c) - 1;
@@ -1158,7 +1174,8 @@ extern "C" mf_status mf_create_graph(int32_t n, int64_t npairs, const int32_t *p
     g->group = (n > 0 && 2 * npairs >= 12LL * n) ? 32 : 8;
     // the search arrays and row offsets in LDS while two workgroups fit a compute unit
     {
-        const size_t need = sizeof(int) * (4 * (size_t)std::max(g->nvmax, 1) + 1);
+        const size_t nvm = (size_t)std::max(g->nvmax, 1);
+        const size_t need = sizeof(int) * (4 * nvm + 1 + (nvm + 31) / 32);
         const size_t cap = std::min<size_t>(80 * 1024, (size_t)prop.sharedMemPerBlock);
         g->ldsBytes = need <= cap ? need : 0;
         static bool attrs = false;
