@@ -278,20 +278,35 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
                     }
                     if (fs == fe) break;
                     const int step = s_nsteps;
-                    for (int i = fs + grp; i < fe; i += NG) {
-                        const int v = Q[i];
-                        const int a1 = off[v + 1];
-                        for (int a = off[v] + lane; a < a1; a += G) {
-                            const int u = head[a];
-                            if (u < 0 || S[u] != kInf) continue;
-                            if (rres[a] > 0 && atomicCAS(&S[u], kInf, step) == kInf) {
-                                Q[atomicAdd(&s_qtail, 1)] = u;
-                                if ((XB[u >> 5] >> (u & 31)) & 1u) {
-                                    atomicSub(&s_live, 1);
-                                    s_hit = 1;
-                                }
+                    // u joins the level through arc a = (v, u) when c_f(u, v) > 0
+                    auto visit = [&](int u, int c) {
+                        if (u < 0 || c <= 0 || S[u] != kInf) return;
+                        if (atomicCAS(&S[u], kInf, step) == kInf) {
+                            Q[atomicAdd(&s_qtail, 1)] = u;
+                            if ((XB[u >> 5] >> (u & 31)) & 1u) {
+                                atomicSub(&s_live, 1);
+                                s_hit = 1;
                             }
                         }
+                    };
+                    // two frontier vertices per group, their first G arcs loaded together
+                    for (int i = fs + grp; i < fe; i += 2 * NG) {
+                        const int v0 = Q[i], v1 = i + NG < fe ? Q[i + NG] : -1;
+                        const int b0 = off[v0], e0 = off[v0 + 1];
+                        const int b1 = v1 >= 0 ? off[v1] : 0, e1 = v1 >= 0 ? off[v1 + 1] : 0;
+                        int u0 = -1, c0 = 0, u1 = -1, c1 = 0;
+                        if (b0 + lane < e0) {
+                            u0 = head[b0 + lane];
+                            c0 = rres[b0 + lane];
+                        }
+                        if (b1 + lane < e1) {
+                            u1 = head[b1 + lane];
+                            c1 = rres[b1 + lane];
+                        }
+                        visit(u0, c0);
+                        visit(u1, c1);
+                        for (int a = b0 + G + lane; a < e0; a += G) visit(head[a], rres[a]);
+                        for (int a = b1 + G + lane; a < e1; a += G) visit(head[a], rres[a]);
                     }
                     __syncthreads();
                     if (tid == 0) {
@@ -648,7 +663,8 @@ __global__ __launch_bounds__(NT) void k_gcollect(Args A) {
     }
 }
 
-constexpr int kNT = 512;
+constexpr int kNT = 512;    // floods and collection
+constexpr int kDNT = 1024;  // discharge: a few regions at a time are active, each gets a whole compute unit
 
 }  // namespace mfg
 
@@ -855,11 +871,11 @@ mf_status launch_discharge(mf_graph *g, const mfg::Args &base, const int *dlist,
     const int blocks = n >= 0 ? std::max(1, std::min(n, g->blocks)) : g->blocks;
     const size_t lds = g->ldsBytes;
     if (g->group == 32) {
-        if (lds) hipLaunchKernelGGL((mfg::k_gdischarge<mfg::kNT, 32, true>), dim3(blocks), dim3(mfg::kNT), lds, s, A);
-        else hipLaunchKernelGGL((mfg::k_gdischarge<mfg::kNT, 32, false>), dim3(blocks), dim3(mfg::kNT), 0, s, A);
+        if (lds) hipLaunchKernelGGL((mfg::k_gdischarge<mfg::kDNT, 32, true>), dim3(blocks), dim3(mfg::kDNT), lds, s, A);
+        else hipLaunchKernelGGL((mfg::k_gdischarge<mfg::kDNT, 32, false>), dim3(blocks), dim3(mfg::kDNT), 0, s, A);
     } else {
-        if (lds) hipLaunchKernelGGL((mfg::k_gdischarge<mfg::kNT, 8, true>), dim3(blocks), dim3(mfg::kNT), lds, s, A);
-        else hipLaunchKernelGGL((mfg::k_gdischarge<mfg::kNT, 8, false>), dim3(blocks), dim3(mfg::kNT), 0, s, A);
+        if (lds) hipLaunchKernelGGL((mfg::k_gdischarge<mfg::kDNT, 8, true>), dim3(blocks), dim3(mfg::kDNT), lds, s, A);
+        else hipLaunchKernelGGL((mfg::k_gdischarge<mfg::kDNT, 8, false>), dim3(blocks), dim3(mfg::kDNT), 0, s, A);
     }
     if (!ok(hipGetLastError())) return MF_E_DEVICE;
     if (g->profile) {
@@ -1180,9 +1196,9 @@ extern "C" mf_status mf_create_graph(int32_t n, int64_t npairs, const int32_t *p
         g->ldsBytes = need <= cap ? need : 0;
         static bool attrs = false;
         if (!attrs) {
-            (void)hipFuncSetAttribute((const void *)mfg::k_gdischarge<mfg::kNT, 32, true>,
+            (void)hipFuncSetAttribute((const void *)mfg::k_gdischarge<mfg::kDNT, 32, true>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024);
-            (void)hipFuncSetAttribute((const void *)mfg::k_gdischarge<mfg::kNT, 8, true>,
+            (void)hipFuncSetAttribute((const void *)mfg::k_gdischarge<mfg::kDNT, 8, true>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, 80 * 1024);
             attrs = true;
         }
