@@ -76,6 +76,8 @@ def parse():
     p.add_argument("--no-nested", action="store_true",
                    help="464 only: skip the nested 256^3 and general-network records")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-stream", action="store_true",
+                   help="graph only: skip the streamed-pages solves (profiling runs)")
     p.add_argument("--no-learned", action="store_true",
                    help="skip the learned-schedule comparison solves (profiling runs)")
     p.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -346,7 +348,8 @@ def bench_graph(args, steps, warmup, cpu):
         return sum(times) / len(times), out
 
     ms_res, res = run(0, steps, warmup)
-    ms_str, stre = run(GRAPH["pages"], max(1, steps // 2), 0)
+    stream = not getattr(args, "no_stream", False)
+    ms_str, stre = run(GRAPH["pages"], max(1, steps // 2), 0) if stream else (None, None)
     # one profiled solve: the discharge launches timed by HIP events on the solve stream
     g = mf.Graph(inst.n, *inst.arrays(), region=reg)
     try:
@@ -364,17 +367,20 @@ def bench_graph(args, steps, warmup, cpu):
            "push_rounds_per_discharge": round(res["stats"]["push_rounds"] / max(res["stats"]["discharges"], 1), 2),
            "search_levels_per_discharge": round(res["stats"]["search_steps"] / max(res["stats"]["discharges"], 1), 1),
            "flow": res["flow"],
-           "streamed": {"device_pages": GRAPH["pages"], "regions": res["info"]["regions"],
-                        "ms_per_step": round(ms_str * 1e3, 3), "value": round(inst.n / ms_str / 1e6, 3),
-                        "unit": "Mvertices/s (PCIe transfers included)",
-                        "sweeps": stre["stats"]["sweeps"], "pages_in": stre["stats"]["pages_in"],
-                        "pages_out": stre["stats"]["pages_out"],
-                        "bytes_h2d": stre["stats"]["bytes_h2d"], "bytes_d2h": stre["stats"]["bytes_d2h"],
-                        "same_result": bool(stre["flow"] == res["flow"] and (stre["smin"] == res["smin"]).all()
-                                            and (stre["smax"] == res["smax"]).all())},
+           "streamed": None if not stream else {
+               "device_pages": GRAPH["pages"], "regions": res["info"]["regions"],
+               "ms_per_step": round(ms_str * 1e3, 3), "value": round(inst.n / ms_str / 1e6, 3),
+               "unit": "Mvertices/s (PCIe transfers included)",
+               "sweeps": stre["stats"]["sweeps"], "pages_in": stre["stats"]["pages_in"],
+               "pages_out": stre["stats"]["pages_out"],
+               "bytes_h2d": stre["stats"]["bytes_h2d"], "bytes_d2h": stre["stats"]["bytes_d2h"],
+               "same_result": bool(stre["flow"] == res["flow"] and (stre["smin"] == res["smin"]).all()
+                                   and (stre["smax"] == res["smax"]).all())},
            "roofline": {"bound": "hbm", "kernel": "k_gdischarge", "achieved": round(achieved, 3),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                        "traffic": None, "avg_launch_ms": round(d_ms / d_launch, 4),
+                        "traffic": measured_traffic("paper_1109_1146_amd/csrc/mf_graph.hip",
+                                                    "k_gdischarge_graph26_128_traffic.json"),
+                        "avg_launch_ms": round(d_ms / d_launch, 4),
                         "algorithmic_bytes_per_launch": round(d_bytes / d_launch, 1)}}
     if cpu:
         import oracle
