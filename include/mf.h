@@ -496,6 +496,29 @@ mf_status mf_graph_state(mf_graph *g, int64_t *r_uv, int64_t *r_vu, int64_t *rt,
                          int32_t *labels);
 void mf_graph_destroy(mf_graph *g);
 
+/* A DIMACS max-flow file ("p max n m", "n id s", "n id t", "a u v cap", "c"
+ * comments; the problem files of the paper's experiments, Sec. 7.2) as the arrays of
+ * mf_create_graph, owned by the library (mf_free_dimacs releases them).  The
+ * vertices other than s and t become 0 .. n-1 in increasing file id
+ * (vertex_id[i] is the file id of vertex i); an arc s -> v adds to c(s, v), an
+ * arc v -> t to c(v, t), an arc s -> t to st_capacity (flow that every maximum
+ * flow carries: add it to mf_graph_flow_value); every other arc u -> v becomes
+ * a pair with c(u, v) = cap and c(v, u) = 0; arcs into s, out of t and from a
+ * vertex to itself carry no s-t flow and are dropped.  Host code only.
+ * Errors: MF_E_INVAL (unreadable file, a malformed line, an id out of range,
+ * no or equal s and t, an arc count other than the problem line's),
+ * MF_E_OVERFLOW (a capacity, or a vertex's summed s- or t-link, above
+ * 2^31 - 1), MF_E_NOMEM. */
+typedef struct {
+    int32_t n;
+    int64_t npairs;
+    int32_t *pu, *pv, *cuv, *cvu, *cs, *ct;
+    int64_t st_capacity;
+    int64_t *vertex_id;
+} mf_dimacs;
+mf_status mf_read_dimacs(const char *path, mf_dimacs **out);
+void mf_free_dimacs(mf_dimacs *d);
+
 void mf_destroy(mf_grid *g);
 const char *mf_status_str(mf_status s);
 

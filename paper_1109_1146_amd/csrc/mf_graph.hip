@@ -1484,3 +1484,150 @@ extern "C" int64_t mf_graph_discharge_bytes(int64_t nv, int64_t na) {
     // written: lab (nv)
     return 4 * ((nv + 1) + 2 * na + 2 * (na + 2 * nv) + nv);
 }
+
+// ---------------------------------------------------------------------------
+// DIMACS max-flow files (the format of the paper's instances).
+// ---------------------------------------------------------------------------
+#include <cstdio>
+#include <cstdlib>
+
+namespace {
+
+void free_dimacs_arrays(mf_dimacs *d) {
+    if (!d) return;
+    free(d->pu);
+    free(d->pv);
+    free(d->cuv);
+    free(d->cvu);
+    free(d->cs);
+    free(d->ct);
+    free(d->vertex_id);
+}
+
+// Reads the next integer of line p (after whitespace); false at the end.
+bool next_int(const char *&p, long long &v) {
+    while (*p == ' ' || *p == '\t') p++;
+    if (!(*p == '-' || (*p >= '0' && *p <= '9'))) return false;
+    char *end = nullptr;
+    v = strtoll(p, &end, 10);
+    if (end == p) return false;
+    p = end;
+    return true;
+}
+
+}  // namespace
+
+extern "C" mf_status mf_read_dimacs(const char *path, mf_dimacs **out) {
+    if (!path || !out) return MF_E_INVAL;
+    *out = nullptr;
+    FILE *f = fopen(path, "r");
+    if (!f) return MF_E_INVAL;
+    long long N = -1, M = -1, src = -1, snk = -1;
+    std::vector<long long> au, av, ac;
+    char *line = nullptr;
+    size_t cap = 0;
+    mf_status st = MF_OK;
+    while (st == MF_OK && getline(&line, &cap, f) >= 0) {
+        const char *p = line;
+        while (*p == ' ' || *p == '\t') p++;
+        if (*p == 'c' || *p == '\n' || *p == '\r' || *p == '\0') continue;
+        const char kind = *p++;
+        if (kind == 'p') {
+            while (*p == ' ' || *p == '\t') p++;
+            if (strncmp(p, "max", 3) != 0 || N >= 0) { st = MF_E_INVAL; break; }
+            p += 3;
+            if (!next_int(p, N) || !next_int(p, M) || N < 2 || M < 0 || N > 0x7fffffffLL) st = MF_E_INVAL;
+        } else if (kind == 'n') {
+            long long id;
+            if (N < 0 || !next_int(p, id) || id < 1 || id > N) { st = MF_E_INVAL; break; }
+            while (*p == ' ' || *p == '\t') p++;
+            if (*p == 's') src = id;
+            else if (*p == 't') snk = id;
+            else st = MF_E_INVAL;
+        } else if (kind == 'a') {
+            long long u, v, c;
+            if (N < 0 || !next_int(p, u) || !next_int(p, v) || !next_int(p, c) || u < 1 || u > N || v < 1 ||
+                v > N || c < 0) {
+                st = MF_E_INVAL;
+                break;
+            }
+            if (c > 0x7fffffffLL) { st = MF_E_OVERFLOW; break; }
+            au.push_back(u);
+            av.push_back(v);
+            ac.push_back(c);
+        } else {
+            st = MF_E_INVAL;
+        }
+    }
+    free(line);
+    fclose(f);
+    if (st != MF_OK) return st;
+    if (N < 0 || src < 0 || snk < 0 || src == snk || (long long)au.size() != M) return MF_E_INVAL;
+    // vertices other than s and t, numbered in increasing file id
+    const int32_t n = (int32_t)(N - 2);
+    std::vector<int32_t> idx((size_t)N + 1, -1);
+    mf_dimacs *d = (mf_dimacs *)calloc(1, sizeof(mf_dimacs));
+    if (!d) return MF_E_NOMEM;
+    d->n = n;
+    d->vertex_id = (int64_t *)malloc(sizeof(int64_t) * (size_t)std::max(n, 1));
+    d->cs = (int32_t *)calloc((size_t)std::max(n, 1), sizeof(int32_t));
+    d->ct = (int32_t *)calloc((size_t)std::max(n, 1), sizeof(int32_t));
+    if (!d->vertex_id || !d->cs || !d->ct) {
+        free_dimacs_arrays(d);
+        free(d);
+        return MF_E_NOMEM;
+    }
+    for (long long id = 1, k = 0; id <= N; id++)
+        if (id != src && id != snk) {
+            idx[id] = (int32_t)k;
+            d->vertex_id[k++] = id;
+        }
+    std::vector<long long> cs64((size_t)std::max(n, 1), 0), ct64((size_t)std::max(n, 1), 0);
+    std::vector<int32_t> pu, pv, cuv;
+    long long st_cap = 0;
+    for (size_t i = 0; i < au.size(); i++) {
+        const long long u = au[i], v = av[i], c = ac[i];
+        if (u == v || u == snk || v == src) continue;  // arcs that carry no s-t flow
+        if (u == src && v == snk) st_cap += c;
+        else if (u == src) cs64[idx[v]] += c;
+        else if (v == snk) ct64[idx[u]] += c;
+        else {
+            pu.push_back(idx[u]);
+            pv.push_back(idx[v]);
+            cuv.push_back((int32_t)c);
+        }
+    }
+    for (int32_t v = 0; v < n; v++) {
+        if (cs64[v] > 0x7fffffffLL || ct64[v] > 0x7fffffffLL) {
+            free_dimacs_arrays(d);
+            free(d);
+            return MF_E_OVERFLOW;
+        }
+        d->cs[v] = (int32_t)cs64[v];
+        d->ct[v] = (int32_t)ct64[v];
+    }
+    const size_t m = pu.size();
+    d->npairs = (int64_t)m;
+    d->st_capacity = st_cap;
+    d->pu = (int32_t *)malloc(sizeof(int32_t) * std::max(m, (size_t)1));
+    d->pv = (int32_t *)malloc(sizeof(int32_t) * std::max(m, (size_t)1));
+    d->cuv = (int32_t *)malloc(sizeof(int32_t) * std::max(m, (size_t)1));
+    d->cvu = (int32_t *)calloc(std::max(m, (size_t)1), sizeof(int32_t));
+    if (!d->pu || !d->pv || !d->cuv || !d->cvu) {
+        free_dimacs_arrays(d);
+        free(d);
+        return MF_E_NOMEM;
+    }
+    if (m) {
+        memcpy(d->pu, pu.data(), sizeof(int32_t) * m);
+        memcpy(d->pv, pv.data(), sizeof(int32_t) * m);
+        memcpy(d->cuv, cuv.data(), sizeof(int32_t) * m);
+    }
+    *out = d;
+    return MF_OK;
+}
+
+extern "C" void mf_free_dimacs(mf_dimacs *d) {
+    free_dimacs_arrays(d);
+    free(d);
+}

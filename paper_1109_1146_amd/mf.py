@@ -34,7 +34,8 @@ EXPORTED = ("mf_create_grid", "mf_set_caps", "mf_solve", "mf_flow_value", "mf_mi
             "mf_model_loss_grad", "mf_model_adam_step", "mf_boundary_relabel", "mf_region_relabel",
             "mf_global_relabel", "mf_model_forward_noalloc", "mf_region_reduction",
             "mf_create_graph", "mf_graph_get_info", "mf_graph_solve", "mf_graph_flow_value",
-            "mf_graph_min_cut", "mf_graph_state", "mf_graph_destroy", "mf_graph_discharge_bytes")
+            "mf_graph_min_cut", "mf_graph_state", "mf_graph_destroy", "mf_graph_discharge_bytes",
+            "mf_read_dimacs", "mf_free_dimacs")
 
 
 class mf_solve_opts(ctypes.Structure):
@@ -87,6 +88,14 @@ class mf_graph_stats(ctypes.Structure):
                 ("bytes_h2d", ctypes.c_int64), ("bytes_d2h", ctypes.c_int64), ("ms", ctypes.c_double),
                 ("discharged_vertices", ctypes.c_int64), ("discharged_arcs", ctypes.c_int64),
                 ("discharge_launches", ctypes.c_int64), ("discharge_ms", ctypes.c_double)]
+
+
+class mf_dimacs(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("npairs", ctypes.c_int64),
+                ("pu", ctypes.POINTER(ctypes.c_int32)), ("pv", ctypes.POINTER(ctypes.c_int32)),
+                ("cuv", ctypes.POINTER(ctypes.c_int32)), ("cvu", ctypes.POINTER(ctypes.c_int32)),
+                ("cs", ctypes.POINTER(ctypes.c_int32)), ("ct", ctypes.POINTER(ctypes.c_int32)),
+                ("st_capacity", ctypes.c_int64), ("vertex_id", ctypes.POINTER(ctypes.c_int64))]
 
 
 class MFError(RuntimeError):
@@ -191,6 +200,10 @@ def load(path: str = LIB_PATH):
     lib.mf_graph_destroy.restype = None
     lib.mf_graph_discharge_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64]
     lib.mf_graph_discharge_bytes.restype = ctypes.c_int64
+    lib.mf_read_dimacs.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.POINTER(mf_dimacs))]
+    lib.mf_read_dimacs.restype = ctypes.c_int
+    lib.mf_free_dimacs.argtypes = [ctypes.POINTER(mf_dimacs)]
+    lib.mf_free_dimacs.restype = None
     _lib = lib
     return lib
 
@@ -610,3 +623,23 @@ def solve_graph(inst, region=None, region_size=4096, device_pages=0, **solve_kw)
 
 def graph_discharge_bytes(nv, na) -> int:
     return int(load().mf_graph_discharge_bytes(int(nv), int(na)))
+
+
+def read_dimacs(path):
+    """A DIMACS max-flow file through the library's reader (mf_read_dimacs): a
+    dict with n, the pair arrays pu, pv, cuv, cvu, the t-links cs, ct (numpy
+    int32 copies), st_capacity (flow of the arcs from s straight to t) and
+    vertex_id (the file id of every vertex)."""
+    lib = load()
+    d = ctypes.POINTER(mf_dimacs)()
+    _check(lib.mf_read_dimacs(str(path).encode(), ctypes.byref(d)), "mf_read_dimacs")
+    try:
+        r = d.contents
+        n, m = int(r.n), int(r.npairs)
+        arr = lambda ptr, k: np.ctypeslib.as_array(ptr, shape=(k,)).copy() if k else np.zeros(0, np.int32)
+        out = dict(n=n, pu=arr(r.pu, m), pv=arr(r.pv, m), cuv=arr(r.cuv, m), cvu=arr(r.cvu, m),
+                   cs=arr(r.cs, n), ct=arr(r.ct, n), st_capacity=int(r.st_capacity),
+                   vertex_id=(np.ctypeslib.as_array(r.vertex_id, shape=(n,)).copy() if n else np.zeros(0, np.int64)))
+    finally:
+        lib.mf_free_dimacs(d)
+    return out

@@ -149,3 +149,34 @@ def test_sweep_guard_then_resume(mf):
         assert st["sweeps"] >= 2
         assert g.flow_value() == ref["flow"]
         assert (g.min_cut(mf.MF_CUT_MAX_SOURCE) == ref["smax"]).all()
+
+
+def test_dimacs_file_end_to_end(mf, tmp_path):
+    """A DIMACS max-flow file (the problem files of the paper's experiments):
+    read by the library, split into regions and solved on the GPU; the flow
+    plus the s -> t arcs equals the oracle's, and so do both cuts."""
+    inst = synth.random_graph(3000, 6, 8700, long_frac=0.1, shuffle=False)
+    s_id, t_id = 1, inst.n + 2  # the file numbers s first and t last
+    lines = [f"p max {inst.n + 2} 0"]
+    arcs = []
+    for u, v, a, b in zip(inst.pu, inst.pv, inst.cuv, inst.cvu):
+        arcs.append((int(u) + 2, int(v) + 2, int(a)))
+        arcs.append((int(v) + 2, int(u) + 2, int(b)))
+    for v in range(inst.n):
+        if inst.cs[v]:
+            arcs.append((s_id, v + 2, int(inst.cs[v])))
+        if inst.ct[v]:
+            arcs.append((v + 2, t_id, int(inst.ct[v])))
+    arcs.append((s_id, t_id, 11))
+    lines[0] = f"p max {inst.n + 2} {len(arcs)}"
+    lines += [f"n {s_id} s", f"n {t_id} t"] + [f"a {u} {v} {c}" for u, v, c in arcs]
+    path = tmp_path / "net.max"
+    path.write_text("\n".join(lines) + "\n")
+    d = mf.read_dimacs(path)
+    assert d["n"] == inst.n and d["st_capacity"] == 11
+    ref = oracle.solve_pairs(inst.n, *inst.arrays())
+    with mf.Graph(d["n"], d["pu"], d["pv"], d["cuv"], d["cvu"], d["cs"], d["ct"], region_size=250) as g:
+        g.solve()
+        assert g.flow_value() + d["st_capacity"] == ref["flow"] + 11
+        assert (g.min_cut(mf.MF_CUT_MIN_SOURCE) == ref["smin"]).all()
+        assert (g.min_cut(mf.MF_CUT_MAX_SOURCE) == ref["smax"]).all()

@@ -92,3 +92,77 @@ def test_grid26_graph_is_the_26_neighbourhood():
     a = oracle.solve_pairs(g.n, *g.arrays())
     b = oracle.solve_pairs(g.n, *g.arrays(), method="dinic")
     assert a["flow"] == b["flow"] and (a["smin"] == b["smin"]).all() and (a["smax"] == b["smax"]).all()
+
+
+def _write_dimacs(path, N, s, t, arcs, comment=True):
+    with open(path, "w") as f:
+        if comment:
+            f.write("c a max-flow problem\n")
+        f.write(f"p max {N} {len(arcs)}\n")
+        f.write(f"n {s} s\nn {t} t\n")
+        for u, v, c in arcs:
+            f.write(f"a {u} {v} {c}\n")
+
+
+def _random_dimacs(seed, N=40, m=160):
+    rng = np.random.default_rng(seed)
+    s, t = (int(x) for x in rng.choice(np.arange(1, N + 1), size=2, replace=False))
+    arcs = []
+    for _ in range(m):
+        u, v = (int(x) for x in rng.integers(1, N + 1, size=2))
+        arcs.append((u, v, int(rng.integers(0, 30))))
+    # every special kind of arc at least once
+    arcs += [(s, t, 7), (t, s, 5), (s, s, 3), (t, 1 if t != 1 else 2, 4)]
+    return N, s, t, arcs
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_dimacs_reader_keeps_the_max_flow(mf, tmp_path, seed):
+    """The reader's pair form (s- and t-links, s -> t arcs as a constant) has the
+    maximum flow of the file's network, computed here on the file's own arcs by
+    scipy's maximum_flow, and the vertex numbering is the file's ids without s
+    and t in increasing order."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import maximum_flow
+    N, s, t, arcs = _random_dimacs(seed)
+    path = tmp_path / "g.max"
+    _write_dimacs(path, N, s, t, arcs)
+    d = mf.read_dimacs(path)
+    assert d["n"] == N - 2
+    assert list(d["vertex_id"]) == [i for i in range(1, N + 1) if i not in (s, t)]
+    assert d["st_capacity"] == sum(c for u, v, c in arcs if u == s and v == t)
+    # the file's network, parallel arcs summed, self-arcs dropped
+    cap = {}
+    for u, v, c in arcs:
+        if u != v:
+            cap[(u - 1, v - 1)] = cap.get((u - 1, v - 1), 0) + c
+    rows, cols, vals = zip(*[(u, v, c) for (u, v), c in cap.items()])
+    g = csr_matrix((np.array(vals, np.int32), (np.array(rows), np.array(cols))), shape=(N, N))
+    want = maximum_flow(g, s - 1, t - 1).flow_value
+    got = oracle.solve_pairs(d["n"], d["pu"], d["pv"], d["cuv"], d["cvu"], d["cs"], d["ct"])["flow"]
+    assert got + d["st_capacity"] == want
+
+
+@pytest.mark.parametrize("case", ["no_problem", "bad_arc", "id_range", "count", "no_sink", "huge_cap",
+                                  "missing_file"])
+def test_dimacs_reader_rejects_bad_files(mf, tmp_path, case):
+    path = tmp_path / "bad.max"
+    status = mf.MF_E_INVAL
+    if case == "no_problem":
+        path.write_text("n 1 s\nn 2 t\na 1 2 3\n")
+    elif case == "bad_arc":
+        path.write_text("p max 3 1\nn 1 s\nn 2 t\na 1 x 3\n")
+    elif case == "id_range":
+        path.write_text("p max 3 1\nn 1 s\nn 2 t\na 1 4 3\n")
+    elif case == "count":
+        path.write_text("p max 3 2\nn 1 s\nn 2 t\na 1 3 3\n")
+    elif case == "no_sink":
+        path.write_text("p max 3 1\nn 1 s\na 1 3 3\n")
+    elif case == "huge_cap":
+        path.write_text("p max 3 1\nn 1 s\nn 2 t\na 1 3 3000000000\n")
+        status = mf.MF_E_OVERFLOW
+    else:
+        path = tmp_path / "absent.max"
+    with pytest.raises(mf.MFError) as e:
+        mf.read_dimacs(path)
+    assert e.value.status == status
