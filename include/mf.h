@@ -429,7 +429,7 @@ typedef struct mf_graph mf_graph; /* opaque, owned by the library */
 
 typedef struct {
     int64_t n, npairs;           /* vertices and pairs of the network */
-    int64_t regions;             /* 1 + the largest region number */
+    int64_t regions;             /* distinct region numbers (or blocks of region_size vertices) */
     int64_t boundary_size;       /* |B|: vertices with a pair into another region; d_inf = max(|B|, 1) */
     int64_t boundary_pairs;      /* pairs between two regions */
     int64_t page_words;          /* int32 words per page slot (the largest region's page) */
@@ -465,8 +465,9 @@ int64_t mf_graph_discharge_bytes(int64_t nv, int64_t na);
  * arrays, read during the call only): pair i joins pu[i] != pv[i] (both in
  * [0, n)) with c(pu, pv) = cuv[i] and c(pv, pu) = cvu[i]; cs[v] = c(s, v) and
  * ct[v] = c(v, t); all int32 >= 0; several pairs may join the same vertices.
- * region[v] >= 0 is the region of v (any assignment), or region == NULL for
- * regions of region_size consecutive vertex numbers.  device_pages: 0 (or at
+ * region[v] >= 0 is the region of v (any assignment; the numbers need not be
+ * dense), or region == NULL for regions of region_size consecutive vertex
+ * numbers.  device_pages: 0 (or at
  * least the number of regions) keeps every page in device memory; 1 or more
  * streams the pages through that many device page slots.  The initial preflow
  * (Sec. 2: every s-link saturated, labels 0) is written into the pages.

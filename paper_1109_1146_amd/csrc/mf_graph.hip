@@ -1013,7 +1013,7 @@ mf_status collect(mf_graph *g, int mode, unsigned char *cut, long long *sumRt) {
 
 }  // namespace
 
-extern "C" mf_status mf_create_graph(int32_t n, int64_t npairs, const int32_t *pu, const int32_t *pv,
+static mf_status mf_create_graph_impl(int32_t n, int64_t npairs, const int32_t *pu, const int32_t *pv,
                                      const int32_t *cuv, const int32_t *cvu, const int32_t *cs,
                                      const int32_t *ct, const int32_t *region, int32_t region_size,
                                      int64_t device_pages, mf_graph **out) {
@@ -1040,17 +1040,34 @@ extern "C" mf_status mf_create_graph(int32_t n, int64_t npairs, const int32_t *p
     }
     for (int32_t v = 0; v < n; v++)
         if (inflow[v] > 0x7fffffffLL) return MF_E_OVERFLOW;  // bounds the excess of v
-    // ---- regions
+    // ---- regions: the caller's region numbers renumbered densely in increasing
+    // order (any numbers >= 0 are allowed), or blocks of region_size vertices
     std::vector<int> reg((size_t)n);
     int K = 0;
-    for (int32_t v = 0; v < n; v++) {
-        const long long r = region ? (long long)region[v] : (long long)(v / region_size);
-        if (r < 0 || r >= 0x7fffffffLL) return MF_E_INVAL;
-        reg[v] = (int)r;
-        K = std::max(K, (int)r + 1);
+    if (region) {
+        std::vector<int32_t> ids(region, region + n);
+        std::sort(ids.begin(), ids.end());
+        ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+        if (!ids.empty() && ids[0] < 0) return MF_E_INVAL;
+        K = (int)ids.size();
+        for (int32_t v = 0; v < n; v++)
+            reg[v] = (int)(std::lower_bound(ids.begin(), ids.end(), region[v]) - ids.begin());
+    } else {
+        for (int32_t v = 0; v < n; v++) reg[v] = v / region_size;
+        K = n > 0 ? (int)((n - 1) / region_size + 1) : 0;
     }
     mf_graph *g = new (std::nothrow) mf_graph;
     if (!g) return MF_E_NOMEM;
+    // a host allocation that fails below throws: the handle is released on the way out
+    struct Guard {
+        mf_graph *g;
+        ~Guard() {
+            if (g) {
+                free_graph(g);
+                delete g;
+            }
+        }
+    } guard{g};
     g->n = n;
     g->np = npairs;
     g->K = K;
@@ -1097,7 +1114,6 @@ extern "C" mf_status mf_create_graph(int32_t n, int64_t npairs, const int32_t *p
     for (int r = 0; r < K; r++) {
         for (int v : members[r]) na[r] += deg[v];
         if (na[r] > 0x3fffffffLL / 4) {
-            delete g;
             return MF_E_INVAL;  // 32-bit offsets inside a page
         }
         const Layout L = layout_of(nv[r], (int)na[r]);
@@ -1118,7 +1134,6 @@ extern "C" mf_status mf_create_graph(int32_t n, int64_t npairs, const int32_t *p
         hp = store.data();
     } else {
         if (!ok(hipHostMalloc((void **)&g->hpages, std::max(storeWords, (size_t)1) * sizeof(int), 0))) {
-            delete g;
             return MF_E_NOMEM;
         }
         memset(g->hpages, 0, storeWords * sizeof(int));
@@ -1181,8 +1196,6 @@ extern "C" mf_status mf_create_graph(int32_t n, int64_t npairs, const int32_t *p
     // ---- device
     hipDeviceProp_t prop;
     if (!ok(hipGetDevice(&g->device)) || !ok(hipGetDeviceProperties(&prop, g->device))) {
-        free_graph(g);
-        delete g;
         return MF_E_DEVICE;
     }
     g->numCU = prop.multiProcessorCount;
@@ -1230,8 +1243,6 @@ extern "C" mf_status mf_create_graph(int32_t n, int64_t npairs, const int32_t *p
            ok(dalloc(&g->cutbuf, (size_t)n)) &&
            ok(hipHostMalloc(&g->pinned, sizeof(int) * (16 + (size_t)K), 0));
     if (!good) {
-        free_graph(g);
-        delete g;
         return MF_E_NOMEM;
     }
     std::vector<int> allreg_h(K);
@@ -1262,10 +1273,9 @@ extern "C" mf_status mf_create_graph(int32_t n, int64_t npairs, const int32_t *p
         good = ok(hipMemcpyAsync(g->pool, hp, storeWords * sizeof(int), hipMemcpyHostToDevice, s));
     good = good && ok(hipStreamSynchronize(s));
     if (!good) {
-        free_graph(g);
-        delete g;
         return MF_E_DEVICE;
     }
+    guard.g = nullptr;
     *out = g;
     return MF_OK;
 }
@@ -1293,7 +1303,7 @@ extern "C" mf_status mf_graph_get_info(const mf_graph *g, mf_graph_info *info) {
     return MF_OK;
 }
 
-extern "C" mf_status mf_graph_solve(mf_graph *g, const mf_graph_opts *opts, mf_graph_stats *st) {
+static mf_status mf_graph_solve_impl(mf_graph *g, const mf_graph_opts *opts, mf_graph_stats *st) {
     if (!g) return MF_E_INVAL;
     mf_graph_opts o;
     memset(&o, 0, sizeof(o));
@@ -1406,7 +1416,7 @@ extern "C" mf_status mf_graph_flow_value(const mf_graph *g, int64_t *out) {
     return MF_OK;
 }
 
-extern "C" mf_status mf_graph_min_cut(mf_graph *g, int32_t kind, uint8_t *out_source_side) {
+static mf_status mf_graph_min_cut_impl(mf_graph *g, int32_t kind, uint8_t *out_source_side) {
     if (!g || !out_source_side) return MF_E_INVAL;
     if (kind != MF_CUT_MIN_SOURCE && kind != MF_CUT_MAX_SOURCE) return MF_E_INVAL;
     if (!g->solved) return MF_E_STATE;
@@ -1422,7 +1432,7 @@ extern "C" mf_status mf_graph_min_cut(mf_graph *g, int32_t kind, uint8_t *out_so
     return MF_OK;
 }
 
-extern "C" mf_status mf_graph_state(mf_graph *g, int64_t *r_uv, int64_t *r_vu, int64_t *rt, int64_t *ex,
+static mf_status mf_graph_state_impl(mf_graph *g, int64_t *r_uv, int64_t *r_vu, int64_t *rt, int64_t *ex,
                                     int32_t *labels) {
     if (!g) return MF_E_INVAL;
     GTRY(hipSetDevice(g->device));
@@ -1517,7 +1527,7 @@ bool next_int(const char *&p, long long &v) {
 
 }  // namespace
 
-extern "C" mf_status mf_read_dimacs(const char *path, mf_dimacs **out) {
+static mf_status mf_read_dimacs_impl(const char *path, mf_dimacs **out) {
     if (!path || !out) return MF_E_INVAL;
     *out = nullptr;
     FILE *f = fopen(path, "r");
@@ -1630,4 +1640,66 @@ extern "C" mf_status mf_read_dimacs(const char *path, mf_dimacs **out) {
 extern "C" void mf_free_dimacs(mf_dimacs *d) {
     free_dimacs_arrays(d);
     free(d);
+}
+
+extern "C" mf_status mf_create_graph(int32_t n, int64_t npairs, const int32_t *pu, const int32_t *pv, const int32_t *cuv,
+                                     const int32_t *cvu, const int32_t *cs, const int32_t *ct, const int32_t *region,
+                                     int32_t region_size, int64_t device_pages, mf_graph **out) {
+    // host allocations throw on failure; no exception leaves the C ABI
+    try {
+        return mf_create_graph_impl(n, npairs, pu, pv, cuv, cvu, cs, ct, region, region_size, device_pages, out);
+    } catch (const std::bad_alloc &) {
+        if (out) *out = nullptr;
+        return MF_E_NOMEM;
+    } catch (...) {
+        if (out) *out = nullptr;
+        return MF_E_DEVICE;
+    }
+}
+
+extern "C" mf_status mf_graph_solve(mf_graph *g, const mf_graph_opts *opts, mf_graph_stats *stats) {
+    // host allocations throw on failure; no exception leaves the C ABI
+    try {
+        return mf_graph_solve_impl(g, opts, stats);
+    } catch (const std::bad_alloc &) {
+        return MF_E_NOMEM;
+    } catch (...) {
+        return MF_E_DEVICE;
+    }
+}
+
+extern "C" mf_status mf_graph_state(mf_graph *g, int64_t *r_uv, int64_t *r_vu, int64_t *rt, int64_t *ex,
+                                    int32_t *labels) {
+    // host allocations throw on failure; no exception leaves the C ABI
+    try {
+        return mf_graph_state_impl(g, r_uv, r_vu, rt, ex, labels);
+    } catch (const std::bad_alloc &) {
+        return MF_E_NOMEM;
+    } catch (...) {
+        return MF_E_DEVICE;
+    }
+}
+
+extern "C" mf_status mf_graph_min_cut(mf_graph *g, int32_t kind, uint8_t *out_source_side) {
+    // host allocations throw on failure; no exception leaves the C ABI
+    try {
+        return mf_graph_min_cut_impl(g, kind, out_source_side);
+    } catch (const std::bad_alloc &) {
+        return MF_E_NOMEM;
+    } catch (...) {
+        return MF_E_DEVICE;
+    }
+}
+
+extern "C" mf_status mf_read_dimacs(const char *path, mf_dimacs **out) {
+    // host allocations throw on failure; no exception leaves the C ABI
+    try {
+        return mf_read_dimacs_impl(path, out);
+    } catch (const std::bad_alloc &) {
+        if (out) *out = nullptr;
+        return MF_E_NOMEM;
+    } catch (...) {
+        if (out) *out = nullptr;
+        return MF_E_DEVICE;
+    }
 }

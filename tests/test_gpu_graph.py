@@ -180,3 +180,15 @@ def test_dimacs_file_end_to_end(mf, tmp_path):
         assert g.flow_value() + d["st_capacity"] == ref["flow"] + 11
         assert (g.min_cut(mf.MF_CUT_MIN_SOURCE) == ref["smin"]).all()
         assert (g.min_cut(mf.MF_CUT_MAX_SOURCE) == ref["smax"]).all()
+
+
+def test_sparse_region_numbers(mf):
+    """Region numbers need not be dense: any numbers >= 0 give the same
+    partition as their ranks."""
+    inst = synth.random_graph(4000, 5, 8800)
+    dense = synth.random_regions(inst.n, 12, 8801)
+    sparse = (dense.astype(np.int64) * 1000003 + 17).astype(np.int32)
+    a = _check(mf, inst, region=dense)
+    b = _check(mf, inst, region=sparse)
+    assert a["info"]["regions"] == b["info"]["regions"] == 12
+    assert a["info"]["boundary_size"] == b["info"]["boundary_size"]
