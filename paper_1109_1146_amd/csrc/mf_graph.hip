@@ -704,8 +704,8 @@ struct mf_graph {
     u64 *act = nullptr, *counters = nullptr, *stats = nullptr, *sum = nullptr;
     unsigned char *cutbuf = nullptr;
     void *pinned = nullptr;           // mailbox: [0..7] words, then the region list
-    hipStream_t s = nullptr, sc = nullptr;
-    hipEvent_t evLoad[2] = {nullptr, nullptr}, evComp[2] = {nullptr, nullptr};
+    hipStream_t s = nullptr, sc = nullptr, sd = nullptr;  // solve, page loads, page write-backs
+    hipEvent_t evLoad[2] = {nullptr, nullptr}, evComp[2] = {nullptr, nullptr}, evWB[2] = {nullptr, nullptr};
     long long sum_ct = 0, flow = 0;
     long long sweeps = 0;
     int cur = 0;                      // lab[cur] holds the current boundary labels
@@ -746,9 +746,11 @@ void free_graph(mf_graph *g) {
     for (int h = 0; h < 2; h++) {
         if (g->evLoad[h]) (void)hipEventDestroy(g->evLoad[h]);
         if (g->evComp[h]) (void)hipEventDestroy(g->evComp[h]);
+        if (g->evWB[h]) (void)hipEventDestroy(g->evWB[h]);
     }
     if (g->s) (void)hipStreamDestroy(g->s);
     if (g->sc) (void)hipStreamDestroy(g->sc);
+    if (g->sd) (void)hipStreamDestroy(g->sd);
 }
 
 int cdiv(long long a, int b) { return (int)((a + b - 1) / b); }
@@ -782,8 +784,9 @@ mfg::Args base_args(mf_graph *g) {
 // the device list (order, count on the device).  Streamed pages: the host list
 // `list` (n regions) in batches of g->half regions, alternating between the
 // two halves of the page slots (a single slot is one half), with the next
-// batch's pages loaded on the copy stream while the current batch runs, and
-// the state part of each page written back after its kernel when `writeBack`.
+// batch's pages loaded on one copy stream while the current batch runs, and
+// the state part of each page written back after its kernel on another (when
+// `writeBack`), so that the two directions of the link overlap.
 template <class Launch>
 mf_status page_pass(mf_graph *g, const int *dlist, const int *hlist, int n, bool writeBack,
                     Launch launch) {
@@ -797,17 +800,18 @@ mf_status page_pass(mf_graph *g, const int *dlist, const int *hlist, int n, bool
     const int nb = (n + g->half - 1) / g->half;
     auto write_back = [&](int h) -> mf_status {
         if (!writeBack || pending[h] == 0) return MF_OK;
-        GTRY(hipStreamWaitEvent(g->sc, g->evComp[h], 0));
+        GTRY(hipStreamWaitEvent(g->sd, g->evComp[h], 0));
         for (int i = 0; i < pending[h]; i++) {
             const int r = hlist[pendLo[h] + i];
             const Layout L = layout_of(g->rinfo[r].x, g->rinfo[r].y);
             const size_t slot = (size_t)h * g->half + i;
             const size_t bytes = (size_t)(L.words - L.res) * sizeof(int);
             GTRY(hipMemcpyAsync(g->hpages + (size_t)r * g->stride + L.res,
-                                g->pool + slot * g->stride + L.res, bytes, hipMemcpyDeviceToHost, g->sc));
+                                g->pool + slot * g->stride + L.res, bytes, hipMemcpyDeviceToHost, g->sd));
             g->pages_out++;
             g->bytes_d2h += (long long)bytes;
         }
+        GTRY(hipEventRecord(g->evWB[h], g->sd));
         pending[h] = 0;
         return MF_OK;
     };
@@ -816,7 +820,9 @@ mf_status page_pass(mf_graph *g, const int *dlist, const int *hlist, int n, bool
         mf_status st = write_back(h);
         if (st != MF_OK) return st;
         // the slots of this half are free once the kernel that used them ended
+        // and their state was written back
         GTRY(hipStreamWaitEvent(g->sc, g->evComp[h], 0));
+        GTRY(hipStreamWaitEvent(g->sc, g->evWB[h], 0));
         for (int i = 0; i < cnt;) {
             // consecutive regions in consecutive slots: one copy (the last page without its padding)
             int j = i + 1;
@@ -844,8 +850,7 @@ mf_status page_pass(mf_graph *g, const int *dlist, const int *hlist, int n, bool
         if (st != MF_OK) return st;
     }
     // later work on the compute stream comes after the write-backs
-    GTRY(hipEventRecord(g->evLoad[0], g->sc));
-    GTRY(hipStreamWaitEvent(g->s, g->evLoad[0], 0));
+    for (int h = 0; h < g->nhalves; h++) GTRY(hipStreamWaitEvent(g->s, g->evWB[h], 0));
     return MF_OK;
 }
 
@@ -1222,10 +1227,12 @@ static mf_status mf_create_graph_impl(int32_t n, int64_t npairs, const int32_t *
     const int listMax = g->resident ? K : g->half;
     g->blocks = std::max(1, std::min({std::max(listMax, 1), 2 * g->numCU, budgetBlocks}));
     bool good = ok(hipStreamCreateWithFlags(&g->s, hipStreamNonBlocking)) &&
-                ok(hipStreamCreateWithFlags(&g->sc, hipStreamNonBlocking));
+                ok(hipStreamCreateWithFlags(&g->sc, hipStreamNonBlocking)) &&
+                ok(hipStreamCreateWithFlags(&g->sd, hipStreamNonBlocking));
     for (int h = 0; h < 2 && good; h++)
         good = ok(hipEventCreateWithFlags(&g->evLoad[h], hipEventDisableTiming)) &&
-               ok(hipEventCreateWithFlags(&g->evComp[h], hipEventDisableTiming));
+               ok(hipEventCreateWithFlags(&g->evComp[h], hipEventDisableTiming)) &&
+               ok(hipEventCreateWithFlags(&g->evWB[h], hipEventDisableTiming));
     const size_t poolWords = (size_t)g->P * (size_t)g->stride;
     good = good && ok(dalloc(&g->pool, poolWords)) && ok(dalloc(&g->drinfo, (size_t)K)) &&
            ok(dalloc(&g->blocal, (size_t)nB)) && ok(dalloc(&g->bregion, (size_t)nB)) &&
@@ -1285,6 +1292,7 @@ extern "C" void mf_graph_destroy(mf_graph *g) {
     (void)hipSetDevice(g->device);
     if (g->s) (void)hipStreamSynchronize(g->s);
     if (g->sc) (void)hipStreamSynchronize(g->sc);
+    if (g->sd) (void)hipStreamSynchronize(g->sd);
     free_graph(g);
     delete g;
 }
@@ -1361,6 +1369,7 @@ static mf_status mf_graph_solve_impl(mf_graph *g, const mf_graph_opts *opts, mf_
     GTRY(hipEventRecord(e1, g->s));
     GTRY(hipStreamSynchronize(g->s));
     GTRY(hipStreamSynchronize(g->sc));
+    GTRY(hipStreamSynchronize(g->sd));
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
     (void)hipEventDestroy(e0);
@@ -1438,6 +1447,7 @@ static mf_status mf_graph_state_impl(mf_graph *g, int64_t *r_uv, int64_t *r_vu, 
     GTRY(hipSetDevice(g->device));
     GTRY(hipStreamSynchronize(g->s));
     GTRY(hipStreamSynchronize(g->sc));
+    GTRY(hipStreamSynchronize(g->sd));
     const size_t storeWords = (size_t)g->K * (size_t)g->stride;
     std::vector<int> store;
     const int *hp = g->hpages;
