@@ -51,14 +51,14 @@ def measured_traffic(kernel_src, summary, config=None):
     return float(rec["traffic_bytes_per_launch"])
 
 WORKLOADS = {
-    "2d": dict(cfg=1, tag="grid2d8_2048", relabel=10, partial=False, desc="2048x2048 2D 8-connected blob grid, 64 blobs, 10% n-links zeroed, "
+    "2d": dict(cfg=1, tag="grid2d8_2048", relabel=10, partial=False, round_cap=3, desc="2048x2048 2D 8-connected blob grid, 64 blobs, 10% n-links zeroed, "
                            "64x64 regions (1024), seed 1"),
-    "3d": dict(cfg=2, tag="grid3d6_256", relabel=4, partial=True,
+    "3d": dict(cfg=2, tag="grid3d6_256", relabel=4, partial=True, round_cap=4,
                desc="256^3 3D 6-connected blob grid, 32 blobs, 32^3 regions (512), seed 2"),
     "batch": dict(cfg=3, tag="batch512", relabel=None, partial=None, desc="512 independent 2D blob grids, sides log-uniform in [32,512], "
                               "half 4- and half 8-connected, seeds 3000+i, one batched solve"),
     # the headline workload: plain vs learned-ordered ARD
-    "464": dict(cfg=4, tag="grid3d6_464", relabel=4, partial=False, crop=(192, 192, 192),
+    "464": dict(cfg=4, tag="grid3d6_464", relabel=4, partial=True, round_cap=24, crop=(192, 192, 192),
                 reference="grid3d6_464_oracle.json",
                 desc="464^3 3D 6-connected blob grid, 256 blobs, 64^3 regions (512; last layer 16 thick), seed 4"),
 }
@@ -88,6 +88,9 @@ def parse():
     p.add_argument("--partial", choices=("auto", "on", "off"), default="auto",
                    help="partial discharges (sweep s runs only the stages k <= s of ARD); auto: "
                         "the workload's tuned setting (the autotuner's for the batch)")
+    p.add_argument("--round-cap", type=int, default=None, metavar="N",
+                   help="at most N search-and-push rounds per region discharge and sweep (0 = off; "
+                        "default: the workload's tuned setting)")
     p.add_argument("--boundary-relabel", type=int, default=None, metavar="N",
                    help="boundary relabel heuristic after every sweep with at most N levels "
                         "(0 = off); default: off for the single grids, the autotuner's choice "
@@ -206,7 +209,8 @@ def bench_batch(args):
         # fixed settings (profiling runs): no tuning solves
         tune = dict(region_shape=tuple(args.region_shape), relabel_every=args.relabel_every or 0,
                     partial=args.partial == "on", boundary_relabel=args.boundary_relabel or 0,
-                    schedule=mf.MF_SCHED_PARD, region_kernel=mf.MF_KERNEL_AUTO, timings=[])
+                    schedule=mf.MF_SCHED_PARD, region_kernel=mf.MF_KERNEL_AUTO,
+                    round_cap=args.round_cap or 0, timings=[])
     else:
         tune = autotune.autotune_batch(insts, calib=48, reps=1, partial=forced, brl=brl)
     args.partial = tune["partial"]
@@ -218,7 +222,7 @@ def bench_batch(args):
         st = b.solve(global_relabel_every=tune["relabel_every"], graph=not profile,
                      profile=profile, stream=stream.cuda_stream, partial=args.partial,
                      boundary_relabel=args.boundary_relabel, schedule=tune["schedule"],
-                     region_kernel=tune["region_kernel"])
+                     region_kernel=tune["region_kernel"], round_cap=tune["round_cap"])
         flows = b.flow_values()
         cut = b.min_cut(mf.MF_CUT_MIN_SOURCE)
         return st, flows, cut
@@ -241,7 +245,8 @@ def bench_batch(args):
                                config=dict(region_shape=list(tune["region_shape"]),
                                            relabel_every=tune["relabel_every"],
                                            partial=bool(args.partial),
-                                           boundary_relabel=args.boundary_relabel))
+                                           boundary_relabel=args.boundary_relabel,
+                                           round_cap=tune["round_cap"]))
     rec = {
         "metric": "exact-maxflow solve throughput (batched plain P-ARD), % HBM peak",
         "value": round(total_n / (ms / 1e3) / 1e6, 3), "unit": "Mvertices/s",
@@ -253,7 +258,7 @@ def bench_batch(args):
                    "global_relabel_every": tune["relabel_every"], "graph": True,
                    "partial_discharges": args.partial, "boundary_relabel": args.boundary_relabel,
                    "schedule": "colour phases (Alg. 1)" if tune["schedule"] == mf.MF_SCHED_COLORED
-                   else "P-ARD (Alg. 2)", "region_kernel": kname},
+                   else "P-ARD (Alg. 2)", "region_kernel": kname, "round_cap": tune["round_cap"]},
         "instances_per_s": round(len(insts) / (ms / 1e3), 1),
         "sweeps": st["sweeps"], "region_discharges": st["region_discharges"],
         "flow": int(flows.sum()),
@@ -435,10 +440,12 @@ def bench_grid(args, wl, steps, warmup, compare, cpu):
     del cs, ct, nbr
     info = g.info()
     relabel, partial, brl = args.relabel_every, args.partial, args.boundary_relabel
+    rcap = args.round_cap
 
     def step(profile):
         st = g.solve(stream=stream.cuda_stream, profile=profile, global_relabel_every=relabel,
                      partial=partial, boundary_relabel=brl, method=method, schedule=schedule,
+                     round_cap=rcap,
                      max_sweeps=1 << 40)
         cut = g.min_cut(mf.MF_CUT_MIN_SOURCE)
         return st, cut
@@ -474,10 +481,11 @@ def bench_grid(args, wl, steps, warmup, compare, cpu):
                    "schedule": ("S-" if args.schedule == "colored" else "P-") + args.method.upper()
                                + (" (colour phases)" if args.schedule == "colored" else "")
                                + (", partial discharges" if partial else "")
-                               + (", boundary relabel" if brl else ""),
+                               + (", boundary relabel" if brl else "")
+                               + (f", at most {rcap} rounds per discharge and sweep" if rcap else ""),
                    "connectivity": inst.conn,
                    "global_relabel_every": relabel, "partial_discharges": partial,
-                   "boundary_relabel": brl},
+                   "boundary_relabel": brl, "round_cap": rcap},
         "sweeps": stats[-1]["sweeps"],
         "region_discharges": stats[-1]["region_discharges"],
         "flow": flow,
@@ -510,7 +518,7 @@ def bench_grid(args, wl, steps, warmup, compare, cpu):
         # sweeps, discharges and solve time next to plain P-ARD, same exact
         # flow; and the colour phases in fixed order, the learned colour
         # schedule's skeleton without the network
-        base = dict(global_relabel_every=relabel, stream=stream.cuda_stream, partial=partial)
+        base = dict(global_relabel_every=relabel, stream=stream.cuda_stream, partial=partial, round_cap=rcap)
         try:
             from paper_1109_1146_amd import learned
             model = learned.load_model()
@@ -603,11 +611,14 @@ def main():
     args.partial = {"on": True, "off": False}.get(args.partial, wl["partial"])
     if args.boundary_relabel is None:
         args.boundary_relabel = 0
+    if args.round_cap is None:
+        args.round_cap = wl.get("round_cap", 0)
     if args.schedule == "colored":
         args.boundary_relabel, args.no_learned = 0, True
     if args.method == "prd":
         # the exact relabel and the heuristics are those of region distances
         args.relabel_every, args.partial, args.boundary_relabel, args.no_learned = 0, False, 0, True
+        args.round_cap = 0
     headline = args.workload == "464"
     sub = bench_grid(args, wl, args.steps, args.warmup, compare=not args.no_learned,
                      cpu=not args.no_cpu_baseline)
@@ -635,13 +646,15 @@ def main():
         w3 = WORKLOADS["3d"]
         a3 = argparse.Namespace(**vars(args))
         a3.relabel_every, a3.partial = w3["relabel"], w3["partial"]
+        a3.round_cap = w3.get("round_cap", 0)
         n3 = bench_grid(a3, w3, 3, 1, compare=False, cpu=False)
         rec["grid3d6_256"] = {"workload": n3["config"]["workload"], "steps": 3, "warmup": 1,
                               "ms_per_step": n3["ms_per_step"], "value": n3["value"],
                               "unit": "Mvertices/s", "sweeps": n3["sweeps"],
                               "region_discharges": n3["region_discharges"],
                               "global_relabel_every": w3["relabel"],
-                              "partial_discharges": w3["partial"], "roofline": n3["roofline"]}
+                              "partial_discharges": w3["partial"], "round_cap": a3.round_cap,
+                              "roofline": n3["roofline"]}
         # the general-network path (region pages) on a 26-connected volume
         rec["graph26_128"] = bench_graph(args, 2, 1, cpu=not args.no_cpu_baseline)
     print(json.dumps(rec), flush=True)

@@ -129,6 +129,14 @@ typedef struct {
                                      label_trace_cap are not recorded.  Forces eager launches (no
                                      graph) */
     int64_t label_trace_cap;      /* steps the label trace holds */
+    int32_t round_cap;            /* n >= 1: a region discharge runs at most n search-and-push rounds
+                                     per sweep; excess its last (complete, label-writing) search still
+                                     finds reaching a target stays in the region, which stays active
+                                     for the next sweep (the mechanism of partial discharges, Sec. 6.2,
+                                     with a cap on rounds instead of stages).  A sweep lasts as long
+                                     as its slowest region: the cap shortens the longest discharges
+                                     and lets the others go on in the next sweep.  The flow and cuts
+                                     are the same.  0 = off; not with MF_METHOD_PRD (MF_E_INVAL) */
 } mf_solve_opts;
 
 /* region discharge operation, see mf_solve_opts.method */

@@ -1,5 +1,6 @@
 """Autotuner for batched solves: region shape, relabel interval, partial
-discharges (Sec. 6.2), the boundary relabel heuristic (Sec. 6.1), the schedule
+discharges (Sec. 6.2), the cap on search-and-push rounds of a region discharge
+per sweep, the boundary relabel heuristic (Sec. 6.1), the schedule
 (P-ARD of Alg. 2 or the colour phases of Alg. 1) and the workgroup shape of a
 region discharge (the region kernel: one 64-lane wavefront per region, or a
 512-thread workgroup with the region in LDS).
@@ -30,6 +31,7 @@ PARTIAL = (False, True)
 BRL = (0, 8)  # boundary relabel after every sweep: off, or at most 8 levels
 SCHEDULES = (mf.MF_SCHED_PARD, mf.MF_SCHED_COLORED)
 KERNELS = (mf.MF_KERNEL_WAVE, mf.MF_KERNEL_LDS)  # 64-lane wavefront, 512-thread workgroup
+ROUND_CAPS = (0, 4)  # rounds of a region discharge per sweep: no cap, or 4
 
 
 def calibration_subset(instances, size=48, seed=0):
@@ -42,9 +44,10 @@ def calibration_subset(instances, size=48, seed=0):
 
 
 def autotune_batch(instances, tiles=TILES, relabel=RELABEL, partial=PARTIAL, calib=48, reps=2,
-                   graph=True, brl=BRL, finalists=3, schedules=SCHEDULES, kernels=KERNELS):
+                   graph=True, brl=BRL, finalists=3, schedules=SCHEDULES, kernels=KERNELS,
+                   round_caps=ROUND_CAPS):
     """Return dict(region_shape, relabel_every, partial, boundary_relabel,
-    schedule, region_kernel, timings) for this batch."""
+    schedule, region_kernel, round_cap, timings) for this batch."""
     sample = calibration_subset(instances, calib)
 
     def timed(b, kw):
@@ -64,17 +67,18 @@ def autotune_batch(instances, tiles=TILES, relabel=RELABEL, partial=PARTIAL, cal
                 for pd in partial:
                     for sch in schedules:
                         for ker in kernels:
-                            kw = dict(global_relabel_every=ev, graph=graph, partial=pd, schedule=sch,
-                                      region_kernel=ker)
-                            try:
-                                ms = timed(b, kw)
-                            except mf.MFError as e:
-                                if e.status != mf.MF_E_INVAL:
-                                    raise
-                                continue  # not applicable to this region shape
-                            timings.append(dict(stage="subset", region_shape=list(tile), relabel_every=ev,
-                                                partial=pd, boundary_relabel=0, schedule=sch,
-                                                region_kernel=ker, ms=ms))
+                            for rc in round_caps:
+                                kw = dict(global_relabel_every=ev, graph=graph, partial=pd, schedule=sch,
+                                          region_kernel=ker, round_cap=rc)
+                                try:
+                                    ms = timed(b, kw)
+                                except mf.MFError as e:
+                                    if e.status != mf.MF_E_INVAL:
+                                        raise
+                                    continue  # not applicable to this region shape
+                                timings.append(dict(stage="subset", region_shape=list(tile), relabel_every=ev,
+                                                    partial=pd, boundary_relabel=0, schedule=sch,
+                                                    region_kernel=ker, round_cap=rc, ms=ms))
         finally:
             b.close()
     best = sorted(timings, key=lambda t: t["ms"])[:max(1, finalists)]
@@ -90,7 +94,7 @@ def autotune_batch(instances, tiles=TILES, relabel=RELABEL, partial=PARTIAL, cal
                         continue
                     kw = dict(global_relabel_every=cand["relabel_every"], graph=graph,
                               partial=cand["partial"], boundary_relabel=br, schedule=cand["schedule"],
-                              region_kernel=cand["region_kernel"])
+                              region_kernel=cand["region_kernel"], round_cap=cand["round_cap"])
                     full.append(dict(cand, stage="full", boundary_relabel=br, ms=timed(b, kw)))
         finally:
             b.close()
@@ -98,14 +102,15 @@ def autotune_batch(instances, tiles=TILES, relabel=RELABEL, partial=PARTIAL, cal
     win = min(full, key=lambda t: t["ms"])
     return dict(region_shape=tuple(win["region_shape"]), relabel_every=win["relabel_every"],
                 partial=win["partial"], boundary_relabel=win["boundary_relabel"],
-                schedule=win["schedule"], region_kernel=win["region_kernel"], timings=timings)
+                schedule=win["schedule"], region_kernel=win["region_kernel"], round_cap=win["round_cap"],
+                timings=timings)
 
 
 def solve_batch(instances, region_shape=None, relabel_every=None, graph=True, tune=None,
-                partial=None, boundary_relabel=None, schedule=None, region_kernel=None):
+                partial=None, boundary_relabel=None, schedule=None, region_kernel=None, round_cap=None):
     """Solve all instances in one batch; returns (flows, batch handle, tuning)."""
     if (region_shape is None or relabel_every is None or partial is None or boundary_relabel is None
-            or schedule is None or region_kernel is None):
+            or schedule is None or region_kernel is None or round_cap is None):
         tune = tune or autotune_batch(instances, graph=graph)
         region_shape = region_shape or tune["region_shape"]
         relabel_every = tune["relabel_every"] if relabel_every is None else relabel_every
@@ -113,12 +118,14 @@ def solve_batch(instances, region_shape=None, relabel_every=None, graph=True, tu
         boundary_relabel = tune["boundary_relabel"] if boundary_relabel is None else boundary_relabel
         schedule = tune["schedule"] if schedule is None else schedule
         region_kernel = tune["region_kernel"] if region_kernel is None else region_kernel
+        round_cap = tune["round_cap"] if round_cap is None else round_cap
     b = mf.load_batch(instances, region_shape=region_shape)
     st = b.solve(global_relabel_every=relabel_every, graph=graph, partial=partial,
-                 boundary_relabel=boundary_relabel, schedule=schedule, region_kernel=region_kernel)
+                 boundary_relabel=boundary_relabel, schedule=schedule, region_kernel=region_kernel,
+                 round_cap=round_cap)
     return b.flow_values(), b, dict(region_shape=tuple(region_shape), relabel_every=relabel_every,
                                     partial=partial, boundary_relabel=boundary_relabel, schedule=schedule,
-                                    region_kernel=region_kernel, stats=st, tune=tune)
+                                    region_kernel=region_kernel, round_cap=round_cap, stats=st, tune=tune)
 
 
 if __name__ == "__main__":

@@ -773,7 +773,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     if (colored && (o.boundary_relabel || (o.features && o.features_cap > 0))) return MF_E_INVAL;
     // push-relabel region discharge: distance labels over every arc; the
     // heuristics and the exact relabel here are those of region distances
-    if (prd && (learned || o.partial || o.boundary_relabel ||
+    if (o.round_cap < 0) return MF_E_INVAL;
+    if (prd && (learned || o.partial || o.boundary_relabel || o.round_cap ||
                 o.global_relabel_every || (o.features && o.features_cap > 0) ||
                 (o.region_kernel != MF_KERNEL_AUTO && o.region_kernel != MF_KERNEL_HBM)))
         return MF_E_INVAL;
@@ -886,7 +887,8 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     D.traceCap = o.trace ? o.trace_cap : 0;
     D.partial = o.partial;
     D.sweepCount = g->counters;
-    D.actCarry = o.partial ? g->counters + 1 : nullptr;
+    D.actCarry = (o.partial || o.round_cap > 0) ? g->counters + 1 : nullptr;
+    D.roundCap = o.round_cap;
     size_t lds = g->useLDS ? (size_t)16 * G.V : 0;
     RegionPick RP;
     {
@@ -967,7 +969,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                     FA.ringL = g->ringL; FA.ringM = g->ringM; FA.nring = g->nring; FA.dinf = g->dinf;
                     // with partial discharges excess can stay inside a region, and
                     // so it can during the first sweep of colour phases
-                    FA.ringOnly = (first + j >= ncol && !o.partial) ? 1 : 0;
+                    FA.ringOnly = (first + j >= ncol && !o.partial && o.round_cap <= 0) ? 1 : 0;
                     FA.ringX = g->ringX;
                     FA.out = (o.features && first + j < o.features_cap)
                                  ? o.features + (size_t)(first + j) * G.nreg * mfd::kFeat
@@ -1063,6 +1065,7 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
                                   (long long)(regionMode << 2) | (long long)(regionNarrow << 4) |
                                   (long long)((g->lab[0] < g->lab[1]) ? 1 : 0) << 6 |
                                   (long long)(o.partial ? 1 : 0) << 7 | (long long)brl << 40 |
+                                  (long long)std::min(o.round_cap, 0xffff) << 24 |
                                   (long long)(prd ? 1 : 0) << 56 | (long long)(colored ? 1 : 0) << 57;
             if (!g->graph_exec || g->graph_key != key) {
                 if (g->graph_exec) { (void)hipGraphExecDestroy(g->graph_exec); g->graph_exec = nullptr; }

@@ -206,6 +206,7 @@ __global__ __launch_bounds__(NT) void k_discharge_lds(DischargeArgs A) {
         // complete search, whose labels are written
         const bool relabelOnly = s_active == 2;
         bool full = !A.partial || relabelOnly;
+        bool roundCapped = false;  // the round cap was reached: one more complete search
         for (;;) {
             const long long t_round = wall_clock64();
             bool capped = false;
@@ -371,7 +372,7 @@ __global__ __launch_bounds__(NT) void k_discharge_lds(DischargeArgs A) {
                 }
                 break;
             }
-            if (full && A.partial) {
+            if (full && (A.partial || roundCapped)) {
                 // complete search after capped rounds: the excess it reaches lies
                 // beyond the cap and stays; the region stays active
                 if (tid == 0) {
@@ -383,6 +384,11 @@ __global__ __launch_bounds__(NT) void k_discharge_lds(DischargeArgs A) {
             if (++iter > A.maxIter) {
                 if (tid == 0) atomicOr(A.err, 4);
                 break;
+            }
+            if (A.roundCap > 0 && iter > A.roundCap) {
+                roundCapped = true;  // search once more, complete, for the region relabel
+                full = true;
+                continue;
             }
             // ---------------- push excess down the search levels ----------------
             for (int s = nsteps - 1; s >= 0; s--) {

@@ -451,6 +451,12 @@ __global__ __launch_bounds__(kRowsNT) void k_discharge_rows(DischargeArgs A) {
                 writeMode = true;
                 continue;
             }
+            if (A.roundCap > 0 && iter > A.roundCap) {
+                // round cap: the last search writes the region relabel; excess it
+                // still finds waits in the region for the next sweep
+                writeMode = true;
+                continue;
+            }
 
             // ---------------- push along admissible arcs until nothing moves ----------------
             unsigned canPush = 0u;

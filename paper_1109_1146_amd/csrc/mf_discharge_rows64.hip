@@ -586,6 +586,12 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                 writeMode = true;
                 continue;
             }
+            if (A.roundCap > 0 && iter > A.roundCap) {
+                // round cap: the last search writes the region relabel; excess it
+                // still finds waits in the region for the next sweep
+                writeMode = true;
+                continue;
+            }
 
             // ---------------- push along admissible arcs until nothing moves ----------------
             // recv held the visited rows: clear it for the pushes (clr is zero)

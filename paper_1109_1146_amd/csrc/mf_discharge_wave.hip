@@ -480,6 +480,12 @@ __global__ __launch_bounds__(64) void k_discharge_wave(DischargeArgs A) {
                 writeMode = true;
                 continue;
             }
+            if (A.roundCap > 0 && iter > A.roundCap) {
+                // round cap: the last search writes the region relabel; excess it
+                // still finds waits in the region for the next sweep
+                writeMode = true;
+                continue;
+            }
             // ---------------- push along admissible arcs until nothing moves ----------------
 #pragma unroll
             for (int k = 0; k < K; k++) admM[k * 64 + lane] = adm[k];

@@ -232,13 +232,14 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
         // complete search, whose labels are written
         const bool relabelOnly = s_active == 2;
         bool full = !A.partial || relabelOnly;
+        bool roundCapped = false;  // the round cap was reached: one more complete search
         bool firstSearch = true, lastComplete = false;
         for (;;) {
             bool capped = false, early = false;
             // a push-round search stops once every live excess vertex is labelled;
             // the search whose labels are written must be complete (with partial
-            // discharges that is the full one after the capped rounds)
-            const bool earlyOk = !(A.partial && full) && !relabelOnly;
+            // discharges or after the round cap, the full one after the capped rounds)
+            const bool earlyOk = !((A.partial || roundCapped) && full) && !relabelOnly;
             // ---------------- multi-level search from the targets ----------------
             if (tid == 0) {
                 s_qtail = 0;
@@ -516,7 +517,7 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
                 }
                 break;
             }
-            if (full && A.partial) {
+            if (full && (A.partial || roundCapped)) {
                 // complete search after capped rounds: the excess it reaches lies
                 // beyond the cap and stays; the region stays active
                 if (tid == 0) {
@@ -528,6 +529,11 @@ __global__ __launch_bounds__(NT) void k_discharge(DischargeArgs A) {
             if (++iter > A.maxIter) {
                 if (tid == 0) atomicOr(A.err, 4);
                 break;
+            }
+            if (A.roundCap > 0 && iter > A.roundCap) {
+                roundCapped = true;  // search once more, complete, for the region relabel
+                full = true;
+                continue;
             }
             // ---------------- push excess down the search levels ----------------
             const int nsteps = s_nsteps;

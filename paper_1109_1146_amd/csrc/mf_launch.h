@@ -40,7 +40,8 @@ struct DischargeArgs {
     int partial;
     const unsigned long long *sweepCount;
     int capShift;        // log2 of the steps per sweep (colour phases of Alg. 1: 2 or 4 steps)
-    unsigned long long *actCarry;  // null unless partial
+    unsigned long long *actCarry;  // null unless partial or roundCap
+    int roundCap;        // > 0: at most this many push rounds per discharge and sweep
     // Push-relabel region discharge (Sec. 3, Proc. PRD; HBM kernel only): labels
     // are the distance labels of Sec. 2 (d(t) = 0, every arc of length 1, dinf =
     // n) instead of region distances

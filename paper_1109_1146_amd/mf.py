@@ -49,7 +49,8 @@ class mf_solve_opts(ctypes.Structure):
                 ("defer_mode", ctypes.c_int32), ("features", ctypes.c_void_p),
                 ("features_cap", ctypes.c_int64), ("partial", ctypes.c_int32),
                 ("boundary_relabel", ctypes.c_int32), ("method", ctypes.c_int32),
-                ("label_trace", ctypes.c_void_p), ("label_trace_cap", ctypes.c_int64)]
+                ("label_trace", ctypes.c_void_p), ("label_trace_cap", ctypes.c_int64),
+                ("round_cap", ctypes.c_int32)]
 
 
 class mf_solve_stats(ctypes.Structure):
@@ -299,8 +300,9 @@ class Grid:
               max_sweeps=0, stream=None, profile=False, region_kernel=MF_KERNEL_AUTO,
               trace=None, graph=False, model=None, max_defer=0, defer_threshold=0.0,
               features=None, defer_mode=0, partial=False, boundary_relabel=0,
-              method=MF_METHOD_ARD, label_trace=None):
+              method=MF_METHOD_ARD, label_trace=None, round_cap=0):
         """trace: optional int32 device tensor of shape (cap, TRACE_FIELDS);
+        round_cap: n > 0 caps a region discharge at n search-and-push rounds per sweep;
         partial: partial discharges (sweep s runs the stages k <= s only);
         boundary_relabel: n > 0 runs the boundary relabel heuristic after every
         sweep with at most n levels of its search;
@@ -322,7 +324,8 @@ class Grid:
                           features_cap=fcap, partial=1 if partial else 0,
                           boundary_relabel=int(boundary_relabel), method=int(method),
                           label_trace=label_trace.data_ptr() if label_trace is not None else None,
-                          label_trace_cap=int(label_trace.shape[0]) if label_trace is not None else 0)
+                          label_trace_cap=int(label_trace.shape[0]) if label_trace is not None else 0,
+                          round_cap=int(round_cap))
         if model is not None:
             o.model = model._h
         s = mf_solve_stats()

@@ -15,8 +15,8 @@ back (mf_get_state).  On that state:
   monotonicity) and its last entry is the final state's labels.
 
 Every region kernel (wavefront, row-bitmask with 32- and 64-vertex rows, LDS
-workgroup, HBM), with and without partial discharges and the boundary relabel,
-and the colour phases of Alg. 1."""
+workgroup, HBM), with and without partial discharges, capped discharge rounds
+and the boundary relabel, and the colour phases of Alg. 1."""
 import numpy as np
 import pytest
 
@@ -48,6 +48,9 @@ CASES = [
     ("3d_rows64", (64, 64, 100), 6, (64, 64, 64), "ROWS64", {}, True),
     ("3d_rows64_partial_brl", (64, 100, 64), 6, (64, 64, 64), "ROWS64",
      dict(partial=True, boundary_relabel=8), False),
+    ("2d8_wave_roundcap", (48, 40), 8, (16, 20), "WAVE", dict(round_cap=1), True),
+    ("3d_rows64_roundcap", (64, 64, 100), 6, (64, 64, 64), "ROWS64", dict(round_cap=2), True),
+    ("3d_hbm_roundcap", (10, 12, 14), 6, (5, 6, 7), "HBM", dict(round_cap=1), False),
 ]
 
 
@@ -96,7 +99,8 @@ def test_labels_after_sweeps(mf, ci, sweeps):
         dstar = region_distance(inst.n, pu, pv, r_uv, r_vu, region, rt, dinf)
         assert (lab <= dstar).all(), f"{int((lab > dstar).sum())} labels above d*B"
         # Sec. 4.3-4.4: after a full sweep only boundary vertices are active
-        if not kw.get("partial"):
+        # (partial and capped discharges may leave excess inside a region)
+        if not kw.get("partial") and not kw.get("round_cap"):
             active = (ex > 0) & (lab < dinf)
             assert not (active & ~bmask).any(), f"{int((active & ~bmask).sum())} active interior vertices"
         # Alg. 3 on this state, with these labels as the halo labels

@@ -444,9 +444,11 @@ def test_batch_workload_512_exact(mf):
     sub = [t for t in tune["timings"] if t["stage"] == "subset"]
     assert {t["schedule"] for t in sub} == {mf.MF_SCHED_PARD, mf.MF_SCHED_COLORED}
     assert {t["region_kernel"] for t in sub} == {mf.MF_KERNEL_WAVE, mf.MF_KERNEL_LDS}
+    assert {t["round_cap"] for t in sub} == {0, 4}
     st = _batch_check(mf, insts, tune["region_shape"], global_relabel_every=tune["relabel_every"],
                       partial=tune["partial"], boundary_relabel=tune["boundary_relabel"],
-                      schedule=tune["schedule"], region_kernel=tune["region_kernel"], graph=True)
+                      schedule=tune["schedule"], region_kernel=tune["region_kernel"],
+                      round_cap=tune["round_cap"], graph=True)
     assert st["sweeps"] > 0
     # the other schedule and workgroup shape are exact too
     other = dict(schedule=mf.MF_SCHED_COLORED if tune["schedule"] == mf.MF_SCHED_PARD else mf.MF_SCHED_PARD,
