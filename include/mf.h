@@ -243,7 +243,8 @@ mf_status mf_set_caps(mf_grid *g, const int32_t *src_cap, const int32_t *sink_ca
 /* Solve the loaded instance to a maximum preflow.  opts may be NULL
  * (defaults: P-ARD, gap on, global relabel off).  st may be NULL.  Blocks
  * until the result is on the device and the stream is synchronised.  A second
- * call re-solves the same instance from Init.
+ * call re-solves the same instance from Init.  st is filled on MF_OK and on
+ * MF_E_SWEEPS (then with the sweeps run up to the limit).
  * Errors: MF_E_STATE (no instance), MF_E_SWEEPS, MF_E_DEVICE, MF_E_INVAL. */
 mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_stats *st);
 

@@ -613,9 +613,12 @@ static int global_relabel(mf_grid *g, int *lab, u64 *act, hipStream_t s) {
     const bool wave = g->ndim == 2 && G.tx <= 64 && G.ty <= 64;
     const bool rows = g->ndim == 3 && G.K == 6 && G.tx == 32 && G.ty >= 2 && G.tz >= 2 &&
                       R % 64 == 0 && R <= 1024;
-    if (wave || rows) {
+    // 3D 64^3 regions: one workgroup per region, 64-bit rows in registers
+    const bool rows64 = g->ndim == 3 && mfd::rows64_applicable(G.K, G.tx, G.ty, G.tz);
+    if (wave || rows || rows64) {
         const size_t need = wave ? (size_t)G.nreg * (G.K + 1) * 64 * sizeof(u64)
-                                 : (size_t)G.nreg * 7 * R * sizeof(unsigned);
+                                 : (rows ? (size_t)G.nreg * 7 * R * sizeof(unsigned)
+                                         : mfd::grelabel_rows64_cache_bytes(G.nreg));
         if (g->gcache_bytes < need) {
             if (g->gcache) (void)hipFree(g->gcache);
             g->gcache = nullptr;
@@ -626,7 +629,7 @@ static int global_relabel(mf_grid *g, int *lab, u64 *act, hipStream_t s) {
         A.cache = g->gcache;
     }
     const int blocks = wave ? std::min(G.nreg, g->numCU * 8)
-                            : (rows ? std::min(G.nreg, g->numCU * 2) : std::min(G.nreg, g->nslots * 4));
+                            : ((rows || rows64) ? std::min(G.nreg, g->numCU * 2) : std::min(G.nreg, g->nslots * 4));
     // levels are launched in batches; a level with no flagged region is a cheap no-op
     const int batch = 4;
     int D = 0;
@@ -643,7 +646,9 @@ static int global_relabel(mf_grid *g, int *lab, u64 *act, hipStream_t s) {
             A.candBitsOut = (unsigned *)g->cand + (size_t)((lv + 1) & 1) * (G.N / 32);
             if (!ok(hipMemsetAsync(g->changed + j, 0, sizeof(unsigned), s))) return -1;
             hipError_t e = wave ? mfd::launch_grelabel_wave(A, blocks, s)
-                                : (rows ? mfd::launch_grelabel_rows(A, blocks, s) : mfd::launch_grelabel(A, blocks, s));
+                                : (rows ? mfd::launch_grelabel_rows(A, blocks, s)
+                                        : (rows64 ? mfd::launch_grelabel_rows64(A, blocks, s)
+                                                  : mfd::launch_grelabel(A, blocks, s)));
             if (!ok(e)) return -1;
         }
         if (!ok(hipMemcpyAsync(g->pinned + 14, g->changed + batch - 1, sizeof(unsigned), hipMemcpyDeviceToHost, s)))
@@ -1106,39 +1111,10 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         if ((long long)g->pinned[1] >= max_steps) { status = MF_E_SWEEPS; break; }
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
-    if (status == MF_E_SWEEPS) {
-        // the state after the sweeps run so far stays readable
-        g->final_parity = colored ? 0 : (int)(g->pinned[1] & 1ull);
-        g->has_state = true;
-        // skipped regions refreshed only their border labels: the current labels
-        // are the larger entry of the two buffers
-        if (!colored) HIP_TRY(mfd::launch_label_max(g->lab[g->final_parity], g->lab[g->final_parity ^ 1], G.N, s));
-        HIP_TRY(hipStreamSynchronize(s));
-    }
-    if (status != MF_OK) return status;
-    const long long steps = (long long)g->pinned[1];
-    g->final_parity = colored ? 0 : (int)(steps & 1);
-    if (!colored) HIP_TRY(mfd::launch_label_max(g->lab[g->final_parity], g->lab[g->final_parity ^ 1], G.N, s));
-    const long long sweeps = (steps + ncol - 1) / ncol;
-    // flow value |f| = sum (c_t - c_f(., t))
-    HIP_TRY(hipMemsetAsync(g->sums + 2, 0, sizeof(u64), s));
-    HIP_TRY(mfd::launch_sum_i32(g->rt, G.N, g->sums + 2, s));
-    HIP_TRY(hipMemcpyAsync(g->pinned + 3, g->sums + 2, sizeof(u64), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(g->pinned + 16, g->stats, 16 * sizeof(u64), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    g->flow = g->sum_ct - (long long)g->pinned[3];
-    if (g->batch) {
-        HIP_TRY(hipMemsetAsync(g->instRt, 0, sizeof(u64) * g->batch, s));
-        HIP_TRY(mfd::launch_instance_rt(G, g->rt, g->reginst, g->instRt, s));
-        std::vector<u64> rts(g->batch);
-        HIP_TRY(hipMemcpyAsync(rts.data(), g->instRt, sizeof(u64) * g->batch, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        for (int i = 0; i < g->batch; i++) g->iflow[i] = g->isum_ct[i] - (long long)rts[i];
-    }
-    g->solved = true;
-    g->has_state = true;
-    auto t1 = std::chrono::high_resolution_clock::now();
-    if (st) {
+    // the statistics of the sweeps run (also when the sweep limit ends the solve)
+    auto fill_stats = [&](long long sweeps) {
+        if (!st) return;
+        auto t1 = std::chrono::high_resolution_clock::now();
         memset(st, 0, sizeof(*st));
         st->sweeps = sweeps;
         st->region_discharges = (int64_t)g->pinned[16];
@@ -1163,7 +1139,41 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
         st->discharge_ms = discharge_ms;
         st->discharge_launches = timed;
         st->discharge_bytes = (double)st->discharged_vertices * (double)mf_discharge_bytes_per_vertex(g->K);
+    };
+    if (status == MF_E_SWEEPS) {
+        // the state after the sweeps run so far stays readable
+        g->final_parity = colored ? 0 : (int)(g->pinned[1] & 1ull);
+        g->has_state = true;
+        // skipped regions refreshed only their border labels: the current labels
+        // are the larger entry of the two buffers
+        if (!colored) HIP_TRY(mfd::launch_label_max(g->lab[g->final_parity], g->lab[g->final_parity ^ 1], G.N, s));
+        HIP_TRY(hipMemcpyAsync(g->pinned + 16, g->stats, 16 * sizeof(u64), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        fill_stats(((long long)g->pinned[1] + ncol - 1) / ncol);
     }
+    if (status != MF_OK) return status;
+    const long long steps = (long long)g->pinned[1];
+    g->final_parity = colored ? 0 : (int)(steps & 1);
+    if (!colored) HIP_TRY(mfd::launch_label_max(g->lab[g->final_parity], g->lab[g->final_parity ^ 1], G.N, s));
+    const long long sweeps = (steps + ncol - 1) / ncol;
+    // flow value |f| = sum (c_t - c_f(., t))
+    HIP_TRY(hipMemsetAsync(g->sums + 2, 0, sizeof(u64), s));
+    HIP_TRY(mfd::launch_sum_i32(g->rt, G.N, g->sums + 2, s));
+    HIP_TRY(hipMemcpyAsync(g->pinned + 3, g->sums + 2, sizeof(u64), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(g->pinned + 16, g->stats, 16 * sizeof(u64), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    g->flow = g->sum_ct - (long long)g->pinned[3];
+    if (g->batch) {
+        HIP_TRY(hipMemsetAsync(g->instRt, 0, sizeof(u64) * g->batch, s));
+        HIP_TRY(mfd::launch_instance_rt(G, g->rt, g->reginst, g->instRt, s));
+        std::vector<u64> rts(g->batch);
+        HIP_TRY(hipMemcpyAsync(rts.data(), g->instRt, sizeof(u64) * g->batch, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int i = 0; i < g->batch; i++) g->iflow[i] = g->isum_ct[i] - (long long)rts[i];
+    }
+    g->solved = true;
+    g->has_state = true;
+    fill_stats(sweeps);
     return MF_OK;
 }
 

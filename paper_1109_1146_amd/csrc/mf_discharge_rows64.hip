@@ -388,9 +388,12 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                     cnt += __popcll(exM[j] & ~rtm & ~deadB[row]);
                 }
             }
+            // the labels of a writing search are stored once per stage, for the
+            // vertices visited since the previous stage (recv holds the visited
+            // rows at each stage's end; each thread clears and reads its own rows)
             if (writeMode) {
 #pragma unroll
-                for (int j = 0; j < kRPT; j++) r64_store_labels(A.labNew + base, 64 * (kRPT * wid + j), F[j], 0, lane);
+                for (int j = 0; j < kRPT; j++) recvB[row0 + 64 * j] = 0ull;
             }
             int p = 0;
             int stage = 0;
@@ -444,11 +447,13 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                         vis[j] |= F[j];
                     }
                     // Pass 2, slots with new vertices in some lane: the arcs by which
-                    // the new vertices were reached are their admissible arcs
+                    // the new vertices were reached are their admissible arcs (a
+                    // writing search is followed by no push: it needs neither them
+                    // nor the count of unlabelled excess vertices)
 #pragma unroll
                     for (int j = 0; j < kRPT; j++) {
                         const u64 nw = F[j];
-                        if (__ballot(nw != 0ull) == 0ull) continue;
+                        if (writeMode || __ballot(nw != 0ull) == 0ull) continue;
                         const u64 cur = old[j];
                         const u64 fzp = j < kRPT - 1 ? old[j + 1] : above;
                         const u64 fzm = j > 0 ? old[j - 1] : prev;
@@ -467,11 +472,6 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                         if (t4) g_or(ad + 4 * R, t4);
                         if (t5) g_or(ad + 5 * R, t5);
                     }
-                    if (writeMode) {
-#pragma unroll
-                        for (int j = 0; j < kRPT; j++)
-                            r64_store_labels(A.labNew + base, 64 * (kRPT * wid + j), F[j], stage, lane);
-                    }
                     p ^= 1;
                 }
                 const long long t1f = wall_clock64();
@@ -479,6 +479,12 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                 if (early) break;
                 // next stage: smallest candidate among unvisited border vertices
                 // (the visited rows go to the recv buffer, free during a search)
+                if (writeMode) {
+#pragma unroll
+                    for (int j = 0; j < kRPT; j++)
+                        r64_store_labels(A.labNew + base, 64 * (kRPT * wid + j), vis[j] & ~recvB[row0 + 64 * j],
+                                         stage, lane);
+                }
 #pragma unroll
                 for (int j = 0; j < kRPT; j++) recvB[row0 + 64 * j] = vis[j];
                 __syncthreads();
@@ -533,7 +539,7 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                     // the candidate came from one of these boundary arcs
 #pragma unroll
                     for (int k = 0; k < 6; k++)
-                        if ((match >> k) & 1u) g_or(admG + (size_t)k * R + rw, bit);
+                        if (((match >> k) & 1u) && !writeMode) g_or(admG + (size_t)k * R + rw, bit);
                     slotC[i] = kInf;
                     atomicOr(&clrB[rw], bit);  // seeds (clr is all zero during a search)
                   }
@@ -548,10 +554,6 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                     F[j] = sd & ~vis[j];
                     vis[j] |= F[j];
                     if (F[j] & exM[j]) cnt -= __popcll(F[j] & exM[j] & ~deadB[row]);
-                }
-                if (writeMode) {
-#pragma unroll
-                    for (int j = 0; j < kRPT; j++) r64_store_labels(A.labNew + base, 64 * (kRPT * wid + j), F[j], level, lane);
                 }
                 t_stage += wall_clock64() - t1f;
             }
@@ -829,6 +831,180 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
         __syncthreads();
     }
 }
+
+// Global relabel, one distance level D (see k_grelabel in mf_kernels.hip), for
+// the 64^3 tiles of k_discharge_rows64, with the same row ownership: lane y of
+// wave w holds the rows (y, z) with z = 8w .. 8w + 7 in registers.  At level 0
+// every region builds its residual-arc masks from HBM and keeps them, with the
+// mask of its unlabelled vertices, in a per-region cache (seven planes of 4096
+// rows); later levels read the cache.  The flood advances one step per
+// workgroup barrier, from t at level 0 and from the seed bits marked by the
+// previous level otherwise; reached vertices get label D, and reached border
+// vertices mark their residual predecessors across the border (unlabelled) as
+// seeds of D + 1 and flag their regions.
+__global__ __launch_bounds__(kNT) void k_grelabel_rows64(GRelabelArgs A) {
+    __shared__ __align__(16) u64 zF[kFaceWords];  // [2 parity][2 face][kW][64]
+    __shared__ __align__(16) unsigned char anyB[2][kW];
+    __shared__ int s_go;
+    const Geo &G = A.G;
+    const int V = G.V, N = G.N, D = A.level, dinf = A.dinf;
+    constexpr int R = kMaxRows;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int row0 = lane + 64 * kRPT * wid;  // row of slot j: row0 + 64 j
+    int rc = 0;
+    // predecessor across the border of the reached border vertex (z, y, x) in
+    // direction k: u = v + o_k with residual arc (u, v) in direction k ^ 1
+    auto mark = [&](int r, int z, int y, int x, int k) {
+        const int ug = cross_nbr(G, r, z, y, x, k);
+        if (ug < 0 || A.res[(size_t)(k ^ 1) * N + ug] <= 0 || A.lab[ug] != dinf) return;
+        atomicOr(&A.candBitsOut[ug >> 5], 1u << (ug & 31));
+        const int ru = ug / V;
+        if (A.flagOut[ru] == 0 && atomicExch(&A.flagOut[ru], 1) == 0) atomicAdd(A.flagged, 1u);
+    };
+    for (int r = blockIdx.x; r < G.nreg; r += gridDim.x) {
+        if (tid == 0) {
+            s_go = (D == 0) ? 1 : A.flagIn[r];
+            if (D > 0) A.flagIn[r] = 0;
+        }
+        __syncthreads();
+        const int go = s_go;
+        __syncthreads();
+        if (!go) continue;
+        const size_t base = (size_t)r * V;
+        GA u64 *cr = (GA u64 *)A.cache + (size_t)r * 7 * R;
+        u64 rk[kRPT][6], F[kRPT], avail[kRPT];
+        if (D == 0) {
+            // planes 0..5 residual arcs, plane 6 residual t-links (the seeds): one
+            // load of a plane brings one row (one vertex per lane), the seven
+            // planes of two rows are in flight before their ballots
+#pragma unroll
+            for (int j = 0; j < kRPT; j++) {
+                const int rowA = 64 * (kRPT * wid + j);
+#pragma unroll
+                for (int q = 0; q < 6; q++) rk[j][q] = 0ull;
+                F[j] = 0ull;
+#pragma unroll 1
+                for (int l0 = 0; l0 < 64; l0 += 2) {
+                    int v[2][7];
+#pragma unroll
+                    for (int i = 0; i < 2; i++) {
+                        const size_t off = base + (size_t)(rowA + l0 + i) * 64 + lane;
+#pragma unroll
+                        for (int q = 0; q < 7; q++) v[i][q] = (q < 6 ? A.res + (size_t)q * N : A.rt)[off];
+                    }
+#pragma unroll
+                    for (int i = 0; i < 2; i++) {
+#pragma unroll
+                        for (int q = 0; q < 6; q++) {
+                            const u64 b = __ballot(v[i][q] > 0);
+                            if (lane == l0 + i) rk[j][q] = b;
+                        }
+                        const u64 bt = __ballot(v[i][6] > 0);
+                        if (lane == l0 + i) F[j] = bt;
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kRPT; j++) {
+#pragma unroll
+                for (int q = 0; q < 6; q++) cr[(size_t)q * R + row0 + 64 * j] = rk[j][q];
+                avail[j] = ~F[j];
+            }
+        } else {
+            GA u64 *cb = (GA u64 *)A.candBitsIn + (base >> 6);
+#pragma unroll
+            for (int j = 0; j < kRPT; j++) {
+                const int row = row0 + 64 * j;
+#pragma unroll
+                for (int q = 0; q < 6; q++) rk[j][q] = cr[(size_t)q * R + row];
+                const u64 U = cr[(size_t)6 * R + row];
+                const u64 c = cb[row];
+                if (c) cb[row] = 0ull;
+                F[j] = c & U;
+                avail[j] = U & ~F[j];
+            }
+        }
+        int p = 0;
+        for (;;) {
+            u64 anyF = 0ull;
+#pragma unroll
+            for (int j = 0; j < kRPT; j++) anyF |= F[j];
+            zF[((p * 2 + 0) * kW + wid) * 64 + lane] = F[0];
+            zF[((p * 2 + 1) * kW + wid) * 64 + lane] = F[kRPT - 1];
+            if (!r64_block_any(anyF != 0ull, anyB, rc)) break;
+            // z = 8w - 1 (top face of the wave below) and z = 8w + 8 (bottom face of the wave above)
+            const u64 below = wid > 0 ? zF[((p * 2 + 1) * kW + wid - 1) * 64 + lane] : 0ull;
+            const u64 above = wid < kW - 1 ? zF[((p * 2 + 0) * kW + wid + 1) * 64 + lane] : 0ull;
+            u64 old[kRPT];
+#pragma unroll
+            for (int j = 0; j < kRPT; j++) old[j] = F[j];
+#pragma unroll
+            for (int j = 0; j < kRPT; j++) {
+                const u64 cur = old[j];
+                const u64 fzp = j < kRPT - 1 ? old[j + 1] : above;
+                const u64 fzm = j > 0 ? old[j - 1] : below;
+                const u64 fyp = r64_from_next_lane(cur), fym = r64_from_prev_lane(cur);
+                const u64 reach = (rk[j][0] & (cur >> 1)) | (rk[j][1] & (cur << 1)) | (rk[j][2] & fyp) |
+                                  (rk[j][3] & fym) | (rk[j][4] & fzp) | (rk[j][5] & fzm);
+                F[j] = reach & avail[j];
+                avail[j] &= ~F[j];
+            }
+            p ^= 1;
+        }
+        // reached = unlabelled before this level and not available now; the
+        // unlabelled mask of the cache is written by every row at level 0
+#pragma unroll
+        for (int j = 0; j < kRPT; j++) {
+            const int row = row0 + 64 * j;
+            const u64 U0 = D == 0 ? ~0ull : cr[(size_t)6 * R + row];
+            F[j] = U0 & ~avail[j];
+            if (D == 0 || F[j]) cr[(size_t)6 * R + row] = avail[j];
+        }
+#pragma unroll
+        for (int j = 0; j < kRPT; j++) r64_store_labels(A.lab + base, 64 * (kRPT * wid + j), F[j], D, lane);
+        // x faces: bit 63 leaves by +x, bit 0 by -x
+#pragma unroll
+        for (int j = 0; j < kRPT; j++) {
+            const int z = kRPT * wid + j;
+            if (F[j] >> 63) mark(r, z, lane, 63, 0);
+            if (F[j] & 1ull) mark(r, z, lane, 0, 1);
+        }
+        // y faces: the rows of lane 63 (+y) and lane 0 (-y), one vertex per lane
+#pragma unroll
+        for (int j = 0; j < kRPT; j++) {
+            const int z = kRPT * wid + j;
+            const u64 top = ((u64)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)(F[j] >> 32), 63) << 32) |
+                            (u64)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)F[j], 63);
+            const u64 bot = ((u64)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)(F[j] >> 32), 0) << 32) |
+                            (u64)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)F[j], 0);
+            if ((top >> lane) & 1ull) mark(r, z, 63, lane, 2);
+            if ((bot >> lane) & 1ull) mark(r, z, 0, lane, 3);
+        }
+        // z faces: slot 0 of wave 0 (-z) and slot 7 of the last wave (+z), one row
+        // (one y) at a time, one vertex per lane
+        if (wid == 0 || wid == kW - 1) {
+            const u64 m = wid == 0 ? F[0] : F[kRPT - 1];
+            const int z = wid == 0 ? 0 : 64 - 1, k = wid == 0 ? 5 : 4;
+            u64 pend = __ballot(m != 0ull);
+            while (pend) {
+                const int yy = __builtin_ctzll(pend);
+                pend &= pend - 1;
+                const u64 bits = ((u64)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)(m >> 32), yy) << 32) |
+                                 (u64)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)m, yy);
+                if ((bits >> lane) & 1ull) mark(r, z, yy, lane, k);
+            }
+        }
+    }
+}
+
+hipError_t launch_grelabel_rows64(const GRelabelArgs &A, int blocks, hipStream_t s) {
+    if (!rows64_applicable(A.G.K, A.G.tx, A.G.ty, A.G.tz) || !A.cache || !A.candBitsIn || !A.candBitsOut)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_grelabel_rows64, dim3(blocks), dim3(kNT), 0, s, A);
+    return hipGetLastError();
+}
+
+size_t grelabel_rows64_cache_bytes(int nreg) { return (size_t)nreg * 7 * kMaxRows * sizeof(u64); }
 
 void set_rows64_attributes() {
     (void)hipFuncSetAttribute((const void *)k_discharge_rows64, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -185,6 +185,10 @@ hipError_t launch_grelabel(const GRelabelArgs &A, int blocks, hipStream_t s);
 hipError_t launch_grelabel_rows(const GRelabelArgs &A, int blocks, hipStream_t s);
 size_t grelabel_rows_lds(int ty, int tz);
 hipError_t launch_grelabel_wave(const GRelabelArgs &A, int blocks, hipStream_t s);
+// Relabel level for the 64^3 tiles of the 64-vertex-row discharge; cache:
+// grelabel_rows64_cache_bytes(nreg) bytes.
+hipError_t launch_grelabel_rows64(const GRelabelArgs &A, int blocks, hipStream_t s);
+size_t grelabel_rows64_cache_bytes(int nreg);
 hipError_t launch_activity(const Geo &G, const int *ex, const int *lab, int dinf, int *ractive,
                            unsigned long long *act, hipStream_t s);
 

@@ -100,8 +100,9 @@ class mf_dimacs(ctypes.Structure):
 
 
 class MFError(RuntimeError):
-    def __init__(self, status, where):
+    def __init__(self, status, where, stats=None):
         self.status = status
+        self.stats = stats  # mf_solve on MF_E_SWEEPS: the statistics of the sweeps run
         super().__init__(f"{where}: {status_str(status)} (status {status})")
 
 
@@ -329,7 +330,10 @@ class Grid:
         if model is not None:
             o.model = model._h
         s = mf_solve_stats()
-        _check(load().mf_solve(self._h, ctypes.byref(o), ctypes.byref(s)), "mf_solve")
+        rc = load().mf_solve(self._h, ctypes.byref(o), ctypes.byref(s))
+        if rc == MF_E_SWEEPS:
+            raise MFError(rc, "mf_solve", s.as_dict())
+        _check(rc, "mf_solve")
         return s.as_dict()
 
     def flow_value(self):

@@ -156,6 +156,9 @@ def test_max_sweeps_stops_exactly(mf):
             g.solve(max_sweeps=3, label_trace=trace)
         assert e.value.status == mf.MF_E_SWEEPS
         lab = g.state()["labels"]
+        # the statistics of the three sweeps come with the error
+        st = e.value.stats
+        assert st is not None and st["sweeps"] == 3 and st["region_discharges"] > 0
     tr = trace.cpu().numpy()
     assert int((tr[:, 0] >= 0).sum()) == 3
     assert (tr[2] == lab).all()

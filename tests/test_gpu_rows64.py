@@ -86,3 +86,36 @@ def test_rows64_selection_errors(mf):
             with pytest.raises(mf.MFError) as e:
                 g.solve(region_kernel=mf.MF_KERNEL_ROWS64)
             assert e.value.status == mf.MF_E_INVAL
+
+
+
+@pytest.mark.parametrize("sweeps", [1, 2, 4])
+@pytest.mark.parametrize("kind", ["random", "blob"])
+def test_rows64_exact_relabel_is_region_distance(mf, kind, sweeps):
+    """Row a6 on 64^3 tiles (the 64-vertex-row relabel kernel): on the solver's
+    own state after 1, 2 and 4 sweeps, the exact relabel gives min(d*B, dinf)
+    bit for bit, d*B from a separate shortest-path computation; eight regions,
+    ragged on every axis, so that seeds cross every face direction."""
+    from tests.helpers import region_distance, state_to_pairs
+    dims = (100, 128, 90)
+    if kind == "random":
+        inst = synth.random_grid(dims, 6, 4500 + sweeps, tile=T64, cap_hi=12)
+    else:
+        inst = synth.blob_grid(dims, 6, 4510 + sweeps, 6, 4.0, 16.0, zero_frac=0.1, tile=T64,
+                               name=f"rows64_relabel_{sweeps}")
+    print(f"case {inst.name} dims={dims} sweeps={sweeps}", flush=True)
+    with mf.Grid(inst.dims, inst.conn, T64) as g:
+        g.set_caps(inst.cs, inst.ct, inst.nbr)
+        try:
+            g.solve(max_sweeps=sweeps, check_every=1, region_kernel=mf.MF_KERNEL_ROWS64)
+        except mf.MFError as e:
+            assert e.status == mf.MF_E_SWEEPS
+        dinf = max(g.info()["boundary_size"], 1)
+        g.global_relabel()
+        state = g.state()
+    pu, pv, _, _ = oracle.grid_pairs(inst.dims, inst.nbr, synth.offsets_for(3, 6))
+    region = oracle.grid_regions(inst.dims, T64)
+    r_uv, r_vu = state_to_pairs(inst, state)
+    dstar = region_distance(inst.n, pu, pv, r_uv, r_vu, region, state["rt"], dinf)
+    lab = state["labels"].astype(np.int64)
+    assert (lab == dstar).all(), f"{int((lab != dstar).sum())} labels differ from d*B"
