@@ -1208,16 +1208,19 @@ static mf_status compute_marks(mf_grid *g, int32_t kind) {
     const int Rr = G.ty * G.tz;
     const bool rows = g->ndim == 3 && G.K == 6 && G.tx == 32 && G.ty >= 2 && G.tz >= 2 &&
                       Rr % 64 == 0 && Rr <= 1024;
+    // 3D 64^3 tiles: one workgroup per region, 64-bit rows in registers
+    const bool rows64 = g->ndim == 3 && mfd::rows64_applicable(G.K, G.tx, G.ty, G.tz);
     int blocks = wave ? std::min(G.nreg, g->numCU * 16)
-                      : (rows ? std::min(G.nreg, g->numCU * 2)
-                              : std::min(G.nreg, g->nslots * 4));  // scratch holds 4V ints per slot
+                      : ((rows || rows64) ? std::min(G.nreg, g->numCU * 2)
+                                          : std::min(G.nreg, g->nslots * 4));  // scratch holds 4V ints per slot
     for (int round = 0;; round++) {
         A.round = round;
         A.dirtyIn = g->dirty + (size_t)(round & 1) * G.nreg;
         A.dirtyOut = g->dirty + (size_t)((round + 1) & 1) * G.nreg;
         HIP_TRY(hipMemsetAsync(g->changed, 0, sizeof(unsigned), s));
         HIP_TRY(wave ? mfd::launch_flood_wave(A, blocks, s)
-                     : (rows ? mfd::launch_flood_rows(A, blocks, s) : mfd::launch_flood(A, blocks, s)));
+                     : (rows ? mfd::launch_flood_rows(A, blocks, s)
+                             : (rows64 ? mfd::launch_flood_rows64(A, blocks, s) : mfd::launch_flood(A, blocks, s))));
         HIP_TRY(hipMemcpyAsync(g->pinned, g->changed, sizeof(unsigned), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (*(unsigned *)g->pinned == 0u) break;

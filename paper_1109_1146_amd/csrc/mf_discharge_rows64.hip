@@ -997,6 +997,169 @@ __global__ __launch_bounds__(kNT) void k_grelabel_rows64(GRelabelArgs A) {
     }
 }
 
+// Residual reachability for the cuts (the region floods of k_flood, same
+// marks) on the 64^3 tiles of k_discharge_rows64, with its row ownership.
+// dir 0 floods forward from the excess vertices along arcs with c_f > 0 (the
+// frontier is masked by the arcs at their tails and moved to their heads), dir
+// 1 backward from t.  Each round every dirty region builds its residual-arc
+// masks and its marks (round 0: the seeds) from HBM, floods one step per
+// workgroup barrier, stores the marks of the vertices it reached, and marks
+// the neighbours across the border that its reached border vertices reach
+// (atomic exchange, as k_flood), flagging their regions.
+__global__ __launch_bounds__(kNT) void k_flood_rows64(FloodArgs A) {
+    __shared__ __align__(16) u64 zF[kFaceWords];  // [2 parity][2 face][kW][64]
+    __shared__ __align__(16) unsigned char anyB[2][kW];
+    __shared__ int s_go;
+    const Geo &G = A.G;
+    const int V = G.V, N = G.N, dir = A.dir;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    int rc = 0;
+    // the neighbour wg across the border of the reached border vertex (z, y, x)
+    // in direction k, when the arc between them points the flood's way
+    auto xmark = [&](int r, int z, int y, int x, int k) {
+        const int wg = cross_nbr(G, r, z, y, x, k);
+        if (wg < 0) return;
+        // backward: the arc (u, v) from u = v + o_k, in direction k ^ 1, is residual
+        if (dir == 1 && A.res[(size_t)(k ^ 1) * N + wg] <= 0) return;
+        if (A.mark[wg] == 0 && atomicExch(&A.mark[wg], 1) == 0) {
+            A.dirtyOut[wg / V] = 1;
+            atomicAdd(A.changed, 1u);
+        }
+    };
+    for (int r = blockIdx.x; r < G.nreg; r += gridDim.x) {
+        if (tid == 0) {
+            s_go = (A.round == 0) ? 1 : A.dirtyIn[r];
+            A.dirtyIn[r] = 0;
+        }
+        __syncthreads();
+        const int go = s_go;
+        __syncthreads();
+        if (!go) continue;
+        const size_t base = (size_t)r * V;
+        // planes 0..5 residual arcs, plane 6 the marks (round 0: the seeds, ex > 0
+        // forward, r_t > 0 backward); one load of a plane brings one row
+        const int *p6 = A.round > 0 ? A.mark : (dir == 0 ? A.ex : A.rt);
+        u64 rk[kRPT][6], M[kRPT];
+#pragma unroll
+        for (int j = 0; j < kRPT; j++) {
+            const int rowA = 64 * (kRPT * wid + j);
+#pragma unroll
+            for (int q = 0; q < 6; q++) rk[j][q] = 0ull;
+            M[j] = 0ull;
+#pragma unroll 1
+            for (int l0 = 0; l0 < 64; l0 += 2) {
+                int v[2][7];
+#pragma unroll
+                for (int i = 0; i < 2; i++) {
+                    const size_t off = base + (size_t)(rowA + l0 + i) * 64 + lane;
+#pragma unroll
+                    for (int q = 0; q < 7; q++) v[i][q] = (q < 6 ? A.res + (size_t)q * N : p6)[off];
+                }
+#pragma unroll
+                for (int i = 0; i < 2; i++) {
+#pragma unroll
+                    for (int q = 0; q < 6; q++) {
+                        const u64 b = __ballot(v[i][q] > 0);
+                        if (lane == l0 + i) rk[j][q] = b;
+                    }
+                    const u64 bm = __ballot(v[i][6] > 0);
+                    if (lane == l0 + i) M[j] = bm;
+                }
+            }
+        }
+        u64 F[kRPT], reached[kRPT];
+#pragma unroll
+        for (int j = 0; j < kRPT; j++) F[j] = reached[j] = M[j];
+        int p = 0;
+        for (;;) {
+            u64 anyF = 0ull;
+#pragma unroll
+            for (int j = 0; j < kRPT; j++) anyF |= F[j];
+            // z faces: forward, the frontier on the arcs leaving the wave's slab
+            // (-z from slot 0, +z from slot 7); backward, the frontier itself
+            zF[((p * 2 + 0) * kW + wid) * 64 + lane] = dir == 0 ? (F[0] & rk[0][5]) : F[0];
+            zF[((p * 2 + 1) * kW + wid) * 64 + lane] = dir == 0 ? (F[kRPT - 1] & rk[kRPT - 1][4]) : F[kRPT - 1];
+            if (!r64_block_any(anyF != 0ull, anyB, rc)) break;
+            const u64 below = wid > 0 ? zF[((p * 2 + 1) * kW + wid - 1) * 64 + lane] : 0ull;
+            const u64 above = wid < kW - 1 ? zF[((p * 2 + 0) * kW + wid + 1) * 64 + lane] : 0ull;
+            u64 old[kRPT];
+#pragma unroll
+            for (int j = 0; j < kRPT; j++) old[j] = F[j];
+#pragma unroll
+            for (int j = 0; j < kRPT; j++) {
+                const u64 cur = old[j];
+                u64 reach;
+                if (dir == 0) {
+                    // heads of the residual arcs leaving the frontier
+                    const u64 fromZm = j > 0 ? (old[j - 1] & rk[j - 1][4]) : below;
+                    const u64 fromZp = j < kRPT - 1 ? (old[j + 1] & rk[j + 1][5]) : above;
+                    reach = ((cur & rk[j][0]) << 1) | ((cur & rk[j][1]) >> 1) | r64_from_prev_lane(cur & rk[j][2]) |
+                            r64_from_next_lane(cur & rk[j][3]) | fromZm | fromZp;
+                } else {
+                    // tails of the residual arcs entering the frontier
+                    const u64 fzp = j < kRPT - 1 ? old[j + 1] : above;
+                    const u64 fzm = j > 0 ? old[j - 1] : below;
+                    reach = (rk[j][0] & (cur >> 1)) | (rk[j][1] & (cur << 1)) | (rk[j][2] & r64_from_next_lane(cur)) |
+                            (rk[j][3] & r64_from_prev_lane(cur)) | (rk[j][4] & fzp) | (rk[j][5] & fzm);
+                }
+                F[j] = reach & ~reached[j];
+                reached[j] |= F[j];
+            }
+            p ^= 1;
+        }
+        // marks of this round, seeds included (stores of 1 race harmlessly with
+        // the neighbours' exchanges)
+#pragma unroll
+        for (int j = 0; j < kRPT; j++)
+            r64_store_labels(A.mark + base, 64 * (kRPT * wid + j), A.round > 0 ? reached[j] & ~M[j] : reached[j], 1,
+                             lane);
+        // reached border vertices; forward only those whose leaving arc is residual
+        // x faces: bit 63 leaves by +x, bit 0 by -x
+#pragma unroll
+        for (int j = 0; j < kRPT; j++) {
+            const int z = kRPT * wid + j;
+            const u64 m0 = dir == 0 ? reached[j] & rk[j][0] : reached[j];
+            const u64 m1 = dir == 0 ? reached[j] & rk[j][1] : reached[j];
+            if (m0 >> 63) xmark(r, z, lane, 63, 0);
+            if (m1 & 1ull) xmark(r, z, lane, 0, 1);
+        }
+        // y faces: the rows of lane 63 (+y) and lane 0 (-y), one vertex per lane
+#pragma unroll
+        for (int j = 0; j < kRPT; j++) {
+            const int z = kRPT * wid + j;
+            const u64 m2 = dir == 0 ? reached[j] & rk[j][2] : reached[j];
+            const u64 m3 = dir == 0 ? reached[j] & rk[j][3] : reached[j];
+            const u64 top = ((u64)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)(m2 >> 32), 63) << 32) |
+                            (u64)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)m2, 63);
+            const u64 bot = ((u64)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)(m3 >> 32), 0) << 32) |
+                            (u64)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)m3, 0);
+            if ((top >> lane) & 1ull) xmark(r, z, 63, lane, 2);
+            if ((bot >> lane) & 1ull) xmark(r, z, 0, lane, 3);
+        }
+        // z faces: slot 0 of wave 0 (-z) and slot 7 of the last wave (+z), one row
+        // (one y) at a time, one vertex per lane
+        if (wid == 0 || wid == kW - 1) {
+            const int k = wid == 0 ? 5 : 4, z = wid == 0 ? 0 : 64 - 1;
+            const u64 rm = wid == 0 ? reached[0] : reached[kRPT - 1];
+            const u64 m = dir == 0 ? rm & (wid == 0 ? rk[0][5] : rk[kRPT - 1][4]) : rm;
+            u64 pend = __ballot(m != 0ull);
+            while (pend) {
+                const int yy = __builtin_ctzll(pend);
+                pend &= pend - 1;
+                const u64 bits = ((u64)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)(m >> 32), yy) << 32) |
+                                 (u64)(unsigned)__builtin_amdgcn_readlane((int)(unsigned)m, yy);
+                if ((bits >> lane) & 1ull) xmark(r, z, yy, lane, k);
+            }
+        }
+    }
+}
+
+hipError_t launch_flood_rows64(const FloodArgs &A, int blocks, hipStream_t s) {
+    if (!rows64_applicable(A.G.K, A.G.tx, A.G.ty, A.G.tz) || A.noCross) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_flood_rows64, dim3(blocks), dim3(kNT), 0, s, A);
+    return hipGetLastError();
+}
+
 hipError_t launch_grelabel_rows64(const GRelabelArgs &A, int blocks, hipStream_t s) {
     if (!rows64_applicable(A.G.K, A.G.tx, A.G.ty, A.G.tz) || !A.cache || !A.candBitsIn || !A.candBitsOut)
         return hipErrorInvalidValue;

@@ -189,6 +189,8 @@ hipError_t launch_grelabel_wave(const GRelabelArgs &A, int blocks, hipStream_t s
 // grelabel_rows64_cache_bytes(nreg) bytes.
 hipError_t launch_grelabel_rows64(const GRelabelArgs &A, int blocks, hipStream_t s);
 size_t grelabel_rows64_cache_bytes(int nreg);
+// Cut flood round for the 64^3 tiles of the 64-vertex-row discharge.
+hipError_t launch_flood_rows64(const FloodArgs &A, int blocks, hipStream_t s);
 hipError_t launch_activity(const Geo &G, const int *ex, const int *lab, int dinf, int *ractive,
                            unsigned long long *act, hipStream_t s);
 
