@@ -58,7 +58,7 @@ WORKLOADS = {
     "batch": dict(cfg=3, tag="batch512", relabel=None, partial=None, desc="512 independent 2D blob grids, sides log-uniform in [32,512], "
                               "half 4- and half 8-connected, seeds 3000+i, one batched solve"),
     # the headline workload: plain vs learned-ordered ARD
-    "464": dict(cfg=4, tag="grid3d6_464", relabel=4, partial=True, round_cap=24, crop=(192, 192, 192),
+    "464": dict(cfg=4, tag="grid3d6_464", relabel=3, partial=True, round_cap=16, crop=(192, 192, 192),
                 reference="grid3d6_464_oracle.json",
                 desc="464^3 3D 6-connected blob grid, 256 blobs, 64^3 regions (512; last layer 16 thick), seed 4"),
 }
