@@ -276,7 +276,7 @@ def bench_batch(args):
             lkw = dict(schedule=mf.MF_SCHED_LEARNED, model=model, defer_threshold=learned.DEFAULT_THRESHOLD,
                        max_defer=learned.DEFAULT_MAX_DEFER, global_relabel_every=tune["relabel_every"],
                        stream=stream.cuda_stream, partial=args.partial,
-                       boundary_relabel=args.boundary_relabel)
+                       boundary_relabel=args.boundary_relabel, round_cap=tune["round_cap"])
             b.solve(**lkw)
             lt = []
             for _ in range(max(1, min(args.steps, 3))):
