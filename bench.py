@@ -313,7 +313,7 @@ def bench_batch(args):
 
 
 
-GRAPH = dict(dims=(128, 128, 128), seed=9000, tile=(16, 16, 16), pages=64,
+GRAPH = dict(dims=(128, 128, 128), seed=9000, tile=(16, 16, 16), pages=64, round_cap=2,
              desc="128^3 volume with the 26-neighbourhood (26.8 M pairs, capacities <= 100), "
                   "4 blobs with sharp borders, 16^3 box regions (512), seed 9000")
 
@@ -340,7 +340,7 @@ def bench_graph(args, steps, warmup, cpu):
             try:
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                st = g.solve()
+                st = g.solve(round_cap=GRAPH["round_cap"])
                 smin = g.min_cut(mf.MF_CUT_MIN_SOURCE)
                 smax = g.min_cut(mf.MF_CUT_MAX_SOURCE)
                 torch.cuda.synchronize()
@@ -358,7 +358,7 @@ def bench_graph(args, steps, warmup, cpu):
     # one profiled solve: the discharge launches timed by HIP events on the solve stream
     g = mf.Graph(inst.n, *inst.arrays(), region=reg)
     try:
-        pst = g.solve(profile=True)
+        pst = g.solve(profile=True, round_cap=GRAPH["round_cap"])
     finally:
         g.close()
     D, V, A = pst["discharges"], pst["discharged_vertices"], pst["discharged_arcs"]
@@ -367,7 +367,7 @@ def bench_graph(args, steps, warmup, cpu):
     achieved = d_bytes / (d_ms / 1e3) / 1e9 if d_ms > 0 else 0.0
     rec = {"workload": GRAPH["desc"], "n": inst.n, "pairs": inst.npairs, "steps": steps, "warmup": warmup,
            "ms_per_step": round(ms_res * 1e3, 3), "value": round(inst.n / ms_res / 1e6, 3),
-           "unit": "Mvertices/s", "sweeps": res["stats"]["sweeps"],
+           "unit": "Mvertices/s", "round_cap": GRAPH["round_cap"], "sweeps": res["stats"]["sweeps"],
            "region_discharges": res["stats"]["discharges"], "boundary_size": res["info"]["boundary_size"],
            "push_rounds_per_discharge": round(res["stats"]["push_rounds"] / max(res["stats"]["discharges"], 1), 2),
            "search_levels_per_discharge": round(res["stats"]["search_steps"] / max(res["stats"]["discharges"], 1), 1),

@@ -452,6 +452,11 @@ typedef struct {
     int32_t gap;                 /* global gap heuristic: 1 = on (the default with opts NULL), 0 = off */
     int32_t check_every;         /* resident pages: sweeps enqueued between termination checks; 0 = 8 */
     int32_t profile;             /* 1 = time every discharge launch with HIP events */
+    int32_t round_cap;           /* n > 0: a region discharge runs at most n push rounds in a
+                                  * sweep; its last, complete search then writes the region
+                                  * relabel (Alg. 3) on the current state and a region still
+                                  * holding excess that reaches a target stays active for the
+                                  * next sweep; 0 = no cap (Proc. ARD to the end).  < 0: MF_E_INVAL */
 } mf_graph_opts;
 
 typedef struct {

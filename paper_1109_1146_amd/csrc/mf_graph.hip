@@ -86,6 +86,9 @@ struct Args {
     int *err;
     u64 *stats;         // [0] discharges [1] push rounds [2] search steps [3] vertices [4] arcs
     const u64 *actIn;
+    int roundCap;       // > 0: at most this many push rounds per discharge and sweep
+    u64 *actCarry;      // regions a capped discharge left active (counted into the next sweep)
+    int *ractive;       // region flags of the next sweep
     int mode;           // flood: 0 = backward from t, 1 = forward from the excess
     int first;          // flood: first round
     int *markB;         // flood marks of the boundary vertices
@@ -206,6 +209,10 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
         __syncthreads();
         long long iter = 0, steps = 0;
         bool firstSearch = true, lastComplete = false;
+        // round cap: after roundCap push rounds one more complete search writes
+        // the region relabel on the current state; excess it still finds reaching
+        // a target stays in the region, which stays active
+        bool finalSearch = false;
         for (;;) {
             bool early = false;
             if (tid == 0) {
@@ -263,7 +270,7 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
                     s_nsteps = 1;
                 }
                 s_fe = s_qtail;
-                s_stop = s_hit && s_live == 0;
+                s_stop = !finalSearch && s_hit && s_live == 0;
             }
             __syncthreads();
             int fs = 0;
@@ -316,7 +323,7 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
                             s_nsteps = step + 1;
                         }
                         s_fe = s_qtail;
-                        s_stop = s_hit && s_live == 0;
+                        s_stop = !finalSearch && s_hit && s_live == 0;
                     }
                     fs = fe;
                     __syncthreads();
@@ -354,7 +361,7 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
                     stepLevel[step] = level;
                     s_nsteps = step + 1;
                     s_fe = s_qtail;
-                    s_stop = s_hit && s_live == 0;
+                    s_stop = !finalSearch && s_hit && s_live == 0;
                 }
                 __syncthreads();
             }
@@ -369,6 +376,13 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
             if (found) s_found = 1;
             __syncthreads();
             if (!s_found) break;
+            if (finalSearch) {
+                if (tid == 0) {
+                    A.ractive[r] = 1;
+                    atomicAdd(A.actCarry, 1ull);
+                }
+                break;
+            }
             if (++iter > A.maxIter) {
                 if (tid == 0) atomicOr(A.err, 4);
                 break;
@@ -436,6 +450,7 @@ __global__ __launch_bounds__(NT) void k_gdischarge(Args A) {
                 }
                 __syncthreads();
             }
+            if (A.roundCap > 0 && iter >= A.roundCap) finalSearch = true;
         }
         // region relabel (Alg. 3): a vertex's label is its stage, d_inf without one
         for (int l = tid; l < nv; l += NT) {
@@ -702,6 +717,8 @@ struct mf_graph {
     int *err = nullptr, *maxlab = nullptr, *gap = nullptr;
     unsigned *qhead = nullptr, *changed = nullptr, *hist = nullptr;
     u64 *act = nullptr, *counters = nullptr, *stats = nullptr, *sum = nullptr;
+    u64 *carry = nullptr;             // regions left active by capped discharges, per sweep
+    int roundCap = 0;                 // push rounds per discharge and sweep, 0: no cap
     unsigned char *cutbuf = nullptr;
     void *pinned = nullptr;           // mailbox: [0..7] words, then the region list
     hipStream_t s = nullptr, sc = nullptr, sd = nullptr;  // solve, page loads, page write-backs
@@ -737,7 +754,7 @@ void free_graph(mf_graph *g) {
     void *d[] = {g->pool, g->blocal, g->bregion, g->lab[0], g->lab[1], g->drinfo, g->exIn, g->cr,
                  g->cp, g->cslot, g->order, g->allreg, g->cnt, g->ractive, g->scratch, g->markB,
                  g->err, g->maxlab, g->gap, g->qhead, g->changed, g->hist, g->act, g->counters,
-                 g->stats, g->sum, g->cutbuf};
+                 g->stats, g->sum, g->carry, g->cutbuf};
     for (void *p : d)
         if (p) (void)hipFree(p);
     if (g->hpages) (void)hipHostFree(g->hpages);
@@ -777,6 +794,9 @@ mfg::Args base_args(mf_graph *g) {
     A.sum = g->sum;
     A.slotBase = -1;
     A.listN = -1;
+    A.roundCap = g->roundCap;
+    A.actCarry = g->carry;
+    A.ractive = g->ractive;
     return A;
 }
 
@@ -946,7 +966,7 @@ mf_status enqueue_sweep(mf_graph *g, long long i, bool gapOn, int *regionsOut) {
     G.actOut = actOut;
     G.qheadNext = g->qhead;
     G.counters = g->counters;
-    G.actCarry = nullptr;
+    G.actCarry = g->carry;  // zero unless a capped discharge left its region active
     GTRY(mfd::launch_gap_find(G, s));
     hipLaunchKernelGGL(mfg::k_gapply, dim3(cdiv(std::max(g->nB, 1), 256)), dim3(256), 0, s, labNew, g->exIn,
                        g->bregion, g->ractive, g->nB, g->gap, g->dinf, actOut, actIn);
@@ -1247,6 +1267,7 @@ static mf_status mf_create_graph_impl(int32_t n, int64_t npairs, const int32_t *
            ok(dalloc(&g->qhead, 2)) && ok(dalloc(&g->changed, 1)) &&
            ok(dalloc(&g->hist, (size_t)mfd::kHistBins)) && ok(dalloc(&g->act, 2)) &&
            ok(dalloc(&g->counters, 4)) && ok(dalloc(&g->stats, 8)) && ok(dalloc(&g->sum, 1)) &&
+           ok(dalloc(&g->carry, 1)) &&
            ok(dalloc(&g->cutbuf, (size_t)n)) &&
            ok(hipHostMalloc(&g->pinned, sizeof(int) * (16 + (size_t)K), 0));
     if (!good) {
@@ -1275,6 +1296,7 @@ static mf_status mf_create_graph_impl(int32_t n, int64_t npairs, const int32_t *
            ok(hipMemsetAsync(g->hist, 0, sizeof(unsigned) * (size_t)mfd::kHistBins, s)) &&
            ok(hipMemcpyAsync(g->act, actInit, sizeof(actInit), hipMemcpyHostToDevice, s)) &&
            ok(hipMemsetAsync(g->counters, 0, sizeof(u64) * 4, s)) &&
+           ok(hipMemsetAsync(g->carry, 0, sizeof(u64), s)) &&
            ok(hipMemsetAsync(g->stats, 0, sizeof(u64) * 8, s));
     if (good && g->resident && storeWords > 0)
         good = ok(hipMemcpyAsync(g->pool, hp, storeWords * sizeof(int), hipMemcpyHostToDevice, s));
@@ -1317,8 +1339,9 @@ static mf_status mf_graph_solve_impl(mf_graph *g, const mf_graph_opts *opts, mf_
     memset(&o, 0, sizeof(o));
     o.gap = 1;
     if (opts) o = *opts;
-    if (o.max_sweeps < 0 || o.check_every < 0) return MF_E_INVAL;
+    if (o.max_sweeps < 0 || o.check_every < 0 || o.round_cap < 0) return MF_E_INVAL;
     GTRY(hipSetDevice(g->device));
+    g->roundCap = o.round_cap;
     const long long bound = 2LL * g->nB * g->nB + 1;
     const long long maxSweeps = o.max_sweeps > 0 ? o.max_sweeps : bound;
     const int every = o.check_every > 0 ? o.check_every : 8;

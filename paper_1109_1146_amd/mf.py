@@ -79,7 +79,7 @@ class mf_graph_info(ctypes.Structure):
 
 class mf_graph_opts(ctypes.Structure):
     _fields_ = [("max_sweeps", ctypes.c_int64), ("gap", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("profile", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("round_cap", ctypes.c_int32)]
 
 
 class mf_graph_stats(ctypes.Structure):
@@ -590,8 +590,10 @@ class Graph:
         _check(load().mf_graph_get_info(self._h, ctypes.byref(i)), "mf_graph_get_info")
         return {f: getattr(i, f) for f, _ in mf_graph_info._fields_}
 
-    def solve(self, max_sweeps=0, gap=True, check_every=0, profile=False):
-        o = mf_graph_opts(int(max_sweeps), 1 if gap else 0, int(check_every), 1 if profile else 0)
+    def solve(self, max_sweeps=0, gap=True, check_every=0, profile=False, round_cap=0):
+        """round_cap: n > 0 caps a region discharge at n push rounds per sweep."""
+        o = mf_graph_opts(int(max_sweeps), 1 if gap else 0, int(check_every), 1 if profile else 0,
+                          int(round_cap))
         st = mf_graph_stats()
         _check(load().mf_graph_solve(self._h, ctypes.byref(o), ctypes.byref(st)), "mf_graph_solve")
         return {f: getattr(st, f) for f, _ in mf_graph_stats._fields_}

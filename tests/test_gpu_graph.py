@@ -27,9 +27,9 @@ def _region_of(inst, region, region_size):
     return np.arange(inst.n) // region_size
 
 
-def _check(mf, inst, region=None, region_size=4096, device_pages=0, **kw):
+def _check(mf, inst, region=None, region_size=4096, device_pages=0, sweep_bound=True, **kw):
     print(f"case {inst.name} n={inst.n} pairs={inst.npairs} regions="
-          f"{'given' if region is not None else f'blocks of {region_size}'} pages={device_pages}", flush=True)
+          f"{'given' if region is not None else f'blocks of {region_size}'} pages={device_pages} {kw}", flush=True)
     out = mf.solve_graph(inst, region=region, region_size=region_size, device_pages=device_pages, **kw)
     ref = oracle.solve_pairs(inst.n, *inst.arrays())
     assert out["flow"] == ref["flow"]
@@ -49,7 +49,8 @@ def _check(mf, inst, region=None, region_size=4096, device_pages=0, **kw):
     lab = st["labels"].astype(np.int64)
     assert (lab >= 0).all() and (lab <= dinf).all()
     assert_valid_labels(inst.pu, inst.pv, st["r_uv"], st["r_vu"], reg, st["rt"], lab, bmask, dinf)
-    assert out["stats"]["sweeps"] <= 2 * info["boundary_size"] ** 2 + 1
+    if sweep_bound:
+        assert out["stats"]["sweeps"] <= 2 * info["boundary_size"] ** 2 + 1
     return out
 
 
@@ -192,3 +193,39 @@ def test_sparse_region_numbers(mf):
     b = _check(mf, inst, region=sparse)
     assert a["info"]["regions"] == b["info"]["regions"] == 12
     assert a["info"]["boundary_size"] == b["info"]["boundary_size"]
+
+
+# n, degree, regions, region size / count, round cap, device page slots (0: resident)
+ROUNDCAP = [
+    (2000, 6, "blocks", 256, 1, 0), (5000, 8, "blocks", 700, 2, 0), (8000, 5, "scattered", 40, 1, 0),
+    (3000, 10, "blocks", 100, 3, 0), (20000, 6, "blocks", 2048, 1, 3), (6000, 6, "blocks", 500, 2, 1),
+]
+
+
+@pytest.mark.parametrize("case", range(len(ROUNDCAP)))
+def test_round_cap(mf, case):
+    """Capped push rounds per discharge and sweep (the reading of capped rounds:
+    the last, complete search of a capped discharge writes the region relabel
+    and the region stays active): the same exact flow, both cuts, a certified
+    state and valid labels, resident and streamed."""
+    n, deg, kind, size, cap, pages = ROUNDCAP[case]
+    inst = synth.random_graph(n, deg, 8600 + case, long_frac=0.1)
+    region = synth.random_regions(n, size, 8700 + case) if kind == "scattered" else None
+    out = _check(mf, inst, region=region, region_size=size, device_pages=pages, sweep_bound=False,
+                 round_cap=cap)
+    assert out["stats"]["push_rounds"] <= out["stats"]["discharges"] * (cap + 1)
+
+
+@pytest.mark.parametrize("cap", [1, 2])
+def test_round_cap_26_connected(mf, cap):
+    dims, tile = (40, 36, 44), (12, 12, 12)
+    inst = synth.grid26_graph(dims, 8800 + cap)
+    _check(mf, inst, region=synth.block_regions(dims, tile), sweep_bound=False, round_cap=cap)
+
+
+def test_round_cap_rejected_when_negative(mf):
+    inst = synth.random_graph(300, 4, 8900)
+    with mf.Graph(inst.n, inst.pu, inst.pv, inst.cuv, inst.cvu, inst.cs, inst.ct, region_size=64) as g:
+        with pytest.raises(mf.MFError) as e:
+            g.solve(round_cap=-1)
+        assert e.value.status == mf.MF_E_INVAL
