@@ -137,6 +137,17 @@ __device__ __forceinline__ GA T *r64_opaque(GA T *p) {
     return p;
 }
 
+// A pointer the compiler knows to be uniform (scalar registers): a global
+// access through it plus a 32-bit per-lane byte offset takes the scalar-base
+// form, with no 64-bit address arithmetic in the vector ALU.
+template <typename T>
+__device__ __forceinline__ GA T *r64_uniform(GA T *p) {
+    const u64 v = (u64)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (GA T *)(((u64)hi << 32) | lo);
+}
+
 // Non-returning relaxed atomics on global words.
 __device__ __forceinline__ void g_or(GA u64 *p, u64 v) {
     __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -424,53 +435,50 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                     if (!(any & 1)) break;
                     levels++;
                     // z = 8w - 1 (top face of the wave below) and z = 8w + 8 (bottom face of the wave above)
-                    GA u64 *admL = r64_opaque(admG);
                     u64 prev = wid > 0 ? zF[((p * 2 + 1) * kW + wid - 1) * 64 + lane] : 0ull;
                     const u64 above = wid < kW - 1 ? zF[((p * 2 + 0) * kW + wid + 1) * 64 + lane] : 0ull;
-                    // Pass 1, every slot without branches (the eight slots are
-                    // independent, so their instructions interleave): the new
-                    // vertices nw of each row, u with c_f(u, u + o_k) > 0 and
-                    // u + o_k in the frontier (y +- 1 from the neighbouring lanes,
-                    // z +- 1 from the neighbouring slots or waves).
                     u64 old[kRPT];
 #pragma unroll
                     for (int j = 0; j < kRPT; j++) old[j] = F[j];
+                    // One pass per slot (the eight slots are independent, so their
+                    // instructions interleave): the new vertices nw of each row,
+                    // u with c_f(u, u + o_k) > 0 and u + o_k in the frontier (y +- 1
+                    // from the neighbouring lanes, z +- 1 from the neighbouring slots
+                    // or waves), then the arcs by which they were reached, their
+                    // admissible arcs, ORed into one plane per direction.  The level
+                    // is bound by vector-ALU issue: the six ORs go out for every lane
+                    // with new vertices, without a test per direction (a 64-bit
+                    // compare and branch each cost more than the ORs of zero), and
+                    // address the planes by scalar base and 32-bit offset.
+                    GA u64 *ad0 = r64_uniform(admG), *ad1 = r64_uniform(admG + R), *ad2 = r64_uniform(admG + 2 * R);
+                    GA u64 *ad3 = r64_uniform(admG + 3 * R), *ad4 = r64_uniform(admG + 4 * R), *ad5 = r64_uniform(admG + 5 * R);
 #pragma unroll
                     for (int j = 0; j < kRPT; j++) {
                         const u64 cur = old[j];
                         const u64 fzp = j < kRPT - 1 ? old[j + 1] : above;
                         const u64 fzm = j > 0 ? old[j - 1] : prev;
                         const u64 fyp = r64_from_next_lane(cur), fym = r64_from_prev_lane(cur);
-                        const u64 reach = (rk[j][0] & (cur >> 1)) | (rk[j][1] & (cur << 1)) | (rk[j][2] & fyp) |
-                                          (rk[j][3] & fym) | (rk[j][4] & fzp) | (rk[j][5] & fzm);
-                        F[j] = reach & ~vis[j];
-                        vis[j] |= F[j];
-                    }
-                    // Pass 2, slots with new vertices in some lane: the arcs by which
-                    // the new vertices were reached are their admissible arcs (a
-                    // writing search is followed by no push: it needs neither them
-                    // nor the count of unlabelled excess vertices)
-#pragma unroll
-                    for (int j = 0; j < kRPT; j++) {
-                        const u64 nw = F[j];
+                        const u64 a0 = rk[j][0] & (cur >> 1), a1 = rk[j][1] & (cur << 1), a2 = rk[j][2] & fyp;
+                        const u64 a3 = rk[j][3] & fym, a4 = rk[j][4] & fzp, a5 = rk[j][5] & fzm;
+                        const u64 nw = (a0 | a1 | a2 | a3 | a4 | a5) & ~vis[j];
+                        F[j] = nw;
+                        vis[j] |= nw;
+                        // a writing search is followed by no push: it needs neither the
+                        // admissible arcs nor the count of unlabelled excess vertices
                         if (writeMode || __ballot(nw != 0ull) == 0ull) continue;
-                        const u64 cur = old[j];
-                        const u64 fzp = j < kRPT - 1 ? old[j + 1] : above;
-                        const u64 fzm = j > 0 ? old[j - 1] : prev;
-                        const u64 fyp = r64_from_next_lane(cur), fym = r64_from_prev_lane(cur);
                         if (!nw) continue;
-                        const int row = row0 + 64 * j;
+                        const unsigned row = (unsigned)(row0 + 64 * j);
                         if (nw & exM[j]) cnt -= __popcll(nw & exM[j] & ~deadB[row]);
-                        GA u64 *ad = admL + (unsigned)row;
-                        const u64 t0 = nw & rk[j][0] & (cur >> 1), t1 = nw & rk[j][1] & (cur << 1);
-                        const u64 t2 = nw & rk[j][2] & fyp, t3 = nw & rk[j][3] & fym;
-                        const u64 t4 = nw & rk[j][4] & fzp, t5 = nw & rk[j][5] & fzm;
-                        if (t0) g_or(ad, t0);
-                        if (t1) g_or(ad + R, t1);
-                        if (t2) g_or(ad + 2 * R, t2);
-                        if (t3) g_or(ad + 3 * R, t3);
-                        if (t4) g_or(ad + 4 * R, t4);
-                        if (t5) g_or(ad + 5 * R, t5);
+                        // an opaque 32-bit offset: widened to 64 bits, it would no
+                        // longer fit the scalar-base form
+                        unsigned boff = row * 8u;
+                        asm volatile("" : "+v"(boff));
+                        g_or((GA u64 *)((GA char *)ad0 + boff), nw & a0);
+                        g_or((GA u64 *)((GA char *)ad1 + boff), nw & a1);
+                        g_or((GA u64 *)((GA char *)ad2 + boff), nw & a2);
+                        g_or((GA u64 *)((GA char *)ad3 + boff), nw & a3);
+                        g_or((GA u64 *)((GA char *)ad4 + boff), nw & a4);
+                        g_or((GA u64 *)((GA char *)ad5 + boff), nw & a5);
                     }
                     p ^= 1;
                 }
