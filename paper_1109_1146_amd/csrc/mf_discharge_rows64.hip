@@ -732,17 +732,41 @@ __global__ __launch_bounds__(kNT) void k_discharge_rows64(DischargeArgs A) {
                             const int it = it0 + b * kNT;
                             uu[b] = it < nItems ? (int)wlist[it] : -1;
                         }
+                        // every load of the kInFlight vertices issued before any is
+                        // used, without a branch (an empty entry reads vertex 0 and is
+                        // masked afterwards), and of each 64-bit row word only the
+                        // 32-bit half that holds the vertex's bit: with branches and
+                        // whole words the compiler, at this register pressure, put
+                        // each load behind the previous one's wait
+                        {
+                            unsigned hw[kInFlight][7];
+                            int ev[kInFlight];
+                            GA const unsigned *rt32 = (GA const unsigned *)r64_uniform(rtG);
+                            GA const unsigned *ad32 = (GA const unsigned *)r64_uniform(admG);
+                            GA const int *ex32 = (GA const int *)r64_uniform((GA int *)(A.ex + base));
 #pragma unroll
-                        for (int b = 0; b < kInFlight; b++) {
-                            rtw[b] = 0ull;
-                            a0[b] = 0u;
-                            ee[b] = 0;
-                            if (uu[b] >= 0) {
-                                rtw[b] = rtG[uu[b] >> 6];
-                                const unsigned rr = (unsigned)(uu[b] >> 6), xb = (unsigned)(uu[b] & 63);
+                            for (int b = 0; b < kInFlight; b++) {
+                                const unsigned u = uu[b] >= 0 ? (unsigned)uu[b] : 0u;
+                                unsigned hi = u >> 5;  // 32-bit word of the bit: 2 rr + (xb >> 5)
+                                asm volatile("" : "+v"(hi));
+                                hw[b][6] = rt32[hi];
 #pragma unroll
-                                for (int k = 0; k < 6; k++) a0[b] |= (unsigned)((admG[(size_t)k * R + rr] >> xb) & 1ull) << k;
-                                ee[b] = A.ex[base + uu[b]];
+                                for (int k = 0; k < 6; k++) hw[b][k] = ad32[(unsigned)(2 * k * R) + hi];
+                                unsigned uo = u;
+                                asm volatile("" : "+v"(uo));
+                                ev[b] = ex32[uo];
+                            }
+#pragma unroll
+                            for (int b = 0; b < kInFlight; b++) {
+                                const bool in = uu[b] >= 0;
+                                const unsigned sh = (unsigned)uu[b] & 31u;
+                                unsigned a = 0u;
+#pragma unroll
+                                for (int k = 0; k < 6; k++) a |= ((hw[b][k] >> sh) & 1u) << k;
+                                a0[b] = in ? a : 0u;
+                                // the t-link bit in its place in the 64-bit row word
+                                rtw[b] = (in && ((hw[b][6] >> sh) & 1u)) ? (1ull << ((unsigned)uu[b] & 63u)) : 0ull;
+                                ee[b] = in ? ev[b] : 0;
                             }
                         }
 #pragma unroll
