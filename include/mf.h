@@ -84,7 +84,8 @@ typedef struct {
     int32_t global_relabel_every; /* exact region-distance relabel every N sweeps; 0 = off */
     int32_t gap;                  /* 1 = global gap heuristic on (default), 0 = off */
     int32_t check_every;          /* sweeps enqueued between host-side termination checks; 0 = 8 */
-    int64_t max_sweeps;           /* guard; 0 = 2|B|^2 + 1 (the bound of Sec. 4.3-4.4) */
+    int64_t max_sweeps;           /* guard; 0 = 2|B|^2 + 1 (the bound of Sec. 4.3-4.4), at least
+                                   * 2^20 with round_cap > 0, where that bound does not hold */
     const void *model;            /* mf_model * for MF_SCHED_LEARNED, else NULL */
     void *stream;                 /* hipStream_t to run on; NULL = the null stream */
     int32_t profile;              /* 1 = time every discharge launch with HIP events */
@@ -448,7 +449,8 @@ typedef struct {
 } mf_graph_info;
 
 typedef struct {
-    int64_t max_sweeps;          /* guard; 0 = 2|B|^2 + 1 (the bound of Sec. 4.3-4.4) */
+    int64_t max_sweeps;          /* guard; 0 = 2|B|^2 + 1 (the bound of Sec. 4.3-4.4), at least
+                                  * 2^20 with round_cap > 0, where that bound does not hold */
     int32_t gap;                 /* global gap heuristic: 1 = on (the default with opts NULL), 0 = off */
     int32_t check_every;         /* resident pages: sweeps enqueued between termination checks; 0 = 8 */
     int32_t profile;             /* 1 = time every discharge launch with HIP events */

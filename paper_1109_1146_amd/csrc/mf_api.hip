@@ -840,6 +840,9 @@ extern "C" mf_status mf_solve(mf_grid *g, const mf_solve_opts *opts, mf_solve_st
     const int dinf = prd ? (int)std::max<long long>(g->n, 1) : g->dinf;
     long long B = prd ? (long long)dinf : (g->nB > 0 ? g->nB : 1);
     long long bound = (B > 2000000000LL) ? (1LL << 62) : 2 * B * B + 1;
+    // capped rounds spread one discharge over several sweeps, so the bound of
+    // full discharges does not hold: the default guard is then at least 2^20
+    if (o.round_cap > 0) bound = std::max(bound, 1LL << 20);
     long long max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : bound;
     // the device counts steps: sweeps (Alg. 2) or colour phases (Alg. 1)
     const long long max_steps = max_sweeps > (1LL << 60) / ncol ? max_sweeps : max_sweeps * ncol;

@@ -1342,7 +1342,9 @@ static mf_status mf_graph_solve_impl(mf_graph *g, const mf_graph_opts *opts, mf_
     if (o.max_sweeps < 0 || o.check_every < 0 || o.round_cap < 0) return MF_E_INVAL;
     GTRY(hipSetDevice(g->device));
     g->roundCap = o.round_cap;
-    const long long bound = 2LL * g->nB * g->nB + 1;
+    // capped rounds spread one discharge over several sweeps, so the bound of
+    // full discharges does not hold: the default guard is then at least 2^20
+    const long long bound = o.round_cap > 0 ? std::max(2LL * g->nB * g->nB + 1, 1LL << 20) : 2LL * g->nB * g->nB + 1;
     const long long maxSweeps = o.max_sweeps > 0 ? o.max_sweeps : bound;
     const int every = o.check_every > 0 ? o.check_every : 8;
     const long long pin0 = g->pages_in, pout0 = g->pages_out, h2d0 = g->bytes_h2d, d2h0 = g->bytes_d2h;

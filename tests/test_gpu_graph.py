@@ -199,6 +199,7 @@ def test_sparse_region_numbers(mf):
 ROUNDCAP = [
     (2000, 6, "blocks", 256, 1, 0), (5000, 8, "blocks", 700, 2, 0), (8000, 5, "scattered", 40, 1, 0),
     (3000, 10, "blocks", 100, 3, 0), (20000, 6, "blocks", 2048, 1, 3), (6000, 6, "blocks", 500, 2, 1),
+    (1500, 6, "single", 0, 1, 0), (400, 4, "singletons", 0, 1, 0),
 ]
 
 
@@ -211,6 +212,10 @@ def test_round_cap(mf, case):
     n, deg, kind, size, cap, pages = ROUNDCAP[case]
     inst = synth.random_graph(n, deg, 8600 + case, long_frac=0.1)
     region = synth.random_regions(n, size, 8700 + case) if kind == "scattered" else None
+    # one region: a capped discharge carries its own region to the next sweep
+    # (no boundary, so nothing else keeps the solve going); one-vertex regions:
+    # every vertex a region, the cap on single-vertex discharges
+    size = n if kind == "single" else (1 if kind == "singletons" else size)
     out = _check(mf, inst, region=region, region_size=size, device_pages=pages, sweep_bound=False,
                  round_cap=cap)
     assert out["stats"]["push_rounds"] <= out["stats"]["discharges"] * (cap + 1)

@@ -100,3 +100,17 @@ def test_round_cap_rejected_with_prd_and_negative(mf):
             with pytest.raises(mf.MFError) as e:
                 g.solve(**kw)
             assert e.value.status == mf.MF_E_INVAL
+
+
+@pytest.mark.parametrize("dims,conn,tile", [((64, 64), 8, (64, 64)), ((64, 64, 64), 6, (64, 64, 64)),
+                                            ((30, 40), 4, (8, 8))])
+def test_round_cap_default_guard(mf, dims, conn, tile):
+    """With capped rounds the 2|B|^2 + 1 bound of full discharges does not hold
+    (a single region, |B| = 0, may need many sweeps for its one discharge), so
+    the default guard (max_sweeps = 0) must not stop a capped solve early."""
+    inst = synth.blob_grid(dims, conn, 9300 + len(dims), 4, 3.0, 10.0, tile=tile, name="rc_guard")
+    print(f"case {inst.name} dims={dims} tile={tile} cap=1 default guard", flush=True)
+    out = mf.solve_instance(inst, round_cap=1)
+    ref = oracle.solve_grid(inst)
+    assert out["flow"] == ref["flow"]
+    assert (out["smin"] == ref["smin"]).all() and (out["smax"] == ref["smax"]).all()
